@@ -1,0 +1,124 @@
+"""A-priori and a-posteriori error bounds used as test assertions.
+
+* thm22: Theorem 2.2 as stated, bound on the best uniform polynomial
+  approximation error E_k(x log x, [a, b]) for k >= 2 with gamma = a / b.
+* thm22_proof: the value the proof of Theorem 2.2 actually establishes.  The
+  proof reduces E_k to b / (2 (1-gamma)^(k-1)) times an integral whose closed
+  form is (1-sqrt(gamma))^(2k) (1+gamma+2k sqrt(gamma)) / (2 (k^2-1)); the last
+  display of the printed proof shows twice that.  Carried through, the bound is
+  b (1-gamma) (1+gamma+2k sqrt(gamma)) / (4 (k^2-1)) rho^k, rho =
+  (1-sqrt(gamma)) / (1+sqrt(gamma)), which exceeds the stated form by the
+  factor 1 + sqrt(gamma) (the two agree for gamma = 0, Remark 2.3).  Assertions
+  that must be rigorous use thm22_proof; tests check both against a minimax
+  linear program and thm22_proof against numerical quadrature of the integral.
+* rem23: Remark 2.3, the gamma = 0 case b / (4 (k^2 - 1)).
+* cor32: Corollary 3.2, |S(A) - T_d| bound for a distance-d colouring (d >= 2).
+* prop44_poly: Proposition 4.4 in the polynomial case (q = 1):
+  |psi - psi_k| <= 2 ||b||^2 E_{2k-1}(f, [lambda_min, lambda_max]), bounded
+  with thm22_proof at degree 2k - 1.
+* g_m and the a-posteriori bracket of Theorem 4.8 for the polynomial Krylov
+  method (K_m = I, h_{m+1} = beta_m e_m), and the geometric-mean estimate
+  (4.10) of Example 4.10.
+
+Pinned by: thm22 against the integral of its proof; every bound checked to
+hold on exact errors computed by diagonalization (tests).
+"""
+import numpy as np
+from scipy import integrate
+
+from .entropy import f_entropy
+
+
+def thm22(k, a, b):
+    k = np.asarray(k, np.float64)
+    g = a / b
+    sg = np.sqrt(g)
+    return b * (1 - sg) * (1 + g + 2 * k * sg) / (4 * (k * k - 1)) * ((1 - sg) / (1 + sg)) ** k
+
+
+def thm22_proof(k, a, b):
+    k = np.asarray(k, np.float64)
+    g = a / b
+    sg = np.sqrt(g)
+    return b * (1 - g) * (1 + g + 2 * k * sg) / (4 * (k * k - 1)) * ((1 - sg) / (1 + sg)) ** k
+
+
+def thm22_integral(k, a, b):
+    """b / (2 (1-gamma)^(k-1)) * int_0^inf (sqrt(1+t) - sqrt(gamma+t))^(2k) dt,
+    the quantity the proof of Theorem 2.2 bounds in closed form."""
+    g = a / b
+
+    def integrand(t):
+        # sqrt(1+t) - sqrt(g+t) = (1-g) / (sqrt(1+t) + sqrt(g+t)), cancellation-free
+        return ((1 - g) / (np.sqrt(1 + t) + np.sqrt(g + t))) ** (2 * k)
+
+    val, _ = integrate.quad(integrand, 0, np.inf, limit=400, epsabs=0, epsrel=1e-12)
+    return b * val / (2 * (1 - g) ** (k - 1))
+
+
+def rem23(k, b):
+    k = np.asarray(k, np.float64)
+    return b / (4 * (k * k - 1))
+
+
+def cor32(d, n, a, b):
+    """Corollary 3.2 (2 n E_d with Theorem 2.2 as stated)."""
+    d = np.asarray(d, np.float64)
+    g = a / b
+    sg = np.sqrt(g)
+    return n * b * (1 - sg) * (1 + g + 2 * d * sg) / (2 * (d * d - 1)) * ((1 - sg) / (1 + sg)) ** d
+
+
+def prop44_poly(k, norm2, a, b):
+    """Bound on |psi - psi_k| after k polynomial Krylov steps (k >= 2)."""
+    return 2 * norm2 * thm22_proof(2 * k - 1, a, b)
+
+
+def _fprime(x):
+    return -np.log(x) - 1.0
+
+
+def _fsecond(x):
+    return -1.0 / x
+
+
+def g_m(z, theta, U, beta_m, f=f_entropy, fp=_fprime, fpp=_fsecond):
+    """eq. (4.8) for the polynomial Krylov method, for f = -x log x.
+
+    T_m = U diag(theta) U^T; K_m = I and h_{m+1}^T = beta_m e_m^T, so the
+    coefficients are a*_j = beta_m U[m-1, j], b*_j = U[0, j] and
+    c*_j = sum_{l != j} a*_l b*_l / (theta_j - theta_l).
+    """
+    z = np.atleast_1d(np.asarray(z, np.float64))
+    a = beta_m * U[-1, :]
+    bb = U[0, :]
+    ab = a * bb
+    diff = theta[:, None] - theta[None, :]
+    np.fill_diagonal(diff, np.inf)
+    c = (ab[None, :] / diff).sum(axis=1)
+    out = np.zeros_like(z)
+    fth = f(theta)
+    for j in range(theta.size):
+        dz = z - theta[j]
+        near = np.abs(dz) <= 1e-12 * max(1.0, abs(theta[j]))
+        term = np.empty_like(z)
+        zz = z[~near]
+        d = dz[~near]
+        term[~near] = (ab[j] ** 2 * ((f(zz) - fth[j]) / d ** 2 - fp(theta[j]) / d)
+                       + 2 * ab[j] * c[j] * (f(zz) - fth[j]) / d)
+        term[near] = 0.5 * ab[j] ** 2 * fpp(theta[j]) + 2 * ab[j] * c[j] * fp(theta[j])
+        out += term
+    return out
+
+
+def posterior_bracket(alpha, beta, m, norm2, lam_min, lam_max, grid=2000):
+    """Theorem 4.8: (lower, upper) bounds on |psi - psi_m| and the estimate
+    (4.10), evaluating g_m on a log-spaced grid of [lam_min, lam_max] plus the
+    Ritz values inside it."""
+    from scipy.linalg import eigh_tridiagonal
+    theta, U = eigh_tridiagonal(alpha[:m], beta[:m - 1])
+    z = np.geomspace(lam_min, lam_max, grid)
+    z = np.concatenate([z, theta[(theta > lam_min) & (theta < lam_max)]])
+    g = np.abs(g_m(z, theta, U, beta[m - 1]))
+    lo, hi = norm2 * g.min(), norm2 * g.max()
+    return lo, hi, np.sqrt(lo * hi)
