@@ -1,0 +1,226 @@
+/*
+ * vne.h -- C ABI of the MI355X Lanczos-quadrature engine for the von Neumann
+ * entropy S(rho) = tr(-rho log rho) of a sparse symmetric positive
+ * semidefinite matrix rho (Benzi, Rinelli, Simunec, "Computation of the von
+ * Neumann entropy of large matrices via trace estimators and rational Krylov
+ * methods").
+ *
+ * The engine computes quadratic forms psi = b^T f(A) b, f(x) = -x log x, by
+ * the polynomial Krylov (Lanczos) method with Gauss quadrature, eq. (4.2):
+ * psi_k = ||b||^2 e_1^T f(T_k) e_1, for a whole block of probe vectors at
+ * once, and combines them into a trace estimate: Hutchinson, eq. (3.8);
+ * probing with a distance-d colouring, eq. (3.1)-(3.2) and Algorithm 1;
+ * Hutch++, eq. (3.9) with f(A) Omega from eq. (4.3).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a vne_status; nothing throws or aborts across the
+ *    ABI.  After a failure vne_last_error(ctx) describes it (per context; the
+ *    context-free helpers write into the caller's msg buffer when given one).
+ *  - The caller owns every array it passes.  The library never frees caller
+ *    memory.  Arrays marked "host" are plain CPU memory; arrays with a
+ *    `location` field may live on the device (VNE_DEVICE: a pointer returned
+ *    by hipMalloc or a torch tensor's data_ptr on the context's device).
+ *  - Sizes are int64 element counts; index arrays are int32.
+ *  - A context is used by one host thread at a time.  All device work of a
+ *    context runs on its stream; every call returns only after its results
+ *    are in the caller's buffers (the call synchronizes that stream).
+ *  - Matrix layout: compressed sparse rows with sorted, unique column indices
+ *    in [0, n), row_ptr[0] = 0, row_ptr[n] = nnz.  The represented matrix is
+ *    A = scale * CSR.  For graph density matrices the CSR holds the exact
+ *    integers of the Laplacian L = D - Adj (eq. (2.3)) and scale = 1 / tr(L),
+ *    so A = rho exactly and the null vector 1 stays exact (eq. (2.2)).
+ *  - Probe blocks on the device are n x m_pad row-major (probe index fastest),
+ *    m_pad = m rounded up to the kernel's column tile.
+ */
+#ifndef VNE_H
+#define VNE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VNE_OK = 0,
+    VNE_EINVAL = -1,    /* malformed argument or matrix                        */
+    VNE_ENOMEM = -2,    /* device allocation failed or the HBM budget is spent */
+    VNE_EDEVICE = -3,   /* a HIP runtime call failed                           */
+    VNE_ENOTSUP = -4,   /* valid request outside what this build supports      */
+    VNE_EBUSY = -5,     /* resource in use (e.g. releasing a graph in a plan)  */
+    VNE_ENUMERIC = -6   /* NaN or Inf appeared in the Lanczos coefficients     */
+} vne_status;
+
+enum { VNE_F32 = 0, VNE_F64 = 1 };          /* element type of values / dense blocks */
+enum { VNE_HOST = 0, VNE_DEVICE = 1 };      /* where a caller array lives            */
+
+/* mode bits of an estimate */
+enum {
+    VNE_MODE_F64 = 1u << 0,     /* FP64 Lanczos vectors (default: FP32 vectors;
+                                   alpha/beta sums, coefficients and the
+                                   quadrature are FP64 in both modes)          */
+    VNE_MODE_DESING = 1u << 1   /* implicit desingularization (Remark 4.6):
+                                   start from c = b - (1^T b / n) 1; requires
+                                   zero row sums (A 1 = 0)                     */
+};
+
+/* probe kinds */
+enum {
+    VNE_PROBE_RADEMACHER = 0,   /* m Rademacher vectors, estimate = mean (3.8) */
+    VNE_PROBE_HUTCHPP = 1,      /* n_sketch + (m - n_sketch) Rademacher vectors,
+                                   estimate by Hutch++ (3.9)                   */
+    VNE_PROBE_COLORING = 2,     /* indicator vector per colour (3.1),
+                                   estimate = sum (3.2)                        */
+    VNE_PROBE_DENSE = 3         /* caller-supplied n x m block, estimate = mean */
+};
+
+/* validation flags of vne_csr_validate / vne_graph_register */
+enum {
+    VNE_VALIDATE_SYMMETRIC = 1u << 0,  /* check A = A^T (O(nnz log deg))       */
+    VNE_VALIDATE_ZERO_ROWSUM = 1u << 1 /* check every row sums to zero         */
+};
+
+typedef struct vne_ctx vne_ctx;
+
+typedef struct {
+    int64_t n;                /* rows = columns, n >= 1                          */
+    int64_t nnz;              /* stored entries                                  */
+    const int32_t *row_ptr;   /* [n+1]                                           */
+    const int32_t *col_idx;   /* [nnz]                                           */
+    const void *values;       /* [nnz], element type value_dtype                 */
+    int32_t value_dtype;      /* VNE_F32 or VNE_F64                              */
+    int32_t location;         /* VNE_HOST or VNE_DEVICE, for the three arrays    */
+    const int64_t *node_keys; /* host [n] or NULL: key of each row in the probe
+                                 hash (the original node id); NULL = row index  */
+    double scale;             /* A = scale * CSR, finite and > 0                 */
+} vne_csr;
+
+typedef struct {
+    int32_t kind;             /* VNE_PROBE_*                                     */
+    int32_t m;                /* probe vectors in the block, 1 <= m             */
+    uint64_t seed;            /* RADEMACHER / HUTCHPP: hash seed                 */
+    int32_t n_sketch;         /* HUTCHPP: N_r = columns of Omega (the first
+                                 n_sketch hash columns); G uses the next m-N_r */
+    int32_t location;         /* DENSE / COLORING arrays: VNE_HOST/VNE_DEVICE    */
+    const int32_t *colors;    /* COLORING: [n] colour of each row in [0, m)     */
+    const void *dense;        /* DENSE: n x m row-major, FP32 (default mode) or
+                                 FP64 (VNE_MODE_F64)                             */
+} vne_probes;
+
+typedef struct {
+    double estimate;          /* out: trace estimate for this probe kind          */
+    double *quad;             /* host [m] or NULL: psi of every quadratic form   */
+    double *alpha;            /* host [m*k] or NULL: column c, step j at c*k+j   */
+    double *beta;             /* host [m*k] or NULL: same layout; beta_j couples
+                                 v_j and v_{j+1}; 0 after a breakdown            */
+    int32_t *k_eff;           /* host [m] or NULL: Krylov dimension used         */
+    double *norm2;            /* host [m] or NULL: ||c||^2 of the start vector   */
+} vne_result;
+
+/* ----------------------------------------------------------------------------
+ * Context-free host helpers (no GPU needed).
+ * ------------------------------------------------------------------------- */
+
+/* Library version string (static storage). */
+const char *vne_version(void);
+
+/* Graph density matrix, eq. (2.3) with the preprocessing of Section 6.1.
+ * Input: n_nodes >= 1 and n_edges pairs edges[2*e], edges[2*e+1] in
+ * [0, n_nodes) (host).  Self loops are dropped, repeated edges count once
+ * (binary weights), and only the largest connected component is kept (ties:
+ * the component holding the smallest node id); kept nodes are renumbered in
+ * increasing original id.  Output: the Laplacian L = D - Adj of that
+ * component in CSR with every diagonal entry stored, values as exact
+ * integers in value_dtype, node_ids[i] = original id of row i, and
+ * *scale = 1 / tr(L).  Call once with row_ptr == NULL to get *n_out and
+ * *nnz_out, then again with arrays of those sizes.  EINVAL on bad input or a
+ * component with no edge (tr(L) = 0).  msg (may be NULL) receives a message. */
+vne_status vne_laplacian_from_edges(int64_t n_nodes, int64_t n_edges, const int64_t *edges,
+                                    int64_t *n_out, int64_t *nnz_out, int32_t *row_ptr,
+                                    int32_t *col_idx, void *values, int32_t value_dtype,
+                                    int64_t *node_ids, double *scale, char *msg, int64_t msg_len);
+
+/* Structural and numerical checks of a host CSR: sizes, monotone row_ptr,
+ * sorted unique in-range columns, finite values, finite positive scale, plus
+ * the checks selected by flags (VNE_VALIDATE_*).  EINVAL with a message on
+ * the first violation. */
+vne_status vne_csr_validate(const vne_csr *csr, uint32_t flags, char *msg, int64_t msg_len);
+
+/* Greedy distance-d colouring, Algorithm 1 of Section 3.1: nodes in order of
+ * descending degree (number of off-diagonal entries; ties by increasing row
+ * index), each taking the smallest colour (from 0) not used by an earlier
+ * node within geodesic distance d in the graph of the matrix.  Host CSR only.
+ * colors_out: host [n]; *n_colors = number of colours used.  d >= 1. */
+vne_status vne_color_greedy(const vne_csr *csr, int32_t d, int32_t *colors_out,
+                            int32_t *n_colors, char *msg, int64_t msg_len);
+
+/* ----------------------------------------------------------------------------
+ * Device context and graph registry.
+ * ------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context allocates for graphs and workspaces (0 = no cap).
+ * hip_stream: a hipStream_t to run on (borrowed), or NULL for the null
+ * stream.  *out receives the context. */
+vne_status vne_ctx_create(int device, uint64_t hbm_budget_bytes, void *hip_stream, vne_ctx **out);
+
+/* Release every device allocation of the context and the context itself. */
+void vne_ctx_destroy(vne_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); static until the next
+ * call on ctx.  NULL ctx gives the message of the last failed vne_ctx_create. */
+const char *vne_last_error(const vne_ctx *ctx);
+
+/* Replace the stream (hipStream_t, borrowed; NULL = null stream). */
+vne_status vne_ctx_set_stream(vne_ctx *ctx, void *hip_stream);
+
+/* Device bytes currently held by the context. */
+vne_status vne_ctx_memory(const vne_ctx *ctx, uint64_t *bytes_in_use);
+
+/* Register a matrix.  HOST arrays are copied into device memory owned by the
+ * context until vne_graph_release; DEVICE arrays are borrowed and must stay
+ * valid and unchanged until release.  The structure is validated (see
+ * vne_csr_validate; DEVICE arrays are copied back for the checks).  The work
+ * schedule of the Lanczos kernels (row segments of long rows, cost-balanced
+ * blocks) is built here.  *graph_id receives a handle >= 0. */
+vne_status vne_graph_register(vne_ctx *ctx, const vne_csr *csr, uint32_t validate_flags,
+                              int32_t *graph_id);
+
+/* Free a registered matrix and every cached workspace built for it. */
+vne_status vne_graph_release(vne_ctx *ctx, int32_t graph_id);
+
+/* ----------------------------------------------------------------------------
+ * Estimates.
+ * ------------------------------------------------------------------------- */
+
+/* k_steps Lanczos steps on every probe vector of `probes` for the matrix
+ * `graph_id`, Gauss quadrature of each quadratic form (eq. (4.2)) and the
+ * estimator of the probe kind.  1 <= k_steps <= 128.  With VNE_MODE_DESING
+ * each start vector b is replaced by c = b - (1^T b / n) 1 (Remark 4.6).
+ * Breakdown: a column stops after step j when beta_j <= tau (|alpha_j| +
+ * beta_{j-1}), tau = 2^-18 for FP32 vectors and 2^-23 for FP64 vectors;
+ * k_eff records j.  Results go to the caller's host buffers in *out (each may
+ * be NULL except `out` itself).  For HUTCHPP, quad/alpha/beta/k_eff/norm2
+ * describe the final block [Q | G~] of m quadratic forms (the sketch's own
+ * coefficients are not returned).  Workspaces are cached per (graph, probe
+ * width, k, mode, kind) and reused by later calls. */
+vne_status vne_entropy_estimate(vne_ctx *ctx, int32_t graph_id, const vne_probes *probes,
+                                int32_t k_steps, uint32_t mode, vne_result *out);
+
+/* Kernel timing for measurement: when enabled, the context records a HIP
+ * event pair on its stream around every launch of the Lanczos step kernel
+ * and accumulates their durations.  vne_kernel_timing returns (and with
+ * reset != 0 clears) the number of timed launches, their total milliseconds
+ * and the algorithmic bytes those launches were due to move (CSR once, the
+ * gathered block once, the previous block once, the new block once per
+ * step).  Timing adds one event pair per launch and no synchronization
+ * inside a call. */
+vne_status vne_enable_kernel_timing(vne_ctx *ctx, int32_t enable);
+vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, double *total_ms,
+                             double *algorithmic_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VNE_H */

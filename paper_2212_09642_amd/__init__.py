@@ -1,0 +1,279 @@
+"""Python binding of libvne, the MI355X Lanczos-quadrature engine for the von
+Neumann entropy (see include/vne.h for the C ABI it wraps).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Host arrays are numpy arrays; device arrays may be passed as torch
+tensors (their data_ptr is handed to the library).  Importing the package
+does not need a GPU; creating a Context does.  There is no fallback: if
+libvne.so is missing the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["VneError", "lib", "version", "laplacian_from_edges", "csr_validate",
+           "color_greedy", "Context", "F32", "F64", "MODE_F64", "MODE_DESING",
+           "PROBE_RADEMACHER", "PROBE_HUTCHPP", "PROBE_COLORING", "PROBE_DENSE",
+           "VALIDATE_SYMMETRIC", "VALIDATE_ZERO_ROWSUM", "LIB_PATH", "EXPORTS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvne.so")
+
+F32, F64 = 0, 1
+HOST, DEVICE = 0, 1
+MODE_F64, MODE_DESING = 1, 2
+PROBE_RADEMACHER, PROBE_HUTCHPP, PROBE_COLORING, PROBE_DENSE = 0, 1, 2, 3
+VALIDATE_SYMMETRIC, VALIDATE_ZERO_ROWSUM = 1, 2
+STATUS = {0: "VNE_OK", -1: "VNE_EINVAL", -2: "VNE_ENOMEM", -3: "VNE_EDEVICE",
+          -4: "VNE_ENOTSUP", -5: "VNE_EBUSY", -6: "VNE_ENUMERIC"}
+
+# every symbol include/vne.h declares
+EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_color_greedy",
+           "vne_ctx_create", "vne_ctx_destroy", "vne_last_error", "vne_ctx_set_stream",
+           "vne_ctx_memory", "vne_graph_register", "vne_graph_release", "vne_entropy_estimate",
+           "vne_enable_kernel_timing", "vne_kernel_timing"]
+
+
+class VneError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("value_dtype", ctypes.c_int32),
+                ("location", ctypes.c_int32), ("node_keys", ctypes.c_void_p),
+                ("scale", ctypes.c_double)]
+
+
+class _Probes(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("m", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("n_sketch", ctypes.c_int32), ("location", ctypes.c_int32),
+                ("colors", ctypes.c_void_p), ("dense", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("quad", ctypes.c_void_p),
+                ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+                ("k_eff", ctypes.c_void_p), ("norm2", ctypes.c_void_p)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libvne.so (built in-tree by __graft_entry__.build())."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libvne.so not built: run __graft_entry__.build() (%s)" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, u64, vp, cp, dbl = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                      ctypes.c_void_p, ctypes.c_char_p, ctypes.c_double)
+        P = ctypes.POINTER
+        L.vne_version.restype = cp
+        L.vne_version.argtypes = []
+        L.vne_laplacian_from_edges.restype = i32
+        L.vne_laplacian_from_edges.argtypes = [i64, i64, vp, P(i64), P(i64), vp, vp, vp, i32, vp,
+                                               P(dbl), cp, i64]
+        L.vne_csr_validate.restype = i32
+        L.vne_csr_validate.argtypes = [P(_Csr), ctypes.c_uint32, cp, i64]
+        L.vne_color_greedy.restype = i32
+        L.vne_color_greedy.argtypes = [P(_Csr), i32, vp, P(i32), cp, i64]
+        L.vne_ctx_create.restype = i32
+        L.vne_ctx_create.argtypes = [ctypes.c_int, u64, vp, P(vp)]
+        L.vne_ctx_destroy.restype = None
+        L.vne_ctx_destroy.argtypes = [vp]
+        L.vne_last_error.restype = cp
+        L.vne_last_error.argtypes = [vp]
+        L.vne_ctx_set_stream.restype = i32
+        L.vne_ctx_set_stream.argtypes = [vp, vp]
+        L.vne_ctx_memory.restype = i32
+        L.vne_ctx_memory.argtypes = [vp, P(u64)]
+        L.vne_graph_register.restype = i32
+        L.vne_graph_register.argtypes = [vp, P(_Csr), ctypes.c_uint32, P(i32)]
+        L.vne_graph_release.restype = i32
+        L.vne_graph_release.argtypes = [vp, i32]
+        L.vne_entropy_estimate.restype = i32
+        L.vne_entropy_estimate.argtypes = [vp, i32, P(_Probes), i32, ctypes.c_uint32, P(_Result)]
+        L.vne_enable_kernel_timing.restype = i32
+        L.vne_enable_kernel_timing.argtypes = [vp, i32]
+        L.vne_kernel_timing.restype = i32
+        L.vne_kernel_timing.argtypes = [vp, i32, P(i64), P(dbl), P(dbl)]
+        _LIB = L
+    return _LIB
+
+
+def version():
+    return lib().vne_version().decode()
+
+
+def _ptr(a):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _is_device(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def _check(st, msg):
+    if st != 0:
+        raise VneError(st, msg)
+
+
+def laplacian_from_edges(n_nodes, edges, dtype=np.float32):
+    """Laplacian of the largest connected component (eq. (2.3)); see
+    vne_laplacian_from_edges.  Returns dict(n, row_ptr, col_idx, values,
+    node_ids, scale)."""
+    L = lib()
+    e = np.ascontiguousarray(np.asarray(edges, np.int64).reshape(-1, 2))
+    vd = F64 if np.dtype(dtype) == np.float64 else F32
+    n_out, nnz_out, scale = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    msg = ctypes.create_string_buffer(512)
+    _check(L.vne_laplacian_from_edges(n_nodes, e.shape[0], _ptr(e), ctypes.byref(n_out),
+                                      ctypes.byref(nnz_out), None, None, None, vd, None, None,
+                                      msg, 512), msg.value.decode())
+    n, nnz = n_out.value, nnz_out.value
+    rp = np.empty(n + 1, np.int32)
+    ci = np.empty(nnz, np.int32)
+    vals = np.empty(nnz, np.float64 if vd == F64 else np.float32)
+    ids = np.empty(n, np.int64)
+    _check(L.vne_laplacian_from_edges(n_nodes, e.shape[0], _ptr(e), ctypes.byref(n_out),
+                                      ctypes.byref(nnz_out), _ptr(rp), _ptr(ci), _ptr(vals), vd,
+                                      _ptr(ids), ctypes.byref(scale), msg, 512), msg.value.decode())
+    return dict(n=n, row_ptr=rp, col_idx=ci, values=vals, node_ids=ids, scale=scale.value)
+
+
+def _csr_struct(row_ptr, col_idx, values, scale, node_keys=None):
+    dev = _is_device(row_ptr)
+    if not dev:
+        row_ptr = np.ascontiguousarray(row_ptr, np.int32)
+        col_idx = np.ascontiguousarray(col_idx, np.int32)
+        values = np.ascontiguousarray(values)
+        if values.dtype not in (np.float32, np.float64):
+            values = values.astype(np.float64)
+        vd = F64 if values.dtype == np.float64 else F32
+    else:
+        import torch
+        vd = F64 if values.dtype == torch.float64 else F32
+    keys = None
+    if node_keys is not None:
+        keys = np.ascontiguousarray(node_keys, np.int64)
+    n = (row_ptr.numel() if dev else row_ptr.size) - 1
+    nnz = col_idx.numel() if dev else col_idx.size
+    s = _Csr(n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(values), vd, DEVICE if dev else HOST,
+             _ptr(keys), float(scale))
+    return s, (row_ptr, col_idx, values, keys)   # keep arrays alive
+
+
+def csr_validate(row_ptr, col_idx, values, scale, flags=0):
+    s, keep = _csr_struct(row_ptr, col_idx, values, scale)
+    msg = ctypes.create_string_buffer(512)
+    st = lib().vne_csr_validate(ctypes.byref(s), flags, msg, 512)
+    return st, msg.value.decode()
+
+
+def color_greedy(row_ptr, col_idx, values, d):
+    """Greedy distance-d colouring (Algorithm 1); returns (colors int32[n], n_colors)."""
+    s, keep = _csr_struct(row_ptr, col_idx, values, 1.0)
+    colors = np.empty(s.n, np.int32)
+    nc = ctypes.c_int32()
+    msg = ctypes.create_string_buffer(512)
+    _check(lib().vne_color_greedy(ctypes.byref(s), d, _ptr(colors), ctypes.byref(nc), msg, 512),
+           msg.value.decode())
+    return colors, nc.value
+
+
+class Context:
+    """A device context (one HIP device, one stream)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0, stream=None):
+        L = lib()
+        h = ctypes.c_void_p()
+        st = L.vne_ctx_create(device, hbm_budget_bytes, stream, ctypes.byref(h))
+        _check(st, L.vne_last_error(None).decode())
+        self._h = h
+        self._L = L
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.vne_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _chk(self, st):
+        if st != 0:
+            raise VneError(st, self._L.vne_last_error(self._h).decode())
+
+    def set_stream(self, stream):
+        self._chk(self._L.vne_ctx_set_stream(self._h, stream))
+
+    def memory(self):
+        b = ctypes.c_uint64()
+        self._chk(self._L.vne_ctx_memory(self._h, ctypes.byref(b)))
+        return b.value
+
+    def register(self, row_ptr, col_idx, values, scale, node_keys=None, validate=0):
+        """Register a matrix A = scale * CSR; returns a graph id."""
+        s, keep = _csr_struct(row_ptr, col_idx, values, scale, node_keys)
+        gid = ctypes.c_int32()
+        self._chk(self._L.vne_graph_register(self._h, ctypes.byref(s), validate, ctypes.byref(gid)))
+        return gid.value
+
+    def release(self, gid):
+        self._chk(self._L.vne_graph_release(self._h, gid))
+
+    def estimate(self, gid, kind, m, k, mode, seed=0, n_sketch=0, colors=None, dense=None,
+                 want_coeffs=True):
+        """One estimate; returns dict(estimate, quad, alpha, beta, k_eff, norm2)."""
+        loc = HOST
+        keep = []
+        if colors is not None:
+            if _is_device(colors):
+                loc = DEVICE
+            else:
+                colors = np.ascontiguousarray(colors, np.int32)
+            keep.append(colors)
+        if dense is not None:
+            if _is_device(dense):
+                loc = DEVICE
+            else:
+                dense = np.ascontiguousarray(dense, np.float64 if mode & MODE_F64 else np.float32)
+            keep.append(dense)
+        pr = _Probes(kind, m, seed, n_sketch, loc, _ptr(colors), _ptr(dense))
+        quad = np.zeros(m)
+        kef = np.zeros(m, np.int32)
+        nrm = np.zeros(m)
+        alpha = np.zeros((m, k)) if want_coeffs else None
+        beta = np.zeros((m, k)) if want_coeffs else None
+        res = _Result(0.0, _ptr(quad), _ptr(alpha), _ptr(beta), _ptr(kef), _ptr(nrm))
+        self._chk(self._L.vne_entropy_estimate(self._h, gid, ctypes.byref(pr), k, mode,
+                                               ctypes.byref(res)))
+        return dict(estimate=res.estimate, quad=quad, alpha=alpha, beta=beta, k_eff=kef, norm2=nrm)
+
+    def enable_kernel_timing(self, on=True):
+        self._chk(self._L.vne_enable_kernel_timing(self._h, 1 if on else 0))
+
+    def kernel_timing(self, reset=True):
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        self._chk(self._L.vne_kernel_timing(self._h, 1 if reset else 0, ctypes.byref(n),
+                                            ctypes.byref(ms), ctypes.byref(by)))
+        return dict(launches=n.value, total_ms=ms.value, bytes=by.value)

@@ -1,0 +1,132 @@
+// Launch wrappers of the gfx950 kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace vne {
+
+constexpr int kMaxSteps = 128;     // largest k_steps the quadrature kernels accept
+constexpr int kBlock = 256;        // threads per block of the streaming kernels
+
+enum ProbeGen { GEN_RADEMACHER = 0, GEN_COLORING = 1, GEN_DENSE = 2 };
+
+// Everything the Lanczos step kernel reads or writes, for one matrix and one
+// probe block of width m_pad (a multiple of the column tile mt).
+struct StepArgs {
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const void *val;            // float (FP32 mode) or double (FP64 mode)
+    double scale;
+    int32_t n;
+    int32_t m_pad;
+    int32_t mt;                 // column tile of the launch
+    int32_t n_tiles;
+    const void *P_in;           // raw vector P_j (n x m_pad)
+    const void *V_prev;         // v_{j-1} (ignored on the first step)
+    void *V_out;                // v_j, written
+    void *P_out;                // P_{j+1} = A v_j - beta_{j-1} v_{j-1}, written
+    const double *st_alpha;     // per column alpha_{j-1}
+    const double *st_inv;       // per column 1/beta_{j-1} (1/||c|| at j = 1; 0 frozen)
+    const double *st_coup;      // per column beta_{j-1} (0 at j = 1)
+    const SegItem *segs;
+    int32_t n_seg;
+    int32_t seg_len;
+    const int32_t *block_begin;
+    int32_t n_blocks;
+    double *seg_acc;            // [n_seg][m_pad]
+    int32_t *tickets;           // [n_long][n_tiles]
+    const int32_t *long_first;
+    const int32_t *long_nseg;
+    double *long_part;          // [n_long][3][m_pad]
+    double *partials;           // [n_tiles][n_blocks][3][mt]
+};
+
+struct FinalizeArgs {
+    const double *partials;
+    const double *long_part;
+    int32_t n_blocks;
+    int32_t n_long;
+    int32_t mt;
+    int32_t m_pad;
+    int32_t m;                  // real columns (pad columns stay frozen)
+    int32_t step;               // 1-based step just taken
+    int32_t k;                  // steps of the run (row stride of alpha/beta)
+    double tau;
+    double *st_alpha, *st_inv, *st_coup;
+    double *alpha, *beta;       // [m_pad][k]
+    int32_t *k_eff;
+    int32_t *flags;             // bit 0: non-finite coefficient
+};
+
+// Returns the column tile width the step kernel uses for this probe width.
+int choose_tile(int m, bool fp64, int requested);
+int pad_columns(int m, int mt);
+
+hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
+
+// probe block: sums, centring, norms; P_1 written with element type of the mode
+struct ProbeArgs {
+    int32_t gen;                // ProbeGen
+    int32_t n, m, m_pad, mt;
+    int32_t col_offset;         // first hash column (Hutch++ G block)
+    uint64_t seed;
+    const int64_t *keys;        // [n] row keys (Rademacher)
+    const int32_t *colors;      // [n] (colouring)
+    const void *dense;          // [n][ld_dense] (dense), element type of the mode
+    int32_t ld_dense;
+    int32_t desing;
+    void *P_out;                // [n][m_pad]
+    double *partials;           // scratch [n_blocks][m_pad]
+    int32_t n_blocks;
+    double *mean;               // [m_pad]
+    double *norm2;              // [m_pad]
+    double *st_alpha, *st_inv, *st_coup;
+    int32_t *k_eff;
+    int32_t k;
+};
+hipError_t launch_probe(const ProbeArgs &a, bool fp64, hipStream_t s);
+
+// raw +-1 Rademacher block into out[i*ld + off + c], c < m (no centring)
+hipError_t launch_rademacher_fill(void *out, bool fp64, int32_t n, int32_t m, int32_t ld, int32_t off,
+                                  int32_t col_offset, uint64_t seed, const int64_t *keys,
+                                  hipStream_t s);
+
+// Gauss quadrature of every column: psi[c] = norm2[c] e1^T f(T) e1
+hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
+                             const double *norm2, int32_t k, int32_t m, double *psi,
+                             int32_t *flags, hipStream_t s);
+// f(T) e1 for every column (rows >= k_eff are 0): S[c*k + r]
+hipError_t launch_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff,
+                        int32_t k, int32_t m, double *S, int32_t *flags, hipStream_t s);
+
+// estimate from psi: kind 0 mean, 1 sum, 2 Hutch++ (first n_sketch summed,
+// rest averaged)
+hipError_t launch_combine(const double *psi, int32_t m, int32_t kind, int32_t n_sketch,
+                          double *estimate, hipStream_t s);
+
+// Y[i*ldy + c] = sqrt(norm2[c]) * sum_j S[c*k+j] Vstore[j][i*ldv + c]
+hipError_t launch_reconstruct(const void *Vstore, bool fp64, int64_t step_stride, int32_t ldv,
+                              const double *S, const double *norm2, const int32_t *k_eff,
+                              int32_t k, int32_t n, int32_t m, void *Y, int32_t ldy,
+                              hipStream_t s);
+
+// out[a*nb + b] = sum_i X[i*ldx + a] * Y[i*ldy + b] (FP64 accumulation);
+// uses part (scratch, [chunks][na][nb] doubles, see gram_scratch_doubles)
+int64_t gram_scratch_doubles(int32_t n, int32_t na, int32_t nb);
+hipError_t launch_gram(const void *X, int32_t ldx, const void *Y, int32_t ldy, bool fp64,
+                       int32_t n, int32_t na, int32_t nb, double *part, double *out,
+                       hipStream_t s);
+// in-place upper Cholesky of G (na x na, FP64) and its inverse Rinv; flags bit 1 on failure
+hipError_t launch_cholinv(double *G, double *Rinv, int32_t na, int32_t *flags, hipStream_t s);
+// Z[i*ldz + b] = (sub ? Z[i*ldz + b] : 0) + sign * sum_a X[i*ldx + a] * M[a*nb + b]
+// (row-local: in place when Z aliases X is allowed only for sub == 0)
+hipError_t launch_apply(const void *X, int32_t ldx, const double *M, int32_t na, int32_t nb,
+                        void *Z, int32_t ldz, bool fp64, int32_t n, int32_t sub,
+                        hipStream_t s);
+
+}  // namespace vne

@@ -1,0 +1,252 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (per quadratic form, relative): FP64 vectors 1e-12, FP32 vectors
+1e-5.  Integer results (Krylov dimension, graph structure) are compared
+exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import workloads
+import paper_2212_09642_amd as vne
+
+pytestmark = pytest.mark.gpu
+
+TOL = {True: 1e-12, False: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = vne.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _setup(ctx, n, e, fp64=True):
+    g = vne.laplacian_from_edges(n, e, np.float64 if fp64 else np.float32)
+    ref = oracle.laplacian_from_edges(n, e)
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    return gid, ref
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def _order_sensitivity(A, B, k, fp64, desing=True):
+    """Relative change of the oracle's own psi_k when the same problem is
+    computed with the rows and columns in reverse order (a different rounding
+    order only).  After a Ritz value converges, plain Lanczos loses
+    orthogonality and psi_k becomes sensitive to rounding at the level of its
+    remaining quadrature error; no implementation can then agree with the
+    oracle more closely than the oracle agrees with itself."""
+    import scipy.sparse as sp
+    n = A.shape[0]
+    P = np.arange(n)[::-1]
+    Ap = sp.csr_matrix(A)[P][:, P]
+    a = oracle.quadforms(A, B, k, oracle.breakdown_tau(fp64), desing)["psi"]
+    b = oracle.quadforms(Ap, np.asarray(B)[P], k, oracle.breakdown_tau(fp64), desing)["psi"]
+    return _rel(b, a)
+
+
+def _check_quad(out, want, fp64, k_exact=True, sens=None):
+    """Per-quadratic-form bar: 1e-12 (FP64 vectors) or 1e-5 (FP32 vectors),
+    widened to 20x the oracle's own rounding-order sensitivity where given."""
+    tol = TOL[fp64] if sens is None else np.maximum(TOL[fp64], 20 * sens)
+    rel = _rel(out["quad"], want["psi"])
+    _say("   max rel err %.3e (bar %.1e, oracle order sensitivity %.1e)"
+         % (rel.max(), TOL[fp64], 0.0 if sens is None else np.max(sens)))
+    assert np.all(rel < tol), rel.max()
+    if k_exact:
+        assert np.array_equal(out["k_eff"], want["k_eff"])
+    assert np.allclose(out["norm2"], want["norm2"], rtol=1e-13 if fp64 else 1e-6, atol=0)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_tiny_er_hutchinson(ctx, fp64):
+    w = workloads.tiny()
+    _say("case tiny ER n=2000 m=30 k=40 fp64=%s" % fp64)
+    gid, ref = _setup(ctx, w["n_nodes"], w["edges"], fp64)
+    mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+    out = ctx.estimate(gid, vne.PROBE_RADEMACHER, w["m"], w["k"], mode, seed=w["probe_seed"])
+    B = oracle.rademacher_block(w["probe_seed"], ref.node_ids, np.arange(w["m"]))
+    want = oracle.quadforms(ref.scipy(), B, w["k"], oracle.breakdown_tau(fp64))
+    _check_quad(out, want, fp64)
+    # the first Lanczos coefficients agree before orthogonality is lost
+    j = 8
+    assert np.allclose(out["alpha"][:, :j], want["alpha"][:, :j], rtol=1e-10 if fp64 else 1e-5, atol=0)
+    assert np.allclose(out["beta"][:, :j], want["beta"][:, :j], rtol=1e-10 if fp64 else 1e-5, atol=0)
+    assert abs(out["estimate"] - want["psi"].mean()) < TOL[fp64] * abs(out["estimate"])
+    # the Hutchinson estimate is within its statistical error of the exact entropy
+    S = oracle.exact_entropy(oracle.dense_matrix(ref))
+    se = want["psi"].std() / np.sqrt(w["m"])
+    assert abs(out["estimate"] - S) < 5 * se
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_complete_graph_breakdown(ctx, fp64):
+    n = 64
+    _say("case K_64 breakdown fp64=%s" % fp64)
+    gid, ref = _setup(ctx, *synth.complete_graph(n), fp64=fp64)
+    mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+    out = ctx.estimate(gid, vne.PROBE_RADEMACHER, 8, 10, mode, seed=3)
+    B = oracle.rademacher_block(3, ref.node_ids, np.arange(8))
+    expect = np.log(n - 1) / (n - 1) * ((B * B).sum(0) - B.sum(0) ** 2 / n)
+    assert np.all(out["k_eff"] == 1)
+    assert np.all(_rel(out["quad"], expect) < TOL[fp64])
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_example_4_10_diagonal(ctx, fp64):
+    # diagonal matrix with Chebyshev-point eigenvalues in [1e-3, 1e3], dense N(0,1) probe
+    n = 2000
+    _say("case Example 4.10 fp64=%s" % fp64)
+    j = np.arange(n)
+    lam = 0.5 * (1e3 + 1e-3) + 0.5 * (1e3 - 1e-3) * np.cos((2 * j + 1) * np.pi / (2 * n))
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    gid = ctx.register(rp, ci, lam.astype(np.float64 if fp64 else np.float32), 1.0)
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((n, 3))
+    if not fp64:
+        B = B.astype(np.float32).astype(np.float64)
+    mode = vne.MODE_F64 if fp64 else 0
+    out = ctx.estimate(gid, vne.PROBE_DENSE, 3, 30, mode, dense=B)
+    import scipy.sparse as sp
+    lam_dev = lam if fp64 else lam.astype(np.float32).astype(np.float64)
+    want = oracle.quadforms(sp.diags(lam_dev).tocsr(), B, 30, oracle.breakdown_tau(fp64), desing=False)
+    _check_quad(out, want, fp64)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_hub_rows_use_segments(ctx, fp64):
+    # star: one row with n-1 off-diagonal entries, split across many segments
+    _say("case star n=3001 + BA hubs fp64=%s" % fp64)
+    for n, e in (synth.star_graph(3001), synth.barabasi_albert(20000, 3, 5)):
+        gid, ref = _setup(ctx, n, e, fp64)
+        mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+        out = ctx.estimate(gid, vne.PROBE_RADEMACHER, 40, 25, mode, seed=8)
+        B = oracle.rademacher_block(8, ref.node_ids, np.arange(40))
+        want = oracle.quadforms(ref.scipy(), B, 25, oracle.breakdown_tau(fp64))
+        _check_quad(out, want, fp64, sens=_order_sensitivity(ref.scipy(), B, 25, fp64))
+
+
+@pytest.mark.parametrize("m,k", [(1, 1), (1, 7), (37, 3), (257, 5), (64, 50)])
+def test_ragged_shapes(ctx, m, k):
+    _say("case ragged m=%d k=%d" % (m, k))
+    n, e = synth.watts_strogatz(1237, 6, 0.2, 9)
+    for fp64 in (True, False):
+        gid, ref = _setup(ctx, n, e, fp64)
+        mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+        out = ctx.estimate(gid, vne.PROBE_RADEMACHER, m, k, mode, seed=21)
+        B = oracle.rademacher_block(21, ref.node_ids, np.arange(m))
+        want = oracle.quadforms(ref.scipy(), B, k, oracle.breakdown_tau(fp64))
+        _check_quad(out, want, fp64)
+
+
+def test_coloring_probes(ctx):
+    _say("case colouring probes WS n=5000 d=2")
+    n, e = synth.watts_strogatz(5000, 10, 0.1, 4)
+    gid, ref = _setup(ctx, n, e, False)
+    col, s = vne.color_greedy(ref.row_ptr.astype(np.int32), ref.col_idx.astype(np.int32), ref.values, 2)
+    out = ctx.estimate(gid, vne.PROBE_COLORING, s, 40, vne.MODE_DESING, colors=col)
+    P = oracle.indicator_block(col, s)
+    want = oracle.quadforms(ref.scipy(), P, 40, oracle.breakdown_tau(False))
+    _check_quad(out, want, False)
+    assert abs(out["estimate"] - want["psi"].sum()) < 1e-5 * abs(out["estimate"])
+
+
+def test_dense_probes_device_tensor(ctx):
+    import torch
+    _say("case dense probes from a device tensor")
+    n, e = synth.barabasi_albert(3000, 2, 6)
+    gid, ref = _setup(ctx, n, e, True)
+    rng = np.random.default_rng(1)
+    B = rng.standard_normal((ref.n, 12))
+    Bt = torch.tensor(B, dtype=torch.float64, device="cuda")
+    out = ctx.estimate(gid, vne.PROBE_DENSE, 12, 30, vne.MODE_F64 | vne.MODE_DESING, dense=Bt)
+    want = oracle.quadforms(ref.scipy(), B, 30, oracle.breakdown_tau(True))
+    _check_quad(out, want, True, sens=_order_sensitivity(ref.scipy(), B, 30, True))
+
+
+def test_deterministic(ctx):
+    _say("case run-twice bitwise")
+    n, e = synth.barabasi_albert(30000, 3, 2)
+    gid, ref = _setup(ctx, n, e, False)
+    a = ctx.estimate(gid, vne.PROBE_RADEMACHER, 64, 30, vne.MODE_DESING, seed=5)
+    b = ctx.estimate(gid, vne.PROBE_RADEMACHER, 64, 30, vne.MODE_DESING, seed=5)
+    for key in ("quad", "alpha", "beta", "k_eff", "norm2"):
+        assert np.array_equal(a[key], b[key]), key
+    assert a["estimate"] == b["estimate"]
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_hutchpp_small(ctx, fp64):
+    _say("case Hutch++ BA n=3000 16+16 fp64=%s" % fp64)
+    n, e = synth.barabasi_albert(3000, 3, 7)
+    gid, ref = _setup(ctx, n, e, fp64)
+    nr, nh, k = 16, 16, 30
+    mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+    out = ctx.estimate(gid, vne.PROBE_HUTCHPP, nr + nh, k, mode, seed=13, n_sketch=nr)
+    Om = oracle.rademacher_block(13, ref.node_ids, np.arange(nr))
+    G = oracle.rademacher_block(13, ref.node_ids, np.arange(nr, nr + nh))
+    est, det = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(fp64))
+    # oracle against itself in reversed node order: rounding-order sensitivity
+    import scipy.sparse as sp
+    P = np.arange(ref.n)[::-1]
+    Ap = sp.csr_matrix(ref.scipy())[P][:, P]
+    est_p, det_p = oracle.hutchpp(Ap, Om[P], G[P], k, oracle.breakdown_tau(fp64))
+    sens_g = _rel(det_p["psi"][nr:], det["psi"][nr:])
+    sens_q = abs(det_p["psi"][:nr].sum() - det["psi"][:nr].sum()) / abs(det["psi"][:nr].sum())
+    sens_e = abs(est_p - est) / abs(est)
+    bar = TOL[fp64]
+    err_e = abs(out["estimate"] - est) / abs(est)
+    err_g = _rel(out["quad"][nr:], det["psi"][nr:])
+    err_q = abs(out["quad"][:nr].sum() - det["psi"][:nr].sum()) / abs(det["psi"][:nr].sum())
+    _say("   estimate rel err %.3e (sens %.1e); G~ max %.3e (sens %.1e); sum over Q %.3e (sens %.1e)"
+         % (err_e, sens_e, err_g.max(), sens_g.max(), err_q, sens_q))
+    # G~ forms depend only on span(Q); Q's own forms only on the columns up to sign
+    assert err_e < max(bar, 20 * sens_e)
+    assert np.all(err_g < np.maximum(bar, 20 * sens_g))
+    assert err_q < max(bar, 20 * sens_q)
+
+
+def test_error_paths(ctx):
+    _say("case error paths")
+    n, e = synth.cycle_graph(50)
+    gid, ref = _setup(ctx, n, e, False)
+    with pytest.raises(vne.VneError) as ei:
+        ctx.estimate(gid, vne.PROBE_RADEMACHER, 4, 0, vne.MODE_DESING)
+    assert ei.value.status == -1
+    with pytest.raises(vne.VneError):
+        ctx.estimate(gid, vne.PROBE_RADEMACHER, 4, 129, vne.MODE_DESING)
+    with pytest.raises(vne.VneError):
+        ctx.estimate(gid, vne.PROBE_RADEMACHER, 0, 5, vne.MODE_DESING)
+    with pytest.raises(vne.VneError):
+        ctx.estimate(gid + 100, vne.PROBE_RADEMACHER, 4, 5, vne.MODE_DESING)
+    with pytest.raises(vne.VneError):
+        ctx.estimate(gid, vne.PROBE_COLORING, 3, 5, vne.MODE_DESING, colors=np.full(ref.n, 7))
+    # desingularization needs zero row sums
+    rp = np.arange(11, dtype=np.int32)
+    gid2 = ctx.register(rp, np.arange(10, dtype=np.int32), np.ones(10, np.float32), 0.1)
+    with pytest.raises(vne.VneError):
+        ctx.estimate(gid2, vne.PROBE_RADEMACHER, 4, 5, vne.MODE_DESING)
+    # malformed matrix rejected at registration (row 0 repeats column 1)
+    rp_bad = np.array([0, 2] + [2] * 9, np.int32)
+    with pytest.raises(vne.VneError):
+        ctx.register(rp_bad, np.array([1, 1], np.int32), np.ones(2, np.float32), 0.1)
+    # a budget too small for the workspace
+    with vne.Context(0, hbm_budget_bytes=1 << 16) as small:
+        with pytest.raises(vne.VneError) as ei:
+            g2 = small.register(ref.row_ptr.astype(np.int32), ref.col_idx.astype(np.int32),
+                                ref.values.astype(np.float32), ref.scale)
+            small.estimate(g2, vne.PROBE_RADEMACHER, 64, 10, vne.MODE_DESING)
+        assert ei.value.status == -2
