@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput of the Lanczos-quadrature entropy hot path on one MI355X.
+
+One step is one whole entropy estimate of the workload (probe block, every
+Lanczos step, quadrature, estimator combine, results copied back to the
+host), with the matrix already resident in HBM.  The default workload is the
+single-large-graph configuration: Barabasi-Albert n = 200000, 3 edges per new
+node, rho = L / tr(L), Hutch++ with 128 sketch + 128 Hutchinson Rademacher
+vectors, 60 Lanczos steps, FP32 vectors with FP64 coefficients.
+
+value = algorithmic bytes of all Lanczos step launches in the timed steps
+divided by the timed wall-clock (GB/s).  Algorithmic bytes of one step
+launch: 4 (n + 1) + nnz (4 + 4) + 3 n m 4 (CSR once; v_j gathered once,
+v_{j-1} read once, v_{j+1} written once).  The roofline object reports the
+same bytes over the step kernel's own HIP-event time.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|tiny|probing]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "runtime.hip"):
+        with open(os.path.join(ROOT, "paper_2212_09642_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary
+    (null when missing or taken on a different kernel source)."""
+    path = os.path.join(ROOT, "profiles", "lanczos_step_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def reorder_csr(g, how):
+    """Relabel the rows of a registered-form CSR (experiment: locality of the
+    gathers).  Row keys keep the original node ids, so the probes are the same."""
+    import numpy as np
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    A = sp.csr_matrix((g["values"], g["col_idx"], g["row_ptr"]), shape=(g["n"], g["n"]))
+    if how == "rcm":
+        perm = reverse_cuthill_mckee(A, symmetric_mode=True)
+    elif how == "degree":
+        deg = np.diff(g["row_ptr"])
+        perm = np.argsort(-deg, kind="stable")
+    else:
+        raise SystemExit("unknown reorder %s" % how)
+    B = A[perm][:, perm].tocsr()
+    B.sort_indices()
+    return dict(n=g["n"], row_ptr=B.indptr.astype(np.int32), col_idx=B.indices.astype(np.int32),
+                values=B.data.astype(g["values"].dtype), node_ids=g["node_ids"][perm], scale=g["scale"])
+
+
+def build_workload(name, reorder=None):
+    import numpy as np
+    import paper_2212_09642_amd as vne
+    from synth import workloads
+    if name == "large":
+        w = workloads.large()
+        m = w["n_sketch"] + w["n_hutch"]
+        spec = dict(kind=vne.PROBE_HUTCHPP, m=m, k=w["k"], mode=vne.MODE_DESING,
+                    seed=w["probe_seed"], n_sketch=w["n_sketch"])
+    elif name == "tiny":
+        w = workloads.tiny()
+        spec = dict(kind=vne.PROBE_RADEMACHER, m=w["m"], k=w["k"],
+                    mode=vne.MODE_DESING | vne.MODE_F64, seed=w["probe_seed"], n_sketch=0)
+    elif name == "probing":
+        w = workloads.probing()
+        spec = dict(kind=vne.PROBE_COLORING, m=None, k=w["k"], mode=vne.MODE_DESING, seed=0,
+                    n_sketch=0)
+    else:
+        raise SystemExit("unknown workload %s" % name)
+    fp64 = bool(spec["mode"] & vne.MODE_F64)
+    g = vne.laplacian_from_edges(w["n_nodes"], w["edges"], np.float64 if fp64 else np.float32)
+    if reorder:
+        g = reorder_csr(g, reorder)
+    if name == "probing":
+        col, s = vne.color_greedy(g["row_ptr"], g["col_idx"], g["values"], w["d"])
+        spec["colors"] = col
+        spec["m"] = s
+    return w, g, spec
+
+
+def cpu_baseline(g, spec, sample_cols, k):
+    """The oracle (plain FP64 Lanczos + quadrature) on a bounded sample of the
+    same workload: sample_cols Rademacher columns, all k steps."""
+    import numpy as np
+    import oracle
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.asarray(g["values"], np.float64) * g["scale"], g["col_idx"], g["row_ptr"]),
+                      shape=(g["n"], g["n"]))
+    B = oracle.rademacher_block(spec["seed"], g["node_ids"], np.arange(sample_cols))
+    t0 = time.perf_counter()
+    oracle.quadforms(A, B, k, oracle.breakdown_tau(False))
+    dt = time.perf_counter() - t0
+    n, nnz = g["n"], len(g["col_idx"])
+    bytes_equiv = k * (4.0 * (n + 1) + nnz * 8.0 + 3.0 * n * sample_cols * 4.0)
+    return dict(value=bytes_equiv / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
+                sample="oracle Lanczos + Gauss quadrature on %d Rademacher columns x %d steps "
+                       "of the same graph (%.1f s); GB/s counts the bytes the FP32 path would move "
+                       "for the same steps" % (sample_cols, k, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--cpu-sample-cols", type=int, default=24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--reorder", default=None, help="experiment: relabel rows (rcm | degree)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 2 GiB device copy (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2212_09642_amd as vne
+
+    if args.copy_calibration:
+        x = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": x.numel() * 4, "copies": 3}))
+        return
+
+    w, g, spec = build_workload(args.workload, args.reorder)
+    n, nnz = g["n"], len(g["col_idx"])
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = vne.Context(0, stream=stream)
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+
+    def one():
+        return ctx.estimate(gid, spec["kind"], spec["m"], spec["k"], spec["mode"], seed=spec["seed"],
+                            n_sketch=spec["n_sketch"], colors=spec.get("colors"), want_coeffs=False)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    ctx.enable_kernel_timing(True)
+    ctx.kernel_timing(reset=True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        out = one()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_timing(reset=True)
+    ctx.enable_kernel_timing(False)
+
+    value = kt["bytes"] / wall / 1e9
+    achieved = kt["bytes"] / (kt["total_ms"] / 1e3) / 1e9 if kt["total_ms"] > 0 else 0.0
+    traffic = load_traffic(w["name"])
+    fp64 = bool(spec["mode"] & vne.MODE_F64)
+    res = {
+        "metric": "Lanczos SpMM GB/s (% HBM peak); entropy queries/s + p99 latency at 1e-3 rel",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if fp64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n": n, "nnz": nnz, "m": spec["m"], "k": spec["k"],
+                   "estimator": {vne.PROBE_HUTCHPP: "hutch++", vne.PROBE_RADEMACHER: "hutchinson",
+                                 vne.PROBE_COLORING: "probing"}[spec["kind"]],
+                   "n_sketch": spec["n_sketch"], "graph_seed": None, "probe_seed": spec["seed"]},
+        "queries_per_s": round(args.steps / wall, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+        "estimate": out["estimate"],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_lanczos_step", "launches": kt["launches"],
+                     "avg_launch_ms": round(kt["total_ms"] / max(kt["launches"], 1), 5),
+                     "algorithmic_bytes_per_launch": round(kt["bytes"] / max(kt["launches"], 1))},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline and args.workload in ("large", "tiny"):
+        res["cpu_baseline"] = cpu_baseline(g, spec, min(args.cpu_sample_cols, spec["m"]), spec["k"])
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -107,11 +107,15 @@ Schedule build_schedule(const int32_t *row_ptr, int64_t n, int32_t seg_len, int6
     int64_t nb = std::max<int64_t>(1, (total + cost_per_block - 1) / cost_per_block);
     nb = std::min<int64_t>(nb, std::max<int32_t>(1, max_blocks));
     nb = std::min<int64_t>(nb, std::max<int64_t>(1, n_items));
+    // a multiple of 8 (the 8 XCDs each take a contiguous range); blocks past
+    // the cost-balanced ones are empty
+    const int64_t nb_work = nb;
+    nb = (nb + 7) / 8 * 8;
     s.block_begin.assign(nb + 1, 0);
     int64_t acc = 0, b = 1;
-    for (int64_t t = 0; t < n_items && b < nb; ++t) {
+    for (int64_t t = 0; t < n_items && b < nb_work; ++t) {
         acc += cost[t];
-        while (b < nb && acc * nb >= b * total) s.block_begin[b++] = (int32_t)(t + 1);
+        while (b < nb_work && acc * nb_work >= b * total) s.block_begin[b++] = (int32_t)(t + 1);
     }
     while (b < nb) s.block_begin[b++] = (int32_t)n_items;
     s.block_begin[nb] = (int32_t)n_items;

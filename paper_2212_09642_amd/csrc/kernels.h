@@ -11,6 +11,7 @@ namespace vne {
 
 constexpr int kMaxSteps = 128;     // largest k_steps the quadrature kernels accept
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
+constexpr int kStepThreads = 256;  // threads per block of the Lanczos step kernel
 
 enum ProbeGen { GEN_RADEMACHER = 0, GEN_COLORING = 1, GEN_DENSE = 2 };
 
@@ -28,6 +29,8 @@ struct StepArgs {
     const void *P_in;           // raw vector P_j (n x m_pad)
     const void *V_prev;         // v_{j-1} (ignored on the first step)
     void *V_out;                // v_j, written
+    const void *V_cur;          // two-pass schedule: v_j as written by the normalize pass
+    int32_t two_pass;           // 0: lazy schedule, 1: normalize pass + single-stream SpMM
     void *P_out;                // P_{j+1} = A v_j - beta_{j-1} v_{j-1}, written
     const double *st_alpha;     // per column alpha_{j-1}
     const double *st_inv;       // per column 1/beta_{j-1} (1/||c|| at j = 1; 0 frozen)
@@ -38,16 +41,20 @@ struct StepArgs {
     const int32_t *block_begin;
     int32_t n_blocks;
     double *seg_acc;            // [n_seg][m_pad]
-    int32_t *tickets;           // [n_long][n_tiles]
+    int32_t n_long;             // rows split into segments
     const int32_t *long_first;
     const int32_t *long_nseg;
     double *long_part;          // [n_long][3][m_pad]
-    double *partials;           // [n_tiles][n_blocks][3][mt]
+    double *partials;           // [n_blocks][3][m_pad]
 };
+
+constexpr int kLevel2 = 32;       // first-level reduction rows of the step partials
 
 struct FinalizeArgs {
     const double *partials;
     const double *long_part;
+    double *level2;             // [n_level2][3][m_pad]
+    int32_t n_level2;
     int32_t n_blocks;
     int32_t n_long;
     int32_t mt;
@@ -66,6 +73,7 @@ struct FinalizeArgs {
 int choose_tile(int m, bool fp64, int requested);
 int pad_columns(int m, int mt);
 
+// [normalize pass,] step kernel, then (if the matrix has long rows) the long-row kernel
 hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 
@@ -100,20 +108,23 @@ hipError_t launch_rademacher_fill(void *out, bool fp64, int32_t n, int32_t m, in
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
                              const double *norm2, int32_t k, int32_t m, double *psi,
                              int32_t *flags, hipStream_t s);
-// f(T) e1 for every column (rows >= k_eff are 0): S[c*k + r]
+// f(T) e1 for every column (rows >= k_eff are 0), step-major: S[r*m + c]; rot_scratch
+// holds rot_capacity(k) recorded rotations (24 bytes each) per column
+__host__ __device__ int64_t rot_capacity(int32_t k);
+constexpr int64_t kRotBytes = 24;
 hipError_t launch_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff,
-                        int32_t k, int32_t m, double *S, int32_t *flags, hipStream_t s);
+                        int32_t k, int32_t m, double *S, void *rot_scratch, int32_t *flags,
+                        hipStream_t s);
 
 // estimate from psi: kind 0 mean, 1 sum, 2 Hutch++ (first n_sketch summed,
 // rest averaged)
 hipError_t launch_combine(const double *psi, int32_t m, int32_t kind, int32_t n_sketch,
                           double *estimate, hipStream_t s);
 
-// Y[i*ldy + c] = sqrt(norm2[c]) * sum_j S[c*k+j] Vstore[j][i*ldv + c]
+// Y[i*ldy + c] = sqrt(norm2[c]) * sum_j S[j*m + c] Vstore[j][i*ldv + c]  (m <= 128)
 hipError_t launch_reconstruct(const void *Vstore, bool fp64, int64_t step_stride, int32_t ldv,
-                              const double *S, const double *norm2, const int32_t *k_eff,
-                              int32_t k, int32_t n, int32_t m, void *Y, int32_t ldy,
-                              hipStream_t s);
+                              const double *S, const double *norm2, int32_t k, int32_t n,
+                              int32_t m, void *Y, int32_t ldy, hipStream_t s);
 
 // out[a*nb + b] = sum_i X[i*ldx + a] * Y[i*ldy + b] (FP64 accumulation);
 // uses part (scratch, [chunks][na][nb] doubles, see gram_scratch_doubles)
@@ -121,7 +132,8 @@ int64_t gram_scratch_doubles(int32_t n, int32_t na, int32_t nb);
 hipError_t launch_gram(const void *X, int32_t ldx, const void *Y, int32_t ldy, bool fp64,
                        int32_t n, int32_t na, int32_t nb, double *part, double *out,
                        hipStream_t s);
-// in-place upper Cholesky of G (na x na, FP64) and its inverse Rinv; flags bit 1 on failure
+// upper Cholesky factor of G (na x na, FP64, na <= 128) and its inverse Rinv;
+// flags bit 1 when a pivot is not positive
 hipError_t launch_cholinv(double *G, double *Rinv, int32_t na, int32_t *flags, hipStream_t s);
 // Z[i*ldz + b] = (sub ? Z[i*ldz + b] : 0) + sign * sum_a X[i*ldx + a] * M[a*nb + b]
 // (row-local: in place when Z aliases X is allowed only for sub == 0)

@@ -8,6 +8,7 @@
 // reproducible for a given launch shape.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -95,100 +96,100 @@ __device__ __forceinline__ double block_sum_256(double v, double *sh) {
 // Lanczos step: u = A v_j on the CSR (gathering m-vectors), recurrence
 // w = u - beta_{j-1} v_{j-1}, and the FP64 partial sums v.w, w.w, v.v per
 // column; v_j is materialised on the fly from (P_j, v_{j-1}) and written.
+// A lane group of LPR lanes owns one row (or row segment) and MT = CPL * LPR
+// columns of the tile; each lane holds CPL consecutive columns.
 // ---------------------------------------------------------------------------
 
-template <typename T, int CPL, int LPR, bool FIRST>
-__global__ void __launch_bounds__(256) k_lanczos_step(StepArgs a) {
-    constexpr int MT = CPL * LPR;
-    constexpr int GPW = 64 / LPR;        // lane groups per wave
-    constexpr int NG = 4 * GPW;          // lane groups per block
-    constexpr int U = (CPL == 4) ? 4 : 4;
-    __shared__ double red[3][NG * MT];
-
-    const int nb_total = gridDim.x * gridDim.y;
-    const int lin = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, nb_total);
-    const int tile = lin / a.n_blocks;
-    const int b = lin % a.n_blocks;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int grp = lane / LPR;
-    const int gl = lane % LPR;
-    const int gid = wave * GPW + grp;
-    const int c0 = tile * MT + gl * CPL;
-    const int64_t ld = a.m_pad;
-
-    const T *P_in = static_cast<const T *>(a.P_in);
-    const T *V_prev = static_cast<const T *>(a.V_prev);
-    T *V_out = static_cast<T *>(a.V_out);
-    T *P_out = static_cast<T *>(a.P_out);
-    const T *val = static_cast<const T *>(a.val);
-
+// TWO = false (lazy schedule): v_j is never stored before the SpMM; every
+// entry of it, at a neighbour or at the row itself, is evaluated from P_j and
+// v_{j-1}, and the step also writes v_j.  TWO = true (two-pass schedule): a
+// streaming pass has already written v_j (k_normalize), and the SpMM gathers
+// v_j alone.  Both evaluate every entry of v_j with the same expression, so
+// the two schedules give bitwise identical results.
+template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
+struct StepCore {
+    static constexpr int MT = CPL * LPR;
+    const StepArgs &a;
+    int c0;
+    int64_t ld;
+    const T *P_in, *V_prev, *V_cur, *val;
+    T *V_out, *P_out;
     T al[CPL], inv[CPL];
     double coup[CPL];
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-        al[k] = (T)a.st_alpha[c0 + k];
-        inv[k] = (T)a.st_inv[c0 + k];
-        coup[k] = a.st_coup[c0 + k];
-    }
-    double s_vw[CPL], s_ww[CPL], s_vv[CPL];
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) s_vw[k] = s_ww[k] = s_vv[k] = 0.0;
 
-    // one row (or row segment): acc = sum_p val[p] * v_j[col[p], cols]
-    auto gather = [&](int p0, int p1, double (&acc)[CPL]) {
+    __device__ __forceinline__ StepCore(const StepArgs &args, int tile, int gl) : a(args) {
+        c0 = tile * MT + gl * CPL;
+        ld = a.m_pad;
+        P_in = static_cast<const T *>(a.P_in);
+        V_prev = static_cast<const T *>(a.V_prev);
+        V_cur = static_cast<const T *>(a.V_cur);
+        V_out = static_cast<T *>(a.V_out);
+        P_out = static_cast<T *>(a.P_out);
+        val = static_cast<const T *>(a.val);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            al[k] = (T)a.st_alpha[c0 + k];
+            inv[k] = (T)a.st_inv[c0 + k];
+            coup[k] = a.st_coup[c0 + k];
+        }
+    }
+
+    // acc = sum over entries p in [p0, p1) of val[p] * v_j[col[p], cols], in
+    // batches of U entries whose loads are all in flight together; batch
+    // slots past the end point at the row itself with a zero weight
+    __device__ __forceinline__ void gather(int row, int p0, int p1, double (&acc)[CPL]) const {
+        constexpr int U = 8;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
-        int p = p0;
-        for (; p + U <= p1; p += U) {
+        for (int p = p0; p < p1; p += U) {
             int jj[U];
             T vv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                jj[u] = a.col[p + u];
-                vv[u] = val[p + u];
+                const bool ok = p + u < p1;
+                jj[u] = ok ? a.col[p + u] : row;
+                vv[u] = ok ? val[p + u] : (T)0;
             }
             T pv[U][CPL], qv[U][CPL];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                load_vec<T, CPL>(P_in + (int64_t)jj[u] * ld + c0, pv[u]);
-                if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)jj[u] * ld + c0, qv[u]);
+                if (TWO) {
+                    load_vec<T, CPL>(V_cur + (int64_t)jj[u] * ld + c0, pv[u]);
+                } else {
+                    load_vec<T, CPL>(P_in + (int64_t)jj[u] * ld + c0, pv[u]);
+                    if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)jj[u] * ld + c0, qv[u]);
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
 #pragma unroll
                 for (int k = 0; k < CPL; ++k) {
-                    T v = materialize(pv[u][k], FIRST ? (T)0 : qv[u][k], al[k], inv[k]);
+                    const T v = TWO ? pv[u][k] : materialize(pv[u][k], FIRST ? (T)0 : qv[u][k], al[k], inv[k]);
                     acc[k] = fma((double)vv[u], (double)v, acc[k]);
                 }
             }
         }
-        for (; p < p1; ++p) {
-            const int j = a.col[p];
-            const T vv = val[p];
-            T pv[CPL], qv[CPL];
-            load_vec<T, CPL>(P_in + (int64_t)j * ld + c0, pv);
-            if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)j * ld + c0, qv);
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                T v = materialize(pv[k], FIRST ? (T)0 : qv[k], al[k], inv[k]);
-                acc[k] = fma((double)vv, (double)v, acc[k]);
-            }
-        }
-    };
+    }
 
-    // finish a row: w = scale*acc - beta_{j-1} v_{j-1}; store P_{j+1}, v_j;
-    // return the row's contributions to v.w, w.w, v.v
-    auto finish = [&](int row, const double (&acc)[CPL], double (&dvw)[CPL], double (&dww)[CPL],
-                      double (&dvv)[CPL]) {
-        T pv[CPL], qv[CPL], v[CPL], wr[CPL];
-        load_vec<T, CPL>(P_in + (int64_t)row * ld + c0, pv);
+    // the row's own entries: pv = P_j (lazy) or v_j (two-pass), qv = v_{j-1}
+    __device__ __forceinline__ void load_self(int row, T (&pv)[CPL], T (&qv)[CPL]) const {
+        load_vec<T, CPL>((TWO ? V_cur : P_in) + (int64_t)row * ld + c0, pv);
         if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)row * ld + c0, qv);
+        else
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) qv[k] = (T)0;
+    }
+
+    // w = scale*acc - beta_{j-1} v_{j-1}; store P_{j+1} (and v_j, lazy); the
+    // row's contributions to v.w, w.w, v.v
+    __device__ __forceinline__ void finish(int row, const T (&pv)[CPL], const T (&qv)[CPL],
+                                           const double (&acc)[CPL], double (&dvw)[CPL],
+                                           double (&dww)[CPL], double (&dvv)[CPL]) const {
+        T v[CPL], wr[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-            const T q = FIRST ? (T)0 : qv[k];
-            v[k] = materialize(pv[k], q, al[k], inv[k]);
-            const double w = fma(-coup[k], (double)q, a.scale * acc[k]);
+            v[k] = TWO ? pv[k] : materialize(pv[k], qv[k], al[k], inv[k]);
+            const double w = fma(-coup[k], (double)qv[k], a.scale * acc[k]);
             wr[k] = (T)w;
             const double vd = (double)v[k], wd = (double)wr[k];
             dvw[k] = vd * wd;
@@ -196,35 +197,84 @@ __global__ void __launch_bounds__(256) k_lanczos_step(StepArgs a) {
             dvv[k] = vd * vd;
         }
         store_vec<T, CPL>(P_out + (int64_t)row * ld + c0, wr);
-        store_vec<T, CPL>(V_out + (int64_t)row * ld + c0, v);
-    };
+        if (!TWO) store_vec<T, CPL>(V_out + (int64_t)row * ld + c0, v);
+    }
+};
+
+// Two-pass schedule, first pass: v_j = (P_j - alpha_{j-1} v_{j-1}) / beta_{j-1}
+// for every entry, streaming, CPL consecutive columns per thread.
+template <typename T, int CPL, bool FIRST>
+__global__ void __launch_bounds__(256) k_normalize(StepArgs a) {
+    const T *P = static_cast<const T *>(a.P_in);
+    const T *Vp = static_cast<const T *>(a.V_prev);
+    T *Vo = static_cast<T *>(a.V_out);
+    const int64_t groups = (int64_t)a.n * (a.m_pad / CPL);
+    const int cg = a.m_pad / CPL;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < groups; t += (int64_t)gridDim.x * 256) {
+        const int64_t i = t / cg;
+        const int c0 = (int)(t % cg) * CPL;
+        T pv[CPL], qv[CPL], v[CPL];
+        load_vec<T, CPL>(P + i * a.m_pad + c0, pv);
+        if (!FIRST) load_vec<T, CPL>(Vp + i * a.m_pad + c0, qv);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+            v[k] = materialize(pv[k], FIRST ? (T)0 : qv[k], (T)a.st_alpha[c0 + k], (T)a.st_inv[c0 + k]);
+        store_vec<T, CPL>(Vo + i * a.m_pad + c0, v);
+    }
+}
+
+template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
+__global__ void __launch_bounds__(kStepThreads) k_lanczos_step(StepArgs a) {
+    using Core = StepCore<T, CPL, LPR, FIRST, TWO>;
+    constexpr int MT = Core::MT;
+    constexpr int GPW = 64 / LPR;                    // lane groups per wave
+    constexpr int NG = (kStepThreads / 64) * GPW;    // lane groups per block
+    __shared__ double red[3][NG * MT];
+
+    // column tiles are dispatched one after the other (tile-major grid), so
+    // the gathered block of one tile stays resident in the last-level cache;
+    // within a tile each XCD takes one contiguous range of row blocks
+    // (n_blocks is a multiple of 8)
+    const int tile = blockIdx.y;
+    const int b = xcd_remap(blockIdx.x, a.n_blocks);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int grp = lane / LPR;
+    const int gl = lane % LPR;
+    const int gid = wave * GPW + grp;
+    const Core core(a, tile, gl);
+
+    double s_vw[CPL], s_ww[CPL], s_vv[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) s_vw[k] = s_ww[k] = s_vv[k] = 0.0;
 
     const int ib = a.block_begin[b], ie = a.block_begin[b + 1];
     for (int it = ib + gid; it < ie; it += NG) {
-        int row, p0, p1, lrow = -1;
-        if (it < a.n_seg) {
+        int row, p0, p1;
+        const bool seg = it < a.n_seg;
+        if (seg) {
             const SegItem s = a.segs[it];
             row = s.row;
             p0 = s.p0;
             p1 = s.p1;
-            lrow = s.lrow;
         } else {
             row = it - a.n_seg;
             p0 = a.row_ptr[row];
             p1 = a.row_ptr[row + 1];
-            if (p1 - p0 > a.seg_len) continue;
+            if (p1 - p0 > a.seg_len) continue;      // long row: done by its segments
         }
         if (LPR == 64) {
             row = __builtin_amdgcn_readfirstlane(row);
             p0 = __builtin_amdgcn_readfirstlane(p0);
             p1 = __builtin_amdgcn_readfirstlane(p1);
-            lrow = __builtin_amdgcn_readfirstlane(lrow);
         }
         double acc[CPL];
-        gather(p0, p1, acc);
-        if (lrow < 0) {
+        if (!seg) {
+            T pv[CPL], qv[CPL];
+            core.load_self(row, pv, qv);
+            core.gather(row, p0, p1, acc);
             double dvw[CPL], dww[CPL], dvv[CPL];
-            finish(row, acc, dvw, dww, dvv);
+            core.finish(row, pv, qv, acc, dvw, dww, dvv);
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
                 s_vw[k] += dvw[k];
@@ -232,38 +282,12 @@ __global__ void __launch_bounds__(256) k_lanczos_step(StepArgs a) {
                 s_vv[k] += dvv[k];
             }
         } else {
-            // long row: publish this segment's partial product; the last
-            // segment to arrive adds all segments in order and finishes the row
-            double *dst = a.seg_acc + (int64_t)it * ld + c0;
+            // segment of a long row: its partial product is finished by
+            // k_long_rows after this kernel (the kernel boundary orders it)
+            core.gather(row, p0, p1, acc);
+            double *dst = a.seg_acc + (int64_t)it * core.ld + core.c0;
 #pragma unroll
             for (int k = 0; k < CPL; ++k) dst[k] = acc[k];
-            __threadfence();
-            int old = 0;
-            if (gl == 0) old = atomicAdd(&a.tickets[lrow * a.n_tiles + tile], 1);
-            old = __shfl(old, grp * LPR, 64);
-            const int nseg = a.long_nseg[lrow];
-            if (old == nseg - 1) {
-                __threadfence();
-                const int first = a.long_first[lrow];
-                double tot[CPL];
-#pragma unroll
-                for (int k = 0; k < CPL; ++k) tot[k] = 0.0;
-                for (int sgi = 0; sgi < nseg; ++sgi) {
-                    const volatile double *src = a.seg_acc + (int64_t)(first + sgi) * ld + c0;
-#pragma unroll
-                    for (int k = 0; k < CPL; ++k) tot[k] += src[k];
-                }
-                double dvw[CPL], dww[CPL], dvv[CPL];
-                finish(row, tot, dvw, dww, dvv);
-                double *lp = a.long_part + (int64_t)lrow * 3 * ld + c0;
-#pragma unroll
-                for (int k = 0; k < CPL; ++k) {
-                    lp[k] = dvw[k];
-                    lp[ld + k] = dww[k];
-                    lp[2 * ld + k] = dvv[k];
-                }
-                if (gl == 0) a.tickets[lrow * a.n_tiles + tile] = 0;
-            }
         }
     }
 
@@ -275,38 +299,108 @@ __global__ void __launch_bounds__(256) k_lanczos_step(StepArgs a) {
         red[2][gid * MT + gl * CPL + k] = s_vv[k];
     }
     __syncthreads();
-    double *out = a.partials + ((int64_t)tile * a.n_blocks + b) * 3 * MT;
-    for (int t = threadIdx.x; t < 3 * MT; t += 256) {
+    // partials layout [n_blocks][3][m_pad]: the finalize reads whole rows
+    double *out = a.partials + (int64_t)b * 3 * a.m_pad + tile * MT;
+    for (int t = threadIdx.x; t < 3 * MT; t += kStepThreads) {
         const int sidx = t / MT, cc = t % MT;
         double sum = 0.0;
 #pragma unroll 4
         for (int g = 0; g < NG; ++g) sum += red[sidx][g * MT + cc];
-        out[t] = sum;
+        out[(int64_t)sidx * a.m_pad + cc] = sum;
+    }
+}
+
+// Long rows: add the segment partial products in segment order and finish
+// the row; its dot-product contributions go to a slot of its own.
+template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
+__global__ void __launch_bounds__(256) k_long_rows(StepArgs a) {
+    using Core = StepCore<T, CPL, LPR, FIRST, TWO>;
+    constexpr int GPW = 64 / LPR;
+    constexpr int NG = 4 * GPW;
+    const int tile = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / LPR;
+    const int gl = lane % LPR;
+    const int L = blockIdx.x * NG + (threadIdx.x >> 6) * GPW + grp;
+    if (L >= a.n_long) return;
+    const Core core(a, tile, gl);
+    const int first = a.long_first[L], nseg = a.long_nseg[L];
+    const int row = a.segs[first].row;
+    double tot[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) tot[k] = 0.0;
+    constexpr int UQ = 8;
+    int q = 0;
+    for (; q + UQ <= nseg; q += UQ) {
+        double buf[UQ][CPL];
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) {
+            const double *src = a.seg_acc + (int64_t)(first + q + u) * core.ld + core.c0;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) buf[u][k] = src[k];
+        }
+#pragma unroll
+        for (int u = 0; u < UQ; ++u)
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) tot[k] += buf[u][k];
+    }
+    for (; q < nseg; ++q) {
+        const double *src = a.seg_acc + (int64_t)(first + q) * core.ld + core.c0;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) tot[k] += src[k];
+    }
+    T pv[CPL], qv[CPL];
+    core.load_self(row, pv, qv);
+    double dvw[CPL], dww[CPL], dvv[CPL];
+    core.finish(row, pv, qv, tot, dvw, dww, dvv);
+    double *lp = a.long_part + (int64_t)L * 3 * core.ld + core.c0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        lp[k] = dvw[k];
+        lp[core.ld + k] = dww[k];
+        lp[2 * core.ld + k] = dvv[k];
     }
 }
 
 int choose_tile(int m, bool fp64, int requested) {
+    // column tile = CPL * LPR; by default at most 128 FP32 (64 FP64) columns,
+    // the widest tile whose gathered block stays cache friendly on large graphs
     const int cpl = fp64 ? 2 : 4;
     const int maxt = cpl * 64, mint = cpl * 4;
-    if (requested > 0) {
-        int t = mint;
-        while (t < requested && t < maxt) t *= 2;
-        return t;
-    }
+    const int cap = requested > 0 ? maxt : (fp64 ? 64 : 128);
+    const int want = requested > 0 ? requested : m;
     int t = mint;
-    while (t < m && t < maxt) t *= 2;
+    while (t < want && t < cap) t *= 2;
     return t;
 }
 
 int pad_columns(int m, int mt) { return ((m + mt - 1) / mt) * mt; }
 
+template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
+static void launch_step_k(const StepArgs &a, hipStream_t s) {
+    if (TWO) {
+        const int64_t groups = (int64_t)a.n * (a.m_pad / CPL);
+        const unsigned nb = (unsigned)std::min<int64_t>((groups + 255) / 256, 8192);
+        hipLaunchKernelGGL((k_normalize<T, CPL, FIRST>), dim3(nb), dim3(256), 0, s, a);
+    }
+    dim3 grid(a.n_blocks, a.n_tiles);
+    hipLaunchKernelGGL((k_lanczos_step<T, CPL, LPR, FIRST, TWO>), grid, dim3(kStepThreads), 0, s, a);
+    if (a.n_long > 0) {
+        constexpr int NG = 4 * (64 / LPR);
+        dim3 lg((a.n_long + NG - 1) / NG, a.n_tiles);
+        hipLaunchKernelGGL((k_long_rows<T, CPL, LPR, FIRST, TWO>), lg, dim3(256), 0, s, a);
+    }
+}
+
 template <typename T, int CPL, int LPR>
 static hipError_t launch_step_t(const StepArgs &a, bool first, hipStream_t s) {
-    dim3 grid(a.n_blocks, a.n_tiles);
-    if (first)
-        hipLaunchKernelGGL((k_lanczos_step<T, CPL, LPR, true>), grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_lanczos_step<T, CPL, LPR, false>), grid, dim3(256), 0, s, a);
+    if (a.two_pass) {
+        if (first) launch_step_k<T, CPL, LPR, true, true>(a, s);
+        else launch_step_k<T, CPL, LPR, false, true>(a, s);
+    } else {
+        if (first) launch_step_k<T, CPL, LPR, true, false>(a, s);
+        else launch_step_k<T, CPL, LPR, false, false>(a, s);
+    }
     return hipGetLastError();
 }
 
@@ -337,27 +431,71 @@ hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s) 
 // breakdown test and the scalars of the next lazy normalisation.
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
-    __shared__ double sh[256];
-    const int c = blockIdx.x;
-    const int tile = c / a.mt, cc = c % a.mt;
+// First level: block (x, r) adds, for 64 columns, the partial rows
+// r, r + R, r + 2R, ... of the step blocks (then of the long rows) in fixed
+// order; the result goes to level2[r][3][m_pad].
+__global__ void __launch_bounds__(256) k_reduce_partials(FinalizeArgs a) {
+    __shared__ double sh[3][4][64];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    const int r = blockIdx.y, R = gridDim.y;
     double s3[3] = {0.0, 0.0, 0.0};
-    for (int bb = threadIdx.x; bb < a.n_blocks; bb += 256) {
-        const double *p = a.partials + ((int64_t)tile * a.n_blocks + bb) * 3 * a.mt + cc;
-        s3[0] += p[0];
-        s3[1] += p[a.mt];
-        s3[2] += p[2 * a.mt];
+    if (c < a.m_pad) {
+        constexpr int UB = 4;
+        const int stride = 4 * R;
+        int bb = r + grp * R;
+        for (; bb + stride * (UB - 1) < a.n_blocks; bb += stride * UB) {
+            double buf[UB][3];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const double *p = a.partials + (int64_t)(bb + stride * u) * 3 * a.m_pad + c;
+                buf[u][0] = p[0];
+                buf[u][1] = p[a.m_pad];
+                buf[u][2] = p[2 * a.m_pad];
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                s3[0] += buf[u][0];
+                s3[1] += buf[u][1];
+                s3[2] += buf[u][2];
+            }
+        }
+        for (; bb < a.n_blocks; bb += stride) {
+            const double *p = a.partials + (int64_t)bb * 3 * a.m_pad + c;
+            s3[0] += p[0];
+            s3[1] += p[a.m_pad];
+            s3[2] += p[2 * a.m_pad];
+        }
+        for (int L = r + grp * R; L < a.n_long; L += stride) {
+            const double *p = a.long_part + (int64_t)L * 3 * a.m_pad + c;
+            s3[0] += p[0];
+            s3[1] += p[a.m_pad];
+            s3[2] += p[2 * a.m_pad];
+        }
     }
-    for (int L = threadIdx.x; L < a.n_long; L += 256) {
-        const double *p = a.long_part + (int64_t)L * 3 * a.m_pad + c;
-        s3[0] += p[0];
-        s3[1] += p[a.m_pad];
-        s3[2] += p[2 * a.m_pad];
+    sh[0][grp][lane] = s3[0];
+    sh[1][grp][lane] = s3[1];
+    sh[2][grp][lane] = s3[2];
+    __syncthreads();
+    if (grp != 0 || c >= a.m_pad) return;
+    double* out = a.level2 + (int64_t)r * 3 * a.m_pad + c;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) out[(int64_t)q * a.m_pad] = sh[q][0][lane] + sh[q][1][lane] + sh[q][2][lane] + sh[q][3][lane];
+}
+
+// Second level and coefficient update: sum the R first-level rows in order,
+// then alpha_j = (v.w)/(v.v), beta_j^2 = w.w - alpha_j (v.w) = ||w - alpha_j v||^2,
+// breakdown test and the scalars of the next normalisation.
+__global__ void __launch_bounds__(64) k_finalize(FinalizeArgs a) {
+    const int c = blockIdx.x * 64 + threadIdx.x;
+    if (c >= a.m_pad) return;
+    double svw = 0.0, sww = 0.0, svv = 0.0;
+    for (int r = 0; r < a.n_level2; ++r) {
+        const double *p = a.level2 + (int64_t)r * 3 * a.m_pad + c;
+        svw += p[0];
+        sww += p[a.m_pad];
+        svv += p[2 * a.m_pad];
     }
-    const double svw = block_sum_256(s3[0], sh);
-    const double sww = block_sum_256(s3[1], sh);
-    const double svv = block_sum_256(s3[2], sh);
-    if (threadIdx.x != 0) return;
     const int j = a.step - 1;
     const double inv_prev = a.st_inv[c];
     if (inv_prev == 0.0 || c >= a.m) {      // frozen earlier, empty or pad column
@@ -391,7 +529,8 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
 }
 
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(a.m_pad), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((a.m_pad + 63) / 64, a.n_level2), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3((a.m_pad + 63) / 64), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -509,129 +648,224 @@ hipError_t launch_rademacher_fill(void *out, bool fp64, int32_t n, int32_t m, in
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric tridiagonal eigenproblem by implicit QR steps with Wilkinson
-// shifts (Golub & Van Loan, implicit symmetric QR step), tracking selected
-// rows of the eigenvector matrix Z (T = Z diag(d) Z^T).  d: diagonal, e:
-// off-diagonal (e[i] couples i and i+1).  NR rows of Z are tracked, row
-// indices rows[0..NR); z[r][*] starts as the unit row e_{rows[r]}^T.
-// Returns false if an eigenvalue needed more than 60 sweeps.
+// Symmetric tridiagonal eigenproblem T = Z diag(theta) Z^T by implicit QR
+// steps with Wilkinson shifts (Golub & Van Loan, implicit symmetric QR step),
+// one wavefront per column.  Lane l keeps rows l and l + 64 of T (diagonal
+// d, off-diagonal e, e[i] coupling i and i+1) and of the tracked first row z
+// of Z in registers; the bulge chase runs wave-uniformly, reading the rows it
+// needs with readlane and writing them back with a lane select.  Deflation is
+// found for all indices at once with a ballot.
 // ---------------------------------------------------------------------------
 
-template <int NR>
-__device__ bool tridiag_qr(double *d, double *e, int n, double (*z)[kMaxSteps]) {
+struct Rot {
+    double c, s;
+    int32_t i, pad;
+};
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// element i (wave-uniform) of a two-register lane-resident vector
+__device__ __forceinline__ double get_row(double lo, double hi, int i) {
+    return i < 64 ? readlane_d(lo, i) : readlane_d(hi, i - 64);
+}
+__device__ __forceinline__ void set_row(double &lo, double &hi, int i, double x, int lane) {
+    if (i < 64) lo = (lane == i) ? x : lo;
+    else hi = (lane == i - 64) ? x : hi;
+}
+
+struct LaneTri {
+    double d0, d1, e0, e1, z0, z1;
+};
+
+// Runs the QR iteration on the first n (<= 128) rows.  Records every rotation
+// in rot[0..cap) when rot != nullptr.  Returns 0 on success, bit 2 if an
+// eigenvalue needed more than 60 sweeps, bit 3 if the record overflowed.
+__device__ int lane_tridiag_qr(LaneTri &t, int n, int lane, Rot *rot, int cap, int *nrot) {
     const double eps = 1.1102230246251565e-16;   // 2^-53
-    int hi = n - 1;
-    int sweeps = 0;
+    int status = 0, cnt = 0;
+    int hi = n - 1, sweeps = 0;
     while (hi > 0) {
-        if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) {
-            e[hi - 1] = 0.0;
+        // negligible off-diagonals, all indices at once
+        double dn0 = __shfl_down(t.d0, 1, 64);
+        const double d64 = readlane_d(t.d1, 0);
+        if (lane == 63) dn0 = d64;
+        const double dn1 = __shfl_down(t.d1, 1, 64);
+        const bool p0 = (lane >= n - 1) || fabs(t.e0) <= eps * (fabs(t.d0) + fabs(dn0)) || fabs(t.e0) < 1e-300;
+        const bool p1 = (lane + 64 >= n - 1) || fabs(t.e1) <= eps * (fabs(t.d1) + fabs(dn1)) ||
+                        fabs(t.e1) < 1e-300;
+        const uint64_t m0 = __ballot(p0), m1 = __ballot(p1);
+        const int b = hi - 1;
+        const bool negl = b < 64 ? ((m0 >> b) & 1ull) : ((m1 >> (b - 64)) & 1ull);
+        if (negl) {
+            set_row(t.e0, t.e1, b, 0.0, lane);
             --hi;
             sweeps = 0;
             continue;
         }
-        int lo = hi - 1;
-        while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
-        if (lo > 0) e[lo - 1] = 0.0;
-        if (++sweeps > 60) return false;
+        // lo = 1 + largest negligible index below hi - 1 (0 if none)
+        int lo = 0;
+        {
+            uint64_t h1 = b > 64 ? (m1 & ((b - 64 >= 64) ? ~0ull : ((1ull << (b - 64)) - 1ull))) : 0ull;
+            uint64_t h0 = b >= 64 ? m0 : (m0 & ((1ull << b) - 1ull));
+            if (h1) lo = 64 + (63 - __builtin_clzll(h1)) + 1;
+            else if (h0) lo = (63 - __builtin_clzll(h0)) + 1;
+        }
+        if (lo > 0) set_row(t.e0, t.e1, lo - 1, 0.0, lane);
+        if (++sweeps > 60) {
+            status |= 4;
+            break;
+        }
         // Wilkinson shift from the trailing 2x2 block
-        const double dl = 0.5 * (d[hi - 1] - d[hi]);
-        const double bh = e[hi - 1];
-        const double den = dl + copysign(hypot(dl, bh), dl == 0.0 ? 1.0 : dl);
-        const double mu = d[hi] - bh * (bh / den);
-        double x = d[lo] - mu, y = e[lo];
+        const double dh1 = get_row(t.d0, t.d1, hi - 1), dh = get_row(t.d0, t.d1, hi);
+        const double bh = get_row(t.e0, t.e1, hi - 1);
+        const double dl = 0.5 * (dh1 - dh);
+        const double rt = sqrt(fma(dl, dl, bh * bh));
+        const double den = dl + (dl < 0.0 ? -rt : rt);
+        const double mu = dh - bh * (bh / den);
+        // bulge chase with the active rows carried in registers
+        double di = get_row(t.d0, t.d1, lo), dj = get_row(t.d0, t.d1, lo + 1);
+        double ei = get_row(t.e0, t.e1, lo);
+        double enx = lo + 1 < hi ? get_row(t.e0, t.e1, lo + 1) : 0.0;
+        double zi = get_row(t.z0, t.z1, lo), zj = get_row(t.z0, t.z1, lo + 1);
+        double x = di - mu, y = ei;
         for (int i = lo; i < hi; ++i) {
-            const double r = hypot(x, y);
-            const double c = r == 0.0 ? 1.0 : x / r;
-            const double s = r == 0.0 ? 0.0 : y / r;
-            if (i > lo) e[i - 1] = r;
-            const double ai = d[i], aj = d[i + 1], bb = e[i];
-            const double cs = c * s, cc = c * c, ss = s * s;
-            d[i] = cc * ai + 2.0 * cs * bb + ss * aj;
-            d[i + 1] = ss * ai - 2.0 * cs * bb + cc * aj;
-            e[i] = cs * (aj - ai) + (cc - ss) * bb;
-            if (i + 1 < hi) {
-                y = s * e[i + 1];
-                e[i + 1] = c * e[i + 1];
-                x = e[i];
+            const double r = sqrt(fma(x, x, y * y));
+            double c = 1.0, s = 0.0;
+            if (r != 0.0) {
+                const double ir = 1.0 / r;
+                c = x * ir;
+                s = y * ir;
             }
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                const double zi = z[q][i], zj = z[q][i + 1];
-                z[q][i] = c * zi + s * zj;
-                z[q][i + 1] = -s * zi + c * zj;
+            if (i > lo) set_row(t.e0, t.e1, i - 1, r, lane);
+            const double cs = c * s, cc = c * c, ss = s * s;
+            const double ndi = fma(cc, di, fma(2.0 * cs, ei, ss * dj));
+            const double ndj = fma(ss, di, fma(-2.0 * cs, ei, cc * dj));
+            const double nei = fma(cs, dj - di, (cc - ss) * ei);
+            const double nzi = fma(c, zi, s * zj);
+            const double nzj = fma(-s, zi, c * zj);
+            set_row(t.d0, t.d1, i, ndi, lane);
+            set_row(t.z0, t.z1, i, nzi, lane);
+            if (rot) {
+                if (cnt < cap) {
+                    if (lane == 0) rot[cnt] = Rot{c, s, i, 0};
+                    ++cnt;
+                } else {
+                    status |= 8;
+                }
+            }
+            if (i + 1 < hi) {
+                y = s * enx;
+                ei = c * enx;
+                x = nei;
+                di = ndj;
+                dj = get_row(t.d0, t.d1, i + 2);
+                enx = i + 2 < hi ? get_row(t.e0, t.e1, i + 2) : 0.0;
+                zi = nzj;
+                zj = get_row(t.z0, t.z1, i + 2);
+            } else {
+                set_row(t.d0, t.d1, i + 1, ndj, lane);
+                set_row(t.e0, t.e1, i, nei, lane);
+                set_row(t.z0, t.z1, i + 1, nzj, lane);
             }
         }
     }
-    return true;
+    if (nrot) *nrot = cnt;
+    return status;
 }
 
-__global__ void __launch_bounds__(64) k_quadrature(const double *alpha, const double *beta,
-                                                   const int32_t *k_eff, const double *norm2, int32_t k,
-                                                   int32_t m, double *psi, int32_t *flags) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void load_tri(LaneTri &t, const double *alpha, const double *beta, int ke, int lane) {
+    t.d0 = lane < ke ? alpha[lane] : 0.0;
+    t.d1 = lane + 64 < ke ? alpha[lane + 64] : 0.0;
+    t.e0 = lane + 1 < ke ? beta[lane] : 0.0;
+    t.e1 = lane + 65 < ke ? beta[lane + 64] : 0.0;
+    t.z0 = lane == 0 ? 1.0 : 0.0;
+    t.z1 = 0.0;
+}
+
+// fixed-order sum over the 64 lanes (butterfly; every lane gets the result)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const double *beta,
+                                                    const int32_t *k_eff, const double *norm2, int32_t k,
+                                                    int32_t m, double *psi, int32_t *flags) {
+    const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
     if (c >= m) return;
-    const int ke = k_eff[c];
+    const int ke = __builtin_amdgcn_readfirstlane(k_eff[c]);
     if (ke <= 0) {
-        psi[c] = 0.0;
+        if (lane == 0) psi[c] = 0.0;
         return;
     }
-    double d[kMaxSteps], e[kMaxSteps];
-    double z[1][kMaxSteps];
-    for (int i = 0; i < ke; ++i) {
-        d[i] = alpha[(int64_t)c * k + i];
-        e[i] = i + 1 < ke ? beta[(int64_t)c * k + i] : 0.0;
-        z[0][i] = i == 0 ? 1.0 : 0.0;
+    LaneTri t;
+    load_tri(t, alpha + (int64_t)c * k, beta + (int64_t)c * k, ke, lane);
+    const int st = lane_tridiag_qr(t, ke, lane, nullptr, 0, nullptr);
+    double part = 0.0;
+    if (lane < ke) part += t.z0 * t.z0 * f_entropy(t.d0);
+    if (lane + 64 < ke) part += t.z1 * t.z1 * f_entropy(t.d1);
+    const double tot = wave_sum(part);
+    if (lane == 0) {
+        psi[c] = norm2[c] * tot;
+        if (st) atomicOr(flags, st);
     }
-    if (!tridiag_qr<1>(d, e, ke, z)) atomicOr(flags, 4);
-    double s = 0.0;
-    for (int i = 0; i < ke; ++i) s += z[0][i] * z[0][i] * f_entropy(d[i]);
-    psi[c] = norm2[c] * s;
 }
 
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
                              const double *norm2, int32_t k, int32_t m, double *psi, int32_t *flags,
                              hipStream_t s) {
     if (k > kMaxSteps) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_quadrature, dim3((m + 63) / 64), dim3(64), 0, s, alpha, beta, k_eff, norm2, k, m,
-                       psi, flags);
+    hipLaunchKernelGGL(k_quadrature, dim3((m + 3) / 4), dim3(256), 0, s, alpha, beta, k_eff, norm2, k, m, psi,
+                       flags);
     return hipGetLastError();
 }
 
-// f(T) e1: one wave per column; lane l tracks rows 0, l and l + 64 of Z
-// (every lane repeats the same QR on its own copy of d, e).
-__global__ void __launch_bounds__(64) k_fT_e1(const double *alpha, const double *beta,
-                                              const int32_t *k_eff, int32_t k, int32_t m, double *S,
-                                              int32_t *flags) {
-    const int c = blockIdx.x;
-    const int l = threadIdx.x;
-    const int ke = k_eff[c];
-    double *out = S + (int64_t)c * k;
-    for (int r = l; r < k; r += 64) out[r] = 0.0;
+__host__ __device__ int64_t rot_capacity(int32_t k) { return 4 * (int64_t)k * k + 64; }
+
+// f(T) e1 = Z f(theta) Z^T e1: QR with the rotations recorded, then the
+// rotations are applied in reverse order to w = f(theta) .* z.
+__global__ void __launch_bounds__(256) k_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff,
+                                               int32_t k, int32_t m, double *S, Rot *rot_buf, int32_t *flags) {
+    const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (c >= m) return;
+    const int ke = __builtin_amdgcn_readfirstlane(k_eff[c]);
+    // S is stored step-major: S[r * m + c]
+    if (lane < k) S[(int64_t)lane * m + c] = 0.0;
+    if (lane + 64 < k) S[(int64_t)(lane + 64) * m + c] = 0.0;
     if (ke <= 0) return;
-    double d[kMaxSteps], e[kMaxSteps];
-    double z[3][kMaxSteps];
-    for (int i = 0; i < ke; ++i) {
-        d[i] = alpha[(int64_t)c * k + i];
-        e[i] = i + 1 < ke ? beta[(int64_t)c * k + i] : 0.0;
-        z[0][i] = i == 0 ? 1.0 : 0.0;
-        z[1][i] = i == l ? 1.0 : 0.0;
-        z[2][i] = i == l + 64 ? 1.0 : 0.0;
+    LaneTri t;
+    load_tri(t, alpha + (int64_t)c * k, beta + (int64_t)c * k, ke, lane);
+    const int cap = (int)rot_capacity(k);
+    Rot *rot = rot_buf + (int64_t)c * cap;
+    int nrot = 0;
+    const int st = lane_tridiag_qr(t, ke, lane, rot, cap, &nrot);
+    double w0 = lane < ke ? f_entropy(t.d0) * t.z0 : 0.0;
+    double w1 = lane + 64 < ke ? f_entropy(t.d1) * t.z1 : 0.0;
+    for (int q = nrot - 1; q >= 0; --q) {
+        const Rot r = rot[q];
+        const int i = __builtin_amdgcn_readfirstlane(r.i);
+        const double a = get_row(w0, w1, i), b = get_row(w0, w1, i + 1);
+        set_row(w0, w1, i, fma(r.c, a, -r.s * b), lane);
+        set_row(w0, w1, i + 1, fma(r.s, a, r.c * b), lane);
     }
-    if (!tridiag_qr<3>(d, e, ke, z) && l == 0) atomicOr(flags, 4);
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = 0; i < ke; ++i) {
-        const double w = f_entropy(d[i]) * z[0][i];
-        s1 += z[1][i] * w;
-        s2 += z[2][i] * w;
-    }
-    if (l < ke) out[l] = s1;
-    if (l + 64 < ke) out[l + 64] = s2;
+    if (lane < ke) S[(int64_t)lane * m + c] = w0;
+    if (lane + 64 < ke) S[(int64_t)(lane + 64) * m + c] = w1;
+    if (lane == 0 && st) atomicOr(flags, st);
 }
 
-hipError_t launch_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff, int32_t k,
-                        int32_t m, double *S, int32_t *flags, hipStream_t s) {
+hipError_t launch_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff, int32_t k, int32_t m,
+                        double *S, void *rot_scratch, int32_t *flags, hipStream_t s) {
     if (k > kMaxSteps) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fT_e1, dim3(m), dim3(64), 0, s, alpha, beta, k_eff, k, m, S, flags);
+    hipLaunchKernelGGL(k_fT_e1, dim3((m + 3) / 4), dim3(256), 0, s, alpha, beta, k_eff, k, m, S,
+                       (Rot *)rot_scratch, flags);
     return hipGetLastError();
 }
 
@@ -666,38 +900,84 @@ hipError_t launch_combine(const double *psi, int32_t m, int32_t kind, int32_t n_
 // Hutch++ pieces
 // ---------------------------------------------------------------------------
 
-template <typename T>
+// Y[i, c] = ||c_c|| sum_j S[j, c] v_j[i, c] (eq. (4.3)).  Thread layout: CPL
+// consecutive columns of RPT rows; a block covers 256 / (m_pad / CPL) * RPT
+// rows and streams the stored basis a few steps at a time.
+template <typename T, int CPL>
 __global__ void __launch_bounds__(256) k_reconstruct(const T *V, int64_t stride, int32_t ldv,
                                                      const double *S, const double *norm2,
-                                                     const int32_t *k_eff, int32_t k, int32_t n,
-                                                     int32_t m, T *Y, int32_t ldy) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (int64_t)n * m) return;
-    const int64_t i = t / m;
-    const int c = (int)(t % m);
-    const int ke = k_eff[c];
-    double acc = 0.0;
-    for (int j = 0; j < ke; ++j) acc = fma(S[(int64_t)c * k + j], (double)V[j * stride + i * ldv + c], acc);
-    Y[i * ldy + c] = (T)(sqrt(norm2[c]) * acc);
+                                                     int32_t k, int32_t n, int32_t m, T *Y, int32_t ldy) {
+    constexpr int RPT = 4, UJ = 2;
+    const int groups = (m + CPL - 1) / CPL;            // column groups per row
+    const int rows_per_pass = 256 / groups;
+    if ((int)threadIdx.x >= rows_per_pass * groups) return;
+    const int cg = threadIdx.x % groups, ro = threadIdx.x / groups;
+    const int c0 = cg * CPL;
+    const int64_t rbase = (int64_t)blockIdx.x * rows_per_pass * RPT + ro;
+    double acc[RPT][CPL];
+    bool ok[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        ok[q] = rbase + (int64_t)q * rows_per_pass < n;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) acc[q][u] = 0.0;
+    }
+    for (int j = 0; j < k; j += UJ) {
+        T vb[UJ][RPT][CPL];
+        double sb[UJ][CPL];
+#pragma unroll
+        for (int t = 0; t < UJ; ++t) {
+            const bool jok = j + t < k;
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) sb[t][u] = (jok && c0 + u < m) ? S[(int64_t)(j + t) * m + c0 + u] : 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t r = rbase + (int64_t)q * rows_per_pass;
+                if (jok && ok[q]) load_vec<T, CPL>(V + (int64_t)(j + t) * stride + r * ldv + c0, vb[t][q]);
+                else
+#pragma unroll
+                    for (int u = 0; u < CPL; ++u) vb[t][q][u] = (T)0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < UJ; ++t)
+#pragma unroll
+            for (int q = 0; q < RPT; ++q)
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) acc[q][u] = fma(sb[t][u], (double)vb[t][q][u], acc[q][u]);
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        if (!ok[q]) continue;
+        const int64_t r = rbase + (int64_t)q * rows_per_pass;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+            if (c0 + u < m) Y[r * ldy + c0 + u] = (T)(sqrt(norm2[c0 + u]) * acc[q][u]);
+    }
 }
 
 hipError_t launch_reconstruct(const void *Vstore, bool fp64, int64_t step_stride, int32_t ldv,
-                              const double *S, const double *norm2, const int32_t *k_eff, int32_t k,
-                              int32_t n, int32_t m, void *Y, int32_t ldy, hipStream_t s) {
-    const int64_t total = (int64_t)n * m;
-    dim3 g((unsigned)((total + 255) / 256));
+                              const double *S, const double *norm2, int32_t k, int32_t n, int32_t m,
+                              void *Y, int32_t ldy, hipStream_t s) {
+    // ldv (the sketch plan's padded width) is a multiple of the vector width
+    const int cpl = fp64 ? 2 : 4;
+    const int groups = (m + cpl - 1) / cpl;
+    if (groups > 256 || ldv % cpl) return hipErrorInvalidValue;
+    const int rows_per_block = (256 / groups) * 4;
+    dim3 g((unsigned)((n + rows_per_block - 1) / rows_per_block));
     if (fp64)
-        hipLaunchKernelGGL(k_reconstruct<double>, g, dim3(256), 0, s, (const double *)Vstore, step_stride,
-                           ldv, S, norm2, k_eff, k, n, m, (double *)Y, ldy);
+        hipLaunchKernelGGL((k_reconstruct<double, 2>), g, dim3(256), 0, s, (const double *)Vstore, step_stride,
+                           ldv, S, norm2, k, n, m, (double *)Y, ldy);
     else
-        hipLaunchKernelGGL(k_reconstruct<float>, g, dim3(256), 0, s, (const float *)Vstore, step_stride, ldv,
-                           S, norm2, k_eff, k, n, m, (float *)Y, ldy);
+        hipLaunchKernelGGL((k_reconstruct<float, 4>), g, dim3(256), 0, s, (const float *)Vstore, step_stride, ldv,
+                           S, norm2, k, n, m, (float *)Y, ldy);
     return hipGetLastError();
 }
 
-// Gram X^T Y: block (tile of 32 x 32 outputs, chunk of rows); each thread
-// owns 4 outputs; rows are staged through LDS 64 at a time.
-constexpr int kGramTile = 32;
+// Gram X^T Y: a block computes a 64 x 64 tile of outputs over a chunk of
+// rows; each thread owns a 4 x 4 sub-tile; rows are staged through LDS 32 at
+// a time.  Products of FP32 inputs are exact in FP64; accumulation is FP64.
+constexpr int kGramTile = 64;
 constexpr int kGramChunk = 2048;
 
 int64_t gram_scratch_doubles(int32_t n, int32_t na, int32_t nb) {
@@ -708,35 +988,50 @@ int64_t gram_scratch_doubles(int32_t n, int32_t na, int32_t nb) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_gram(const T *X, int32_t ldx, const T *Y, int32_t ldy, int32_t n,
                                               int32_t na, int32_t nb, double *part) {
-    __shared__ double xs[64][kGramTile + 1];
-    __shared__ double ys[64][kGramTile + 1];
+    constexpr int RS = 32;
+    __shared__ double xs[RS][kGramTile];
+    __shared__ double ys[RS][kGramTile];
     const int ta = blockIdx.x * kGramTile, tb = blockIdx.y * kGramTile;
     const int chunk = blockIdx.z;
     const int64_t r0 = (int64_t)chunk * kGramChunk;
     const int64_t r1 = min((int64_t)n, r0 + kGramChunk);
-    const int oa = threadIdx.x / 8;           // 0..31
-    const int ob = (threadIdx.x % 8) * 4;     // 0..28
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t rs = r0; rs < r1; rs += 64) {
-        for (int q = threadIdx.x; q < 64 * kGramTile; q += 256) {
+    const int oa = (threadIdx.x / 16) * 4;    // 0..60
+    const int ob = (threadIdx.x % 16) * 4;    // 0..60
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int64_t rs = r0; rs < r1; rs += RS) {
+        for (int q = threadIdx.x; q < RS * kGramTile; q += 256) {
             const int rr = q / kGramTile, cc = q % kGramTile;
             const int64_t r = rs + rr;
             xs[rr][cc] = (r < r1 && ta + cc < na) ? (double)X[r * ldx + ta + cc] : 0.0;
             ys[rr][cc] = (r < r1 && tb + cc < nb) ? (double)Y[r * ldy + tb + cc] : 0.0;
         }
         __syncthreads();
-#pragma unroll 8
-        for (int rr = 0; rr < 64; ++rr) {
-            const double xa = xs[rr][oa];
+#pragma unroll 4
+        for (int rr = 0; rr < RS; ++rr) {
+            double xa[4], yb[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = fma(xa, ys[rr][ob + q], acc[q]);
+            for (int u = 0; u < 4; ++u) {
+                xa[u] = xs[rr][oa + u];
+                yb[u] = ys[rr][ob + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(xa[u], yb[v], acc[u][v]);
         }
         __syncthreads();
     }
     double *out = part + (int64_t)chunk * na * nb;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (ta + oa < na && tb + ob + q < nb) out[(int64_t)(ta + oa) * nb + tb + ob + q] = acc[q];
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (ta + oa + u < na && tb + ob + v < nb)
+                out[(int64_t)(ta + oa + u) * nb + tb + ob + v] = acc[u][v];
 }
 
 __global__ void __launch_bounds__(256) k_gram_reduce(const double *part, int64_t chunks, int64_t total,
@@ -764,87 +1059,116 @@ hipError_t launch_gram(const void *X, int32_t ldx, const void *Y, int32_t ldy, b
     return hipGetLastError();
 }
 
-// Upper Cholesky G = R^T R (in place, one block) and R^{-1} (upper).
-__global__ void __launch_bounds__(256) k_cholinv(double *G, double *Rinv, int32_t na, int32_t *flags) {
+// Upper Cholesky G = R^T R and R^{-1} (upper), one block, G staged in LDS
+// (na <= 128: 128 KB of the 160 KB LDS of a gfx950 CU).  R overwrites the
+// upper triangle; R^{-1} is built in the strict lower triangle (transposed)
+// with its diagonal in dinv, one column per thread.
+__global__ void __launch_bounds__(256) k_cholinv(const double *G_in, double *Rinv, int32_t na, int32_t *flags) {
+    __shared__ double G[128 * 128];
+    __shared__ double dinv[128];
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
+    for (int t = threadIdx.x; t < na * na; t += 256) G[t] = G_in[t];
     __syncthreads();
     for (int j = 0; j < na; ++j) {
-        // R[j][j] and row j of R: G[j][q] for q >= j hold the trailing update
-        __syncthreads();
         if (threadIdx.x == 0) {
-            const double djj = G[(int64_t)j * na + j];
+            const double djj = G[j * na + j];
             if (!(djj > 0.0)) bad = 1;
-            G[(int64_t)j * na + j] = djj > 0.0 ? sqrt(djj) : 1.0;
+            G[j * na + j] = djj > 0.0 ? sqrt(djj) : 1.0;
         }
         __syncthreads();
-        const double rjj = G[(int64_t)j * na + j];
-        for (int q = j + 1 + threadIdx.x; q < na; q += 256) G[(int64_t)j * na + q] /= rjj;
+        const double rjj = G[j * na + j];
+        for (int q = j + 1 + threadIdx.x; q < na; q += 256) G[j * na + q] /= rjj;
         __syncthreads();
-        // trailing update G[p][q] -= R[j][p] R[j][q], p, q > j (upper part)
         const int rem = na - j - 1;
         for (int t = threadIdx.x; t < rem * rem; t += 256) {
             const int p = j + 1 + t / rem, q = j + 1 + t % rem;
-            if (q >= p) G[(int64_t)p * na + q] -= G[(int64_t)j * na + p] * G[(int64_t)j * na + q];
+            if (q >= p) G[p * na + q] -= G[j * na + p] * G[j * na + q];
+        }
+        __syncthreads();
+    }
+    // column col of R^{-1}: x_p = (delta_{p,col} - sum_{q=p+1..col} R[p][q] x_q) / R[p][p],
+    // x_q (q < col) kept at G[col][q], x_col at dinv[col]
+    for (int col = threadIdx.x; col < na; col += 256) {
+        const double xc = 1.0 / G[col * na + col];
+        dinv[col] = xc;
+        for (int p = col - 1; p >= 0; --p) {
+            double acc = G[p * na + col] * xc;
+            for (int q = p + 1; q < col; ++q) acc = fma(G[p * na + q], G[col * na + q], acc);
+            G[col * na + p] = -acc / G[p * na + p];
         }
     }
     __syncthreads();
-    // zero the strict lower part so G holds R
     for (int t = threadIdx.x; t < na * na; t += 256) {
         const int p = t / na, q = t % na;
-        if (q < p) G[t] = 0.0;
-    }
-    __syncthreads();
-    // Rinv column by column: R x = e_col, back substitution
-    for (int col = threadIdx.x; col < na; col += 256) {
-        for (int p = na - 1; p >= 0; --p) {
-            double s = (p == col) ? 1.0 : 0.0;
-            for (int q = p + 1; q <= col; ++q) s -= G[(int64_t)p * na + q] * Rinv[(int64_t)q * na + col];
-            Rinv[(int64_t)p * na + col] = p <= col ? s / G[(int64_t)p * na + p] : 0.0;
-        }
+        Rinv[t] = q > p ? G[q * na + p] : (q == p ? dinv[p] : 0.0);
     }
     if (threadIdx.x == 0 && bad) atomicOr(flags, 2);
 }
 
 hipError_t launch_cholinv(double *G, double *Rinv, int32_t na, int32_t *flags, hipStream_t s) {
+    if (na > 128) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(256), 0, s, G, Rinv, na, flags);
     return hipGetLastError();
 }
 
-// Z = (sub ? Z : 0) + sgn * X M, row-local: a block owns 32 rows, stages its
-// X rows in LDS (FP64) before writing, so Z may alias X when sub == 0.
+// Z = (sub ? Z - X M : X M), row-local: a block owns 32 rows, stages them in
+// LDS (FP64) before anything is written, so Z may alias X when sub == 0; M
+// is staged 32 columns at a time; each thread owns a 2 x 2 output sub-tile.
 template <typename T>
 __global__ void __launch_bounds__(256) k_apply(const T *X, int32_t ldx, const double *M, int32_t na,
                                                int32_t nb, T *Z, int32_t ldz, int32_t n, int32_t sub) {
-    extern __shared__ double xs[];   // [32][na]
+    __shared__ double xs[32][129];
+    __shared__ double ms[128][33];
     const int64_t r0 = (int64_t)blockIdx.x * 32;
     for (int q = threadIdx.x; q < 32 * na; q += 256) {
         const int rr = q / na, cc = q % na;
         const int64_t r = r0 + rr;
-        xs[q] = r < n ? (double)X[r * ldx + cc] : 0.0;
+        xs[rr][cc] = r < n ? (double)X[r * ldx + cc] : 0.0;
     }
-    __syncthreads();
-    for (int q = threadIdx.x; q < 32 * nb; q += 256) {
-        const int rr = q / nb, cc = q % nb;
-        const int64_t r = r0 + rr;
-        if (r >= n) continue;
-        double acc = 0.0;
-        for (int t = 0; t < na; ++t) acc = fma(xs[rr * na + t], M[(int64_t)t * nb + cc], acc);
-        if (sub) Z[r * ldz + cc] = (T)((double)Z[r * ldz + cc] - acc);
-        else Z[r * ldz + cc] = (T)acc;
+    const int tr = (threadIdx.x / 16) * 2;     // rows tr, tr+1
+    const int tc = (threadIdx.x % 16) * 2;     // columns tc, tc+1 of the chunk
+    for (int cb = 0; cb < nb; cb += 32) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < na * 32; q += 256) {
+            const int t = q / 32, cc = q % 32;
+            ms[t][cc] = cb + cc < nb ? M[(int64_t)t * nb + cb + cc] : 0.0;
+        }
+        __syncthreads();
+        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        for (int t = 0; t < na; ++t) {
+            const double x0 = xs[tr][t], x1 = xs[tr + 1][t];
+            const double m0 = ms[t][tc], m1 = ms[t][tc + 1];
+            acc[0][0] = fma(x0, m0, acc[0][0]);
+            acc[0][1] = fma(x0, m1, acc[0][1]);
+            acc[1][0] = fma(x1, m0, acc[1][0]);
+            acc[1][1] = fma(x1, m1, acc[1][1]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t r = r0 + tr + u;
+            if (r >= n) continue;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int cc = cb + tc + v;
+                if (cc >= nb) continue;
+                if (sub) Z[r * ldz + cc] = (T)((double)Z[r * ldz + cc] - acc[u][v]);
+                else Z[r * ldz + cc] = (T)acc[u][v];
+            }
+        }
     }
 }
 
 hipError_t launch_apply(const void *X, int32_t ldx, const double *M, int32_t na, int32_t nb, void *Z,
                         int32_t ldz, bool fp64, int32_t n, int32_t sub, hipStream_t s) {
+    if (na > 128) return hipErrorInvalidValue;
     dim3 g((unsigned)((n + 31) / 32));
-    const size_t shm = (size_t)32 * na * sizeof(double);
     if (fp64)
-        hipLaunchKernelGGL(k_apply<double>, g, dim3(256), shm, s, (const double *)X, ldx, M, na, nb,
-                           (double *)Z, ldz, n, sub);
-    else
-        hipLaunchKernelGGL(k_apply<float>, g, dim3(256), shm, s, (const float *)X, ldx, M, na, nb, (float *)Z,
+        hipLaunchKernelGGL(k_apply<double>, g, dim3(256), 0, s, (const double *)X, ldx, M, na, nb, (double *)Z,
                            ldz, n, sub);
+    else
+        hipLaunchKernelGGL(k_apply<float>, g, dim3(256), 0, s, (const float *)X, ldx, M, na, nb, (float *)Z, ldz,
+                           n, sub);
     return hipGetLastError();
 }
 

@@ -32,9 +32,15 @@ struct Plan {
     int probe_blocks = 0;
     DevBuf P[2], V[2], Vstore;
     DevBuf alpha, beta, st_alpha, st_inv, st_coup, k_eff, norm2, mean, psi, estimate, flags;
-    DevBuf partials, probe_part, seg_acc, tickets, long_part, colors, dense;
+    DevBuf partials, level2, probe_part, seg_acc, long_part, colors, dense;
     // Hutch++ extras (only in the quadratic-form plan of a Hutch++ run)
-    DevBuf S, B, gram_part, gram, rinv;
+    DevBuf S, B, gram_part, gram, rinv, rot;
+    // the k-step loop captured as one HIP graph, per two_pass schedule;
+    // with kernel timing on, one graph per step part instead, so that event
+    // pairs recorded between graph launches bracket the Lanczos step kernels
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    std::vector<hipGraphExec_t> part_exec[2];   // [2k]: step j, finalize j
+    std::vector<hipEvent_t> ev;                 // 2k events
 };
 
 struct Graph {
@@ -50,6 +56,7 @@ struct Graph {
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Plan>> plans;
     bool alive = false;
     bool zero_rowsum = false;            // A 1 = 0 exactly (checked at registration)
+    double local_frac = 0.0;             // off-diagonal entries with |i - j| <= 256
 };
 
 }  // namespace
@@ -57,15 +64,18 @@ struct Graph {
 struct vne_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;    // used when the caller gives no stream
     uint64_t budget = 0, used = 0;
     std::string err;
     std::vector<std::unique_ptr<Graph>> graphs;
     bool timing = false;
     int64_t t_launches = 0;
     double t_ms = 0.0, t_bytes = 0.0;
-    std::vector<hipEvent_t> ev;          // pairs
-    std::vector<double> ev_bytes;        // per pair
-    int ev_used = 0;
+    struct Pending {
+        void *plan;
+        double bytes;
+    };
+    std::vector<Pending> pending;        // timed step loops not yet collected
 };
 
 namespace {
@@ -111,11 +121,23 @@ void dev_free(vne_ctx *c, DevBuf *b) {
 }
 
 void free_plan(vne_ctx *c, Plan *p) {
+    for (auto &e : p->exec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    for (auto &v : p->part_exec) {
+        for (auto &e : v)
+            if (e) (void)hipGraphExecDestroy(e);
+        v.clear();
+    }
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    p->ev.clear();
     DevBuf *all[] = {&p->P[0], &p->P[1], &p->V[0], &p->V[1], &p->Vstore, &p->alpha, &p->beta,
                      &p->st_alpha, &p->st_inv, &p->st_coup, &p->k_eff, &p->norm2, &p->mean, &p->psi,
-                     &p->estimate, &p->flags, &p->partials, &p->probe_part, &p->seg_acc, &p->tickets,
+                     &p->estimate, &p->flags, &p->partials, &p->level2, &p->probe_part, &p->seg_acc,
                      &p->long_part, &p->colors, &p->dense, &p->S, &p->B, &p->gram_part, &p->gram,
-                     &p->rinv};
+                     &p->rinv, &p->rot};
     for (DevBuf *b : all) dev_free(c, b);
 }
 
@@ -190,53 +212,34 @@ vne_status get_plan(vne_ctx *c, Graph *g, int m, int k, bool fp64, bool store, i
     A(&p->psi, cols * 8);
     A(&p->estimate, 8);
     A(&p->flags, 4);
-    A(&p->partials, (size_t)p->n_tiles * s.n_blocks() * 3 * p->mt * 8);
+    A(&p->partials, (size_t)s.n_blocks() * 3 * cols * 8);
+    A(&p->level2, (size_t)kLevel2 * 3 * cols * 8);
     p->probe_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (g->n + 255) / 256));
     A(&p->probe_part, (size_t)p->probe_blocks * cols * 8);
     A(&p->seg_acc, (size_t)std::max(1, s.n_seg) * cols * 8);
-    A(&p->tickets, (size_t)std::max(1, s.n_long) * p->n_tiles * 4);
     A(&p->long_part, (size_t)std::max(1, s.n_long) * 3 * cols * 8);
     if (st != VNE_OK) {
         free_plan(c, p.get());
         return st;
     }
-    HIP_TRY(c, hipMemsetAsync(p->tickets.p, 0, p->tickets.bytes, c->stream));
     HIP_TRY(c, hipMemsetAsync(p->long_part.p, 0, p->long_part.bytes, c->stream));
     *out = p.get();
     g->plans[key] = std::move(p);
     return VNE_OK;
 }
 
-vne_status timed_step(vne_ctx *c, const StepArgs &a, bool fp64, bool first, double bytes) {
-    if (c->timing) {
-        if ((size_t)(c->ev_used + 1) * 2 > c->ev.size()) {
-            for (int q = 0; q < 2; ++q) {
-                hipEvent_t e;
-                HIP_TRY(c, hipEventCreate(&e));
-                c->ev.push_back(e);
-            }
-            c->ev_bytes.push_back(0.0);
-        }
-        HIP_TRY(c, hipEventRecord(c->ev[2 * c->ev_used], c->stream));
-    }
-    HIP_TRY(c, launch_step(a, fp64, first, c->stream));
-    if (c->timing) {
-        HIP_TRY(c, hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
-        c->ev_bytes[c->ev_used] = bytes;
-        c->ev_used++;
-    }
-    return VNE_OK;
-}
-
 vne_status collect_timing(vne_ctx *c) {
-    for (int i = 0; i < c->ev_used; ++i) {
-        float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
-        c->t_ms += ms;
-        c->t_bytes += c->ev_bytes[i];
-        c->t_launches++;
+    for (auto &pd : c->pending) {
+        Plan *p = (Plan *)pd.plan;
+        for (int j = 0; j < p->k; ++j) {
+            float ms = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, p->ev[2 * j], p->ev[2 * j + 1]));
+            c->t_ms += ms;
+            c->t_bytes += pd.bytes;
+            c->t_launches++;
+        }
     }
-    c->ev_used = 0;
+    c->pending.clear();
     return VNE_OK;
 }
 
@@ -300,7 +303,14 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
     a.block_begin = (const int32_t *)g->block_begin.p;
     a.n_blocks = s.n_blocks();
     a.seg_acc = (double *)p->seg_acc.p;
-    a.tickets = (int32_t *)p->tickets.p;
+    a.n_long = s.n_long;
+    // schedule: lazy (4 streams, two gathered) when most neighbours are near
+    // in memory and the gathers hit in cache; otherwise normalize pass +
+    // single-stream SpMM
+    {
+        const int forced = env_int("VNE_SCHED", -1);
+        a.two_pass = forced >= 0 ? forced : (g->local_frac < 0.5 ? 1 : 0);
+    }
     a.long_first = (const int32_t *)g->long_first.p;
     a.long_nseg = (const int32_t *)g->long_nseg.p;
     a.long_part = (double *)p->long_part.p;
@@ -309,6 +319,8 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
     FinalizeArgs f{};
     f.partials = (const double *)p->partials.p;
     f.long_part = (const double *)p->long_part.p;
+    f.level2 = (double *)p->level2.p;
+    f.n_level2 = kLevel2;
     f.n_blocks = s.n_blocks();
     f.n_long = s.n_long;
     f.mt = p->mt;
@@ -324,8 +336,11 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
     f.k_eff = (int32_t *)p->k_eff.p;
     f.flags = (int32_t *)p->flags.p;
 
-    char *Pb[2] = {(char *)p->P[0].p, (char *)p->P[1].p};
-    for (int j = 1; j <= p->k; ++j) {
+    const bool use_graph = env_int("VNE_GRAPH", 1) != 0;
+    const bool timing = c->timing;
+    // part 0: the step kernels of step j; part 1: its reduction and finalize
+    auto issue = [&](int j, int part) -> vne_status {
+        char *Pb[2] = {(char *)p->P[0].p, (char *)p->P[1].p};
         a.P_in = Pb[(j - 1) & 1];
         a.P_out = Pb[j & 1];
         if (p->store) {
@@ -336,10 +351,73 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
             a.V_out = p->V[(j - 1) & 1].p;
             a.V_prev = p->V[j & 1].p;
         }
-        vne_status st = timed_step(c, a, p->fp64, j == 1, bytes);
-        if (st != VNE_OK) return st;
-        f.step = j;
-        HIP_TRY(c, launch_finalize(f, c->stream));
+        a.V_cur = a.V_out;
+        if (part == 0) {
+            HIP_TRY(c, launch_step(a, p->fp64, j == 1, c->stream));
+        } else {
+            f.step = j;
+            HIP_TRY(c, launch_finalize(f, c->stream));
+        }
+        return VNE_OK;
+    };
+    auto capture = [&](hipGraphExec_t *ex, int j0, int j1, int part_only) -> vne_status {
+        hipGraph_t graph = nullptr;
+        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        vne_status st = VNE_OK;
+        for (int j = j0; j <= j1 && st == VNE_OK; ++j)
+            for (int part = 0; part < 2 && st == VNE_OK; ++part)
+                if (part_only < 0 || part == part_only) st = issue(j, part);
+        hipError_t e_end = hipStreamEndCapture(c->stream, &graph);
+        if (st != VNE_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e_end != hipSuccess) return hip_fail(c, e_end, "hipStreamEndCapture");
+        hipError_t e_inst = hipGraphInstantiate(ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e_inst != hipSuccess) {
+            *ex = nullptr;
+            return hip_fail(c, e_inst, "hipGraphInstantiate");
+        }
+        return VNE_OK;
+    };
+    if (timing && p->ev.size() < (size_t)(2 * p->k)) {
+        while (p->ev.size() < (size_t)(2 * p->k)) {
+            hipEvent_t e;
+            HIP_TRY(c, hipEventCreate(&e));
+            p->ev.push_back(e);
+        }
+    }
+    const int sched = a.two_pass ? 1 : 0;
+    vne_status st = VNE_OK;
+    if (use_graph && !timing) {
+        hipGraphExec_t &ex = p->exec[sched];
+        if (!ex && (st = capture(&ex, 1, p->k, -1)) != VNE_OK) return st;
+        HIP_TRY(c, hipGraphLaunch(ex, c->stream));
+    } else if (use_graph) {
+        auto &parts = p->part_exec[sched];
+        if (parts.empty()) {
+            parts.assign(2 * p->k, nullptr);
+            for (int j = 1; j <= p->k; ++j)
+                for (int part = 0; part < 2; ++part)
+                    if ((st = capture(&parts[2 * (j - 1) + part], j, j, part)) != VNE_OK) return st;
+        }
+        for (int j = 1; j <= p->k; ++j) {
+            HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1)], c->stream));
+            HIP_TRY(c, hipGraphLaunch(parts[2 * (j - 1)], c->stream));
+            HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1) + 1], c->stream));
+            HIP_TRY(c, hipGraphLaunch(parts[2 * (j - 1) + 1], c->stream));
+        }
+    } else {
+        for (int j = 1; j <= p->k; ++j) {
+            if (timing) HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1)], c->stream));
+            if ((st = issue(j, 0)) != VNE_OK) return st;
+            if (timing) HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1) + 1], c->stream));
+            if ((st = issue(j, 1)) != VNE_OK) return st;
+        }
+    }
+    if (timing) {
+        c->pending.push_back({p, bytes});
     }
     HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p,
                                  (const int32_t *)p->k_eff.p, (const double *)p->norm2.p, p->k, p->m,
@@ -391,8 +469,17 @@ extern "C" vne_status vne_ctx_create(int device, uint64_t hbm_budget_bytes, void
     }
     auto *c = new vne_ctx();
     c->device = device;
-    c->stream = (hipStream_t)hip_stream;
     c->budget = hbm_budget_bytes;
+    // the legacy null stream cannot be captured into a graph: without a
+    // caller stream the context runs on a stream of its own (blocking, so it
+    // stays ordered with work on the null stream; default priority)
+    e = hipStreamCreate(&c->own_stream);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+        delete c;
+        return VNE_EDEVICE;
+    }
+    c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
     *out = c;
     return VNE_OK;
 }
@@ -403,7 +490,7 @@ extern "C" void vne_ctx_destroy(vne_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (auto &g : c->graphs)
         if (g) free_graph(c, g.get());
-    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
 
@@ -413,7 +500,7 @@ extern "C" const char *vne_last_error(const vne_ctx *c) {
 
 extern "C" vne_status vne_ctx_set_stream(vne_ctx *c, void *hip_stream) {
     if (!c) return VNE_EINVAL;
-    c->stream = (hipStream_t)hip_stream;
+    c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
     return VNE_OK;
 }
 
@@ -466,6 +553,17 @@ extern "C" vne_status vne_graph_register(vne_ctx *c, const vne_csr *csr, uint32_
         v64[p] = v;
         v32[p] = (float)v;
     }
+    {
+        int64_t off = 0, near = 0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int32_t q = hv.row_ptr[i]; q < hv.row_ptr[i + 1]; ++q) {
+                const int64_t j = hv.col_idx[q];
+                if (j == i) continue;
+                ++off;
+                near += (j - i <= 256 && i - j <= 256);
+            }
+        g->local_frac = off ? (double)near / (double)off : 1.0;
+    }
     g->zero_rowsum = true;
     for (int64_t i = 0; i < n && g->zero_rowsum; ++i) {
         double rs = 0.0;
@@ -494,8 +592,8 @@ extern "C" vne_status vne_graph_register(vne_ctx *c, const vne_csr *csr, uint32_
     g->d_keys = (const int64_t *)g->keys.p;
 
     // work schedule: segments of long rows, cost-balanced blocks
-    const int seg_len = std::max(1, env_int("VNE_SEG_LEN", 32));
-    const int max_blocks = std::max(1, env_int("VNE_MAX_BLOCKS", 2048));
+    const int seg_len = std::max(1, env_int("VNE_SEG_LEN", 64));
+    const int max_blocks = std::max(8, env_int("VNE_MAX_BLOCKS", 1024));
     int64_t total_cost = nnz + 4 * n;
     int64_t cpb = std::max<int64_t>(256, (total_cost + max_blocks - 1) / max_blocks);
     g->sched = build_schedule(hv.row_ptr, n, seg_len, cpb, max_blocks);
@@ -556,13 +654,14 @@ static vne_status estimate_hutchpp(vne_ctx *c, Graph *g, const vne_probes *pr, i
         auto A = [&](DevBuf *b, size_t bytes) {
             if (st == VNE_OK) st = dev_alloc(c, b, bytes);
         };
-        A(&q->S, (size_t)sk->m_pad * k * 8);
+        A(&q->S, (size_t)nr * k * 8);
         A(&q->B, (size_t)g->n * m * es);
         const int64_t gd = std::max(gram_scratch_doubles((int32_t)g->n, nr, nr),
                                     gram_scratch_doubles((int32_t)g->n, nr, std::max(nh, 1)));
         A(&q->gram_part, (size_t)gd * 8);
         A(&q->gram, (size_t)nr * std::max(nr, nh) * 8);
         A(&q->rinv, (size_t)nr * nr * 8);
+        A(&q->rot, (size_t)nr * rot_capacity(k) * kRotBytes);
         if (st != VNE_OK) return st;
     }
     hipStream_t s = c->stream;
@@ -573,16 +672,17 @@ static vne_status estimate_hutchpp(vne_ctx *c, Graph *g, const vne_probes *pr, i
     ps.col_offset = 0;
     if ((st = run_lanczos(c, g, sk, ps, desing)) != VNE_OK) return st;
     HIP_TRY(c, launch_fT_e1((const double *)sk->alpha.p, (const double *)sk->beta.p, (const int32_t *)sk->k_eff.p,
-                            k, nr, (double *)q->S.p, (int32_t *)sk->flags.p, s));
+                            k, nr, (double *)q->S.p, q->rot.p, (int32_t *)sk->flags.p, s));
     const int64_t step_stride = (int64_t)g->n * sk->m_pad;
     HIP_TRY(c, launch_reconstruct(sk->Vstore.p, fp64, step_stride, sk->m_pad, (const double *)q->S.p,
-                                  (const double *)sk->norm2.p, (const int32_t *)sk->k_eff.p, k, (int32_t)g->n, nr,
-                                  q->B.p, m, s));
+                                  (const double *)sk->norm2.p, k, (int32_t)g->n, nr, q->B.p, m, s));
     // 2. G block, raw +-1 in the columns after the sketch
     if (nh > 0)
         HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)g->n, nh, m, nr, nr, pr->seed, g->d_keys, s));
-    // 3. Q = orth(Y) by CholeskyQR2 (FP64 Gram and triangular factors), in place
-    for (int pass = 0; pass < 2; ++pass) {
+    // 3. Q = orth(Y) by CholeskyQR (FP64 Gram and triangular factors), in
+    // place; a second pass in FP64 mode (with FP32 storage the rounding of Q
+    // itself bounds its orthogonality, so one pass suffices)
+    for (int pass = 0; pass < (fp64 ? 2 : 1); ++pass) {
         HIP_TRY(c, launch_gram(q->B.p, m, q->B.p, m, fp64, (int32_t)g->n, nr, nr, (double *)q->gram_part.p,
                                (double *)q->gram.p, s));
         HIP_TRY(c, launch_cholinv((double *)q->gram.p, (double *)q->rinv.p, nr, (int32_t *)sk->flags.p, s));
@@ -610,6 +710,7 @@ static vne_status estimate_hutchpp(vne_ctx *c, Graph *g, const vne_probes *pr, i
     if (fl_s & 2) return fail(c, VNE_ENUMERIC, "Cholesky of the sketch Gram matrix failed (rank-deficient sketch)");
     if ((fl_q | fl_s) & 1) return fail(c, VNE_ENUMERIC, "non-finite Lanczos coefficient");
     if ((fl_q | fl_s) & 4) return fail(c, VNE_ENUMERIC, "tridiagonal QR did not converge");
+    if (fl_s & 8) return fail(c, VNE_ENUMERIC, "tridiagonal QR rotation record overflowed");
     return VNE_OK;
 }
 

@@ -50,7 +50,7 @@ int main() {
         for (int p = 0; p < rp[n]; ++p)
             if (cover[p] != 1) return fail("coverage");
         const int nb = s.n_blocks();
-        if (nb < 1 || nb > maxb) return fail("block count");
+        if (nb < 1 || nb > (maxb + 7) / 8 * 8 || nb % 8) return fail("block count");
         if (s.block_begin[0] != 0 || s.block_begin[nb] != s.n_items()) return fail("block ends");
         for (int b = 0; b < nb; ++b)
             if (s.block_begin[b + 1] < s.block_begin[b]) return fail("block order");
