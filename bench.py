@@ -126,7 +126,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large")
-    ap.add_argument("--cpu-sample-cols", type=int, default=24)
+    ap.add_argument("--cpu-sample-cols", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reorder", default=None, help="experiment: relabel rows (rcm | degree)")
     ap.add_argument("--copy-calibration", action="store_true",

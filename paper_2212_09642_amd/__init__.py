@@ -17,7 +17,8 @@ __all__ = ["VneError", "lib", "version", "laplacian_from_edges", "csr_validate",
            "PROBE_RADEMACHER", "PROBE_HUTCHPP", "PROBE_COLORING", "PROBE_DENSE",
            "VALIDATE_SYMMETRIC", "VALIDATE_ZERO_ROWSUM", "LIB_PATH", "EXPORTS"]
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvne.so")
+LIB_PATH = os.environ.get("VNE_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                           "libvne.so")
 
 F32, F64 = 0, 1
 HOST, DEVICE = 0, 1

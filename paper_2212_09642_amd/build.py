@@ -23,22 +23,27 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose=True):
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=True, out=None, defines=(), build_dir=None):
+    """Compile and link libvne.so (or `out`); `defines` adds -D flags to the
+    HIP sources (used for A/B measurements of compile-time options)."""
+    lib_path = out or LIB
+    bdir = build_dir or BUILD
+    os.makedirs(bdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     objs = []
     for src in HOST_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
+        obj = os.path.join(bdir, src + ".o")
         _run(["g++"] + CXX_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC] + HIP_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
+        obj = os.path.join(bdir, src + ".o")
+        _run([HIPCC] + HIP_FLAGS + ["-D" + d for d in defines] + inc +
+             ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

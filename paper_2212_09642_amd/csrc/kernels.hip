@@ -43,6 +43,49 @@ __device__ __forceinline__ void store_vec(T *p, const T (&in)[N]) {
     *reinterpret_cast<V *>(p) = v;
 }
 
+// Streaming accesses (read or written once per step) carry the non-temporal
+// hint so that the caches keep the gathered block instead.
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+template <typename T, int N> struct NVecOf;
+template <> struct NVecOf<float, 4> { using type = nf4; };
+template <> struct NVecOf<double, 2> { using type = nd2; };
+
+template <typename T, int N>
+__device__ __forceinline__ void load_vec_nt(const T *p, T (&out)[N]) {
+    using V = typename NVecOf<T, N>::type;
+    V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    const T *q = reinterpret_cast<const T *>(&v);
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = q[k];
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_vec_nt(T *p, const T (&in)[N]) {
+    using V = typename NVecOf<T, N>::type;
+    V v;
+    T *q = reinterpret_cast<T *>(&v);
+#pragma unroll
+    for (int k = 0; k < N; ++k) q[k] = in[k];
+    __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+}
+
+template <bool NT, typename T, int N>
+__device__ __forceinline__ void load_s(const T *p, T (&out)[N]) {
+    if (NT) load_vec_nt<T, N>(p, out);
+    else load_vec<T, N>(p, out);
+}
+template <bool NT, typename T, int N>
+__device__ __forceinline__ void store_s(T *p, const T (&in)[N]) {
+    if (NT) store_vec_nt<T, N>(p, in);
+    else store_vec<T, N>(p, in);
+}
+
+#ifndef VNE_STREAM_NT
+#define VNE_STREAM_NT 1
+#endif
+constexpr bool kNT = VNE_STREAM_NT != 0;
+
 // Lazily normalised Lanczos vector: v_j = (P_j - alpha_{j-1} v_{j-1}) / beta_{j-1},
 // evaluated identically wherever an entry of v_j is needed.
 __device__ __forceinline__ float materialize(float p, float vp, float a, float inv) {
@@ -174,7 +217,7 @@ struct StepCore {
     // the row's own entries: pv = P_j (lazy) or v_j (two-pass), qv = v_{j-1}
     __device__ __forceinline__ void load_self(int row, T (&pv)[CPL], T (&qv)[CPL]) const {
         load_vec<T, CPL>((TWO ? V_cur : P_in) + (int64_t)row * ld + c0, pv);
-        if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)row * ld + c0, qv);
+        if (!FIRST) load_s<kNT && TWO, T, CPL>(V_prev + (int64_t)row * ld + c0, qv);
         else
 #pragma unroll
             for (int k = 0; k < CPL; ++k) qv[k] = (T)0;
@@ -196,8 +239,8 @@ struct StepCore {
             dww[k] = wd * wd;
             dvv[k] = vd * vd;
         }
-        store_vec<T, CPL>(P_out + (int64_t)row * ld + c0, wr);
-        if (!TWO) store_vec<T, CPL>(V_out + (int64_t)row * ld + c0, v);
+        store_s<kNT, T, CPL>(P_out + (int64_t)row * ld + c0, wr);
+        if (!TWO) store_s<kNT, T, CPL>(V_out + (int64_t)row * ld + c0, v);
     }
 };
 
@@ -214,8 +257,8 @@ __global__ void __launch_bounds__(256) k_normalize(StepArgs a) {
         const int64_t i = t / cg;
         const int c0 = (int)(t % cg) * CPL;
         T pv[CPL], qv[CPL], v[CPL];
-        load_vec<T, CPL>(P + i * a.m_pad + c0, pv);
-        if (!FIRST) load_vec<T, CPL>(Vp + i * a.m_pad + c0, qv);
+        load_s<kNT, T, CPL>(P + i * a.m_pad + c0, pv);
+        if (!FIRST) load_s<kNT, T, CPL>(Vp + i * a.m_pad + c0, qv);
 #pragma unroll
         for (int k = 0; k < CPL; ++k)
             v[k] = materialize(pv[k], FIRST ? (T)0 : qv[k], (T)a.st_alpha[c0 + k], (T)a.st_inv[c0 + k]);

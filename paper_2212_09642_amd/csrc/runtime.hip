@@ -304,12 +304,12 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
     a.n_blocks = s.n_blocks();
     a.seg_acc = (double *)p->seg_acc.p;
     a.n_long = s.n_long;
-    // schedule: lazy (4 streams, two gathered) when most neighbours are near
-    // in memory and the gathers hit in cache; otherwise normalize pass +
-    // single-stream SpMM
+    // schedule: normalize pass + single-stream SpMM by default (measured
+    // faster on both random and ring-local graphs); the lazy one-pass
+    // schedule (4 streams, two of them gathered) stays selectable
     {
         const int forced = env_int("VNE_SCHED", -1);
-        a.two_pass = forced >= 0 ? forced : (g->local_frac < 0.5 ? 1 : 0);
+        a.two_pass = forced >= 0 ? forced : 1;
     }
     a.long_first = (const int32_t *)g->long_first.p;
     a.long_nseg = (const int32_t *)g->long_nseg.p;

@@ -1,0 +1,114 @@
+"""Summaries of rocprofv3 output databases (the rocpd SQLite files that
+``rocprofv3 -d DIR -o run`` writes) for the files kept under profiles/.
+
+    python -m paper_2212_09642_amd.profiling stats DB OUT.md --cmd "..."
+    python -m paper_2212_09642_amd.profiling traffic FETCH_DB WRITE_DB COPY_FETCH_DB \
+        COPY_WRITE_DB OUT.json --workload NAME --copy-bytes B --cmd "..."
+
+The Lanczos step unit is the normalize pass (two-pass schedule), the SpMM +
+recurrence kernel and the long-row kernel of one step; its average duration
+is what bench.py times with HIP events around each step.
+"""
+import argparse
+import collections
+import json
+import os
+import sqlite3
+import sys
+
+STEP_KERNELS = ("k_normalize", "k_lanczos_step", "k_long_rows")
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("vne::", "")
+
+
+def kernel_stats(db):
+    con = sqlite3.connect(db)
+    rows = list(con.execute("select name, total_calls, total_duration, average from top_kernels"))
+    # the top_kernels view reports microseconds
+    return [(n, int(c), float(t), float(a)) for n, c, t, a in rows]
+
+
+def step_unit(rows):
+    steps = sum(c for n, c, t, a in rows if "k_lanczos_step" in n)
+    total = sum(t for n, c, t, a in rows if any(k in n for k in STEP_KERNELS))
+    return steps, total
+
+
+def cmd_stats(args):
+    rows = kernel_stats(args.db)
+    tot = sum(r[2] for r in rows)
+    out = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", args.cmd, "```", "",
+           "| kernel | calls | total ms | avg us | share |", "|---|---:|---:|---:|---:|"]
+    for n, c, t, a in rows:
+        out.append("| `%s` | %d | %.3f | %.2f | %.1f%% |" % (_short(n), c, t / 1e3, a, 100 * t / tot))
+    steps, st = step_unit(rows)
+    out += ["", "All kernels: %.3f ms." % (tot / 1e3),
+            "Lanczos step unit (normalize + SpMM/recurrence + long rows): %d steps, %.3f ms total, "
+            "%.2f us average per step." % (steps, st / 1e3, st / max(steps, 1))]
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def _counter(db, name_filter=None):
+    con = sqlite3.connect(db)
+    acc = collections.defaultdict(float)
+    calls = collections.Counter()
+    for kname, ctr, val in con.execute("select kernel_name, counter_name, value from counters_collection"):
+        if name_filter and not any(k in kname for k in name_filter):
+            continue
+        acc[(kname, ctr)] += float(val)
+        calls[(kname, ctr)] += 1
+    return acc, calls
+
+
+def cmd_traffic(args):
+    fetch, fcalls = _counter(args.fetch_db, STEP_KERNELS)
+    write, wcalls = _counter(args.write_db, STEP_KERNELS)
+    cf, _ = _counter(args.copy_fetch_db, ("copyBuffer",))
+    cw, _ = _counter(args.copy_write_db, ("copyBuffer",))
+    # calibration: what the counters read (KiB per dispatch) for a plain copy
+    # of known size, one dispatch per copy
+    copy_fetch_kib = sum(cf.values()) / max(args.copies, 1)
+    copy_write_kib = sum(cw.values()) / max(args.copies, 1)
+    f_scale = args.copy_bytes / (copy_fetch_kib * 1024.0)
+    w_scale = args.copy_bytes / (copy_write_kib * 1024.0)
+    steps = sum(c for (k, _), c in fcalls.items() if "k_lanczos_step" in k)
+    fetch_kib = sum(fetch.values())
+    write_kib = sum(write.values())
+    per_step = (fetch_kib * f_scale + write_kib * w_scale) * 1024.0 / max(steps, 1)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    d = {"workload": args.workload, "kernel": "Lanczos step unit (" + ", ".join(STEP_KERNELS) + ")",
+         "steps": steps, "fetch_kib_total": fetch_kib, "write_kib_total": write_kib,
+         "copy_calibration": {"bytes_each_way": args.copy_bytes, "fetch_kib": copy_fetch_kib,
+                              "write_kib": copy_write_kib, "fetch_scale": f_scale, "write_scale": w_scale},
+         "hbm_bytes_per_launch": per_step, "kernel_source_hash": bench.kernel_source_hash(),
+         "command": args.cmd}
+    with open(args.out, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps(d, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("out")
+    s.add_argument("--cmd", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch_db", "write_db", "copy_fetch_db", "copy_write_db", "out"):
+        t.add_argument(k)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--copies", type=int, default=3)
+    t.add_argument("--cmd", required=True)
+    args = ap.parse_args()
+    {"stats": cmd_stats, "traffic": cmd_traffic}[args.what](args)
+
+
+if __name__ == "__main__":
+    main()
