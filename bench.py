@@ -14,7 +14,13 @@ launch: 4 (n + 1) + nnz (4 + 4) + 3 n m 4 (CSR once; v_j gathered once,
 v_{j-1} read once, v_{j+1} written once).  The roofline object reports the
 same bytes over the step kernel's own HIP-event time.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|tiny|probing]
+The batch workload (512 ER/BA graphs, n log-uniform in [1e3, 5e4], 64
+Rademacher probes each, 50 steps, FP32) runs every graph in one stacked
+launch per Lanczos step; its line also reports the same queries issued one
+graph at a time (one captured launch sequence per graph) and the speedup.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload large|tiny|probing|batch]
 """
 import argparse
 import hashlib
@@ -120,6 +126,109 @@ def cpu_baseline(g, spec, sample_cols, k):
                        "for the same steps" % (sample_cols, k, dt))
 
 
+def run_batch(args):
+    """512 graphs, one stacked launch per step, against per-graph launches."""
+    import numpy as np
+    import torch
+    import paper_2212_09642_amd as vne
+    from synth import workloads
+    specs = workloads.batch_specs()
+    m, k, seed0 = 64, 50, workloads.PROBE_SEED
+    graphs = [vne.laplacian_from_edges(*workloads.batch_graph(sp), np.float32) for sp in specs]
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = vne.Context(0, stream=stream)
+    gids = [ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+            for g in graphs]
+    queries = [dict(gid=gid, kind=vne.PROBE_RADEMACHER, m=m, k=k, seed=seed0 + q)
+               for q, gid in enumerate(gids)]
+    mode = vne.MODE_DESING
+    n_tot = sum(g["n"] for g in graphs)
+    nnz_tot = sum(len(g["col_idx"]) for g in graphs)
+    print("batch workload: %d graphs, n=%d, nnz=%d" % (len(graphs), n_tot, nnz_tot), file=sys.stderr, flush=True)
+
+    def one():
+        return ctx.estimate_batch(queries, mode)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    ctx.enable_kernel_timing(True)
+    ctx.kernel_timing(reset=True)
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        outs = one()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.kernel_timing(reset=True)
+    ctx.enable_kernel_timing(False)
+    print("batch timed: %.1f ms per batch" % (wall / args.steps * 1e3), file=sys.stderr, flush=True)
+
+    # the same queries, one graph per call (each graph's own captured step
+    # loop): one untimed pass (capture, tile choice), one timed pass
+    def per_graph():
+        return [ctx.estimate(q["gid"], q["kind"], q["m"], q["k"], mode, seed=q["seed"], want_coeffs=False)
+                for q in queries]
+    solo = per_graph()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    solo = per_graph()
+    torch.cuda.synchronize()
+    solo_s = time.perf_counter() - ts
+    rel = max(abs(a["estimate"] - b["estimate"]) / abs(b["estimate"]) for a, b in zip(outs, solo))
+    print("per-graph pass: %.1f ms" % (solo_s * 1e3), file=sys.stderr, flush=True)
+
+    value = kt["bytes"] / wall / 1e9
+    achieved = kt["bytes"] / (kt["total_ms"] / 1e3) / 1e9 if kt["total_ms"] > 0 else 0.0
+    name = "batch512_er_ba_n1e3_5e4_hutchinson64_k50_f32"
+    res = {
+        "metric": "Lanczos SpMM GB/s (% HBM peak); entropy queries/s + p99 latency at 1e-3 rel",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "graphs": len(graphs), "n_total": n_tot, "nnz_total": nnz_tot, "m": m,
+                   "k": k, "estimator": "hutchinson", "graph_seed": workloads.GRAPH_SEED_BATCH,
+                   "probe_seed": seed0},
+        "queries_per_s": round(len(queries) * args.steps / wall, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+        "per_graph_launches": {"ms_per_batch": round(solo_s * 1e3, 3),
+                               "queries_per_s": round(len(queries) / solo_s, 3),
+                               "speedup_of_stacked_launch": round(solo_s / (wall / args.steps), 3),
+                               "max_rel_diff_of_estimates": rel},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(name),
+                     "kernel": "k_lanczos_step", "launches": kt["launches"],
+                     "avg_launch_ms": round(kt["total_ms"] / max(kt["launches"], 1), 5),
+                     "algorithmic_bytes_per_launch": round(kt["bytes"] / max(kt["launches"], 1))},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        import scipy.sparse as sp
+        t0 = time.perf_counter()
+        done, by = 0, 0.0
+        for q, g in enumerate(graphs):
+            A = sp.csr_matrix((np.asarray(g["values"], np.float64) * g["scale"], g["col_idx"], g["row_ptr"]),
+                              shape=(g["n"], g["n"]))
+            B = oracle.rademacher_block(seed0 + q, g["node_ids"], np.arange(m))
+            oracle.quadforms(A, B, k, oracle.breakdown_tau(False))
+            done += 1
+            by += k * (4.0 * (g["n"] + 1) + len(g["col_idx"]) * 8.0 + 3.0 * g["n"] * m * 4.0)
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = dict(value=by / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
+                                   queries_per_s=done / dt,
+                                   sample="oracle Lanczos + Gauss quadrature on the first %d graphs of the "
+                                          "batch, 64 Rademacher columns x 50 steps each (%.1f s); GB/s counts "
+                                          "the bytes the FP32 path would move for the same steps" % (done, dt))
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +238,8 @@ def main():
     ap.add_argument("--cpu-sample-cols", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reorder", default=None, help="experiment: relabel rows (rcm | degree)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="batch workload: seconds of oracle work in the CPU baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 2 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -148,6 +259,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": x.numel() * 4, "copies": 3}))
+        return
+
+    if args.workload == "batch":
+        run_batch(args)
         return
 
     w, g, spec = build_workload(args.workload, args.reorder)
@@ -197,7 +312,7 @@ def main():
         "config": {"workload": w["name"], "n": n, "nnz": nnz, "m": spec["m"], "k": spec["k"],
                    "estimator": {vne.PROBE_HUTCHPP: "hutch++", vne.PROBE_RADEMACHER: "hutchinson",
                                  vne.PROBE_COLORING: "probing"}[spec["kind"]],
-                   "n_sketch": spec["n_sketch"], "graph_seed": None, "probe_seed": spec["seed"]},
+                   "n_sketch": spec["n_sketch"], "graph_seed": w.get("graph_seed"), "probe_seed": spec["seed"]},
         "queries_per_s": round(args.steps / wall, 3),
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),

@@ -207,6 +207,27 @@ vne_status vne_graph_release(vne_ctx *ctx, int32_t graph_id);
 vne_status vne_entropy_estimate(vne_ctx *ctx, int32_t graph_id, const vne_probes *probes,
                                 int32_t k_steps, uint32_t mode, vne_result *out);
 
+/* n_queries independent estimates in one stacked launch per Lanczos step:
+ * the matrices are placed as the diagonal blocks of one block-diagonal
+ * matrix (rows, work blocks and probe blocks of query q after those of
+ * queries 0..q-1), so that every step is one SpMM + recurrence launch over
+ * all of them.  Query q runs k_steps[q] steps on probes[q] for
+ * graph_ids[q] and writes out[q]; each result is the one vne_entropy_estimate
+ * gives for that query alone, up to the order of the FP64 reductions (the
+ * per-graph sums add the same partials in the same order; only the first
+ * level of the reduction differs).  All queries take one probe kind, one of
+ * RADEMACHER, COLORING or DENSE (HUTCHPP is not batched: VNE_ENOTSUP);
+ * COLORING and DENSE probes must be HOST arrays here.  A graph id may appear
+ * more than once.  The stacked copy of the matrices is cached for the exact
+ * id sequence (at most VNE_MAX_SETS such sets, default 4, least recently
+ * used freed first); the column tile of the launch is picked on first use by
+ * timing three steps of each admissible tile (VNE_AUTOTUNE=0 disables;
+ * VNE_AUTOTUNE_CACHE=<file> keeps the choices).  Errors: VNE_EINVAL for bad
+ * ids, sizes or mode bits; VNE_ENOMEM when the HBM budget is exceeded. */
+vne_status vne_entropy_estimate_batch(vne_ctx *ctx, int32_t n_queries, const int32_t *graph_ids,
+                                      const vne_probes *probes, const int32_t *k_steps,
+                                      uint32_t mode, vne_result *out);
+
 /* Kernel timing for measurement: when enabled, the context records a HIP
  * event pair on its stream around every launch of the Lanczos step kernel
  * and accumulates their durations.  vne_kernel_timing returns (and with

@@ -32,7 +32,7 @@ STATUS = {0: "VNE_OK", -1: "VNE_EINVAL", -2: "VNE_ENOMEM", -3: "VNE_EDEVICE",
 EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_color_greedy",
            "vne_ctx_create", "vne_ctx_destroy", "vne_last_error", "vne_ctx_set_stream",
            "vne_ctx_memory", "vne_graph_register", "vne_graph_release", "vne_entropy_estimate",
-           "vne_enable_kernel_timing", "vne_kernel_timing"]
+           "vne_entropy_estimate_batch", "vne_enable_kernel_timing", "vne_kernel_timing"]
 
 
 class VneError(RuntimeError):
@@ -99,6 +99,9 @@ def lib():
         L.vne_graph_release.argtypes = [vp, i32]
         L.vne_entropy_estimate.restype = i32
         L.vne_entropy_estimate.argtypes = [vp, i32, P(_Probes), i32, ctypes.c_uint32, P(_Result)]
+        L.vne_entropy_estimate_batch.restype = i32
+        L.vne_entropy_estimate_batch.argtypes = [vp, i32, P(i32), P(_Probes), P(i32), ctypes.c_uint32,
+                                                 P(_Result)]
         L.vne_enable_kernel_timing.restype = i32
         L.vne_enable_kernel_timing.argtypes = [vp, i32]
         L.vne_kernel_timing.restype = i32
@@ -269,6 +272,40 @@ class Context:
         self._chk(self._L.vne_entropy_estimate(self._h, gid, ctypes.byref(pr), k, mode,
                                                ctypes.byref(res)))
         return dict(estimate=res.estimate, quad=quad, alpha=alpha, beta=beta, k_eff=kef, norm2=nrm)
+
+    def estimate_batch(self, queries, mode, want_coeffs=False):
+        """Several queries in one stacked launch per step.  queries: list of
+        dicts with keys gid, kind, m, k and optionally seed, colors, dense
+        (host arrays).  Returns one result dict per query."""
+        nq = len(queries)
+        ids = (ctypes.c_int32 * nq)()
+        ks = (ctypes.c_int32 * nq)()
+        prs = (_Probes * nq)()
+        ress = (_Result * nq)()
+        keep, outs = [], []
+        vdt = np.float64 if mode & MODE_F64 else np.float32
+        for i, q in enumerate(queries):
+            m, k = int(q["m"]), int(q["k"])
+            colors, dense = q.get("colors"), q.get("dense")
+            if colors is not None:
+                colors = np.ascontiguousarray(colors, np.int32)
+                keep.append(colors)
+            if dense is not None:
+                dense = np.ascontiguousarray(dense, vdt)
+                keep.append(dense)
+            ids[i] = int(q["gid"])
+            ks[i] = k
+            prs[i] = _Probes(int(q["kind"]), m, int(q.get("seed", 0)), 0, HOST, _ptr(colors), _ptr(dense))
+            o = dict(quad=np.zeros(m), k_eff=np.zeros(m, np.int32), norm2=np.zeros(m),
+                     alpha=np.zeros((m, k)) if want_coeffs else None,
+                     beta=np.zeros((m, k)) if want_coeffs else None)
+            outs.append(o)
+            ress[i] = _Result(0.0, _ptr(o["quad"]), _ptr(o["alpha"]), _ptr(o["beta"]), _ptr(o["k_eff"]),
+                              _ptr(o["norm2"]))
+        self._chk(self._L.vne_entropy_estimate_batch(self._h, nq, ids, prs, ks, mode, ress))
+        for i, o in enumerate(outs):
+            o["estimate"] = ress[i].estimate
+        return outs
 
     def enable_kernel_timing(self, on=True):
         self._chk(self._L.vne_enable_kernel_timing(self._h, 1 if on else 0))

@@ -73,8 +73,22 @@ vne_status validate_host_csr(const vne_csr *csr, uint32_t flags, std::string *ms
     return VNE_OK;
 }
 
+static void ranges_from_items(Schedule &s) {
+    const int32_t nb = (int32_t)s.block_begin.size() - 1;
+    s.block_ranges.assign(4 * (size_t)nb, 0);
+    for (int32_t b = 0; b < nb; ++b) {
+        const int64_t ib = s.block_begin[b], ie = s.block_begin[b + 1];
+        const int64_t sb = std::min<int64_t>(ib, s.n_seg), se = std::min<int64_t>(ie, s.n_seg);
+        const int64_t rb = std::max<int64_t>(ib, s.n_seg) - s.n_seg, re = std::max<int64_t>(ie, s.n_seg) - s.n_seg;
+        s.block_ranges[4 * b + 0] = (int32_t)sb;
+        s.block_ranges[4 * b + 1] = (int32_t)se;
+        s.block_ranges[4 * b + 2] = (int32_t)rb;
+        s.block_ranges[4 * b + 3] = (int32_t)re;
+    }
+}
+
 Schedule build_schedule(const int32_t *row_ptr, int64_t n, int32_t seg_len, int64_t cost_per_block,
-                        int32_t max_blocks) {
+                        int32_t max_blocks, bool pad8) {
     Schedule s;
     s.seg_len = seg_len;
     s.n_rows = n;
@@ -110,7 +124,7 @@ Schedule build_schedule(const int32_t *row_ptr, int64_t n, int32_t seg_len, int6
     // a multiple of 8 (the 8 XCDs each take a contiguous range); blocks past
     // the cost-balanced ones are empty
     const int64_t nb_work = nb;
-    nb = (nb + 7) / 8 * 8;
+    if (pad8) nb = (nb + 7) / 8 * 8;
     s.block_begin.assign(nb + 1, 0);
     int64_t acc = 0, b = 1;
     for (int64_t t = 0; t < n_items && b < nb_work; ++t) {
@@ -119,6 +133,48 @@ Schedule build_schedule(const int32_t *row_ptr, int64_t n, int32_t seg_len, int6
     }
     while (b < nb) s.block_begin[b++] = (int32_t)n_items;
     s.block_begin[nb] = (int32_t)n_items;
+    ranges_from_items(s);
+    return s;
+}
+
+Schedule stack_schedules(const std::vector<Schedule> &parts, const std::vector<int64_t> &row_offset,
+                         const std::vector<int64_t> &nnz_offset, std::vector<int32_t> *graph_block_begin,
+                         std::vector<int32_t> *graph_long_begin, std::vector<int32_t> *block_graph) {
+    Schedule s;
+    const size_t G = parts.size();
+    graph_block_begin->assign(G + 1, 0);
+    graph_long_begin->assign(G + 1, 0);
+    block_graph->clear();
+    s.seg_len = G ? parts[0].seg_len : 0;
+    for (size_t q = 0; q < G; ++q) {
+        const Schedule &p = parts[q];
+        const int32_t seg0 = (int32_t)s.segs.size(), long0 = s.n_long;
+        (*graph_block_begin)[q] = s.n_blocks();
+        (*graph_long_begin)[q] = s.n_long;
+        for (const SegItem &it : p.segs)
+            s.segs.push_back({(int32_t)(it.row + row_offset[q]), (int32_t)(it.p0 + nnz_offset[q]),
+                              (int32_t)(it.p1 + nnz_offset[q]), it.lrow + long0});
+        for (int32_t L = 0; L < p.n_long; ++L) {
+            s.long_first.push_back(p.long_first[L] + seg0);
+            s.long_nseg.push_back(p.long_nseg[L]);
+        }
+        s.n_long += p.n_long;
+        for (int32_t b = 0; b < p.n_blocks(); ++b) {
+            s.block_ranges.push_back(p.block_ranges[4 * b + 0] + seg0);
+            s.block_ranges.push_back(p.block_ranges[4 * b + 1] + seg0);
+            s.block_ranges.push_back((int32_t)(p.block_ranges[4 * b + 2] + row_offset[q]));
+            s.block_ranges.push_back((int32_t)(p.block_ranges[4 * b + 3] + row_offset[q]));
+            block_graph->push_back((int32_t)q);
+        }
+        s.n_rows += p.n_rows;
+    }
+    (*graph_block_begin)[G] = s.n_blocks();
+    (*graph_long_begin)[G] = s.n_long;
+    s.n_seg = (int32_t)s.segs.size();
+    while (s.n_blocks() % 8) {   // empty blocks
+        for (int q = 0; q < 4; ++q) s.block_ranges.push_back(0);
+        block_graph->push_back(G ? (int32_t)G - 1 : 0);
+    }
     return s;
 }
 

@@ -38,7 +38,7 @@ struct StepArgs {
     const SegItem *segs;
     int32_t n_seg;
     int32_t seg_len;
-    const int32_t *block_begin;
+    const int4 *block_ranges;   // [n_blocks] {seg_begin, seg_end, row_begin, row_end}
     int32_t n_blocks;
     double *seg_acc;            // [n_seg][m_pad]
     int32_t n_long;             // rows split into segments
@@ -46,6 +46,13 @@ struct StepArgs {
     const int32_t *long_nseg;
     double *long_part;          // [n_long][3][m_pad]
     double *partials;           // [n_blocks][3][m_pad]
+    // several graphs in one launch (block-diagonal matrix, rows stacked by
+    // graph; work blocks never straddle two graphs).  Per-column state is
+    // indexed graph * m_pad + column.  nullptr arrays mean one graph.
+    const int32_t *block_graph; // [n_blocks]
+    const int32_t *row_graph;   // [n]
+    const int32_t *long_graph;  // [n_long]
+    const double *graph_scale;  // [G]
 };
 
 constexpr int kLevel2 = 32;       // first-level reduction rows of the step partials
@@ -64,9 +71,17 @@ struct FinalizeArgs {
     int32_t k;                  // steps of the run (row stride of alpha/beta)
     double tau;
     double *st_alpha, *st_inv, *st_coup;
-    double *alpha, *beta;       // [m_pad][k]
+    double *alpha, *beta;       // [G * m_pad][k]
     int32_t *k_eff;
     int32_t *flags;             // bit 0: non-finite coefficient
+    // several graphs: per-graph single-level reduction over the graph's own
+    // blocks and long rows (in order); per-graph step counts and widths
+    int32_t n_graphs;
+    int32_t segmented;
+    const int32_t *graph_block_begin;  // [G+1]
+    const int32_t *graph_long_begin;   // [G+1]
+    const int32_t *graph_k;            // [G] (nullptr: k)
+    const int32_t *graph_m;            // [G] (nullptr: m)
 };
 
 // Returns the column tile width the step kernel uses for this probe width.
@@ -96,6 +111,15 @@ struct ProbeArgs {
     double *st_alpha, *st_inv, *st_coup;
     int32_t *k_eff;
     int32_t k;
+    // blocks own row ranges of one graph each; per-graph seed, width, steps
+    const int32_t *block_row_begin;    // [n_blocks+1]
+    const int32_t *block_graph;        // [n_blocks]
+    const int32_t *graph_block_begin;  // [G+1]
+    const int64_t *graph_row_begin;    // [G+1]
+    const uint64_t *seeds;             // [G]
+    const int32_t *graph_k;            // [G]
+    const int32_t *graph_m;            // [G]
+    int32_t n_graphs;
 };
 hipError_t launch_probe(const ProbeArgs &a, bool fp64, hipStream_t s);
 
@@ -117,9 +141,11 @@ hipError_t launch_fT_e1(const double *alpha, const double *beta, const int32_t *
                         hipStream_t s);
 
 // estimate from psi: kind 0 mean, 1 sum, 2 Hutch++ (first n_sketch summed,
-// rest averaged)
+// rest averaged); one estimate per graph from psi[g * ld + c], c < graph_m[g]
 hipError_t launch_combine(const double *psi, int32_t m, int32_t kind, int32_t n_sketch,
                           double *estimate, hipStream_t s);
+hipError_t launch_combine_graphs(const double *psi, int32_t ld, const int32_t *graph_m, int32_t n_graphs,
+                                 int32_t kind, double *estimates, hipStream_t s);
 
 // Y[i*ldy + c] = sqrt(norm2[c]) * sum_j S[j*m + c] Vstore[j][i*ldv + c]  (m <= 128)
 hipError_t launch_reconstruct(const void *Vstore, bool fp64, int64_t step_stride, int32_t ldv,

@@ -160,9 +160,13 @@ struct StepCore {
     T al[CPL], inv[CPL];
     double coup[CPL];
 
-    __device__ __forceinline__ StepCore(const StepArgs &args, int tile, int gl) : a(args) {
+    double scale;
+
+    __device__ __forceinline__ StepCore(const StepArgs &args, int tile, int gl, int g) : a(args) {
         c0 = tile * MT + gl * CPL;
         ld = a.m_pad;
+        scale = a.graph_scale ? a.graph_scale[g] : a.scale;
+        const int64_t s0 = (int64_t)g * a.m_pad + c0;   // per-column state of this graph
         P_in = static_cast<const T *>(a.P_in);
         V_prev = static_cast<const T *>(a.V_prev);
         V_cur = static_cast<const T *>(a.V_cur);
@@ -171,9 +175,9 @@ struct StepCore {
         val = static_cast<const T *>(a.val);
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-            al[k] = (T)a.st_alpha[c0 + k];
-            inv[k] = (T)a.st_inv[c0 + k];
-            coup[k] = a.st_coup[c0 + k];
+            al[k] = (T)a.st_alpha[s0 + k];
+            inv[k] = (T)a.st_inv[s0 + k];
+            coup[k] = a.st_coup[s0 + k];
         }
     }
 
@@ -232,7 +236,7 @@ struct StepCore {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             v[k] = TWO ? pv[k] : materialize(pv[k], qv[k], al[k], inv[k]);
-            const double w = fma(-coup[k], (double)qv[k], a.scale * acc[k]);
+            const double w = fma(-coup[k], (double)qv[k], scale * acc[k]);
             wr[k] = (T)w;
             const double vd = (double)v[k], wd = (double)wr[k];
             dvw[k] = vd * wd;
@@ -256,12 +260,13 @@ __global__ void __launch_bounds__(256) k_normalize(StepArgs a) {
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < groups; t += (int64_t)gridDim.x * 256) {
         const int64_t i = t / cg;
         const int c0 = (int)(t % cg) * CPL;
+        const int64_t s0 = (a.row_graph ? (int64_t)a.row_graph[i] * a.m_pad : 0) + c0;
         T pv[CPL], qv[CPL], v[CPL];
         load_s<kNT, T, CPL>(P + i * a.m_pad + c0, pv);
         if (!FIRST) load_s<kNT, T, CPL>(Vp + i * a.m_pad + c0, qv);
 #pragma unroll
         for (int k = 0; k < CPL; ++k)
-            v[k] = materialize(pv[k], FIRST ? (T)0 : qv[k], (T)a.st_alpha[c0 + k], (T)a.st_inv[c0 + k]);
+            v[k] = materialize(pv[k], FIRST ? (T)0 : qv[k], (T)a.st_alpha[s0 + k], (T)a.st_inv[s0 + k]);
         store_vec<T, CPL>(Vo + i * a.m_pad + c0, v);
     }
 }
@@ -285,23 +290,28 @@ __global__ void __launch_bounds__(kStepThreads) k_lanczos_step(StepArgs a) {
     const int grp = lane / LPR;
     const int gl = lane % LPR;
     const int gid = wave * GPW + grp;
-    const Core core(a, tile, gl);
+    const int g = a.block_graph ? a.block_graph[b] : 0;
+    const Core core(a, tile, gl, g);
 
     double s_vw[CPL], s_ww[CPL], s_vv[CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) s_vw[k] = s_ww[k] = s_vv[k] = 0.0;
 
-    const int ib = a.block_begin[b], ie = a.block_begin[b + 1];
-    for (int it = ib + gid; it < ie; it += NG) {
-        int row, p0, p1;
-        const bool seg = it < a.n_seg;
+    // the block's segments, then its rows
+    const int4 rg = a.block_ranges[b];
+    const int n_sb = rg.y - rg.x;
+    const int total = n_sb + (rg.w - rg.z);
+    for (int t = gid; t < total; t += NG) {
+        int row, p0, p1, it = 0;
+        const bool seg = t < n_sb;
         if (seg) {
+            it = rg.x + t;
             const SegItem s = a.segs[it];
             row = s.row;
             p0 = s.p0;
             p1 = s.p1;
         } else {
-            row = it - a.n_seg;
+            row = rg.z + (t - n_sb);
             p0 = a.row_ptr[row];
             p1 = a.row_ptr[row + 1];
             if (p1 - p0 > a.seg_len) continue;      // long row: done by its segments
@@ -366,7 +376,7 @@ __global__ void __launch_bounds__(256) k_long_rows(StepArgs a) {
     const int gl = lane % LPR;
     const int L = blockIdx.x * NG + (threadIdx.x >> 6) * GPW + grp;
     if (L >= a.n_long) return;
-    const Core core(a, tile, gl);
+    const Core core(a, tile, gl, a.long_graph ? a.long_graph[L] : 0);
     const int first = a.long_first[L], nseg = a.long_nseg[L];
     const int row = a.segs[first].row;
     double tot[CPL];
@@ -526,9 +536,49 @@ __global__ void __launch_bounds__(256) k_reduce_partials(FinalizeArgs a) {
     for (int q = 0; q < 3; ++q) out[(int64_t)q * a.m_pad] = sh[q][0][lane] + sh[q][1][lane] + sh[q][2][lane] + sh[q][3][lane];
 }
 
-// Second level and coefficient update: sum the R first-level rows in order,
-// then alpha_j = (v.w)/(v.v), beta_j^2 = w.w - alpha_j (v.w) = ||w - alpha_j v||^2,
-// breakdown test and the scalars of the next normalisation.
+// alpha_j = (v.w)/(v.v), beta_j^2 = w.w - alpha_j (v.w) = ||w - alpha_j v||^2,
+// breakdown test and the scalars of the next normalisation, for the column
+// c of graph g (state index gc = g * m_pad + c).  A graph with fewer steps
+// than the launch keeps its last beta and stops.
+__device__ __forceinline__ void update_coefficients(const FinalizeArgs &a, int g, int c, double svw, double sww,
+                                                    double svv) {
+    const int64_t gc = (int64_t)g * a.m_pad + c;
+    const int j = a.step - 1;
+    const int kg = a.graph_k ? a.graph_k[g] : a.k;
+    const int mg = a.graph_m ? a.graph_m[g] : a.m;
+    const double inv_prev = a.st_inv[gc];
+    if (inv_prev == 0.0 || c >= mg || a.step > kg) {   // frozen, empty, pad column or done
+        a.alpha[gc * a.k + j] = 0.0;
+        a.beta[gc * a.k + j] = 0.0;
+        a.st_inv[gc] = 0.0;
+        a.st_alpha[gc] = 0.0;
+        a.st_coup[gc] = 0.0;
+        return;
+    }
+    const double coup_prev = a.st_coup[gc];
+    const double alpha = svw / svv;
+    double b2 = sww - alpha * svw;
+    b2 = b2 > 0.0 ? b2 : 0.0;
+    const double beta = sqrt(b2);
+    a.alpha[gc * a.k + j] = alpha;
+    const bool finite = isfinite(alpha) && isfinite(beta);
+    if (!finite) atomicOr(a.flags, 1);
+    if (!finite || beta <= a.tau * (fabs(alpha) + coup_prev)) {
+        a.k_eff[gc] = a.step;
+        a.beta[gc * a.k + j] = 0.0;
+        a.st_inv[gc] = 0.0;
+        a.st_alpha[gc] = 0.0;
+        a.st_coup[gc] = 0.0;
+    } else {
+        a.beta[gc * a.k + j] = beta;
+        const bool last = a.step == kg;
+        a.st_alpha[gc] = last ? 0.0 : alpha;
+        a.st_inv[gc] = last ? 0.0 : 1.0 / beta;
+        a.st_coup[gc] = last ? 0.0 : beta;
+    }
+}
+
+// Second level (one graph): sum the R first-level rows in order, update.
 __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs a) {
     const int c = blockIdx.x * 64 + threadIdx.x;
     if (c >= a.m_pad) return;
@@ -539,39 +589,37 @@ __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs a) {
         sww += p[a.m_pad];
         svv += p[2 * a.m_pad];
     }
-    const int j = a.step - 1;
-    const double inv_prev = a.st_inv[c];
-    if (inv_prev == 0.0 || c >= a.m) {      // frozen earlier, empty or pad column
-        a.alpha[(int64_t)c * a.k + j] = 0.0;
-        a.beta[(int64_t)c * a.k + j] = 0.0;
-        a.st_inv[c] = 0.0;
-        a.st_alpha[c] = 0.0;
-        a.st_coup[c] = 0.0;
-        return;
+    update_coefficients(a, 0, c, svw, sww, svv);
+}
+
+// Several graphs: thread (g, c) adds graph g's block partials, then its long
+// rows, in order, and updates.
+__global__ void __launch_bounds__(256) k_finalize_graphs(FinalizeArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)a.n_graphs * a.m_pad) return;
+    const int g = (int)(t / a.m_pad), c = (int)(t % a.m_pad);
+    double svw = 0.0, sww = 0.0, svv = 0.0;
+    for (int bb = a.graph_block_begin[g]; bb < a.graph_block_begin[g + 1]; ++bb) {
+        const double *p = a.partials + (int64_t)bb * 3 * a.m_pad + c;
+        svw += p[0];
+        sww += p[a.m_pad];
+        svv += p[2 * a.m_pad];
     }
-    const double coup_prev = a.st_coup[c];
-    const double alpha = svw / svv;
-    double b2 = sww - alpha * svw;
-    b2 = b2 > 0.0 ? b2 : 0.0;
-    const double beta = sqrt(b2);
-    a.alpha[(int64_t)c * a.k + j] = alpha;
-    const bool finite = isfinite(alpha) && isfinite(beta);
-    if (!finite) atomicOr(a.flags, 1);
-    if (!finite || beta <= a.tau * (fabs(alpha) + coup_prev)) {
-        a.k_eff[c] = a.step;
-        a.beta[(int64_t)c * a.k + j] = 0.0;
-        a.st_inv[c] = 0.0;
-        a.st_alpha[c] = 0.0;
-        a.st_coup[c] = 0.0;
-    } else {
-        a.beta[(int64_t)c * a.k + j] = beta;
-        a.st_alpha[c] = alpha;
-        a.st_inv[c] = 1.0 / beta;
-        a.st_coup[c] = beta;
+    for (int L = a.graph_long_begin[g]; L < a.graph_long_begin[g + 1]; ++L) {
+        const double *p = a.long_part + (int64_t)L * 3 * a.m_pad + c;
+        svw += p[0];
+        sww += p[a.m_pad];
+        svv += p[2 * a.m_pad];
     }
+    update_coefficients(a, g, c, svw, sww, svv);
 }
 
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
+    if (a.segmented) {
+        const int64_t t = (int64_t)a.n_graphs * a.m_pad;
+        hipLaunchKernelGGL(k_finalize_graphs, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_reduce_partials, dim3((a.m_pad + 63) / 64, a.n_level2), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_finalize, dim3((a.m_pad + 63) / 64), dim3(64), 0, s, a);
     return hipGetLastError();
@@ -584,32 +632,37 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ __forceinline__ double probe_value(const ProbeArgs &a, int64_t i, int c) {
-    if (c >= a.m) return 0.0;
-    if (a.gen == GEN_RADEMACHER) return rademacher(a.seed, a.keys[i], (int64_t)a.col_offset + c);
+__device__ __forceinline__ double probe_value(const ProbeArgs &a, int g, int64_t i, int c) {
+    const int mg = a.graph_m ? a.graph_m[g] : a.m;
+    if (c >= mg) return 0.0;
+    if (a.gen == GEN_RADEMACHER)
+        return rademacher(a.seeds ? a.seeds[g] : a.seed, a.keys[i], (int64_t)a.col_offset + c);
     if (a.gen == GEN_COLORING) return a.colors[i] == c ? 1.0 : 0.0;
     return (double)static_cast<const T *>(a.dense)[i * a.ld_dense + c];
 }
 
+// Block b owns rows [block_row_begin[b], block_row_begin[b+1]) of one graph.
+// Pass 1 sums every column; pass 2 writes P_1 = b - mean (element type of the
+// mode) and sums the squares of the stored values.
 template <typename T, int PASS>
 __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     __shared__ double sh[256];
     const int rows_per = 256 / a.mt;
     const int cc = threadIdx.x % a.mt, rr = threadIdx.x / a.mt;
-    const int64_t per_block = ((int64_t)a.n + a.n_blocks - 1) / a.n_blocks;
-    const int64_t r0 = (int64_t)blockIdx.x * per_block;
-    const int64_t r1 = min((int64_t)a.n, r0 + per_block);
+    const int b = blockIdx.x;
+    const int g = a.block_graph ? a.block_graph[b] : 0;
+    const int64_t r0 = a.block_row_begin[b], r1 = a.block_row_begin[b + 1];
     T *P = static_cast<T *>(a.P_out);
     for (int t0 = 0; t0 < a.m_pad; t0 += a.mt) {
         const int c = t0 + cc;
         double acc = 0.0;
-        const double mu = PASS == 2 ? a.mean[c] : 0.0;
+        const double mu = PASS == 2 ? a.mean[(int64_t)g * a.m_pad + c] : 0.0;
         for (int64_t i = r0 + rr; i < r1; i += rows_per) {
-            const double b = probe_value<T>(a, i, c);
+            const double v = probe_value<T>(a, g, i, c);
             if (PASS == 1) {
-                acc += b;
+                acc += v;
             } else {
-                const T cv = (T)(b - mu);
+                const T cv = (T)(v - mu);
                 P[i * a.m_pad + c] = cv;
                 acc += (double)cv * (double)cv;
             }
@@ -618,40 +671,46 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
         sh[threadIdx.x] = acc;
         __syncthreads();
         if (rr == 0) {
-            double s = 0.0;
-            for (int q = 0; q < rows_per; ++q) s += sh[q * a.mt + cc];
-            a.partials[(int64_t)blockIdx.x * a.m_pad + c] = s;
+            double sum = 0.0;
+            for (int q = 0; q < rows_per; ++q) sum += sh[q * a.mt + cc];
+            a.partials[(int64_t)b * a.m_pad + c] = sum;
         }
         __syncthreads();
     }
 }
 
+// (g, c) per block: adds graph g's probe-block partials in order.
 template <int PASS>
 __global__ void __launch_bounds__(256) k_probe_reduce(ProbeArgs a) {
     __shared__ double sh[256];
-    const int c = blockIdx.x;
-    double s = 0.0;
-    for (int bb = threadIdx.x; bb < a.n_blocks; bb += 256) s += a.partials[(int64_t)bb * a.m_pad + c];
-    s = block_sum_256(s, sh);
+    const int g = blockIdx.x / a.m_pad, c = blockIdx.x % a.m_pad;
+    const int64_t gc = (int64_t)g * a.m_pad + c;
+    double sum = 0.0;
+    for (int bb = a.graph_block_begin[g] + threadIdx.x; bb < a.graph_block_begin[g + 1]; bb += 256)
+        sum += a.partials[(int64_t)bb * a.m_pad + c];
+    sum = block_sum_256(sum, sh);
     if (threadIdx.x != 0) return;
+    const int mg = a.graph_m ? a.graph_m[g] : a.m;
+    const int kg = a.graph_k ? a.graph_k[g] : a.k;
     if (PASS == 1) {
-        a.mean[c] = a.desing ? s / (double)a.n : 0.0;
+        const double ng = (double)(a.graph_row_begin[g + 1] - a.graph_row_begin[g]);
+        a.mean[gc] = a.desing ? sum / ng : 0.0;
     } else {
-        a.norm2[c] = s;
-        a.st_alpha[c] = 0.0;
-        a.st_coup[c] = 0.0;
-        if (s > 0.0 && c < a.m) {
-            a.st_inv[c] = 1.0 / sqrt(s);
-            a.k_eff[c] = a.k;
+        a.norm2[gc] = sum;
+        a.st_alpha[gc] = 0.0;
+        a.st_coup[gc] = 0.0;
+        if (sum > 0.0 && c < mg) {
+            a.st_inv[gc] = 1.0 / sqrt(sum);
+            a.k_eff[gc] = kg;
         } else {
-            a.st_inv[c] = 0.0;
-            a.k_eff[c] = 0;
+            a.st_inv[gc] = 0.0;
+            a.k_eff[gc] = 0;
         }
     }
 }
 
 hipError_t launch_probe(const ProbeArgs &a, bool fp64, hipStream_t s) {
-    dim3 g(a.n_blocks), r(a.m_pad);
+    dim3 g(a.n_blocks), r((unsigned)((int64_t)a.n_graphs * a.m_pad));
     if (fp64) {
         hipLaunchKernelGGL((k_probe<double, 1>), g, dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_probe_reduce<1>), r, dim3(256), 0, s, a);
@@ -931,6 +990,23 @@ __global__ void __launch_bounds__(256) k_combine(const double *psi, int32_t m, i
         else if (kind == 1) *estimate = b;
         else *estimate = a + (m > n_sketch ? b / (double)(m - n_sketch) : 0.0);
     }
+}
+
+__global__ void __launch_bounds__(256) k_combine_graphs(const double *psi, int32_t ld, const int32_t *graph_m,
+                                                        int32_t kind, double *estimates) {
+    __shared__ double sh[256];
+    const int g = blockIdx.x;
+    const int mg = graph_m[g];
+    double b = 0.0;
+    for (int c = threadIdx.x; c < mg; c += 256) b += psi[(int64_t)g * ld + c];
+    b = block_sum_256(b, sh);
+    if (threadIdx.x == 0) estimates[g] = kind == 1 ? b : (mg > 0 ? b / (double)mg : 0.0);
+}
+
+hipError_t launch_combine_graphs(const double *psi, int32_t ld, const int32_t *graph_m, int32_t n_graphs,
+                                 int32_t kind, double *estimates, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine_graphs, dim3(n_graphs), dim3(256), 0, s, psi, ld, graph_m, kind, estimates);
+    return hipGetLastError();
 }
 
 hipError_t launch_combine(const double *psi, int32_t m, int32_t kind, int32_t n_sketch, double *estimate,

@@ -1,12 +1,17 @@
-// Host runtime of the entropy engine: context, graph registry, cached
-// workspaces ("plans") and the estimate entry points of vne.h.
+// Host runtime of the entropy engine: context, graph registry, graph sets
+// (one graph, or several graphs stacked into one block-diagonal launch),
+// cached workspaces ("plans"), the tile autotuner and the estimate entry
+// points of vne.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
+#include <sstream>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -27,36 +32,56 @@ struct DevBuf {
 
 struct Plan {
     bool fp64 = false;
-    int m = 0, m_pad = 0, mt = 0, n_tiles = 0, k = 0;
+    int G = 1;                       // graphs in the set
+    int m = 0, m_pad = 0, mt = 0, k = 0;
     bool store = false;              // keep every v_j (Hutch++ sketch)
-    int probe_blocks = 0;
     DevBuf P[2], V[2], Vstore;
     DevBuf alpha, beta, st_alpha, st_inv, st_coup, k_eff, norm2, mean, psi, estimate, flags;
     DevBuf partials, level2, probe_part, seg_acc, long_part, colors, dense;
+    DevBuf graph_k, graph_m, seeds;  // per graph
+    std::vector<int32_t> h_graph_k, h_graph_m;
     // Hutch++ extras (only in the quadratic-form plan of a Hutch++ run)
     DevBuf S, B, gram_part, gram, rinv, rot;
-    // the k-step loop captured as one HIP graph, per two_pass schedule;
-    // with kernel timing on, one graph per step part instead, so that event
-    // pairs recorded between graph launches bracket the Lanczos step kernels
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    std::vector<hipGraphExec_t> part_exec[2];   // [2k]: step j, finalize j
-    std::vector<hipEvent_t> ev;                 // 2k events
+    // the k-step loop captured as one HIP graph, per (schedule, tile); with
+    // kernel timing on, one graph per step part instead, so that event pairs
+    // recorded between graph launches bracket the Lanczos step kernels
+    std::map<std::pair<int, int>, hipGraphExec_t> exec;
+    std::map<std::pair<int, int>, std::vector<hipGraphExec_t>> part_exec;
+    std::vector<hipEvent_t> ev;      // 2k events
 };
 
 struct Graph {
     int64_t n = 0, nnz = 0;
     double scale = 1.0;
-    DevBuf row_ptr, col, val32, val64, keys;         // owned copies
+    std::vector<int32_t> h_row_ptr, h_col;   // host copies (schedules, stacking)
+    std::vector<double> h_val;
+    std::vector<int64_t> h_keys;
+    DevBuf row_ptr, col;                     // owned device copies (host input)
     const int32_t *d_row_ptr = nullptr, *d_col = nullptr;
-    const float *d_val32 = nullptr;
-    const double *d_val64 = nullptr;
-    const int64_t *d_keys = nullptr;
     Schedule sched;
-    DevBuf segs, block_begin, long_first, long_nseg;
-    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Plan>> plans;
     bool alive = false;
-    bool zero_rowsum = false;            // A 1 = 0 exactly (checked at registration)
-    double local_frac = 0.0;             // off-diagonal entries with |i - j| <= 256
+    bool zero_rowsum = false;                // A 1 = 0 exactly
+};
+
+// Graphs stacked as one block-diagonal matrix: rows, entries, work blocks and
+// probe blocks of graph q follow those of graphs 0..q-1.  A set of one graph
+// uses the graph's own row_ptr / col_idx.
+struct GraphSet {
+    std::vector<int32_t> ids;
+    int G = 1;
+    int64_t n = 0, nnz = 0;
+    double scale = 1.0;
+    bool zero_rowsum = true;
+    const int32_t *d_row_ptr = nullptr, *d_col = nullptr;
+    DevBuf row_ptr, col, val32, val64, keys;
+    DevBuf row_graph, long_graph, block_graph, graph_block_begin, graph_long_begin, graph_scale;
+    DevBuf segs, block_ranges, long_first, long_nseg;
+    DevBuf probe_rows, probe_block_graph, probe_graph_begin, graph_row_begin;
+    Schedule sched;
+    std::vector<int64_t> h_row_begin;                      // [G+1]
+    int probe_blocks = 0;
+    uint64_t last_use = 0;
+    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Plan>> plans;
 };
 
 }  // namespace
@@ -68,6 +93,8 @@ struct vne_ctx {
     uint64_t budget = 0, used = 0;
     std::string err;
     std::vector<std::unique_ptr<Graph>> graphs;
+    std::map<std::vector<int32_t>, std::unique_ptr<GraphSet>> sets;
+    uint64_t tick = 0;                   // set use counter (eviction order)
     bool timing = false;
     int64_t t_launches = 0;
     double t_ms = 0.0, t_bytes = 0.0;
@@ -76,6 +103,8 @@ struct vne_ctx {
         double bytes;
     };
     std::vector<Pending> pending;        // timed step loops not yet collected
+    std::map<std::string, int> tuned;    // autotuner: set signature -> column tile
+    std::string tune_file;
 };
 
 namespace {
@@ -94,6 +123,12 @@ vne_status hip_fail(vne_ctx *c, hipError_t e, const char *what) {
     do {                                                             \
         hipError_t _e = (expr);                                      \
         if (_e != hipSuccess) return hip_fail((ctx), _e, #expr);     \
+    } while (0)
+
+#define VNE_TRY(expr)                       \
+    do {                                    \
+        vne_status _s = (expr);             \
+        if (_s != VNE_OK) return _s;        \
     } while (0)
 
 vne_status dev_alloc(vne_ctx *c, DevBuf *b, size_t bytes) {
@@ -120,48 +155,12 @@ void dev_free(vne_ctx *c, DevBuf *b) {
     b->bytes = 0;
 }
 
-void free_plan(vne_ctx *c, Plan *p) {
-    for (auto &e : p->exec)
-        if (e) {
-            (void)hipGraphExecDestroy(e);
-            e = nullptr;
-        }
-    for (auto &v : p->part_exec) {
-        for (auto &e : v)
-            if (e) (void)hipGraphExecDestroy(e);
-        v.clear();
-    }
-    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
-    p->ev.clear();
-    DevBuf *all[] = {&p->P[0], &p->P[1], &p->V[0], &p->V[1], &p->Vstore, &p->alpha, &p->beta,
-                     &p->st_alpha, &p->st_inv, &p->st_coup, &p->k_eff, &p->norm2, &p->mean, &p->psi,
-                     &p->estimate, &p->flags, &p->partials, &p->level2, &p->probe_part, &p->seg_acc,
-                     &p->long_part, &p->colors, &p->dense, &p->S, &p->B, &p->gram_part, &p->gram,
-                     &p->rinv, &p->rot};
-    for (DevBuf *b : all) dev_free(c, b);
-}
-
-void free_graph(vne_ctx *c, Graph *g) {
-    for (auto &kv : g->plans) free_plan(c, kv.second.get());
-    g->plans.clear();
-    DevBuf *all[] = {&g->row_ptr, &g->col, &g->val32, &g->val64, &g->keys,
-                     &g->segs, &g->block_begin, &g->long_first, &g->long_nseg};
-    for (DevBuf *b : all) dev_free(c, b);
-    g->alive = false;
-}
-
 // Allocates max(count, 1) elements and copies count elements (none if h is NULL).
 template <typename T>
 vne_status upload(vne_ctx *c, DevBuf *b, const T *h, size_t count) {
-    vne_status st = dev_alloc(c, b, std::max<size_t>(count, 1) * sizeof(T));
-    if (st != VNE_OK) return st;
+    VNE_TRY(dev_alloc(c, b, std::max<size_t>(count, 1) * sizeof(T)));
     if (count && h) HIP_TRY(c, hipMemcpy(b->p, h, count * sizeof(T), hipMemcpyHostToDevice));
     return VNE_OK;
-}
-
-Graph *get_graph(vne_ctx *c, int32_t gid) {
-    if (gid < 0 || gid >= (int32_t)c->graphs.size() || !c->graphs[gid] || !c->graphs[gid]->alive) return nullptr;
-    return c->graphs[gid].get();
 }
 
 int env_int(const char *name, int dflt) {
@@ -169,25 +168,223 @@ int env_int(const char *name, int dflt) {
     return v ? atoi(v) : dflt;
 }
 
-// Workspace for a probe block of width m on graph g.
-vne_status get_plan(vne_ctx *c, Graph *g, int m, int k, bool fp64, bool store, int tag, Plan **out) {
+void free_plan(vne_ctx *c, Plan *p) {
+    for (auto &kv : p->exec)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    p->exec.clear();
+    for (auto &kv : p->part_exec)
+        for (auto &e : kv.second)
+            if (e) (void)hipGraphExecDestroy(e);
+    p->part_exec.clear();
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    p->ev.clear();
+    DevBuf *all[] = {&p->P[0], &p->P[1], &p->V[0], &p->V[1], &p->Vstore, &p->alpha, &p->beta,
+                     &p->st_alpha, &p->st_inv, &p->st_coup, &p->k_eff, &p->norm2, &p->mean, &p->psi,
+                     &p->estimate, &p->flags, &p->partials, &p->level2, &p->probe_part, &p->seg_acc,
+                     &p->long_part, &p->colors, &p->dense, &p->graph_k, &p->graph_m, &p->seeds,
+                     &p->S, &p->B, &p->gram_part, &p->gram, &p->rinv, &p->rot};
+    for (DevBuf *b : all) dev_free(c, b);
+}
+
+void free_set(vne_ctx *c, GraphSet *s) {
+    for (auto &kv : s->plans) free_plan(c, kv.second.get());
+    s->plans.clear();
+    DevBuf *all[] = {&s->row_ptr, &s->col, &s->val32, &s->val64, &s->keys, &s->row_graph, &s->long_graph,
+                     &s->block_graph, &s->graph_block_begin, &s->graph_long_begin, &s->graph_scale,
+                     &s->segs, &s->block_ranges, &s->long_first, &s->long_nseg, &s->probe_rows,
+                     &s->probe_block_graph, &s->probe_graph_begin, &s->graph_row_begin};
+    for (DevBuf *b : all) dev_free(c, b);
+}
+
+void free_graph(vne_ctx *c, Graph *g) {
+    dev_free(c, &g->row_ptr);
+    dev_free(c, &g->col);
+    g->alive = false;
+}
+
+Graph *get_graph(vne_ctx *c, int32_t gid) {
+    if (gid < 0 || gid >= (int32_t)c->graphs.size() || !c->graphs[gid] || !c->graphs[gid]->alive) return nullptr;
+    return c->graphs[gid].get();
+}
+
+
+// Work blocks of a set of several graphs: each graph's own schedule, built
+// with one cost per block for the whole set (so that a batch of many small
+// graphs gets a few blocks per graph, not the padded count of a lone graph).
+Schedule set_schedule(const std::vector<Graph *> &gs, const std::vector<int64_t> &row_begin,
+                      const std::vector<int64_t> &nnz_begin, std::vector<int32_t> *gbb, std::vector<int32_t> *glb,
+                      std::vector<int32_t> *bg) {
+    int64_t total = 0;
+    for (const Graph *g : gs) total += g->nnz + 4 * g->n;
+    const int max_blocks = std::max(8, env_int("VNE_SET_MAX_BLOCKS", 4096));
+    const int64_t cpb = std::max<int64_t>(256, (total + max_blocks - 1) / max_blocks);
+    std::vector<Schedule> parts;
+    for (const Graph *g : gs)
+        parts.push_back(build_schedule(g->h_row_ptr.data(), g->n, g->sched.seg_len, cpb, max_blocks, false));
+    return stack_schedules(parts, std::vector<int64_t>(row_begin.begin(), row_begin.end() - 1),
+                           std::vector<int64_t>(nnz_begin.begin(), nnz_begin.end() - 1), gbb, glb, bg);
+}
+
+// The set of the given graphs (built and cached on first use).
+vne_status get_set(vne_ctx *c, const std::vector<int32_t> &ids, GraphSet **out) {
+    auto it = c->sets.find(ids);
+    if (it != c->sets.end()) {
+        it->second->last_use = ++c->tick;
+        *out = it->second.get();
+        return VNE_OK;
+    }
+    if (ids.size() > 1) {
+        // keep at most VNE_MAX_SETS stacked sets (least recently used first out)
+        const size_t cap = (size_t)std::max(1, env_int("VNE_MAX_SETS", 4));
+        for (;;) {
+            size_t multi = 0;
+            auto victim = c->sets.end();
+            for (auto jt = c->sets.begin(); jt != c->sets.end(); ++jt) {
+                if (jt->second->G < 2) continue;
+                ++multi;
+                if (victim == c->sets.end() || jt->second->last_use < victim->second->last_use) victim = jt;
+            }
+            if (multi < cap) break;
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            free_set(c, victim->second.get());
+            c->sets.erase(victim);
+        }
+    }
+    auto s = std::make_unique<GraphSet>();
+    s->last_use = ++c->tick;
+    s->ids = ids;
+    s->G = (int)ids.size();
+    std::vector<Graph *> gs;
+    for (int32_t id : ids) {
+        Graph *g = get_graph(c, id);
+        if (!g) return fail(c, VNE_EINVAL, "unknown graph id " + std::to_string(id));
+        gs.push_back(g);
+    }
+    const int G = s->G;
+    s->h_row_begin.assign(G + 1, 0);
+    std::vector<int64_t> nnz_begin(G + 1, 0);
+    for (int q = 0; q < G; ++q) {
+        s->h_row_begin[q + 1] = s->h_row_begin[q] + gs[q]->n;
+        nnz_begin[q + 1] = nnz_begin[q] + gs[q]->nnz;
+        s->zero_rowsum = s->zero_rowsum && gs[q]->zero_rowsum;
+    }
+    s->n = s->h_row_begin[G];
+    s->nnz = nnz_begin[G];
+    if (s->n > INT32_MAX - 1 || s->nnz > INT32_MAX) return fail(c, VNE_ENOTSUP, "batch too large for int32 indices");
+    s->scale = gs[0]->scale;
+    vne_status st = VNE_OK;
+    auto fin = [&](vne_status e) {
+        free_set(c, s.get());
+        return e;
+    };
+    // stacked matrix (for one graph: the graph's own index arrays)
+    if (G == 1) {
+        s->d_row_ptr = gs[0]->d_row_ptr;
+        s->d_col = gs[0]->d_col;
+    } else {
+        std::vector<int32_t> rp(s->n + 1), ci(s->nnz), rg(s->n);
+        for (int q = 0; q < G; ++q) {
+            const Graph *g = gs[q];
+            for (int64_t i = 0; i < g->n; ++i) {
+                rp[s->h_row_begin[q] + i] = (int32_t)(g->h_row_ptr[i] + nnz_begin[q]);
+                rg[s->h_row_begin[q] + i] = q;
+            }
+            for (int64_t p = 0; p < g->nnz; ++p) ci[nnz_begin[q] + p] = (int32_t)(g->h_col[p] + s->h_row_begin[q]);
+        }
+        rp[s->n] = (int32_t)s->nnz;
+        std::vector<double> scales(G);
+        for (int q = 0; q < G; ++q) scales[q] = gs[q]->scale;
+        if ((st = upload(c, &s->row_ptr, rp.data(), rp.size())) != VNE_OK ||
+            (st = upload(c, &s->col, ci.data(), ci.size())) != VNE_OK ||
+            (st = upload(c, &s->row_graph, rg.data(), rg.size())) != VNE_OK ||
+            (st = upload(c, &s->graph_scale, scales.data(), scales.size())) != VNE_OK)
+            return fin(st);
+        s->d_row_ptr = (const int32_t *)s->row_ptr.p;
+        s->d_col = (const int32_t *)s->col.p;
+    }
+    {
+        std::vector<float> v32(s->nnz);
+        std::vector<double> v64(s->nnz);
+        std::vector<int64_t> keys(s->n);
+        for (int q = 0; q < G; ++q) {
+            const Graph *g = gs[q];
+            for (int64_t p = 0; p < g->nnz; ++p) {
+                v64[nnz_begin[q] + p] = g->h_val[p];
+                v32[nnz_begin[q] + p] = (float)g->h_val[p];
+            }
+            std::copy(g->h_keys.begin(), g->h_keys.end(), keys.begin() + s->h_row_begin[q]);
+        }
+        if ((st = upload(c, &s->val32, v32.data(), v32.size())) != VNE_OK ||
+            (st = upload(c, &s->val64, v64.data(), v64.size())) != VNE_OK ||
+            (st = upload(c, &s->keys, keys.data(), keys.size())) != VNE_OK)
+            return fin(st);
+    }
+    // work schedule
+    std::vector<int32_t> gbb, glb, bg;
+    if (G == 1) {
+        s->sched = gs[0]->sched;
+        gbb = {0, s->sched.n_blocks()};
+        glb = {0, s->sched.n_long};
+    } else {
+        s->sched = set_schedule(gs, s->h_row_begin, nnz_begin, &gbb, &glb, &bg);
+        std::vector<int32_t> lg(s->sched.n_long);
+        for (int q = 0; q < G; ++q)
+            for (int L = glb[q]; L < glb[q + 1]; ++L) lg[L] = q;
+        if ((st = upload(c, &s->long_graph, lg.data(), lg.size())) != VNE_OK ||
+            (st = upload(c, &s->block_graph, bg.data(), bg.size())) != VNE_OK)
+            return fin(st);
+    }
+    const Schedule &sc = s->sched;
+    if ((st = upload(c, &s->segs, sc.segs.data(), sc.segs.size())) != VNE_OK ||
+        (st = upload(c, &s->block_ranges, sc.block_ranges.data(), sc.block_ranges.size())) != VNE_OK ||
+        (st = upload(c, &s->long_first, sc.long_first.data(), sc.long_first.size())) != VNE_OK ||
+        (st = upload(c, &s->long_nseg, sc.long_nseg.data(), sc.long_nseg.size())) != VNE_OK ||
+        (st = upload(c, &s->graph_block_begin, gbb.data(), gbb.size())) != VNE_OK ||
+        (st = upload(c, &s->graph_long_begin, glb.data(), glb.size())) != VNE_OK)
+        return fin(st);
+    // probe blocks: row ranges inside one graph each, about 2048 blocks in all
+    const int64_t probe_rows = std::min<int64_t>(2048, std::max<int64_t>(64, (s->n + 2047) / 2048));
+    std::vector<int32_t> prows, pbg, pgb(G + 1, 0);
+    for (int q = 0; q < G; ++q) {
+        pgb[q] = (int32_t)pbg.size();
+        for (int64_t r = s->h_row_begin[q]; r < s->h_row_begin[q + 1]; r += probe_rows) {
+            prows.push_back((int32_t)r);
+            pbg.push_back(q);
+        }
+    }
+    pgb[G] = (int32_t)pbg.size();
+    prows.push_back((int32_t)s->n);
+    s->probe_blocks = (int)pbg.size();
+    if ((st = upload(c, &s->probe_rows, prows.data(), prows.size())) != VNE_OK ||
+        (st = upload(c, &s->probe_block_graph, pbg.data(), pbg.size())) != VNE_OK ||
+        (st = upload(c, &s->probe_graph_begin, pgb.data(), pgb.size())) != VNE_OK ||
+        (st = upload(c, &s->graph_row_begin, s->h_row_begin.data(), s->h_row_begin.size())) != VNE_OK)
+        return fin(st);
+    *out = s.get();
+    c->sets[ids] = std::move(s);
+    return VNE_OK;
+}
+
+// Workspace for probe blocks of width m (per graph) and k steps on a set.
+vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool store, int tag, Plan **out) {
     auto key = std::make_tuple(m, k, (int)fp64, (int)store, tag);
-    auto it = g->plans.find(key);
-    if (it != g->plans.end()) {
+    auto it = set->plans.find(key);
+    if (it != set->plans.end()) {
         *out = it->second.get();
         return VNE_OK;
     }
     auto p = std::make_unique<Plan>();
     p->fp64 = fp64;
+    p->G = set->G;
     p->m = m;
     p->k = k;
     p->store = store;
     p->mt = choose_tile(m, fp64, env_int("VNE_TILE", 0));
     p->m_pad = pad_columns(m, p->mt);
-    p->n_tiles = p->m_pad / p->mt;
     const size_t es = fp64 ? 8 : 4;
-    const size_t blk = (size_t)g->n * p->m_pad * es;
-    const Schedule &s = g->sched;
+    const size_t blk = (size_t)set->n * p->m_pad * es;
+    const Schedule &s = set->sched;
+    const size_t cols = (size_t)p->G * p->m_pad;      // (graph, column) pairs
     vne_status st = VNE_OK;
     auto A = [&](DevBuf *b, size_t bytes) {
         if (st == VNE_OK) st = dev_alloc(c, b, bytes);
@@ -200,7 +397,6 @@ vne_status get_plan(vne_ctx *c, Graph *g, int m, int k, bool fp64, bool store, i
         A(&p->V[0], blk);
         A(&p->V[1], blk);
     }
-    const size_t cols = (size_t)p->m_pad;
     A(&p->alpha, cols * k * 8);
     A(&p->beta, cols * k * 8);
     A(&p->st_alpha, cols * 8);
@@ -210,21 +406,24 @@ vne_status get_plan(vne_ctx *c, Graph *g, int m, int k, bool fp64, bool store, i
     A(&p->norm2, cols * 8);
     A(&p->mean, cols * 8);
     A(&p->psi, cols * 8);
-    A(&p->estimate, 8);
+    A(&p->estimate, (size_t)p->G * 8);
     A(&p->flags, 4);
-    A(&p->partials, (size_t)s.n_blocks() * 3 * cols * 8);
-    A(&p->level2, (size_t)kLevel2 * 3 * cols * 8);
-    p->probe_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (g->n + 255) / 256));
-    A(&p->probe_part, (size_t)p->probe_blocks * cols * 8);
-    A(&p->seg_acc, (size_t)std::max(1, s.n_seg) * cols * 8);
-    A(&p->long_part, (size_t)std::max(1, s.n_long) * 3 * cols * 8);
+    A(&p->partials, (size_t)s.n_blocks() * 3 * p->m_pad * 8);
+    A(&p->level2, (size_t)kLevel2 * 3 * p->m_pad * 8);
+    A(&p->probe_part, (size_t)set->probe_blocks * p->m_pad * 8);
+    A(&p->seg_acc, (size_t)std::max(1, s.n_seg) * p->m_pad * 8);
+    A(&p->long_part, (size_t)std::max(1, s.n_long) * 3 * p->m_pad * 8);
+    A(&p->graph_k, (size_t)p->G * 4);
+    A(&p->graph_m, (size_t)p->G * 4);
+    A(&p->seeds, (size_t)p->G * 8);
     if (st != VNE_OK) {
         free_plan(c, p.get());
         return st;
     }
     HIP_TRY(c, hipMemsetAsync(p->long_part.p, 0, p->long_part.bytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(p->seeds.p, 0, p->seeds.bytes, c->stream));
     *out = p.get();
-    g->plans[key] = std::move(p);
+    set->plans[key] = std::move(p);
     return VNE_OK;
 }
 
@@ -243,36 +442,49 @@ vne_status collect_timing(vne_ctx *c) {
     return VNE_OK;
 }
 
+// Probe description for run_lanczos.
 struct ProbeSpec {
     int gen = GEN_RADEMACHER;
-    uint64_t seed = 0;
+    std::vector<uint64_t> seeds;       // per graph (Rademacher)
     int col_offset = 0;
-    const int32_t *colors = nullptr;   // device
-    const void *dense = nullptr;       // device
+    const int32_t *colors = nullptr;   // device, stacked rows
+    const void *dense = nullptr;       // device, stacked rows
     int ld_dense = 0;
+};
+
+struct RunOpts {
+    bool collect = true;               // record kernel timing for this run
+    int steps = -1;                    // autotuner: only this many steps, no graph, no quadrature
+    int tile = 0;                      // column tile (0: the plan's)
 };
 
 // Probe block, k Lanczos steps, quadrature.  Leaves psi, coefficients,
 // k_eff and norm2 in the plan.
-vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool desing) {
-    const Schedule &s = g->sched;
+vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, bool desing,
+                       const RunOpts &opt = RunOpts()) {
+    const Schedule &s = set->sched;
+    const int mt = opt.tile > 0 ? opt.tile : p->mt;
     HIP_TRY(c, hipMemsetAsync(p->flags.p, 0, 4, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(p->graph_k.p, p->h_graph_k.data(), p->G * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(p->graph_m.p, p->h_graph_m.data(), p->G * 4, hipMemcpyHostToDevice, c->stream));
+    if (!ps.seeds.empty())
+        HIP_TRY(c, hipMemcpyAsync(p->seeds.p, ps.seeds.data(), p->G * 8, hipMemcpyHostToDevice, c->stream));
     ProbeArgs pa{};
     pa.gen = ps.gen;
-    pa.n = (int32_t)g->n;
+    pa.n = (int32_t)set->n;
     pa.m = p->m;
     pa.m_pad = p->m_pad;
-    pa.mt = p->mt;
+    pa.mt = mt;
     pa.col_offset = ps.col_offset;
-    pa.seed = ps.seed;
-    pa.keys = g->d_keys;
+    pa.seed = ps.seeds.empty() ? 0 : ps.seeds[0];
+    pa.keys = (const int64_t *)set->keys.p;
     pa.colors = ps.colors;
     pa.dense = ps.dense;
     pa.ld_dense = ps.ld_dense;
     pa.desing = desing ? 1 : 0;
     pa.P_out = p->P[0].p;
     pa.partials = (double *)p->probe_part.p;
-    pa.n_blocks = p->probe_blocks;
+    pa.n_blocks = set->probe_blocks;
     pa.mean = (double *)p->mean.p;
     pa.norm2 = (double *)p->norm2.p;
     pa.st_alpha = (double *)p->st_alpha.p;
@@ -280,30 +492,52 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
     pa.st_coup = (double *)p->st_coup.p;
     pa.k_eff = (int32_t *)p->k_eff.p;
     pa.k = p->k;
+    pa.block_row_begin = (const int32_t *)set->probe_rows.p;
+    pa.block_graph = (const int32_t *)set->probe_block_graph.p;
+    pa.graph_block_begin = (const int32_t *)set->probe_graph_begin.p;
+    pa.graph_row_begin = (const int64_t *)set->graph_row_begin.p;
+    pa.seeds = (const uint64_t *)p->seeds.p;
+    pa.graph_k = (const int32_t *)p->graph_k.p;
+    pa.graph_m = (const int32_t *)p->graph_m.p;
+    pa.n_graphs = p->G;
     HIP_TRY(c, launch_probe(pa, p->fp64, c->stream));
 
     const size_t es = p->fp64 ? 8 : 4;
-    const size_t blk_elems = (size_t)g->n * p->m_pad;
-    const double bytes = 4.0 * (g->n + 1) + (double)g->nnz * (4.0 + es) + 3.0 * g->n * p->m * es;
+    const size_t blk_elems = (size_t)set->n * p->m_pad;
+    // algorithmic bytes of one step launch: CSR once, v_j gathered once,
+    // v_{j-1} read once, P_{j+1} written once (real columns only)
+    int64_t m_sum = 0;
+    for (int q = 0; q < p->G; ++q) m_sum += (int64_t)p->h_graph_m[q] * (set->h_row_begin[q + 1] - set->h_row_begin[q]);
+    const double bytes = 4.0 * (set->n + 1) + (double)set->nnz * (4.0 + es) + 3.0 * (double)m_sum * es;
     StepArgs a{};
-    a.row_ptr = g->d_row_ptr;
-    a.col = g->d_col;
-    a.val = p->fp64 ? (const void *)g->d_val64 : (const void *)g->d_val32;
-    a.scale = g->scale;
-    a.n = (int32_t)g->n;
+    a.row_ptr = set->d_row_ptr;
+    a.col = set->d_col;
+    a.val = p->fp64 ? set->val64.p : set->val32.p;
+    a.scale = set->scale;
+    a.n = (int32_t)set->n;
     a.m_pad = p->m_pad;
-    a.mt = p->mt;
-    a.n_tiles = p->n_tiles;
+    a.mt = mt;
+    a.n_tiles = p->m_pad / mt;
     a.st_alpha = (const double *)p->st_alpha.p;
     a.st_inv = (const double *)p->st_inv.p;
     a.st_coup = (const double *)p->st_coup.p;
-    a.segs = (const SegItem *)g->segs.p;
+    a.segs = (const SegItem *)set->segs.p;
     a.n_seg = s.n_seg;
     a.seg_len = s.seg_len;
-    a.block_begin = (const int32_t *)g->block_begin.p;
+    a.block_ranges = (const int4 *)set->block_ranges.p;
     a.n_blocks = s.n_blocks();
     a.seg_acc = (double *)p->seg_acc.p;
     a.n_long = s.n_long;
+    a.long_first = (const int32_t *)set->long_first.p;
+    a.long_nseg = (const int32_t *)set->long_nseg.p;
+    a.long_part = (double *)p->long_part.p;
+    a.partials = (double *)p->partials.p;
+    if (set->G > 1) {
+        a.block_graph = (const int32_t *)set->block_graph.p;
+        a.row_graph = (const int32_t *)set->row_graph.p;
+        a.long_graph = (const int32_t *)set->long_graph.p;
+        a.graph_scale = (const double *)set->graph_scale.p;
+    }
     // schedule: normalize pass + single-stream SpMM by default (measured
     // faster on both random and ring-local graphs); the lazy one-pass
     // schedule (4 streams, two of them gathered) stays selectable
@@ -311,10 +545,6 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
         const int forced = env_int("VNE_SCHED", -1);
         a.two_pass = forced >= 0 ? forced : 1;
     }
-    a.long_first = (const int32_t *)g->long_first.p;
-    a.long_nseg = (const int32_t *)g->long_nseg.p;
-    a.long_part = (double *)p->long_part.p;
-    a.partials = (double *)p->partials.p;
 
     FinalizeArgs f{};
     f.partials = (const double *)p->partials.p;
@@ -323,7 +553,7 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
     f.n_level2 = kLevel2;
     f.n_blocks = s.n_blocks();
     f.n_long = s.n_long;
-    f.mt = p->mt;
+    f.mt = mt;
     f.m_pad = p->m_pad;
     f.m = p->m;
     f.k = p->k;
@@ -335,9 +565,17 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
     f.beta = (double *)p->beta.p;
     f.k_eff = (int32_t *)p->k_eff.p;
     f.flags = (int32_t *)p->flags.p;
+    f.n_graphs = p->G;
+    f.segmented = p->G > 1 ? 1 : 0;
+    f.graph_block_begin = (const int32_t *)set->graph_block_begin.p;
+    f.graph_long_begin = (const int32_t *)set->graph_long_begin.p;
+    f.graph_k = (const int32_t *)p->graph_k.p;
+    f.graph_m = (const int32_t *)p->graph_m.p;
 
-    const bool use_graph = env_int("VNE_GRAPH", 1) != 0;
-    const bool timing = c->timing;
+    const bool tuning = opt.steps > 0;
+    const int nsteps = tuning ? std::min(opt.steps, p->k) : p->k;
+    const bool use_graph = env_int("VNE_GRAPH", 1) != 0 && !tuning;
+    const bool timing = c->timing && opt.collect;
     // part 0: the step kernels of step j; part 1: its reduction and finalize
     auto issue = [&](int j, int part) -> vne_status {
         char *Pb[2] = {(char *)p->P[0].p, (char *)p->P[1].p};
@@ -381,26 +619,24 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
         }
         return VNE_OK;
     };
-    if (timing && p->ev.size() < (size_t)(2 * p->k)) {
+    if (timing) {
         while (p->ev.size() < (size_t)(2 * p->k)) {
             hipEvent_t e;
             HIP_TRY(c, hipEventCreate(&e));
             p->ev.push_back(e);
         }
     }
-    const int sched = a.two_pass ? 1 : 0;
-    vne_status st = VNE_OK;
+    const auto key = std::make_pair(a.two_pass ? 1 : 0, mt);
     if (use_graph && !timing) {
-        hipGraphExec_t &ex = p->exec[sched];
-        if (!ex && (st = capture(&ex, 1, p->k, -1)) != VNE_OK) return st;
+        hipGraphExec_t &ex = p->exec[key];
+        if (!ex) VNE_TRY(capture(&ex, 1, p->k, -1));
         HIP_TRY(c, hipGraphLaunch(ex, c->stream));
     } else if (use_graph) {
-        auto &parts = p->part_exec[sched];
+        auto &parts = p->part_exec[key];
         if (parts.empty()) {
             parts.assign(2 * p->k, nullptr);
             for (int j = 1; j <= p->k; ++j)
-                for (int part = 0; part < 2; ++part)
-                    if ((st = capture(&parts[2 * (j - 1) + part], j, j, part)) != VNE_OK) return st;
+                for (int part = 0; part < 2; ++part) VNE_TRY(capture(&parts[2 * (j - 1) + part], j, j, part));
         }
         for (int j = 1; j <= p->k; ++j) {
             HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1)], c->stream));
@@ -409,34 +645,296 @@ vne_status run_lanczos(vne_ctx *c, Graph *g, Plan *p, const ProbeSpec &ps, bool 
             HIP_TRY(c, hipGraphLaunch(parts[2 * (j - 1) + 1], c->stream));
         }
     } else {
-        for (int j = 1; j <= p->k; ++j) {
+        for (int j = 1; j <= nsteps; ++j) {
             if (timing) HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1)], c->stream));
-            if ((st = issue(j, 0)) != VNE_OK) return st;
+            VNE_TRY(issue(j, 0));
             if (timing) HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1) + 1], c->stream));
-            if ((st = issue(j, 1)) != VNE_OK) return st;
+            VNE_TRY(issue(j, 1));
         }
     }
-    if (timing) {
-        c->pending.push_back({p, bytes});
-    }
-    HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p,
-                                 (const int32_t *)p->k_eff.p, (const double *)p->norm2.p, p->k, p->m,
-                                 (double *)p->psi.p, (int32_t *)p->flags.p, c->stream));
+    if (tuning) return VNE_OK;
+    if (timing) c->pending.push_back({p, bytes});
+    HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p, (const int32_t *)p->k_eff.p,
+                                 (const double *)p->norm2.p, p->k, p->G * p->m_pad, (double *)p->psi.p,
+                                 (int32_t *)p->flags.p, c->stream));
     return VNE_OK;
 }
 
-vne_status copy_out(vne_ctx *c, Plan *p, vne_result *out, int32_t *flags_h) {
-    const int m = p->m, k = p->k;
+// Column tile of a plan, chosen by timing a few steps of every tile that
+// divides the padded width; cached per set shape.  VNE_AUTOTUNE=0 (or a
+// forced VNE_TILE) keeps the default rule; VNE_AUTOTUNE_CACHE names a file
+// that keeps the choices across processes.
+vne_status autotune(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, bool desing) {
+    if (const int forced = env_int("VNE_TILE", 0); forced > 0) {
+        const int t = choose_tile(p->m, p->fp64, forced);
+        if (p->m_pad % t == 0) p->mt = t;
+        return VNE_OK;
+    }
+    if (env_int("VNE_AUTOTUNE", 1) == 0) return VNE_OK;
+    std::ostringstream sig;
+    sig << "G" << set->G << "_n" << set->n << "_nnz" << set->nnz << "_m" << p->m_pad << (p->fp64 ? "_f64" : "_f32")
+        << "_s" << set->sched.seg_len << "_b" << set->sched.n_blocks();
+    auto it = c->tuned.find(sig.str());
+    if (it != c->tuned.end()) {
+        if (p->m_pad % it->second == 0) p->mt = it->second;
+        return VNE_OK;
+    }
+    const int cpl = p->fp64 ? 2 : 4;
+    std::vector<int> cands;
+    for (int t = cpl * 4; t <= cpl * 64; t *= 2)
+        if (t <= p->m_pad && p->m_pad % t == 0) cands.push_back(t);
+    int best = p->mt;
+    if (cands.size() > 1) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_TRY(c, hipEventCreate(&e0));
+        HIP_TRY(c, hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        vne_status st = VNE_OK;
+        for (int t : cands) {
+            RunOpts o;
+            o.collect = false;
+            o.steps = std::min(3, p->k);
+            o.tile = t;
+            if ((st = run_lanczos(c, set, p, ps, desing, o)) != VNE_OK) break;   // warm-up
+            hipError_t e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess && (st = run_lanczos(c, set, p, ps, desing, o)) != VNE_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = hip_fail(c, e, "autotune timing");
+                break;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        VNE_TRY(st);
+    }
+    p->mt = best;
+    c->tuned[sig.str()] = best;
+    if (!c->tune_file.empty()) {
+        std::ofstream f(c->tune_file, std::ios::app);
+        if (f) f << sig.str() << " " << best << "\n";
+    }
+    return VNE_OK;
+}
+
+vne_status check_flags(vne_ctx *c, int32_t fl) {
+    if (fl & 2) return fail(c, VNE_ENUMERIC, "Cholesky of the sketch Gram matrix failed (rank-deficient sketch)");
+    if (fl & 1) return fail(c, VNE_ENUMERIC, "non-finite Lanczos coefficient");
+    if (fl & 4) return fail(c, VNE_ENUMERIC, "tridiagonal QR did not converge");
+    if (fl & 8) return fail(c, VNE_ENUMERIC, "tridiagonal QR rotation record overflowed");
+    return VNE_OK;
+}
+
+// Results of every graph of the plan: one device-to-host copy per array,
+// then scattered into out[q] (m[q] columns, k[q] steps).  Also reads the
+// flag word of the plan (and of extra, if given) and synchronises.
+vne_status copy_out(vne_ctx *c, Plan *p, const int32_t *m, const int32_t *k, vne_result *out, Plan *extra) {
     hipStream_t s = c->stream;
-    HIP_TRY(c, hipMemcpyAsync(&out->estimate, p->estimate.p, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipMemcpyAsync(flags_h, p->flags.p, 4, hipMemcpyDeviceToHost, s));
-    if (out->quad) HIP_TRY(c, hipMemcpyAsync(out->quad, p->psi.p, (size_t)m * 8, hipMemcpyDeviceToHost, s));
-    if (out->alpha)
-        HIP_TRY(c, hipMemcpyAsync(out->alpha, p->alpha.p, (size_t)m * k * 8, hipMemcpyDeviceToHost, s));
-    if (out->beta) HIP_TRY(c, hipMemcpyAsync(out->beta, p->beta.p, (size_t)m * k * 8, hipMemcpyDeviceToHost, s));
-    if (out->k_eff) HIP_TRY(c, hipMemcpyAsync(out->k_eff, p->k_eff.p, (size_t)m * 4, hipMemcpyDeviceToHost, s));
-    if (out->norm2) HIP_TRY(c, hipMemcpyAsync(out->norm2, p->norm2.p, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+    const int G = p->G;
+    const size_t cols = (size_t)G * p->m_pad;
+    bool any_quad = false, any_alpha = false, any_beta = false, any_keff = false, any_norm = false;
+    for (int q = 0; q < G; ++q) {
+        any_quad |= out[q].quad != nullptr;
+        any_alpha |= out[q].alpha != nullptr;
+        any_beta |= out[q].beta != nullptr;
+        any_keff |= out[q].k_eff != nullptr;
+        any_norm |= out[q].norm2 != nullptr;
+    }
+    std::vector<double> est(G), psi(any_quad ? cols : 0), nrm(any_norm ? cols : 0);
+    std::vector<double> al(any_alpha ? cols * p->k : 0), be(any_beta ? cols * p->k : 0);
+    std::vector<int32_t> ke(any_keff ? cols : 0);
+    int32_t fl[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(est.data(), p->estimate.p, (size_t)G * 8, hipMemcpyDeviceToHost, s));
+    if (any_quad) HIP_TRY(c, hipMemcpyAsync(psi.data(), p->psi.p, cols * 8, hipMemcpyDeviceToHost, s));
+    if (any_norm) HIP_TRY(c, hipMemcpyAsync(nrm.data(), p->norm2.p, cols * 8, hipMemcpyDeviceToHost, s));
+    if (any_keff) HIP_TRY(c, hipMemcpyAsync(ke.data(), p->k_eff.p, cols * 4, hipMemcpyDeviceToHost, s));
+    if (any_alpha) HIP_TRY(c, hipMemcpyAsync(al.data(), p->alpha.p, al.size() * 8, hipMemcpyDeviceToHost, s));
+    if (any_beta) HIP_TRY(c, hipMemcpyAsync(be.data(), p->beta.p, be.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(&fl[0], p->flags.p, 4, hipMemcpyDeviceToHost, s));
+    if (extra) HIP_TRY(c, hipMemcpyAsync(&fl[1], extra->flags.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->timing) VNE_TRY(collect_timing(c));
+    for (int q = 0; q < G; ++q) {
+        const size_t c0 = (size_t)q * p->m_pad;
+        vne_result &o = out[q];
+        o.estimate = est[q];
+        if (o.quad) std::memcpy(o.quad, psi.data() + c0, (size_t)m[q] * 8);
+        if (o.norm2) std::memcpy(o.norm2, nrm.data() + c0, (size_t)m[q] * 8);
+        if (o.k_eff) std::memcpy(o.k_eff, ke.data() + c0, (size_t)m[q] * 4);
+        for (int col = 0; col < m[q]; ++col) {
+            if (o.alpha) std::memcpy(o.alpha + (size_t)col * k[q], al.data() + (c0 + col) * p->k, (size_t)k[q] * 8);
+            if (o.beta) std::memcpy(o.beta + (size_t)col * k[q], be.data() + (c0 + col) * p->k, (size_t)k[q] * 8);
+        }
+    }
+    return check_flags(c, fl[0] | fl[1]);
+}
+
+vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int k, bool fp64, bool desing,
+                            vne_result *out) {
+    const int nr = pr->n_sketch, m = pr->m, nh = m - nr;
+    if (nr < 1 || nh < 0 || nr > 128) return fail(c, VNE_ENOTSUP, "Hutch++ needs 1 <= n_sketch <= min(m, 128)");
+    const size_t es = fp64 ? 8 : 4;
+    Plan *sk = nullptr, *q = nullptr;
+    VNE_TRY(get_plan(c, set, nr, k, fp64, true, 1, &sk));
+    VNE_TRY(get_plan(c, set, m, k, fp64, false, 2, &q));
+    const int64_t n = set->n;
+    vne_status st = VNE_OK;
+    if (!q->B.p) {
+        auto A = [&](DevBuf *b, size_t bytes) {
+            if (st == VNE_OK) st = dev_alloc(c, b, bytes);
+        };
+        A(&q->S, (size_t)nr * k * 8);
+        A(&q->B, (size_t)n * m * es);
+        const int64_t gd = std::max(gram_scratch_doubles((int32_t)n, nr, nr),
+                                    gram_scratch_doubles((int32_t)n, nr, std::max(nh, 1)));
+        A(&q->gram_part, (size_t)gd * 8);
+        A(&q->gram, (size_t)nr * std::max(nr, nh) * 8);
+        A(&q->rinv, (size_t)nr * nr * 8);
+        A(&q->rot, (size_t)nr * rot_capacity(k) * kRotBytes);
+        VNE_TRY(st);
+    }
+    sk->h_graph_k = {k};
+    sk->h_graph_m = {nr};
+    q->h_graph_k = {k};
+    q->h_graph_m = {m};
+    hipStream_t s = c->stream;
+    const int64_t *keys = (const int64_t *)set->keys.p;
+    // 1. sketch: k Lanczos steps on Omega (kept basis), then Y = f(A) Omega by eq. (4.3)
+    ProbeSpec ps;
+    ps.gen = GEN_RADEMACHER;
+    ps.seeds = {pr->seed};
+    VNE_TRY(run_lanczos(c, set, sk, ps, desing));
+    HIP_TRY(c, launch_fT_e1((const double *)sk->alpha.p, (const double *)sk->beta.p, (const int32_t *)sk->k_eff.p,
+                            k, nr, (double *)q->S.p, q->rot.p, (int32_t *)sk->flags.p, s));
+    const int64_t step_stride = n * sk->m_pad;
+    HIP_TRY(c, launch_reconstruct(sk->Vstore.p, fp64, step_stride, sk->m_pad, (const double *)q->S.p,
+                                  (const double *)sk->norm2.p, k, (int32_t)n, nr, q->B.p, m, s));
+    // 2. G block, raw +-1 in the columns after the sketch
+    if (nh > 0) HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)n, nh, m, nr, nr, pr->seed, keys, s));
+    // 3. Q = orth(Y) by CholeskyQR (FP64 Gram and triangular factors), in
+    // place; a second pass in FP64 mode (with FP32 storage the rounding of Q
+    // itself bounds its orthogonality, so one pass suffices)
+    for (int pass = 0; pass < (fp64 ? 2 : 1); ++pass) {
+        HIP_TRY(c, launch_gram(q->B.p, m, q->B.p, m, fp64, (int32_t)n, nr, nr, (double *)q->gram_part.p,
+                               (double *)q->gram.p, s));
+        HIP_TRY(c, launch_cholinv((double *)q->gram.p, (double *)q->rinv.p, nr, (int32_t *)sk->flags.p, s));
+        HIP_TRY(c, launch_apply(q->B.p, m, (const double *)q->rinv.p, nr, nr, q->B.p, m, fp64, (int32_t)n, 0, s));
+    }
+    // 4. G~ = G - Q (Q^T G)
+    if (nh > 0) {
+        char *Gp = (char *)q->B.p + (size_t)nr * es;
+        HIP_TRY(c, launch_gram(q->B.p, m, Gp, m, fp64, (int32_t)n, nr, nh, (double *)q->gram_part.p,
+                               (double *)q->gram.p, s));
+        HIP_TRY(c, launch_apply(q->B.p, m, (const double *)q->gram.p, nr, nh, Gp, m, fp64, (int32_t)n, 1, s));
+    }
+    // 5. quadratic forms of [Q | G~] and the Hutch++ combination (3.9)
+    ProbeSpec pq;
+    pq.gen = GEN_DENSE;
+    pq.dense = q->B.p;
+    pq.ld_dense = m;
+    VNE_TRY(run_lanczos(c, set, q, pq, desing));
+    HIP_TRY(c, launch_combine((const double *)q->psi.p, m, 2, nr, (double *)q->estimate.p, s));
+    const int32_t mm = m, kk = k;
+    return copy_out(c, q, &mm, &kk, out, sk);
+}
+
+// One query per graph of the set, all graphs in one stacked launch per step.
+vne_status estimate_set(vne_ctx *c, GraphSet *set, const vne_probes *pr, const int32_t *k_steps, bool fp64,
+                        bool desing, vne_result *out) {
+    const int G = set->G;
+    const int kind = pr[0].kind;
+    int k_max = 0, m_max = 0;
+    std::vector<int32_t> ms(G);
+    for (int q = 0; q < G; ++q) {
+        if (pr[q].kind != kind) return fail(c, VNE_ENOTSUP, "a batch takes one probe kind");
+        if (pr[q].m < 1) return fail(c, VNE_EINVAL, "probe count m must be >= 1");
+        if (k_steps[q] < 1 || k_steps[q] > kMaxSteps) return fail(c, VNE_EINVAL, "k_steps must be in [1, 128]");
+        k_max = std::max(k_max, (int)k_steps[q]);
+        m_max = std::max(m_max, (int)pr[q].m);
+        ms[q] = pr[q].m;
+    }
+    if (m_max > (1 << 20)) return fail(c, VNE_ENOTSUP, "probe count too large");
+    Plan *p = nullptr;
+    VNE_TRY(get_plan(c, set, m_max, k_max, fp64, false, 0, &p));
+    p->h_graph_k.assign(k_steps, k_steps + G);
+    p->h_graph_m = ms;
+    ProbeSpec ps;
+    int combine_kind = 0;
+    const size_t es = fp64 ? 8 : 4;
+    switch (kind) {
+        case VNE_PROBE_RADEMACHER:
+            ps.gen = GEN_RADEMACHER;
+            for (int q = 0; q < G; ++q) ps.seeds.push_back(pr[q].seed);
+            break;
+        case VNE_PROBE_COLORING: {
+            ps.gen = GEN_COLORING;
+            combine_kind = 1;
+            if (G == 1 && pr[0].location == VNE_DEVICE) {
+                if (!pr[0].colors) return fail(c, VNE_EINVAL, "colors is NULL");
+                ps.colors = pr[0].colors;
+                break;
+            }
+            std::vector<int32_t> col(set->n);
+            for (int q = 0; q < G; ++q) {
+                if (!pr[q].colors || pr[q].location != VNE_HOST)
+                    return fail(c, VNE_EINVAL, "colors must be host arrays in a batch");
+                const int64_t r0 = set->h_row_begin[q], nq = set->h_row_begin[q + 1] - r0;
+                for (int64_t i = 0; i < nq; ++i) {
+                    const int32_t v = pr[q].colors[i];
+                    if (v < 0 || v >= pr[q].m)
+                        return fail(c, VNE_EINVAL, "colour out of range at row " + std::to_string(i));
+                    col[r0 + i] = v;
+                }
+            }
+            if (!p->colors.p) VNE_TRY(dev_alloc(c, &p->colors, (size_t)set->n * 4));
+            HIP_TRY(c, hipMemcpyAsync(p->colors.p, col.data(), (size_t)set->n * 4, hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            ps.colors = (const int32_t *)p->colors.p;
+            break;
+        }
+        case VNE_PROBE_DENSE: {
+            ps.gen = GEN_DENSE;
+            if (G == 1 && pr[0].location == VNE_DEVICE) {
+                if (!pr[0].dense) return fail(c, VNE_EINVAL, "dense is NULL");
+                ps.dense = pr[0].dense;
+                ps.ld_dense = pr[0].m;
+                break;
+            }
+            std::vector<char> buf((size_t)set->n * m_max * es, 0);
+            for (int q = 0; q < G; ++q) {
+                if (!pr[q].dense || pr[q].location != VNE_HOST)
+                    return fail(c, VNE_EINVAL, "dense blocks must be host arrays in a batch");
+                const int64_t r0 = set->h_row_begin[q], nq = set->h_row_begin[q + 1] - r0;
+                for (int64_t i = 0; i < nq; ++i)
+                    std::memcpy(buf.data() + (size_t)(r0 + i) * m_max * es,
+                                (const char *)pr[q].dense + (size_t)i * pr[q].m * es, (size_t)pr[q].m * es);
+            }
+            if (!p->dense.p) VNE_TRY(dev_alloc(c, &p->dense, buf.size()));
+            HIP_TRY(c, hipMemcpyAsync(p->dense.p, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            ps.dense = p->dense.p;
+            ps.ld_dense = m_max;
+            break;
+        }
+        default:
+            return fail(c, VNE_EINVAL, "unknown probe kind");
+    }
+    VNE_TRY(autotune(c, set, p, ps, desing));
+    VNE_TRY(run_lanczos(c, set, p, ps, desing));
+    HIP_TRY(c, launch_combine_graphs((const double *)p->psi.p, p->m_pad, (const int32_t *)p->graph_m.p, G,
+                                     combine_kind, (double *)p->estimate.p, c->stream));
+    return copy_out(c, p, ms.data(), k_steps, out, nullptr);
+}
+
+vne_status check_mode(vne_ctx *c, uint32_t mode) {
+    if (mode & ~(uint32_t)(VNE_MODE_F64 | VNE_MODE_DESING)) return fail(c, VNE_EINVAL, "unknown mode bits");
     return VNE_OK;
 }
 
@@ -480,6 +978,14 @@ extern "C" vne_status vne_ctx_create(int device, uint64_t hbm_budget_bytes, void
         return VNE_EDEVICE;
     }
     c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
+    if (const char *tf = getenv("VNE_AUTOTUNE_CACHE")) {
+        c->tune_file = tf;
+        std::ifstream f(tf);
+        std::string sig;
+        int t;
+        while (f >> sig >> t)
+            if (t > 0) c->tuned[sig] = t;
+    }
     *out = c;
     return VNE_OK;
 }
@@ -488,6 +994,8 @@ extern "C" void vne_ctx_destroy(vne_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->sets) free_set(c, kv.second.get());
+    c->sets.clear();
     for (auto &g : c->graphs)
         if (g) free_graph(c, g.get());
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -518,93 +1026,66 @@ extern "C" vne_status vne_graph_register(vne_ctx *c, const vne_csr *csr, uint32_
     const int64_t n = csr->n, nnz = csr->nnz;
     if (n < 1 || nnz < 0 || nnz > INT32_MAX || n > INT32_MAX - 1) return fail(c, VNE_EINVAL, "bad sizes");
     if (csr->location != VNE_HOST && csr->location != VNE_DEVICE) return fail(c, VNE_EINVAL, "bad location");
+    if (csr->value_dtype != VNE_F32 && csr->value_dtype != VNE_F64) return fail(c, VNE_EINVAL, "bad value dtype");
+    auto g = std::make_unique<Graph>();
     // host view of the three arrays (copied back for device input)
-    std::vector<int32_t> h_rp, h_ci;
+    const size_t vs = csr->value_dtype == VNE_F64 ? 8 : 4;
     std::vector<char> h_val;
     vne_csr hv = *csr;
-    const size_t vs = csr->value_dtype == VNE_F64 ? 8 : 4;
     if (csr->location == VNE_DEVICE) {
         if (!csr->row_ptr || (nnz && (!csr->col_idx || !csr->values))) return fail(c, VNE_EINVAL, "NULL CSR array");
-        h_rp.resize(n + 1);
-        h_ci.resize(nnz);
+        g->h_row_ptr.resize(n + 1);
+        g->h_col.resize(nnz);
         h_val.resize(nnz * vs);
-        HIP_TRY(c, hipMemcpy(h_rp.data(), csr->row_ptr, (n + 1) * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(g->h_row_ptr.data(), csr->row_ptr, (n + 1) * 4, hipMemcpyDeviceToHost));
         if (nnz) {
-            HIP_TRY(c, hipMemcpy(h_ci.data(), csr->col_idx, nnz * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(c, hipMemcpy(g->h_col.data(), csr->col_idx, nnz * 4, hipMemcpyDeviceToHost));
             HIP_TRY(c, hipMemcpy(h_val.data(), csr->values, nnz * vs, hipMemcpyDeviceToHost));
         }
-        hv.row_ptr = h_rp.data();
-        hv.col_idx = h_ci.data();
+        hv.row_ptr = g->h_row_ptr.data();
+        hv.col_idx = g->h_col.data();
         hv.values = h_val.data();
         hv.location = VNE_HOST;
     }
     std::string msg;
     vne_status st = validate_host_csr(&hv, flags, &msg);
     if (st != VNE_OK) return fail(c, st, msg);
-
-    auto g = std::make_unique<Graph>();
+    if (csr->location == VNE_HOST) {
+        g->h_row_ptr.assign(hv.row_ptr, hv.row_ptr + n + 1);
+        g->h_col.assign(hv.col_idx, hv.col_idx + nnz);
+    }
     g->n = n;
     g->nnz = nnz;
     g->scale = csr->scale;
-    std::vector<float> v32(nnz);
-    std::vector<double> v64(nnz);
-    for (int64_t p = 0; p < nnz; ++p) {
-        double v = csr->value_dtype == VNE_F64 ? ((const double *)hv.values)[p] : (double)((const float *)hv.values)[p];
-        v64[p] = v;
-        v32[p] = (float)v;
-    }
-    {
-        int64_t off = 0, near = 0;
-        for (int64_t i = 0; i < n; ++i)
-            for (int32_t q = hv.row_ptr[i]; q < hv.row_ptr[i + 1]; ++q) {
-                const int64_t j = hv.col_idx[q];
-                if (j == i) continue;
-                ++off;
-                near += (j - i <= 256 && i - j <= 256);
-            }
-        g->local_frac = off ? (double)near / (double)off : 1.0;
-    }
+    g->h_val.resize(nnz);
+    for (int64_t p = 0; p < nnz; ++p)
+        g->h_val[p] = csr->value_dtype == VNE_F64 ? ((const double *)hv.values)[p] : (double)((const float *)hv.values)[p];
     g->zero_rowsum = true;
     for (int64_t i = 0; i < n && g->zero_rowsum; ++i) {
         double rs = 0.0;
-        for (int32_t q = hv.row_ptr[i]; q < hv.row_ptr[i + 1]; ++q) rs += v64[q];
+        for (int32_t q = g->h_row_ptr[i]; q < g->h_row_ptr[i + 1]; ++q) rs += g->h_val[q];
         g->zero_rowsum = rs == 0.0;
     }
-    std::vector<int64_t> keys(n);
-    for (int64_t i = 0; i < n; ++i) keys[i] = csr->node_keys ? csr->node_keys[i] : i;
+    g->h_keys.resize(n);
+    for (int64_t i = 0; i < n; ++i) g->h_keys[i] = csr->node_keys ? csr->node_keys[i] : i;
     if (csr->location == VNE_DEVICE) {
         g->d_row_ptr = csr->row_ptr;
         g->d_col = csr->col_idx;
     } else {
-        if ((st = upload(c, &g->row_ptr, hv.row_ptr, n + 1)) != VNE_OK) { free_graph(c, g.get()); return st; }
-        if ((st = upload(c, &g->col, hv.col_idx, nnz)) != VNE_OK) { free_graph(c, g.get()); return st; }
+        if ((st = upload(c, &g->row_ptr, g->h_row_ptr.data(), n + 1)) != VNE_OK ||
+            (st = upload(c, &g->col, g->h_col.data(), nnz)) != VNE_OK) {
+            free_graph(c, g.get());
+            return st;
+        }
         g->d_row_ptr = (const int32_t *)g->row_ptr.p;
         g->d_col = (const int32_t *)g->col.p;
     }
-    if ((st = upload(c, &g->val32, v32.data(), nnz)) != VNE_OK ||
-        (st = upload(c, &g->val64, v64.data(), nnz)) != VNE_OK ||
-        (st = upload(c, &g->keys, keys.data(), n)) != VNE_OK) {
-        free_graph(c, g.get());
-        return st;
-    }
-    g->d_val32 = (const float *)g->val32.p;
-    g->d_val64 = (const double *)g->val64.p;
-    g->d_keys = (const int64_t *)g->keys.p;
-
     // work schedule: segments of long rows, cost-balanced blocks
     const int seg_len = std::max(1, env_int("VNE_SEG_LEN", 64));
     const int max_blocks = std::max(8, env_int("VNE_MAX_BLOCKS", 1024));
-    int64_t total_cost = nnz + 4 * n;
-    int64_t cpb = std::max<int64_t>(256, (total_cost + max_blocks - 1) / max_blocks);
-    g->sched = build_schedule(hv.row_ptr, n, seg_len, cpb, max_blocks);
-    const Schedule &s = g->sched;
-    if ((st = upload(c, &g->segs, s.segs.data(), s.segs.size())) != VNE_OK ||
-        (st = upload(c, &g->block_begin, s.block_begin.data(), s.block_begin.size())) != VNE_OK ||
-        (st = upload(c, &g->long_first, s.long_first.data(), s.long_first.size())) != VNE_OK ||
-        (st = upload(c, &g->long_nseg, s.long_nseg.data(), s.long_nseg.size())) != VNE_OK) {
-        free_graph(c, g.get());
-        return st;
-    }
+    const int64_t total_cost = nnz + 4 * n;
+    const int64_t cpb = std::max<int64_t>(256, (total_cost + max_blocks - 1) / max_blocks);
+    g->sched = build_schedule(g->h_row_ptr.data(), n, seg_len, cpb, max_blocks);
     g->alive = true;
     c->graphs.push_back(std::move(g));
     *graph_id = (int32_t)c->graphs.size() - 1;
@@ -613,9 +1094,19 @@ extern "C" vne_status vne_graph_register(vne_ctx *c, const vne_csr *csr, uint32_
 
 extern "C" vne_status vne_graph_release(vne_ctx *c, int32_t gid) {
     if (!c) return VNE_EINVAL;
+    c->err.clear();
     Graph *g = get_graph(c, gid);
     if (!g) return fail(c, VNE_EINVAL, "unknown graph id");
+    HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto it = c->sets.begin(); it != c->sets.end();) {
+        if (std::find(it->first.begin(), it->first.end(), gid) != it->first.end()) {
+            free_set(c, it->second.get());
+            it = c->sets.erase(it);
+        } else {
+            ++it;
+        }
+    }
     free_graph(c, g);
     return VNE_OK;
 }
@@ -640,148 +1131,45 @@ extern "C" vne_status vne_kernel_timing(vne_ctx *c, int32_t reset, int64_t *laun
     return VNE_OK;
 }
 
-static vne_status estimate_hutchpp(vne_ctx *c, Graph *g, const vne_probes *pr, int k, bool fp64, bool desing,
-                                   vne_result *out) {
-    const int nr = pr->n_sketch, m = pr->m, nh = m - nr;
-    if (nr < 1 || nh < 0 || nr > 128) return fail(c, VNE_ENOTSUP, "Hutch++ needs 1 <= n_sketch <= min(m, 128)");
-    const size_t es = fp64 ? 8 : 4;
-    Plan *sk = nullptr, *q = nullptr;
-    vne_status st = get_plan(c, g, nr, k, fp64, true, 1, &sk);
-    if (st != VNE_OK) return st;
-    st = get_plan(c, g, m, k, fp64, false, 2, &q);
-    if (st != VNE_OK) return st;
-    if (!q->B.p) {
-        auto A = [&](DevBuf *b, size_t bytes) {
-            if (st == VNE_OK) st = dev_alloc(c, b, bytes);
-        };
-        A(&q->S, (size_t)nr * k * 8);
-        A(&q->B, (size_t)g->n * m * es);
-        const int64_t gd = std::max(gram_scratch_doubles((int32_t)g->n, nr, nr),
-                                    gram_scratch_doubles((int32_t)g->n, nr, std::max(nh, 1)));
-        A(&q->gram_part, (size_t)gd * 8);
-        A(&q->gram, (size_t)nr * std::max(nr, nh) * 8);
-        A(&q->rinv, (size_t)nr * nr * 8);
-        A(&q->rot, (size_t)nr * rot_capacity(k) * kRotBytes);
-        if (st != VNE_OK) return st;
-    }
-    hipStream_t s = c->stream;
-    // 1. sketch: k Lanczos steps on Omega (kept basis), then Y = f(A) Omega by eq. (4.3)
-    ProbeSpec ps;
-    ps.gen = GEN_RADEMACHER;
-    ps.seed = pr->seed;
-    ps.col_offset = 0;
-    if ((st = run_lanczos(c, g, sk, ps, desing)) != VNE_OK) return st;
-    HIP_TRY(c, launch_fT_e1((const double *)sk->alpha.p, (const double *)sk->beta.p, (const int32_t *)sk->k_eff.p,
-                            k, nr, (double *)q->S.p, q->rot.p, (int32_t *)sk->flags.p, s));
-    const int64_t step_stride = (int64_t)g->n * sk->m_pad;
-    HIP_TRY(c, launch_reconstruct(sk->Vstore.p, fp64, step_stride, sk->m_pad, (const double *)q->S.p,
-                                  (const double *)sk->norm2.p, k, (int32_t)g->n, nr, q->B.p, m, s));
-    // 2. G block, raw +-1 in the columns after the sketch
-    if (nh > 0)
-        HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)g->n, nh, m, nr, nr, pr->seed, g->d_keys, s));
-    // 3. Q = orth(Y) by CholeskyQR (FP64 Gram and triangular factors), in
-    // place; a second pass in FP64 mode (with FP32 storage the rounding of Q
-    // itself bounds its orthogonality, so one pass suffices)
-    for (int pass = 0; pass < (fp64 ? 2 : 1); ++pass) {
-        HIP_TRY(c, launch_gram(q->B.p, m, q->B.p, m, fp64, (int32_t)g->n, nr, nr, (double *)q->gram_part.p,
-                               (double *)q->gram.p, s));
-        HIP_TRY(c, launch_cholinv((double *)q->gram.p, (double *)q->rinv.p, nr, (int32_t *)sk->flags.p, s));
-        HIP_TRY(c, launch_apply(q->B.p, m, (const double *)q->rinv.p, nr, nr, q->B.p, m, fp64, (int32_t)g->n, 0, s));
-    }
-    // 4. G~ = G - Q (Q^T G)
-    if (nh > 0) {
-        char *Gp = (char *)q->B.p + (size_t)nr * es;
-        HIP_TRY(c, launch_gram(q->B.p, m, Gp, m, fp64, (int32_t)g->n, nr, nh, (double *)q->gram_part.p,
-                               (double *)q->gram.p, s));
-        HIP_TRY(c, launch_apply(q->B.p, m, (const double *)q->gram.p, nr, nh, Gp, m, fp64, (int32_t)g->n, 1, s));
-    }
-    // 5. quadratic forms of [Q | G~] and the Hutch++ combination (3.9)
-    ProbeSpec pq;
-    pq.gen = GEN_DENSE;
-    pq.dense = q->B.p;
-    pq.ld_dense = m;
-    if ((st = run_lanczos(c, g, q, pq, desing)) != VNE_OK) return st;
-    HIP_TRY(c, launch_combine((const double *)q->psi.p, m, 2, nr, (double *)q->estimate.p, s));
-    int32_t fl_q = 0, fl_s = 0;
-    st = copy_out(c, q, out, &fl_q);
-    if (st != VNE_OK) return st;
-    HIP_TRY(c, hipMemcpy(&fl_s, sk->flags.p, 4, hipMemcpyDeviceToHost));
-    if (c->timing && (st = collect_timing(c)) != VNE_OK) return st;
-    if (fl_s & 2) return fail(c, VNE_ENUMERIC, "Cholesky of the sketch Gram matrix failed (rank-deficient sketch)");
-    if ((fl_q | fl_s) & 1) return fail(c, VNE_ENUMERIC, "non-finite Lanczos coefficient");
-    if ((fl_q | fl_s) & 4) return fail(c, VNE_ENUMERIC, "tridiagonal QR did not converge");
-    if (fl_s & 8) return fail(c, VNE_ENUMERIC, "tridiagonal QR rotation record overflowed");
-    return VNE_OK;
-}
-
 extern "C" vne_status vne_entropy_estimate(vne_ctx *c, int32_t gid, const vne_probes *pr, int32_t k,
                                            uint32_t mode, vne_result *out) {
     if (!c) return VNE_EINVAL;
     c->err.clear();
     if (!pr || !out) return fail(c, VNE_EINVAL, "NULL argument");
-    Graph *g = get_graph(c, gid);
-    if (!g) return fail(c, VNE_EINVAL, "unknown graph id");
+    if (!get_graph(c, gid)) return fail(c, VNE_EINVAL, "unknown graph id");
     if (k < 1 || k > kMaxSteps) return fail(c, VNE_EINVAL, "k_steps must be in [1, 128]");
     if (pr->m < 1) return fail(c, VNE_EINVAL, "probe count m must be >= 1");
-    if (pr->m > (1 << 20)) return fail(c, VNE_ENOTSUP, "probe count too large");
-    if (mode & ~(uint32_t)(VNE_MODE_F64 | VNE_MODE_DESING)) return fail(c, VNE_EINVAL, "unknown mode bits");
+    VNE_TRY(check_mode(c, mode));
     HIP_TRY(c, hipSetDevice(c->device));
+    GraphSet *set = nullptr;
+    VNE_TRY(get_set(c, {gid}, &set));
     const bool fp64 = (mode & VNE_MODE_F64) != 0;
     const bool desing = (mode & VNE_MODE_DESING) != 0;
-    if (desing && !g->zero_rowsum)
+    if (desing && !set->zero_rowsum)
         return fail(c, VNE_EINVAL, "VNE_MODE_DESING needs a matrix whose rows sum to zero (A 1 = 0)");
-    if (pr->kind == VNE_PROBE_HUTCHPP) return estimate_hutchpp(c, g, pr, k, fp64, desing, out);
+    if (pr->kind == VNE_PROBE_HUTCHPP) return estimate_hutchpp(c, set, pr, k, fp64, desing, out);
+    return estimate_set(c, set, pr, &k, fp64, desing, out);
+}
 
-    Plan *p = nullptr;
-    vne_status st = get_plan(c, g, pr->m, k, fp64, false, 0, &p);
-    if (st != VNE_OK) return st;
-    ProbeSpec ps;
-    int combine_kind = 0;
-    const size_t es = fp64 ? 8 : 4;
-    switch (pr->kind) {
-        case VNE_PROBE_RADEMACHER:
-            ps.gen = GEN_RADEMACHER;
-            ps.seed = pr->seed;
-            break;
-        case VNE_PROBE_COLORING: {
-            if (!pr->colors) return fail(c, VNE_EINVAL, "colors is NULL");
-            ps.gen = GEN_COLORING;
-            combine_kind = 1;
-            if (pr->location == VNE_DEVICE) {
-                ps.colors = pr->colors;
-            } else {
-                for (int64_t i = 0; i < g->n; ++i)
-                    if (pr->colors[i] < 0 || pr->colors[i] >= pr->m)
-                        return fail(c, VNE_EINVAL, "colour out of range at row " + std::to_string(i));
-                if (!p->colors.p && (st = dev_alloc(c, &p->colors, (size_t)g->n * 4)) != VNE_OK) return st;
-                HIP_TRY(c, hipMemcpyAsync(p->colors.p, pr->colors, (size_t)g->n * 4, hipMemcpyHostToDevice, c->stream));
-                ps.colors = (const int32_t *)p->colors.p;
-            }
-            break;
-        }
-        case VNE_PROBE_DENSE: {
-            if (!pr->dense) return fail(c, VNE_EINVAL, "dense is NULL");
-            ps.gen = GEN_DENSE;
-            ps.ld_dense = pr->m;
-            if (pr->location == VNE_DEVICE) {
-                ps.dense = pr->dense;
-            } else {
-                if (!p->dense.p && (st = dev_alloc(c, &p->dense, (size_t)g->n * pr->m * es)) != VNE_OK) return st;
-                HIP_TRY(c, hipMemcpyAsync(p->dense.p, pr->dense, (size_t)g->n * pr->m * es, hipMemcpyHostToDevice,
-                                          c->stream));
-                ps.dense = p->dense.p;
-            }
-            break;
-        }
-        default:
-            return fail(c, VNE_EINVAL, "unknown probe kind");
+extern "C" vne_status vne_entropy_estimate_batch(vne_ctx *c, int32_t n_queries, const int32_t *graph_ids,
+                                                 const vne_probes *probes, const int32_t *k_steps, uint32_t mode,
+                                                 vne_result *out) {
+    if (!c) return VNE_EINVAL;
+    c->err.clear();
+    if (n_queries < 1 || !graph_ids || !probes || !k_steps || !out)
+        return fail(c, VNE_EINVAL, "NULL argument or empty batch");
+    VNE_TRY(check_mode(c, mode));
+    HIP_TRY(c, hipSetDevice(c->device));
+    std::vector<int32_t> ids(graph_ids, graph_ids + n_queries);
+    for (int q = 0; q < n_queries; ++q) {
+        if (!get_graph(c, ids[q])) return fail(c, VNE_EINVAL, "unknown graph id " + std::to_string(ids[q]));
+        if (probes[q].kind == VNE_PROBE_HUTCHPP) return fail(c, VNE_ENOTSUP, "Hutch++ queries are not batched");
     }
-    if ((st = run_lanczos(c, g, p, ps, desing)) != VNE_OK) return st;
-    HIP_TRY(c, launch_combine((const double *)p->psi.p, p->m, combine_kind, 0, (double *)p->estimate.p, c->stream));
-    int32_t fl = 0;
-    if ((st = copy_out(c, p, out, &fl)) != VNE_OK) return st;
-    if (c->timing && (st = collect_timing(c)) != VNE_OK) return st;
-    if (fl & 1) return fail(c, VNE_ENUMERIC, "non-finite Lanczos coefficient");
-    if (fl & 4) return fail(c, VNE_ENUMERIC, "tridiagonal QR did not converge");
-    return VNE_OK;
+    GraphSet *set = nullptr;
+    VNE_TRY(get_set(c, ids, &set));
+    const bool fp64 = (mode & VNE_MODE_F64) != 0;
+    const bool desing = (mode & VNE_MODE_DESING) != 0;
+    if (desing && !set->zero_rowsum)
+        return fail(c, VNE_EINVAL, "VNE_MODE_DESING needs matrices whose rows sum to zero (A 1 = 0)");
+    return estimate_set(c, set, probes, k_steps, fp64, desing, out);
 }

@@ -20,7 +20,7 @@ PROBE_SEED = 9642
 def tiny():
     """ER n=2000, mean degree 8; 30 Rademacher probes, 40 steps, FP64."""
     n, e = graphs.erdos_renyi(2000, 8.0, GRAPH_SEED_TINY)
-    return dict(name="er2000_d8_hutchinson30_k40_f64", n_nodes=n, edges=e,
+    return dict(name="er2000_d8_hutchinson30_k40_f64", n_nodes=n, edges=e, graph_seed=GRAPH_SEED_TINY,
                 m=30, k=40, probe_seed=PROBE_SEED, fp64=True)
 
 
@@ -28,7 +28,7 @@ def large():
     """BA n=2e5, 3 edges per new node; Hutch++ 128 sketch + 128 Hutchinson
     Rademacher vectors (256 in one block), 60 steps, FP32 vectors."""
     n, e = graphs.barabasi_albert(200_000, 3, GRAPH_SEED_LARGE)
-    return dict(name="ba200k_m3_hutchpp256_k60_f32", n_nodes=n, edges=e,
+    return dict(name="ba200k_m3_hutchpp256_k60_f32", n_nodes=n, edges=e, graph_seed=GRAPH_SEED_LARGE,
                 n_sketch=128, n_hutch=128, k=60, probe_seed=PROBE_SEED,
                 fp64=False)
 
@@ -36,7 +36,7 @@ def large():
 def probing(n=1_000_000):
     """WS n=1e6, k=10, p=0.1; greedy distance-2 coloring, 80 steps, FP32."""
     n, e = graphs.watts_strogatz(n, 10, 0.1, GRAPH_SEED_PROBING)
-    return dict(name="ws%d_k10_p0.1_probing_d2_k80_f32" % n, n_nodes=n,
+    return dict(name="ws%d_k10_p0.1_probing_d2_k80_f32" % n, n_nodes=n, graph_seed=GRAPH_SEED_PROBING,
                 edges=e, d=2, k=80, fp64=False)
 
 
