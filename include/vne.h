@@ -21,9 +21,11 @@
  *    `location` field may live on the device (VNE_DEVICE: a pointer returned
  *    by hipMalloc or a torch tensor's data_ptr on the context's device).
  *  - Sizes are int64 element counts; index arrays are int32.
- *  - A context is used by one host thread at a time.  All device work of a
- *    context runs on its stream; every call returns only after its results
- *    are in the caller's buffers (the call synchronizes that stream).
+ *  - Calls on one context are serialised by a lock of the context.  All
+ *    device work of a context's own calls runs on its stream; every call
+ *    returns only after its results are in the caller's buffers (the call
+ *    synchronizes that stream).  A server (vne_server_*) runs on a stream and
+ *    a worker thread of its own.
  *  - Matrix layout: compressed sparse rows with sorted, unique column indices
  *    in [0, n), row_ptr[0] = 0, row_ptr[n] = nnz.  The represented matrix is
  *    A = scale * CSR.  For graph density matrices the CSR holds the exact
@@ -239,6 +241,112 @@ vne_status vne_entropy_estimate_batch(vne_ctx *ctx, int32_t n_queries, const int
 vne_status vne_enable_kernel_timing(vne_ctx *ctx, int32_t enable);
 vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, double *total_ms,
                              double *algorithmic_bytes);
+
+/* ----------------------------------------------------------------------------
+ * Serving loop (continuous batching).
+ *
+ * A server owns a worker thread, a HIP stream (default priority) and an
+ * arena of device memory for the state of running queries.  A query asks for
+ * the entropy estimate of a registered graph with Rademacher probes (eq.
+ * (3.8)).  It is split into slot tasks of at most max_cols probe columns;
+ * tasks wait in arrival order and are admitted while fewer than max_slots
+ * run and the arena has room for their vectors and coefficients (a task that
+ * does not fit waits, and the ones behind it wait too; a task larger than the
+ * whole arena fails its query with VNE_ENOMEM).  Every tick advances all
+ * running tasks by one Lanczos step, whatever their graphs, in one set of
+ * launches; a task that reaches its step count gets its Gauss quadrature and
+ * frees its slot at once, and the query's estimate is combined on the device
+ * when its last task ends.  A task's arithmetic depends only on its own graph,
+ * probes and step count, so a query's result is bitwise the same alone and
+ * among any other queries (for the same server mode).
+ *
+ * rel_eps == 0: the query gives m (<= max_probes) and k_steps (<= 128).
+ * rel_eps > 0: half of the relative error budget goes to the quadrature and
+ * half to sampling (Remarks 5.1, 5.2).  Steps: the smallest k with
+ * 2 n lambda_ub / (4 ((2k-1)^2 - 1)) <= (rel_eps / 2) S_lower (Proposition 4.4
+ * with the gamma = 0 bound of Remark 2.3, ||c||^2 <= n), where lambda_ub is
+ * the Gershgorin bound max_i sum_j |A_ij| and S_lower = -log tr(A^2) <= S(A)
+ * for a unit-trace PSD matrix (otherwise k = max_steps).  Probes: a pilot of
+ * pilot_probes columns runs first; N = ceil((z sd / ((rel_eps / 2) mean))^2)
+ * over its quadratic forms, clamped to [pilot_probes, max_probes]; the pilot's
+ * forms are kept and columns pilot_probes..N-1 follow.
+ *
+ * Thread safety: submit, poll and stats may be called from any thread.
+ * While a server runs, its context may still register graphs and run
+ * estimates (they take the context lock); a graph with queries in the server
+ * cannot be released (VNE_EBUSY).  Stop every server of a context before
+ * destroying it.  The first query on a graph builds the graph's device arrays
+ * if no estimate has done so.
+ * ------------------------------------------------------------------------- */
+
+typedef struct vne_server vne_server;
+
+typedef struct {
+    int32_t max_slots;          /* tasks running at once (0: 64) */
+    uint64_t arena_bytes;       /* device memory for running tasks (0: a quarter of free memory) */
+    int32_t max_cols;           /* probe columns per task (0: 256; at most 4096) */
+    int32_t pilot_probes;       /* pilot width (0: 16) */
+    int32_t max_probes;         /* cap on a query's probe count (0: 4096) */
+    int32_t max_steps;          /* cap on the planned step count (0: 100; at most 128) */
+    double z;                   /* standard errors of the sampling bound (0: 2.576, delta = 1e-2) */
+    uint32_t mode;              /* VNE_MODE_* bits of every query of the server */
+} vne_server_cfg;
+
+typedef struct {
+    int32_t graph_id;
+    double rel_eps;             /* > 0: probes and steps from the error rule above */
+    int32_t m;                  /* rel_eps == 0: probe count */
+    int32_t k_steps;            /* rel_eps == 0: Lanczos steps */
+    uint64_t seed;              /* probe seed; query columns are hash columns 0..N-1 */
+} vne_query;
+
+typedef struct {
+    vne_status status;          /* of the query itself */
+    char message[128];          /* "" on success */
+    double estimate;            /* eq. (3.8) over the N quadratic forms */
+    double std_error;           /* sample standard deviation of the forms / sqrt(N) */
+    double quad_bound;          /* rel_eps > 0: the a-priori per-form quadrature bound used */
+    int32_t probes, steps;      /* N and k */
+    double queue_ms;            /* submit -> first task admitted */
+    double latency_ms;          /* submit -> result ready on the host */
+} vne_query_result;
+
+typedef struct {
+    int64_t ticks, tasks, queries_done;
+    double slot_occupancy;      /* mean running tasks per tick */
+    uint64_t arena_bytes, arena_in_use, arena_peak;
+    int32_t active, pending;
+} vne_server_info;
+
+/* Start a server on ctx.  cfg is copied.  Fails with VNE_ENOMEM when the
+ * arena does not fit the context's budget or the device. */
+vne_status vne_server_start(vne_ctx *ctx, const vne_server_cfg *cfg, vne_server **out);
+
+/* Queue a query; *ticket identifies it.  VNE_EINVAL for a bad graph id or
+ * bad sizes (message in vne_last_error(ctx)); VNE_EBUSY once stop began. */
+vne_status vne_server_submit(vne_server *srv, const vne_query *query, uint64_t *ticket);
+
+/* Wait up to timeout_ms (-1: no limit, 0: do not wait) for a query.  On
+ * VNE_OK *res holds the result (res->status is the query's own status) and
+ * quad (may be NULL) receives min(N, quad_cap) quadratic forms; the ticket is
+ * then forgotten.  VNE_EBUSY: not finished yet.  VNE_EINVAL: unknown ticket. */
+vne_status vne_server_poll(vne_server *srv, uint64_t ticket, int32_t timeout_ms, vne_query_result *res,
+                           double *quad, int32_t quad_cap);
+
+vne_status vne_server_stats(vne_server *srv, vne_server_info *stats);
+
+/* Finish every queued and running query, stop the worker and free the
+ * server's memory.  srv is invalid afterwards. */
+vne_status vne_server_stop(vne_server *srv);
+
+/* The error rule of the serving loop, for callers that plan on their own:
+ * smallest k >= 2 (at most k_max) with 2 norm2 lambda_max / (4 ((2k-1)^2-1))
+ * <= share * rel_eps * s_lower; and ceil((z sigma / (share rel_eps s_hat))^2)
+ * clamped to [n_min, n_max]. */
+int32_t vne_plan_steps(double norm2, double lambda_max, double s_lower, double rel_eps, double share,
+                       int32_t k_max);
+int32_t vne_plan_probes(double s_hat, double sigma, double rel_eps, double share, double z, int32_t n_min,
+                        int32_t n_max);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,9 @@ STATUS = {0: "VNE_OK", -1: "VNE_EINVAL", -2: "VNE_ENOMEM", -3: "VNE_EDEVICE",
 EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_color_greedy",
            "vne_ctx_create", "vne_ctx_destroy", "vne_last_error", "vne_ctx_set_stream",
            "vne_ctx_memory", "vne_graph_register", "vne_graph_release", "vne_entropy_estimate",
-           "vne_entropy_estimate_batch", "vne_enable_kernel_timing", "vne_kernel_timing"]
+           "vne_entropy_estimate_batch", "vne_enable_kernel_timing", "vne_kernel_timing",
+           "vne_server_start", "vne_server_submit", "vne_server_poll", "vne_server_stats",
+           "vne_server_stop", "vne_plan_steps", "vne_plan_probes"]
 
 
 class VneError(RuntimeError):
@@ -59,6 +61,30 @@ class _Result(ctypes.Structure):
     _fields_ = [("estimate", ctypes.c_double), ("quad", ctypes.c_void_p),
                 ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p),
                 ("k_eff", ctypes.c_void_p), ("norm2", ctypes.c_void_p)]
+
+
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("arena_bytes", ctypes.c_uint64), ("max_cols", ctypes.c_int32),
+                ("pilot_probes", ctypes.c_int32), ("max_probes", ctypes.c_int32), ("max_steps", ctypes.c_int32),
+                ("z", ctypes.c_double), ("mode", ctypes.c_uint32)]
+
+
+class _Query(ctypes.Structure):
+    _fields_ = [("graph_id", ctypes.c_int32), ("rel_eps", ctypes.c_double), ("m", ctypes.c_int32),
+                ("k_steps", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class _QueryResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("message", ctypes.c_char * 128), ("estimate", ctypes.c_double),
+                ("std_error", ctypes.c_double), ("quad_bound", ctypes.c_double), ("probes", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("tasks", ctypes.c_int64), ("queries_done", ctypes.c_int64),
+                ("slot_occupancy", ctypes.c_double), ("arena_bytes", ctypes.c_uint64),
+                ("arena_in_use", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64), ("active", ctypes.c_int32),
+                ("pending", ctypes.c_int32)]
 
 
 _LIB = None
@@ -102,6 +128,20 @@ def lib():
         L.vne_entropy_estimate_batch.restype = i32
         L.vne_entropy_estimate_batch.argtypes = [vp, i32, P(i32), P(_Probes), P(i32), ctypes.c_uint32,
                                                  P(_Result)]
+        L.vne_server_start.restype = i32
+        L.vne_server_start.argtypes = [vp, P(_ServerCfg), P(vp)]
+        L.vne_server_submit.restype = i32
+        L.vne_server_submit.argtypes = [vp, P(_Query), P(u64)]
+        L.vne_server_poll.restype = i32
+        L.vne_server_poll.argtypes = [vp, u64, i32, P(_QueryResult), vp, i32]
+        L.vne_server_stats.restype = i32
+        L.vne_server_stats.argtypes = [vp, P(_ServerInfo)]
+        L.vne_server_stop.restype = i32
+        L.vne_server_stop.argtypes = [vp]
+        L.vne_plan_steps.restype = i32
+        L.vne_plan_steps.argtypes = [dbl, dbl, dbl, dbl, dbl, i32]
+        L.vne_plan_probes.restype = i32
+        L.vne_plan_probes.argtypes = [dbl, dbl, dbl, dbl, dbl, i32, i32]
         L.vne_enable_kernel_timing.restype = i32
         L.vne_enable_kernel_timing.argtypes = [vp, i32]
         L.vne_kernel_timing.restype = i32
@@ -315,3 +355,66 @@ class Context:
         self._chk(self._L.vne_kernel_timing(self._h, 1 if reset else 0, ctypes.byref(n),
                                             ctypes.byref(ms), ctypes.byref(by)))
         return dict(launches=n.value, total_ms=ms.value, bytes=by.value)
+
+
+def plan_steps(norm2, lambda_max, s_lower, rel_eps, share=0.5, k_max=100):
+    """Steps of the serving error rule (Proposition 4.4 with Remark 2.3)."""
+    return lib().vne_plan_steps(norm2, lambda_max, s_lower, rel_eps, share, k_max)
+
+
+def plan_probes(s_hat, sigma, rel_eps, share=0.5, z=2.576, n_min=16, n_max=4096):
+    """Probe count of the serving error rule."""
+    return lib().vne_plan_probes(s_hat, sigma, rel_eps, share, z, n_min, n_max)
+
+
+class Server:
+    """Serving loop on a context (continuous batching, HBM-budget admission)."""
+
+    def __init__(self, ctx, mode, arena_bytes=0, max_slots=0, max_cols=0, pilot_probes=0, max_probes=0,
+                 max_steps=0, z=0.0):
+        self._ctx = ctx
+        self._L = ctx._L
+        cfg = _ServerCfg(max_slots, arena_bytes, max_cols, pilot_probes, max_probes, max_steps, z, mode)
+        h = ctypes.c_void_p()
+        ctx._chk(self._L.vne_server_start(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.max_probes = max_probes or 4096
+
+    def submit(self, gid, rel_eps=0.0, m=0, k=0, seed=0):
+        t = ctypes.c_uint64()
+        q = _Query(gid, rel_eps, m, k, seed)
+        self._ctx._chk(self._L.vne_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket, timeout_ms=-1, want_quad=False):
+        """Result dict, or None when not finished within timeout_ms."""
+        r = _QueryResult()
+        quad = np.zeros(self.max_probes) if want_quad else None
+        st = self._L.vne_server_poll(self._h, ticket, timeout_ms, ctypes.byref(r), _ptr(quad),
+                                     self.max_probes if want_quad else 0)
+        if st == -5:
+            return None
+        if st != 0:
+            raise VneError(st, "poll of ticket %d" % ticket)
+        out = dict(status=r.status, message=r.message.decode(), estimate=r.estimate, std_error=r.std_error,
+                   quad_bound=r.quad_bound, probes=r.probes, steps=r.steps, queue_ms=r.queue_ms,
+                   latency_ms=r.latency_ms)
+        if want_quad:
+            out["quad"] = quad[:r.probes].copy()
+        return out
+
+    def stats(self):
+        i = _ServerInfo()
+        self._L.vne_server_stats(self._h, ctypes.byref(i))
+        return {k: getattr(i, k) for k, _ in _ServerInfo._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            self._L.vne_server_stop(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

@@ -9,8 +9,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvne.so")
 
-HOST_SOURCES = ["host_graph.cpp", "coloring.cpp"]
-HIP_SOURCES = ["kernels.hip", "runtime.hip"]
+HOST_SOURCES = ["host_graph.cpp", "coloring.cpp", "serve_host.cpp"]
+HIP_SOURCES = ["kernels.hip", "runtime.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -41,7 +41,9 @@ def build(verbose=True, out=None, defines=(), build_dir=None):
              ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = lib_path + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    # only the C ABI is exported
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC",
+          "-Wl,--version-script=" + os.path.join(CSRC, "libvne.map"), "-o", tmp] + objs)
     os.replace(tmp, lib_path)
     return lib_path
 

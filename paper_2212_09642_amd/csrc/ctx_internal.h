@@ -1,0 +1,137 @@
+// Context internals shared by the runtime and the serving loop (host code
+// of libvne; not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace vne {
+namespace rt {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    bool fp64 = false;
+    int G = 1;                       // graphs in the set
+    int m = 0, m_pad = 0, mt = 0, k = 0;
+    bool store = false;              // keep every v_j (Hutch++ sketch)
+    DevBuf P[2], V[2], Vstore;
+    DevBuf alpha, beta, st_alpha, st_inv, st_coup, k_eff, norm2, mean, psi, estimate, flags;
+    DevBuf partials, level2, probe_part, seg_acc, long_part, colors, dense;
+    DevBuf graph_k, graph_m, seeds;  // per graph
+    std::vector<int32_t> h_graph_k, h_graph_m;
+    // Hutch++ extras (only in the quadratic-form plan of a Hutch++ run)
+    DevBuf S, B, gram_part, gram, rinv, rot;
+    // the k-step loop captured as one HIP graph, per (schedule, tile); with
+    // kernel timing on, one graph per step part instead, so that event pairs
+    // recorded between graph launches bracket the Lanczos step kernels
+    std::map<std::pair<int, int>, hipGraphExec_t> exec;
+    std::map<std::pair<int, int>, std::vector<hipGraphExec_t>> part_exec;
+    std::vector<hipEvent_t> ev;      // 2k events
+};
+
+struct Graph {
+    int64_t n = 0, nnz = 0;
+    double scale = 1.0;
+    std::vector<int32_t> h_row_ptr, h_col;   // host copies (schedules, stacking)
+    std::vector<double> h_val;
+    std::vector<int64_t> h_keys;
+    DevBuf row_ptr, col;                     // owned device copies (host input)
+    const int32_t *d_row_ptr = nullptr, *d_col = nullptr;
+    Schedule sched;
+    bool alive = false;
+    bool zero_rowsum = false;                // A 1 = 0 exactly
+    // spectral facts of A = scale * CSR for the serving error rule
+    double lambda_ub = 0.0;                  // max_i sum_j |A_ij| >= lambda_max (Gershgorin)
+    double fro2 = 0.0;                       // ||A||_F^2 = tr(A^2) for symmetric A
+    double trace = 0.0;
+    int in_use = 0;                          // queries of a running server on this graph
+};
+
+// Graphs stacked as one block-diagonal matrix: rows, entries, work blocks and
+// probe blocks of graph q follow those of graphs 0..q-1.  A set of one graph
+// uses the graph's own row_ptr / col_idx.
+struct GraphSet {
+    std::vector<int32_t> ids;
+    int G = 1;
+    int64_t n = 0, nnz = 0;
+    double scale = 1.0;
+    bool zero_rowsum = true;
+    const int32_t *d_row_ptr = nullptr, *d_col = nullptr;
+    DevBuf row_ptr, col, val32, val64, keys;
+    DevBuf row_graph, long_graph, block_graph, graph_block_begin, graph_long_begin, graph_scale;
+    DevBuf segs, block_ranges, long_first, long_nseg;
+    DevBuf probe_rows, probe_block_graph, probe_graph_begin, graph_row_begin;
+    Schedule sched;
+    std::vector<int64_t> h_row_begin;                      // [G+1]
+    int probe_blocks = 0;
+    uint64_t last_use = 0;
+    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Plan>> plans;
+};
+
+}  // namespace rt
+}  // namespace vne
+
+struct vne_ctx {
+    using Graph = vne::rt::Graph;
+    using GraphSet = vne::rt::GraphSet;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;    // used when the caller gives no stream
+    uint64_t budget = 0, used = 0;
+    std::string err;
+    std::vector<std::unique_ptr<Graph>> graphs;
+    std::map<std::vector<int32_t>, std::unique_ptr<GraphSet>> sets;
+    uint64_t tick = 0;                   // set use counter (eviction order)
+    bool timing = false;
+    int64_t t_launches = 0;
+    double t_ms = 0.0, t_bytes = 0.0;
+    struct Pending {
+        void *plan;
+        double bytes;
+    };
+    std::vector<Pending> pending;        // timed step loops not yet collected
+    std::map<std::string, int> tuned;    // autotuner: set signature -> column tile
+    std::string tune_file;
+    // serialises the registry (register, release, estimates) against the
+    // worker thread of a server running on this context
+    std::recursive_mutex mu;
+};
+
+namespace vne {
+namespace rt {
+
+#define HIP_TRY(ctx, expr)                                           \
+    do {                                                             \
+        hipError_t _e = (expr);                                      \
+        if (_e != hipSuccess) return hip_fail((ctx), _e, #expr);     \
+    } while (0)
+
+#define VNE_TRY(expr)                       \
+    do {                                    \
+        vne_status _s = (expr);             \
+        if (_s != VNE_OK) return _s;        \
+    } while (0)
+
+vne_status fail(vne_ctx *c, vne_status st, const std::string &m);
+vne_status hip_fail(vne_ctx *c, hipError_t e, const char *what);
+vne_status dev_alloc(vne_ctx *c, DevBuf *b, size_t bytes);
+void dev_free(vne_ctx *c, DevBuf *b);
+int env_int(const char *name, int dflt);
+Graph *get_graph(vne_ctx *c, int32_t gid);
+// the device arrays of one graph (a set of one), built on first use
+vne_status get_set(vne_ctx *c, const std::vector<int32_t> &ids, GraphSet **out);
+
+}  // namespace rt
+}  // namespace vne

@@ -92,6 +92,19 @@ int pad_columns(int m, int mt);
 hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 
+// Several independent problems ("slots") per launch, two-pass schedule, one
+// column tile mt for all of them.  args: device array of per-slot StepArgs
+// (graph fields unused: one matrix per slot).  step_map entries {slot, work
+// block, tile, 0} cover every block (padding blocks included) and tile of
+// each slot; long_map entries {slot, group, tile, 0} cover the long rows in
+// groups of long_rows_per_group(mt, fp64).  The first step of a slot needs
+// its v_{j-1} buffer zeroed.  Then, per slot, launch_finalize_slots with
+// map entries {slot, column chunk of 256}.
+hipError_t launch_step_slots(const StepArgs *args, const int4 *step_map, int32_t n_step, const int4 *long_map,
+                             int32_t n_long, int32_t mt, bool fp64, hipStream_t s);
+int long_rows_per_group(int mt, bool fp64);
+hipError_t launch_finalize_slots(const FinalizeArgs *fargs, const int2 *map, int32_t n_entries, hipStream_t s);
+
 // probe block: sums, centring, norms; P_1 written with element type of the mode
 struct ProbeArgs {
     int32_t gen;                // ProbeGen

@@ -271,20 +271,15 @@ __global__ void __launch_bounds__(256) k_normalize(StepArgs a) {
     }
 }
 
+// One work block b of the schedule, column tile `tile`: its segments, then
+// its rows, and the block's partial sums (red: shared scratch of the block).
 template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
-__global__ void __launch_bounds__(kStepThreads) k_lanczos_step(StepArgs a) {
+__device__ __forceinline__ void step_block(const StepArgs &a, int b, int tile,
+                                           double (*red)[(kStepThreads / 64) * (64 / LPR) * CPL * LPR]) {
     using Core = StepCore<T, CPL, LPR, FIRST, TWO>;
     constexpr int MT = Core::MT;
     constexpr int GPW = 64 / LPR;                    // lane groups per wave
     constexpr int NG = (kStepThreads / 64) * GPW;    // lane groups per block
-    __shared__ double red[3][NG * MT];
-
-    // column tiles are dispatched one after the other (tile-major grid), so
-    // the gathered block of one tile stays resident in the last-level cache;
-    // within a tile each XCD takes one contiguous range of row blocks
-    // (n_blocks is a multiple of 8)
-    const int tile = blockIdx.y;
-    const int b = xcd_remap(blockIdx.x, a.n_blocks);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int grp = lane / LPR;
@@ -363,18 +358,72 @@ __global__ void __launch_bounds__(kStepThreads) k_lanczos_step(StepArgs a) {
     }
 }
 
+template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
+__global__ void __launch_bounds__(kStepThreads) k_lanczos_step(StepArgs a) {
+    constexpr int NG = (kStepThreads / 64) * (64 / LPR);
+    __shared__ double red[3][NG * CPL * LPR];
+    // column tiles are dispatched one after the other (tile-major grid), so
+    // the gathered block of one tile stays resident in the last-level cache;
+    // within a tile each XCD takes one contiguous range of row blocks
+    // (n_blocks is a multiple of 8)
+    step_block<T, CPL, LPR, FIRST, TWO>(a, xcd_remap(blockIdx.x, a.n_blocks), blockIdx.y, red);
+}
+
+// Several independent problems ("slots") in one launch: entry e = {slot,
+// work block, column tile} of map runs block e.y, tile e.z of slot e.x, whose
+// matrix, vectors and state args[e.x] describes.  Two-pass schedule; the
+// first step of a slot runs as a later step whose v_{j-1} is zero and whose
+// alpha_{j-1}, beta_{j-1} are zero, which gives the same values.
+template <typename T, int CPL, int LPR>
+__global__ void __launch_bounds__(kStepThreads) k_lanczos_step_slots(const StepArgs *args, const int4 *map,
+                                                                     int32_t n_entries) {
+    constexpr int NG = (kStepThreads / 64) * (64 / LPR);
+    __shared__ double red[3][NG * CPL * LPR];
+    const int4 e = map[xcd_remap(blockIdx.x, n_entries)];
+    const StepArgs a = args[e.x];
+    step_block<T, CPL, LPR, false, true>(a, e.y, e.z, red);
+}
+
+// Normalize pass of the slots: entry {slot, work block, tile} writes v_j on
+// the block's row range, tile columns.
+template <typename T, int CPL, int LPR>
+__global__ void __launch_bounds__(256) k_normalize_slots(const StepArgs *args, const int4 *map, int32_t n_entries) {
+    constexpr int MT = CPL * LPR;
+    constexpr int RP = 256 / LPR;                    // rows per pass
+    const int4 e = map[xcd_remap(blockIdx.x, n_entries)];
+    const StepArgs a = args[e.x];
+    const int4 rg = a.block_ranges[e.y];
+    const int c0 = e.z * MT + (int)(threadIdx.x % LPR) * CPL;
+    const T *P = static_cast<const T *>(a.P_in);
+    const T *Vp = static_cast<const T *>(a.V_prev);
+    T *Vo = static_cast<T *>(a.V_out);
+    T al[CPL], inv[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        al[k] = (T)a.st_alpha[c0 + k];
+        inv[k] = (T)a.st_inv[c0 + k];
+    }
+    for (int64_t i = rg.z + (int)(threadIdx.x / LPR); i < rg.w; i += RP) {
+        T pv[CPL], qv[CPL], v[CPL];
+        load_s<kNT, T, CPL>(P + i * a.m_pad + c0, pv);
+        load_s<kNT, T, CPL>(Vp + i * a.m_pad + c0, qv);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) v[k] = materialize(pv[k], qv[k], al[k], inv[k]);
+        store_vec<T, CPL>(Vo + i * a.m_pad + c0, v);
+    }
+}
+
 // Long rows: add the segment partial products in segment order and finish
 // the row; its dot-product contributions go to a slot of its own.
 template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
-__global__ void __launch_bounds__(256) k_long_rows(StepArgs a) {
+__device__ __forceinline__ void long_rows_group(const StepArgs &a, int group, int tile) {
     using Core = StepCore<T, CPL, LPR, FIRST, TWO>;
     constexpr int GPW = 64 / LPR;
     constexpr int NG = 4 * GPW;
-    const int tile = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int grp = lane / LPR;
     const int gl = lane % LPR;
-    const int L = blockIdx.x * NG + (threadIdx.x >> 6) * GPW + grp;
+    const int L = group * NG + (threadIdx.x >> 6) * GPW + grp;
     if (L >= a.n_long) return;
     const Core core(a, tile, gl, a.long_graph ? a.long_graph[L] : 0);
     const int first = a.long_first[L], nseg = a.long_nseg[L];
@@ -413,6 +462,19 @@ __global__ void __launch_bounds__(256) k_long_rows(StepArgs a) {
         lp[core.ld + k] = dww[k];
         lp[2 * core.ld + k] = dvv[k];
     }
+}
+
+template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
+__global__ void __launch_bounds__(256) k_long_rows(StepArgs a) {
+    long_rows_group<T, CPL, LPR, FIRST, TWO>(a, blockIdx.x, blockIdx.y);
+}
+
+// entry {slot, group of long rows, tile}
+template <typename T, int CPL, int LPR>
+__global__ void __launch_bounds__(256) k_long_rows_slots(const StepArgs *args, const int4 *map) {
+    const int4 e = map[blockIdx.x];
+    const StepArgs a = args[e.x];
+    long_rows_group<T, CPL, LPR, false, true>(a, e.y, e.z);
 }
 
 int choose_tile(int m, bool fp64, int requested) {
@@ -455,6 +517,42 @@ static hipError_t launch_step_t(const StepArgs &a, bool first, hipStream_t s) {
         else launch_step_k<T, CPL, LPR, false, false>(a, s);
     }
     return hipGetLastError();
+}
+
+template <typename T, int CPL, int LPR>
+static hipError_t launch_slots_t(const StepArgs *args, const int4 *step_map, int32_t n_step,
+                                 const int4 *long_map, int32_t n_long, hipStream_t s) {
+    if (n_step > 0) {
+        hipLaunchKernelGGL((k_normalize_slots<T, CPL, LPR>), dim3(n_step), dim3(256), 0, s, args, step_map, n_step);
+        hipLaunchKernelGGL((k_lanczos_step_slots<T, CPL, LPR>), dim3(n_step), dim3(kStepThreads), 0, s, args,
+                           step_map, n_step);
+    }
+    if (n_long > 0) hipLaunchKernelGGL((k_long_rows_slots<T, CPL, LPR>), dim3(n_long), dim3(256), 0, s, args, long_map);
+    return hipGetLastError();
+}
+
+int long_rows_per_group(int mt, bool fp64) { return 4 * (64 / (mt / (fp64 ? 2 : 4))); }
+
+hipError_t launch_step_slots(const StepArgs *args, const int4 *step_map, int32_t n_step, const int4 *long_map,
+                             int32_t n_long, int32_t mt, bool fp64, hipStream_t s) {
+    if (!fp64) {
+        switch (mt) {
+            case 16: return launch_slots_t<float, 4, 4>(args, step_map, n_step, long_map, n_long, s);
+            case 32: return launch_slots_t<float, 4, 8>(args, step_map, n_step, long_map, n_long, s);
+            case 64: return launch_slots_t<float, 4, 16>(args, step_map, n_step, long_map, n_long, s);
+            case 128: return launch_slots_t<float, 4, 32>(args, step_map, n_step, long_map, n_long, s);
+            case 256: return launch_slots_t<float, 4, 64>(args, step_map, n_step, long_map, n_long, s);
+        }
+    } else {
+        switch (mt) {
+            case 8: return launch_slots_t<double, 2, 4>(args, step_map, n_step, long_map, n_long, s);
+            case 16: return launch_slots_t<double, 2, 8>(args, step_map, n_step, long_map, n_long, s);
+            case 32: return launch_slots_t<double, 2, 16>(args, step_map, n_step, long_map, n_long, s);
+            case 64: return launch_slots_t<double, 2, 32>(args, step_map, n_step, long_map, n_long, s);
+            case 128: return launch_slots_t<double, 2, 64>(args, step_map, n_step, long_map, n_long, s);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s) {
@@ -612,6 +710,34 @@ __global__ void __launch_bounds__(256) k_finalize_graphs(FinalizeArgs a) {
         svv += p[2 * a.m_pad];
     }
     update_coefficients(a, g, c, svw, sww, svv);
+}
+
+// Slots: thread (slot e.x, column e.y * 256 + tid) adds the slot's block
+// partials, then its long rows, in order, and updates.
+__global__ void __launch_bounds__(256) k_finalize_slots(const FinalizeArgs *fargs, const int2 *map) {
+    const int2 e = map[blockIdx.x];
+    const FinalizeArgs a = fargs[e.x];
+    const int c = e.y * 256 + threadIdx.x;
+    if (c >= a.m_pad) return;
+    double svw = 0.0, sww = 0.0, svv = 0.0;
+    for (int bb = 0; bb < a.n_blocks; ++bb) {
+        const double *p = a.partials + (int64_t)bb * 3 * a.m_pad + c;
+        svw += p[0];
+        sww += p[a.m_pad];
+        svv += p[2 * a.m_pad];
+    }
+    for (int L = 0; L < a.n_long; ++L) {
+        const double *p = a.long_part + (int64_t)L * 3 * a.m_pad + c;
+        svw += p[0];
+        sww += p[a.m_pad];
+        svv += p[2 * a.m_pad];
+    }
+    update_coefficients(a, 0, c, svw, sww, svv);
+}
+
+hipError_t launch_finalize_slots(const FinalizeArgs *fargs, const int2 *map, int32_t n_entries, hipStream_t s) {
+    if (n_entries > 0) hipLaunchKernelGGL(k_finalize_slots, dim3(n_entries), dim3(256), 0, s, fargs, map);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {

@@ -16,6 +16,7 @@
 #include <tuple>
 #include <vector>
 
+#include "ctx_internal.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -25,89 +26,10 @@ namespace {
 
 std::string g_create_error;
 
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-struct Plan {
-    bool fp64 = false;
-    int G = 1;                       // graphs in the set
-    int m = 0, m_pad = 0, mt = 0, k = 0;
-    bool store = false;              // keep every v_j (Hutch++ sketch)
-    DevBuf P[2], V[2], Vstore;
-    DevBuf alpha, beta, st_alpha, st_inv, st_coup, k_eff, norm2, mean, psi, estimate, flags;
-    DevBuf partials, level2, probe_part, seg_acc, long_part, colors, dense;
-    DevBuf graph_k, graph_m, seeds;  // per graph
-    std::vector<int32_t> h_graph_k, h_graph_m;
-    // Hutch++ extras (only in the quadratic-form plan of a Hutch++ run)
-    DevBuf S, B, gram_part, gram, rinv, rot;
-    // the k-step loop captured as one HIP graph, per (schedule, tile); with
-    // kernel timing on, one graph per step part instead, so that event pairs
-    // recorded between graph launches bracket the Lanczos step kernels
-    std::map<std::pair<int, int>, hipGraphExec_t> exec;
-    std::map<std::pair<int, int>, std::vector<hipGraphExec_t>> part_exec;
-    std::vector<hipEvent_t> ev;      // 2k events
-};
-
-struct Graph {
-    int64_t n = 0, nnz = 0;
-    double scale = 1.0;
-    std::vector<int32_t> h_row_ptr, h_col;   // host copies (schedules, stacking)
-    std::vector<double> h_val;
-    std::vector<int64_t> h_keys;
-    DevBuf row_ptr, col;                     // owned device copies (host input)
-    const int32_t *d_row_ptr = nullptr, *d_col = nullptr;
-    Schedule sched;
-    bool alive = false;
-    bool zero_rowsum = false;                // A 1 = 0 exactly
-};
-
-// Graphs stacked as one block-diagonal matrix: rows, entries, work blocks and
-// probe blocks of graph q follow those of graphs 0..q-1.  A set of one graph
-// uses the graph's own row_ptr / col_idx.
-struct GraphSet {
-    std::vector<int32_t> ids;
-    int G = 1;
-    int64_t n = 0, nnz = 0;
-    double scale = 1.0;
-    bool zero_rowsum = true;
-    const int32_t *d_row_ptr = nullptr, *d_col = nullptr;
-    DevBuf row_ptr, col, val32, val64, keys;
-    DevBuf row_graph, long_graph, block_graph, graph_block_begin, graph_long_begin, graph_scale;
-    DevBuf segs, block_ranges, long_first, long_nseg;
-    DevBuf probe_rows, probe_block_graph, probe_graph_begin, graph_row_begin;
-    Schedule sched;
-    std::vector<int64_t> h_row_begin;                      // [G+1]
-    int probe_blocks = 0;
-    uint64_t last_use = 0;
-    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Plan>> plans;
-};
-
 }  // namespace
 
-struct vne_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    hipStream_t own_stream = nullptr;    // used when the caller gives no stream
-    uint64_t budget = 0, used = 0;
-    std::string err;
-    std::vector<std::unique_ptr<Graph>> graphs;
-    std::map<std::vector<int32_t>, std::unique_ptr<GraphSet>> sets;
-    uint64_t tick = 0;                   // set use counter (eviction order)
-    bool timing = false;
-    int64_t t_launches = 0;
-    double t_ms = 0.0, t_bytes = 0.0;
-    struct Pending {
-        void *plan;
-        double bytes;
-    };
-    std::vector<Pending> pending;        // timed step loops not yet collected
-    std::map<std::string, int> tuned;    // autotuner: set signature -> column tile
-    std::string tune_file;
-};
-
-namespace {
+namespace vne {
+namespace rt {
 
 vne_status fail(vne_ctx *c, vne_status st, const std::string &m) {
     c->err = m;
@@ -118,18 +40,6 @@ vne_status hip_fail(vne_ctx *c, hipError_t e, const char *what) {
     c->err = std::string(what) + ": " + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? VNE_ENOMEM : VNE_EDEVICE;
 }
-
-#define HIP_TRY(ctx, expr)                                           \
-    do {                                                             \
-        hipError_t _e = (expr);                                      \
-        if (_e != hipSuccess) return hip_fail((ctx), _e, #expr);     \
-    } while (0)
-
-#define VNE_TRY(expr)                       \
-    do {                                    \
-        vne_status _s = (expr);             \
-        if (_s != VNE_OK) return _s;        \
-    } while (0)
 
 vne_status dev_alloc(vne_ctx *c, DevBuf *b, size_t bytes) {
     if (bytes == 0) bytes = 256;
@@ -938,7 +848,10 @@ vne_status check_mode(vne_ctx *c, uint32_t mode) {
     return VNE_OK;
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace vne
+
+using namespace vne::rt;
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -1020,6 +933,7 @@ extern "C" vne_status vne_ctx_memory(const vne_ctx *c, uint64_t *bytes) {
 
 extern "C" vne_status vne_graph_register(vne_ctx *c, const vne_csr *csr, uint32_t flags, int32_t *graph_id) {
     if (!c) return VNE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lock(c->mu);
     c->err.clear();
     if (!csr || !graph_id) return fail(c, VNE_EINVAL, "NULL argument");
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1061,11 +975,22 @@ extern "C" vne_status vne_graph_register(vne_ctx *c, const vne_csr *csr, uint32_
     for (int64_t p = 0; p < nnz; ++p)
         g->h_val[p] = csr->value_dtype == VNE_F64 ? ((const double *)hv.values)[p] : (double)((const float *)hv.values)[p];
     g->zero_rowsum = true;
-    for (int64_t i = 0; i < n && g->zero_rowsum; ++i) {
-        double rs = 0.0;
-        for (int32_t q = g->h_row_ptr[i]; q < g->h_row_ptr[i + 1]; ++q) rs += g->h_val[q];
-        g->zero_rowsum = rs == 0.0;
+    double amax = 0.0, fro2 = 0.0, tr = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double rs = 0.0, ra = 0.0;
+        for (int32_t q = g->h_row_ptr[i]; q < g->h_row_ptr[i + 1]; ++q) {
+            const double v = g->h_val[q];
+            rs += v;
+            ra += std::fabs(v);
+            fro2 += v * v;
+            if (g->h_col[q] == i) tr += v;
+        }
+        g->zero_rowsum = g->zero_rowsum && rs == 0.0;
+        amax = std::max(amax, ra);
     }
+    g->lambda_ub = std::fabs(g->scale) * amax;
+    g->fro2 = g->scale * g->scale * fro2;
+    g->trace = g->scale * tr;
     g->h_keys.resize(n);
     for (int64_t i = 0; i < n; ++i) g->h_keys[i] = csr->node_keys ? csr->node_keys[i] : i;
     if (csr->location == VNE_DEVICE) {
@@ -1094,9 +1019,11 @@ extern "C" vne_status vne_graph_register(vne_ctx *c, const vne_csr *csr, uint32_
 
 extern "C" vne_status vne_graph_release(vne_ctx *c, int32_t gid) {
     if (!c) return VNE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lock(c->mu);
     c->err.clear();
     Graph *g = get_graph(c, gid);
     if (!g) return fail(c, VNE_EINVAL, "unknown graph id");
+    if (g->in_use > 0) return fail(c, VNE_EBUSY, "graph has queries in a running server");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (auto it = c->sets.begin(); it != c->sets.end();) {
@@ -1134,6 +1061,7 @@ extern "C" vne_status vne_kernel_timing(vne_ctx *c, int32_t reset, int64_t *laun
 extern "C" vne_status vne_entropy_estimate(vne_ctx *c, int32_t gid, const vne_probes *pr, int32_t k,
                                            uint32_t mode, vne_result *out) {
     if (!c) return VNE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lock(c->mu);
     c->err.clear();
     if (!pr || !out) return fail(c, VNE_EINVAL, "NULL argument");
     if (!get_graph(c, gid)) return fail(c, VNE_EINVAL, "unknown graph id");
@@ -1155,6 +1083,7 @@ extern "C" vne_status vne_entropy_estimate_batch(vne_ctx *c, int32_t n_queries, 
                                                  const vne_probes *probes, const int32_t *k_steps, uint32_t mode,
                                                  vne_result *out) {
     if (!c) return VNE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lock(c->mu);
     c->err.clear();
     if (n_queries < 1 || !graph_ids || !probes || !k_steps || !out)
         return fail(c, VNE_EINVAL, "NULL argument or empty batch");
