@@ -98,11 +98,15 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 // block, tile, 0} cover every block (padding blocks included) and tile of
 // each slot; long_map entries {slot, group, tile, 0} cover the long rows in
 // groups of long_rows_per_group(mt, fp64).  The first step of a slot needs
-// its v_{j-1} buffer zeroed.  Then, per slot, launch_finalize_slots with
-// map entries {slot, column chunk of 256}.
+// its v_{j-1} buffer zeroed.  Then launch_finalize_slots with map entries
+// {slot, column chunk of kFinalizeCols}; each slot's FinalizeArgs carries
+// n_level2 = kSlotLevel2 and a level2 scratch of kSlotLevel2 * 3 * m_pad
+// doubles.
 hipError_t launch_step_slots(const StepArgs *args, const int4 *step_map, int32_t n_step, const int4 *long_map,
                              int32_t n_long, int32_t mt, bool fp64, hipStream_t s);
 int long_rows_per_group(int mt, bool fp64);
+constexpr int kFinalizeCols = 16;
+constexpr int kSlotLevel2 = 16;   // first-level parts of a slot's reduction (FinalizeArgs.n_level2)
 hipError_t launch_finalize_slots(const FinalizeArgs *fargs, const int2 *map, int32_t n_entries, hipStream_t s);
 
 // probe block: sums, centring, norms; P_1 written with element type of the mode

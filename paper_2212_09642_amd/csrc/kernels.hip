@@ -86,6 +86,25 @@ __device__ __forceinline__ void store_s(T *p, const T (&in)[N]) {
 #endif
 constexpr bool kNT = VNE_STREAM_NT != 0;
 
+// entries of a CSR row whose gathers are issued together: 16 when a row's
+// lane group is wide (16 or more lanes, so few rows share a wave and each
+// needs more loads in flight), else 8 (measured); VNE_GATHER_U forces one
+#ifndef VNE_GATHER_U
+#define VNE_GATHER_U 0
+#endif
+template <int LPR>
+constexpr int gather_batch() { return VNE_GATHER_U > 0 ? VNE_GATHER_U : (LPR >= 16 ? 16 : 8); }
+
+// minimum waves per SIMD requested for the step kernels (0: compiler's choice)
+#ifndef VNE_STEP_WAVES
+#define VNE_STEP_WAVES 0
+#endif
+#if VNE_STEP_WAVES > 0
+#define VNE_STEP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(VNE_STEP_WAVES)))
+#else
+#define VNE_STEP_OCCUPANCY
+#endif
+
 // Lazily normalised Lanczos vector: v_j = (P_j - alpha_{j-1} v_{j-1}) / beta_{j-1},
 // evaluated identically wherever an entry of v_j is needed.
 __device__ __forceinline__ float materialize(float p, float vp, float a, float inv) {
@@ -181,41 +200,64 @@ struct StepCore {
         }
     }
 
-    // acc = sum over entries p in [p0, p1) of val[p] * v_j[col[p], cols], in
-    // batches of U entries whose loads are all in flight together; batch
-    // slots past the end point at the row itself with a zero weight
-    __device__ __forceinline__ void gather(int row, int p0, int p1, double (&acc)[CPL]) const {
-        constexpr int U = 8;
+    static constexpr int U = gather_batch<LPR>();
+
+    // column indices and weights of entries [p, p + UB) of a row; slots past
+    // p1 point at the row itself with a zero weight
+    template <int UB>
+    __device__ __forceinline__ void batch_index(int row, int p, int p1, int (&jj)[UB], T (&vv)[UB]) const {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
-        for (int p = p0; p < p1; p += U) {
-            int jj[U];
-            T vv[U];
+        for (int u = 0; u < UB; ++u) {
+            const bool ok = p + u < p1;
+            jj[u] = ok ? a.col[p + u] : row;
+            vv[u] = ok ? val[p + u] : (T)0;
+        }
+    }
+
+    // the gathered entries of v_j (lazy: P_j and v_{j-1}) of a batch
+    template <int UB>
+    __device__ __forceinline__ void batch_load(const int (&jj)[UB], T (&pv)[UB][CPL], T (&qv)[UB][CPL]) const {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = p + u < p1;
-                jj[u] = ok ? a.col[p + u] : row;
-                vv[u] = ok ? val[p + u] : (T)0;
-            }
-            T pv[U][CPL], qv[U][CPL];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (TWO) {
-                    load_vec<T, CPL>(V_cur + (int64_t)jj[u] * ld + c0, pv[u]);
-                } else {
-                    load_vec<T, CPL>(P_in + (int64_t)jj[u] * ld + c0, pv[u]);
-                    if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)jj[u] * ld + c0, qv[u]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-#pragma unroll
-                for (int k = 0; k < CPL; ++k) {
-                    const T v = TWO ? pv[u][k] : materialize(pv[u][k], FIRST ? (T)0 : qv[u][k], al[k], inv[k]);
-                    acc[k] = fma((double)vv[u], (double)v, acc[k]);
-                }
+        for (int u = 0; u < UB; ++u) {
+            if (TWO) {
+                load_vec<T, CPL>(V_cur + (int64_t)jj[u] * ld + c0, pv[u]);
+            } else {
+                load_vec<T, CPL>(P_in + (int64_t)jj[u] * ld + c0, pv[u]);
+                if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)jj[u] * ld + c0, qv[u]);
             }
         }
+    }
+
+    template <int UB>
+    __device__ __forceinline__ void batch_acc(const T (&vv)[UB], const T (&pv)[UB][CPL], const T (&qv)[UB][CPL],
+                                              double (&acc)[CPL]) const {
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                const T v = TWO ? pv[u][k] : materialize(pv[u][k], FIRST ? (T)0 : qv[u][k], al[k], inv[k]);
+                acc[k] = fma((double)vv[u], (double)v, acc[k]);
+            }
+        }
+    }
+
+    // acc += sum over entries p in [p0, p1) of val[p] * v_j[col[p], cols],
+    // in batches of UB entries whose loads are all in flight together
+    template <int UB = U>
+    __device__ __forceinline__ void gather_from(int row, int p0, int p1, double (&acc)[CPL]) const {
+        for (int p = p0; p < p1; p += UB) {
+            int jj[UB];
+            T vv[UB], pv[UB][CPL], qv[UB][CPL];
+            batch_index<UB>(row, p, p1, jj, vv);
+            batch_load<UB>(jj, pv, qv);
+            batch_acc<UB>(vv, pv, qv, acc);
+        }
+    }
+
+    __device__ __forceinline__ void gather(int row, int p0, int p1, double (&acc)[CPL]) const {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
+        gather_from(row, p0, p1, acc);
     }
 
     // the row's own entries: pv = P_j (lazy) or v_j (two-pass), qv = v_{j-1}
@@ -288,64 +330,106 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int b, int tile,
     const int g = a.block_graph ? a.block_graph[b] : 0;
     const Core core(a, tile, gl, g);
 
-    double s_vw[CPL], s_ww[CPL], s_vv[CPL];
+    // the lane group's running sums of v.w, w.w, v.v live in its own slots
+    // of red (fixed order within the group)
+    double *my0 = &red[0][gid * MT + gl * CPL];
+    double *my1 = &red[1][gid * MT + gl * CPL];
+    double *my2 = &red[2][gid * MT + gl * CPL];
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) s_vw[k] = s_ww[k] = s_vv[k] = 0.0;
+    for (int k = 0; k < CPL; ++k) my0[k] = my1[k] = my2[k] = 0.0;
 
-    // the block's segments, then its rows
+    // the block's items: its segments, then its rows.  Software pipeline
+    // over the items of a lane group: while the gathers of item t are in
+    // flight, the first column/weight batch of item t + NG and the location
+    // (row_ptr or segment record) of item t + 2 NG are loaded.
     const int4 rg = a.block_ranges[b];
     const int n_sb = rg.y - rg.x;
     const int total = n_sb + (rg.w - rg.z);
-    for (int t = gid; t < total; t += NG) {
-        int row, p0, p1, it = 0;
-        const bool seg = t < n_sb;
-        if (seg) {
-            it = rg.x + t;
-            const SegItem s = a.segs[it];
-            row = s.row;
-            p0 = s.p0;
-            p1 = s.p1;
-        } else {
-            row = rg.z + (t - n_sb);
-            p0 = a.row_ptr[row];
-            p1 = a.row_ptr[row + 1];
-            if (p1 - p0 > a.seg_len) continue;      // long row: done by its segments
-        }
-        if (LPR == 64) {
-            row = __builtin_amdgcn_readfirstlane(row);
-            p0 = __builtin_amdgcn_readfirstlane(p0);
-            p1 = __builtin_amdgcn_readfirstlane(p1);
-        }
-        double acc[CPL];
-        if (!seg) {
-            T pv[CPL], qv[CPL];
-            core.load_self(row, pv, qv);
-            core.gather(row, p0, p1, acc);
-            double dvw[CPL], dww[CPL], dvv[CPL];
-            core.finish(row, pv, qv, acc, dvw, dww, dvv);
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                s_vw[k] += dvw[k];
-                s_ww[k] += dww[k];
-                s_vv[k] += dvv[k];
+    constexpr int U = Core::U;
+    struct Item {
+        int row, p0, p1, it;
+        bool seg;
+    };
+    auto locate = [&](int t) {
+        Item x{0, 0, 0, 0, false};
+        if (t < total) {
+            x.seg = t < n_sb;
+            if (x.seg) {
+                x.it = rg.x + t;
+                const SegItem sg = a.segs[x.it];
+                x.row = sg.row;
+                x.p0 = sg.p0;
+                x.p1 = sg.p1;
+            } else {
+                x.row = rg.z + (t - n_sb);
+                x.p0 = a.row_ptr[x.row];
+                x.p1 = a.row_ptr[x.row + 1];
             }
-        } else {
-            // segment of a long row: its partial product is finished by
-            // k_long_rows after this kernel (the kernel boundary orders it)
-            core.gather(row, p0, p1, acc);
-            double *dst = a.seg_acc + (int64_t)it * core.ld + core.c0;
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) dst[k] = acc[k];
         }
+        return x;
+    };
+    // a long row is done by its segments: no entries here, no result
+    auto settle = [&](Item &x, bool &skip, int t) {
+        skip = t >= total || (!x.seg && x.p1 - x.p0 > a.seg_len);
+        if (skip) x.p1 = x.p0;
+        if (LPR == 64) {
+            x.row = __builtin_amdgcn_readfirstlane(x.row);
+            x.p0 = __builtin_amdgcn_readfirstlane(x.p0);
+            x.p1 = __builtin_amdgcn_readfirstlane(x.p1);
+        }
+    };
+    Item cur = locate(gid);
+    bool cur_skip;
+    settle(cur, cur_skip, gid);
+    int jj[U];
+    T vv[U];
+    core.template batch_index<U>(cur.row, cur.p0, cur.p1, jj, vv);
+    Item nxt = locate(gid + NG);
+    for (int t = gid; t < total; t += NG) {
+        T pv[U][CPL], qv[U][CPL];
+        core.template batch_load<U>(jj, pv, qv);
+        T sp[CPL], sq[CPL];
+        if (!cur.seg) core.load_self(cur.row, sp, sq);
+        bool nxt_skip;
+        settle(nxt, nxt_skip, t + NG);
+        int njj[U];
+        T nvv[U];
+        core.template batch_index<U>(nxt.row, nxt.p0, nxt.p1, njj, nvv);
+        const Item nn = locate(t + 2 * NG);
+        double acc[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
+        core.template batch_acc<U>(vv, pv, qv, acc);
+        if (cur.p1 - cur.p0 > U) core.template gather_from<(U > 1 ? U / 2 : 1)>(cur.row, cur.p0 + U, cur.p1, acc);
+        if (!cur_skip) {
+            if (!cur.seg) {
+                double dvw[CPL], dww[CPL], dvv[CPL];
+                core.finish(cur.row, sp, sq, acc, dvw, dww, dvv);
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    my0[k] += dvw[k];
+                    my1[k] += dww[k];
+                    my2[k] += dvv[k];
+                }
+            } else {
+                // segment of a long row: its partial product is finished by
+                // k_long_rows after this kernel (the kernel boundary orders it)
+                double *dst = a.seg_acc + (int64_t)cur.it * core.ld + core.c0;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) dst[k] = acc[k];
+            }
+        }
+        cur = nxt;
+        cur_skip = nxt_skip;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            jj[u] = njj[u];
+            vv[u] = nvv[u];
+        }
+        nxt = nn;
     }
 
     // block reduction over the lane groups that share columns (fixed order)
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-        red[0][gid * MT + gl * CPL + k] = s_vw[k];
-        red[1][gid * MT + gl * CPL + k] = s_ww[k];
-        red[2][gid * MT + gl * CPL + k] = s_vv[k];
-    }
     __syncthreads();
     // partials layout [n_blocks][3][m_pad]: the finalize reads whole rows
     double *out = a.partials + (int64_t)b * 3 * a.m_pad + tile * MT;
@@ -359,7 +443,7 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int b, int tile,
 }
 
 template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
-__global__ void __launch_bounds__(kStepThreads) k_lanczos_step(StepArgs a) {
+__global__ void __launch_bounds__(kStepThreads) VNE_STEP_OCCUPANCY k_lanczos_step(StepArgs a) {
     constexpr int NG = (kStepThreads / 64) * (64 / LPR);
     __shared__ double red[3][NG * CPL * LPR];
     // column tiles are dispatched one after the other (tile-major grid), so
@@ -375,7 +459,7 @@ __global__ void __launch_bounds__(kStepThreads) k_lanczos_step(StepArgs a) {
 // first step of a slot runs as a later step whose v_{j-1} is zero and whose
 // alpha_{j-1}, beta_{j-1} are zero, which gives the same values.
 template <typename T, int CPL, int LPR>
-__global__ void __launch_bounds__(kStepThreads) k_lanczos_step_slots(const StepArgs *args, const int4 *map,
+__global__ void __launch_bounds__(kStepThreads) VNE_STEP_OCCUPANCY k_lanczos_step_slots(const StepArgs *args, const int4 *map,
                                                                      int32_t n_entries) {
     constexpr int NG = (kStepThreads / 64) * (64 / LPR);
     __shared__ double red[3][NG * CPL * LPR];
@@ -712,22 +796,67 @@ __global__ void __launch_bounds__(256) k_finalize_graphs(FinalizeArgs a) {
     update_coefficients(a, g, c, svw, sww, svv);
 }
 
-// Slots: thread (slot e.x, column e.y * 256 + tid) adds the slot's block
-// partials, then its long rows, in order, and updates.
-__global__ void __launch_bounds__(256) k_finalize_slots(const FinalizeArgs *fargs, const int2 *map) {
+// Slots, first level: block (slot e.x, columns e.y * C .., part blockIdx.y)
+// of 16 groups of C threads.  The slot's items (its work blocks, then its
+// long rows) are cut into n_level2 * G contiguous ranges; group q of part r
+// adds range r * G + q in order, and the block writes the G group sums, added
+// in order, to level2[r][3][m_pad] of the slot.  The order depends only on
+// the slot's own shape.
+__global__ void __launch_bounds__(256) k_reduce_slots(const FinalizeArgs *fargs, const int2 *map) {
+    constexpr int C = kFinalizeCols, G = 256 / C;
+    __shared__ double sh[3][G][C];
     const int2 e = map[blockIdx.x];
     const FinalizeArgs a = fargs[e.x];
-    const int c = e.y * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    const int cc = threadIdx.x % C, grp = threadIdx.x / C;
+    const int c = e.y * C + cc;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (c < a.m_pad && r < a.n_level2) {
+        const int total = a.n_blocks + a.n_long;
+        const int ranges = a.n_level2 * G;
+        const int per = (total + ranges - 1) / ranges;
+        const int i0 = min(total, (r * G + grp) * per), i1 = min(total, i0 + per);
+        const int b1 = min(i1, a.n_blocks);
+        for (int i = i0; i < b1; ++i) {
+            const double *p = a.partials + (int64_t)i * 3 * a.m_pad + c;
+            s0 += p[0];
+            s1 += p[a.m_pad];
+            s2 += p[2 * a.m_pad];
+        }
+        for (int i = max(i0, a.n_blocks); i < i1; ++i) {
+            const double *p = a.long_part + (int64_t)(i - a.n_blocks) * 3 * a.m_pad + c;
+            s0 += p[0];
+            s1 += p[a.m_pad];
+            s2 += p[2 * a.m_pad];
+        }
+    }
+    sh[0][grp][cc] = s0;
+    sh[1][grp][cc] = s1;
+    sh[2][grp][cc] = s2;
+    __syncthreads();
+    if (grp != 0 || c >= a.m_pad || r >= a.n_level2) return;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int q = 0; q < G; ++q) {
+        t0 += sh[0][q][cc];
+        t1 += sh[1][q][cc];
+        t2 += sh[2][q][cc];
+    }
+    double *out = a.level2 + (int64_t)r * 3 * a.m_pad + c;
+    out[0] = t0;
+    out[a.m_pad] = t1;
+    out[2 * a.m_pad] = t2;
+}
+
+// Slots, second level: thread (slot, column) adds the n_level2 rows in order
+// and updates.
+__global__ void __launch_bounds__(kFinalizeCols) k_finalize_slots(const FinalizeArgs *fargs, const int2 *map) {
+    const int2 e = map[blockIdx.x];
+    const FinalizeArgs a = fargs[e.x];
+    const int c = e.y * kFinalizeCols + threadIdx.x;
     if (c >= a.m_pad) return;
     double svw = 0.0, sww = 0.0, svv = 0.0;
-    for (int bb = 0; bb < a.n_blocks; ++bb) {
-        const double *p = a.partials + (int64_t)bb * 3 * a.m_pad + c;
-        svw += p[0];
-        sww += p[a.m_pad];
-        svv += p[2 * a.m_pad];
-    }
-    for (int L = 0; L < a.n_long; ++L) {
-        const double *p = a.long_part + (int64_t)L * 3 * a.m_pad + c;
+    for (int r = 0; r < a.n_level2; ++r) {
+        const double *p = a.level2 + (int64_t)r * 3 * a.m_pad + c;
         svw += p[0];
         sww += p[a.m_pad];
         svv += p[2 * a.m_pad];
@@ -736,7 +865,10 @@ __global__ void __launch_bounds__(256) k_finalize_slots(const FinalizeArgs *farg
 }
 
 hipError_t launch_finalize_slots(const FinalizeArgs *fargs, const int2 *map, int32_t n_entries, hipStream_t s) {
-    if (n_entries > 0) hipLaunchKernelGGL(k_finalize_slots, dim3(n_entries), dim3(256), 0, s, fargs, map);
+    if (n_entries > 0) {
+        hipLaunchKernelGGL(k_reduce_slots, dim3(n_entries, kSlotLevel2), dim3(256), 0, s, fargs, map);
+        hipLaunchKernelGGL(k_finalize_slots, dim3(n_entries), dim3(kFinalizeCols), 0, s, fargs, map);
+    }
     return hipGetLastError();
 }
 
@@ -897,25 +1029,50 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// element i (wave-uniform) of a two-register lane-resident vector
+// element i (wave-uniform, < 128) of a two-register lane-resident vector;
+// both halves are read and the choice is a scalar select (no branch)
+template <int NH = 2>
 __device__ __forceinline__ double get_row(double lo, double hi, int i) {
-    return i < 64 ? readlane_d(lo, i) : readlane_d(hi, i - 64);
+    if (NH == 1) return readlane_d(lo, i & 63);
+    const double a = readlane_d(lo, i & 63), b = readlane_d(hi, i & 63);
+    return i < 64 ? a : b;
 }
+// writes x into element i; any i outside [0, 64 * NH) (e.g. -1) writes nothing
+template <int NH = 2>
 __device__ __forceinline__ void set_row(double &lo, double &hi, int i, double x, int lane) {
-    if (i < 64) lo = (lane == i) ? x : lo;
-    else hi = (lane == i - 64) ? x : hi;
+    lo = (lane == i) ? x : lo;
+    if (NH == 2) hi = (lane + 64 == i) ? x : hi;
+}
+
+// Givens rotation [c s; -s c] taking (x, y) to (r, 0): 1/r from the
+// hardware reciprocal square root and one Newton step (c^2 + s^2 = 1 to a
+// few units of rounding, which keeps the QR sweep backward stable).
+__device__ __forceinline__ void givens(double x, double y, double &c, double &s, double &r) {
+    const double a = fma(x, x, y * y);
+    double q = __builtin_amdgcn_rsq(a);
+    q = q * fma(-0.5 * a, q * q, 1.5);
+    const bool nz = a > 0.0;
+    c = nz ? x * q : 1.0;
+    s = nz ? y * q : 0.0;
+    r = nz ? a * q : 0.0;
 }
 
 struct LaneTri {
     double d0, d1, e0, e1, z0, z1;
 };
 
-// Runs the QR iteration on the first n (<= 128) rows.  Records every rotation
-// in rot[0..cap) when rot != nullptr.  Returns 0 on success, bit 2 if an
-// eigenvalue needed more than 60 sweeps, bit 3 if the record overflowed.
+// Runs the QR iteration on the first n (<= 128) rows.  With RECORD, every
+// rotation goes to rot[0..cap), 64 at a time from lane-resident chunks.
+// Returns 0 on success, bit 2 if an eigenvalue needed more than 60 sweeps,
+// bit 3 if the record overflowed.  The chase body has no branch: the rows
+// two ahead of the bulge (untouched by the sweep so far) are read while the
+// rotation is computed.
+template <bool RECORD, int NH>
 __device__ int lane_tridiag_qr(LaneTri &t, int n, int lane, Rot *rot, int cap, int *nrot) {
     const double eps = 1.1102230246251565e-16;   // 2^-53
     int status = 0, cnt = 0;
+    double rc = 1.0, rs = 0.0;
+    int ri = 0;
     int hi = n - 1, sweeps = 0;
     while (hi > 0) {
         // negligible off-diagonals, all indices at once
@@ -930,7 +1087,7 @@ __device__ int lane_tridiag_qr(LaneTri &t, int n, int lane, Rot *rot, int cap, i
         const int b = hi - 1;
         const bool negl = b < 64 ? ((m0 >> b) & 1ull) : ((m1 >> (b - 64)) & 1ull);
         if (negl) {
-            set_row(t.e0, t.e1, b, 0.0, lane);
+            set_row<NH>(t.e0, t.e1, b, 0.0, lane);
             --hi;
             sweeps = 0;
             continue;
@@ -943,66 +1100,77 @@ __device__ int lane_tridiag_qr(LaneTri &t, int n, int lane, Rot *rot, int cap, i
             if (h1) lo = 64 + (63 - __builtin_clzll(h1)) + 1;
             else if (h0) lo = (63 - __builtin_clzll(h0)) + 1;
         }
-        if (lo > 0) set_row(t.e0, t.e1, lo - 1, 0.0, lane);
+        if (lo > 0) set_row<NH>(t.e0, t.e1, lo - 1, 0.0, lane);
         if (++sweeps > 60) {
             status |= 4;
             break;
         }
         // Wilkinson shift from the trailing 2x2 block
-        const double dh1 = get_row(t.d0, t.d1, hi - 1), dh = get_row(t.d0, t.d1, hi);
-        const double bh = get_row(t.e0, t.e1, hi - 1);
+        const double dh1 = get_row<NH>(t.d0, t.d1, hi - 1), dh = get_row<NH>(t.d0, t.d1, hi);
+        const double bh = get_row<NH>(t.e0, t.e1, hi - 1);
         const double dl = 0.5 * (dh1 - dh);
         const double rt = sqrt(fma(dl, dl, bh * bh));
         const double den = dl + (dl < 0.0 ? -rt : rt);
         const double mu = dh - bh * (bh / den);
         // bulge chase with the active rows carried in registers
-        double di = get_row(t.d0, t.d1, lo), dj = get_row(t.d0, t.d1, lo + 1);
-        double ei = get_row(t.e0, t.e1, lo);
-        double enx = lo + 1 < hi ? get_row(t.e0, t.e1, lo + 1) : 0.0;
-        double zi = get_row(t.z0, t.z1, lo), zj = get_row(t.z0, t.z1, lo + 1);
+        double di = get_row<NH>(t.d0, t.d1, lo), dj = get_row<NH>(t.d0, t.d1, lo + 1);
+        double ei = get_row<NH>(t.e0, t.e1, lo);
+        const double e_lo1 = get_row<NH>(t.e0, t.e1, lo + 1);
+        double enx = lo + 1 < hi ? e_lo1 : 0.0;
+        double zi = get_row<NH>(t.z0, t.z1, lo), zj = get_row<NH>(t.z0, t.z1, lo + 1);
         double x = di - mu, y = ei;
         for (int i = lo; i < hi; ++i) {
-            const double r = sqrt(fma(x, x, y * y));
-            double c = 1.0, s = 0.0;
-            if (r != 0.0) {
-                const double ir = 1.0 / r;
-                c = x * ir;
-                s = y * ir;
-            }
-            if (i > lo) set_row(t.e0, t.e1, i - 1, r, lane);
-            const double cs = c * s, cc = c * c, ss = s * s;
+            const int i2 = min(i + 2, 64 * NH - 1);
+            const double dn = get_row<NH>(t.d0, t.d1, i2), en = get_row<NH>(t.e0, t.e1, i2);
+            const double zn = get_row<NH>(t.z0, t.z1, i2);
+            double c, sn, r;
+            givens(x, y, c, sn, r);
+            set_row<NH>(t.e0, t.e1, i > lo ? i - 1 : -1, r, lane);
+            const double cs = c * sn, cc = c * c, ss = sn * sn;
             const double ndi = fma(cc, di, fma(2.0 * cs, ei, ss * dj));
             const double ndj = fma(ss, di, fma(-2.0 * cs, ei, cc * dj));
             const double nei = fma(cs, dj - di, (cc - ss) * ei);
-            const double nzi = fma(c, zi, s * zj);
-            const double nzj = fma(-s, zi, c * zj);
-            set_row(t.d0, t.d1, i, ndi, lane);
-            set_row(t.z0, t.z1, i, nzi, lane);
-            if (rot) {
-                if (cnt < cap) {
-                    if (lane == 0) rot[cnt] = Rot{c, s, i, 0};
-                    ++cnt;
-                } else {
-                    status |= 8;
+            const double nzi = fma(c, zi, sn * zj);
+            const double nzj = fma(-sn, zi, c * zj);
+            set_row<NH>(t.d0, t.d1, i, ndi, lane);
+            set_row<NH>(t.z0, t.z1, i, nzi, lane);
+            if (RECORD) {
+                const int slot = cnt & 63;
+                rc = lane == slot ? c : rc;
+                rs = lane == slot ? sn : rs;
+                ri = lane == slot ? i : ri;
+                ++cnt;
+                if ((cnt & 63) == 0) {
+                    if (cnt <= cap) rot[cnt - 64 + lane] = Rot{rc, rs, ri, 0};
+                    else status |= 8;
                 }
             }
-            if (i + 1 < hi) {
-                y = s * enx;
-                ei = c * enx;
-                x = nei;
-                di = ndj;
-                dj = get_row(t.d0, t.d1, i + 2);
-                enx = i + 2 < hi ? get_row(t.e0, t.e1, i + 2) : 0.0;
-                zi = nzj;
-                zj = get_row(t.z0, t.z1, i + 2);
+            // carried rows for the next rotation (after the last one they
+            // hold rows hi - 1 and hi of the sweep's result)
+            y = sn * enx;
+            ei = c * enx;
+            x = nei;
+            di = ndj;
+            dj = dn;
+            enx = i + 2 < hi ? en : 0.0;
+            zi = nzj;
+            zj = zn;
+        }
+        set_row<NH>(t.d0, t.d1, hi, di, lane);
+        set_row<NH>(t.e0, t.e1, hi - 1, x, lane);
+        set_row<NH>(t.z0, t.z1, hi, zi, lane);
+    }
+    if (RECORD) {
+        const int part = cnt & 63;
+        if (part) {
+            if (cnt <= cap) {
+                if (lane < part) rot[cnt - part + lane] = Rot{rc, rs, ri, 0};
             } else {
-                set_row(t.d0, t.d1, i + 1, ndj, lane);
-                set_row(t.e0, t.e1, i, nei, lane);
-                set_row(t.z0, t.z1, i + 1, nzj, lane);
+                status |= 8;
             }
         }
+        if (nrot) *nrot = min(cnt, cap);
     }
-    if (nrot) *nrot = cnt;
     return status;
 }
 
@@ -1035,7 +1203,8 @@ __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const d
     }
     LaneTri t;
     load_tri(t, alpha + (int64_t)c * k, beta + (int64_t)c * k, ke, lane);
-    const int st = lane_tridiag_qr(t, ke, lane, nullptr, 0, nullptr);
+    const int st = ke <= 64 ? lane_tridiag_qr<false, 1>(t, ke, lane, nullptr, 0, nullptr)
+                            : lane_tridiag_qr<false, 2>(t, ke, lane, nullptr, 0, nullptr);
     double part = 0.0;
     if (lane < ke) part += t.z0 * t.z0 * f_entropy(t.d0);
     if (lane + 64 < ke) part += t.z1 * t.z1 * f_entropy(t.d1);
@@ -1074,15 +1243,45 @@ __global__ void __launch_bounds__(256) k_fT_e1(const double *alpha, const double
     const int cap = (int)rot_capacity(k);
     Rot *rot = rot_buf + (int64_t)c * cap;
     int nrot = 0;
-    const int st = lane_tridiag_qr(t, ke, lane, rot, cap, &nrot);
+    const int st = ke <= 64 ? lane_tridiag_qr<true, 1>(t, ke, lane, rot, cap, &nrot)
+                            : lane_tridiag_qr<true, 2>(t, ke, lane, rot, cap, &nrot);
     double w0 = lane < ke ? f_entropy(t.d0) * t.z0 : 0.0;
     double w1 = lane + 64 < ke ? f_entropy(t.d1) * t.z1 : 0.0;
-    for (int q = nrot - 1; q >= 0; --q) {
-        const Rot r = rot[q];
-        const int i = __builtin_amdgcn_readfirstlane(r.i);
-        const double a = get_row(w0, w1, i), b = get_row(w0, w1, i + 1);
-        set_row(w0, w1, i, fma(r.c, a, -r.s * b), lane);
-        set_row(w0, w1, i + 1, fma(r.s, a, r.c * b), lane);
+    // the wave's own record, read back in reverse order in chunks of 64 (lane
+    // j of a chunk holds rotation top - 64 + j); the next chunk is in flight
+    // while the current one is applied
+    __threadfence_block();
+    auto fetch = [&](int top, double &cr, double &sr, int &ir) {
+        const int idx = top - 64 + lane;
+        if (idx >= 0) {
+            const Rot r = rot[idx];
+            cr = r.c;
+            sr = r.s;
+            ir = r.i;
+        } else {
+            cr = 1.0;
+            sr = 0.0;
+            ir = 0;
+        }
+    };
+    double cr = 1.0, sr = 0.0;
+    int ir = 0;
+    if (nrot > 0) fetch(nrot, cr, sr, ir);
+    for (int top = nrot; top > 0; top -= 64) {
+        double ncr = 1.0, nsr = 0.0;
+        int nir = 0;
+        if (top > 64) fetch(top - 64, ncr, nsr, nir);
+        const int j_end = top >= 64 ? 0 : 64 - top;
+        for (int j = 63; j >= j_end; --j) {
+            const double c = readlane_d(cr, j), sn = readlane_d(sr, j);
+            const int i = __builtin_amdgcn_readlane(ir, j);
+            const double a = get_row(w0, w1, i), b = get_row(w0, w1, i + 1);
+            set_row(w0, w1, i, fma(c, a, -sn * b), lane);
+            set_row(w0, w1, i + 1, fma(sn, a, c * b), lane);
+        }
+        cr = ncr;
+        sr = nsr;
+        ir = nir;
     }
     if (lane < ke) S[(int64_t)lane * m + c] = w0;
     if (lane + 64 < ke) S[(int64_t)(lane + 64) * m + c] = w1;

@@ -54,7 +54,7 @@ struct SrvTask {
     char *P[2] = {nullptr, nullptr}, *V[2] = {nullptr, nullptr};
     double *alpha = nullptr, *beta = nullptr, *st_alpha = nullptr, *st_inv = nullptr, *st_coup = nullptr;
     double *norm2 = nullptr, *mean = nullptr, *partials = nullptr, *probe_part = nullptr;
-    double *seg_acc = nullptr, *long_part = nullptr;
+    double *seg_acc = nullptr, *long_part = nullptr, *level2 = nullptr;
     int32_t *k_eff = nullptr;
 };
 
@@ -150,6 +150,7 @@ size_t task_bytes(const GraphSet *set, int m_pad, int k, bool fp64) {
     b += rnd((size_t)set->probe_blocks * m_pad * 8);
     b += rnd((size_t)std::max(1, sc.n_seg) * m_pad * 8);
     b += rnd((size_t)std::max(1, sc.n_long) * 3 * m_pad * 8);
+    b += rnd((size_t)kSlotLevel2 * 3 * m_pad * 8);
     return b;
 }
 
@@ -179,6 +180,7 @@ void carve(SrvTask &t, char *base, const GraphSet *set, bool fp64) {
     t.probe_part = (double *)take((size_t)set->probe_blocks * t.m_pad * 8);
     t.seg_acc = (double *)take((size_t)std::max(1, sc.n_seg) * t.m_pad * 8);
     t.long_part = (double *)take((size_t)std::max(1, sc.n_long) * 3 * t.m_pad * 8);
+    t.level2 = (double *)take((size_t)kSlotLevel2 * 3 * t.m_pad * 8);
 }
 
 // Tasks for columns [c0, c1) of a query, at most max_cols each, in the
@@ -445,6 +447,8 @@ FinalizeArgs fin_args(const vne_server *s, const SrvTask &t, const GraphSet *set
     FinalizeArgs f{};
     f.partials = t.partials;
     f.long_part = t.long_part;
+    f.level2 = t.level2;
+    f.n_level2 = kSlotLevel2;
     f.n_blocks = set->sched.n_blocks();
     f.n_long = set->sched.n_long;
     f.mt = t.mt;
@@ -490,7 +494,7 @@ vne_status tick(vne_server *s) {
             for (int tile = 0; tile < nt; ++tile)
                 for (int gi = 0; gi < (set->sched.n_long + per - 1) / per; ++gi) lm.push_back(make_int4(i, gi, tile, 0));
         }
-        for (int ch = 0; ch < (t.m_pad + 255) / 256; ++ch) fmap.push_back(make_int2(i, ch));
+        for (int ch = 0; ch < (t.m_pad + kFinalizeCols - 1) / kFinalizeCols; ++ch) fmap.push_back(make_int2(i, ch));
     }
     size_t bytes = rnd(sizeof(StepArgs) * A) + rnd(sizeof(FinalizeArgs) * A) + rnd(sizeof(int2) * fmap.size());
     for (auto &kv : smap) bytes += rnd(sizeof(int4) * kv.second.size());
