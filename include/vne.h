@@ -268,8 +268,10 @@ vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, dou
  * the Gershgorin bound max_i sum_j |A_ij| and S_lower = -log tr(A^2) <= S(A)
  * for a unit-trace PSD matrix (otherwise k = max_steps).  Probes: a pilot of
  * pilot_probes columns runs first; N = ceil((z sd / ((rel_eps / 2) mean))^2)
- * over its quadratic forms, clamped to [pilot_probes, max_probes]; the pilot's
- * forms are kept and columns pilot_probes..N-1 follow.
+ * over its quadratic forms, clamped to [pilot_probes, max_probes] and, when
+ * above the pilot, rounded up to whole groups of 16 columns; the pilot's
+ * forms are kept and columns pilot_probes..N-1 follow.  Tasks are max_cols
+ * wide while that much is left, then powers of two of at least 16 columns.
  *
  * Thread safety: submit, poll and stats may be called from any thread.
  * While a server runs, its context may still register graphs and run

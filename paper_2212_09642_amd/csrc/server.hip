@@ -183,14 +183,24 @@ void carve(SrvTask &t, char *base, const GraphSet *set, bool fp64) {
     t.level2 = (double *)take((size_t)kSlotLevel2 * 3 * t.m_pad * 8);
 }
 
-// Tasks for columns [c0, c1) of a query, at most max_cols each, in the
-// pending queue after every task of an earlier ticket.
+// Tasks for columns [c0, c1) of a query, in the pending queue after every
+// task of an earlier ticket.  Widths: max_cols while that much is left, then
+// the largest power of two (at least 16) that fits, then the rest, so that a
+// task's width is a whole number of column tiles wherever possible.
 void add_tasks(vne_server *s, SrvQuery &q, int c0, int c1, bool pilot) {
     std::vector<SrvTask> ts;
-    for (int c = c0; c < c1; c += s->cfg.max_cols) {
+    for (int c = c0; c < c1;) {
+        const int rem = c1 - c;
+        int w = rem;
+        if (rem >= s->cfg.max_cols) {
+            w = s->cfg.max_cols;
+        } else if (rem >= 16) {
+            w = 16;
+            while (2 * w <= rem) w *= 2;
+        }
         SrvTask t;
         t.ticket = q.ticket;
-        t.m = std::min(s->cfg.max_cols, c1 - c);
+        t.m = w;
         t.mt = choose_tile(t.m, s->fp64, 0);
         t.m_pad = pad_columns(t.m, t.mt);
         t.k = q.k;
@@ -198,6 +208,7 @@ void add_tasks(vne_server *s, SrvQuery &q, int c0, int c1, bool pilot) {
         t.pilot = pilot;
         t.bytes = task_bytes(q.set, t.m_pad, t.k, s->fp64);
         ts.push_back(t);
+        c += w;
     }
     q.cols_issued = c1;
     q.tasks_open += (int)ts.size();
@@ -329,7 +340,11 @@ vne_status poll_events(vne_server *s, bool block_one) {
             mean /= n0;
             for (int i = 0; i < n0; ++i) var += (q->h_buf[i] - mean) * (q->h_buf[i] - mean);
             const double sd = n0 > 1 ? std::sqrt(var / (n0 - 1)) : 0.0;
+            // the rule's N, rounded up to whole 16-column groups: the extra
+            // columns would be computed as padding anyway, and more probes
+            // only tighten the estimate
             q->N = plan_probes(mean, sd, q->q.rel_eps, 0.5, s->cfg.z, n0, s->psi_cap);
+            if (q->N > n0) q->N = std::min(s->psi_cap, n0 + (q->N - n0 + 15) / 16 * 16);
             q->planned = true;
             if (q->N > n0) add_tasks(s, *q, n0, q->N, false);
             else VNE_TRY(issue_final(s, *q));

@@ -4,6 +4,7 @@
     python -m paper_2212_09642_amd.profiling stats DB OUT.md --cmd "..."
     python -m paper_2212_09642_amd.profiling traffic FETCH_DB WRITE_DB COPY_FETCH_DB \
         COPY_WRITE_DB OUT.json --workload NAME --copy-bytes B --cmd "..."
+    python -m paper_2212_09642_amd.profiling serve BENCH_LINE.json OUT.md --cmd "..."
 
 The Lanczos step unit is the normalize pass (two-pass schedule), the SpMM +
 recurrence kernel and the long-row kernel of one step; its average duration
@@ -92,6 +93,27 @@ def cmd_traffic(args):
     print(json.dumps(d, indent=1))
 
 
+def cmd_serve(args):
+    """Rate table of a `bench.py --workload serve` line."""
+    with open(args.line) as fh:
+        d = json.loads(fh.read().strip().splitlines()[-1])
+    c = d["config"]
+    out = ["# Serving loop: Poisson arrivals at several rates", "", "Command:", "", "```", args.cmd, "```", "",
+           "Workload `%s`: %d graphs, relative accuracy %g per query, %d queries per rate."
+           % (c["workload"], c["graphs"], c["rel_eps"], c["queries_per_rate"]), "",
+           "| offered /s | completed /s | p50 ms | p99 ms | algorithmic GB/s | mean probes | mean steps | "
+           "sampling target met | running slots per tick |",
+           "|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in d["rates"]:
+        out.append("| %g | %.1f | %.1f | %.1f | %.0f | %.0f | %.1f | %d/%d | %.2f |" % (
+            r["offered_per_s"], r["completed_per_s"], r["p50_ms"], r["p99_ms"], r["algorithmic_GBps"],
+            r["mean_probes"], r["mean_steps"], r["sampling_target_met"], r["queries"], r["slot_occupancy"]))
+    out += ["", "Saturated throughput: %.1f queries/s." % d["value"]]
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -106,8 +128,12 @@ def main():
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--copies", type=int, default=3)
     t.add_argument("--cmd", required=True)
+    v = sub.add_parser("serve")
+    v.add_argument("line")
+    v.add_argument("out")
+    v.add_argument("--cmd", required=True)
     args = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic}[args.what](args)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "serve": cmd_serve}[args.what](args)
 
 
 if __name__ == "__main__":

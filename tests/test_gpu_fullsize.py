@@ -1,0 +1,98 @@
+"""Parity at the benchmark sizes, in the benchmark's launch configuration,
+on sampled outputs the oracle computes one by one.
+
+* large: BA n = 2e5 (3 edges per node), FP32, k = 60.  The 256-wide
+  Rademacher block runs through the same step kernels and column tile as the
+  bench's quadratic-form phase; columns 0, 77, 200, 255 are checked against
+  the oracle.  The Hutch++ estimate of the bench is checked against that
+  Hutchinson estimate on the same probes (both unbiased for S; the difference
+  must stay within five standard errors of the Hutchinson mean).
+* probing: WS n = 1e6 (k = 10, p = 0.1), distance-2 colouring, k = 80:
+  colours 0, 11 and the last one against the oracle; the colouring itself is
+  compared bit for bit with the oracle elsewhere (CPU, slow).
+* batch: the 512-graph batch (64 probes, k = 50): four sampled graphs
+  (smallest, largest, one ER, one BA), four columns each.
+Bars: 1e-5 relative per quadratic form, widened to 20x the oracle's own
+rounding-order sensitivity (same problem, rows reversed) where that is larger.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import workloads
+import paper_2212_09642_amd as vne
+from gpu_common import TOL, ctx, _say, _rel  # noqa: F401
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _sampled_check(A, keys, B, out_quad, cols, k, desing=True):
+    want = oracle.quadforms(A, B, k, oracle.breakdown_tau(False), desing)["psi"]
+    n = A.shape[0]
+    P = np.arange(n)[::-1]
+    import scipy.sparse as sp
+    Ap = sp.csr_matrix(A)[P][:, P]
+    alt = oracle.quadforms(Ap, np.asarray(B)[P], k, oracle.breakdown_tau(False), desing)["psi"]
+    sens = _rel(alt, want)
+    rel = _rel(out_quad[cols], want)
+    bar = max(TOL[False], 20 * float(sens.max()))
+    _say("   sampled columns %s: max rel err %.2e (bar %.1e)" % (list(cols), rel.max(), bar))
+    assert np.all(rel < bar), rel
+
+
+def test_large_configuration_sampled(ctx):
+    w = workloads.large()
+    _say("case full size: BA n=2e5, m=256, k=60")
+    g = vne.laplacian_from_edges(w["n_nodes"], w["edges"], np.float32)
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    m, k = w["n_sketch"] + w["n_hutch"], w["k"]
+    out = ctx.estimate(gid, vne.PROBE_RADEMACHER, m, k, vne.MODE_DESING, seed=w["probe_seed"], want_coeffs=False)
+    cols = np.array([0, 77, 200, 255])
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.asarray(g["values"], np.float64) * g["scale"], g["col_idx"], g["row_ptr"]),
+                      shape=(g["n"], g["n"]))
+    B = oracle.rademacher_block(w["probe_seed"], g["node_ids"], cols)
+    _sampled_check(A, g["node_ids"], B, out["quad"], cols, k)
+    hpp = ctx.estimate(gid, vne.PROBE_HUTCHPP, m, k, vne.MODE_DESING, seed=w["probe_seed"],
+                       n_sketch=w["n_sketch"], want_coeffs=False)
+    se = out["quad"].std(ddof=1) / np.sqrt(m)
+    _say("   Hutch++ %.8f, Hutchinson %.8f +- %.1e" % (hpp["estimate"], out["estimate"], se))
+    assert abs(hpp["estimate"] - out["estimate"]) < 5 * se
+
+
+def test_probing_configuration_sampled(ctx):
+    w = workloads.probing()
+    _say("case full size: WS n=1e6, distance-2 colouring, k=80")
+    g = vne.laplacian_from_edges(w["n_nodes"], w["edges"], np.float32)
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    col, s = vne.color_greedy(g["row_ptr"], g["col_idx"], g["values"], w["d"])
+    out = ctx.estimate(gid, vne.PROBE_COLORING, s, w["k"], vne.MODE_DESING, colors=col, want_coeffs=False)
+    cols = np.array([0, 11, s - 1])
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.asarray(g["values"], np.float64) * g["scale"], g["col_idx"], g["row_ptr"]),
+                      shape=(g["n"], g["n"]))
+    B = oracle.indicator_block(col, s)[:, cols]
+    _sampled_check(A, g["node_ids"], B, out["quad"], cols, w["k"])
+    assert abs(out["estimate"] - out["quad"].sum()) <= 1e-13 * abs(out["estimate"])
+
+
+def test_batch_configuration_sampled(ctx):
+    _say("case full size: 512-graph batch, 64 probes, k=50")
+    specs = workloads.batch_specs()
+    graphs = [vne.laplacian_from_edges(*workloads.batch_graph(sp_), np.float32) for sp_ in specs]
+    gids = [ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+            for g in graphs]
+    queries = [dict(gid=gid, kind=vne.PROBE_RADEMACHER, m=64, k=50, seed=workloads.PROBE_SEED + q)
+               for q, gid in enumerate(gids)]
+    outs = ctx.estimate_batch(queries, vne.MODE_DESING)
+    sizes = np.array([g["n"] for g in graphs])
+    picks = [int(sizes.argmin()), int(sizes.argmax()), 2, 3]      # even specs are ER, odd are BA
+    import scipy.sparse as sp
+    for q in picks:
+        g = graphs[q]
+        _say("  graph %d (%s) n=%d" % (q, specs[q][0], g["n"]))
+        A = sp.csr_matrix((np.asarray(g["values"], np.float64) * g["scale"], g["col_idx"], g["row_ptr"]),
+                          shape=(g["n"], g["n"]))
+        cols = np.array([0, 21, 42, 63])
+        B = oracle.rademacher_block(workloads.PROBE_SEED + q, g["node_ids"], cols)
+        _sampled_check(A, g["node_ids"], B, outs[q]["quad"], cols, 50)
