@@ -18,7 +18,9 @@
   with thm22_proof at degree 2k - 1.
 * g_m and the a-posteriori bracket of Theorem 4.8 for the polynomial Krylov
   method (K_m = I, h_{m+1} = beta_m e_m), and the geometric-mean estimate
-  (4.10) of Example 4.10.
+  (4.10) of Example 4.10; g_m_entropy evaluates eq. (4.8) for -x log x with
+  divided differences free of cancellation near the Ritz values (pinned
+  against the generic g_m away from them and against its own limits).
 
 Pinned by: thm22 against the integral of its proof; every bound checked to
 hold on exact errors computed by diagonalization (tests).
@@ -111,14 +113,53 @@ def g_m(z, theta, U, beta_m, f=f_entropy, fp=_fprime, fpp=_fsecond):
     return out
 
 
+def entropy_divided_differences(z, theta):
+    """D1 = (f(z) - f(theta)) / (z - theta) and
+    D2 = (D1 - f'(theta)) / (z - theta) for f(x) = -x log x, z, theta > 0,
+    with their limits f'(theta) and f''(theta) / 2 at z = theta (the limits
+    eq. (4.8) takes).  Written with r = z / theta, t = r - 1:
+    f(z) - f(theta) = -theta (t log theta + r log r), so
+    D1 = -log theta - (1 + t) log1p(t) / t and D2 = q(t) / theta,
+    q(t) = (t - (1 + t) log1p(t)) / t^2; both by their Taylor series for
+    |t| < 1e-3, where the quotients would cancel."""
+    z = np.asarray(z, np.float64)
+    t = z / theta - 1.0
+    small = np.abs(t) < 1e-3
+    ts = np.where(small, 1.0, t)
+    l1 = np.log1p(ts)
+    h = np.where(small, 1.0 + t / 2 - t * t / 6 + t ** 3 / 12 - t ** 4 / 20, (1.0 + ts) * l1 / ts)
+    q = np.where(small, -0.5 + t / 6 - t * t / 12 + t ** 3 / 20 - t ** 4 / 30, (ts - (1.0 + ts) * l1) / (ts * ts))
+    return -np.log(theta) - h, q / theta
+
+
+def g_m_entropy(z, theta, U, beta_m, theta_floor):
+    """eq. (4.8) for f = -x log x in the polynomial case, evaluated with the
+    cancellation-free divided differences above.  Ritz values below
+    theta_floor (rounding-level ones, possible only along a null direction)
+    are raised to it."""
+    z = np.atleast_1d(np.asarray(z, np.float64))
+    a = beta_m * U[-1, :]
+    bb = U[0, :]
+    ab = a * bb
+    diff = theta[:, None] - theta[None, :]
+    np.fill_diagonal(diff, np.inf)
+    c = (ab[None, :] / diff).sum(axis=1)
+    th = np.maximum(theta, theta_floor)
+    out = np.zeros_like(z)
+    for j in range(theta.size):
+        d1, d2 = entropy_divided_differences(z, th[j])
+        out += ab[j] ** 2 * d2 + 2 * ab[j] * c[j] * d1
+    return out
+
+
 def posterior_bracket(alpha, beta, m, norm2, lam_min, lam_max, grid=2000):
     """Theorem 4.8: (lower, upper) bounds on |psi - psi_m| and the estimate
     (4.10), evaluating g_m on a log-spaced grid of [lam_min, lam_max] plus the
-    Ritz values inside it."""
+    Ritz values inside it (lam_min > 0)."""
     from scipy.linalg import eigh_tridiagonal
     theta, U = eigh_tridiagonal(alpha[:m], beta[:m - 1])
     z = np.geomspace(lam_min, lam_max, grid)
     z = np.concatenate([z, theta[(theta > lam_min) & (theta < lam_max)]])
-    g = np.abs(g_m(z, theta, U, beta[m - 1]))
+    g = np.abs(g_m_entropy(z, theta, U, beta[m - 1], lam_min))
     lo, hi = norm2 * g.min(), norm2 * g.max()
     return lo, hi, np.sqrt(lo * hi)

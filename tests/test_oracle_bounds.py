@@ -51,3 +51,43 @@ def test_theorem_4_8_bracket_on_example_4_10():
                                                lam.min(), lam.max())
         assert lo * (1 - 1e-8) <= err <= hi * (1 + 1e-8)
         assert est / 30 < err < est * 30                     # geometric-mean estimate (4.10)
+
+
+def test_entropy_divided_differences_pins():
+    """The cancellation-free divided differences against their definitions
+    away from theta (plain quotients in long double precision are not
+    needed: |t| >= 0.1 leaves no cancellation), against the limits f'(theta)
+    and f''(theta)/2 at z = theta, and continuity across the series switch."""
+    th = 3.7e-4
+    z = th * np.array([0.2, 0.5, 0.9, 1.1, 2.0, 7.0])
+    d1, d2 = bounds.entropy_divided_differences(z, th)
+    f = oracle.f_entropy
+    fp = -np.log(th) - 1.0
+    assert np.allclose(d1, (f(z) - f(th)) / (z - th), rtol=1e-12, atol=0)
+    assert np.allclose(d2, ((f(z) - f(th)) / (z - th) - fp) / (z - th), rtol=1e-10, atol=0)
+    e1, e2 = bounds.entropy_divided_differences(np.array([th]), th)
+    assert np.isclose(e1[0], fp, rtol=1e-15) and np.isclose(e2[0], -0.5 / th, rtol=1e-15)
+    for t in (1e-3 * (1 - 1e-9), 1e-3 * (1 + 1e-9), -1e-3 * (1 - 1e-9), -1e-3 * (1 + 1e-9)):
+        a1, a2 = bounds.entropy_divided_differences(np.array([th * (1 + t)]), th)
+        b1, b2 = bounds.entropy_divided_differences(np.array([th * (1 + t * (1 + 1e-7))]), th)
+        assert abs(a1[0] - b1[0]) < 1e-9 * abs(a1[0]) and abs(a2[0] - b2[0]) < 1e-9 * abs(a2[0])
+
+
+def test_g_m_entropy_matches_generic_away_from_ritz_values():
+    rng = np.random.default_rng(2)
+    n = 300
+    lam = np.sort(rng.uniform(1e-4, 1e-2, n))
+    import scipy.sparse as sp
+    A = sp.diags(lam).tocsr()
+    b = rng.standard_normal((n, 1))
+    res = oracle.lanczos(A, b, 12, oracle.breakdown_tau(True))
+    from scipy.linalg import eigh_tridiagonal
+    m = 10
+    theta, U = eigh_tridiagonal(res["alpha"][0][:m], res["beta"][0][:m - 1])
+    z = np.geomspace(1e-4, 1e-2, 400)
+    dist = np.min(np.abs(z[:, None] / theta[None, :] - 1.0), axis=1)
+    z = z[dist > 0.05]
+    g1 = bounds.g_m(z, theta, U, res["beta"][0][m - 1])
+    g2 = bounds.g_m_entropy(z, theta, U, res["beta"][0][m - 1], 1e-12)
+    # terms of size max|g| cancel in the sum over Ritz values: absolute bar
+    assert np.allclose(g1, g2, rtol=1e-9, atol=1e-8 * np.abs(g1).max())
