@@ -230,6 +230,22 @@ vne_status vne_entropy_estimate_batch(vne_ctx *ctx, int32_t n_queries, const int
                                       const vne_probes *probes, const int32_t *k_steps,
                                       uint32_t mode, vne_result *out);
 
+/* A-posteriori error bracket of Theorem 4.8 for the polynomial Krylov
+ * method, per column of a result (host arrays laid out as in vne_result:
+ * alpha, beta [m*k], k_eff, norm2 [m]) after min(k_eff[c], steps) steps:
+ * lo[c] <= |psi - psi_m| <= hi[c] with lo, hi = ||c||^2 min, max |g_m(z)| of
+ * eq. (4.8) for f = -x log x, the extremes taken over n_grid log-spaced
+ * points of [lam_lo, lam_hi] plus the Ritz values inside it.  The interval
+ * must contain the spectrum of A seen by the start vectors (for a Laplacian
+ * density matrix with VNE_MODE_DESING: [lambda_2, lambda_n]; any
+ * 0 < lam_lo <= lambda_2 and lam_hi >= lambda_n, e.g. a Gershgorin bound,
+ * keep hi an upper bound).  Ritz values below lam_lo are raised to it.  A
+ * column whose recurrence stopped on beta = 0 gets lo = hi = 0.  Needs
+ * 1 <= steps <= k <= 128, 0 < lam_lo < lam_hi, 2 <= n_grid <= 65536. */
+vne_status vne_error_bounds(vne_ctx *ctx, int32_t m, int32_t k, const double *alpha, const double *beta,
+                            const int32_t *k_eff, const double *norm2, int32_t steps, double lam_lo,
+                            double lam_hi, int32_t n_grid, double *lo, double *hi);
+
 /* Kernel timing for measurement: when enabled, the context records a HIP
  * event pair on its stream around every launch of the Lanczos step kernel
  * and accumulates their durations.  vne_kernel_timing returns (and with
@@ -262,11 +278,16 @@ vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, dou
  *
  * rel_eps == 0: the query gives m (<= max_probes) and k_steps (<= 128).
  * rel_eps > 0: half of the relative error budget goes to the quadrature and
- * half to sampling (Remarks 5.1, 5.2).  Steps: the smallest k with
+ * half to sampling (Remarks 5.1, 5.2).  Steps: at most the smallest k with
  * 2 n lambda_ub / (4 ((2k-1)^2 - 1)) <= (rel_eps / 2) S_lower (Proposition 4.4
  * with the gamma = 0 bound of Remark 2.3, ||c||^2 <= n), where lambda_ub is
  * the Gershgorin bound max_i sum_j |A_ij| and S_lower = -log tr(A^2) <= S(A)
- * for a unit-trace PSD matrix (otherwise k = max_steps).  Probes: a pilot of
+ * for a unit-trace PSD matrix (otherwise k = max_steps, no early stop).  A
+ * task stops earlier at the first of steps 3, 5, 7, ... at which the Theorem
+ * 4.8 upper bound (vne_error_bounds over [1e-12 lambda_ub, lambda_ub], 256
+ * grid points) is within (rel_eps / 2) S_lower for each of its probes; the
+ * step is recorded on the device, so the result does not depend on when the
+ * worker notices it.  Probes: a pilot of
  * pilot_probes columns runs first; N = ceil((z sd / ((rel_eps / 2) mean))^2)
  * over its quadratic forms, clamped to [pilot_probes, max_probes] and, when
  * above the pilot, rounded up to whole groups of 16 columns; the pilot's
@@ -307,8 +328,8 @@ typedef struct {
     char message[128];          /* "" on success */
     double estimate;            /* eq. (3.8) over the N quadratic forms */
     double std_error;           /* sample standard deviation of the forms / sqrt(N) */
-    double quad_bound;          /* rel_eps > 0: the a-priori per-form quadrature bound used */
-    int32_t probes, steps;      /* N and k */
+    double quad_bound;          /* rel_eps > 0: the per-form quadrature error target */
+    int32_t probes, steps;      /* N, and the most Lanczos steps a task of the query used */
     double queue_ms;            /* submit -> first task admitted */
     double latency_ms;          /* submit -> result ready on the host */
 } vne_query_result;

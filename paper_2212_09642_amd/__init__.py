@@ -34,7 +34,7 @@ EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_c
            "vne_ctx_memory", "vne_graph_register", "vne_graph_release", "vne_entropy_estimate",
            "vne_entropy_estimate_batch", "vne_enable_kernel_timing", "vne_kernel_timing",
            "vne_server_start", "vne_server_submit", "vne_server_poll", "vne_server_stats",
-           "vne_server_stop", "vne_plan_steps", "vne_plan_probes"]
+           "vne_server_stop", "vne_plan_steps", "vne_plan_probes", "vne_error_bounds"]
 
 
 class VneError(RuntimeError):
@@ -138,6 +138,8 @@ def lib():
         L.vne_server_stats.argtypes = [vp, P(_ServerInfo)]
         L.vne_server_stop.restype = i32
         L.vne_server_stop.argtypes = [vp]
+        L.vne_error_bounds.restype = i32
+        L.vne_error_bounds.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, dbl, dbl, i32, vp, vp]
         L.vne_plan_steps.restype = i32
         L.vne_plan_steps.argtypes = [dbl, dbl, dbl, dbl, dbl, i32]
         L.vne_plan_probes.restype = i32
@@ -346,6 +348,20 @@ class Context:
         for i, o in enumerate(outs):
             o["estimate"] = ress[i].estimate
         return outs
+
+    def error_bounds(self, alpha, beta, k_eff, norm2, steps, lam_lo, lam_hi, n_grid=2000):
+        """Theorem 4.8 bracket (lo, hi) per column after min(k_eff, steps) steps."""
+        alpha = np.ascontiguousarray(alpha, np.float64)
+        beta = np.ascontiguousarray(beta, np.float64)
+        k_eff = np.ascontiguousarray(k_eff, np.int32)
+        norm2 = np.ascontiguousarray(norm2, np.float64)
+        m, k = alpha.shape
+        lo = np.zeros(m)
+        hi = np.zeros(m)
+        self._chk(self._L.vne_error_bounds(self._h, m, k, _ptr(alpha), _ptr(beta), _ptr(k_eff), _ptr(norm2),
+                                           int(steps), float(lam_lo), float(lam_hi), int(n_grid), _ptr(lo),
+                                           _ptr(hi)))
+        return lo, hi
 
     def enable_kernel_timing(self, on=True):
         self._chk(self._L.vne_enable_kernel_timing(self._h, 1 if on else 0))

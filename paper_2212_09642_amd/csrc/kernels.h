@@ -145,10 +145,12 @@ hipError_t launch_rademacher_fill(void *out, bool fp64, int32_t n, int32_t m, in
                                   int32_t col_offset, uint64_t seed, const int64_t *keys,
                                   hipStream_t s);
 
-// Gauss quadrature of every column: psi[c] = norm2[c] e1^T f(T) e1
+// Gauss quadrature of every column after min(k_eff[c], steps) steps:
+// psi[c] = norm2[c] e1^T f(T) e1 (1 <= steps <= k).  With `stop` given, a
+// record {uid, j > 0} there lowers steps to j (a-posteriori stopping).
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
-                             const double *norm2, int32_t k, int32_t m, double *psi,
-                             int32_t *flags, hipStream_t s);
+                             const double *norm2, int32_t k, int32_t steps, int32_t m, double *psi,
+                             int32_t *flags, hipStream_t s, const int2 *stop = nullptr, int32_t uid = 0);
 // f(T) e1 for every column (rows >= k_eff are 0), step-major: S[r*m + c]; rot_scratch
 // holds rot_capacity(k) recorded rotations (24 bytes each) per column
 __host__ __device__ int64_t rot_capacity(int32_t k);
@@ -156,6 +158,33 @@ constexpr int64_t kRotBytes = 24;
 hipError_t launch_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff,
                         int32_t k, int32_t m, double *S, void *rot_scratch, int32_t *flags,
                         hipStream_t s);
+
+// Theorem 4.8 bracket per column (see kernels.hip): one problem = m columns
+// of Lanczos coefficients (layout [m][k]) after `steps` steps
+struct BoundArgs {
+    const double *alpha, *beta;
+    const int32_t *k_eff;
+    const double *norm2;
+    int32_t k, m, steps;
+    double lam_lo, lam_hi;      // 0 < lam_lo < lam_hi
+    int32_t n_grid;             // >= 2
+    double *lo, *hi;            // [m]
+    int32_t *flags;             // QR status bits
+};
+// map entries {problem, group of 4 columns}
+hipError_t launch_error_bound(const BoundArgs *args, const int2 *map, int32_t n_entries, hipStream_t s);
+
+struct StopArgs {
+    const double *hi;
+    int32_t m;
+    double tol;
+    int32_t step;
+    int32_t uid;
+    int2 *state;                // {uid, first step with every hi <= tol, or 0}
+};
+hipError_t launch_stop_check(const StopArgs *args, int32_t n, hipStream_t s);
+constexpr int kBoundGrid = 256;            // grid points of the serving loop's checks
+constexpr double kLamLoFraction = 1e-12;   // serving: lower end of the bound interval / lambda_ub
 
 // estimate from psi: kind 0 mean, 1 sum, 2 Hutch++ (first n_sketch summed,
 // rest averaged); one estimate per graph from psi[g * ld + c], c < graph_m[g]

@@ -1059,6 +1059,7 @@ __device__ __forceinline__ void givens(double x, double y, double &c, double &s,
 
 struct LaneTri {
     double d0, d1, e0, e1, z0, z1;
+    double w0 = 0.0, w1 = 0.0;   // last row of the eigenvector matrix (LAST)
 };
 
 // Runs the QR iteration on the first n (<= 128) rows.  With RECORD, every
@@ -1067,7 +1068,7 @@ struct LaneTri {
 // bit 3 if the record overflowed.  The chase body has no branch: the rows
 // two ahead of the bulge (untouched by the sweep so far) are read while the
 // rotation is computed.
-template <bool RECORD, int NH>
+template <bool RECORD, int NH, bool LAST = false>
 __device__ int lane_tridiag_qr(LaneTri &t, int n, int lane, Rot *rot, int cap, int *nrot) {
     const double eps = 1.1102230246251565e-16;   // 2^-53
     int status = 0, cnt = 0;
@@ -1118,11 +1119,17 @@ __device__ int lane_tridiag_qr(LaneTri &t, int n, int lane, Rot *rot, int cap, i
         const double e_lo1 = get_row<NH>(t.e0, t.e1, lo + 1);
         double enx = lo + 1 < hi ? e_lo1 : 0.0;
         double zi = get_row<NH>(t.z0, t.z1, lo), zj = get_row<NH>(t.z0, t.z1, lo + 1);
+        double wi = 0.0, wj = 0.0;
+        if (LAST) {
+            wi = get_row<NH>(t.w0, t.w1, lo);
+            wj = get_row<NH>(t.w0, t.w1, lo + 1);
+        }
         double x = di - mu, y = ei;
         for (int i = lo; i < hi; ++i) {
             const int i2 = min(i + 2, 64 * NH - 1);
             const double dn = get_row<NH>(t.d0, t.d1, i2), en = get_row<NH>(t.e0, t.e1, i2);
             const double zn = get_row<NH>(t.z0, t.z1, i2);
+            const double wn = LAST ? get_row<NH>(t.w0, t.w1, i2) : 0.0;
             double c, sn, r;
             givens(x, y, c, sn, r);
             set_row<NH>(t.e0, t.e1, i > lo ? i - 1 : -1, r, lane);
@@ -1132,8 +1139,11 @@ __device__ int lane_tridiag_qr(LaneTri &t, int n, int lane, Rot *rot, int cap, i
             const double nei = fma(cs, dj - di, (cc - ss) * ei);
             const double nzi = fma(c, zi, sn * zj);
             const double nzj = fma(-sn, zi, c * zj);
+            const double nwi = fma(c, wi, sn * wj);
+            const double nwj = fma(-sn, wi, c * wj);
             set_row<NH>(t.d0, t.d1, i, ndi, lane);
             set_row<NH>(t.z0, t.z1, i, nzi, lane);
+            if (LAST) set_row<NH>(t.w0, t.w1, i, nwi, lane);
             if (RECORD) {
                 const int slot = cnt & 63;
                 rc = lane == slot ? c : rc;
@@ -1155,10 +1165,13 @@ __device__ int lane_tridiag_qr(LaneTri &t, int n, int lane, Rot *rot, int cap, i
             enx = i + 2 < hi ? en : 0.0;
             zi = nzj;
             zj = zn;
+            wi = nwj;
+            wj = wn;
         }
         set_row<NH>(t.d0, t.d1, hi, di, lane);
         set_row<NH>(t.e0, t.e1, hi - 1, x, lane);
         set_row<NH>(t.z0, t.z1, hi, zi, lane);
+        if (LAST) set_row<NH>(t.w0, t.w1, hi, wi, lane);
     }
     if (RECORD) {
         const int part = cnt & 63;
@@ -1192,11 +1205,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const double *beta,
                                                     const int32_t *k_eff, const double *norm2, int32_t k,
-                                                    int32_t m, double *psi, int32_t *flags) {
+                                                    int32_t steps, int32_t m, double *psi, int32_t *flags,
+                                                    const int2 *stop, int32_t uid) {
     const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (c >= m) return;
-    const int ke = __builtin_amdgcn_readfirstlane(k_eff[c]);
+    if (stop) {
+        const int2 st = *stop;
+        if (st.x == uid && st.y > 0) steps = min(steps, st.y);
+    }
+    const int ke = __builtin_amdgcn_readfirstlane(min(k_eff[c], steps));
     if (ke <= 0) {
         if (lane == 0) psi[c] = 0.0;
         return;
@@ -1215,12 +1233,151 @@ __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const d
     }
 }
 
+// ---------------------------------------------------------------------------
+// A-posteriori error bracket of Theorem 4.8 for the polynomial Krylov method
+// (K_m = I, h_{m+1} = beta_m e_m): with T_m = U diag(theta) U^T,
+// a_j = beta_m U[m-1, j], b_j = U[0, j], c_j = sum_{l != j} a_l b_l / (theta_j -
+// theta_l), eq. (4.8) is g_m(z) = sum_j (a_j b_j)^2 D2(z, theta_j) +
+// 2 a_j b_j c_j D1(z, theta_j) with the divided differences of f = -x log x
+// D1 = (f(z) - f(theta)) / (z - theta), D2 = (D1 - f'(theta)) / (z - theta).
+// With r = z / theta, t = r - 1: D1 = -log theta - (1 + t) log1p(t) / t and
+// D2 = q(t) / theta, q(t) = (t - (1 + t) log1p(t)) / t^2, by their Taylor
+// series for |t| < 1e-3 (the limits at z = theta are the ones eq. (4.8)
+// gives).  lo, hi = ||c||^2 min, max |g_m| over n_grid log-spaced points of
+// [lam_lo, lam_hi] and the Ritz values inside it; Ritz values below lam_lo
+// are raised to it.  A column whose recurrence stopped on a zero beta has an
+// invariant Krylov space and zero error.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void entropy_dd(double z, double th, double log_th, double inv_th, double &d1,
+                                           double &d2) {
+    const double t = fma(z, inv_th, -1.0);
+    double h, q;
+    if (fabs(t) < 1e-3) {
+        h = 1.0 + t * (0.5 + t * (-1.0 / 6.0 + t * (1.0 / 12.0 + t * (-1.0 / 20.0))));
+        q = -0.5 + t * (1.0 / 6.0 + t * (-1.0 / 12.0 + t * (1.0 / 20.0 + t * (-1.0 / 30.0))));
+    } else {
+        const double l1 = log1p(t);
+        const double it = 1.0 / t;
+        h = (1.0 + t) * l1 * it;
+        q = (t - (1.0 + t) * l1) * it * it;
+    }
+    d1 = -log_th - h;
+    d2 = q * inv_th;
+}
+
+template <int NH>
+__device__ void bound_column(const BoundArgs &a, int c, int lane) {
+    const int64_t base = (int64_t)c * a.k;
+    const int ke = __builtin_amdgcn_readfirstlane(a.k_eff[c]);
+    const int mm = min(ke, a.steps);
+    const double beta_m = mm > 0 ? a.beta[base + mm - 1] : 0.0;
+    if (mm <= 0 || beta_m == 0.0) {
+        if (lane == 0) {
+            a.lo[c] = 0.0;
+            a.hi[c] = 0.0;
+        }
+        return;
+    }
+    LaneTri t;
+    load_tri(t, a.alpha + base, a.beta + base, mm, lane);
+    t.w0 = lane == mm - 1 ? 1.0 : 0.0;
+    t.w1 = lane + 64 == mm - 1 ? 1.0 : 0.0;
+    const int st = lane_tridiag_qr<false, NH, true>(t, mm, lane, nullptr, 0, nullptr);
+    if (st && lane == 0) atomicOr(a.flags, st);
+    // per Ritz value (lane j, and j + 64): a_j b_j, c_j, the raised theta
+    double ab0 = lane < mm ? beta_m * t.w0 * t.z0 : 0.0;
+    double ab1 = lane + 64 < mm ? beta_m * t.w1 * t.z1 : 0.0;
+    double c0 = 0.0, c1 = 0.0;
+    for (int l = 0; l < mm; ++l) {
+        const double thl = get_row<NH>(t.d0, t.d1, l), abl = get_row<NH>(ab0, ab1, l);
+        if (l != lane) c0 += abl / (t.d0 - thl);
+        if (NH == 2 && l != lane + 64) c1 += abl / (t.d1 - thl);
+    }
+    const double th0 = fmax(t.d0, a.lam_lo), th1 = fmax(t.d1, a.lam_lo);
+    const double lg0 = log(th0), lg1 = log(th1), iv0 = 1.0 / th0, iv1 = 1.0 / th1;
+    const double ratio = log(a.lam_hi / a.lam_lo) / (double)max(a.n_grid - 1, 1);
+    double gmax = 0.0, gmin = INFINITY;
+    const int npts = a.n_grid + mm;
+    for (int p0 = 0; p0 < npts; p0 += 64) {
+        const int p = p0 + lane;
+        // grid point, or the Ritz value p - n_grid if it lies inside the interval
+        const int j = max(p - a.n_grid, 0);
+        const double s0 = __shfl(t.d0, j & 63, 64), s1 = __shfl(t.d1, j & 63, 64);
+        const double th = j < 64 ? s0 : s1;
+        const bool grid_pt = p < a.n_grid;
+        const double z = grid_pt ? (p == a.n_grid - 1 ? a.lam_hi : a.lam_lo * exp(ratio * (double)p)) : th;
+        const bool use = p < npts && (grid_pt || (th > a.lam_lo && th < a.lam_hi));
+        double g = 0.0;
+        for (int j = 0; j < mm; ++j) {
+            const double thj = get_row<NH>(th0, th1, j), lgj = get_row<NH>(lg0, lg1, j);
+            const double ivj = get_row<NH>(iv0, iv1, j), abj = get_row<NH>(ab0, ab1, j);
+            const double cj = get_row<NH>(c0, c1, j);
+            (void)thj;
+            double d1, d2;
+            entropy_dd(z, thj, lgj, ivj, d1, d2);
+            g = fma(abj * abj, d2, fma(2.0 * abj * cj, d1, g));
+        }
+        if (use) {
+            gmax = fmax(gmax, fabs(g));
+            gmin = fmin(gmin, fabs(g));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+        gmin = fmin(gmin, __shfl_xor(gmin, o, 64));
+    }
+    if (lane == 0) {
+        const double nb = a.norm2[c];
+        a.lo[c] = nb * gmin;
+        a.hi[c] = nb * gmax;
+    }
+}
+
+// entry e = {problem, column group}: columns 4 e.y .. 4 e.y + 3 of args[e.x]
+__global__ void __launch_bounds__(256) k_error_bound(const BoundArgs *args, const int2 *map) {
+    const int2 e = map[blockIdx.x];
+    const BoundArgs a = args[e.x];
+    const int c = __builtin_amdgcn_readfirstlane(e.y * 4 + (int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (c >= a.m) return;
+    const int ke = __builtin_amdgcn_readfirstlane(min(a.k_eff[c], a.steps));
+    if (ke <= 64) bound_column<1>(a, c, lane);
+    else bound_column<2>(a, c, lane);
+}
+
+hipError_t launch_error_bound(const BoundArgs *args, const int2 *map, int32_t n_entries, hipStream_t s) {
+    if (n_entries > 0) hipLaunchKernelGGL(k_error_bound, dim3(n_entries), dim3(256), 0, s, args, map);
+    return hipGetLastError();
+}
+
+// One block per problem: if every column's upper bound is within tol, the
+// first such step is recorded in state = {uid, stop step} (a state left by an
+// earlier owner of the memory, with another uid, is reset first).
+__global__ void __launch_bounds__(64) k_stop_check(const StopArgs *args) {
+    const StopArgs a = args[blockIdx.x];
+    bool ok = true;
+    for (int c = threadIdx.x; c < a.m; c += 64) ok = ok && a.hi[c] <= a.tol;
+    const bool all = __all(ok);
+    if (threadIdx.x != 0) return;
+    int2 st = *a.state;
+    if (st.x != a.uid) st = make_int2(a.uid, 0);
+    if (all && st.y == 0) st.y = a.step;
+    *a.state = st;
+}
+
+hipError_t launch_stop_check(const StopArgs *args, int32_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_stop_check, dim3(n), dim3(64), 0, s, args);
+    return hipGetLastError();
+}
+
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
-                             const double *norm2, int32_t k, int32_t m, double *psi, int32_t *flags,
-                             hipStream_t s) {
-    if (k > kMaxSteps) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_quadrature, dim3((m + 3) / 4), dim3(256), 0, s, alpha, beta, k_eff, norm2, k, m, psi,
-                       flags);
+                             const double *norm2, int32_t k, int32_t steps, int32_t m, double *psi,
+                             int32_t *flags, hipStream_t s, const int2 *stop, int32_t uid) {
+    if (k > kMaxSteps || steps < 1 || steps > k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_quadrature, dim3((m + 3) / 4), dim3(256), 0, s, alpha, beta, k_eff, norm2, k, steps, m,
+                       psi, flags, stop, uid);
     return hipGetLastError();
 }
 

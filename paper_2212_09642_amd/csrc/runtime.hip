@@ -565,7 +565,7 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
     if (tuning) return VNE_OK;
     if (timing) c->pending.push_back({p, bytes});
     HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p, (const int32_t *)p->k_eff.p,
-                                 (const double *)p->norm2.p, p->k, p->G * p->m_pad, (double *)p->psi.p,
+                                 (const double *)p->norm2.p, p->k, p->k, p->G * p->m_pad, (double *)p->psi.p,
                                  (int32_t *)p->flags.p, c->stream));
     return VNE_OK;
 }
@@ -1077,6 +1077,61 @@ extern "C" vne_status vne_entropy_estimate(vne_ctx *c, int32_t gid, const vne_pr
         return fail(c, VNE_EINVAL, "VNE_MODE_DESING needs a matrix whose rows sum to zero (A 1 = 0)");
     if (pr->kind == VNE_PROBE_HUTCHPP) return estimate_hutchpp(c, set, pr, k, fp64, desing, out);
     return estimate_set(c, set, pr, &k, fp64, desing, out);
+}
+
+extern "C" vne_status vne_error_bounds(vne_ctx *c, int32_t m, int32_t k, const double *alpha, const double *beta,
+                                       const int32_t *k_eff, const double *norm2, int32_t steps, double lam_lo,
+                                       double lam_hi, int32_t n_grid, double *lo, double *hi) {
+    if (!c) return VNE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lock(c->mu);
+    c->err.clear();
+    if (!alpha || !beta || !k_eff || !norm2 || !lo || !hi) return fail(c, VNE_EINVAL, "NULL argument");
+    if (m < 1 || k < 1 || k > kMaxSteps || steps < 1 || steps > k)
+        return fail(c, VNE_EINVAL, "need m >= 1, 1 <= steps <= k <= 128");
+    if (!(lam_lo > 0.0) || !(lam_hi > lam_lo) || !std::isfinite(lam_hi))
+        return fail(c, VNE_EINVAL, "need 0 < lam_lo < lam_hi");
+    if (n_grid < 2 || n_grid > (1 << 16)) return fail(c, VNE_EINVAL, "n_grid must be in [2, 65536]");
+    HIP_TRY(c, hipSetDevice(c->device));
+    DevBuf d_al, d_be, d_ke, d_nr, d_lo, d_hi, d_args, d_map, d_fl;
+    auto fin = [&](vne_status st) {
+        DevBuf *all[] = {&d_al, &d_be, &d_ke, &d_nr, &d_lo, &d_hi, &d_args, &d_map, &d_fl};
+        for (DevBuf *b : all) dev_free(c, b);
+        return st;
+    };
+    const int ng = (m + 3) / 4;
+    std::vector<int2> map(ng);
+    for (int i = 0; i < ng; ++i) map[i] = make_int2(0, i);
+    vne_status st = VNE_OK;
+    if ((st = upload(c, &d_al, alpha, (size_t)m * k)) != VNE_OK || (st = upload(c, &d_be, beta, (size_t)m * k)) != VNE_OK ||
+        (st = upload(c, &d_ke, k_eff, (size_t)m)) != VNE_OK || (st = upload(c, &d_nr, norm2, (size_t)m)) != VNE_OK ||
+        (st = dev_alloc(c, &d_lo, (size_t)m * 8)) != VNE_OK || (st = dev_alloc(c, &d_hi, (size_t)m * 8)) != VNE_OK ||
+        (st = upload(c, &d_map, map.data(), map.size())) != VNE_OK || (st = dev_alloc(c, &d_fl, 4)) != VNE_OK)
+        return fin(st);
+    BoundArgs a{};
+    a.alpha = (const double *)d_al.p;
+    a.beta = (const double *)d_be.p;
+    a.k_eff = (const int32_t *)d_ke.p;
+    a.norm2 = (const double *)d_nr.p;
+    a.k = k;
+    a.m = m;
+    a.steps = steps;
+    a.lam_lo = lam_lo;
+    a.lam_hi = lam_hi;
+    a.n_grid = n_grid;
+    a.lo = (double *)d_lo.p;
+    a.hi = (double *)d_hi.p;
+    a.flags = (int32_t *)d_fl.p;
+    if ((st = upload(c, &d_args, &a, 1)) != VNE_OK) return fin(st);
+    int32_t fl = 0;
+    hipError_t e = hipMemsetAsync(d_fl.p, 0, 4, c->stream);
+    if (e == hipSuccess) e = launch_error_bound((const BoundArgs *)d_args.p, (const int2 *)d_map.p, ng, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(lo, d_lo.p, (size_t)m * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hi, d_hi.p, (size_t)m * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&fl, d_fl.p, 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fin(hip_fail(c, e, "error bound kernel"));
+    fin(VNE_OK);
+    return check_flags(c, fl);
 }
 
 extern "C" vne_status vne_entropy_estimate_batch(vne_ctx *c, int32_t n_queries, const int32_t *graph_ids,

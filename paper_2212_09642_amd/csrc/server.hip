@@ -12,10 +12,13 @@
 // so a query gives the same bits alone and in any mix.
 //
 // With rel_eps > 0 a query first runs a pilot of pilot_probes columns; the
-// step count comes from the a-priori bound of Proposition 4.4 with Remark 2.3
+// step cap comes from the a-priori bound of Proposition 4.4 with Remark 2.3
 // (lambda_max from a Gershgorin bound, S(A) from below by -log tr(A^2)), the
 // probe count from the pilot's sample standard deviation (Remarks 5.1, 5.2:
-// half of the relative budget each).
+// half of the relative budget each).  A task stops earlier at the first
+// checked step at which the a-posteriori upper bound of Theorem 4.8 meets the
+// same per-form target for all its probes; the device records that step and
+// the quadrature uses it, whenever the host learns of it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,6 +59,12 @@ struct SrvTask {
     double *norm2 = nullptr, *mean = nullptr, *partials = nullptr, *probe_part = nullptr;
     double *seg_acc = nullptr, *long_part = nullptr, *level2 = nullptr;
     int32_t *k_eff = nullptr;
+    // a-posteriori stopping (queries with rel_eps > 0)
+    bool adaptive = false;
+    double tol = 0.0;                // per quadratic form
+    int32_t uid = 0, slot = -1;      // mailbox entry while running
+    double *b_lo = nullptr, *b_hi = nullptr;
+    int2 *d_state = nullptr;         // {uid, first step within tol}
 };
 
 struct SrvQuery {
@@ -68,6 +77,7 @@ struct SrvQuery {
     bool planned = false, started = false;
     bool pilot_wait = false, final_wait = false, done = false;
     double s_lower = 0.0, bound = 0.0;
+    int steps_used = 0;              // largest step count a task of the query used
     uint64_t off = 0;                // arena block: psi [cap], estimate, flags
     double *d_psi = nullptr, *d_est = nullptr;
     int32_t *d_flags = nullptr;
@@ -113,6 +123,9 @@ struct vne_server {
     int ring_pos = 0;
     char *d_desc = nullptr;
     size_t d_desc_cap = 0;
+    int2 *mailbox = nullptr;                         // pinned [max_slots]: stop records
+    std::vector<int> free_slots;
+    int32_t next_uid = 1;
 
     // statistics (worker-owned; snap is the copy readers see)
     int64_t ticks = 0, tasks_admitted = 0, queries_done = 0;
@@ -151,6 +164,7 @@ size_t task_bytes(const GraphSet *set, int m_pad, int k, bool fp64) {
     b += rnd((size_t)std::max(1, sc.n_seg) * m_pad * 8);
     b += rnd((size_t)std::max(1, sc.n_long) * 3 * m_pad * 8);
     b += rnd((size_t)kSlotLevel2 * 3 * m_pad * 8);
+    b += 2 * rnd((size_t)m_pad * 8) + 256;
     return b;
 }
 
@@ -181,6 +195,9 @@ void carve(SrvTask &t, char *base, const GraphSet *set, bool fp64) {
     t.seg_acc = (double *)take((size_t)std::max(1, sc.n_seg) * t.m_pad * 8);
     t.long_part = (double *)take((size_t)std::max(1, sc.n_long) * 3 * t.m_pad * 8);
     t.level2 = (double *)take((size_t)kSlotLevel2 * 3 * t.m_pad * 8);
+    t.b_lo = (double *)take((size_t)t.m_pad * 8);
+    t.b_hi = (double *)take((size_t)t.m_pad * 8);
+    t.d_state = (int2 *)take(256);
 }
 
 // Tasks for columns [c0, c1) of a query, in the pending queue after every
@@ -206,6 +223,8 @@ void add_tasks(vne_server *s, SrvQuery &q, int c0, int c1, bool pilot) {
         t.k = q.k;
         t.col0 = c;
         t.pilot = pilot;
+        t.adaptive = q.q.rel_eps > 0.0 && q.s_lower > 0.0;
+        t.tol = 0.5 * q.q.rel_eps * q.s_lower;
         t.bytes = task_bytes(q.set, t.m_pad, t.k, s->fp64);
         ts.push_back(t);
         c += w;
@@ -255,7 +274,7 @@ void finish_query(vne_server *s, SrvQuery &q, vne_status st, const std::string &
     q.res.status = st;
     std::snprintf(q.res.message, sizeof(q.res.message), "%s", msg.c_str());
     q.res.probes = q.N;
-    q.res.steps = q.k;
+    q.res.steps = q.steps_used > 0 ? q.steps_used : q.k;
     q.res.quad_bound = q.bound;
     q.res.queue_ms = q.started ? ms_between(q.t_submit, q.t_admit) : 0.0;
     q.res.latency_ms = ms_between(q.t_submit, q.t_done);
@@ -389,6 +408,10 @@ vne_status admit(vne_server *s) {
         s->arena_peak = std::max(s->arena_peak, s->arena.in_use());
         s->pending.pop_front();
         carve(t, (char *)s->arena_mem.p + t.off, q->set, s->fp64);
+        t.uid = s->next_uid++;
+        t.slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        SRV_HIP(s, hipMemsetAsync(t.d_state, 0, sizeof(int2), s->stream));
         // probe block (the query's hash columns col0.., eq. (3.8)) and zero v_0
         const GraphSet *set = q->set;
         ProbeArgs pa{};
@@ -483,6 +506,30 @@ FinalizeArgs fin_args(const vne_server *s, const SrvTask &t, const GraphSet *set
     return f;
 }
 
+// Quadrature of a task after `steps` steps, its memory and mailbox entry
+// back, and the query's next stage when it was the query's last task.
+vne_status end_task(vne_server *s, SrvTask &t, SrvQuery &q, int steps) {
+    // an adaptive task's own stop record (if the device made one) decides the
+    // step count, whenever the host noticed it
+    SRV_HIP(s, launch_quadrature(t.alpha, t.beta, t.k_eff, t.norm2, t.k, steps, t.m, q.d_psi + t.col0, q.d_flags,
+                                 s->stream, t.adaptive ? t.d_state : nullptr, t.uid));
+    s->arena.release(t.off);
+    s->free_slots.push_back(t.slot);
+    q.steps_used = std::max(q.steps_used, steps);
+    q.tasks_open--;
+    if (q.tasks_open > 0) return VNE_OK;
+    if (!q.planned) {
+        // pilot done: its psi and the flags to the host
+        SRV_HIP(s, hipMemcpyAsync(q.h_buf, q.d_psi, (size_t)q.cols_issued * 8, hipMemcpyDeviceToHost, s->stream));
+        SRV_HIP(s, hipMemcpyAsync(q.h_buf + s->psi_cap + 1, q.d_flags, 4, hipMemcpyDeviceToHost, s->stream));
+        SRV_HIP(s, hipEventRecord(q.ev, s->stream));
+        q.pilot_wait = true;
+    } else if (q.cols_issued == q.N) {
+        VNE_TRY(issue_final(s, q));
+    }
+    return VNE_OK;
+}
+
 // One Lanczos step of every active slot.
 vne_status tick(vne_server *s) {
     const int A = (int)s->active.size();
@@ -511,7 +558,45 @@ vne_status tick(vne_server *s) {
         }
         for (int ch = 0; ch < (t.m_pad + kFinalizeCols - 1) / kFinalizeCols; ++ch) fmap.push_back(make_int2(i, ch));
     }
+    // a-posteriori checks (Theorem 4.8) of adaptive tasks after this step:
+    // from step 3 on, every other step
+    std::vector<BoundArgs> ba;
+    std::vector<StopArgs> sta;
+    std::vector<int2> bmap;
+    std::vector<int> checked;
+    for (int i = 0; i < A; ++i) {
+        const SrvTask &t = s->active[i];
+        const int j = t.j + 1;
+        if (!t.adaptive || j < 3 || j % 2 == 0 || j >= t.k) continue;
+        const Graph *g = qs[i]->g;
+        BoundArgs b{};
+        b.alpha = t.alpha;
+        b.beta = t.beta;
+        b.k_eff = t.k_eff;
+        b.norm2 = t.norm2;
+        b.k = t.k;
+        b.m = t.m;
+        b.steps = j;
+        b.lam_hi = g->lambda_ub;
+        b.lam_lo = g->lambda_ub * kLamLoFraction;
+        b.n_grid = kBoundGrid;
+        b.lo = t.b_lo;
+        b.hi = t.b_hi;
+        b.flags = qs[i]->d_flags;
+        for (int grp = 0; grp < (t.m + 3) / 4; ++grp) bmap.push_back(make_int2((int)ba.size(), grp));
+        ba.push_back(b);
+        StopArgs sc{};
+        sc.hi = t.b_hi;
+        sc.m = t.m;
+        sc.tol = t.tol;
+        sc.step = j;
+        sc.uid = t.uid;
+        sc.state = t.d_state;
+        sta.push_back(sc);
+        checked.push_back(i);
+    }
     size_t bytes = rnd(sizeof(StepArgs) * A) + rnd(sizeof(FinalizeArgs) * A) + rnd(sizeof(int2) * fmap.size());
+    bytes += rnd(sizeof(BoundArgs) * ba.size()) + rnd(sizeof(int2) * bmap.size()) + rnd(sizeof(StopArgs) * sta.size());
     for (auto &kv : smap) bytes += rnd(sizeof(int4) * kv.second.size());
     for (auto &kv : lmap) bytes += rnd(sizeof(int4) * kv.second.size());
     // staging ring: wait until the copy that last used this slot has run
@@ -548,6 +633,9 @@ vne_status tick(vne_server *s) {
     std::map<int, const int4 *> d_sm, d_lm;
     for (auto &kv : smap) d_sm[kv.first] = (const int4 *)put(kv.second.data(), sizeof(int4) * kv.second.size());
     for (auto &kv : lmap) d_lm[kv.first] = (const int4 *)put(kv.second.data(), sizeof(int4) * kv.second.size());
+    const BoundArgs *d_ba = (const BoundArgs *)put(ba.data(), sizeof(BoundArgs) * ba.size());
+    const int2 *d_bm = (const int2 *)put(bmap.data(), sizeof(int2) * bmap.size());
+    const StopArgs *d_st = (const StopArgs *)put(sta.data(), sizeof(StopArgs) * sta.size());
     SRV_HIP(s, hipMemcpyAsync(s->d_desc, h, off, hipMemcpyHostToDevice, s->stream));
     SRV_HIP(s, hipEventRecord(s->ring_ev[r], s->stream));
     s->ring_used[r] = true;
@@ -559,32 +647,34 @@ vne_status tick(vne_server *s) {
                                      mt, s->fp64, s->stream));
     }
     SRV_HIP(s, launch_finalize_slots(d_fa, d_fm, (int32_t)fmap.size(), s->stream));
+    if (!sta.empty()) {
+        SRV_HIP(s, launch_error_bound(d_ba, d_bm, (int32_t)bmap.size(), s->stream));
+        SRV_HIP(s, launch_stop_check(d_st, (int32_t)sta.size(), s->stream));
+        for (int i : checked) {
+            const SrvTask &t = s->active[i];
+            SRV_HIP(s, hipMemcpyAsync(s->mailbox + t.slot, t.d_state, sizeof(int2), hipMemcpyDeviceToHost,
+                                      s->stream));
+        }
+    }
     s->ticks++;
     s->occupancy_sum += A;
-    // tasks that took their last step: quadrature (eq. (4.2)) into the query's psi
+    // tasks at their step cap, and adaptive tasks whose recorded stop step
+    // has reached the host, end: quadrature (eq. (4.2)) into the query's psi
     std::vector<SrvTask> keep;
     for (int i = 0; i < A; ++i) {
         SrvTask &t = s->active[i];
-        SrvQuery &q = *qs[i];
         t.j++;
-        if (t.j < t.k) {
+        int use = t.j >= t.k ? t.k : 0;
+        if (!use && t.adaptive) {
+            const volatile int2 *mb = s->mailbox + t.slot;
+            const int u = mb->x, st = mb->y;
+            if (u == t.uid && st > 0) use = st;
+        }
+        if (!use) {
             keep.push_back(t);
             continue;
         }
-        SRV_HIP(s, launch_quadrature(t.alpha, t.beta, t.k_eff, t.norm2, t.k, t.m, q.d_psi + t.col0, q.d_flags,
-                                     s->stream));
-        s->arena.release(t.off);
-        q.tasks_open--;
-        if (q.tasks_open > 0) continue;
-        if (!q.planned) {
-            // pilot done: its psi and the flags to the host
-            SRV_HIP(s, hipMemcpyAsync(q.h_buf, q.d_psi, (size_t)q.cols_issued * 8, hipMemcpyDeviceToHost, s->stream));
-            SRV_HIP(s, hipMemcpyAsync(q.h_buf + s->psi_cap + 1, q.d_flags, 4, hipMemcpyDeviceToHost, s->stream));
-            SRV_HIP(s, hipEventRecord(q.ev, s->stream));
-            q.pilot_wait = true;
-        } else if (q.cols_issued == q.N) {
-            VNE_TRY(issue_final(s, q));
-        }
+        VNE_TRY(end_task(s, t, *qs[i], use));
     }
     s->active.swap(keep);
     return VNE_OK;
@@ -607,8 +697,9 @@ void start_query(vne_server *s, SrvQuery &q) {
         q.s_lower = density ? -std::log(g->fro2) : 0.0;
         q.k = density ? plan_steps((double)g->n, g->lambda_ub, q.s_lower, q.q.rel_eps, 0.5, s->cfg.max_steps)
                       : s->cfg.max_steps;
-        const double d = 2.0 * q.k - 1.0;
-        q.bound = 2.0 * (double)g->n * g->lambda_ub / (4.0 * (d * d - 1.0));
+        // per-form target: the a-priori bound at k meets it, and adaptive
+        // tasks stop once the a-posteriori bound does
+        q.bound = density ? 0.5 * q.q.rel_eps * q.s_lower : 0.0;
         q.N = std::min(s->cfg.pilot_probes, s->psi_cap);
         add_tasks(s, q, 0, q.N, true);
     } else {
@@ -737,6 +828,10 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
         e = hipEventCreateWithFlags(&s->ring_ev[r], hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
     }
+    e = hipHostMalloc((void **)&s->mailbox, sizeof(int2) * k.max_slots, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc");
+    std::memset(s->mailbox, 0, sizeof(int2) * k.max_slots);
+    for (int i = k.max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     vne_server *raw = s.release();
     raw->worker = std::thread(worker_loop, raw);
     *out = raw;
@@ -834,6 +929,7 @@ extern "C" vne_status vne_server_stop(vne_server *s) {
         if (s->ring_ev[r]) (void)hipEventDestroy(s->ring_ev[r]);
     }
     if (s->d_desc) (void)hipFree(s->d_desc);
+    if (s->mailbox) (void)hipHostFree(s->mailbox);
     dev_free(c, &s->arena_mem);
     (void)hipStreamDestroy(s->stream);
     delete s;

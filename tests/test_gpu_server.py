@@ -84,6 +84,28 @@ def test_server_same_bits_alone_and_in_a_mix(ctx, pool):
     assert info["slot_occupancy"] > 1.0
 
 
+def test_server_adaptive_same_bits_alone_and_in_a_mix(ctx, pool):
+    """rel_eps queries stop on the a-posteriori bound; the step the device
+    records decides the result, so a query alone and in a mix agree bitwise."""
+    _say("case server: adaptive query alone and in a mix")
+    gid, ref = pool[1]
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+        alone = srv.poll(srv.submit(gid, rel_eps=1e-3, seed=5), want_quad=True)
+        tickets = []
+        for i in range(10):
+            tickets.append(srv.submit(pool[i % len(pool)][0], rel_eps=1e-3, seed=100 + i))
+            if i == 4:
+                mine = srv.submit(gid, rel_eps=1e-3, seed=5)
+            time.sleep(0.001)
+        mixed = srv.poll(mine, want_quad=True)
+        others = [srv.poll(t) for t in tickets]
+    assert alone["status"] == 0 and mixed["status"] == 0 and all(o["status"] == 0 for o in others)
+    _say("  steps %d, probes %d" % (alone["steps"], alone["probes"]))
+    assert alone["probes"] == mixed["probes"]
+    assert np.array_equal(alone["quad"], mixed["quad"])
+    assert alone["estimate"] == mixed["estimate"]
+
+
 def test_server_admission_under_small_arena(ctx, pool):
     _say("case server: admission with an arena for about two tasks")
     gid, ref = pool[5]                       # n = 20000
@@ -121,9 +143,10 @@ def test_server_error_rule_accuracy(ctx):
         lam_ub = np.abs(rho).sum(1).max()
         k_want = vne.plan_steps(float(ref.n), lam_ub, -np.log((rho * rho).sum()), 1e-3, 0.5, 100)
         err = abs(r["estimate"] - S) / S
-        _say("  n=%d N=%d k=%d rel err %.2e (std err %.2e)" % (ref.n, r["probes"], r["steps"], err,
-                                                             r["std_error"] / S))
-        assert r["status"] == 0 and r["steps"] == k_want and r["probes"] >= 16
+        _say("  n=%d N=%d k=%d (a-priori %d) rel err %.2e (std err %.2e)"
+             % (ref.n, r["probes"], r["steps"], k_want, err, r["std_error"] / S))
+        # the a-priori count is the cap; the a-posteriori bound stops earlier
+        assert r["status"] == 0 and 3 <= r["steps"] <= k_want and r["probes"] >= 16
         assert len(r["quad"]) == r["probes"]
         errs.append(err)
     # the rule targets 1e-3 with probability 1 - 1e-2 per query
