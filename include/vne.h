@@ -291,7 +291,9 @@ vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, dou
  * pilot_probes columns runs first; N = ceil((z sd / ((rel_eps / 2) mean))^2)
  * over its quadratic forms, clamped to [pilot_probes, max_probes] and, when
  * above the pilot, rounded up to whole groups of 16 columns; the pilot's
- * forms are kept and columns pilot_probes..N-1 follow.  Tasks are max_cols
+ * forms are kept and columns pilot_probes..N-1 follow.  After each stage the
+ * count is planned again from all forms so far (up to 4 plans), so that the
+ * realized spread, not only the pilot's, meets the target.  Tasks are max_cols
  * wide while that much is left, then powers of two of at least 16 columns.
  *
  * Thread safety: submit, poll and stats may be called from any thread.

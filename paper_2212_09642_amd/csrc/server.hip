@@ -75,9 +75,10 @@ struct SrvQuery {
     int N = 0, k = 0;                // planned probes and steps
     int cols_issued = 0, tasks_open = 0;
     bool planned = false, started = false;
-    bool pilot_wait = false, final_wait = false, done = false;
+    bool stage_wait = false, final_wait = false, done = false;
     double s_lower = 0.0, bound = 0.0;
     int steps_used = 0;              // largest step count a task of the query used
+    int rounds = 0;                  // probe-count plans made (rel_eps > 0)
     uint64_t off = 0;                // arena block: psi [cap], estimate, flags
     double *d_psi = nullptr, *d_est = nullptr;
     int32_t *d_flags = nullptr;
@@ -150,6 +151,8 @@ vne_status srv_hip(vne_server *s, hipError_t e, const char *what) {
     } while (0)
 
 size_t rnd(size_t b) { return (b + 255) / 256 * 256; }
+
+constexpr int kPlanRounds = 4;   // probe-count plans of a rel_eps query (pilot included)
 
 // Arena bytes of a task of width m_pad and k steps on a graph.
 size_t task_bytes(const GraphSet *set, int m_pad, int k, bool fp64) {
@@ -299,7 +302,7 @@ void fail_query(vne_server *s, SrvQuery &q, vne_status st, const std::string &ms
     s->pending.erase(std::remove_if(s->pending.begin(), s->pending.end(),
                                     [&](const SrvTask &t) { return t.ticket == q.ticket; }),
                      s->pending.end());
-    q.pilot_wait = q.final_wait = false;
+    q.stage_wait = q.final_wait = false;
     finish_query(s, q, st, msg);
 }
 
@@ -334,7 +337,7 @@ vne_status poll_events(vne_server *s, bool block_one) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto &kv : s->queries)
-            if (kv.second->pilot_wait || kv.second->final_wait) waiting.push_back(kv.second.get());
+            if (kv.second->stage_wait || kv.second->final_wait) waiting.push_back(kv.second.get());
     }
     bool blocked = false;
     for (SrvQuery *q : waiting) {
@@ -346,8 +349,8 @@ vne_status poll_events(vne_server *s, bool block_one) {
         if (e == hipErrorNotReady) continue;
         if (e != hipSuccess) return srv_hip(s, e, "hipEventQuery");
         int32_t fl = 0;
-        if (q->pilot_wait) {
-            q->pilot_wait = false;
+        if (q->stage_wait) {
+            q->stage_wait = false;
             const int n0 = q->cols_issued;
             std::memcpy(&fl, q->h_buf + s->psi_cap + 1, 4);
             if (fl) {
@@ -359,13 +362,16 @@ vne_status poll_events(vne_server *s, bool block_one) {
             mean /= n0;
             for (int i = 0; i < n0; ++i) var += (q->h_buf[i] - mean) * (q->h_buf[i] - mean);
             const double sd = n0 > 1 ? std::sqrt(var / (n0 - 1)) : 0.0;
-            // the rule's N, rounded up to whole 16-column groups: the extra
-            // columns would be computed as padding anyway, and more probes
-            // only tighten the estimate
-            q->N = plan_probes(mean, sd, q->q.rel_eps, 0.5, s->cfg.z, n0, s->psi_cap);
-            if (q->N > n0) q->N = std::min(s->psi_cap, n0 + (q->N - n0 + 15) / 16 * 16);
+            // the rule's N from every form so far (sequential sampling: the
+            // count is planned again after each stage), rounded up to whole
+            // 16-column groups: the extra columns would be computed as
+            // padding anyway, and more probes only tighten the estimate
+            int nn = plan_probes(mean, sd, q->q.rel_eps, 0.5, s->cfg.z, n0, s->psi_cap);
+            if (nn > n0) nn = std::min(s->psi_cap, n0 + (nn - n0 + 15) / 16 * 16);
+            q->rounds++;
             q->planned = true;
-            if (q->N > n0) add_tasks(s, *q, n0, q->N, false);
+            q->N = nn;
+            if (nn > n0) add_tasks(s, *q, n0, nn, false);
             else VNE_TRY(issue_final(s, *q));
         } else {
             q->final_wait = false;
@@ -518,13 +524,15 @@ vne_status end_task(vne_server *s, SrvTask &t, SrvQuery &q, int steps) {
     q.steps_used = std::max(q.steps_used, steps);
     q.tasks_open--;
     if (q.tasks_open > 0) return VNE_OK;
-    if (!q.planned) {
-        // pilot done: its psi and the flags to the host
+    if (q.q.rel_eps > 0.0 && q.rounds < kPlanRounds && q.cols_issued < s->psi_cap) {
+        // a stage of a rel_eps query done: its forms and the flags to the
+        // host, which plans the probe count again from all forms so far
         SRV_HIP(s, hipMemcpyAsync(q.h_buf, q.d_psi, (size_t)q.cols_issued * 8, hipMemcpyDeviceToHost, s->stream));
         SRV_HIP(s, hipMemcpyAsync(q.h_buf + s->psi_cap + 1, q.d_flags, 4, hipMemcpyDeviceToHost, s->stream));
         SRV_HIP(s, hipEventRecord(q.ev, s->stream));
-        q.pilot_wait = true;
-    } else if (q.cols_issued == q.N) {
+        q.stage_wait = true;
+    } else {
+        q.N = q.cols_issued;
         VNE_TRY(issue_final(s, q));
     }
     return VNE_OK;
@@ -683,7 +691,7 @@ vne_status tick(vne_server *s) {
 bool has_waits(vne_server *s) {
     std::lock_guard<std::mutex> lk(s->mu);
     for (auto &kv : s->queries)
-        if (kv.second->pilot_wait || kv.second->final_wait) return true;
+        if (kv.second->stage_wait || kv.second->final_wait) return true;
     return false;
 }
 
@@ -731,7 +739,7 @@ void worker_loop(vne_server *s) {
             std::unique_lock<std::mutex> lk(s->mu);
             const bool idle = s->incoming.empty() && s->pending.empty() && s->active.empty();
             bool waits = false;
-            for (auto &kv : s->queries) waits = waits || kv.second->pilot_wait || kv.second->final_wait;
+            for (auto &kv : s->queries) waits = waits || kv.second->stage_wait || kv.second->final_wait;
             if (idle && !waits) {
                 if (s->stopping) break;
                 s->cv_work.wait(lk);
@@ -747,7 +755,7 @@ void worker_loop(vne_server *s) {
                 const std::string msg = s->broken_msg;
                 lk.unlock();
                 for (SrvQuery *q : open) {
-                    q->pilot_wait = q->final_wait = false;
+                    q->stage_wait = q->final_wait = false;
                     q->started = false;
                     finish_query(s, *q, VNE_EDEVICE, msg);
                 }
