@@ -198,8 +198,9 @@ hipError_t launch_reconstruct(const void *Vstore, bool fp64, int64_t step_stride
                               const double *S, const double *norm2, int32_t k, int32_t n,
                               int32_t m, void *Y, int32_t ldy, hipStream_t s);
 
-// out[a*nb + b] = sum_i X[i*ldx + a] * Y[i*ldy + b] (FP64 accumulation);
-// uses part (scratch, [chunks][na][nb] doubles, see gram_scratch_doubles)
+// out[a*nb + b] = sum_i X[i*ldx + a] * Y[i*ldy + b] (FP64 accumulation),
+// na <= 128, any nb; uses part (scratch, [chunks][na][nb] doubles, see
+// gram_scratch_doubles)
 int64_t gram_scratch_doubles(int32_t n, int32_t na, int32_t nb);
 hipError_t launch_gram(const void *X, int32_t ldx, const void *Y, int32_t ldy, bool fp64,
                        int32_t n, int32_t na, int32_t nb, double *part, double *out,
@@ -207,8 +208,8 @@ hipError_t launch_gram(const void *X, int32_t ldx, const void *Y, int32_t ldy, b
 // upper Cholesky factor of G (na x na, FP64, na <= 128) and its inverse Rinv;
 // flags bit 1 when a pivot is not positive
 hipError_t launch_cholinv(double *G, double *Rinv, int32_t na, int32_t *flags, hipStream_t s);
-// Z[i*ldz + b] = (sub ? Z[i*ldz + b] : 0) + sign * sum_a X[i*ldx + a] * M[a*nb + b]
-// (row-local: in place when Z aliases X is allowed only for sub == 0)
+// Z[i*ldz + b] = (sub ? Z[i*ldz + b] - s : s), s = sum_a X[i*ldx + a] * M[a*nb + b],
+// na <= 128; row-local: Z may alias X only for sub == 0, which needs nb <= 128
 hipError_t launch_apply(const void *X, int32_t ldx, const double *M, int32_t na, int32_t nb,
                         void *Z, int32_t ldz, bool fp64, int32_t n, int32_t sub,
                         hipStream_t s);

@@ -95,6 +95,12 @@ constexpr bool kNT = VNE_STREAM_NT != 0;
 template <int LPR>
 constexpr int gather_batch() { return VNE_GATHER_U > 0 ? VNE_GATHER_U : (LPR >= 16 ? 16 : 8); }
 
+// basis steps of k_reconstruct in flight per thread (2 measured faster than 4:
+// at 4 the register count halves the waves per SIMD)
+#ifndef VNE_RECON_UJ
+#define VNE_RECON_UJ 2
+#endif
+
 // minimum waves per SIMD requested for the step kernels (0: compiler's choice)
 #ifndef VNE_STEP_WAVES
 #define VNE_STEP_WAVES 0
@@ -1503,12 +1509,13 @@ hipError_t launch_combine(const double *psi, int32_t m, int32_t kind, int32_t n_
 
 // Y[i, c] = ||c_c|| sum_j S[j, c] v_j[i, c] (eq. (4.3)).  Thread layout: CPL
 // consecutive columns of RPT rows; a block covers 256 / (m_pad / CPL) * RPT
-// rows and streams the stored basis a few steps at a time.
+// rows and streams the stored basis (read once: non-temporal) a few steps at
+// a time.
 template <typename T, int CPL>
 __global__ void __launch_bounds__(256) k_reconstruct(const T *V, int64_t stride, int32_t ldv,
                                                      const double *S, const double *norm2,
                                                      int32_t k, int32_t n, int32_t m, T *Y, int32_t ldy) {
-    constexpr int RPT = 4, UJ = 2;
+    constexpr int RPT = 4, UJ = VNE_RECON_UJ;
     const int groups = (m + CPL - 1) / CPL;            // column groups per row
     const int rows_per_pass = 256 / groups;
     if ((int)threadIdx.x >= rows_per_pass * groups) return;
@@ -1534,7 +1541,7 @@ __global__ void __launch_bounds__(256) k_reconstruct(const T *V, int64_t stride,
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int64_t r = rbase + (int64_t)q * rows_per_pass;
-                if (jok && ok[q]) load_vec<T, CPL>(V + (int64_t)(j + t) * stride + r * ldv + c0, vb[t][q]);
+                if (jok && ok[q]) load_vec_nt<T, CPL>(V + (int64_t)(j + t) * stride + r * ldv + c0, vb[t][q]);
                 else
 #pragma unroll
                     for (int u = 0; u < CPL; ++u) vb[t][q][u] = (T)0;
@@ -1575,64 +1582,61 @@ hipError_t launch_reconstruct(const void *Vstore, bool fp64, int64_t step_stride
     return hipGetLastError();
 }
 
-// Gram X^T Y: a block computes a 64 x 64 tile of outputs over a chunk of
-// rows; each thread owns a 4 x 4 sub-tile; rows are staged through LDS 32 at
-// a time.  Products of FP32 inputs are exact in FP64; accumulation is FP64.
-constexpr int kGramTile = 64;
-constexpr int kGramChunk = 2048;
+// Gram X^T Y (na, nb <= 128): a block computes the whole na x nb product over
+// a chunk of rows; each thread owns an 8 x 8 sub-tile; 32 rows at a time are
+// staged through LDS in FP64.  Products of FP32 inputs are exact in FP64;
+// accumulation is FP64; the chunk partials are added in chunk order.
+constexpr int kGramRows = 512;   // rows per chunk
 
 int64_t gram_scratch_doubles(int32_t n, int32_t na, int32_t nb) {
-    const int64_t chunks = (n + kGramChunk - 1) / kGramChunk;
+    const int64_t chunks = (n + kGramRows - 1) / kGramRows;
     return chunks * (int64_t)na * nb;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_gram(const T *X, int32_t ldx, const T *Y, int32_t ldy, int32_t n,
-                                              int32_t na, int32_t nb, double *part) {
+                                              int32_t na, int32_t nb, double *part, int64_t part_stride,
+                                              int32_t ldo) {
     constexpr int RS = 32;
-    __shared__ double xs[RS][kGramTile];
-    __shared__ double ys[RS][kGramTile];
-    const int ta = blockIdx.x * kGramTile, tb = blockIdx.y * kGramTile;
-    const int chunk = blockIdx.z;
-    const int64_t r0 = (int64_t)chunk * kGramChunk;
-    const int64_t r1 = min((int64_t)n, r0 + kGramChunk);
-    const int oa = (threadIdx.x / 16) * 4;    // 0..60
-    const int ob = (threadIdx.x % 16) * 4;    // 0..60
-    double acc[4][4];
+    __shared__ double xs[RS][128];
+    __shared__ double ys[RS][128];
+    const int chunk = blockIdx.x;
+    const int64_t r0 = (int64_t)chunk * kGramRows;
+    const int64_t r1 = min((int64_t)n, r0 + kGramRows);
+    const int a0 = (threadIdx.x / 16) * 8, b0 = (threadIdx.x % 16) * 8;
+    double acc[8][8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
     for (int64_t rs = r0; rs < r1; rs += RS) {
-        for (int q = threadIdx.x; q < RS * kGramTile; q += 256) {
-            const int rr = q / kGramTile, cc = q % kGramTile;
+        for (int q = threadIdx.x; q < RS * 128; q += 256) {
+            const int rr = q / 128, cc = q % 128;
             const int64_t r = rs + rr;
-            xs[rr][cc] = (r < r1 && ta + cc < na) ? (double)X[r * ldx + ta + cc] : 0.0;
-            ys[rr][cc] = (r < r1 && tb + cc < nb) ? (double)Y[r * ldy + tb + cc] : 0.0;
+            xs[rr][cc] = (r < r1 && cc < na) ? (double)X[r * ldx + cc] : 0.0;
+            ys[rr][cc] = (r < r1 && cc < nb) ? (double)Y[r * ldy + cc] : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
         for (int rr = 0; rr < RS; ++rr) {
-            double xa[4], yb[4];
+            double xa[8], yb[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                xa[u] = xs[rr][oa + u];
-                yb[u] = ys[rr][ob + u];
+            for (int u = 0; u < 8; ++u) {
+                xa[u] = xs[rr][a0 + u];
+                yb[u] = ys[rr][b0 + u];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 8; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(xa[u], yb[v], acc[u][v]);
+                for (int v = 0; v < 8; ++v) acc[u][v] = fma(xa[u], yb[v], acc[u][v]);
         }
         __syncthreads();
     }
-    double *out = part + (int64_t)chunk * na * nb;
+    double *out = part + (int64_t)chunk * part_stride;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            if (ta + oa + u < na && tb + ob + v < nb)
-                out[(int64_t)(ta + oa + u) * nb + tb + ob + v] = acc[u][v];
+        for (int v = 0; v < 8; ++v)
+            if (a0 + u < na && b0 + v < nb) out[(int64_t)(a0 + u) * ldo + b0 + v] = acc[u][v];
 }
 
 __global__ void __launch_bounds__(256) k_gram_reduce(const double *part, int64_t chunks, int64_t total,
@@ -1646,30 +1650,33 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double *part, int64_t
 
 hipError_t launch_gram(const void *X, int32_t ldx, const void *Y, int32_t ldy, bool fp64, int32_t n,
                        int32_t na, int32_t nb, double *part, double *out, hipStream_t s) {
-    const int64_t chunks = (n + kGramChunk - 1) / kGramChunk;
-    dim3 g((na + kGramTile - 1) / kGramTile, (nb + kGramTile - 1) / kGramTile, (unsigned)chunks);
-    if (fp64)
-        hipLaunchKernelGGL(k_gram<double>, g, dim3(256), 0, s, (const double *)X, ldx, (const double *)Y, ldy,
-                           n, na, nb, part);
-    else
-        hipLaunchKernelGGL(k_gram<float>, g, dim3(256), 0, s, (const float *)X, ldx, (const float *)Y, ldy, n,
-                           na, nb, part);
+    if (na > 128) return hipErrorInvalidValue;
+    const int64_t chunks = (n + kGramRows - 1) / kGramRows;
     const int64_t total = (int64_t)na * nb;
+    dim3 g((unsigned)chunks);
+    // 128-column slices of Y, each writing its columns of the [na][nb] partials
+    for (int b = 0; b < nb; b += 128) {
+        const int w = min(128, nb - b);
+        if (fp64)
+            hipLaunchKernelGGL(k_gram<double>, g, dim3(256), 0, s, (const double *)X, ldx, (const double *)Y + b,
+                               ldy, n, na, w, part + b, total, nb);
+        else
+            hipLaunchKernelGGL(k_gram<float>, g, dim3(256), 0, s, (const float *)X, ldx, (const float *)Y + b,
+                               ldy, n, na, w, part + b, total, nb);
+    }
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, part, chunks,
                        total, out);
     return hipGetLastError();
 }
 
-// Upper Cholesky G = R^T R and R^{-1} (upper), one block, G staged in LDS
-// (na <= 128: 128 KB of the 160 KB LDS of a gfx950 CU).  R overwrites the
-// upper triangle; R^{-1} is built in the strict lower triangle (transposed)
-// with its diagonal in dinv, one column per thread.
-__global__ void __launch_bounds__(256) k_cholinv(const double *G_in, double *Rinv, int32_t na, int32_t *flags) {
+// Upper Cholesky G = R^T R (na <= 128), one block, G staged in LDS (128 KB
+// of the 160 KB of a gfx950 CU); R overwrites G's upper triangle in memory.
+// A pivot that is not positive sets flags bit 1 (and is replaced by 1).
+__global__ void __launch_bounds__(256) k_chol(double *G_io, int32_t na, int32_t *flags) {
     __shared__ double G[128 * 128];
-    __shared__ double dinv[128];
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
-    for (int t = threadIdx.x; t < na * na; t += 256) G[t] = G_in[t];
+    for (int t = threadIdx.x; t < na * na; t += 256) G[t] = G_io[t];
     __syncthreads();
     for (int j = 0; j < na; ++j) {
         if (threadIdx.x == 0) {
@@ -1681,81 +1688,105 @@ __global__ void __launch_bounds__(256) k_cholinv(const double *G_in, double *Rin
         const double rjj = G[j * na + j];
         for (int q = j + 1 + threadIdx.x; q < na; q += 256) G[j * na + q] /= rjj;
         __syncthreads();
-        const int rem = na - j - 1;
-        for (int t = threadIdx.x; t < rem * rem; t += 256) {
-            const int p = j + 1 + t / rem, q = j + 1 + t % rem;
-            if (q >= p) G[p * na + q] -= G[j * na + p] * G[j * na + q];
+        // trailing update of the upper triangle, 16 x 16 threads
+        const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+        for (int p = j + 1 + ty; p < na; p += 16) {
+            const double gjp = G[j * na + p];
+            for (int q = p + tx; q < na; q += 16) G[p * na + q] -= gjp * G[j * na + q];
         }
         __syncthreads();
     }
-    // column col of R^{-1}: x_p = (delta_{p,col} - sum_{q=p+1..col} R[p][q] x_q) / R[p][p],
-    // x_q (q < col) kept at G[col][q], x_col at dinv[col]
-    for (int col = threadIdx.x; col < na; col += 256) {
-        const double xc = 1.0 / G[col * na + col];
-        dinv[col] = xc;
-        for (int p = col - 1; p >= 0; --p) {
-            double acc = G[p * na + col] * xc;
-            for (int q = p + 1; q < col; ++q) acc = fma(G[p * na + q], G[col * na + q], acc);
-            G[col * na + p] = -acc / G[p * na + p];
-        }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < na * na; t += 256) {
-        const int p = t / na, q = t % na;
-        Rinv[t] = q > p ? G[q * na + p] : (q == p ? dinv[p] : 0.0);
-    }
+    for (int t = threadIdx.x; t < na * na; t += 256) G_io[t] = G[t];
     if (threadIdx.x == 0 && bad) atomicOr(flags, 2);
+}
+
+// R^{-1} (upper) of the upper triangle of R, one wavefront per column: column
+// col solves x_col = 1 / R[col][col], then for p = col - 1 .. 0
+// x_p = -(sum_{q = p+1 .. col} R[p][q] x_q) / R[p][p], the sum formed across
+// the lanes (lane q holds x_q; fixed-order butterfly).
+__global__ void __launch_bounds__(256) k_trinv(const double *R_in, double *Rinv, int32_t na) {
+    __shared__ double R[128 * 128];
+    for (int t = threadIdx.x; t < na * na; t += 256) R[t] = R_in[t];
+    __syncthreads();
+    const int col = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (col >= na) return;
+    const double xc = 1.0 / R[col * na + col];
+    double x0 = lane == col ? xc : 0.0;
+    double x1 = lane + 64 == col ? xc : 0.0;
+    for (int p = col - 1; p >= 0; --p) {
+        double part = 0.0;
+        if (lane > p && lane <= col) part = R[p * na + lane] * x0;
+        if (lane + 64 > p && lane + 64 <= col) part = fma(R[p * na + lane + 64], x1, part);
+        const double xp = -wave_sum(part) / R[p * na + p];
+        x0 = lane == p ? xp : x0;
+        x1 = lane + 64 == p ? xp : x1;
+    }
+    for (int p = lane; p < na; p += 64) {
+        const double v = p < 64 ? x0 : x1;
+        Rinv[(int64_t)p * na + col] = p <= col ? v : 0.0;
+    }
 }
 
 hipError_t launch_cholinv(double *G, double *Rinv, int32_t na, int32_t *flags, hipStream_t s) {
     if (na > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(256), 0, s, G, Rinv, na, flags);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, s, G, na, flags);
+    hipLaunchKernelGGL(k_trinv, dim3((na + 3) / 4), dim3(256), 0, s, G, Rinv, na);
     return hipGetLastError();
 }
 
-// Z = (sub ? Z - X M : X M), row-local: a block owns 32 rows, stages them in
-// LDS (FP64) before anything is written, so Z may alias X when sub == 0; M
-// is staged 32 columns at a time; each thread owns a 2 x 2 output sub-tile.
+// Z = (sub ? Z - X M : X M) (na, nb <= 128), row-local: a block owns 128
+// rows; each thread owns an 8 x 8 sub-tile (8 rows, 8 columns); the inner
+// dimension is staged through LDS 32 at a time (X transposed, FP64).  Every
+// row of X a block reads is read before the block writes Z, so Z may alias
+// X (sub == 0) or hold other columns of the same rows (sub == 1).
 template <typename T>
-__global__ void __launch_bounds__(256) k_apply(const T *X, int32_t ldx, const double *M, int32_t na,
+__global__ void __launch_bounds__(256) k_apply(const T *X, int32_t ldx, const double *M, int32_t ldm, int32_t na,
                                                int32_t nb, T *Z, int32_t ldz, int32_t n, int32_t sub) {
-    __shared__ double xs[32][129];
-    __shared__ double ms[128][33];
-    const int64_t r0 = (int64_t)blockIdx.x * 32;
-    for (int q = threadIdx.x; q < 32 * na; q += 256) {
-        const int rr = q / na, cc = q % na;
-        const int64_t r = r0 + rr;
-        xs[rr][cc] = r < n ? (double)X[r * ldx + cc] : 0.0;
-    }
-    const int tr = (threadIdx.x / 16) * 2;     // rows tr, tr+1
-    const int tc = (threadIdx.x % 16) * 2;     // columns tc, tc+1 of the chunk
-    for (int cb = 0; cb < nb; cb += 32) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < na * 32; q += 256) {
-            const int t = q / 32, cc = q % 32;
-            ms[t][cc] = cb + cc < nb ? M[(int64_t)t * nb + cb + cc] : 0.0;
+    constexpr int TS = 32;
+    __shared__ double xt[TS][128];   // xt[t][row]
+    __shared__ double ms[TS][128];   // ms[t][col]
+    const int64_t r0 = (int64_t)blockIdx.x * 128;
+    const int i0 = (threadIdx.x / 16) * 8, b0 = (threadIdx.x % 16) * 8;
+    double acc[8][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+    for (int t0 = 0; t0 < na; t0 += TS) {
+        for (int q = threadIdx.x; q < TS * 128; q += 256) {
+            // X rows: consecutive threads read consecutive inner indices
+            const int rr = q / TS, tt = q % TS;
+            const int64_t r = r0 + rr;
+            xt[tt][rr] = (r < n && t0 + tt < na) ? (double)X[r * ldx + t0 + tt] : 0.0;
+            const int mt = q / 128, mc = q % 128;
+            ms[mt][mc] = (t0 + mt < na && mc < nb) ? M[(int64_t)(t0 + mt) * ldm + mc] : 0.0;
         }
         __syncthreads();
-        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-        for (int t = 0; t < na; ++t) {
-            const double x0 = xs[tr][t], x1 = xs[tr + 1][t];
-            const double m0 = ms[t][tc], m1 = ms[t][tc + 1];
-            acc[0][0] = fma(x0, m0, acc[0][0]);
-            acc[0][1] = fma(x0, m1, acc[0][1]);
-            acc[1][0] = fma(x1, m0, acc[1][0]);
-            acc[1][1] = fma(x1, m1, acc[1][1]);
-        }
+        for (int tt = 0; tt < TS; ++tt) {
+            double xa[8], mb[8];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int64_t r = r0 + tr + u;
-            if (r >= n) continue;
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                const int cc = cb + tc + v;
-                if (cc >= nb) continue;
-                if (sub) Z[r * ldz + cc] = (T)((double)Z[r * ldz + cc] - acc[u][v]);
-                else Z[r * ldz + cc] = (T)acc[u][v];
+            for (int u = 0; u < 8; ++u) {
+                xa[u] = xt[tt][i0 + u];
+                mb[u] = ms[tt][b0 + u];
             }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int v = 0; v < 8; ++v) acc[u][v] = fma(xa[u], mb[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t r = r0 + i0 + u;
+        if (r >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int cc = b0 + v;
+            if (cc >= nb) continue;
+            if (sub) Z[r * ldz + cc] = (T)((double)Z[r * ldz + cc] - acc[u][v]);
+            else Z[r * ldz + cc] = (T)acc[u][v];
         }
     }
 }
@@ -1763,13 +1794,18 @@ __global__ void __launch_bounds__(256) k_apply(const T *X, int32_t ldx, const do
 hipError_t launch_apply(const void *X, int32_t ldx, const double *M, int32_t na, int32_t nb, void *Z,
                         int32_t ldz, bool fp64, int32_t n, int32_t sub, hipStream_t s) {
     if (na > 128) return hipErrorInvalidValue;
-    dim3 g((unsigned)((n + 31) / 32));
-    if (fp64)
-        hipLaunchKernelGGL(k_apply<double>, g, dim3(256), 0, s, (const double *)X, ldx, M, na, nb, (double *)Z,
-                           ldz, n, sub);
-    else
-        hipLaunchKernelGGL(k_apply<float>, g, dim3(256), 0, s, (const float *)X, ldx, M, na, nb, (float *)Z, ldz,
-                           n, sub);
+    // Z aliasing X (sub == 0) needs one pass over all columns
+    if (sub == 0 && nb > 128) return hipErrorInvalidValue;
+    dim3 g((unsigned)((n + 127) / 128));
+    for (int b = 0; b < nb; b += 128) {
+        const int w = min(128, nb - b);
+        if (fp64)
+            hipLaunchKernelGGL(k_apply<double>, g, dim3(256), 0, s, (const double *)X, ldx, M + b, nb, na, w,
+                               (double *)Z + b, ldz, n, sub);
+        else
+            hipLaunchKernelGGL(k_apply<float>, g, dim3(256), 0, s, (const float *)X, ldx, M + b, nb, na, w,
+                               (float *)Z + b, ldz, n, sub);
+    }
     return hipGetLastError();
 }
 

@@ -566,6 +566,7 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
     }
     if (tuning) return VNE_OK;
     if (timing) c->pending.push_back({p, bytes});
+    if (p->store) return VNE_OK;   // the Hutch++ sketch needs f(T) e1 (k_fT_e1), not psi
     HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p, (const int32_t *)p->k_eff.p,
                                  (const double *)p->norm2.p, p->k, p->k, p->G * p->m_pad, (double *)p->psi.p,
                                  (int32_t *)p->flags.p, c->stream));

@@ -233,3 +233,57 @@ def test_graph_and_timing_paths_agree(ctx, monkeypatch):
     for other in (timed, direct):
         for key in ("quad", "alpha", "beta", "k_eff", "norm2"):
             assert np.array_equal(base[key], other[key]), key
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_max_steps_and_wide_block(ctx, fp64):
+    # k = 128 (the largest the kernels take; the QR runs with two register
+    # halves) and m = 1000 (eight column tiles with a ragged last one)
+    _say("case k=128 and m=1000 fp64=%s" % fp64)
+    n, e = synth.watts_strogatz(3000, 8, 0.1, 41)
+    gid, ref = _setup(ctx, n, e, fp64)
+    mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+    A = ref.scipy()
+    out = ctx.estimate(gid, vne.PROBE_RADEMACHER, 6, 128, mode, seed=12)
+    B = oracle.rademacher_block(12, ref.node_ids, np.arange(6))
+    want = oracle.quadforms(A, B, 128, oracle.breakdown_tau(fp64))
+    _check_quad(out, want, fp64, k_exact=False, sens=_order_sensitivity(A, B, 128, fp64), n=ref.n)
+    out = ctx.estimate(gid, vne.PROBE_RADEMACHER, 1000, 12, mode, seed=13, want_coeffs=False)
+    cols = np.array([0, 511, 999])
+    B = oracle.rademacher_block(13, ref.node_ids, cols)
+    want = oracle.quadforms(A, B, 12, oracle.breakdown_tau(fp64))
+    rel = _rel(out["quad"][cols], want["psi"])
+    assert np.all(rel < TOL[fp64]), rel
+    assert abs(out["estimate"] - out["quad"].mean()) <= 1e-13 * abs(out["estimate"])
+
+
+def test_single_edge_graph(ctx):
+    # two nodes: rho = [[.5, -.5], [-.5, .5]] has eigenvalues 0 and 1, S = 0;
+    # the desingularized probe lies in the eigenvalue-1 direction
+    _say("case single edge")
+    gid, ref = _setup(ctx, 2, np.array([[0, 1]]), True)
+    out = ctx.estimate(gid, vne.PROBE_RADEMACHER, 4, 5, vne.MODE_DESING | vne.MODE_F64, seed=2)
+    assert np.all(out["k_eff"] <= 1)
+    assert np.all(np.abs(out["quad"]) < 1e-15)
+
+
+def test_hutchpp_wide_g_block(ctx):
+    # N_H = 200 > 128: the projection G - Q (Q^T G) runs in column slices
+    _say("case Hutch++ BA n=3000 24+200 fp32")
+    n, e = synth.barabasi_albert(3000, 3, 17)
+    gid, ref = _setup(ctx, n, e, False)
+    nr, nh, k = 24, 200, 25
+    out = ctx.estimate(gid, vne.PROBE_HUTCHPP, nr + nh, k, vne.MODE_DESING, seed=19, n_sketch=nr)
+    Om = oracle.rademacher_block(19, ref.node_ids, np.arange(nr))
+    G = oracle.rademacher_block(19, ref.node_ids, np.arange(nr, nr + nh))
+    est, det = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(False))
+    import scipy.sparse as sp
+    P = np.arange(ref.n)[::-1]
+    Ap = sp.csr_matrix(ref.scipy())[P][:, P]
+    est_p, det_p = oracle.hutchpp(Ap, Om[P], G[P], k, oracle.breakdown_tau(False))
+    sens_g = _rel(det_p["psi"][nr:], det["psi"][nr:])
+    err_g = _rel(out["quad"][nr:], det["psi"][nr:])
+    err_e = abs(out["estimate"] - est) / abs(est)
+    _say("   estimate rel err %.3e; G~ max %.3e (sens %.1e)" % (err_e, err_g.max(), sens_g.max()))
+    assert np.all(err_g < max(TOL[False], 20 * float(sens_g.max())))
+    assert err_e < max(TOL[False], 20 * abs(est_p - est) / abs(est))
