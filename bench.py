@@ -120,9 +120,11 @@ def cpu_baseline(g, spec, sample_cols, k):
     A = sp.csr_matrix((np.asarray(g["values"], np.float64) * g["scale"], g["col_idx"], g["row_ptr"]),
                       shape=(g["n"], g["n"]))
     B = oracle.rademacher_block(spec["seed"], g["node_ids"], np.arange(sample_cols))
-    t0 = time.perf_counter()
-    oracle.quadforms(A, B, k, oracle.breakdown_tau(False))
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):        # one core, as reported
+        t0 = time.perf_counter()
+        oracle.quadforms(A, B, k, oracle.breakdown_tau(False))
+        dt = time.perf_counter() - t0
     n, nnz = g["n"], len(g["col_idx"])
     bytes_equiv = k * (4.0 * (n + 1) + nnz * 8.0 + 3.0 * n * sample_cols * 4.0)
     return dict(value=bytes_equiv / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
@@ -213,6 +215,8 @@ def run_batch(args):
     if not args.no_cpu_baseline:
         import oracle
         import scipy.sparse as sp
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(limits=1)   # one core, as reported
         t0 = time.perf_counter()
         done, by = 0, 0.0
         for q, g in enumerate(graphs):
@@ -225,6 +229,7 @@ def run_batch(args):
             if time.perf_counter() - t0 > args.cpu_seconds:
                 break
         dt = time.perf_counter() - t0
+        limit.restore_original_limits()
         res["cpu_baseline"] = dict(value=by / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
                                    queries_per_s=done / dt,
                                    sample="oracle Lanczos + Gauss quadrature on the first %d graphs of the "

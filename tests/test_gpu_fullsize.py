@@ -12,6 +12,8 @@ on sampled outputs the oracle computes one by one.
   compared bit for bit with the oracle elsewhere (CPU, slow).
 * batch: the 512-graph batch (64 probes, k = 50): four sampled graphs
   (smallest, largest, one ER, one BA), four columns each.
+* the probing configuration without rewiring (ring lattice): the whole
+  estimate against the exact entropy, within Corollary 3.2's bound.
 Bars: 1e-5 relative per quadratic form, widened to 20x the oracle's own
 rounding-order sensitivity (same problem, rows reversed) where that is larger.
 """
@@ -96,3 +98,31 @@ def test_batch_configuration_sampled(ctx):
         cols = np.array([0, 21, 42, 63])
         B = oracle.rademacher_block(workloads.PROBE_SEED + q, g["node_ids"], cols)
         _sampled_check(A, g["node_ids"], B, outs[q]["quad"], cols, 50)
+
+
+def test_probing_ring_lattice_exact_entropy(ctx):
+    """The probing configuration without rewiring (ring lattice n = 1e6,
+    k = 10): its Laplacian is circulant, so S(rho) has a closed form from the
+    eigenvalues 10 - 2 sum_{r=1..5} cos(2 pi j r / n).  The distance-2 probing
+    estimate must be within Corollary 3.2's bound n b / (2 (d^2 - 1)) (a = 0,
+    b = lambda_max) of it."""
+    _say("case full size: ring lattice n=1e6, probing d=2, k=80, exact S")
+    import synth
+    n, kk, d = 1_000_000, 10, 2
+    nn, e = synth.ring_lattice(n, kk)
+    g = vne.laplacian_from_edges(nn, e, np.float32)
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    col, s = vne.color_greedy(g["row_ptr"], g["col_idx"], g["values"], d)
+    out = ctx.estimate(gid, vne.PROBE_COLORING, s, 80, vne.MODE_DESING, colors=col, want_coeffs=False)
+    j = np.arange(n, dtype=np.float64)
+    lam = np.full(n, float(kk))
+    for r in range(1, kk // 2 + 1):
+        lam -= 2.0 * np.cos(2.0 * np.pi * j * r / n)
+    rho = lam / lam.sum()
+    rho_pos = rho[rho > 0]
+    S = float(-np.sum(rho_pos * np.log(rho_pos)))
+    bound = n * rho.max() / (2 * (d * d - 1))
+    err = abs(out["estimate"] - S)
+    _say("   colours %d, S = %.10f, estimate %.10f, |err| = %.3e (rel %.2e), Corollary 3.2 bound %.3e"
+         % (s, S, out["estimate"], err, err / S, bound))
+    assert err <= bound
