@@ -41,10 +41,32 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
+    """Hash of the sources that fix what the Lanczos step unit (probe, step,
+    long-row and normalize kernels) reads and writes per launch: the step
+    kernels' part of kernels.hip and kernels.h, the work schedule builder and
+    the runtime's schedule choice.  Counter figures taken on other sources
+    are not reused."""
+    csrc = os.path.join(ROOT, "paper_2212_09642_amd", "csrc")
+
+    def text(name):
+        with open(os.path.join(csrc, name)) as fh:
+            return fh.read()
+
+    def upto(src, marker):
+        i = src.find(marker)
+        if i < 0:
+            raise RuntimeError("marker %r missing" % marker)
+        return src[:i]
+
+    parts = [upto(text("kernels.hip"), "// Symmetric tridiagonal eigenproblem"),
+             upto(text("kernels.h"), "// Gauss quadrature of every column"),
+             text("host_graph.cpp")]
+    rt = text("runtime.hip")
+    i = rt.find("Schedule set_schedule(")
+    parts.append(rt[i:rt.find("\n}\n", i)] if i >= 0 else rt)
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h", "runtime.hip"):
-        with open(os.path.join(ROOT, "paper_2212_09642_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for part in parts:
+        h.update(part.encode())
     return h.hexdigest()[:16]
 
 
