@@ -230,6 +230,99 @@ vne_status vne_entropy_estimate_batch(vne_ctx *ctx, int32_t n_queries, const int
                                       const vne_probes *probes, const int32_t *k_steps,
                                       uint32_t mode, vne_result *out);
 
+/* Per-vector stopping rule of vne_entropy_estimate_adaptive. */
+typedef struct {
+    const double *tol;          /* host [m]: tolerance of each quadratic form (> 0)        */
+    double lam_lo, lam_hi;      /* interval of the Theorem 4.8 bound, 0 < lam_lo < lam_hi  */
+    int32_t n_grid;             /* log-spaced points of the interval, 2..65536 (0: 256)    */
+} vne_stop_rule;
+
+/* Quadratic forms with an a-posteriori stopping rule (Theorem 4.8, used as
+ * in step 3 of Algorithm 2): Lanczos on every probe vector as in
+ * vne_entropy_estimate, with the upper bound of the bracket (the one
+ * vne_error_bounds returns, on [rule->lam_lo, rule->lam_hi] with
+ * rule->n_grid points) evaluated for every running vector after steps 3, 5,
+ * 7, ... (at most k_max).  Vector c stops at the first such step s with
+ * hi <= rule->tol[c]; its psi is the Gauss quadrature after min(k_eff, s)
+ * steps.  A vector that never meets its tolerance ends at k_max.  The block
+ * stops when every vector has stopped (the call synchronises its stream
+ * after each check to read the running count).  steps_out (host [m], may be
+ * NULL) receives each vector's stop step, or 0 for a vector that never met
+ * its tolerance (its psi is the quadrature after k_max steps).  out->alpha /
+ * out->beta entries past a vector's stop step are unspecified.  Probe kinds RADEMACHER, COLORING and DENSE on one graph;
+ * 3 <= k_max <= 128.  The interval must contain the spectrum the start
+ * vectors see for hi to bound the error (see vne_error_bounds). */
+vne_status vne_entropy_estimate_adaptive(vne_ctx *ctx, int32_t graph_id, const vne_probes *probes,
+                                         int32_t k_max, uint32_t mode, const vne_stop_rule *rule,
+                                         vne_result *out, int32_t *steps_out);
+
+/* Probing method with a relative accuracy target: Algorithm 2 of Section 5. */
+enum { VNE_SELECT_HEURISTIC = 0, VNE_SELECT_BOUND = 1 };
+
+typedef struct {
+    double rel_eps;             /* target relative error epsilon, 0 < rel_eps < 1          */
+    int32_t select;             /* VNE_SELECT_HEURISTIC: eq. (5.1) from T_1..T_3;
+                                   VNE_SELECT_BOUND: Corollary 3.2 with a = 0               */
+    int32_t d_max;              /* largest distance considered, 1..64 (0: 16)              */
+    int32_t k_max;              /* step cap per quadratic form, 3..128 (0: 128)            */
+    uint32_t mode;              /* VNE_MODE_* bits of the Lanczos runs                     */
+    double lam_lo_fraction;     /* lower end of the bound interval / lambda_ub (0: 1e-12)  */
+    int32_t n_grid;             /* bound grid points (0: 256)                              */
+} vne_probing_cfg;
+
+typedef struct {
+    double estimate;            /* T_d: sum of the psi of the final pass                   */
+    int32_t d, n_colors;        /* selected distance and its colour count                  */
+    int32_t fallback;           /* 1: Corollary 3.2 chose d                                */
+    int32_t capped;             /* 1: no d <= d_max met the target (d = d_max)             */
+    int32_t unconverged;        /* colours of the final pass that ended at k_max           */
+    int32_t passes;             /* distance-d passes run (colouring + Lanczos)             */
+    double t_pre[3];            /* T_1, T_2, T_3 of the heuristic (0 with the bound)       */
+    double e1, q[2];            /* fit: |T_2 - T_1|, q for kappa = 2 and 3                 */
+    double s_lower;             /* -log tr(A^2)                                            */
+    double s_hat;               /* rough entropy behind eps_hat                            */
+    double eps_hat;             /* absolute target for d and for the Krylov part           */
+    int64_t vector_steps;       /* sum over passes and colours of the steps used           */
+    int64_t block_steps;        /* sum over passes of the steps the block ran              */
+    double color_ms, lanczos_ms;/* host colouring time; Lanczos passes (wall, synchronised) */
+    int32_t *colors;            /* host [n] or NULL: colouring of the final pass           */
+    double *quad;               /* host [quad_cap] or NULL: psi of the final pass          */
+    int32_t *steps;             /* host [quad_cap] or NULL: stop step per colour (0: k_max
+                                   reached without meeting the tolerance)                   */
+    int32_t quad_cap;           /* the first min(quad_cap, n_colors) entries are written  */
+} vne_probing_result;
+
+/* Algorithm 2 for a unit-trace matrix (a density matrix; EINVAL otherwise).
+ * With S_lower = -log tr(A^2) <= S(A), lambda_ub = max_i sum_j |A_ij|:
+ *  1. select = HEURISTIC: distance-d passes for d = 1, 2, 3 with
+ *     eps_hat0 = rel_eps S_lower / 2; then s_hat = max(S_lower, T_1, T_2, T_3)
+ *     (every T_d is a lower bound of S for an M-matrix, Proposition 3.6),
+ *     eps_hat = rel_eps s_hat / 2 and d from the fit of eq. (5.1) (the larger
+ *     of the kappa = 2 and kappa = 3 models; Corollary 3.2 when the fit has no
+ *     decay).  select = BOUND: s_hat = S_lower and the smallest d >= 2 with
+ *     n lambda_ub / (2 (d^2 - 1)) <= eps_hat.
+ *  2. a greedy distance-d colouring (Algorithm 1, as vne_color_greedy);
+ *  3. psi of each colour indicator v_l with the stopping rule of
+ *     vne_entropy_estimate_adaptive, tolerance eps_hat |V_l| / n (eq. (5.3)),
+ *     on [lam_lo_fraction lambda_ub, lambda_ub];
+ *  4. estimate = sum of psi.
+ * A selected d of 1, 2 or 3 reuses that preprocessing pass.  The colourings
+ * run on the host; the passes on the context's stream. */
+vne_status vne_entropy_probing(vne_ctx *ctx, int32_t graph_id, const vne_probing_cfg *cfg,
+                               vne_probing_result *res);
+
+/* The distance choice of step 1, for callers that plan on their own (host
+ * only): the eq. (5.1) fit from T[3] = {T_1, T_2, T_3} (use_bound = 0) or
+ * Corollary 3.2 alone (use_bound = 1, T may be NULL), for a target eps_hat,
+ * size n and lambda_ub.  1 <= d_max <= 64. */
+typedef struct {
+    int32_t d, fallback, capped;
+    double e1, q[2];
+    double model;               /* the chosen rule's error value at d                      */
+} vne_distance_choice;
+vne_status vne_probing_select(const double *T, double eps_hat, double n, double lambda_ub, int32_t d_max,
+                              int32_t use_bound, vne_distance_choice *out);
+
 /* A-posteriori error bracket of Theorem 4.8 for the polynomial Krylov
  * method, per column of a result (host arrays laid out as in vne_result:
  * alpha, beta [m*k], k_eff, norm2 [m]) after min(k_eff[c], steps) steps:

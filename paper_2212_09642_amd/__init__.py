@@ -15,7 +15,8 @@ import numpy as np
 __all__ = ["VneError", "lib", "version", "laplacian_from_edges", "csr_validate",
            "color_greedy", "Context", "F32", "F64", "MODE_F64", "MODE_DESING",
            "PROBE_RADEMACHER", "PROBE_HUTCHPP", "PROBE_COLORING", "PROBE_DENSE",
-           "VALIDATE_SYMMETRIC", "VALIDATE_ZERO_ROWSUM", "LIB_PATH", "EXPORTS"]
+           "VALIDATE_SYMMETRIC", "VALIDATE_ZERO_ROWSUM", "LIB_PATH", "EXPORTS", "SELECT_HEURISTIC",
+           "SELECT_BOUND", "probing_select"]
 
 LIB_PATH = os.environ.get("VNE_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                            "libvne.so")
@@ -24,6 +25,7 @@ F32, F64 = 0, 1
 HOST, DEVICE = 0, 1
 MODE_F64, MODE_DESING = 1, 2
 PROBE_RADEMACHER, PROBE_HUTCHPP, PROBE_COLORING, PROBE_DENSE = 0, 1, 2, 3
+SELECT_HEURISTIC, SELECT_BOUND = 0, 1
 VALIDATE_SYMMETRIC, VALIDATE_ZERO_ROWSUM = 1, 2
 STATUS = {0: "VNE_OK", -1: "VNE_EINVAL", -2: "VNE_ENOMEM", -3: "VNE_EDEVICE",
           -4: "VNE_ENOTSUP", -5: "VNE_EBUSY", -6: "VNE_ENUMERIC"}
@@ -34,7 +36,8 @@ EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_c
            "vne_ctx_memory", "vne_graph_register", "vne_graph_release", "vne_entropy_estimate",
            "vne_entropy_estimate_batch", "vne_enable_kernel_timing", "vne_kernel_timing",
            "vne_server_start", "vne_server_submit", "vne_server_poll", "vne_server_stats",
-           "vne_server_stop", "vne_plan_steps", "vne_plan_probes", "vne_error_bounds"]
+           "vne_server_stop", "vne_plan_steps", "vne_plan_probes", "vne_error_bounds",
+           "vne_entropy_estimate_adaptive", "vne_entropy_probing", "vne_probing_select"]
 
 
 class VneError(RuntimeError):
@@ -61,6 +64,32 @@ class _Result(ctypes.Structure):
     _fields_ = [("estimate", ctypes.c_double), ("quad", ctypes.c_void_p),
                 ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p),
                 ("k_eff", ctypes.c_void_p), ("norm2", ctypes.c_void_p)]
+
+
+class _StopRule(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_void_p), ("lam_lo", ctypes.c_double), ("lam_hi", ctypes.c_double),
+                ("n_grid", ctypes.c_int32)]
+
+
+class _ProbingCfg(ctypes.Structure):
+    _fields_ = [("rel_eps", ctypes.c_double), ("select", ctypes.c_int32), ("d_max", ctypes.c_int32),
+                ("k_max", ctypes.c_int32), ("mode", ctypes.c_uint32), ("lam_lo_fraction", ctypes.c_double),
+                ("n_grid", ctypes.c_int32)]
+
+
+class _ProbingResult(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("d", ctypes.c_int32), ("n_colors", ctypes.c_int32),
+                ("fallback", ctypes.c_int32), ("capped", ctypes.c_int32), ("unconverged", ctypes.c_int32),
+                ("passes", ctypes.c_int32), ("t_pre", ctypes.c_double * 3), ("e1", ctypes.c_double),
+                ("q", ctypes.c_double * 2), ("s_lower", ctypes.c_double), ("s_hat", ctypes.c_double),
+                ("eps_hat", ctypes.c_double), ("vector_steps", ctypes.c_int64), ("block_steps", ctypes.c_int64),
+                ("color_ms", ctypes.c_double), ("lanczos_ms", ctypes.c_double), ("colors", ctypes.c_void_p),
+                ("quad", ctypes.c_void_p), ("steps", ctypes.c_void_p), ("quad_cap", ctypes.c_int32)]
+
+
+class _DistanceChoice(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("fallback", ctypes.c_int32), ("capped", ctypes.c_int32),
+                ("e1", ctypes.c_double), ("q", ctypes.c_double * 2), ("model", ctypes.c_double)]
 
 
 class _ServerCfg(ctypes.Structure):
@@ -141,6 +170,13 @@ def lib():
         L.vne_error_bounds.restype = i32
         L.vne_error_bounds.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32, dbl, dbl, i32, vp, vp]
         L.vne_plan_steps.restype = i32
+        L.vne_entropy_estimate_adaptive.argtypes = [vp, i32, P(_Probes), i32, ctypes.c_uint32, P(_StopRule),
+                                                    P(_Result), vp]
+        L.vne_entropy_estimate_adaptive.restype = ctypes.c_int
+        L.vne_entropy_probing.argtypes = [vp, i32, P(_ProbingCfg), P(_ProbingResult)]
+        L.vne_entropy_probing.restype = ctypes.c_int
+        L.vne_probing_select.argtypes = [vp, dbl, dbl, dbl, i32, i32, P(_DistanceChoice)]
+        L.vne_probing_select.restype = ctypes.c_int
         L.vne_plan_steps.argtypes = [dbl, dbl, dbl, dbl, dbl, i32]
         L.vne_plan_probes.restype = i32
         L.vne_plan_probes.argtypes = [dbl, dbl, dbl, dbl, dbl, i32, i32]
@@ -363,6 +399,62 @@ class Context:
                                            _ptr(hi)))
         return lo, hi
 
+    def estimate_adaptive(self, gid, kind, m, k_max, mode, tol, lam_lo, lam_hi, n_grid=0, seed=0, colors=None,
+                          dense=None, want_coeffs=False):
+        """Quadratic forms stopped per vector on the Theorem 4.8 upper bound
+        (tolerance tol[c]); returns dict(estimate, quad, steps, alpha, beta,
+        k_eff, norm2)."""
+        loc = HOST
+        keep = []
+        if colors is not None:
+            if _is_device(colors):
+                loc = DEVICE
+            else:
+                colors = np.ascontiguousarray(colors, np.int32)
+            keep.append(colors)
+        if dense is not None:
+            if _is_device(dense):
+                loc = DEVICE
+            else:
+                dense = np.ascontiguousarray(dense, np.float64 if mode & MODE_F64 else np.float32)
+            keep.append(dense)
+        tol = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, np.float64), (m,)))
+        pr = _Probes(kind, m, seed, 0, loc, _ptr(colors), _ptr(dense))
+        rule = _StopRule(_ptr(tol), float(lam_lo), float(lam_hi), int(n_grid))
+        quad = np.zeros(m)
+        steps = np.zeros(m, np.int32)
+        kef = np.zeros(m, np.int32)
+        nrm = np.zeros(m)
+        alpha = np.zeros((m, k_max)) if want_coeffs else None
+        beta = np.zeros((m, k_max)) if want_coeffs else None
+        res = _Result(0.0, _ptr(quad), _ptr(alpha), _ptr(beta), _ptr(kef), _ptr(nrm))
+        self._chk(self._L.vne_entropy_estimate_adaptive(self._h, gid, ctypes.byref(pr), int(k_max), mode,
+                                                        ctypes.byref(rule), ctypes.byref(res), _ptr(steps)))
+        return dict(estimate=res.estimate, quad=quad, steps=steps, alpha=alpha, beta=beta, k_eff=kef, norm2=nrm)
+
+    def probing(self, gid, rel_eps, select=SELECT_HEURISTIC, d_max=0, k_max=0, mode=MODE_DESING,
+                lam_lo_fraction=0.0, n_grid=0, n=None, quad_cap=0):
+        """Algorithm 2 (probing with a relative accuracy target).  With n (the
+        matrix size) the final colouring is returned; quad_cap > 0 returns the
+        first quad_cap psi and stop steps of the final pass."""
+        cfg = _ProbingCfg(float(rel_eps), int(select), int(d_max), int(k_max), int(mode), float(lam_lo_fraction),
+                          int(n_grid))
+        colors = np.zeros(n, np.int32) if n else None
+        quad = np.zeros(quad_cap) if quad_cap > 0 else None
+        steps = np.zeros(quad_cap, np.int32) if quad_cap > 0 else None
+        r = _ProbingResult()
+        r.colors, r.quad, r.steps, r.quad_cap = _ptr(colors), _ptr(quad), _ptr(steps), int(quad_cap)
+        self._chk(self._L.vne_entropy_probing(self._h, gid, ctypes.byref(cfg), ctypes.byref(r)))
+        out = {f: getattr(r, f) for f, _ in _ProbingResult._fields_ if f not in ("colors", "quad", "steps")}
+        out["t_pre"] = list(r.t_pre)
+        out["q"] = list(r.q)
+        if colors is not None:
+            out["colors"] = colors
+        if quad is not None:
+            w = min(quad_cap, r.n_colors)
+            out["quad"], out["steps"] = quad[:w], steps[:w]
+        return out
+
     def enable_kernel_timing(self, on=True):
         self._chk(self._L.vne_enable_kernel_timing(self._h, 1 if on else 0))
 
@@ -371,6 +463,17 @@ class Context:
         self._chk(self._L.vne_kernel_timing(self._h, 1 if reset else 0, ctypes.byref(n),
                                             ctypes.byref(ms), ctypes.byref(by)))
         return dict(launches=n.value, total_ms=ms.value, bytes=by.value)
+
+
+def probing_select(T, eps_hat, n, lambda_ub, d_max, use_bound=False):
+    """The distance choice of Algorithm 2 (eq. (5.1) fit or Corollary 3.2)."""
+    t = None if T is None else np.ascontiguousarray(T, np.float64)
+    c = _DistanceChoice()
+    st = lib().vne_probing_select(_ptr(t), float(eps_hat), float(n), float(lambda_ub), int(d_max),
+                                  1 if use_bound else 0, ctypes.byref(c))
+    if st != 0:
+        raise VneError(st, "vne_probing_select rejected its arguments")
+    return dict(d=c.d, fallback=c.fallback, capped=c.capped, e1=c.e1, q=list(c.q), model=c.model)
 
 
 def plan_steps(norm2, lambda_max, s_lower, rel_eps, share=0.5, k_max=100):

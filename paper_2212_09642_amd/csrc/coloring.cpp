@@ -16,20 +16,7 @@
 
 using namespace vne;
 
-extern "C" vne_status vne_color_greedy(const vne_csr *csr, int32_t d, int32_t *colors_out,
-                                       int32_t *n_colors, char *msg, int64_t msg_len) {
-    if (!csr || csr->location != VNE_HOST) {
-        set_msg(msg, msg_len, "vne_color_greedy needs a host CSR");
-        return VNE_EINVAL;
-    }
-    if (d < 1) { set_msg(msg, msg_len, "distance d must be >= 1"); return VNE_EINVAL; }
-    if (!colors_out || !n_colors) { set_msg(msg, msg_len, "NULL output"); return VNE_EINVAL; }
-    std::string m;
-    vne_status st = validate_host_csr(csr, 0, &m);
-    if (st != VNE_OK) { set_msg(msg, msg_len, m); return st; }
-    const int64_t n = csr->n;
-    const int32_t *rp = csr->row_ptr, *ci = csr->col_idx;
-
+int32_t vne::greedy_color(int64_t n, const int32_t *rp, const int32_t *ci, int32_t d, int32_t *colors_out) {
     std::vector<int32_t> deg(n);
     for (int64_t i = 0; i < n; ++i) {
         int32_t c = 0;
@@ -71,7 +58,21 @@ extern "C" vne_status vne_color_greedy(const vne_csr *csr, int32_t d, int32_t *c
         color[i] = c;
     }
     std::copy(color.begin(), color.end(), colors_out);
-    *n_colors = ncol;
+    return ncol;
+}
+
+extern "C" vne_status vne_color_greedy(const vne_csr *csr, int32_t d, int32_t *colors_out,
+                                       int32_t *n_colors, char *msg, int64_t msg_len) {
+    if (!csr || csr->location != VNE_HOST) {
+        set_msg(msg, msg_len, "vne_color_greedy needs a host CSR");
+        return VNE_EINVAL;
+    }
+    if (d < 1) { set_msg(msg, msg_len, "distance d must be >= 1"); return VNE_EINVAL; }
+    if (!colors_out || !n_colors) { set_msg(msg, msg_len, "NULL output"); return VNE_EINVAL; }
+    std::string m;
+    vne_status st = validate_host_csr(csr, 0, &m);
+    if (st != VNE_OK) { set_msg(msg, msg_len, m); return st; }
+    *n_colors = greedy_color(csr->n, csr->row_ptr, csr->col_idx, d, colors_out);
     set_msg(msg, msg_len, "");
     return VNE_OK;
 }

@@ -39,6 +39,16 @@ struct Plan {
     std::map<std::pair<int, int>, hipGraphExec_t> exec;
     std::map<std::pair<int, int>, std::vector<hipGraphExec_t>> part_exec;
     std::vector<hipEvent_t> ev;      // 2k events
+    // per-column stopping (allocated on first use): tolerances, recorded stop
+    // steps, the bracket of the last check, per-check-step kernel arguments,
+    // the running-column count and its pinned host copy; the step loop is
+    // captured chunk by chunk (steps up to one check), keyed by (schedule,
+    // tile, first step of the chunk)
+    DevBuf col_tol, col_stop, bound_lo, bound_hi, adapt_args, remaining;
+    int32_t *h_remaining = nullptr;
+    std::vector<char> h_adapt;
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> chunk_exec;
+    int steps_run = 0;               // steps the block ran in the last run
 };
 
 struct Graph {
@@ -100,6 +110,7 @@ struct vne_ctx {
     struct Pending {
         void *plan;
         double bytes;
+        int steps;                       // step launches with recorded events
     };
     std::vector<Pending> pending;        // timed step loops not yet collected
     std::map<std::string, int> tuned;    // autotuner: set signature -> column tile
@@ -132,6 +143,44 @@ int env_int(const char *name, int dflt);
 Graph *get_graph(vne_ctx *c, int32_t gid);
 // the device arrays of one graph (a set of one), built on first use
 vne_status get_set(vne_ctx *c, const std::vector<int32_t> &ids, GraphSet **out);
+// buffers of an m-column, k-step problem on a set (cached per shape and tag)
+vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool store, int tag, Plan **out);
+
+// Probe description for run_lanczos.
+struct ProbeSpec {
+    int gen = GEN_RADEMACHER;
+    std::vector<uint64_t> seeds;       // per graph (Rademacher)
+    int col_offset = 0;
+    const int32_t *colors = nullptr;   // device, stacked rows
+    const void *dense = nullptr;       // device, stacked rows
+    int ld_dense = 0;
+};
+
+struct RunOpts {
+    bool collect = true;               // record kernel timing for this run
+    int steps = -1;                    // autotuner: only this many steps, no graph, no quadrature
+    int tile = 0;                      // column tile (0: the plan's)
+    // per-column a-posteriori stopping (one graph): the Theorem 4.8 upper
+    // bound on [lam_lo, lam_hi] (n_grid points) is checked after steps 3, 5,
+    // 7, ...; a column stops at the first check within p->col_tol[c], the
+    // block when every column has stopped
+    bool adaptive = false;
+    double lam_lo = 0.0, lam_hi = 0.0;
+    int n_grid = kBoundGrid;
+};
+
+// Probe block, Lanczos steps, quadrature; leaves psi, coefficients, k_eff and
+// norm2 in the plan (and col_stop, steps_run when adaptive).
+vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, bool desing,
+                       const RunOpts &opt = RunOpts());
+// column tile of the plan (timed choice, cached per set shape)
+vne_status autotune(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, bool desing);
+vne_status check_flags(vne_ctx *c, int32_t fl);
+// probe spec of a set's queries; colours / dense host blocks go to the plan
+vne_status make_probe_spec(vne_ctx *c, GraphSet *set, Plan *p, const vne_probes *pr, int m_max, bool fp64,
+                           ProbeSpec *ps, int *combine_kind);
+vne_status collect_timing(vne_ctx *c);
+vne_status check_mode(vne_ctx *c, uint32_t mode);
 
 }  // namespace rt
 }  // namespace vne

@@ -58,4 +58,8 @@ vne_status validate_host_csr(const vne_csr *csr, uint32_t flags, std::string *ms
 
 void set_msg(char *msg, int64_t msg_len, const std::string &s);
 
+// Greedy distance-d colouring (Algorithm 1) of the pattern of a validated
+// CSR with n rows; colors[n] receives colours from 0; returns the count.
+int32_t greedy_color(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t d, int32_t *colors);
+
 }  // namespace vne

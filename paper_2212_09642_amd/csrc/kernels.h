@@ -147,10 +147,12 @@ hipError_t launch_rademacher_fill(void *out, bool fp64, int32_t n, int32_t m, in
 
 // Gauss quadrature of every column after min(k_eff[c], steps) steps:
 // psi[c] = norm2[c] e1^T f(T) e1 (1 <= steps <= k).  With `stop` given, a
-// record {uid, j > 0} there lowers steps to j (a-posteriori stopping).
+// record {uid, j > 0} there lowers steps to j (a-posteriori stopping); with
+// col_stop given, col_stop[c] > 0 lowers column c's steps to it.
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
                              const double *norm2, int32_t k, int32_t steps, int32_t m, double *psi,
-                             int32_t *flags, hipStream_t s, const int2 *stop = nullptr, int32_t uid = 0);
+                             int32_t *flags, hipStream_t s, const int2 *stop = nullptr, int32_t uid = 0,
+                             const int32_t *col_stop = nullptr);
 // f(T) e1 for every column (rows >= k_eff are 0), step-major: S[r*m + c]; rot_scratch
 // holds rot_capacity(k) recorded rotations (24 bytes each) per column
 __host__ __device__ int64_t rot_capacity(int32_t k);
@@ -170,6 +172,7 @@ struct BoundArgs {
     int32_t n_grid;             // >= 2
     double *lo, *hi;            // [m]
     int32_t *flags;             // QR status bits
+    const int32_t *col_stop;    // [m] or NULL: columns with a recorded stop step are skipped
 };
 // map entries {problem, group of 4 columns}
 hipError_t launch_error_bound(const BoundArgs *args, const int2 *map, int32_t n_entries, hipStream_t s);
@@ -183,6 +186,19 @@ struct StopArgs {
     int2 *state;                // {uid, first step with every hi <= tol, or 0}
 };
 hipError_t launch_stop_check(const StopArgs *args, int32_t n, hipStream_t s);
+// the bracket for the m columns of one problem (args in device memory)
+hipError_t launch_error_bound_cols(const BoundArgs *args, int32_t m, hipStream_t s);
+
+// Per-column stopping: a running column (col_stop[c] == 0) whose upper bound
+// hi[c] is within tol[c] records `step` in col_stop[c]; *remaining receives
+// the number of columns still running.  One block, any m.
+struct ColStopArgs {
+    const double *hi, *tol;
+    int32_t *col_stop;
+    int32_t m, step;
+    int32_t *remaining;
+};
+hipError_t launch_column_stop(const ColStopArgs *args, hipStream_t s);
 constexpr int kBoundGrid = 256;            // grid points of the serving loop's checks
 constexpr double kLamLoFraction = 1e-12;   // serving: lower end of the bound interval / lambda_ub
 

@@ -1212,13 +1212,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const double *beta,
                                                     const int32_t *k_eff, const double *norm2, int32_t k,
                                                     int32_t steps, int32_t m, double *psi, int32_t *flags,
-                                                    const int2 *stop, int32_t uid) {
+                                                    const int2 *stop, int32_t uid, const int32_t *col_stop) {
     const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (c >= m) return;
     if (stop) {
         const int2 st = *stop;
         if (st.x == uid && st.y > 0) steps = min(steps, st.y);
+    }
+    if (col_stop) {
+        const int cs = __builtin_amdgcn_readfirstlane(col_stop[c]);
+        if (cs > 0) steps = min(steps, cs);
     }
     const int ke = __builtin_amdgcn_readfirstlane(min(k_eff[c], steps));
     if (ke <= 0) {
@@ -1274,6 +1278,7 @@ __device__ __forceinline__ void entropy_dd(double z, double th, double log_th, d
 
 template <int NH>
 __device__ void bound_column(const BoundArgs &a, int c, int lane) {
+    if (a.col_stop && __builtin_amdgcn_readfirstlane(a.col_stop[c]) > 0) return;   // stopped earlier
     const int64_t base = (int64_t)c * a.k;
     const int ke = __builtin_amdgcn_readfirstlane(a.k_eff[c]);
     const int mm = min(ke, a.steps);
@@ -1378,12 +1383,55 @@ hipError_t launch_stop_check(const StopArgs *args, int32_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Columns [4 b, 4 b + 4) of the one problem *args per block (b = blockIdx.x).
+__global__ void __launch_bounds__(256) k_error_bound_cols(const BoundArgs *args) {
+    const BoundArgs a = *args;
+    const int c = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (c >= a.m) return;
+    const int ke = __builtin_amdgcn_readfirstlane(min(a.k_eff[c], a.steps));
+    if (ke <= 64) bound_column<1>(a, c, lane);
+    else bound_column<2>(a, c, lane);
+}
+
+hipError_t launch_error_bound_cols(const BoundArgs *args, int32_t m, hipStream_t s) {
+    if (m > 0) hipLaunchKernelGGL(k_error_bound_cols, dim3((m + 3) / 4), dim3(256), 0, s, args);
+    return hipGetLastError();
+}
+
+// One block: every running column whose upper bound is within its tolerance
+// records the step; the count of columns still running goes to *remaining.
+__global__ void __launch_bounds__(256) k_column_stop(const ColStopArgs *args) {
+    const ColStopArgs a = *args;
+    __shared__ int part[4];
+    int run = 0;
+    for (int c = threadIdx.x; c < a.m; c += 256) {
+        int cs = a.col_stop[c];
+        if (cs == 0 && a.hi[c] <= a.tol[c]) {
+            cs = a.step;
+            a.col_stop[c] = cs;
+        }
+        run += cs == 0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) run += __shfl_xor(run, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) *a.remaining = part[0] + part[1] + part[2] + part[3];
+}
+
+hipError_t launch_column_stop(const ColStopArgs *args, hipStream_t s) {
+    hipLaunchKernelGGL(k_column_stop, dim3(1), dim3(256), 0, s, args);
+    return hipGetLastError();
+}
+
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
                              const double *norm2, int32_t k, int32_t steps, int32_t m, double *psi,
-                             int32_t *flags, hipStream_t s, const int2 *stop, int32_t uid) {
+                             int32_t *flags, hipStream_t s, const int2 *stop, int32_t uid,
+                             const int32_t *col_stop) {
     if (k > kMaxSteps || steps < 1 || steps > k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_quadrature, dim3((m + 3) / 4), dim3(256), 0, s, alpha, beta, k_eff, norm2, k, steps, m,
-                       psi, flags, stop, uid);
+                       psi, flags, stop, uid, col_stop);
     return hipGetLastError();
 }
 

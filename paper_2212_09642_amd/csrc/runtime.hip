@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -86,13 +87,19 @@ void free_plan(vne_ctx *c, Plan *p) {
         for (auto &e : kv.second)
             if (e) (void)hipGraphExecDestroy(e);
     p->part_exec.clear();
+    for (auto &kv : p->chunk_exec)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    p->chunk_exec.clear();
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     p->ev.clear();
+    if (p->h_remaining) (void)hipHostFree(p->h_remaining);
+    p->h_remaining = nullptr;
     DevBuf *all[] = {&p->P[0], &p->P[1], &p->V[0], &p->V[1], &p->Vstore, &p->alpha, &p->beta,
                      &p->st_alpha, &p->st_inv, &p->st_coup, &p->k_eff, &p->norm2, &p->mean, &p->psi,
                      &p->estimate, &p->flags, &p->partials, &p->level2, &p->probe_part, &p->seg_acc,
                      &p->long_part, &p->colors, &p->dense, &p->graph_k, &p->graph_m, &p->seeds,
-                     &p->S, &p->B, &p->gram_part, &p->gram, &p->rinv, &p->rot};
+                     &p->S, &p->B, &p->gram_part, &p->gram, &p->rinv, &p->rot, &p->col_tol, &p->col_stop,
+                     &p->bound_lo, &p->bound_hi, &p->adapt_args, &p->remaining};
     for (DevBuf *b : all) dev_free(c, b);
 }
 
@@ -342,7 +349,7 @@ vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool sto
 vne_status collect_timing(vne_ctx *c) {
     for (auto &pd : c->pending) {
         Plan *p = (Plan *)pd.plan;
-        for (int j = 0; j < p->k; ++j) {
+        for (int j = 0; j < pd.steps; ++j) {
             float ms = 0.f;
             HIP_TRY(c, hipEventElapsedTime(&ms, p->ev[2 * j], p->ev[2 * j + 1]));
             c->t_ms += ms;
@@ -354,26 +361,9 @@ vne_status collect_timing(vne_ctx *c) {
     return VNE_OK;
 }
 
-// Probe description for run_lanczos.
-struct ProbeSpec {
-    int gen = GEN_RADEMACHER;
-    std::vector<uint64_t> seeds;       // per graph (Rademacher)
-    int col_offset = 0;
-    const int32_t *colors = nullptr;   // device, stacked rows
-    const void *dense = nullptr;       // device, stacked rows
-    int ld_dense = 0;
-};
-
-struct RunOpts {
-    bool collect = true;               // record kernel timing for this run
-    int steps = -1;                    // autotuner: only this many steps, no graph, no quadrature
-    int tile = 0;                      // column tile (0: the plan's)
-};
-
-// Probe block, k Lanczos steps, quadrature.  Leaves psi, coefficients,
-// k_eff and norm2 in the plan.
+// Probe block, Lanczos steps, quadrature (declared with RunOpts).
 vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, bool desing,
-                       const RunOpts &opt = RunOpts()) {
+                       const RunOpts &opt) {
     const Schedule &s = set->sched;
     const int mt = opt.tile > 0 ? opt.tile : p->mt;
     HIP_TRY(c, hipMemsetAsync(p->flags.p, 0, 4, c->stream));
@@ -510,13 +500,10 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         }
         return VNE_OK;
     };
-    auto capture = [&](hipGraphExec_t *ex, int j0, int j1, int part_only) -> vne_status {
+    auto capture_fn = [&](hipGraphExec_t *ex, const std::function<vne_status()> &body) -> vne_status {
         hipGraph_t graph = nullptr;
         HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-        vne_status st = VNE_OK;
-        for (int j = j0; j <= j1 && st == VNE_OK; ++j)
-            for (int part = 0; part < 2 && st == VNE_OK; ++part)
-                if (part_only < 0 || part == part_only) st = issue(j, part);
+        vne_status st = body();
         hipError_t e_end = hipStreamEndCapture(c->stream, &graph);
         if (st != VNE_OK) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -531,6 +518,14 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         }
         return VNE_OK;
     };
+    auto capture = [&](hipGraphExec_t *ex, int j0, int j1, int part_only) -> vne_status {
+        return capture_fn(ex, [&]() -> vne_status {
+            for (int j = j0; j <= j1; ++j)
+                for (int part = 0; part < 2; ++part)
+                    if (part_only < 0 || part == part_only) VNE_TRY(issue(j, part));
+            return VNE_OK;
+        });
+    };
     if (timing) {
         while (p->ev.size() < (size_t)(2 * p->k)) {
             hipEvent_t e;
@@ -539,6 +534,102 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         }
     }
     const auto key = std::make_pair(a.two_pass ? 1 : 0, mt);
+    if (opt.adaptive && !tuning) {
+        // Per-column stopping: the steps up to each check (3, 5, 7, ...) run
+        // as one chunk, followed by the bracket of the running columns and
+        // the stop record; the host reads the running count after each check
+        // and launches no further chunk once it is zero.
+        if (p->G != 1 || p->store) return fail(c, VNE_ENOTSUP, "per-column stopping runs on one graph");
+        const int K = p->k, M = p->m;
+        const size_t nb = (size_t)(K + 1) * (sizeof(BoundArgs) + sizeof(ColStopArgs));
+        if (!p->col_stop.p) {
+            VNE_TRY(dev_alloc(c, &p->col_stop, (size_t)p->m_pad * 4));
+            VNE_TRY(dev_alloc(c, &p->bound_lo, (size_t)p->m_pad * 8));
+            VNE_TRY(dev_alloc(c, &p->bound_hi, (size_t)p->m_pad * 8));
+            VNE_TRY(dev_alloc(c, &p->adapt_args, nb));
+            VNE_TRY(dev_alloc(c, &p->remaining, 4));
+        }
+        if (!p->col_tol.p) return fail(c, VNE_EINVAL, "per-column tolerances not set");
+        if (!p->h_remaining) HIP_TRY(c, hipHostMalloc((void **)&p->h_remaining, 4, hipHostMallocDefault));
+        p->h_adapt.assign(nb, 0);
+        BoundArgs *hb = (BoundArgs *)p->h_adapt.data();
+        ColStopArgs *hs = (ColStopArgs *)(hb + K + 1);
+        BoundArgs *db = (BoundArgs *)p->adapt_args.p;
+        ColStopArgs *ds = (ColStopArgs *)(db + K + 1);
+        for (int j = 0; j <= K; ++j) {
+            BoundArgs &b = hb[j];
+            b.alpha = (const double *)p->alpha.p;
+            b.beta = (const double *)p->beta.p;
+            b.k_eff = (const int32_t *)p->k_eff.p;
+            b.norm2 = (const double *)p->norm2.p;
+            b.k = K;
+            b.m = M;
+            b.steps = std::max(j, 1);
+            b.lam_lo = opt.lam_lo;
+            b.lam_hi = opt.lam_hi;
+            b.n_grid = opt.n_grid;
+            b.lo = (double *)p->bound_lo.p;
+            b.hi = (double *)p->bound_hi.p;
+            b.flags = (int32_t *)p->flags.p;
+            b.col_stop = (const int32_t *)p->col_stop.p;
+            ColStopArgs &q = hs[j];
+            q.hi = (const double *)p->bound_hi.p;
+            q.tol = (const double *)p->col_tol.p;
+            q.col_stop = (int32_t *)p->col_stop.p;
+            q.m = M;
+            q.step = j;
+            q.remaining = (int32_t *)p->remaining.p;
+        }
+        HIP_TRY(c, hipMemcpyAsync(p->adapt_args.p, p->h_adapt.data(), nb, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemsetAsync(p->col_stop.p, 0, (size_t)p->m_pad * 4, c->stream));
+        struct Chunk {
+            int j0, j1;
+            bool check;
+        };
+        std::vector<Chunk> chunks;
+        int j0 = 1;
+        for (int sc = 3; sc <= K; sc += 2) {
+            chunks.push_back({j0, sc, true});
+            j0 = sc + 1;
+        }
+        if (j0 <= K) chunks.push_back({j0, K, false});
+        auto body = [&](const Chunk &ch) -> vne_status {
+            for (int j = ch.j0; j <= ch.j1; ++j) {
+                if (timing) HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1)], c->stream));
+                VNE_TRY(issue(j, 0));
+                if (timing) HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1) + 1], c->stream));
+                VNE_TRY(issue(j, 1));
+            }
+            if (ch.check) {
+                HIP_TRY(c, launch_error_bound_cols(db + ch.j1, M, c->stream));
+                HIP_TRY(c, launch_column_stop(ds + ch.j1, c->stream));
+            }
+            return VNE_OK;
+        };
+        int ran = 0;
+        for (const Chunk &ch : chunks) {
+            if (use_graph && !timing) {
+                hipGraphExec_t &ex = p->chunk_exec[std::make_tuple(key.first, key.second, ch.j0)];
+                if (!ex) VNE_TRY(capture_fn(&ex, [&]() { return body(ch); }));
+                HIP_TRY(c, hipGraphLaunch(ex, c->stream));
+            } else {
+                VNE_TRY(body(ch));
+            }
+            ran = ch.j1;
+            if (ch.check) {
+                HIP_TRY(c, hipMemcpyAsync(p->h_remaining, p->remaining.p, 4, hipMemcpyDeviceToHost, c->stream));
+                HIP_TRY(c, hipStreamSynchronize(c->stream));
+                if (*p->h_remaining == 0) break;
+            }
+        }
+        p->steps_run = ran;
+        if (timing) c->pending.push_back({p, bytes, ran});
+        HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p,
+                                     (const int32_t *)p->k_eff.p, (const double *)p->norm2.p, K, K, p->m_pad,
+                                     (double *)p->psi.p, (int32_t *)p->flags.p, c->stream, nullptr, 0,
+                                     (const int32_t *)p->col_stop.p));
+        return VNE_OK;
+    }
     if (use_graph && !timing) {
         hipGraphExec_t &ex = p->exec[key];
         if (!ex) VNE_TRY(capture(&ex, 1, p->k, -1));
@@ -565,7 +656,7 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         }
     }
     if (tuning) return VNE_OK;
-    if (timing) c->pending.push_back({p, bytes});
+    if (timing) c->pending.push_back({p, bytes, p->k});
     if (p->store) return VNE_OK;   // the Hutch++ sketch needs f(T) e1 (k_fT_e1), not psi
     HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p, (const int32_t *)p->k_eff.p,
                                  (const double *)p->norm2.p, p->k, p->k, p->G * p->m_pad, (double *)p->psi.p,
@@ -758,6 +849,76 @@ vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int
     return copy_out(c, q, &mm, &kk, out, sk);
 }
 
+// Probe spec of a set's queries (one probe kind): Rademacher seeds, or the
+// colours / dense blocks copied into the plan's buffers in stacked row order
+// (a single graph's device arrays are used in place).
+vne_status make_probe_spec(vne_ctx *c, GraphSet *set, Plan *p, const vne_probes *pr, int m_max, bool fp64,
+                           ProbeSpec *ps, int *combine_kind) {
+    const int G = set->G;
+    const int kind = pr[0].kind;
+    const size_t es = fp64 ? 8 : 4;
+    *combine_kind = 0;
+    switch (kind) {
+        case VNE_PROBE_RADEMACHER:
+            ps->gen = GEN_RADEMACHER;
+            for (int q = 0; q < G; ++q) ps->seeds.push_back(pr[q].seed);
+            break;
+        case VNE_PROBE_COLORING: {
+            ps->gen = GEN_COLORING;
+            *combine_kind = 1;
+            if (G == 1 && pr[0].location == VNE_DEVICE) {
+                if (!pr[0].colors) return fail(c, VNE_EINVAL, "colors is NULL");
+                ps->colors = pr[0].colors;
+                break;
+            }
+            std::vector<int32_t> col(set->n);
+            for (int q = 0; q < G; ++q) {
+                if (!pr[q].colors || pr[q].location != VNE_HOST)
+                    return fail(c, VNE_EINVAL, "colors must be host arrays in a batch");
+                const int64_t r0 = set->h_row_begin[q], nq = set->h_row_begin[q + 1] - r0;
+                for (int64_t i = 0; i < nq; ++i) {
+                    const int32_t v = pr[q].colors[i];
+                    if (v < 0 || v >= pr[q].m)
+                        return fail(c, VNE_EINVAL, "colour out of range at row " + std::to_string(i));
+                    col[r0 + i] = v;
+                }
+            }
+            if (!p->colors.p) VNE_TRY(dev_alloc(c, &p->colors, (size_t)set->n * 4));
+            HIP_TRY(c, hipMemcpyAsync(p->colors.p, col.data(), (size_t)set->n * 4, hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            ps->colors = (const int32_t *)p->colors.p;
+            break;
+        }
+        case VNE_PROBE_DENSE: {
+            ps->gen = GEN_DENSE;
+            if (G == 1 && pr[0].location == VNE_DEVICE) {
+                if (!pr[0].dense) return fail(c, VNE_EINVAL, "dense is NULL");
+                ps->dense = pr[0].dense;
+                ps->ld_dense = pr[0].m;
+                break;
+            }
+            std::vector<char> buf((size_t)set->n * m_max * es, 0);
+            for (int q = 0; q < G; ++q) {
+                if (!pr[q].dense || pr[q].location != VNE_HOST)
+                    return fail(c, VNE_EINVAL, "dense blocks must be host arrays in a batch");
+                const int64_t r0 = set->h_row_begin[q], nq = set->h_row_begin[q + 1] - r0;
+                for (int64_t i = 0; i < nq; ++i)
+                    std::memcpy(buf.data() + (size_t)(r0 + i) * m_max * es,
+                                (const char *)pr[q].dense + (size_t)i * pr[q].m * es, (size_t)pr[q].m * es);
+            }
+            if (!p->dense.p) VNE_TRY(dev_alloc(c, &p->dense, buf.size()));
+            HIP_TRY(c, hipMemcpyAsync(p->dense.p, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            ps->dense = p->dense.p;
+            ps->ld_dense = m_max;
+            break;
+        }
+        default:
+            return fail(c, VNE_EINVAL, "unknown probe kind");
+    }
+    return VNE_OK;
+}
+
 // One query per graph of the set, all graphs in one stacked launch per step.
 vne_status estimate_set(vne_ctx *c, GraphSet *set, const vne_probes *pr, const int32_t *k_steps, bool fp64,
                         bool desing, vne_result *out) {
@@ -780,65 +941,7 @@ vne_status estimate_set(vne_ctx *c, GraphSet *set, const vne_probes *pr, const i
     p->h_graph_m = ms;
     ProbeSpec ps;
     int combine_kind = 0;
-    const size_t es = fp64 ? 8 : 4;
-    switch (kind) {
-        case VNE_PROBE_RADEMACHER:
-            ps.gen = GEN_RADEMACHER;
-            for (int q = 0; q < G; ++q) ps.seeds.push_back(pr[q].seed);
-            break;
-        case VNE_PROBE_COLORING: {
-            ps.gen = GEN_COLORING;
-            combine_kind = 1;
-            if (G == 1 && pr[0].location == VNE_DEVICE) {
-                if (!pr[0].colors) return fail(c, VNE_EINVAL, "colors is NULL");
-                ps.colors = pr[0].colors;
-                break;
-            }
-            std::vector<int32_t> col(set->n);
-            for (int q = 0; q < G; ++q) {
-                if (!pr[q].colors || pr[q].location != VNE_HOST)
-                    return fail(c, VNE_EINVAL, "colors must be host arrays in a batch");
-                const int64_t r0 = set->h_row_begin[q], nq = set->h_row_begin[q + 1] - r0;
-                for (int64_t i = 0; i < nq; ++i) {
-                    const int32_t v = pr[q].colors[i];
-                    if (v < 0 || v >= pr[q].m)
-                        return fail(c, VNE_EINVAL, "colour out of range at row " + std::to_string(i));
-                    col[r0 + i] = v;
-                }
-            }
-            if (!p->colors.p) VNE_TRY(dev_alloc(c, &p->colors, (size_t)set->n * 4));
-            HIP_TRY(c, hipMemcpyAsync(p->colors.p, col.data(), (size_t)set->n * 4, hipMemcpyHostToDevice, c->stream));
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            ps.colors = (const int32_t *)p->colors.p;
-            break;
-        }
-        case VNE_PROBE_DENSE: {
-            ps.gen = GEN_DENSE;
-            if (G == 1 && pr[0].location == VNE_DEVICE) {
-                if (!pr[0].dense) return fail(c, VNE_EINVAL, "dense is NULL");
-                ps.dense = pr[0].dense;
-                ps.ld_dense = pr[0].m;
-                break;
-            }
-            std::vector<char> buf((size_t)set->n * m_max * es, 0);
-            for (int q = 0; q < G; ++q) {
-                if (!pr[q].dense || pr[q].location != VNE_HOST)
-                    return fail(c, VNE_EINVAL, "dense blocks must be host arrays in a batch");
-                const int64_t r0 = set->h_row_begin[q], nq = set->h_row_begin[q + 1] - r0;
-                for (int64_t i = 0; i < nq; ++i)
-                    std::memcpy(buf.data() + (size_t)(r0 + i) * m_max * es,
-                                (const char *)pr[q].dense + (size_t)i * pr[q].m * es, (size_t)pr[q].m * es);
-            }
-            if (!p->dense.p) VNE_TRY(dev_alloc(c, &p->dense, buf.size()));
-            HIP_TRY(c, hipMemcpyAsync(p->dense.p, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
-            HIP_TRY(c, hipStreamSynchronize(c->stream));
-            ps.dense = p->dense.p;
-            ps.ld_dense = m_max;
-            break;
-        }
-        default:
-            return fail(c, VNE_EINVAL, "unknown probe kind");
-    }
+    VNE_TRY(make_probe_spec(c, set, p, pr, m_max, fp64, &ps, &combine_kind));
     VNE_TRY(autotune(c, set, p, ps, desing));
     VNE_TRY(run_lanczos(c, set, p, ps, desing));
     HIP_TRY(c, launch_combine_graphs((const double *)p->psi.p, p->m_pad, (const int32_t *)p->graph_m.p, G,
