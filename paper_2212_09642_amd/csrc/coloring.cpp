@@ -7,14 +7,101 @@
 // (number of off-diagonal entries), ties by increasing row index.  Each node
 // takes the smallest colour, counting from 0, that no already coloured node
 // of its neighbourhood carries.
+//
+// The neighbourhoods do not depend on the colours, only the first-fit scan
+// does.  Nodes are therefore taken in chunks of the visiting order: worker
+// threads list, for every node of the next chunk, the neighbours that come
+// earlier in the order (the only ones coloured when the node's turn comes),
+// while the calling thread runs the first-fit scan over the current chunk in
+// order.  The result is the sequential algorithm's colouring exactly.
 #include <algorithm>
+#include <cstdlib>
+#include <memory>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
 
 using namespace vne;
+
+namespace {
+
+// Neighbour lists of one chunk: node t0 + j lists its earlier neighbours in
+// items[begin[j] .. begin[j + 1]) (per worker, nodes interleaved by worker).
+struct ChunkLists {
+    int64_t t0 = 0, t1 = 0;
+    int nw = 1;
+    std::vector<std::vector<int32_t>> items;     // per worker
+    std::vector<std::vector<int64_t>> begin;     // per worker, per owned node + 1
+};
+
+// one per worker thread, on cache lines of its own (the frontier vectors
+// change size on every push)
+class alignas(128) Searcher {
+public:
+    Searcher(int64_t n, const int32_t *rp, const int32_t *ci, int32_t d, const std::vector<int32_t> &pos)
+        : rp_(rp), ci_(ci), d_(d), pos_(pos), seen_(n, -1) {}
+
+    // earlier neighbours (position < pos of i) of node i within distance d
+    void list(int32_t i, int32_t stamp, std::vector<int32_t> *out) {
+        frontier_.clear();
+        frontier_.push_back(i);
+        seen_[i] = stamp;
+        const int32_t pi = pos_[i];
+        for (int32_t depth = 0; depth < d_ && !frontier_.empty(); ++depth) {
+            next_.clear();
+            for (int32_t x : frontier_) {
+                for (int32_t p = rp_[x]; p < rp_[x + 1]; ++p) {
+                    const int32_t y = ci_[p];
+                    if (seen_[y] == stamp) continue;
+                    seen_[y] = stamp;
+                    next_.push_back(y);
+                    if (pos_[y] < pi) out->push_back(y);
+                }
+            }
+            frontier_.swap(next_);
+        }
+    }
+
+private:
+    const int32_t *rp_, *ci_;
+    int32_t d_;
+    const std::vector<int32_t> &pos_;
+    std::vector<int32_t> seen_;
+    std::vector<int32_t> frontier_, next_;
+};
+
+void build_lists(ChunkLists *cl, std::vector<std::unique_ptr<Searcher>> &srch, const std::vector<int32_t> &order) {
+    const int nw = cl->nw;
+    auto work = [&](int w) {
+        // fill vectors local to the thread, hand them over at the end
+        std::vector<int32_t> it;
+        std::vector<int64_t> bg;
+        it.swap(cl->items[w]);
+        bg.swap(cl->begin[w]);
+        it.clear();
+        bg.clear();
+        bg.push_back(0);
+        for (int64_t t = cl->t0 + w; t < cl->t1; t += nw) {
+            srch[w]->list(order[t], (int32_t)t, &it);
+            bg.push_back((int64_t)it.size());
+        }
+        cl->items[w].swap(it);
+        cl->begin[w].swap(bg);
+    };
+    if (nw == 1) {
+        work(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int w = 1; w < nw; ++w) th.emplace_back(work, w);
+    work(0);
+    for (auto &x : th) x.join();
+}
+
+}  // namespace
 
 int32_t vne::greedy_color(int64_t n, const int32_t *rp, const int32_t *ci, int32_t d, int32_t *colors_out) {
     std::vector<int32_t> deg(n);
@@ -27,35 +114,62 @@ int32_t vne::greedy_color(int64_t n, const int32_t *rp, const int32_t *ci, int32
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+    std::vector<int32_t> pos(n);
+    for (int64_t t = 0; t < n; ++t) pos[order[t]] = (int32_t)t;
+
+    int nw = (int)std::thread::hardware_concurrency();
+    if (const char *e = std::getenv("VNE_COLOR_THREADS")) nw = std::atoi(e);
+    nw = std::max(1, std::min(nw, 16));
+    if (n < 4096) nw = 1;
+    std::vector<std::unique_ptr<Searcher>> srch;
+    for (int w = 0; w < nw; ++w) srch.emplace_back(new Searcher(n, rp, ci, d, pos));
 
     std::vector<int32_t> color(n, -1);
-    std::vector<int64_t> seen(n, -1);         // stamp: last search that reached the node
-    std::vector<int64_t> banned;               // stamp per colour
-    std::vector<int32_t> frontier, next;
+    std::vector<int64_t> banned;                 // stamp per colour
     int32_t ncol = 0;
-    for (int64_t t = 0; t < n; ++t) {
-        const int32_t i = order[t];
-        frontier.clear();
-        frontier.push_back(i);
-        seen[i] = t;
-        for (int32_t depth = 0; depth < d && !frontier.empty(); ++depth) {
-            next.clear();
-            for (int32_t x : frontier) {
-                for (int32_t p = rp[x]; p < rp[x + 1]; ++p) {
-                    int32_t y = ci[p];
-                    if (seen[y] == t) continue;
-                    seen[y] = t;
-                    next.push_back(y);
-                    int32_t c = color[y];
-                    if (c >= 0) banned[c] = t;
-                }
+    // chunk sizes: aim at about 2^24 listed neighbours per chunk
+    const int64_t kBudget = int64_t(1) << 24;
+    int64_t chunk = std::min<int64_t>(n, 1024);
+    ChunkLists cur, nxt;
+    cur.nw = nxt.nw = nw;
+    cur.items.resize(nw);
+    cur.begin.resize(nw);
+    nxt.items.resize(nw);
+    nxt.begin.resize(nw);
+    cur.t0 = 0;
+    cur.t1 = chunk;
+    build_lists(&cur, srch, order);
+    while (cur.t0 < n) {
+        // size the next chunk from this one's mean list length
+        int64_t total = 0;
+        for (int w = 0; w < nw; ++w) total += (int64_t)cur.items[w].size();
+        const double mean = std::max(1.0, (double)total / (double)std::max<int64_t>(1, cur.t1 - cur.t0));
+        chunk = std::max<int64_t>(256, std::min<int64_t>(1 << 16, (int64_t)(kBudget / mean)));
+        nxt.t0 = cur.t1;
+        nxt.t1 = std::min<int64_t>(n, cur.t1 + chunk);
+        std::thread lister;
+        if (nxt.t0 < n) lister = std::thread([&]() { build_lists(&nxt, srch, order); });
+        // first-fit scan of the current chunk, in order
+        for (int64_t t = cur.t0; t < cur.t1; ++t) {
+            const int64_t r = t - cur.t0;
+            const int w = (int)(r % nw);
+            const int64_t slot = r / nw;
+            const auto &it = cur.items[w];
+            for (int64_t q = cur.begin[w][slot]; q < cur.begin[w][slot + 1]; ++q) {
+                const int32_t c = color[it[q]];
+                banned[c] = t;
             }
-            frontier.swap(next);
+            int32_t c = 0;
+            while (c < ncol && banned[c] == t) ++c;
+            if (c == ncol) {
+                ncol++;
+                banned.push_back(-1);
+            }
+            color[order[t]] = c;
         }
-        int32_t c = 0;
-        while (c < ncol && banned[c] == t) ++c;
-        if (c == ncol) { ncol++; banned.push_back(-1); }
-        color[i] = c;
+        if (lister.joinable()) lister.join();
+        std::swap(cur, nxt);
+        if (cur.t0 >= n) break;
     }
     std::copy(color.begin(), color.end(), colors_out);
     return ncol;
