@@ -33,6 +33,20 @@ def large():
                 fp64=False)
 
 
+def probing_eps(graph="ws", n=1_000_000, rel_eps=1e-3):
+    """Algorithm 2 (probing with a relative target): the probing graph (WS
+    n=1e6, k=10, p=0.1; small-world) or the same ring without rewiring (a
+    large-world lattice whose entropy has a closed form), FP32 vectors."""
+    if graph == "ring":
+        n, e = graphs.ring_lattice(n, 10)
+        seed = None
+    else:
+        n, e = graphs.watts_strogatz(n, 10, 0.1, GRAPH_SEED_PROBING)
+        seed = GRAPH_SEED_PROBING
+    name = "%s%d_k10%s_alg2_eps%g_f32" % (graph, n, "_p0.1" if graph == "ws" else "", rel_eps)
+    return dict(name=name, n_nodes=n, edges=e, graph_seed=seed, rel_eps=rel_eps, graph=graph, fp64=False)
+
+
 def probing(n=1_000_000):
     """WS n=1e6, k=10, p=0.1; greedy distance-2 coloring, 80 steps, FP32."""
     n, e = graphs.watts_strogatz(n, 10, 0.1, GRAPH_SEED_PROBING)

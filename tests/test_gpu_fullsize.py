@@ -126,3 +126,26 @@ def test_probing_ring_lattice_exact_entropy(ctx):
     _say("   colours %d, S = %.10f, estimate %.10f, |err| = %.3e (rel %.2e), Corollary 3.2 bound %.3e"
          % (s, S, out["estimate"], err, err / S, bound))
     assert err <= bound
+
+
+def test_algorithm_2_ring_lattice_full_size(ctx):
+    """Algorithm 2 at eps = 1e-3 on the ring lattice n = 1e6, k = 10 (the
+    probing configuration without rewiring) against its closed-form entropy;
+    every colour meets its eq. (5.3) tolerance."""
+    _say("case full size: Algorithm 2, ring lattice n=1e6, eps=1e-3")
+    import bench
+    import synth
+    n, kk, eps = 1_000_000, 10, 1e-3
+    nn, e = synth.ring_lattice(n, kk)
+    g = vne.laplacian_from_edges(nn, e, np.float32)
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    out = ctx.probing(gid, eps, d_max=16, k_max=128)
+    S = bench.ring_lattice_entropy(n, kk)
+    err = abs(out["estimate"] - S) / S
+    _say("   d=%d colours %d passes %d, estimate %.10f, S %.10f, rel err %.2e, colouring %.0f ms, Lanczos %.0f ms"
+         % (out["d"], out["n_colors"], out["passes"], out["estimate"], S, err, out["color_ms"], out["lanczos_ms"]))
+    assert out["unconverged"] == 0
+    assert err <= eps
+    # the probing sums of a Laplacian are lower bounds (Proposition 3.6), up to the Krylov part
+    assert max(out["t_pre"]) <= S + out["eps_hat"]
+    ctx.release(gid)
