@@ -49,6 +49,11 @@ struct Plan {
     std::vector<char> h_adapt;
     std::map<std::tuple<int, int, int>, hipGraphExec_t> chunk_exec;
     int steps_run = 0;               // steps the block ran in the last run
+    // values last uploaded to graph_k / graph_m / seeds (skipped when equal)
+    std::vector<int32_t> up_graph_k, up_graph_m;
+    std::vector<uint64_t> up_seeds;
+    void *h_stage = nullptr;         // pinned staging of copy_out
+    size_t h_stage_bytes = 0;
 };
 
 struct Graph {

@@ -767,15 +767,35 @@ __device__ __forceinline__ void update_coefficients(const FinalizeArgs &a, int g
 }
 
 // Second level (one graph): sum the R first-level rows in order, update.
+// With R = kLevel2 every row is loaded before the first add, so the loads
+// overlap instead of forming a chain of dependent round trips; the sums keep
+// the same order.
 __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs a) {
     const int c = blockIdx.x * 64 + threadIdx.x;
     if (c >= a.m_pad) return;
     double svw = 0.0, sww = 0.0, svv = 0.0;
-    for (int r = 0; r < a.n_level2; ++r) {
-        const double *p = a.level2 + (int64_t)r * 3 * a.m_pad + c;
-        svw += p[0];
-        sww += p[a.m_pad];
-        svv += p[2 * a.m_pad];
+    if (a.n_level2 == kLevel2) {
+        double v[kLevel2][3];
+#pragma unroll
+        for (int r = 0; r < kLevel2; ++r) {
+            const double *p = a.level2 + (int64_t)r * 3 * a.m_pad + c;
+            v[r][0] = p[0];
+            v[r][1] = p[a.m_pad];
+            v[r][2] = p[2 * a.m_pad];
+        }
+#pragma unroll
+        for (int r = 0; r < kLevel2; ++r) {
+            svw += v[r][0];
+            sww += v[r][1];
+            svv += v[r][2];
+        }
+    } else {
+        for (int r = 0; r < a.n_level2; ++r) {
+            const double *p = a.level2 + (int64_t)r * 3 * a.m_pad + c;
+            svw += p[0];
+            sww += p[a.m_pad];
+            svv += p[2 * a.m_pad];
+        }
     }
     update_coefficients(a, 0, c, svw, sww, svv);
 }
@@ -787,7 +807,27 @@ __global__ void __launch_bounds__(256) k_finalize_graphs(FinalizeArgs a) {
     if (t >= (int64_t)a.n_graphs * a.m_pad) return;
     const int g = (int)(t / a.m_pad), c = (int)(t % a.m_pad);
     double svw = 0.0, sww = 0.0, svv = 0.0;
-    for (int bb = a.graph_block_begin[g]; bb < a.graph_block_begin[g + 1]; ++bb) {
+    // batches of 8 partials loaded before they are added (same order)
+    constexpr int UB = 8;
+    const int b0 = a.graph_block_begin[g], b1 = a.graph_block_begin[g + 1];
+    int bb = b0;
+    for (; bb + UB <= b1; bb += UB) {
+        double v[UB][3];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const double *p = a.partials + (int64_t)(bb + u) * 3 * a.m_pad + c;
+            v[u][0] = p[0];
+            v[u][1] = p[a.m_pad];
+            v[u][2] = p[2 * a.m_pad];
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            svw += v[u][0];
+            sww += v[u][1];
+            svv += v[u][2];
+        }
+    }
+    for (; bb < b1; ++bb) {
         const double *p = a.partials + (int64_t)bb * 3 * a.m_pad + c;
         svw += p[0];
         sww += p[a.m_pad];
@@ -861,11 +901,28 @@ __global__ void __launch_bounds__(kFinalizeCols) k_finalize_slots(const Finalize
     const int c = e.y * kFinalizeCols + threadIdx.x;
     if (c >= a.m_pad) return;
     double svw = 0.0, sww = 0.0, svv = 0.0;
-    for (int r = 0; r < a.n_level2; ++r) {
-        const double *p = a.level2 + (int64_t)r * 3 * a.m_pad + c;
-        svw += p[0];
-        sww += p[a.m_pad];
-        svv += p[2 * a.m_pad];
+    if (a.n_level2 == kSlotLevel2) {
+        double v[kSlotLevel2][3];
+#pragma unroll
+        for (int r = 0; r < kSlotLevel2; ++r) {
+            const double *p = a.level2 + (int64_t)r * 3 * a.m_pad + c;
+            v[r][0] = p[0];
+            v[r][1] = p[a.m_pad];
+            v[r][2] = p[2 * a.m_pad];
+        }
+#pragma unroll
+        for (int r = 0; r < kSlotLevel2; ++r) {
+            svw += v[r][0];
+            sww += v[r][1];
+            svv += v[r][2];
+        }
+    } else {
+        for (int r = 0; r < a.n_level2; ++r) {
+            const double *p = a.level2 + (int64_t)r * 3 * a.m_pad + c;
+            svw += p[0];
+            sww += p[a.m_pad];
+            svv += p[2 * a.m_pad];
+        }
     }
     update_coefficients(a, 0, c, svw, sww, svv);
 }

@@ -94,6 +94,9 @@ void free_plan(vne_ctx *c, Plan *p) {
     p->ev.clear();
     if (p->h_remaining) (void)hipHostFree(p->h_remaining);
     p->h_remaining = nullptr;
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    p->h_stage = nullptr;
+    p->h_stage_bytes = 0;
     DevBuf *all[] = {&p->P[0], &p->P[1], &p->V[0], &p->V[1], &p->Vstore, &p->alpha, &p->beta,
                      &p->st_alpha, &p->st_inv, &p->st_coup, &p->k_eff, &p->norm2, &p->mean, &p->psi,
                      &p->estimate, &p->flags, &p->partials, &p->level2, &p->probe_part, &p->seg_acc,
@@ -367,10 +370,21 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
     const Schedule &s = set->sched;
     const int mt = opt.tile > 0 ? opt.tile : p->mt;
     HIP_TRY(c, hipMemsetAsync(p->flags.p, 0, 4, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(p->graph_k.p, p->h_graph_k.data(), p->G * 4, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(p->graph_m.p, p->h_graph_m.data(), p->G * 4, hipMemcpyHostToDevice, c->stream));
-    if (!ps.seeds.empty())
+    // per-graph steps, widths and seeds: uploaded only when they change (a
+    // copy from pageable memory waits for the stream, which would expose the
+    // host's launch latency between the phases of one estimate)
+    if (p->up_graph_k != p->h_graph_k) {
+        HIP_TRY(c, hipMemcpyAsync(p->graph_k.p, p->h_graph_k.data(), p->G * 4, hipMemcpyHostToDevice, c->stream));
+        p->up_graph_k = p->h_graph_k;
+    }
+    if (p->up_graph_m != p->h_graph_m) {
+        HIP_TRY(c, hipMemcpyAsync(p->graph_m.p, p->h_graph_m.data(), p->G * 4, hipMemcpyHostToDevice, c->stream));
+        p->up_graph_m = p->h_graph_m;
+    }
+    if (!ps.seeds.empty() && p->up_seeds != ps.seeds) {
         HIP_TRY(c, hipMemcpyAsync(p->seeds.p, ps.seeds.data(), p->G * 8, hipMemcpyHostToDevice, c->stream));
+        p->up_seeds = ps.seeds;
+    }
     ProbeArgs pa{};
     pa.gen = ps.gen;
     pa.n = (int32_t)set->n;
@@ -751,16 +765,30 @@ vne_status copy_out(vne_ctx *c, Plan *p, const int32_t *m, const int32_t *k, vne
         any_keff |= out[q].k_eff != nullptr;
         any_norm |= out[q].norm2 != nullptr;
     }
-    std::vector<double> est(G), psi(any_quad ? cols : 0), nrm(any_norm ? cols : 0);
-    std::vector<double> al(any_alpha ? cols * p->k : 0), be(any_beta ? cols * p->k : 0);
-    std::vector<int32_t> ke(any_keff ? cols : 0);
-    int32_t fl[2] = {0, 0};
-    HIP_TRY(c, hipMemcpyAsync(est.data(), p->estimate.p, (size_t)G * 8, hipMemcpyDeviceToHost, s));
-    if (any_quad) HIP_TRY(c, hipMemcpyAsync(psi.data(), p->psi.p, cols * 8, hipMemcpyDeviceToHost, s));
-    if (any_norm) HIP_TRY(c, hipMemcpyAsync(nrm.data(), p->norm2.p, cols * 8, hipMemcpyDeviceToHost, s));
-    if (any_keff) HIP_TRY(c, hipMemcpyAsync(ke.data(), p->k_eff.p, cols * 4, hipMemcpyDeviceToHost, s));
-    if (any_alpha) HIP_TRY(c, hipMemcpyAsync(al.data(), p->alpha.p, al.size() * 8, hipMemcpyDeviceToHost, s));
-    if (any_beta) HIP_TRY(c, hipMemcpyAsync(be.data(), p->beta.p, be.size() * 8, hipMemcpyDeviceToHost, s));
+    // every array goes into one pinned staging buffer of the plan, so the
+    // copies queue without waiting and the call synchronises once
+    const size_t n_est = (size_t)G, n_psi = any_quad ? cols : 0, n_nrm = any_norm ? cols : 0;
+    const size_t n_al = any_alpha ? cols * p->k : 0, n_be = any_beta ? cols * p->k : 0;
+    const size_t n_ke = any_keff ? cols : 0;
+    const size_t need = 8 * (n_est + n_psi + n_nrm + n_al + n_be) + 4 * n_ke + 8;
+    if (p->h_stage_bytes < need) {
+        if (p->h_stage) HIP_TRY(c, hipHostFree(p->h_stage));
+        p->h_stage = nullptr;
+        p->h_stage_bytes = 0;
+        HIP_TRY(c, hipHostMalloc(&p->h_stage, need, hipHostMallocDefault));
+        p->h_stage_bytes = need;
+    }
+    double *est = (double *)p->h_stage;
+    double *psi = est + n_est, *nrm = psi + n_psi, *al = nrm + n_nrm, *be = al + n_al;
+    int32_t *ke = (int32_t *)(be + n_be);
+    int32_t *fl = ke + n_ke;
+    fl[0] = fl[1] = 0;
+    HIP_TRY(c, hipMemcpyAsync(est, p->estimate.p, n_est * 8, hipMemcpyDeviceToHost, s));
+    if (n_psi) HIP_TRY(c, hipMemcpyAsync(psi, p->psi.p, n_psi * 8, hipMemcpyDeviceToHost, s));
+    if (n_nrm) HIP_TRY(c, hipMemcpyAsync(nrm, p->norm2.p, n_nrm * 8, hipMemcpyDeviceToHost, s));
+    if (n_ke) HIP_TRY(c, hipMemcpyAsync(ke, p->k_eff.p, n_ke * 4, hipMemcpyDeviceToHost, s));
+    if (n_al) HIP_TRY(c, hipMemcpyAsync(al, p->alpha.p, n_al * 8, hipMemcpyDeviceToHost, s));
+    if (n_be) HIP_TRY(c, hipMemcpyAsync(be, p->beta.p, n_be * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(&fl[0], p->flags.p, 4, hipMemcpyDeviceToHost, s));
     if (extra) HIP_TRY(c, hipMemcpyAsync(&fl[1], extra->flags.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -769,12 +797,12 @@ vne_status copy_out(vne_ctx *c, Plan *p, const int32_t *m, const int32_t *k, vne
         const size_t c0 = (size_t)q * p->m_pad;
         vne_result &o = out[q];
         o.estimate = est[q];
-        if (o.quad) std::memcpy(o.quad, psi.data() + c0, (size_t)m[q] * 8);
-        if (o.norm2) std::memcpy(o.norm2, nrm.data() + c0, (size_t)m[q] * 8);
-        if (o.k_eff) std::memcpy(o.k_eff, ke.data() + c0, (size_t)m[q] * 4);
+        if (o.quad) std::memcpy(o.quad, psi + c0, (size_t)m[q] * 8);
+        if (o.norm2) std::memcpy(o.norm2, nrm + c0, (size_t)m[q] * 8);
+        if (o.k_eff) std::memcpy(o.k_eff, ke + c0, (size_t)m[q] * 4);
         for (int col = 0; col < m[q]; ++col) {
-            if (o.alpha) std::memcpy(o.alpha + (size_t)col * k[q], al.data() + (c0 + col) * p->k, (size_t)k[q] * 8);
-            if (o.beta) std::memcpy(o.beta + (size_t)col * k[q], be.data() + (c0 + col) * p->k, (size_t)k[q] * 8);
+            if (o.alpha) std::memcpy(o.alpha + (size_t)col * k[q], al + (c0 + col) * p->k, (size_t)k[q] * 8);
+            if (o.beta) std::memcpy(o.beta + (size_t)col * k[q], be + (c0 + col) * p->k, (size_t)k[q] * 8);
         }
     }
     return check_flags(c, fl[0] | fl[1]);
