@@ -1266,6 +1266,125 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// e1^T f(T) e1 for f = -x log x (the value of the Gauss rule of eq. (4.2))
+// without diagonalising T.  With sigma >= lambda_max(T) (Gershgorin) and
+// T~ = T / sigma, f(T) = sigma f(T~) - sigma log(sigma) T~; for 0 <= x <= 1,
+// -x log x = x (1 - x) int_0^inf dt / ((x + t)(1 + t)), so
+// e1^T f(T~) e1 = int_0^inf u^T (T~ + t I)^{-1} e1 dt / (1 + t) with
+// u = T~ (I - T~) e1, whose only nonzero entries are the first three.  The
+// first three entries of (T~ + t I)^{-1} e1 follow from the pivots of the
+// bottom-up elimination d_k = a_k + t, d_j = a_j + t - b_j^2 / d_{j+1}, all
+// positive while T~ + t I is positive definite.
+//
+// The integral runs from t0 = 2 c, c the smallest of 5e-16, 5e-14, ...,
+// 5e-8 at which T~ + c I is positive definite (checked by the same
+// elimination), so every eigenvalue of T~ + t I at the nodes is at least
+// t / 2.  c is 5e-16 unless T has negative Ritz values beyond rounding of
+// the coefficients (with FP32 vectors a component along a null vector can
+// give -1e-8 sigma); the eigen route gives such values f = 0.  The part
+// below t0 is t0 (1 - a_1) to first order (the integrand tends to
+// e1^T (I - T~) e1 as t -> 0), added as is.  With t = e^s the rule is the
+// trapezoidal one in s on [ln t0, 37] with kQuadNodes points (three per
+// lane): the integrand is analytic in a strip of half-width pi about the
+// real axis, so the error falls geometrically with the spacing (below 1e-14
+// relative against diagonalisation at t0 = 1e-15, on Lanczos matrices of
+// graphs and on a spectrum spanning 1e-3..1e3).  Returns false, for the
+// whole wave, if no shift makes T~ positive definite: the caller then
+// diagonalises.
+constexpr int kQuadNodes = 192;
+
+template <int NH>
+__device__ bool e1_fT_e1_integral(const LaneTri &t, int ke, int lane, double &out) {
+    // Gershgorin bound of T: |alpha_r| + |beta_{r-1}| + |beta_r| over the rows
+    const double up0 = __shfl_up(t.e0, 1, 64);
+    const double prev0 = lane == 0 ? 0.0 : up0;
+    double g = lane < ke ? fabs(t.d0) + fabs(t.e0) + fabs(prev0) : 0.0;
+    if (NH == 2) {
+        const double up1 = __shfl_up(t.e1, 1, 64);
+        const double prev1 = lane == 0 ? readlane_d(t.e0, 63) : up1;
+        g = fmax(g, lane + 64 < ke ? fabs(t.d1) + fabs(t.e1) + fabs(prev1) : 0.0);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o, 64));
+    const double sigma = g;
+    if (!(sigma > 0.0)) {
+        out = 0.0;                       // T = 0: f(0) = 0
+        return true;
+    }
+    const double is = 1.0 / sigma;
+    // 1. positive definiteness of T~ + c I for the candidate shifts
+    constexpr int NC = 5;
+    const double shift[NC] = {5e-16, 5e-14, 5e-12, 5e-10, 5e-8};
+    double ic[NC];
+    bool pc[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        ic[q] = 0.0;
+        pc[q] = true;
+    }
+    for (int j = ke - 1; j >= 0; --j) {
+        const double aj = get_row<NH>(t.d0, t.d1, j) * is;
+        const double bj = j < ke - 1 ? get_row<NH>(t.e0, t.e1, j) * is : 0.0;
+        const double bj2 = bj * bj;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const double d = fma(-bj2, ic[q], aj + shift[q]);
+            pc[q] = pc[q] && d > 0.0;
+            ic[q] = 1.0 / d;
+        }
+    }
+    double c0 = -1.0;
+#pragma unroll
+    for (int q = NC - 1; q >= 0; --q) c0 = pc[q] ? shift[q] : c0;
+    // wave-uniform data: every lane took the same decisions
+    c0 = readlane_d(c0, 0);
+    if (c0 < 0.0) return false;
+    // 2. the trapezoidal rule on [ln t0, 37]
+    const double t0 = 2.0 * c0;
+    const double s_lo = log(t0);
+    const double s_hi = 37.0;
+    const double h = (s_hi - s_lo) / (double)(kQuadNodes - 1);
+    double tt[3], inv[3], inv1[3], inv2[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        tt[q] = exp(s_lo + h * (double)(lane + 64 * q));
+        inv[q] = 0.0;
+        inv1[q] = inv2[q] = 0.0;
+    }
+    for (int j = ke - 1; j >= 0; --j) {
+        const double aj = get_row<NH>(t.d0, t.d1, j) * is;
+        const double bj = j < ke - 1 ? get_row<NH>(t.e0, t.e1, j) * is : 0.0;
+        const double bj2 = bj * bj;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double d = fma(-bj2, inv[q], aj + tt[q]);
+            inv[q] = 1.0 / d;
+            if (j == 2) inv2[q] = inv[q];
+            if (j == 1) inv1[q] = inv[q];
+        }
+    }
+    const double a0 = get_row<NH>(t.d0, t.d1, 0) * is;
+    const double a1 = ke > 1 ? get_row<NH>(t.d0, t.d1, 1) * is : 0.0;
+    const double b0 = ke > 1 ? get_row<NH>(t.e0, t.e1, 0) * is : 0.0;
+    const double b1 = ke > 2 ? get_row<NH>(t.e0, t.e1, 1) * is : 0.0;
+    const double u1 = a0 - a0 * a0 - b0 * b0;
+    const double u2 = b0 * (1.0 - a0 - a1);
+    const double u3 = -b0 * b1;
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int n = lane + 64 * q;
+        const double y1 = inv[q];
+        const double y2 = ke > 1 ? -b0 * y1 * inv1[q] : 0.0;
+        const double y3 = ke > 2 ? -b1 * y2 * inv2[q] : 0.0;
+        const double w = (n == 0 || n == kQuadNodes - 1) ? 0.5 * h : h;
+        part += w * (u1 * y1 + u2 * y2 + u3 * y3) * (tt[q] / (1.0 + tt[q]));
+    }
+    const double integral = wave_sum(part) + t0 * (1.0 - a0);
+    out = sigma * integral - log(sigma) * (a0 * sigma);
+    return true;
+}
+
 __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const double *beta,
                                                     const int32_t *k_eff, const double *norm2, int32_t k,
                                                     int32_t steps, int32_t m, double *psi, int32_t *flags,
@@ -1288,6 +1407,12 @@ __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const d
     }
     LaneTri t;
     load_tri(t, alpha + (int64_t)c * k, beta + (int64_t)c * k, ke, lane);
+    double val = 0.0;
+    const bool done = ke <= 64 ? e1_fT_e1_integral<1>(t, ke, lane, val) : e1_fT_e1_integral<2>(t, ke, lane, val);
+    if (done) {
+        if (lane == 0) psi[c] = norm2[c] * val;
+        return;
+    }
     const int st = ke <= 64 ? lane_tridiag_qr<false, 1>(t, ke, lane, nullptr, 0, nullptr)
                             : lane_tridiag_qr<false, 2>(t, ke, lane, nullptr, 0, nullptr);
     double part = 0.0;
