@@ -148,18 +148,20 @@ hipError_t launch_rademacher_fill(void *out, bool fp64, int32_t n, int32_t m, in
 // Gauss quadrature of every column after min(k_eff[c], steps) steps:
 // psi[c] = norm2[c] e1^T f(T) e1 (1 <= steps <= k).  With `stop` given, a
 // record {uid, j > 0} there lowers steps to j (a-posteriori stopping); with
-// col_stop given, col_stop[c] > 0 lowers column c's steps to it.
+// col_stop given, col_stop[c] > 0 lowers column c's steps to it.  fp64: the
+// coefficients come from FP64 vectors (tighter limit on the shift of the
+// integral route, see kernels.hip).
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
                              const double *norm2, int32_t k, int32_t steps, int32_t m, double *psi,
-                             int32_t *flags, hipStream_t s, const int2 *stop = nullptr, int32_t uid = 0,
-                             const int32_t *col_stop = nullptr);
+                             int32_t *flags, hipStream_t s, bool fp64, const int2 *stop = nullptr,
+                             int32_t uid = 0, const int32_t *col_stop = nullptr);
 // f(T) e1 for every column (rows >= k_eff are 0), step-major: S[r*m + c]; rot_scratch
 // holds rot_capacity(k) recorded rotations (24 bytes each) per column
 __host__ __device__ int64_t rot_capacity(int32_t k);
 constexpr int64_t kRotBytes = 24;
 hipError_t launch_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff,
                         int32_t k, int32_t m, double *S, void *rot_scratch, int32_t *flags,
-                        hipStream_t s);
+                        hipStream_t s, bool fp64);
 
 // Theorem 4.8 bracket per column (see kernels.hip): one problem = m columns
 // of Lanczos coefficients (layout [m][k]) after `steps` steps

@@ -1277,11 +1277,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 // positive while T~ + t I is positive definite.
 //
 // The integral runs from t0 = 2 c, c the smallest of 5e-16, 5e-14, ...,
-// 5e-8 at which T~ + c I is positive definite (checked by the same
-// elimination), so every eigenvalue of T~ + t I at the nodes is at least
-// t / 2.  c is 5e-16 unless T has negative Ritz values beyond rounding of
-// the coefficients (with FP32 vectors a component along a null vector can
-// give -1e-8 sigma); the eigen route gives such values f = 0.  The part
+// 5e-8 (at most shift_max + 1 of them) at which T~ + c I is positive
+// definite (checked by the same elimination), so every eigenvalue of
+// T~ + t I at the nodes is at least t / 2.  c is 5e-16 unless T has negative
+// Ritz values beyond rounding of the coefficients (with FP32 vectors a
+// component along a null vector can give -1e-8 sigma); the eigen route
+// gives such values f = 0, and the integral differs from it by about c
+// relative.  The part
 // below t0 is t0 (1 - a_1) to first order (the integrand tends to
 // e1^T (I - T~) e1 as t -> 0), added as is.  With t = e^s the rule is the
 // trapezoidal one in s on [ln t0, 37] with kQuadNodes points (three per
@@ -1289,19 +1291,20 @@ __device__ __forceinline__ double wave_sum(double v) {
 // real axis, so the error falls geometrically with the spacing (below 1e-14
 // relative against diagonalisation at t0 = 1e-15, on Lanczos matrices of
 // graphs and on a spectrum spanning 1e-3..1e3).  Returns false, for the
-// whole wave, if no shift makes T~ positive definite: the caller then
-// diagonalises.
+// whole wave, if no allowed shift makes T~ positive definite: the caller
+// then diagonalises.
 constexpr int kQuadNodes = 192;
 
 template <int NH>
-__device__ bool e1_fT_e1_integral(const LaneTri &t, int ke, int lane, double &out) {
+__device__ bool e1_fT_e1_integral(const LaneTri &t, int ke, int lane, int shift_max, double &out) {
     // Gershgorin bound of T: |alpha_r| + |beta_{r-1}| + |beta_r| over the rows
     const double up0 = __shfl_up(t.e0, 1, 64);
     const double prev0 = lane == 0 ? 0.0 : up0;
     double g = lane < ke ? fabs(t.d0) + fabs(t.e0) + fabs(prev0) : 0.0;
     if (NH == 2) {
         const double up1 = __shfl_up(t.e1, 1, 64);
-        const double prev1 = lane == 0 ? readlane_d(t.e0, 63) : up1;
+        const double e63 = readlane_d(t.e0, 63);
+        const double prev1 = lane == 0 ? e63 : up1;
         g = fmax(g, lane + 64 < ke ? fabs(t.d1) + fabs(t.e1) + fabs(prev1) : 0.0);
     }
 #pragma unroll
@@ -1335,7 +1338,7 @@ __device__ bool e1_fT_e1_integral(const LaneTri &t, int ke, int lane, double &ou
     }
     double c0 = -1.0;
 #pragma unroll
-    for (int q = NC - 1; q >= 0; --q) c0 = pc[q] ? shift[q] : c0;
+    for (int q = NC - 1; q >= 0; --q) c0 = (pc[q] && q <= shift_max) ? shift[q] : c0;
     // wave-uniform data: every lane took the same decisions
     c0 = readlane_d(c0, 0);
     if (c0 < 0.0) return false;
@@ -1388,7 +1391,8 @@ __device__ bool e1_fT_e1_integral(const LaneTri &t, int ke, int lane, double &ou
 __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const double *beta,
                                                     const int32_t *k_eff, const double *norm2, int32_t k,
                                                     int32_t steps, int32_t m, double *psi, int32_t *flags,
-                                                    const int2 *stop, int32_t uid, const int32_t *col_stop) {
+                                                    const int2 *stop, int32_t uid, const int32_t *col_stop,
+                                                    int32_t shift_max) {
     const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (c >= m) return;
@@ -1408,7 +1412,8 @@ __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const d
     LaneTri t;
     load_tri(t, alpha + (int64_t)c * k, beta + (int64_t)c * k, ke, lane);
     double val = 0.0;
-    const bool done = ke <= 64 ? e1_fT_e1_integral<1>(t, ke, lane, val) : e1_fT_e1_integral<2>(t, ke, lane, val);
+    const bool done = ke <= 64 ? e1_fT_e1_integral<1>(t, ke, lane, shift_max, val)
+                               : e1_fT_e1_integral<2>(t, ke, lane, shift_max, val);
     if (done) {
         if (lane == 0) psi[c] = norm2[c] * val;
         return;
@@ -1609,37 +1614,27 @@ hipError_t launch_column_stop(const ColStopArgs *args, hipStream_t s) {
 
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
                              const double *norm2, int32_t k, int32_t steps, int32_t m, double *psi,
-                             int32_t *flags, hipStream_t s, const int2 *stop, int32_t uid,
+                             int32_t *flags, hipStream_t s, bool fp64, const int2 *stop, int32_t uid,
                              const int32_t *col_stop) {
     if (k > kMaxSteps || steps < 1 || steps > k) return hipErrorInvalidValue;
+    // FP64 vectors: shifts up to 5e-14 (below 1e-13 relative); FP32: up to 5e-8
+    const int32_t shift_max = fp64 ? 1 : 4;
     hipLaunchKernelGGL(k_quadrature, dim3((m + 3) / 4), dim3(256), 0, s, alpha, beta, k_eff, norm2, k, steps, m,
-                       psi, flags, stop, uid, col_stop);
+                       psi, flags, stop, uid, col_stop, shift_max);
     return hipGetLastError();
 }
 
 __host__ __device__ int64_t rot_capacity(int32_t k) { return 4 * (int64_t)k * k + 64; }
 
 // f(T) e1 = Z f(theta) Z^T e1: QR with the rotations recorded, then the
-// rotations are applied in reverse order to w = f(theta) .* z.
-__global__ void __launch_bounds__(256) k_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff,
-                                               int32_t k, int32_t m, double *S, Rot *rot_buf, int32_t *flags) {
-    const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    if (c >= m) return;
-    const int ke = __builtin_amdgcn_readfirstlane(k_eff[c]);
-    // S is stored step-major: S[r * m + c]
-    if (lane < k) S[(int64_t)lane * m + c] = 0.0;
-    if (lane + 64 < k) S[(int64_t)(lane + 64) * m + c] = 0.0;
-    if (ke <= 0) return;
-    LaneTri t;
-    load_tri(t, alpha + (int64_t)c * k, beta + (int64_t)c * k, ke, lane);
-    const int cap = (int)rot_capacity(k);
-    Rot *rot = rot_buf + (int64_t)c * cap;
+// rotations are applied in reverse order to w = f(theta) .* z.  Rows of the
+// result come back lane-resident in w0 (rows 0..63) and w1 (64..127).
+template <int NH>
+__device__ int fT_e1_qr(LaneTri t, int ke, int lane, Rot *rot, int cap, double &w0, double &w1) {
     int nrot = 0;
-    const int st = ke <= 64 ? lane_tridiag_qr<true, 1>(t, ke, lane, rot, cap, &nrot)
-                            : lane_tridiag_qr<true, 2>(t, ke, lane, rot, cap, &nrot);
-    double w0 = lane < ke ? f_entropy(t.d0) * t.z0 : 0.0;
-    double w1 = lane + 64 < ke ? f_entropy(t.d1) * t.z1 : 0.0;
+    const int st = lane_tridiag_qr<true, NH>(t, ke, lane, rot, cap, &nrot);
+    w0 = lane < ke ? f_entropy(t.d0) * t.z0 : 0.0;
+    w1 = lane + 64 < ke ? f_entropy(t.d1) * t.z1 : 0.0;
     // the wave's own record, read back in reverse order in chunks of 64 (lane
     // j of a chunk holds rotation top - 64 + j); the next chunk is in flight
     // while the current one is applied
@@ -1676,16 +1671,159 @@ __global__ void __launch_bounds__(256) k_fT_e1(const double *alpha, const double
         sr = nsr;
         ir = nir;
     }
+    return st;
+}
+
+// y = M x for the symmetric tridiagonal M with diagonal d and off-diagonal e
+// (e couples rows r and r + 1), all lane-resident (rows r and r + 64).
+template <int NH>
+__device__ __forceinline__ void tri_mul(double d0, double d1, double e0, double e1, double x0, double x1,
+                                        int lane, double &y0, double &y1) {
+    // every cross-lane read runs on all lanes; the row ends are selected after
+    const double up_x0 = __shfl_up(x0, 1, 64), up_e0 = __shfl_up(e0, 1, 64), dn_x0 = __shfl_down(x0, 1, 64);
+    const double x64 = NH == 2 ? readlane_d(x1, 0) : 0.0;
+    const double xm0 = lane == 0 ? 0.0 : up_x0;
+    const double em0 = lane == 0 ? 0.0 : up_e0;
+    const double xp0 = lane == 63 ? x64 : dn_x0;
+    y0 = fma(d0, x0, fma(em0, xm0, e0 * xp0));
+    y1 = 0.0;
+    if (NH == 2) {
+        const double x63 = readlane_d(x0, 63), e63 = readlane_d(e0, 63);
+        const double up_x1 = __shfl_up(x1, 1, 64), up_e1 = __shfl_up(e1, 1, 64), dn_x1 = __shfl_down(x1, 1, 64);
+        const double xm1 = lane == 0 ? x63 : up_x1;
+        const double em1 = lane == 0 ? e63 : up_e1;
+        const double xp1 = lane == 63 ? 0.0 : dn_x1;
+        y1 = fma(d1, x1, fma(em1, xm1, e1 * xp1));
+    }
+}
+
+// f(T) e1 by the integral representation of the quadrature kernel: with
+// z(t) = (T~ + t I)^{-1} e1 and Z = int z(t) dt / (1 + t) over [t0, inf),
+// f(T~) e1 = T~ (I - T~) Z + t0 (I - T~) e1 (the part below t0 to first
+// order) and f(T) e1 = sigma f(T~) e1 - log(sigma) T e1.  For each node, the
+// bottom-up elimination stores the inverse pivots of the lane's node in LDS,
+// then z_1 = 1/d_1, z_{j+1} = -b_j z_j / d_{j+1} runs forward and every
+// entry is summed over the lanes' nodes (fixed butterfly order) into the
+// lane-resident Z.  Returns false when no allowed shift makes T~ positive
+// definite (the caller takes the QR route).
+template <int NH>
+__device__ bool fT_e1_integral(const LaneTri &t, int ke, int lane, int shift_max, double *piv, double &r0,
+                               double &r1) {
+    const double up0 = __shfl_up(t.e0, 1, 64);
+    const double prev0 = lane == 0 ? 0.0 : up0;
+    double g = lane < ke ? fabs(t.d0) + fabs(t.e0) + fabs(prev0) : 0.0;
+    if (NH == 2) {
+        const double up1 = __shfl_up(t.e1, 1, 64);
+        const double e63 = readlane_d(t.e0, 63);
+        const double prev1 = lane == 0 ? e63 : up1;
+        g = fmax(g, lane + 64 < ke ? fabs(t.d1) + fabs(t.e1) + fabs(prev1) : 0.0);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o, 64));
+    const double sigma = g;
+    r0 = r1 = 0.0;
+    if (!(sigma > 0.0)) return true;     // T = 0: f(T) e1 = 0
+    const double is = 1.0 / sigma;
+    constexpr int NC = 5;
+    const double shift[NC] = {5e-16, 5e-14, 5e-12, 5e-10, 5e-8};
+    double ic[NC];
+    bool pc[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        ic[q] = 0.0;
+        pc[q] = true;
+    }
+    for (int j = ke - 1; j >= 0; --j) {
+        const double aj = get_row<NH>(t.d0, t.d1, j) * is;
+        const double bj = j < ke - 1 ? get_row<NH>(t.e0, t.e1, j) * is : 0.0;
+        const double bj2 = bj * bj;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const double d = fma(-bj2, ic[q], aj + shift[q]);
+            pc[q] = pc[q] && d > 0.0;
+            ic[q] = 1.0 / d;
+        }
+    }
+    double c0 = -1.0;
+#pragma unroll
+    for (int q = NC - 1; q >= 0; --q) c0 = (pc[q] && q <= shift_max) ? shift[q] : c0;
+    c0 = readlane_d(c0, 0);
+    if (c0 < 0.0) return false;
+    const double t0 = 2.0 * c0;
+    const double s_lo = log(t0);
+    const double h = (37.0 - s_lo) / (double)(kQuadNodes - 1);
+    double Z0 = 0.0, Z1 = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        const int n = lane + 64 * q;
+        const double tt = exp(s_lo + h * (double)n);
+        const double w = ((n == 0 || n == kQuadNodes - 1) ? 0.5 * h : h) * (tt / (1.0 + tt));
+        double inv = 0.0;
+        for (int j = ke - 1; j >= 0; --j) {
+            const double aj = get_row<NH>(t.d0, t.d1, j) * is;
+            const double bj = j < ke - 1 ? get_row<NH>(t.e0, t.e1, j) * is : 0.0;
+            inv = 1.0 / fma(-bj * bj, inv, aj + tt);
+            piv[j * 64 + lane] = inv;
+        }
+        double z = piv[lane];
+        for (int j = 0; j < ke; ++j) {
+            const double sj = wave_sum(w * z);
+            if (j < 64) Z0 += lane == j ? sj : 0.0;
+            else Z1 += lane == j - 64 ? sj : 0.0;
+            if (j + 1 < ke) z = -(get_row<NH>(t.e0, t.e1, j) * is) * z * piv[(j + 1) * 64 + lane];
+        }
+    }
+    // f(T~) e1 = T~ (Z - T~ Z) + t0 (e1 - T~ e1), T~ = T / sigma
+    const double a0 = t.d0 * is, a1 = t.d1 * is, b0 = t.e0 * is, b1 = t.e1 * is;
+    double y0, y1, v0, v1;
+    tri_mul<NH>(a0, a1, b0, b1, Z0, Z1, lane, y0, y1);
+    tri_mul<NH>(a0, a1, b0, b1, Z0 - y0, Z1 - y1, lane, v0, v1);
+    const double e1_0 = lane == 0 ? 1.0 : 0.0;
+    double te0, te1;
+    tri_mul<NH>(a0, a1, b0, b1, e1_0, 0.0, lane, te0, te1);
+    const double f0 = v0 + t0 * (e1_0 - te0), f1 = v1 - t0 * te1;
+    // f(T) e1 = sigma f(T~) e1 - log(sigma) T e1, T e1 = sigma T~ e1
+    const double ls = log(sigma);
+    r0 = lane < ke ? sigma * (f0 - ls * te0) : 0.0;
+    r1 = lane + 64 < ke ? sigma * (f1 - ls * te1) : 0.0;
+    return true;
+}
+
+// One column per 64-thread block: the integral route, or the QR route when
+// T~ has a negative eigenvalue beyond the allowed shift.
+__global__ void __launch_bounds__(64) k_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff,
+                                              int32_t k, int32_t m, double *S, Rot *rot_buf, int32_t *flags,
+                                              int32_t shift_max) {
+    __shared__ double piv[kMaxSteps * 64];
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (c >= m) return;
+    const int ke = __builtin_amdgcn_readfirstlane(k_eff[c]);
+    // S is stored step-major: S[r * m + c]
+    if (lane < k) S[(int64_t)lane * m + c] = 0.0;
+    if (lane + 64 < k) S[(int64_t)(lane + 64) * m + c] = 0.0;
+    if (ke <= 0) return;
+    LaneTri t;
+    load_tri(t, alpha + (int64_t)c * k, beta + (int64_t)c * k, ke, lane);
+    double w0 = 0.0, w1 = 0.0;
+    int st = 0;
+    const bool done = ke <= 64 ? fT_e1_integral<1>(t, ke, lane, shift_max, piv, w0, w1)
+                               : fT_e1_integral<2>(t, ke, lane, shift_max, piv, w0, w1);
+    if (!done) {
+        const int cap = (int)rot_capacity(k);
+        Rot *rot = rot_buf + (int64_t)c * cap;
+        st = ke <= 64 ? fT_e1_qr<1>(t, ke, lane, rot, cap, w0, w1) : fT_e1_qr<2>(t, ke, lane, rot, cap, w0, w1);
+    }
     if (lane < ke) S[(int64_t)lane * m + c] = w0;
     if (lane + 64 < ke) S[(int64_t)(lane + 64) * m + c] = w1;
     if (lane == 0 && st) atomicOr(flags, st);
 }
 
 hipError_t launch_fT_e1(const double *alpha, const double *beta, const int32_t *k_eff, int32_t k, int32_t m,
-                        double *S, void *rot_scratch, int32_t *flags, hipStream_t s) {
+                        double *S, void *rot_scratch, int32_t *flags, hipStream_t s, bool fp64) {
     if (k > kMaxSteps) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fT_e1, dim3((m + 3) / 4), dim3(256), 0, s, alpha, beta, k_eff, k, m, S,
-                       (Rot *)rot_scratch, flags);
+    if (m > 0)
+        hipLaunchKernelGGL(k_fT_e1, dim3(m), dim3(64), 0, s, alpha, beta, k_eff, k, m, S, (Rot *)rot_scratch, flags,
+                           fp64 ? 1 : 4);
     return hipGetLastError();
 }
 

@@ -640,7 +640,7 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         if (timing) c->pending.push_back({p, bytes, ran});
         HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p,
                                      (const int32_t *)p->k_eff.p, (const double *)p->norm2.p, K, K, p->m_pad,
-                                     (double *)p->psi.p, (int32_t *)p->flags.p, c->stream, nullptr, 0,
+                                     (double *)p->psi.p, (int32_t *)p->flags.p, c->stream, p->fp64, nullptr, 0,
                                      (const int32_t *)p->col_stop.p));
         return VNE_OK;
     }
@@ -674,7 +674,7 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
     if (p->store) return VNE_OK;   // the Hutch++ sketch needs f(T) e1 (k_fT_e1), not psi
     HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p, (const int32_t *)p->k_eff.p,
                                  (const double *)p->norm2.p, p->k, p->k, p->G * p->m_pad, (double *)p->psi.p,
-                                 (int32_t *)p->flags.p, c->stream));
+                                 (int32_t *)p->flags.p, c->stream, p->fp64));
     return VNE_OK;
 }
 
@@ -844,7 +844,7 @@ vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int
     ps.seeds = {pr->seed};
     VNE_TRY(run_lanczos(c, set, sk, ps, desing));
     HIP_TRY(c, launch_fT_e1((const double *)sk->alpha.p, (const double *)sk->beta.p, (const int32_t *)sk->k_eff.p,
-                            k, nr, (double *)q->S.p, q->rot.p, (int32_t *)sk->flags.p, s));
+                            k, nr, (double *)q->S.p, q->rot.p, (int32_t *)sk->flags.p, s, fp64));
     const int64_t step_stride = n * sk->m_pad;
     HIP_TRY(c, launch_reconstruct(sk->Vstore.p, fp64, step_stride, sk->m_pad, (const double *)q->S.p,
                                   (const double *)sk->norm2.p, k, (int32_t)n, nr, q->B.p, m, s));

@@ -518,7 +518,7 @@ vne_status end_task(vne_server *s, SrvTask &t, SrvQuery &q, int steps) {
     // an adaptive task's own stop record (if the device made one) decides the
     // step count, whenever the host noticed it
     SRV_HIP(s, launch_quadrature(t.alpha, t.beta, t.k_eff, t.norm2, t.k, steps, t.m, q.d_psi + t.col0, q.d_flags,
-                                 s->stream, t.adaptive ? t.d_state : nullptr, t.uid));
+                                 s->stream, s->fp64, t.adaptive ? t.d_state : nullptr, t.uid));
     s->arena.release(t.off);
     s->free_slots.push_back(t.slot);
     q.steps_used = std::max(q.steps_used, steps);
