@@ -13,8 +13,11 @@
 // threads list, for every node of the next chunk, the neighbours that come
 // earlier in the order (the only ones coloured when the node's turn comes),
 // while the calling thread runs the first-fit scan over the current chunk in
-// order.  The result is the sequential algorithm's colouring exactly.
+// order.  The result is the sequential algorithm's colouring exactly.  Several
+// distances share one search to the largest of them: every listed neighbour
+// carries its distance, and each distance's scan skips the farther ones.
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <memory>
 #include <numeric>
@@ -34,6 +37,7 @@ struct ChunkLists {
     int64_t t0 = 0, t1 = 0;
     int nw = 1;
     std::vector<std::vector<int32_t>> items;     // per worker
+    std::vector<std::vector<uint8_t>> depth;     // per worker: distance of each listed neighbour
     std::vector<std::vector<int64_t>> begin;     // per worker, per owned node + 1
 };
 
@@ -44,8 +48,9 @@ public:
     Searcher(int64_t n, const int32_t *rp, const int32_t *ci, int32_t d, const std::vector<int32_t> &pos)
         : rp_(rp), ci_(ci), d_(d), pos_(pos), seen_(n, -1) {}
 
-    // earlier neighbours (position < pos of i) of node i within distance d
-    void list(int32_t i, int32_t stamp, std::vector<int32_t> *out) {
+    // earlier neighbours (position < pos of i) of node i within distance d,
+    // with their distance
+    void list(int32_t i, int32_t stamp, std::vector<int32_t> *out, std::vector<uint8_t> *dist) {
         frontier_.clear();
         frontier_.push_back(i);
         seen_[i] = stamp;
@@ -58,7 +63,10 @@ public:
                     if (seen_[y] == stamp) continue;
                     seen_[y] = stamp;
                     next_.push_back(y);
-                    if (pos_[y] < pi) out->push_back(y);
+                    if (pos_[y] < pi) {
+                        out->push_back(y);
+                        dist->push_back((uint8_t)(depth + 1));
+                    }
                 }
             }
             frontier_.swap(next_);
@@ -78,17 +86,21 @@ void build_lists(ChunkLists *cl, std::vector<std::unique_ptr<Searcher>> &srch, c
     auto work = [&](int w) {
         // fill vectors local to the thread, hand them over at the end
         std::vector<int32_t> it;
+        std::vector<uint8_t> dp;
         std::vector<int64_t> bg;
         it.swap(cl->items[w]);
+        dp.swap(cl->depth[w]);
         bg.swap(cl->begin[w]);
         it.clear();
+        dp.clear();
         bg.clear();
         bg.push_back(0);
         for (int64_t t = cl->t0 + w; t < cl->t1; t += nw) {
-            srch[w]->list(order[t], (int32_t)t, &it);
+            srch[w]->list(order[t], (int32_t)t, &it, &dp);
             bg.push_back((int64_t)it.size());
         }
         cl->items[w].swap(it);
+        cl->depth[w].swap(dp);
         cl->begin[w].swap(bg);
     };
     if (nw == 1) {
@@ -103,7 +115,40 @@ void build_lists(ChunkLists *cl, std::vector<std::unique_ptr<Searcher>> &srch, c
 
 }  // namespace
 
-int32_t vne::greedy_color(int64_t n, const int32_t *rp, const int32_t *ci, int32_t d, int32_t *colors_out) {
+// First-fit state of one distance.
+struct FirstFit {
+    int32_t d = 1;
+    std::vector<int32_t> color;
+    std::vector<int64_t> banned;                 // stamp per colour
+    int32_t ncol = 0;
+
+    void scan(const ChunkLists &cl, const std::vector<int32_t> &order) {
+        const int nw = cl.nw;
+        const bool all = d >= 255;
+        for (int64_t t = cl.t0; t < cl.t1; ++t) {
+            const int64_t r = t - cl.t0;
+            const int w = (int)(r % nw);
+            const int64_t slot = r / nw;
+            const auto &it = cl.items[w];
+            const auto &dp = cl.depth[w];
+            // the search lists a node's neighbours by increasing distance
+            for (int64_t q = cl.begin[w][slot]; q < cl.begin[w][slot + 1]; ++q) {
+                if (!all && dp[q] > d) break;
+                banned[color[it[q]]] = t;
+            }
+            int32_t c = 0;
+            while (c < ncol && banned[c] == t) ++c;
+            if (c == ncol) {
+                ncol++;
+                banned.push_back(-1);
+            }
+            color[order[t]] = c;
+        }
+    }
+};
+
+void vne::greedy_color_multi(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *ds, int nd,
+                             int32_t *const *colors_out, int32_t *n_colors) {
     std::vector<int32_t> deg(n);
     for (int64_t i = 0; i < n; ++i) {
         int32_t c = 0;
@@ -116,26 +161,31 @@ int32_t vne::greedy_color(int64_t n, const int32_t *rp, const int32_t *ci, int32
                      [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
     std::vector<int32_t> pos(n);
     for (int64_t t = 0; t < n; ++t) pos[order[t]] = (int32_t)t;
+    int32_t dmax = 1;
+    for (int q = 0; q < nd; ++q) dmax = std::max(dmax, ds[q]);
 
     int nw = (int)std::thread::hardware_concurrency();
     if (const char *e = std::getenv("VNE_COLOR_THREADS")) nw = std::atoi(e);
     nw = std::max(1, std::min(nw, 16));
     if (n < 4096) nw = 1;
     std::vector<std::unique_ptr<Searcher>> srch;
-    for (int w = 0; w < nw; ++w) srch.emplace_back(new Searcher(n, rp, ci, d, pos));
+    for (int w = 0; w < nw; ++w) srch.emplace_back(new Searcher(n, rp, ci, dmax, pos));
 
-    std::vector<int32_t> color(n, -1);
-    std::vector<int64_t> banned;                 // stamp per colour
-    int32_t ncol = 0;
+    std::vector<FirstFit> ff(nd);
+    for (int q = 0; q < nd; ++q) {
+        ff[q].d = ds[q];
+        ff[q].color.assign(n, -1);
+    }
     // chunk sizes: aim at about 2^24 listed neighbours per chunk
     const int64_t kBudget = int64_t(1) << 24;
     int64_t chunk = std::min<int64_t>(n, 1024);
     ChunkLists cur, nxt;
-    cur.nw = nxt.nw = nw;
-    cur.items.resize(nw);
-    cur.begin.resize(nw);
-    nxt.items.resize(nw);
-    nxt.begin.resize(nw);
+    for (ChunkLists *cl : {&cur, &nxt}) {
+        cl->nw = nw;
+        cl->items.resize(nw);
+        cl->depth.resize(nw);
+        cl->begin.resize(nw);
+    }
     cur.t0 = 0;
     cur.t1 = chunk;
     build_lists(&cur, srch, order);
@@ -149,29 +199,25 @@ int32_t vne::greedy_color(int64_t n, const int32_t *rp, const int32_t *ci, int32
         nxt.t1 = std::min<int64_t>(n, cur.t1 + chunk);
         std::thread lister;
         if (nxt.t0 < n) lister = std::thread([&]() { build_lists(&nxt, srch, order); });
-        // first-fit scan of the current chunk, in order
-        for (int64_t t = cur.t0; t < cur.t1; ++t) {
-            const int64_t r = t - cur.t0;
-            const int w = (int)(r % nw);
-            const int64_t slot = r / nw;
-            const auto &it = cur.items[w];
-            for (int64_t q = cur.begin[w][slot]; q < cur.begin[w][slot + 1]; ++q) {
-                const int32_t c = color[it[q]];
-                banned[c] = t;
-            }
-            int32_t c = 0;
-            while (c < ncol && banned[c] == t) ++c;
-            if (c == ncol) {
-                ncol++;
-                banned.push_back(-1);
-            }
-            color[order[t]] = c;
-        }
+        // first-fit scans of the current chunk, one distance per thread
+        std::vector<std::thread> scanners;
+        for (int q = 1; q < nd; ++q) scanners.emplace_back([&, q]() { ff[q].scan(cur, order); });
+        ff[0].scan(cur, order);
+        for (auto &x : scanners) x.join();
         if (lister.joinable()) lister.join();
         std::swap(cur, nxt);
         if (cur.t0 >= n) break;
     }
-    std::copy(color.begin(), color.end(), colors_out);
+    for (int q = 0; q < nd; ++q) {
+        std::copy(ff[q].color.begin(), ff[q].color.end(), colors_out[q]);
+        n_colors[q] = ff[q].ncol;
+    }
+}
+
+int32_t vne::greedy_color(int64_t n, const int32_t *rp, const int32_t *ci, int32_t d, int32_t *colors_out) {
+    int32_t ncol = 0;
+    int32_t *out[1] = {colors_out};
+    greedy_color_multi(n, rp, ci, &d, 1, out, &ncol);
     return ncol;
 }
 

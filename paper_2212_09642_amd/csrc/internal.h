@@ -61,5 +61,9 @@ void set_msg(char *msg, int64_t msg_len, const std::string &s);
 // Greedy distance-d colouring (Algorithm 1) of the pattern of a validated
 // CSR with n rows; colors[n] receives colours from 0; returns the count.
 int32_t greedy_color(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t d, int32_t *colors);
+// The colourings of nd distances ds[q] (1..254) at once, from one search to
+// the largest: colors_out[q][n], n_colors[q].
+void greedy_color_multi(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const int32_t *ds, int nd,
+                        int32_t *const *colors_out, int32_t *n_colors);
 
 }  // namespace vne

@@ -175,14 +175,16 @@ extern "C" vne_status vne_entropy_probing(vne_ctx *c, int32_t gid, const vne_pro
     const double s_lower = -std::log(g->fro2);
     res->s_lower = s_lower;
 
-    // one distance-d pass: colouring (Algorithm 1), tolerances of eq. (5.3),
-    // Lanczos with per-colour stopping
+    // one distance-d pass: colouring (Algorithm 1, unless given), tolerances
+    // of eq. (5.3), Lanczos with per-colour stopping
     auto run_pass = [&](int d, double eps_hat, Pass *ps) -> vne_status {
-        ps->d = d;
-        ps->colors.assign(n, 0);
         auto t0 = Clock::now();
-        ps->n_colors = greedy_color(n, g->h_row_ptr.data(), g->h_col.data(), d, ps->colors.data());
-        res->color_ms += ms_since(t0);
+        if (ps->d != d) {
+            ps->d = d;
+            ps->colors.assign(n, 0);
+            ps->n_colors = greedy_color(n, g->h_row_ptr.data(), g->h_col.data(), d, ps->colors.data());
+            res->color_ms += ms_since(t0);
+        }
         std::vector<double> size(ps->n_colors, 0.0);
         for (int64_t i = 0; i < n; ++i) size[ps->colors[i]] += 1.0;
         std::vector<double> tol(ps->n_colors);
@@ -208,6 +210,23 @@ extern "C" vne_status vne_entropy_probing(vne_ctx *c, int32_t gid, const vne_pro
     DistanceChoice ch;
     const double eps_hat0 = 0.5 * cfg->rel_eps * s_lower;
     if (cfg->select == VNE_SELECT_HEURISTIC) {
+        {
+            // the three colourings from one neighbourhood search
+            auto t0 = Clock::now();
+            const int32_t ds[3] = {1, 2, 3};
+            int32_t *outs[3];
+            int32_t nc[3];
+            for (int q = 0; q < 3; ++q) {
+                pre[q].colors.assign(n, 0);
+                outs[q] = pre[q].colors.data();
+            }
+            greedy_color_multi(n, g->h_row_ptr.data(), g->h_col.data(), ds, 3, outs, nc);
+            for (int q = 0; q < 3; ++q) {
+                pre[q].d = ds[q];
+                pre[q].n_colors = nc[q];
+            }
+            res->color_ms += ms_since(t0);
+        }
         for (int d = 1; d <= 3; ++d) VNE_TRY(run_pass(d, eps_hat0, &pre[d - 1]));
         const double T[3] = {pre[0].out.estimate, pre[1].out.estimate, pre[2].out.estimate};
         for (int i = 0; i < 3; ++i) res->t_pre[i] = T[i];
