@@ -221,3 +221,37 @@ def test_probing_and_adaptive_errors(ctx):
             ctx.estimate_adaptive(gid, vne.PROBE_RADEMACHER, 8, kmax, vne.MODE_DESING, tol, lo, hi)
     ctx.release(g2)
     ctx.release(gid)
+
+
+def test_algorithm_2_closed_forms(ctx):
+    """Closed-form entropies: the complete graph K_n (rho has eigenvalue
+    1/(n-1) with multiplicity n-1: S = log(n-1)) and the star S_n (Laplacian
+    eigenvalues 0, 1 (n-2 times) and n over tr L = 2(n-1))."""
+    _say("case Algorithm 2, complete graph and star")
+    for name, mk, S in [("complete", lambda: synth.complete_graph(300), np.log(299.0)),
+                        ("star", lambda: synth.star_graph(500),
+                         -(498 * (1 / 998) * np.log(1 / 998) + (500 / 998) * np.log(500 / 998)))]:
+        gid, ref = _setup(ctx, *mk(), fp64=False)
+        assert abs(S - oracle.exact_entropy(oracle.dense_matrix(ref))) < 1e-12 * S
+        got = ctx.probing(gid, 1e-3, d_max=16, k_max=64)
+        err = abs(got["estimate"] - S) / S
+        _say("   %s: d=%d colours %d passes %d, rel err %.2e" % (name, got["d"], got["n_colors"], got["passes"], err))
+        assert err <= 1e-3 and got["unconverged"] == 0
+        ctx.release(gid)
+
+
+def test_algorithm_2_reports_unconverged_colours(ctx):
+    """With a step cap below what the tolerances need, every colour still
+    gets its quadrature after k_max steps and the result says how many did
+    not meet their tolerance; the same call with room converges."""
+    _say("case Algorithm 2, step cap too small")
+    gid, ref = _setup(ctx, *synth.erdos_renyi(2000, 8.0, 81), fp64=False)
+    capped = ctx.probing(gid, 1e-5, d_max=3, k_max=3, quad_cap=4096)
+    assert capped["unconverged"] > 0
+    assert np.all(capped["steps"][capped["steps"] > 0] == 3)
+    assert np.isfinite(capped["estimate"])
+    free = ctx.probing(gid, 1e-5, d_max=3, k_max=128)
+    assert free["unconverged"] == 0
+    _say("   capped: %d of %d colours unconverged; with k_max 128: block steps %d"
+         % (capped["unconverged"], capped["n_colors"], free["block_steps"]))
+    ctx.release(gid)
