@@ -6,6 +6,7 @@ from scipy.optimize import linprog
 
 import oracle
 from oracle import bounds
+import synth
 
 
 def _lp_minimax(k, a, b, npts=500):
@@ -91,3 +92,77 @@ def test_g_m_entropy_matches_generic_away_from_ritz_values():
     g2 = bounds.g_m_entropy(z, theta, U, res["beta"][0][m - 1], 1e-12)
     # terms of size max|g| cancel in the sum over Ritz values: absolute bar
     assert np.allclose(g1, g2, rtol=1e-9, atol=1e-8 * np.abs(g1).max())
+
+
+def _g48_mp(a, b, m, z, dps=60):
+    """Eq. (4.8) for -x log x written out term by term in dps-digit arithmetic."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    T = mp.matrix(m, m)
+    for i in range(m):
+        T[i, i] = mp.mpf(a[i])
+        if i < m - 1:
+            T[i, i + 1] = T[i + 1, i] = mp.mpf(b[i])
+    E, Q = mp.eigsy(T)
+    bm = mp.mpf(b[m - 1])
+    th = [E[j] for j in range(m)]
+    ab = [bm * Q[m - 1, j] * Q[0, j] for j in range(m)]
+    cj = [mp.fsum(ab[l] / (th[j] - th[l]) for l in range(m) if l != j) for j in range(m)]
+    f = lambda x: -x * mp.log(x)
+    fp = lambda x: -mp.log(x) - 1
+    out = []
+    for zz in z:
+        zz = mp.mpf(zz)
+        g = mp.mpf(0)
+        for j in range(m):
+            d1 = (f(zz) - f(th[j])) / (zz - th[j])
+            d2 = (d1 - fp(th[j])) / (zz - th[j])
+            g += ab[j] ** 2 * d2 + 2 * ab[j] * cj[j] * d1
+        out.append(float(g))
+    return np.array(out)
+
+
+@pytest.mark.slow
+def test_g_m_residue_form_against_eq_4_8_in_high_precision():
+    """The bracket's g_m (residue form) equals eq. (4.8) evaluated in 60-digit
+    arithmetic on Lanczos matrices of a graph Laplacian, up to m = 39, where
+    eq. (4.8) in double precision has lost several digits; |g_m| decreases
+    in z and g_m < 0."""
+    g = oracle.laplacian_from_edges(*synth.barabasi_albert(1500, 3, 33))
+    A = g.scipy()
+    B = oracle.rademacher_block(3, g.node_ids, np.arange(2))
+    res = oracle.lanczos(A, oracle.desingularize(B), 40, oracle.breakdown_tau(True))
+    lam_hi = float(np.abs(A).sum(1).max())
+    z = np.array([1e-12 * lam_hi, 1e-6 * lam_hi, 1e-3 * lam_hi, lam_hi])
+    for c in range(2):
+        for m in (3, 12, 25, 39):
+            a, b = res["alpha"][c], res["beta"][c]
+            want = _g48_mp(a, b, m, z)
+            got = bounds.g_m_resolvent(z, a, b, m)
+            assert np.all(want < 0) and np.all(np.diff(np.abs(want)) < 0)
+            assert np.allclose(got, want, rtol=1e-10, atol=0), (c, m, got, want)
+
+
+def test_g_m_residue_form_against_adaptive_quadrature():
+    """The trapezoidal rule in ln t against QUADPACK on the same integral,
+    with the corner entry of the resolvent from a banded solve."""
+    from scipy import integrate
+    from scipy.linalg import solve_banded
+    g = oracle.laplacian_from_edges(*synth.watts_strogatz(800, 6, 0.1, 3))
+    A = g.scipy()
+    B = oracle.rademacher_block(5, g.node_ids, np.arange(1))
+    res = oracle.lanczos(A, oracle.desingularize(B), 30, oracle.breakdown_tau(True))
+    a, b = res["alpha"][0], res["beta"][0]
+    for m in (2, 9, 30):
+        def h2(t):
+            ab = np.zeros((3, m))
+            ab[0, 1:] = b[:m - 1]
+            ab[1] = a[:m] + t
+            ab[2, :-1] = b[:m - 1]
+            e = np.zeros(m)
+            e[-1] = 1.0
+            return (b[m - 1] * solve_banded((1, 1), ab, e)[0]) ** 2
+        for zz in (1e-9, 1e-5, 3e-3):
+            val, _ = integrate.quad(lambda s: np.exp(2 * s) * h2(np.exp(s)) / (np.exp(s) + zz), -80, 20,
+                                    limit=2000, epsabs=0, epsrel=1e-12)
+            assert bounds.g_m_resolvent([zz], a, b, m)[0] == pytest.approx(-val, rel=1e-9)
