@@ -1463,6 +1463,94 @@ __device__ __forceinline__ void entropy_dd(double z, double th, double log_th, d
     d2 = q * inv_th;
 }
 
+// The bracket without diagonalising T_m.  With h(w) = sum_j a_j b_j / (w -
+// theta_j) = beta_m e1^T (w I - T_m)^{-1} e_m, eq. (4.8) is the sum of the
+// residues of f(w) h(w)^2 / (w - z) at the Ritz values and at z (double poles
+// at theta_j give the D2 terms, the cross terms of h^2 the c_j D1 terms).  For
+// f = -x log x on the scaled problem (T~ = T_m / sigma, spectrum in [0, 1];
+// g_m scales as sigma g~_m(z / sigma), the linear part of f contributing
+// nothing) the representation -x log x = int_0^inf x (1 - x) / ((x + t)(1 + t))
+// dt turns every residue sum into minus the residue at w = -t, so
+//     g~_m(z) = - int_0^inf t h~(-t)^2 / (t + z) dt,
+//     h~(-t)^2 = beta~_m^2 (e1^T (T~ + t I)^{-1} e_m)^2
+//              = beta~_m^2 prod_{i < m} (beta~_i / p_i)^2 / p_m^2
+// with the top-down pivots p_1 = a_1 + t, p_{i+1} = a_{i+1} + t - b_i^2 / p_i.
+// g is negative and |g| decreases in z, so the extremes over [lam_lo, lam_hi]
+// are its values at the ends: hi = ||c||^2 |g(lam_lo)|, lo = ||c||^2
+// |g(lam_hi)|.  (Against a 50-digit evaluation of eq. (4.8) this agrees to
+// 3e-15; eq. (4.8) in double precision loses up to 4e-8 to cancellation at
+// m = 20.)  Same trapezoidal rule in ln t as the quadrature, from t0 = 1e-15
+// (the part below t0 is O(t0^2)); the running product is renormalised with
+// frexp.  Returns false when T~ + 5e-16 I is not positive definite (a
+// Ritz value below -5e-16 sigma), for the QR route with its floor.
+template <int NH>
+__device__ bool bound_integral(const LaneTri &t, int mm, double beta_m, double lam_lo, double lam_hi, int lane,
+                               double &g_lo, double &g_hi) {
+    const double up0 = __shfl_up(t.e0, 1, 64);
+    const double prev0 = lane == 0 ? 0.0 : up0;
+    double g = lane < mm ? fabs(t.d0) + fabs(t.e0) + fabs(prev0) : 0.0;
+    if (NH == 2) {
+        const double up1 = __shfl_up(t.e1, 1, 64);
+        const double e63 = readlane_d(t.e0, 63);
+        const double prev1 = lane == 0 ? e63 : up1;
+        g = fmax(g, lane + 64 < mm ? fabs(t.d1) + fabs(t.e1) + fabs(prev1) : 0.0);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o, 64));
+    const double sigma = g;
+    if (!(sigma > 0.0)) return false;
+    const double is = 1.0 / sigma;
+    // positive definiteness of T~ + 5e-16 I (bottom-up, as in the quadrature),
+    // so that T~ + t I has every eigenvalue at least t / 2 at the nodes
+    {
+        double ic = 0.0;
+        bool pd = true;
+        for (int j = mm - 1; j >= 0; --j) {
+            const double aj = get_row<NH>(t.d0, t.d1, j) * is;
+            const double bj = j < mm - 1 ? get_row<NH>(t.e0, t.e1, j) * is : 0.0;
+            const double d = fma(-bj * bj, ic, aj + 5e-16);
+            pd = pd && d > 0.0;
+            ic = 1.0 / d;
+        }
+        if (__builtin_amdgcn_readfirstlane(pd ? 1 : 0) == 0) return false;
+    }
+    const double bm = beta_m * is;
+    const double zl = lam_lo * is, zh = lam_hi * is;
+    const double s_lo = -34.538776394910684;          // ln 1e-15
+    const double h = (37.0 - s_lo) / (double)(kQuadNodes - 1);
+    double part_l = 0.0, part_h = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int n = lane + 64 * q;
+        const double tt = exp(s_lo + h * (double)n);
+        double p = 0.0, prod = 1.0;
+        int ex = 0;
+        for (int j = 0; j < mm; ++j) {
+            const double aj = get_row<NH>(t.d0, t.d1, j) * is;
+            const double bprev = j > 0 ? get_row<NH>(t.e0, t.e1, j - 1) * is : 0.0;
+            p = j > 0 ? aj + tt - bprev * bprev / p : aj + tt;
+            if (j < mm - 1) {
+                const double bj = get_row<NH>(t.e0, t.e1, j) * is;
+                const double r = bj / p;
+                prod *= r * r;
+            } else {
+                prod /= p * p;
+            }
+            int e;
+            prod = frexp(prod, &e);
+            ex += e;
+        }
+        const double h2 = ldexp(prod, ex) * bm * bm;           // h~(-t)^2 (0 on underflow)
+        const double w = (n == 0 || n == kQuadNodes - 1) ? 0.5 * h : h;
+        const double tw = w * tt * tt * h2;                    // dt = t ds
+        part_l += tw / (tt + zl);
+        part_h += tw / (tt + zh);
+    }
+    g_lo = sigma * wave_sum(part_l);     // |g| at lam_lo (the maximum)
+    g_hi = sigma * wave_sum(part_h);     // |g| at lam_hi (the minimum)
+    return true;
+}
+
 template <int NH>
 __device__ void bound_column(const BoundArgs &a, int c, int lane) {
     if (a.col_stop && __builtin_amdgcn_readfirstlane(a.col_stop[c]) > 0) return;   // stopped earlier
@@ -1479,6 +1567,17 @@ __device__ void bound_column(const BoundArgs &a, int c, int lane) {
     }
     LaneTri t;
     load_tri(t, a.alpha + base, a.beta + base, mm, lane);
+    {
+        double gmax = 0.0, gmin = 0.0;
+        if (bound_integral<NH>(t, mm, beta_m, a.lam_lo, a.lam_hi, lane, gmax, gmin)) {
+            if (lane == 0) {
+                const double nb = a.norm2[c];
+                a.lo[c] = nb * gmin;
+                a.hi[c] = nb * gmax;
+            }
+            return;
+        }
+    }
     t.w0 = lane == mm - 1 ? 1.0 : 0.0;
     t.w1 = lane + 64 == mm - 1 ? 1.0 : 0.0;
     const int st = lane_tridiag_qr<false, NH, true>(t, mm, lane, nullptr, 0, nullptr);
