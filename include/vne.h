@@ -327,8 +327,12 @@ vne_status vne_probing_select(const double *T, double eps_hat, double n, double 
  * method, per column of a result (host arrays laid out as in vne_result:
  * alpha, beta [m*k], k_eff, norm2 [m]) after min(k_eff[c], steps) steps:
  * lo[c] <= |psi - psi_m| <= hi[c] with lo, hi = ||c||^2 min, max |g_m(z)| of
- * eq. (4.8) for f = -x log x, the extremes taken over n_grid log-spaced
- * points of [lam_lo, lam_hi] plus the Ritz values inside it.  The interval
+ * eq. (4.8) for f = -x log x over [lam_lo, lam_hi].  g_m is evaluated in
+ * its residue form -int_0^inf t (beta_m e1^T (T_m + tI)^{-1} e_m)^2 / (t + z)
+ * dt, in which |g_m| decreases in z, so hi and lo are its values at lam_lo
+ * and lam_hi; a column whose T_m has a Ritz value below -5e-16 of its scale
+ * (rounding) is evaluated term by term over n_grid log-spaced points plus
+ * the Ritz values inside the interval instead.  The interval
  * must contain the spectrum of A seen by the start vectors (for a Laplacian
  * density matrix with VNE_MODE_DESING: [lambda_2, lambda_n]; any
  * 0 < lam_lo <= lambda_2 and lam_hi >= lambda_n, e.g. a Gershgorin bound,

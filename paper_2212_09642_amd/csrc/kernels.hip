@@ -1440,10 +1440,13 @@ __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const d
 // With r = z / theta, t = r - 1: D1 = -log theta - (1 + t) log1p(t) / t and
 // D2 = q(t) / theta, q(t) = (t - (1 + t) log1p(t)) / t^2, by their Taylor
 // series for |t| < 1e-3 (the limits at z = theta are the ones eq. (4.8)
-// gives).  lo, hi = ||c||^2 min, max |g_m| over n_grid log-spaced points of
-// [lam_lo, lam_hi] and the Ritz values inside it; Ritz values below lam_lo
-// are raised to it.  A column whose recurrence stopped on a zero beta has an
-// invariant Krylov space and zero error.
+// gives).  lo, hi = ||c||^2 min, max |g_m| over [lam_lo, lam_hi].  The
+// columns are evaluated in the residue form of eq. (4.8) (bound_integral
+// below), which gives the extremes at the ends of the interval; a column
+// with a Ritz value below -5e-16 of its scale is evaluated term by term over
+// n_grid log-spaced points and the Ritz values inside the interval, Ritz
+// values below lam_lo raised to it.  A column whose recurrence stopped on a
+// zero beta has an invariant Krylov space and zero error.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void entropy_dd(double z, double th, double log_th, double inv_th, double &d1,
