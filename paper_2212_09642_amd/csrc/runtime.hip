@@ -83,10 +83,6 @@ void free_plan(vne_ctx *c, Plan *p) {
     for (auto &kv : p->exec)
         if (kv.second) (void)hipGraphExecDestroy(kv.second);
     p->exec.clear();
-    for (auto &kv : p->part_exec)
-        for (auto &e : kv.second)
-            if (e) (void)hipGraphExecDestroy(e);
-    p->part_exec.clear();
     for (auto &kv : p->chunk_exec)
         if (kv.second) (void)hipGraphExecDestroy(kv.second);
     p->chunk_exec.clear();
@@ -648,19 +644,6 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         hipGraphExec_t &ex = p->exec[key];
         if (!ex) VNE_TRY(capture(&ex, 1, p->k, -1));
         HIP_TRY(c, hipGraphLaunch(ex, c->stream));
-    } else if (use_graph) {
-        auto &parts = p->part_exec[key];
-        if (parts.empty()) {
-            parts.assign(2 * p->k, nullptr);
-            for (int j = 1; j <= p->k; ++j)
-                for (int part = 0; part < 2; ++part) VNE_TRY(capture(&parts[2 * (j - 1) + part], j, j, part));
-        }
-        for (int j = 1; j <= p->k; ++j) {
-            HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1)], c->stream));
-            HIP_TRY(c, hipGraphLaunch(parts[2 * (j - 1)], c->stream));
-            HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1) + 1], c->stream));
-            HIP_TRY(c, hipGraphLaunch(parts[2 * (j - 1) + 1], c->stream));
-        }
     } else {
         for (int j = 1; j <= nsteps; ++j) {
             if (timing) HIP_TRY(c, hipEventRecord(p->ev[2 * (j - 1)], c->stream));
