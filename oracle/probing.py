@@ -13,7 +13,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   model value is written e_1 q^(d-1) / d^kappa, which equals C q^d / d^kappa
   and stays defined at q = 0.
 * bound_d(n, b, eps_hat, d_max): the smallest d >= 2 for which Corollary
-  3.2's bound with a = 0, n b / (2 (d^2 - 1)), is within eps_hat.
+  3.2's bound with a = 0, n b / (2 (d^2 - 1)), is within eps_hat (d_max,
+  flagged capped, when none up to d_max is).
 * select_d(T, eps_hat, n, b, d_max): the smallest d >= 1 whose heuristic
   error is within eps_hat; the bound's d when the fit has no decay (q >= 1
   for either kappa, or e_1 = 0 < e_2).  Both T_d differences zero: d = 1.
@@ -74,11 +75,12 @@ def heuristic_error(d, fits):
 
 def bound_d(n, b, eps_hat, d_max):
     """Smallest d in [2, d_max] with n b / (2 (d^2 - 1)) <= eps_hat, else d_max
-    (with capped=True)."""
-    for d in range(2, max(d_max, 2) + 1):
+    (with capped=True).  Corollary 3.2 covers d >= 2 only: with d_max = 1 the
+    result is d = 1, capped."""
+    for d in range(2, d_max + 1):
         if n * b / (2.0 * (d * d - 1)) <= eps_hat:
             return d, False
-    return max(d_max, 2), True
+    return d_max, True
 
 
 def select_d(T, eps_hat, n, b, d_max):

@@ -12,8 +12,9 @@ namespace vne {
 DistanceChoice probing_bound_distance(double n, double b, double eps_hat, int32_t d_max) {
     DistanceChoice r;
     r.fallback = 1;
-    const int32_t top = std::max<int32_t>(d_max, 2);
-    for (int32_t d = 2; d <= top; ++d) {
+    r.d = d_max;
+    r.model = INFINITY;                  // Corollary 3.2 covers d >= 2 only
+    for (int32_t d = 2; d <= d_max; ++d) {
         const double v = n * b / (2.0 * ((double)d * d - 1.0));
         r.d = d;
         r.model = v;

@@ -17,7 +17,8 @@ struct DistanceChoice {
 };
 
 // Corollary 3.2 with a = 0: the smallest d in [2, d_max] with
-// n b / (2 (d^2 - 1)) <= eps_hat (capped at d_max).
+// n b / (2 (d^2 - 1)) <= eps_hat, else d_max flagged capped (d_max = 1: the
+// corollary covers no allowed d; d = 1, capped).
 DistanceChoice probing_bound_distance(double n, double b, double eps_hat, int32_t d_max);
 
 // Eq. (5.1): |tr f(A) - T_d| ~ C q^d / d^kappa, fitted for kappa = 2 and 3

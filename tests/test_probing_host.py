@@ -44,6 +44,10 @@ def test_choice_edge_cases():
     assert vne.probing_select([2.0, 2.0, 2.0], 1e-3, 1e4, 1e-3, 8)["d"] == 1
     r = vne.probing_select([2.0, 2.0, 2.1], 1e-3, 1e4, 1e-3, 8)
     assert r["fallback"] == 1 and r["capped"] == 1 and r["d"] == 8
+    # Corollary 3.2 starts at d = 2: with d_max = 1 the choice stays at 1, capped
+    for use_bound in (False, True):
+        r = vne.probing_select([2.0, 2.0, 2.1], 1e3, 1e4, 1e-3, 1, use_bound=use_bound)
+        assert (r["d"], r["fallback"], r["capped"]) == (1, 1, 1)
     for bad in [dict(eps_hat=0.0), dict(n=0.0), dict(lambda_ub=-1.0), dict(d_max=0), dict(d_max=65)]:
         args = dict(T=[1.0, 1.1, 1.15], eps_hat=1e-3, n=1e4, lambda_ub=1e-3, d_max=8)
         args.update(bad)
