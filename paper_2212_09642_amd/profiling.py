@@ -53,12 +53,28 @@ def cmd_stats(args):
     print("\n".join(out))
 
 
-def _counter(db, name_filter=None):
+def _counter(db, name_filter=None, skip_steps=0, max_steps=0):
+    """Counter sums per (kernel, counter) over the dispatches matching
+    name_filter, in dispatch order.  skip_steps / max_steps (with step
+    kernels in the filter) keep the dispatches from the (skip_steps + 1)-th
+    Lanczos step kernel on, for max_steps steps (0: all): a step's normalize
+    pass comes before its step kernel, its long rows after."""
     con = sqlite3.connect(db)
     acc = collections.defaultdict(float)
     calls = collections.Counter()
-    for kname, ctr, val in con.execute("select kernel_name, counter_name, value from counters_collection"):
+    rows = con.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection "
+                       "order by dispatch_id").fetchall()
+    step_no = 0          # index of the step the current dispatch belongs to
+    seen_step = False
+    for _, kname, ctr, val in rows:
         if name_filter and not any(k in kname for k in name_filter):
+            continue
+        if "k_normalize" in kname and seen_step:
+            step_no += 1
+            seen_step = False
+        if "k_lanczos_step" in kname:
+            seen_step = True
+        if step_no < skip_steps or (max_steps and step_no >= skip_steps + max_steps):
             continue
         acc[(kname, ctr)] += float(val)
         calls[(kname, ctr)] += 1
@@ -66,8 +82,8 @@ def _counter(db, name_filter=None):
 
 
 def cmd_traffic(args):
-    fetch, fcalls = _counter(args.fetch_db, STEP_KERNELS)
-    write, wcalls = _counter(args.write_db, STEP_KERNELS)
+    fetch, fcalls = _counter(args.fetch_db, STEP_KERNELS, args.skip_steps, args.max_steps)
+    write, wcalls = _counter(args.write_db, STEP_KERNELS, args.skip_steps, args.max_steps)
     cf, _ = _counter(args.copy_fetch_db, ("copyBuffer",))
     cw, _ = _counter(args.copy_write_db, ("copyBuffer",))
     # calibration: what the counters read (KiB per dispatch) for a plain copy
@@ -127,6 +143,8 @@ def main():
     t.add_argument("--workload", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--copies", type=int, default=3)
+    t.add_argument("--skip-steps", type=int, default=0, help="leave out the first Lanczos steps (autotuning)")
+    t.add_argument("--max-steps", type=int, default=0, help="count this many steps after those (0: all)")
     t.add_argument("--cmd", required=True)
     v = sub.add_parser("serve")
     v.add_argument("line")
