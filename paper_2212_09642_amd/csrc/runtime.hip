@@ -552,13 +552,13 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         if (p->G != 1 || p->store) return fail(c, VNE_ENOTSUP, "per-column stopping runs on one graph");
         const int K = p->k, M = p->m;
         const size_t nb = (size_t)(K + 1) * (sizeof(BoundArgs) + sizeof(ColStopArgs));
-        if (!p->col_stop.p) {
-            VNE_TRY(dev_alloc(c, &p->col_stop, (size_t)p->m_pad * 4));
-            VNE_TRY(dev_alloc(c, &p->bound_lo, (size_t)p->m_pad * 8));
-            VNE_TRY(dev_alloc(c, &p->bound_hi, (size_t)p->m_pad * 8));
-            VNE_TRY(dev_alloc(c, &p->adapt_args, nb));
-            VNE_TRY(dev_alloc(c, &p->remaining, 4));
-        }
+        // each buffer on its own, so that a failed allocation leaves no half
+        // set-up plan behind
+        if (!p->col_stop.p) VNE_TRY(dev_alloc(c, &p->col_stop, (size_t)p->m_pad * 4));
+        if (!p->bound_lo.p) VNE_TRY(dev_alloc(c, &p->bound_lo, (size_t)p->m_pad * 8));
+        if (!p->bound_hi.p) VNE_TRY(dev_alloc(c, &p->bound_hi, (size_t)p->m_pad * 8));
+        if (!p->adapt_args.p) VNE_TRY(dev_alloc(c, &p->adapt_args, nb));
+        if (!p->remaining.p) VNE_TRY(dev_alloc(c, &p->remaining, 4));
         if (!p->col_tol.p) return fail(c, VNE_EINVAL, "per-column tolerances not set");
         if (!p->h_remaining) HIP_TRY(c, hipHostMalloc((void **)&p->h_remaining, 4, hipHostMallocDefault));
         p->h_adapt.assign(nb, 0);
@@ -800,20 +800,23 @@ vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int
     VNE_TRY(get_plan(c, set, nr, k, fp64, true, 1, &sk));
     VNE_TRY(get_plan(c, set, m, k, fp64, false, 2, &q));
     const int64_t n = set->n;
-    vne_status st = VNE_OK;
-    if (!q->B.p) {
-        auto A = [&](DevBuf *b, size_t bytes) {
-            if (st == VNE_OK) st = dev_alloc(c, b, bytes);
-        };
-        A(&q->S, (size_t)nr * k * 8);
-        A(&q->B, (size_t)n * m * es);
+    // the Hutch++ workspace of the quadratic-form plan depends on N_r, which
+    // the plan's key (m, k) does not fix: every buffer is checked against
+    // this call's size and replaced when too small
+    auto ensure = [&](DevBuf *b, size_t bytes) -> vne_status {
+        if (b->p && b->bytes >= bytes) return VNE_OK;
+        dev_free(c, b);
+        return dev_alloc(c, b, bytes);
+    };
+    {
         const int64_t gd = std::max(gram_scratch_doubles((int32_t)n, nr, nr),
                                     gram_scratch_doubles((int32_t)n, nr, std::max(nh, 1)));
-        A(&q->gram_part, (size_t)gd * 8);
-        A(&q->gram, (size_t)nr * std::max(nr, nh) * 8);
-        A(&q->rinv, (size_t)nr * nr * 8);
-        A(&q->rot, (size_t)nr * rot_capacity(k) * kRotBytes);
-        VNE_TRY(st);
+        VNE_TRY(ensure(&q->S, (size_t)nr * k * 8));
+        VNE_TRY(ensure(&q->B, (size_t)n * m * es));
+        VNE_TRY(ensure(&q->gram_part, (size_t)gd * 8));
+        VNE_TRY(ensure(&q->gram, (size_t)nr * std::max(nr, nh) * 8));
+        VNE_TRY(ensure(&q->rinv, (size_t)nr * nr * 8));
+        VNE_TRY(ensure(&q->rot, (size_t)nr * rot_capacity(k) * kRotBytes));
     }
     sk->h_graph_k = {k};
     sk->h_graph_m = {nr};

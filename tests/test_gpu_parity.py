@@ -320,3 +320,27 @@ def test_quadrature_negative_and_near_null_spectrum(ctx, fp64, neg):
         # past the first Ritz convergences plain Lanczos is rounding-sensitive
         _check_quad(out, want, fp64, sens=_order_sensitivity(A, B, k, fp64, desing=False), n=n)
     ctx.release(gid)
+
+
+def test_hutchpp_changing_sketch_width(ctx):
+    """The same (m, k) with a different N_r on each call: the workspace sized
+    for N_r = 8 must grow for N_r = 96 and still serve N_r = 8 afterwards;
+    each estimate against the oracle's."""
+    _say("case Hutch++ with N_r = 8, 96, 8 at the same m, k")
+    n, e = synth.erdos_renyi(2500, 6.0, 17)
+    gid, ref = _setup(ctx, n, e, True)
+    m, k = 128, 20
+    mode = vne.MODE_DESING | vne.MODE_F64
+    import scipy.sparse as sp
+    P = np.arange(ref.n)[::-1]
+    Ap = sp.csr_matrix(ref.scipy())[P][:, P]
+    for nr in (8, 96, 8):
+        out = ctx.estimate(gid, vne.PROBE_HUTCHPP, m, k, mode, seed=5, n_sketch=nr, want_coeffs=False)
+        Om = oracle.rademacher_block(5, ref.node_ids, np.arange(nr))
+        G = oracle.rademacher_block(5, ref.node_ids, np.arange(nr, m))
+        est, _ = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(True))
+        est_p, _ = oracle.hutchpp(Ap, Om[P], G[P], k, oracle.breakdown_tau(True))
+        err, sens = abs(out["estimate"] - est) / abs(est), abs(est_p - est) / abs(est)
+        _say("   N_r=%d estimate rel err %.2e (sens %.1e)" % (nr, err, sens))
+        assert err < max(TOL[True], 20 * sens)
+    ctx.release(gid)
