@@ -281,12 +281,13 @@ def run_serve(args):
                                                        max(p[1] for p in pool), time.perf_counter() - t0),
           file=sys.stderr, flush=True)
     eps = 1e-3
-    srv = vne.Server(ctx, vne.MODE_DESING, arena_bytes=int(args.arena_gb * (1 << 30)), max_slots=64,
+    srv = vne.Server(ctx, vne.MODE_DESING, arena_bytes=int(args.arena_gb * (1 << 30)), max_slots=args.max_slots,
                      max_probes=4096)
     # untimed: one query per graph (device arrays of every graph, first launches)
     for gid, *_ in pool:
         srv.poll(srv.submit(gid, rel_eps=eps, seed=1))
     rows = []
+    prev = srv.stats()
     for rate in [float(r) for r in args.rates.split(",")]:
         rng = np.random.Generator(np.random.PCG64(workloads.GRAPH_SEED_SERVE + int(rate)))
         gaps = rng.exponential(1.0 / rate, args.queries)
@@ -309,12 +310,18 @@ def run_serve(args):
                  for r, pk in res)
         met = sum(2.576 * r["std_error"] <= 0.5 * eps * abs(r["estimate"]) for r, _ in res)
         info = srv.stats()
+        # this rate's share of the server's running counters
+        dt_ticks = max(1, info["ticks"] - prev["ticks"])
+        occ = (info["slot_occupancy"] * info["ticks"] - prev["slot_occupancy"] * prev["ticks"]) / dt_ticks
+        tasks, pairs = info["tasks"] - prev["tasks"], info["pair_slots"] - prev["pair_slots"]
+        prev = info
         row = {"offered_per_s": rate, "queries": args.queries, "completed": ok,
                "completed_per_s": round(ok / wall, 3), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                "p99_ms": round(float(np.percentile(lat, 99)), 3), "algorithmic_GBps": round(by / wall / 1e9, 2),
                "mean_probes": round(float(np.mean([r["probes"] for r, _ in res])), 1),
                "mean_steps": round(float(np.mean([r["steps"] for r, _ in res])), 1),
-               "sampling_target_met": met, "slot_occupancy": round(info["slot_occupancy"], 2)}
+               "sampling_target_met": met, "slot_occupancy": round(occ, 2), "tasks": tasks,
+               "tasks_in_pair_slots": 2 * pairs}
         print("rate %s" % json.dumps(row), file=sys.stderr, flush=True)
         rows.append(row)
     srv.stop()
@@ -452,6 +459,7 @@ def main():
     ap.add_argument("--queries", type=int, default=200, help="serve workload: queries per rate")
     ap.add_argument("--pool", type=int, default=24, help="serve workload: graphs in the pool")
     ap.add_argument("--arena-gb", type=float, default=96.0, help="serve workload: server arena (GiB)")
+    ap.add_argument("--max-slots", type=int, default=64, help="serve workload: tasks running at once")
     ap.add_argument("--graph", default="ws", help="probing-eps workload: ws (small-world) or ring (lattice)")
     ap.add_argument("--rel-eps", type=float, default=1e-3, help="probing-eps workload: relative target")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -371,7 +371,14 @@ vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, dou
  * frees its slot at once, and the query's estimate is combined on the device
  * when its last task ends.  A task's arithmetic depends only on its own graph,
  * probes and step count, so a query's result is bitwise the same alone and
- * among any other queries (for the same server mode).
+ * among any other queries (for the same server mode).  Two 16-column tasks
+ * (FP32 mode) of the same graph with the same step cap and stopping rule may
+ * share a pair slot, admitted together: the two 16-column tiles of a work
+ * block run in one workgroup and read each neighbour's 32 columns as one
+ * 128-byte run, where one task alone would use half of every cache line it
+ * fetches.  Each task keeps its own probes, stop record and results, with the
+ * arithmetic it has alone; a pair slot's step kernels stop running once both
+ * tasks have met their stopping rule.
  *
  * rel_eps == 0: the query gives m (<= max_probes) and k_steps (<= 128).
  * rel_eps > 0: half of the relative error budget goes to the quadrature and
@@ -437,7 +444,8 @@ typedef struct {
     int64_t ticks, tasks, queries_done;
     double slot_occupancy;      /* mean running tasks per tick */
     uint64_t arena_bytes, arena_in_use, arena_peak;
-    int32_t active, pending;
+    int32_t active, pending;    /* running and waiting tasks */
+    int64_t pair_slots;         /* slots admitted with two tasks */
 } vne_server_info;
 
 /* Start a server on ctx.  cfg is copied.  Fails with VNE_ENOMEM when the

@@ -113,7 +113,7 @@ class _ServerInfo(ctypes.Structure):
     _fields_ = [("ticks", ctypes.c_int64), ("tasks", ctypes.c_int64), ("queries_done", ctypes.c_int64),
                 ("slot_occupancy", ctypes.c_double), ("arena_bytes", ctypes.c_uint64),
                 ("arena_in_use", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64), ("active", ctypes.c_int32),
-                ("pending", ctypes.c_int32)]
+                ("pending", ctypes.c_int32), ("pair_slots", ctypes.c_int64)]
 
 
 _LIB = None

@@ -53,6 +53,12 @@ struct StepArgs {
     const int32_t *row_graph;   // [n]
     const int32_t *long_graph;  // [n_long]
     const double *graph_scale;  // [G]
+    // serving slots: records {stop_uid + i, j > 0} at stop_state[i] for every
+    // i < stop_count (nullptr: none) mean that every task sharing the slot
+    // has met its stopping rule; the slot's kernels then return at once
+    const int2 *stop_state;
+    int32_t stop_uid;
+    int32_t stop_count;
 };
 
 constexpr int kLevel2 = 32;       // first-level reduction rows of the step partials
@@ -82,6 +88,11 @@ struct FinalizeArgs {
     const int32_t *graph_long_begin;   // [G+1]
     const int32_t *graph_k;            // [G] (nullptr: k)
     const int32_t *graph_m;            // [G] (nullptr: m)
+    const int2 *stop_state;            // slots: as in StepArgs
+    int32_t stop_uid;
+    int32_t stop_count;
+    int32_t *flags_hi;                 // slots: flags of columns >= flag_split (nullptr: flags)
+    int32_t flag_split;
 };
 
 // Returns the column tile width the step kernel uses for this probe width.
@@ -105,6 +116,12 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_step_slots(const StepArgs *args, const int4 *step_map, int32_t n_step, const int4 *long_map,
                              int32_t n_long, int32_t mt, bool fp64, hipStream_t s);
 int long_rows_per_group(int mt, bool fp64);
+// Slots of exactly two 16-column FP32 tiles (m_pad = 32, mt = 16), both
+// tiles of a work block in one workgroup: pair_map entries {slot, work block,
+// 0, 0}; long_map entries {slot, group, tile, 0} as for mt = 16.  Every
+// column gets the same arithmetic, in the same order, as in a 16-column slot.
+hipError_t launch_step_pairs(const StepArgs *args, const int4 *pair_map, int32_t n_pair, const int4 *long_map,
+                             int32_t n_long, hipStream_t s);
 constexpr int kFinalizeCols = 16;
 constexpr int kSlotLevel2 = 16;   // first-level parts of a slot's reduction (FinalizeArgs.n_level2)
 hipError_t launch_finalize_slots(const FinalizeArgs *fargs, const int2 *map, int32_t n_entries, hipStream_t s);
@@ -120,7 +137,8 @@ struct ProbeArgs {
     const void *dense;          // [n][ld_dense] (dense), element type of the mode
     int32_t ld_dense;
     int32_t desing;
-    void *P_out;                // [n][m_pad]
+    void *P_out;                // [n][ld_out]
+    int32_t ld_out;             // row stride of P_out (0: m_pad)
     double *partials;           // scratch [n_blocks][m_pad]
     int32_t n_blocks;
     double *mean;               // [m_pad]
@@ -175,6 +193,9 @@ struct BoundArgs {
     double *lo, *hi;            // [m]
     int32_t *flags;             // QR status bits
     const int32_t *col_stop;    // [m] or NULL: columns with a recorded stop step are skipped
+    const int2 *stop_state;     // slots: as in StepArgs (the whole problem is skipped)
+    int32_t stop_uid;
+    int32_t stop_count;
 };
 // map entries {problem, group of 4 columns}
 hipError_t launch_error_bound(const BoundArgs *args, const int2 *map, int32_t n_entries, hipStream_t s);

@@ -319,28 +319,36 @@ __global__ void __launch_bounds__(256) k_normalize(StepArgs a) {
     }
 }
 
-// One work block b of the schedule, column tile `tile`: its segments, then
-// its rows, and the block's partial sums (red: shared scratch of the block).
-template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
-__device__ __forceinline__ void step_block(const StepArgs &a, int b, int tile,
+// One work block b of the schedule, column tiles tile0 .. tile0 + JT - 1:
+// its segments, then its rows, and the block's partial sums (red: shared
+// scratch of the block, 3 rows per tile).  Each tile has NG lane groups that
+// take the block's items round robin, whatever JT is, so a tile's arithmetic
+// (and its order) is the same in a JT-tile block of JT * kStepThreads
+// threads as alone.  With JT > 1 the lane groups of the JT tiles of one item
+// sit side by side in a wave: their gathers of one neighbour row are one
+// contiguous run of JT * MT columns (narrow tiles fill whole cache lines).
+template <typename T, int CPL, int LPR, bool FIRST, bool TWO, int JT = 1>
+__device__ __forceinline__ void step_block(const StepArgs &a, int b, int tile0,
                                            double (*red)[(kStepThreads / 64) * (64 / LPR) * CPL * LPR]) {
+    static_assert(JT == 1 || LPR * JT <= 64, "the tiles of an item share a wave");
     using Core = StepCore<T, CPL, LPR, FIRST, TWO>;
     constexpr int MT = Core::MT;
     constexpr int GPW = 64 / LPR;                    // lane groups per wave
-    constexpr int NG = (kStepThreads / 64) * GPW;    // lane groups per block
+    constexpr int NG = (kStepThreads / 64) * GPW;    // lane groups per block and tile
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int grp = lane / LPR;
+    const int sub = lane / LPR;
     const int gl = lane % LPR;
-    const int gid = wave * GPW + grp;
+    const int jt = JT == 1 ? 0 : sub % JT;
+    const int gid = wave * (GPW / JT) + sub / JT;
     const int g = a.block_graph ? a.block_graph[b] : 0;
-    const Core core(a, tile, gl, g);
+    const Core core(a, tile0 + jt, gl, g);
 
     // the lane group's running sums of v.w, w.w, v.v live in its own slots
     // of red (fixed order within the group)
-    double *my0 = &red[0][gid * MT + gl * CPL];
-    double *my1 = &red[1][gid * MT + gl * CPL];
-    double *my2 = &red[2][gid * MT + gl * CPL];
+    double *my0 = &red[3 * jt + 0][gid * MT + gl * CPL];
+    double *my1 = &red[3 * jt + 1][gid * MT + gl * CPL];
+    double *my2 = &red[3 * jt + 2][gid * MT + gl * CPL];
 #pragma unroll
     for (int k = 0; k < CPL; ++k) my0[k] = my1[k] = my2[k] = 0.0;
 
@@ -438,13 +446,14 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int b, int tile,
     // block reduction over the lane groups that share columns (fixed order)
     __syncthreads();
     // partials layout [n_blocks][3][m_pad]: the finalize reads whole rows
-    double *out = a.partials + (int64_t)b * 3 * a.m_pad + tile * MT;
-    for (int t = threadIdx.x; t < 3 * MT; t += kStepThreads) {
-        const int sidx = t / MT, cc = t % MT;
+    double *out = a.partials + (int64_t)b * 3 * a.m_pad + tile0 * MT;
+    for (int t = threadIdx.x; t < JT * 3 * MT; t += JT * kStepThreads) {
+        const int row = t / MT, cc = t % MT;         // row = 3 * tile + sum index
+        const int tj = row / 3, sidx = row % 3;
         double sum = 0.0;
 #pragma unroll 4
-        for (int g = 0; g < NG; ++g) sum += red[sidx][g * MT + cc];
-        out[(int64_t)sidx * a.m_pad + cc] = sum;
+        for (int g = 0; g < NG; ++g) sum += red[row][g * MT + cc];
+        out[(int64_t)tj * MT + (int64_t)sidx * a.m_pad + cc] = sum;
     }
 }
 
@@ -464,6 +473,19 @@ __global__ void __launch_bounds__(kStepThreads) VNE_STEP_OCCUPANCY k_lanczos_ste
 // matrix, vectors and state args[e.x] describes.  Two-pass schedule; the
 // first step of a slot runs as a later step whose v_{j-1} is zero and whose
 // alpha_{j-1}, beta_{j-1} are zero, which gives the same values.
+// A slot whose stopping rule was met at an earlier step: the quadrature
+// takes that step's coefficients, so later steps are skipped (the host learns
+// of the stop a few ticks after the device).  The record is written by a
+// kernel of an earlier tick, so every kernel of a tick sees the same value.
+__device__ __forceinline__ bool slot_stopped(const int2 *state, int32_t uid, int32_t count) {
+    if (!state) return false;
+    for (int i = 0; i < count; ++i) {
+        const int2 st = state[i];
+        if (st.x != uid + i || st.y <= 0) return false;
+    }
+    return true;
+}
+
 template <typename T, int CPL, int LPR>
 __global__ void __launch_bounds__(kStepThreads) VNE_STEP_OCCUPANCY k_lanczos_step_slots(const StepArgs *args, const int4 *map,
                                                                      int32_t n_entries) {
@@ -471,7 +493,22 @@ __global__ void __launch_bounds__(kStepThreads) VNE_STEP_OCCUPANCY k_lanczos_ste
     __shared__ double red[3][NG * CPL * LPR];
     const int4 e = map[xcd_remap(blockIdx.x, n_entries)];
     const StepArgs a = args[e.x];
+    if (slot_stopped(a.stop_state, a.stop_uid, a.stop_count)) return;
     step_block<T, CPL, LPR, false, true>(a, e.y, e.z, red);
+}
+
+// Two column tiles of one slot per block (2 * kStepThreads threads): entry
+// {slot, work block, first tile}.  For slots of two narrow tiles, whose
+// single-tile blocks would each gather half of every cache line they fetch.
+template <typename T, int CPL, int LPR>
+__global__ void __launch_bounds__(2 * kStepThreads) k_lanczos_step_pairs(const StepArgs *args, const int4 *map,
+                                                                          int32_t n_entries) {
+    constexpr int NG = (kStepThreads / 64) * (64 / LPR);
+    __shared__ double red[2 * 3][NG * CPL * LPR];
+    const int4 e = map[xcd_remap(blockIdx.x, n_entries)];
+    const StepArgs a = args[e.x];
+    if (slot_stopped(a.stop_state, a.stop_uid, a.stop_count)) return;
+    step_block<T, CPL, LPR, false, true, 2>(a, e.y, e.z, red);
 }
 
 // Normalize pass of the slots: entry {slot, work block, tile} writes v_j on
@@ -482,6 +519,7 @@ __global__ void __launch_bounds__(256) k_normalize_slots(const StepArgs *args, c
     constexpr int RP = 256 / LPR;                    // rows per pass
     const int4 e = map[xcd_remap(blockIdx.x, n_entries)];
     const StepArgs a = args[e.x];
+    if (slot_stopped(a.stop_state, a.stop_uid, a.stop_count)) return;
     const int4 rg = a.block_ranges[e.y];
     const int c0 = e.z * MT + (int)(threadIdx.x % LPR) * CPL;
     const T *P = static_cast<const T *>(a.P_in);
@@ -564,6 +602,7 @@ template <typename T, int CPL, int LPR>
 __global__ void __launch_bounds__(256) k_long_rows_slots(const StepArgs *args, const int4 *map) {
     const int4 e = map[blockIdx.x];
     const StepArgs a = args[e.x];
+    if (slot_stopped(a.stop_state, a.stop_uid, a.stop_count)) return;
     long_rows_group<T, CPL, LPR, false, true>(a, e.y, e.z);
 }
 
@@ -643,6 +682,18 @@ hipError_t launch_step_slots(const StepArgs *args, const int4 *step_map, int32_t
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_pairs(const StepArgs *args, const int4 *pair_map, int32_t n_pair, const int4 *long_map,
+                             int32_t n_long, hipStream_t s) {
+    if (n_pair > 0) {
+        // the normalize pass is elementwise: both tiles as one 32-column tile
+        hipLaunchKernelGGL((k_normalize_slots<float, 4, 8>), dim3(n_pair), dim3(256), 0, s, args, pair_map, n_pair);
+        hipLaunchKernelGGL((k_lanczos_step_pairs<float, 4, 4>), dim3(n_pair), dim3(2 * kStepThreads), 0, s, args,
+                           pair_map, n_pair);
+    }
+    if (n_long > 0) hipLaunchKernelGGL((k_long_rows_slots<float, 4, 4>), dim3(n_long), dim3(256), 0, s, args, long_map);
+    return hipGetLastError();
 }
 
 hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s) {
@@ -750,7 +801,7 @@ __device__ __forceinline__ void update_coefficients(const FinalizeArgs &a, int g
     const double beta = sqrt(b2);
     a.alpha[gc * a.k + j] = alpha;
     const bool finite = isfinite(alpha) && isfinite(beta);
-    if (!finite) atomicOr(a.flags, 1);
+    if (!finite) atomicOr(a.flags_hi && c >= a.flag_split ? a.flags_hi : a.flags, 1);
     if (!finite || beta <= a.tau * (fabs(alpha) + coup_prev)) {
         a.k_eff[gc] = a.step;
         a.beta[gc * a.k + j] = 0.0;
@@ -853,6 +904,7 @@ __global__ void __launch_bounds__(256) k_reduce_slots(const FinalizeArgs *fargs,
     __shared__ double sh[3][G][C];
     const int2 e = map[blockIdx.x];
     const FinalizeArgs a = fargs[e.x];
+    if (slot_stopped(a.stop_state, a.stop_uid, a.stop_count)) return;
     const int r = blockIdx.y;
     const int cc = threadIdx.x % C, grp = threadIdx.x / C;
     const int c = e.y * C + cc;
@@ -898,6 +950,7 @@ __global__ void __launch_bounds__(256) k_reduce_slots(const FinalizeArgs *fargs,
 __global__ void __launch_bounds__(kFinalizeCols) k_finalize_slots(const FinalizeArgs *fargs, const int2 *map) {
     const int2 e = map[blockIdx.x];
     const FinalizeArgs a = fargs[e.x];
+    if (slot_stopped(a.stop_state, a.stop_uid, a.stop_count)) return;
     const int c = e.y * kFinalizeCols + threadIdx.x;
     if (c >= a.m_pad) return;
     double svw = 0.0, sww = 0.0, svv = 0.0;
@@ -974,6 +1027,7 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     const int g = a.block_graph ? a.block_graph[b] : 0;
     const int64_t r0 = a.block_row_begin[b], r1 = a.block_row_begin[b + 1];
     T *P = static_cast<T *>(a.P_out);
+    const int64_t ld = a.ld_out > 0 ? a.ld_out : a.m_pad;
     for (int t0 = 0; t0 < a.m_pad; t0 += a.mt) {
         const int c = t0 + cc;
         double acc = 0.0;
@@ -984,7 +1038,7 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
                 acc += v;
             } else {
                 const T cv = (T)(v - mu);
-                P[i * a.m_pad + c] = cv;
+                P[i * ld + c] = cv;
                 acc += (double)cv * (double)cv;
             }
         }
@@ -1639,6 +1693,7 @@ __device__ void bound_column(const BoundArgs &a, int c, int lane) {
 __global__ void __launch_bounds__(256) k_error_bound(const BoundArgs *args, const int2 *map) {
     const int2 e = map[blockIdx.x];
     const BoundArgs a = args[e.x];
+    if (slot_stopped(a.stop_state, a.stop_uid, a.stop_count)) return;
     const int c = __builtin_amdgcn_readfirstlane(e.y * 4 + (int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (c >= a.m) return;

@@ -48,10 +48,26 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-struct SrvTask {
+// One query's share of a slot: its columns, stopping rule and mailbox entry.
+struct SrvMember {
     uint64_t ticket = 0;
-    int m = 0, m_pad = 0, mt = 0, k = 0, col0 = 0;
+    int m = 0;                       // probe columns
+    int col0 = 0;                    // first column of the query's probe set
+    int c_off = 0;                   // first column within the slot
     bool pilot = false;
+    bool adaptive = false;           // a-posteriori stopping (rel_eps > 0)
+    double tol = 0.0;                // per quadratic form
+    int32_t uid = 0, slot = -1;      // stop record id, mailbox entry while running
+    bool ended = false;
+};
+
+// A slot: one task of a query, or two 16-column FP32 tasks of two queries on
+// the same graph with the same step cap (pair slot, m_pad = 32, mt = 16),
+// whose two column tiles share one workgroup per work block.  Members keep
+// their own probes, stop records and results; every column gets the
+// arithmetic it gets alone.
+struct SrvTask {
+    int m = 0, m_pad = 0, mt = 0, k = 0;
     int j = 0;                       // steps done
     uint64_t off = 0, bytes = 0;
     char *P[2] = {nullptr, nullptr}, *V[2] = {nullptr, nullptr};
@@ -59,12 +75,11 @@ struct SrvTask {
     double *norm2 = nullptr, *mean = nullptr, *partials = nullptr, *probe_part = nullptr;
     double *seg_acc = nullptr, *long_part = nullptr, *level2 = nullptr;
     int32_t *k_eff = nullptr;
-    // a-posteriori stopping (queries with rel_eps > 0)
-    bool adaptive = false;
-    double tol = 0.0;                // per quadratic form
-    int32_t uid = 0, slot = -1;      // mailbox entry while running
     double *b_lo = nullptr, *b_hi = nullptr;
-    int2 *d_state = nullptr;         // {uid, first step within tol}
+    int2 *d_state = nullptr;         // [n_mem] {uid, first step within tol}
+    int n_mem = 1;
+    SrvMember mem[2];
+    bool pair() const { return n_mem == 2; }
 };
 
 struct SrvQuery {
@@ -129,7 +144,7 @@ struct vne_server {
     int32_t next_uid = 1;
 
     // statistics (worker-owned; snap is the copy readers see)
-    int64_t ticks = 0, tasks_admitted = 0, queries_done = 0;
+    int64_t ticks = 0, tasks_admitted = 0, queries_done = 0, pair_slots = 0;
     double occupancy_sum = 0.0;
     vne_server_info snap{};
 };
@@ -219,15 +234,17 @@ void add_tasks(vne_server *s, SrvQuery &q, int c0, int c1, bool pilot) {
             while (2 * w <= rem) w *= 2;
         }
         SrvTask t;
-        t.ticket = q.ticket;
         t.m = w;
         t.mt = choose_tile(t.m, s->fp64, 0);
         t.m_pad = pad_columns(t.m, t.mt);
         t.k = q.k;
-        t.col0 = c;
-        t.pilot = pilot;
-        t.adaptive = q.q.rel_eps > 0.0 && q.s_lower > 0.0;
-        t.tol = 0.5 * q.q.rel_eps * q.s_lower;
+        SrvMember &u = t.mem[0];
+        u.ticket = q.ticket;
+        u.m = w;
+        u.col0 = c;
+        u.pilot = pilot;
+        u.adaptive = q.q.rel_eps > 0.0 && q.s_lower > 0.0;
+        u.tol = 0.5 * q.q.rel_eps * q.s_lower;
         t.bytes = task_bytes(q.set, t.m_pad, t.k, s->fp64);
         ts.push_back(t);
         c += w;
@@ -235,7 +252,7 @@ void add_tasks(vne_server *s, SrvQuery &q, int c0, int c1, bool pilot) {
     q.cols_issued = c1;
     q.tasks_open += (int)ts.size();
     auto pos = s->pending.begin();
-    while (pos != s->pending.end() && pos->ticket <= q.ticket) ++pos;
+    while (pos != s->pending.end() && pos->mem[0].ticket <= q.ticket) ++pos;
     s->pending.insert(pos, ts.begin(), ts.end());
 }
 
@@ -300,7 +317,7 @@ void finish_query(vne_server *s, SrvQuery &q, vne_status st, const std::string &
 // Drops the pending tasks of a query and reports the failure.
 void fail_query(vne_server *s, SrvQuery &q, vne_status st, const std::string &msg) {
     s->pending.erase(std::remove_if(s->pending.begin(), s->pending.end(),
-                                    [&](const SrvTask &t) { return t.ticket == q.ticket; }),
+                                    [&](const SrvTask &t) { return t.mem[0].ticket == q.ticket; }),
                      s->pending.end());
     q.stage_wait = q.final_wait = false;
     finish_query(s, q, st, msg);
@@ -383,12 +400,80 @@ vne_status poll_events(vne_server *s, bool block_one) {
     return VNE_OK;
 }
 
-// Starts waiting tasks while slots and arena space allow (first come, first
-// served: a task that does not fit blocks the ones behind it).
+// The query's own arena block (psi, estimate, flags), pinned buffer and
+// event, taken when its first task is admitted.  false: no room.
+bool open_query(vne_server *s, SrvQuery *q, vne_status *st) {
+    *st = VNE_OK;
+    if (!s->arena.alloc(s->query_bytes, &q->off)) return false;
+    char *qb = (char *)s->arena_mem.p + q->off;
+    q->d_psi = (double *)qb;
+    q->d_est = (double *)(qb + rnd((size_t)s->psi_cap * 8));
+    q->d_flags = (int32_t *)(qb + rnd((size_t)s->psi_cap * 8) + 256);
+    q->h_buf = get_pinned(s);
+    q->ev = get_event(s);
+    q->started = true;
+    q->t_admit = Clock::now();
+    if (!q->h_buf || !q->ev) {
+        *st = srv_hip(s, hipErrorOutOfMemory, "pinned buffer or event");
+        return true;
+    }
+    const hipError_t e = hipMemsetAsync(q->d_flags, 0, 4, s->stream);
+    if (e != hipSuccess) *st = srv_hip(s, e, "hipMemsetAsync");
+    return true;
+}
+
+// A task that can share a pair slot: 16 FP32 columns in one 16-column tile.
+bool pairable(const vne_server *s, const SrvTask &t) {
+    return !s->fp64 && t.n_mem == 1 && t.m == 16 && t.m_pad == 16 && t.mt == 16;
+}
+
+constexpr int kPairWindow = 256;   // pending tasks searched for a partner
+
+// Probe block of member i (the query's hash columns col0.., eq. (3.8)) into
+// its columns of the slot.
+vne_status member_probes(vne_server *s, SrvTask &t, int i, const SrvQuery *q) {
+    const SrvMember &u = t.mem[i];
+    const GraphSet *set = q->set;
+    const size_t es = s->fp64 ? 8 : 4;
+    ProbeArgs pa{};
+    pa.gen = GEN_RADEMACHER;
+    pa.n = (int32_t)set->n;
+    pa.m = u.m;
+    pa.m_pad = t.pair() ? t.mt : t.m_pad;
+    pa.mt = t.mt;
+    pa.ld_out = t.m_pad;
+    pa.col_offset = u.col0;
+    pa.seed = q->q.seed;
+    pa.keys = (const int64_t *)set->keys.p;
+    pa.desing = s->desing ? 1 : 0;
+    pa.P_out = t.P[0] + (size_t)u.c_off * es;
+    pa.partials = t.probe_part;
+    pa.n_blocks = set->probe_blocks;
+    pa.mean = t.mean + u.c_off;
+    pa.norm2 = t.norm2 + u.c_off;
+    pa.st_alpha = t.st_alpha + u.c_off;
+    pa.st_inv = t.st_inv + u.c_off;
+    pa.st_coup = t.st_coup + u.c_off;
+    pa.k_eff = t.k_eff + u.c_off;
+    pa.k = t.k;
+    pa.block_row_begin = (const int32_t *)set->probe_rows.p;
+    pa.block_graph = (const int32_t *)set->probe_block_graph.p;
+    pa.graph_block_begin = (const int32_t *)set->probe_graph_begin.p;
+    pa.graph_row_begin = (const int64_t *)set->graph_row_begin.p;
+    pa.n_graphs = 1;
+    SRV_HIP(s, launch_probe(pa, s->fp64, s->stream));
+    return VNE_OK;
+}
+
+// Starts waiting tasks while mailbox entries and arena space allow (first
+// come, first served: a task that does not fit blocks the ones behind it).
+// A 16-column FP32 task takes the first waiting 16-column task of the same
+// graph with the same step cap and stopping mode as its partner in a pair
+// slot, when the arena has room for it.
 vne_status admit(vne_server *s) {
-    while (!s->pending.empty() && (int)s->active.size() < s->cfg.max_slots) {
+    while (!s->pending.empty() && !s->free_slots.empty()) {
         SrvTask t = s->pending.front();
-        SrvQuery *q = query_of(s, t.ticket);
+        SrvQuery *q = query_of(s, t.mem[0].ticket);
         const size_t need = t.bytes + (q->started ? 0 : s->query_bytes);
         if (need > s->arena.size()) {
             fail_query(s, *q, VNE_ENOMEM,
@@ -396,61 +481,83 @@ vne_status admit(vne_server *s) {
                            std::to_string(s->arena.size()));
             continue;
         }
+        // partner search
+        int partner = -1;
+        SrvQuery *pq = nullptr;
+        size_t pair_bytes = 0;
+        if (pairable(s, t) && s->free_slots.size() >= 2) {
+            const int lim = std::min<int>((int)s->pending.size(), kPairWindow);
+            for (int i = 1; i < lim; ++i) {
+                const SrvTask &c = s->pending[i];
+                if (!pairable(s, c) || c.k != t.k || c.mem[0].adaptive != t.mem[0].adaptive) continue;
+                SrvQuery *cq = query_of(s, c.mem[0].ticket);
+                if (!cq || cq->set != q->set) continue;
+                partner = i;
+                pq = cq;
+                break;
+            }
+            if (partner > 0) {
+                pair_bytes = task_bytes(q->set, 32, t.k, s->fp64);
+                size_t room = s->arena.round(pair_bytes);
+                if (!q->started) room += s->query_bytes;
+                if (pq != q && !pq->started) room += s->query_bytes;
+                if (s->arena.largest_free() < room) partner = -1;
+            }
+        }
         if (!q->started) {
             if (s->arena.largest_free() < s->query_bytes + s->arena.round(t.bytes)) break;
-            if (!s->arena.alloc(s->query_bytes, &q->off)) break;
-            char *qb = (char *)s->arena_mem.p + q->off;
-            q->d_psi = (double *)qb;
-            q->d_est = (double *)(qb + rnd((size_t)s->psi_cap * 8));
-            q->d_flags = (int32_t *)(qb + rnd((size_t)s->psi_cap * 8) + 256);
-            q->h_buf = get_pinned(s);
-            q->ev = get_event(s);
-            if (!q->h_buf || !q->ev) return srv_hip(s, hipErrorOutOfMemory, "pinned buffer or event");
-            SRV_HIP(s, hipMemsetAsync(q->d_flags, 0, 4, s->stream));
-            q->started = true;
-            q->t_admit = Clock::now();
+            vne_status st;
+            if (!open_query(s, q, &st)) break;
+            VNE_TRY(st);
         }
-        if (!s->arena.alloc(t.bytes, &t.off)) break;
+        if (partner > 0 && !pq->started) {
+            vne_status st;
+            if (!open_query(s, pq, &st)) partner = -1;
+            VNE_TRY(st);
+        }
+        if (partner > 0) {
+            t.mem[1] = s->pending[partner].mem[0];
+            t.mem[1].c_off = 16;
+            t.n_mem = 2;
+            t.m = 32;
+            t.m_pad = 32;
+            t.bytes = pair_bytes;
+        }
+        if (!s->arena.alloc(t.bytes, &t.off)) {
+            if (partner < 0) break;
+            // no room for the pair after all: the task alone
+            partner = -1;
+            t.n_mem = 1;
+            t.m = t.m_pad = 16;
+            t.bytes = task_bytes(q->set, 16, t.k, s->fp64);
+            if (!s->arena.alloc(t.bytes, &t.off)) break;
+        }
         s->arena_peak = std::max(s->arena_peak, s->arena.in_use());
+        if (partner > 0) s->pending.erase(s->pending.begin() + partner);
         s->pending.pop_front();
         carve(t, (char *)s->arena_mem.p + t.off, q->set, s->fp64);
-        t.uid = s->next_uid++;
-        t.slot = s->free_slots.back();
-        s->free_slots.pop_back();
-        SRV_HIP(s, hipMemsetAsync(t.d_state, 0, sizeof(int2), s->stream));
-        // probe block (the query's hash columns col0.., eq. (3.8)) and zero v_0
-        const GraphSet *set = q->set;
-        ProbeArgs pa{};
-        pa.gen = GEN_RADEMACHER;
-        pa.n = (int32_t)set->n;
-        pa.m = t.m;
-        pa.m_pad = t.m_pad;
-        pa.mt = t.mt;
-        pa.col_offset = t.col0;
-        pa.seed = q->q.seed;
-        pa.keys = (const int64_t *)set->keys.p;
-        pa.desing = s->desing ? 1 : 0;
-        pa.P_out = t.P[0];
-        pa.partials = t.probe_part;
-        pa.n_blocks = set->probe_blocks;
-        pa.mean = t.mean;
-        pa.norm2 = t.norm2;
-        pa.st_alpha = t.st_alpha;
-        pa.st_inv = t.st_inv;
-        pa.st_coup = t.st_coup;
-        pa.k_eff = t.k_eff;
-        pa.k = t.k;
-        pa.block_row_begin = (const int32_t *)set->probe_rows.p;
-        pa.block_graph = (const int32_t *)set->probe_block_graph.p;
-        pa.graph_block_begin = (const int32_t *)set->probe_graph_begin.p;
-        pa.graph_row_begin = (const int64_t *)set->graph_row_begin.p;
-        pa.n_graphs = 1;
-        SRV_HIP(s, launch_probe(pa, s->fp64, s->stream));
-        SRV_HIP(s, hipMemsetAsync(t.V[1], 0, (size_t)set->n * t.m_pad * (s->fp64 ? 8 : 4), s->stream));
+        for (int i = 0; i < t.n_mem; ++i) {
+            t.mem[i].uid = s->next_uid + i;
+            t.mem[i].slot = s->free_slots.back();
+            s->free_slots.pop_back();
+        }
+        s->next_uid += t.n_mem;
+        SRV_HIP(s, hipMemsetAsync(t.d_state, 0, sizeof(int2) * t.n_mem, s->stream));
+        VNE_TRY(member_probes(s, t, 0, q));
+        if (t.pair()) VNE_TRY(member_probes(s, t, 1, pq));
+        // zero v_0
+        SRV_HIP(s, hipMemsetAsync(t.V[1], 0, (size_t)q->set->n * t.m_pad * (s->fp64 ? 8 : 4), s->stream));
         s->active.push_back(t);
-        s->tasks_admitted++;
+        s->tasks_admitted += t.n_mem;
+        s->pair_slots += t.pair() ? 1 : 0;
     }
     return VNE_OK;
+}
+
+bool all_adaptive(const SrvTask &t) {
+    for (int i = 0; i < t.n_mem; ++i)
+        if (!t.mem[i].adaptive) return false;
+    return true;
 }
 
 StepArgs step_args(const vne_server *s, const SrvTask &t, const GraphSet *set) {
@@ -484,10 +591,14 @@ StepArgs step_args(const vne_server *s, const SrvTask &t, const GraphSet *set) {
     a.long_nseg = (const int32_t *)set->long_nseg.p;
     a.long_part = t.long_part;
     a.partials = t.partials;
+    a.stop_state = all_adaptive(t) ? t.d_state : nullptr;
+    a.stop_uid = t.mem[0].uid;
+    a.stop_count = t.n_mem;
     return a;
 }
 
-FinalizeArgs fin_args(const vne_server *s, const SrvTask &t, const GraphSet *set, int32_t *flags) {
+FinalizeArgs fin_args(const vne_server *s, const SrvTask &t, const GraphSet *set, int32_t *flags,
+                      int32_t *flags_hi) {
     FinalizeArgs f{};
     f.partials = t.partials;
     f.long_part = t.long_part;
@@ -509,18 +620,27 @@ FinalizeArgs fin_args(const vne_server *s, const SrvTask &t, const GraphSet *set
     f.k_eff = t.k_eff;
     f.flags = flags;
     f.n_graphs = 1;
+    f.stop_state = all_adaptive(t) ? t.d_state : nullptr;
+    f.stop_uid = t.mem[0].uid;
+    f.stop_count = t.n_mem;
+    f.flags_hi = t.pair() ? flags_hi : nullptr;
+    f.flag_split = t.pair() ? t.mem[1].c_off : t.m_pad;
     return f;
 }
 
-// Quadrature of a task after `steps` steps, its memory and mailbox entry
-// back, and the query's next stage when it was the query's last task.
-vne_status end_task(vne_server *s, SrvTask &t, SrvQuery &q, int steps) {
+// Quadrature of member i of a slot after `steps` steps, its mailbox entry
+// back, and the query's next stage when it was the query's last task.  The
+// slot's memory goes back when its last member has ended.
+vne_status end_member(vne_server *s, SrvTask &t, int i, SrvQuery &q, int steps) {
+    SrvMember &u = t.mem[i];
     // an adaptive task's own stop record (if the device made one) decides the
     // step count, whenever the host noticed it
-    SRV_HIP(s, launch_quadrature(t.alpha, t.beta, t.k_eff, t.norm2, t.k, steps, t.m, q.d_psi + t.col0, q.d_flags,
-                                 s->stream, s->fp64, t.adaptive ? t.d_state : nullptr, t.uid));
-    s->arena.release(t.off);
-    s->free_slots.push_back(t.slot);
+    const int64_t co = u.c_off;
+    SRV_HIP(s, launch_quadrature(t.alpha + co * t.k, t.beta + co * t.k, t.k_eff + co, t.norm2 + co, t.k, steps, u.m,
+                                 q.d_psi + u.col0, q.d_flags, s->stream, s->fp64,
+                                 u.adaptive ? t.d_state + i : nullptr, u.uid));
+    u.ended = true;
+    s->free_slots.push_back(u.slot);
     q.steps_used = std::max(q.steps_used, steps);
     q.tasks_open--;
     if (q.tasks_open > 0) return VNE_OK;
@@ -541,72 +661,91 @@ vne_status end_task(vne_server *s, SrvTask &t, SrvQuery &q, int steps) {
 // One Lanczos step of every active slot.
 vne_status tick(vne_server *s) {
     const int A = (int)s->active.size();
-    std::vector<SrvQuery *> qs(A);
-    for (int i = 0; i < A; ++i) qs[i] = query_of(s, s->active[i].ticket);
+    // queries of the members of each slot
+    std::vector<SrvQuery *> qs(2 * A, nullptr);
+    for (int i = 0; i < A; ++i)
+        for (int mi = 0; mi < s->active[i].n_mem; ++mi) qs[2 * i + mi] = query_of(s, s->active[i].mem[mi].ticket);
     // descriptors: StepArgs[A], FinalizeArgs[A], then per tile width the step
-    // and long-row maps, then the finalize map
+    // and long-row maps (and those of the pair slots), then the finalize map
     std::vector<StepArgs> sa(A);
     std::vector<FinalizeArgs> fa(A);
     std::map<int, std::vector<int4>> smap, lmap;
+    std::vector<int4> pmap, plmap;
     std::vector<int2> fmap;
+    int running = 0;
     for (int i = 0; i < A; ++i) {
         const SrvTask &t = s->active[i];
-        const GraphSet *set = qs[i]->set;
+        const GraphSet *set = qs[2 * i]->set;
         sa[i] = step_args(s, t, set);
-        fa[i] = fin_args(s, t, set, qs[i]->d_flags);
+        fa[i] = fin_args(s, t, set, qs[2 * i]->d_flags, t.pair() ? qs[2 * i + 1]->d_flags : nullptr);
+        for (int mi = 0; mi < t.n_mem; ++mi) running += t.mem[mi].ended ? 0 : 1;
         const int nt = t.m_pad / t.mt, nb = set->sched.n_blocks();
-        auto &sm = smap[t.mt];
-        for (int tile = 0; tile < nt; ++tile)
-            for (int b = 0; b < nb; ++b) sm.push_back(make_int4(i, b, tile, 0));
+        if (t.pair()) {
+            for (int b = 0; b < nb; ++b) pmap.push_back(make_int4(i, b, 0, 0));
+        } else {
+            auto &sm = smap[t.mt];
+            for (int tile = 0; tile < nt; ++tile)
+                for (int b = 0; b < nb; ++b) sm.push_back(make_int4(i, b, tile, 0));
+        }
         if (set->sched.n_long > 0) {
             const int per = long_rows_per_group(t.mt, s->fp64);
-            auto &lm = lmap[t.mt];
+            auto &lm = t.pair() ? plmap : lmap[t.mt];
             for (int tile = 0; tile < nt; ++tile)
                 for (int gi = 0; gi < (set->sched.n_long + per - 1) / per; ++gi) lm.push_back(make_int4(i, gi, tile, 0));
         }
         for (int ch = 0; ch < (t.m_pad + kFinalizeCols - 1) / kFinalizeCols; ++ch) fmap.push_back(make_int2(i, ch));
     }
-    // a-posteriori checks (Theorem 4.8) of adaptive tasks after this step:
+    // a-posteriori checks (Theorem 4.8) of adaptive members after this step:
     // from step 3 on, every other step
     std::vector<BoundArgs> ba;
     std::vector<StopArgs> sta;
     std::vector<int2> bmap;
-    std::vector<int> checked;
+    std::vector<int2> checked;       // {slot, member}
     for (int i = 0; i < A; ++i) {
         const SrvTask &t = s->active[i];
         const int j = t.j + 1;
-        if (!t.adaptive || j < 3 || j % 2 == 0 || j >= t.k) continue;
-        const Graph *g = qs[i]->g;
-        BoundArgs b{};
-        b.alpha = t.alpha;
-        b.beta = t.beta;
-        b.k_eff = t.k_eff;
-        b.norm2 = t.norm2;
-        b.k = t.k;
-        b.m = t.m;
-        b.steps = j;
-        b.lam_hi = g->lambda_ub;
-        b.lam_lo = g->lambda_ub * kLamLoFraction;
-        b.n_grid = kBoundGrid;
-        b.lo = t.b_lo;
-        b.hi = t.b_hi;
-        b.flags = qs[i]->d_flags;
-        for (int grp = 0; grp < (t.m + 3) / 4; ++grp) bmap.push_back(make_int2((int)ba.size(), grp));
-        ba.push_back(b);
-        StopArgs sc{};
-        sc.hi = t.b_hi;
-        sc.m = t.m;
-        sc.tol = t.tol;
-        sc.step = j;
-        sc.uid = t.uid;
-        sc.state = t.d_state;
-        sta.push_back(sc);
-        checked.push_back(i);
+        if (j < 3 || j % 2 == 0 || j >= t.k) continue;
+        for (int mi = 0; mi < t.n_mem; ++mi) {
+            const SrvMember &u = t.mem[mi];
+            if (!u.adaptive || u.ended) continue;
+            const SrvQuery *q = qs[2 * i + mi];
+            const Graph *g = q->g;
+            const int64_t co = u.c_off;
+            BoundArgs b{};
+            b.alpha = t.alpha + co * t.k;
+            b.beta = t.beta + co * t.k;
+            b.k_eff = t.k_eff + co;
+            b.norm2 = t.norm2 + co;
+            b.k = t.k;
+            b.m = u.m;
+            b.steps = j;
+            b.lam_hi = g->lambda_ub;
+            b.lam_lo = g->lambda_ub * kLamLoFraction;
+            b.n_grid = kBoundGrid;
+            b.lo = t.b_lo + co;
+            b.hi = t.b_hi + co;
+            b.flags = q->d_flags;
+            b.stop_state = t.d_state + mi;
+            b.stop_uid = u.uid;
+            b.stop_count = 1;
+            for (int grp = 0; grp < (u.m + 3) / 4; ++grp) bmap.push_back(make_int2((int)ba.size(), grp));
+            ba.push_back(b);
+            StopArgs sc{};
+            sc.hi = t.b_hi + co;
+            sc.m = u.m;
+            sc.tol = u.tol;
+            sc.step = j;
+            sc.uid = u.uid;
+            sc.state = t.d_state + mi;
+            sta.push_back(sc);
+            checked.push_back(make_int2(i, mi));
+        }
     }
     size_t bytes = rnd(sizeof(StepArgs) * A) + rnd(sizeof(FinalizeArgs) * A) + rnd(sizeof(int2) * fmap.size());
     bytes += rnd(sizeof(BoundArgs) * ba.size()) + rnd(sizeof(int2) * bmap.size()) + rnd(sizeof(StopArgs) * sta.size());
     for (auto &kv : smap) bytes += rnd(sizeof(int4) * kv.second.size());
     for (auto &kv : lmap) bytes += rnd(sizeof(int4) * kv.second.size());
+    bytes += rnd(sizeof(int4) * pmap.size()) + rnd(sizeof(int4) * plmap.size());
     // staging ring: wait until the copy that last used this slot has run
     const int r = s->ring_pos;
     s->ring_pos = (r + 1) % vne_server::kRing;
@@ -641,6 +780,8 @@ vne_status tick(vne_server *s) {
     std::map<int, const int4 *> d_sm, d_lm;
     for (auto &kv : smap) d_sm[kv.first] = (const int4 *)put(kv.second.data(), sizeof(int4) * kv.second.size());
     for (auto &kv : lmap) d_lm[kv.first] = (const int4 *)put(kv.second.data(), sizeof(int4) * kv.second.size());
+    const int4 *d_pm = (const int4 *)put(pmap.data(), sizeof(int4) * pmap.size());
+    const int4 *d_plm = (const int4 *)put(plmap.data(), sizeof(int4) * plmap.size());
     const BoundArgs *d_ba = (const BoundArgs *)put(ba.data(), sizeof(BoundArgs) * ba.size());
     const int2 *d_bm = (const int2 *)put(bmap.data(), sizeof(int2) * bmap.size());
     const StopArgs *d_st = (const StopArgs *)put(sta.data(), sizeof(StopArgs) * sta.size());
@@ -654,35 +795,45 @@ vne_status tick(vne_server *s) {
         SRV_HIP(s, launch_step_slots(d_sa, d_sm[mt], (int32_t)kv.second.size(), n_long ? d_lm[mt] : nullptr, n_long,
                                      mt, s->fp64, s->stream));
     }
+    if (!pmap.empty())
+        SRV_HIP(s, launch_step_pairs(d_sa, d_pm, (int32_t)pmap.size(), plmap.empty() ? nullptr : d_plm,
+                                     (int32_t)plmap.size(), s->stream));
     SRV_HIP(s, launch_finalize_slots(d_fa, d_fm, (int32_t)fmap.size(), s->stream));
     if (!sta.empty()) {
         SRV_HIP(s, launch_error_bound(d_ba, d_bm, (int32_t)bmap.size(), s->stream));
         SRV_HIP(s, launch_stop_check(d_st, (int32_t)sta.size(), s->stream));
-        for (int i : checked) {
-            const SrvTask &t = s->active[i];
-            SRV_HIP(s, hipMemcpyAsync(s->mailbox + t.slot, t.d_state, sizeof(int2), hipMemcpyDeviceToHost,
-                                      s->stream));
+        for (const int2 &c : checked) {
+            const SrvTask &t = s->active[c.x];
+            SRV_HIP(s, hipMemcpyAsync(s->mailbox + t.mem[c.y].slot, t.d_state + c.y, sizeof(int2),
+                                      hipMemcpyDeviceToHost, s->stream));
         }
     }
     s->ticks++;
-    s->occupancy_sum += A;
-    // tasks at their step cap, and adaptive tasks whose recorded stop step
+    s->occupancy_sum += running;
+    // members at the step cap, and adaptive members whose recorded stop step
     // has reached the host, end: quadrature (eq. (4.2)) into the query's psi
     std::vector<SrvTask> keep;
     for (int i = 0; i < A; ++i) {
         SrvTask &t = s->active[i];
         t.j++;
-        int use = t.j >= t.k ? t.k : 0;
-        if (!use && t.adaptive) {
-            const volatile int2 *mb = s->mailbox + t.slot;
-            const int u = mb->x, st = mb->y;
-            if (u == t.uid && st > 0) use = st;
+        bool open = false;
+        for (int mi = 0; mi < t.n_mem; ++mi) {
+            SrvMember &u = t.mem[mi];
+            if (u.ended) continue;
+            int use = t.j >= t.k ? t.k : 0;
+            if (!use && u.adaptive) {
+                const volatile int2 *mb = s->mailbox + u.slot;
+                const int id = mb->x, st = mb->y;
+                if (id == u.uid && st > 0) use = st;
+            }
+            if (!use) {
+                open = true;
+                continue;
+            }
+            VNE_TRY(end_member(s, t, mi, *qs[2 * i + mi], use));
         }
-        if (!use) {
-            keep.push_back(t);
-            continue;
-        }
-        VNE_TRY(end_task(s, t, *qs[i], use));
+        if (open) keep.push_back(t);
+        else s->arena.release(t.off);
     }
     s->active.swap(keep);
     return VNE_OK;
@@ -723,11 +874,15 @@ void publish(vne_server *s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->snap.ticks = s->ticks;
     s->snap.tasks = s->tasks_admitted;
+    s->snap.pair_slots = s->pair_slots;
     s->snap.slot_occupancy = s->ticks ? s->occupancy_sum / (double)s->ticks : 0.0;
     s->snap.arena_bytes = s->arena.size();
     s->snap.arena_in_use = s->arena.in_use();
     s->snap.arena_peak = s->arena_peak;
-    s->snap.active = (int32_t)s->active.size();
+    int running = 0;
+    for (const SrvTask &t : s->active)
+        for (int i = 0; i < t.n_mem; ++i) running += t.mem[i].ended ? 0 : 1;
+    s->snap.active = running;
     s->snap.pending = (int32_t)s->pending.size();
 }
 

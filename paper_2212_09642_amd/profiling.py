@@ -118,12 +118,14 @@ def cmd_serve(args):
            "Workload `%s`: %d graphs, relative accuracy %g per query, %d queries per rate."
            % (c["workload"], c["graphs"], c["rel_eps"], c["queries_per_rate"]), "",
            "| offered /s | completed /s | p50 ms | p99 ms | algorithmic GB/s | mean probes | mean steps | "
-           "sampling target met | running slots per tick |",
-           "|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+           "sampling target met | running tasks per tick | tasks in pair slots |",
+           "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for r in d["rates"]:
-        out.append("| %g | %.1f | %.1f | %.1f | %.0f | %.0f | %.1f | %d/%d | %.2f |" % (
+        pairs = "%d/%d" % (r["tasks_in_pair_slots"], r["tasks"]) if "tasks" in r else "-"
+        out.append("| %g | %.1f | %.1f | %.1f | %.0f | %.0f | %.1f | %d/%d | %.2f | %s |" % (
             r["offered_per_s"], r["completed_per_s"], r["p50_ms"], r["p99_ms"], r["algorithmic_GBps"],
-            r["mean_probes"], r["mean_steps"], r["sampling_target_met"], r["queries"], r["slot_occupancy"]))
+            r["mean_probes"], r["mean_steps"], r["sampling_target_met"], r["queries"], r["slot_occupancy"],
+            pairs))
     out += ["", "Saturated throughput: %.1f queries/s." % d["value"]]
     with open(args.out, "w") as fh:
         fh.write("\n".join(out) + "\n")

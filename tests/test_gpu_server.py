@@ -106,6 +106,56 @@ def test_server_adaptive_same_bits_alone_and_in_a_mix(ctx, pool):
     assert alone["estimate"] == mixed["estimate"]
 
 
+def test_server_pair_slots_same_bits_as_alone(ctx, pool):
+    """16-column tasks of one graph with the same step cap share pair slots;
+    each gives the bits it gives alone, and matches the oracle."""
+    _say("case server: pair slots of 16-column tasks")
+    gid, ref = pool[5]                       # ER n = 20000
+    gid2, _ = pool[1]
+    work = [(gid, 16, 30, s) for s in range(1, 7)] + [(gid, 16, 25, 7), (gid2, 16, 30, 8), (gid, 40, 30, 9)]
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+        alone = [_run_one(srv, *w) for w in work]
+        assert srv.stats()["pair_slots"] == 0
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+        ts = [srv.submit(g, m=m, k=k, seed=sd) for g, m, k, sd in work]
+        mixed = [srv.poll(t, want_quad=True) for t in ts]
+        info = srv.stats()
+    _say("  pair slots %d of %d tasks" % (info["pair_slots"], info["tasks"]))
+    assert info["pair_slots"] >= 3
+    for a, b in zip(alone, mixed):
+        assert a["status"] == 0 and b["status"] == 0
+        assert np.array_equal(a["quad"], b["quad"])
+        assert a["estimate"] == b["estimate"]
+    B = oracle.rademacher_block(3, ref.node_ids, np.arange(16))
+    want = oracle.quadforms(ref.scipy(), B, 30, oracle.breakdown_tau(False))
+    sens = _order_sensitivity(ref.scipy(), B, 30, False)
+    rel = _rel(mixed[2]["quad"], want["psi"])
+    assert np.all(rel < max(TOL[False], 20 * float(np.max(sens)))), rel.max()
+
+
+def test_server_adaptive_pairs_same_bits_as_alone(ctx, pool):
+    """rel_eps queries on one graph: their 16-column pilots share pair slots,
+    each member stops on its own record, and every query gives the bits it
+    gives alone."""
+    _say("case server: adaptive queries in pair slots")
+    gid, _ = pool[5]
+    seeds = [21, 22, 23, 24, 25]
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+        alone = [srv.poll(srv.submit(gid, rel_eps=1e-3, seed=sd), want_quad=True) for sd in seeds]
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+        ts = [srv.submit(gid, rel_eps=1e-3, seed=sd) for sd in seeds]
+        mixed = [srv.poll(t, want_quad=True) for t in ts]
+        info = srv.stats()
+    _say("  pair slots %d of %d tasks; steps %s" % (info["pair_slots"], info["tasks"],
+                                                     [r["steps"] for r in alone]))
+    assert info["pair_slots"] >= 2
+    for a, b in zip(alone, mixed):
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["probes"] == b["probes"]
+        assert np.array_equal(a["quad"], b["quad"])
+        assert a["estimate"] == b["estimate"]
+
+
 def test_server_admission_under_small_arena(ctx, pool):
     _say("case server: admission with an arena for about two tasks")
     gid, ref = pool[5]                       # n = 20000
