@@ -103,7 +103,7 @@ def cmd_traffic(args):
          "copy_calibration": {"bytes_each_way": args.copy_bytes, "fetch_kib": copy_fetch_kib,
                               "write_kib": copy_write_kib, "fetch_scale": f_scale, "write_scale": w_scale},
          "hbm_bytes_per_launch": per_step, "kernel_source_hash": bench.kernel_source_hash(),
-         "command": args.cmd}
+         "skip_steps": args.skip_steps, "max_steps": args.max_steps, "command": args.cmd}
     with open(args.out, "w") as fh:
         json.dump(d, fh, indent=1)
     print(json.dumps(d, indent=1))
