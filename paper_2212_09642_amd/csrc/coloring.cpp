@@ -1,21 +1,25 @@
 // Greedy distance-d colouring (Section 3.1, Algorithm 1) on the host.
 //
-// The paper builds the distance-d neighbourhoods from the pattern of A^d;
-// here each node's neighbourhood is found by a breadth-first search cut at
-// depth d, which visits the same node set (O(n Delta^d) work, as the paper
-// notes for the graph-traversal route).  Visiting order: descending degree
-// (number of off-diagonal entries), ties by increasing row index.  Each node
-// takes the smallest colour, counting from 0, that no already coloured node
-// of its neighbourhood carries.
+// Visiting order: descending degree (number of off-diagonal entries), ties
+// by increasing row index.  Each node takes the smallest colour, counting
+// from 0, that no already coloured node within distance d carries (distance
+// in the graph of the off-diagonal pattern; the paper forms the same
+// neighbourhoods from the pattern of A^d).
 //
-// The neighbourhoods do not depend on the colours, only the first-fit scan
-// does.  Nodes are therefore taken in chunks of the visiting order: worker
-// threads list, for every node of the next chunk, the neighbours that come
-// earlier in the order (the only ones coloured when the node's turn comes),
-// while the calling thread runs the first-fit scan over the current chunk in
-// order.  The result is the sequential algorithm's colouring exactly.  Several
-// distances share one search to the largest of them: every listed neighbour
-// carries its distance, and each distance's scan skips the farther ones.
+// The colours within distance d of node i are the union, over the nodes y
+// within distance a of i, of the colours within distance b of y, for any
+// a + b = d: a shortest path from i to a node z at distance t <= d passes
+// through a node y at distance min(a, t) from i, which is within distance
+// t - min(a, t) <= b of z.  Each distance therefore keeps, per node y, a
+// bitset of the colours found within distance b of y among the nodes
+// coloured so far (b = floor(d / 2), a = d - b).  Node i takes the first
+// colour missing from the union over its distance-a ball, then sets that
+// colour's bit in the sets of its distance-b ball.  The balls (to depth
+// ceil(d_max / 2), with each node's distance) do not depend on the colours:
+// worker threads list them for the next chunk of the visiting order while
+// the calling thread runs the first-fit scans of the current chunk, one
+// thread per distance.  The result is the sequential algorithm's colouring
+// exactly, at the cost of searches to half the depth.
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
@@ -31,13 +35,14 @@ using namespace vne;
 
 namespace {
 
-// Neighbour lists of one chunk: node t0 + j lists its earlier neighbours in
-// items[begin[j] .. begin[j + 1]) (per worker, nodes interleaved by worker).
+// Balls of one chunk: node t0 + j lists its ball in
+// items[begin[j] .. begin[j + 1]) (per worker, nodes interleaved by worker),
+// by nondecreasing distance, the node itself first.
 struct ChunkLists {
     int64_t t0 = 0, t1 = 0;
     int nw = 1;
     std::vector<std::vector<int32_t>> items;     // per worker
-    std::vector<std::vector<uint8_t>> depth;     // per worker: distance of each listed neighbour
+    std::vector<std::vector<uint8_t>> depth;     // per worker: distance of each listed node
     std::vector<std::vector<int64_t>> begin;     // per worker, per owned node + 1
 };
 
@@ -45,28 +50,28 @@ struct ChunkLists {
 // change size on every push)
 class alignas(128) Searcher {
 public:
-    Searcher(int64_t n, const int32_t *rp, const int32_t *ci, int32_t d, const std::vector<int32_t> &pos)
-        : rp_(rp), ci_(ci), d_(d), pos_(pos), seen_(n, -1) {}
+    Searcher(int64_t n, const int32_t *rp, const int32_t *ci, int32_t depth)
+        : rp_(rp), ci_(ci), d_(depth), seen_(n, -1) {}
 
-    // earlier neighbours (position < pos of i) of node i within distance d,
-    // with their distance
+    // the nodes within distance d_ of node i, breadth first, with their distance
     void list(int32_t i, int32_t stamp, std::vector<int32_t> *out, std::vector<uint8_t> *dist) {
         frontier_.clear();
         frontier_.push_back(i);
         seen_[i] = stamp;
-        const int32_t pi = pos_[i];
+        out->push_back(i);
+        dist->push_back(0);
         for (int32_t depth = 0; depth < d_ && !frontier_.empty(); ++depth) {
             next_.clear();
+            const bool last = depth + 1 == d_;     // the last level is not expanded
+            const uint8_t dd = (uint8_t)(depth + 1);
             for (int32_t x : frontier_) {
                 for (int32_t p = rp_[x]; p < rp_[x + 1]; ++p) {
                     const int32_t y = ci_[p];
                     if (seen_[y] == stamp) continue;
                     seen_[y] = stamp;
-                    next_.push_back(y);
-                    if (pos_[y] < pi) {
-                        out->push_back(y);
-                        dist->push_back((uint8_t)(depth + 1));
-                    }
+                    if (!last) next_.push_back(y);
+                    out->push_back(y);
+                    dist->push_back(dd);
                 }
             }
             frontier_.swap(next_);
@@ -76,7 +81,6 @@ public:
 private:
     const int32_t *rp_, *ci_;
     int32_t d_;
-    const std::vector<int32_t> &pos_;
     std::vector<int32_t> seen_;
     std::vector<int32_t> frontier_, next_;
 };
@@ -115,34 +119,84 @@ void build_lists(ChunkLists *cl, std::vector<std::unique_ptr<Searcher>> &srch, c
 
 }  // namespace
 
-// First-fit state of one distance.
+// First-fit state of one distance d: per node, the colours within distance
+// b of it among the coloured nodes, as W 64-bit words.
 struct FirstFit {
-    int32_t d = 1;
+    int32_t d = 1, a = 1, b = 0;
+    int64_t n = 0;
+    int W = 1;
+    std::vector<uint64_t> bits;                  // [n][W]
     std::vector<int32_t> color;
-    std::vector<int64_t> banned;                 // stamp per colour
     int32_t ncol = 0;
 
-    void scan(const ChunkLists &cl, const std::vector<int32_t> &order) {
+    void init(int64_t nn, int32_t dist) {
+        n = nn;
+        d = dist;
+        b = d / 2;
+        a = d - b;
+        W = 1;
+        bits.assign((size_t)n * W, 0);
+        color.assign((size_t)n, -1);
+        ncol = 0;
+    }
+
+    void widen() {
+        std::vector<uint64_t> nb((size_t)n * (W + 1), 0);
+        for (int64_t y = 0; y < n; ++y)
+            for (int w = 0; w < W; ++w) nb[(size_t)y * (W + 1) + w] = bits[(size_t)y * W + w];
+        bits.swap(nb);
+        W++;
+    }
+
+    // WW: the word count W as a compile-time constant (0: any)
+    template <int WW>
+    void scan_w(const ChunkLists &cl, const std::vector<int32_t> &order, int64_t *t_next) {
         const int nw = cl.nw;
-        const bool all = d >= 255;
-        for (int64_t t = cl.t0; t < cl.t1; ++t) {
+        const int Wn = WW > 0 ? WW : W;
+        std::vector<uint64_t> forb(Wn);
+        for (int64_t t = *t_next; t < cl.t1; ++t) {
             const int64_t r = t - cl.t0;
-            const int w = (int)(r % nw);
+            const int wk = (int)(r % nw);
             const int64_t slot = r / nw;
-            const auto &it = cl.items[w];
-            const auto &dp = cl.depth[w];
-            // the search lists a node's neighbours by increasing distance
-            for (int64_t q = cl.begin[w][slot]; q < cl.begin[w][slot + 1]; ++q) {
-                if (!all && dp[q] > d) break;
-                banned[color[it[q]]] = t;
+            const auto &it = cl.items[wk];
+            const auto &dp = cl.depth[wk];
+            const int64_t q0 = cl.begin[wk][slot], q1 = cl.begin[wk][slot + 1];
+            // union over the distance-a ball (listed by distance)
+            for (int w = 0; w < Wn; ++w) forb[w] = 0;
+            for (int64_t q = q0; q < q1 && dp[q] <= a; ++q) {
+                const uint64_t *src = &bits[(size_t)it[q] * Wn];
+                for (int w = 0; w < Wn; ++w) forb[w] |= src[w];
             }
-            int32_t c = 0;
-            while (c < ncol && banned[c] == t) ++c;
-            if (c == ncol) {
-                ncol++;
-                banned.push_back(-1);
+            int w = 0;
+            while (w < Wn && forb[w] == ~0ull) ++w;
+            const int32_t c = w * 64 + (w < Wn ? __builtin_ctzll(~forb[w]) : 0);
+            if (c >= 64 * Wn) {
+                // every colour of the W words is taken: one more word, and
+                // the rest of the chunk with the new width
+                widen();
+                *t_next = t;
+                return;
             }
-            color[order[t]] = c;
+            const int32_t i = order[t];
+            color[i] = c;
+            ncol = std::max(ncol, c + 1);
+            // mark c in the sets of the distance-b ball
+            const uint64_t m = 1ull << (c & 63);
+            for (int64_t q = q0; q < q1 && dp[q] <= b; ++q) bits[(size_t)it[q] * Wn + w] |= m;
+        }
+        *t_next = cl.t1;
+    }
+
+    void scan(const ChunkLists &cl, const std::vector<int32_t> &order) {
+        int64_t t = cl.t0;
+        while (t < cl.t1) {
+            switch (W) {
+                case 1: scan_w<1>(cl, order, &t); break;
+                case 2: scan_w<2>(cl, order, &t); break;
+                case 3: scan_w<3>(cl, order, &t); break;
+                case 4: scan_w<4>(cl, order, &t); break;
+                default: scan_w<0>(cl, order, &t); break;
+            }
         }
     }
 };
@@ -159,23 +213,18 @@ void vne::greedy_color_multi(int64_t n, const int32_t *rp, const int32_t *ci, co
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
-    std::vector<int32_t> pos(n);
-    for (int64_t t = 0; t < n; ++t) pos[order[t]] = (int32_t)t;
-    int32_t dmax = 1;
-    for (int q = 0; q < nd; ++q) dmax = std::max(dmax, ds[q]);
+    int32_t depth = 1;                         // the deepest ball any distance needs
+    for (int q = 0; q < nd; ++q) depth = std::max(depth, ds[q] - ds[q] / 2);
 
     int nw = (int)std::thread::hardware_concurrency();
     if (const char *e = std::getenv("VNE_COLOR_THREADS")) nw = std::atoi(e);
     nw = std::max(1, std::min(nw, 16));
     if (n < 4096) nw = 1;
     std::vector<std::unique_ptr<Searcher>> srch;
-    for (int w = 0; w < nw; ++w) srch.emplace_back(new Searcher(n, rp, ci, dmax, pos));
+    for (int w = 0; w < nw; ++w) srch.emplace_back(new Searcher(n, rp, ci, depth));
 
     std::vector<FirstFit> ff(nd);
-    for (int q = 0; q < nd; ++q) {
-        ff[q].d = ds[q];
-        ff[q].color.assign(n, -1);
-    }
+    for (int q = 0; q < nd; ++q) ff[q].init(n, ds[q]);
     // chunk sizes: aim at about 2^24 listed neighbours per chunk
     const int64_t kBudget = int64_t(1) << 24;
     int64_t chunk = std::min<int64_t>(n, 1024);

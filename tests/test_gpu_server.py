@@ -156,6 +156,37 @@ def test_server_adaptive_pairs_same_bits_as_alone(ctx, pool):
         assert a["estimate"] == b["estimate"]
 
 
+def test_server_fp64_matches_oracle_and_mix(ctx):
+    """An FP64 server (FP64 vectors; slot kernels with two columns per lane):
+    explicit queries of several widths against the oracle at the FP64 bar,
+    and adaptive queries give the same bits alone and together."""
+    _say("case server: FP64 mode")
+    graphs = [_reg(ctx, *synth.erdos_renyi(2500, 7.0, 61), fp64=True),
+              _reg(ctx, *synth.watts_strogatz(3000, 8, 0.1, 62), fp64=True)]
+    mode = vne.MODE_DESING | vne.MODE_F64
+    with vne.Server(ctx, mode, arena_bytes=1 << 30) as srv:
+        work = [(0, 8, 20, 1), (1, 16, 25, 2), (0, 40, 30, 3), (1, 130, 18, 4)]
+        ts = [srv.submit(graphs[g][0], m=m, k=k, seed=sd) for g, m, k, sd in work]
+        got = [srv.poll(t, want_quad=True) for t in ts]
+        for (g, m, k, sd), r in zip(work, got):
+            ref = graphs[g][1]
+            assert r["status"] == 0, r["message"]
+            B = oracle.rademacher_block(sd, ref.node_ids, np.arange(m))
+            want = oracle.quadforms(ref.scipy(), B, k, oracle.breakdown_tau(True))
+            sens = _order_sensitivity(ref.scipy(), B, k, True)
+            rel = _rel(r["quad"], want["psi"])
+            _say("  n=%d m=%d k=%d max rel err %.1e (sens %.1e)" % (ref.n, m, k, rel.max(), sens.max()))
+            assert np.all(rel < max(TOL[True], 20 * float(np.max(sens)))), rel.max()
+        alone = [srv.poll(srv.submit(graphs[i % 2][0], rel_eps=1e-3, seed=70 + i), want_quad=True)
+                 for i in range(4)]
+        ts = [srv.submit(graphs[i % 2][0], rel_eps=1e-3, seed=70 + i) for i in range(4)]
+        mixed = [srv.poll(t, want_quad=True) for t in ts]
+        assert srv.stats()["pair_slots"] == 0        # pairs are FP32 only
+    for a, b in zip(alone, mixed):
+        assert a["status"] == 0 and b["status"] == 0
+        assert np.array_equal(a["quad"], b["quad"]) and a["estimate"] == b["estimate"]
+
+
 def test_server_admission_under_small_arena(ctx, pool):
     _say("case server: admission with an arena for about two tasks")
     gid, ref = pool[5]                       # n = 20000
