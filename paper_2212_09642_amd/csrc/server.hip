@@ -1,15 +1,17 @@
 // Serving loop: entropy queries on registered graphs, admitted by an HBM
 // budget, run with continuous batching.
 //
-// A query is split into slot tasks of at most max_cols probe columns.  Every
-// admitted task is a slot: its matrix stays the registered graph's, its
-// vectors and Lanczos state live in the server's arena.  One tick advances
-// every active slot by one Lanczos step in a few launches (normalize, SpMM +
-// recurrence, long rows, finalize) whatever graphs the slots belong to; a
-// task that reaches its step count gets its quadrature and leaves, and
-// waiting tasks are admitted between ticks as slots and arena space free up.
-// A slot's arithmetic depends only on its own graph, probes and step count,
-// so a query gives the same bits alone and in any mix.
+// A query is split into slot tasks of at most max_cols probe columns.  An
+// admitted task gets a slot (two 16-column FP32 tasks of one graph that wait
+// together may share a pair slot): its matrix stays the registered graph's,
+// its vectors and Lanczos state live in the server's arena.  One tick
+// advances every active slot by one Lanczos step in a few launches
+// (normalize, SpMM + recurrence, long rows, finalize) whatever graphs the
+// slots belong to; a task that reaches its step count gets its quadrature
+// and leaves, and waiting tasks are admitted between ticks as mailbox
+// entries and arena space free up.  A task's arithmetic depends only on its
+// own graph, probes and step count (in a pair slot too), so a query gives
+// the same bits alone and in any mix.
 //
 // With rel_eps > 0 a query first runs a pilot of pilot_probes columns; the
 // step cap comes from the a-priori bound of Proposition 4.4 with Remark 2.3
