@@ -858,15 +858,21 @@ __global__ void __launch_bounds__(256) k_finalize_graphs(FinalizeArgs a) {
     if (t >= (int64_t)a.n_graphs * a.m_pad) return;
     const int g = (int)(t / a.m_pad), c = (int)(t % a.m_pad);
     double svw = 0.0, sww = 0.0, svv = 0.0;
-    // batches of 8 partials loaded before they are added (same order)
+    // the graph's block partials, then its long-row partials, in order; in
+    // batches of UB whose loads are all issued before the adds (same order)
+    const int b0 = a.graph_block_begin[g], nb = a.graph_block_begin[g + 1] - b0;
+    const int L0 = a.graph_long_begin[g], total = nb + (a.graph_long_begin[g + 1] - L0);
+    auto src = [&](int i) -> const double * {
+        return i < nb ? a.partials + (int64_t)(b0 + i) * 3 * a.m_pad + c
+                      : a.long_part + (int64_t)(L0 + i - nb) * 3 * a.m_pad + c;
+    };
     constexpr int UB = 8;
-    const int b0 = a.graph_block_begin[g], b1 = a.graph_block_begin[g + 1];
-    int bb = b0;
-    for (; bb + UB <= b1; bb += UB) {
+    int i = 0;
+    for (; i + UB <= total; i += UB) {
         double v[UB][3];
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
-            const double *p = a.partials + (int64_t)(bb + u) * 3 * a.m_pad + c;
+            const double *p = src(i + u);
             v[u][0] = p[0];
             v[u][1] = p[a.m_pad];
             v[u][2] = p[2 * a.m_pad];
@@ -878,14 +884,8 @@ __global__ void __launch_bounds__(256) k_finalize_graphs(FinalizeArgs a) {
             svv += v[u][2];
         }
     }
-    for (; bb < b1; ++bb) {
-        const double *p = a.partials + (int64_t)bb * 3 * a.m_pad + c;
-        svw += p[0];
-        sww += p[a.m_pad];
-        svv += p[2 * a.m_pad];
-    }
-    for (int L = a.graph_long_begin[g]; L < a.graph_long_begin[g + 1]; ++L) {
-        const double *p = a.long_part + (int64_t)L * 3 * a.m_pad + c;
+    for (; i < total; ++i) {
+        const double *p = src(i);
         svw += p[0];
         sww += p[a.m_pad];
         svv += p[2 * a.m_pad];
