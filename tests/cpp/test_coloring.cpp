@@ -1,8 +1,10 @@
 // Host check of the threaded greedy distance-d colouring (Algorithm 1): on
 // random graphs large enough for the chunked, threaded path, the colouring
 // equals a plain sequential first-fit with a breadth-first search per node,
-// for 1 and several worker threads and for several distances from one shared
-// search; and no two nodes within distance d share a colour.
+// for 1 and several worker threads, for several distances from one shared
+// search, and with bitset memory caps that send some or all distances to
+// the earlier-neighbour route; and no two nodes within distance d share a
+// colour.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -133,14 +135,18 @@ int main() {
                 return 1;
             }
         }
+        // the bitset route alone, then caps that send the distances whose
+        // colours outgrow them (some or all) to the earlier-neighbour route
+        for (const char *cap : {"268435456", "200000", "8"})
         for (const char *th : {"1", "3", "8"}) {
+            setenv("VNE_COLOR_BITSET_BYTES", cap, 1);
             setenv("VNE_COLOR_THREADS", th, 1);
             for (int q = 0; q < 3; ++q) {
                 std::vector<int32_t> col(c.n, -7);
                 const int s = vne::greedy_color(c.n, c.rp.data(), c.ci.data(), ds[q], col.data());
                 if (col != ref[q] || s != *std::max_element(col.begin(), col.end()) + 1) {
-                    std::printf("FAIL: graph %zu d %d threads %s differs from the sequential reference\n", gi,
-                                ds[q], th);
+                    std::printf("FAIL: graph %zu d %d threads %s cap %s differs from the sequential reference\n",
+                                gi, ds[q], th, cap);
                     return 1;
                 }
             }
@@ -150,7 +156,7 @@ int main() {
             vne::greedy_color_multi(c.n, c.rp.data(), c.ci.data(), ds, 3, outs, counts);
             for (int q = 0; q < 3; ++q)
                 if (multi[q] != ref[q]) {
-                    std::printf("FAIL: graph %zu shared search d %d threads %s\n", gi, ds[q], th);
+                    std::printf("FAIL: graph %zu shared search d %d threads %s cap %s\n", gi, ds[q], th, cap);
                     return 1;
                 }
         }
