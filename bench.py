@@ -282,7 +282,7 @@ def run_serve(args):
           file=sys.stderr, flush=True)
     eps = 1e-3
     srv = vne.Server(ctx, vne.MODE_DESING, arena_bytes=int(args.arena_gb * (1 << 30)), max_slots=args.max_slots,
-                     max_probes=4096)
+                     max_cols=args.max_cols, max_probes=4096)
     # untimed: one query per graph (device arrays of every graph, first launches)
     for gid, *_ in pool:
         srv.poll(srv.submit(gid, rel_eps=eps, seed=1))
@@ -460,6 +460,7 @@ def main():
     ap.add_argument("--pool", type=int, default=24, help="serve workload: graphs in the pool")
     ap.add_argument("--arena-gb", type=float, default=96.0, help="serve workload: server arena (GiB)")
     ap.add_argument("--max-slots", type=int, default=64, help="serve workload: tasks running at once")
+    ap.add_argument("--max-cols", type=int, default=256, help="serve workload: probe columns per task")
     ap.add_argument("--graph", default="ws", help="probing-eps workload: ws (small-world) or ring (lattice)")
     ap.add_argument("--rel-eps", type=float, default=1e-3, help="probing-eps workload: relative target")
     ap.add_argument("--copy-calibration", action="store_true",
