@@ -112,7 +112,9 @@ def test_server_pair_slots_same_bits_as_alone(ctx, pool):
     _say("case server: pair slots of 16-column tasks")
     gid, ref = pool[5]                       # ER n = 20000
     gid2, _ = pool[1]
-    work = [(gid, 16, 30, s) for s in range(1, 7)] + [(gid, 16, 25, 7), (gid2, 16, 30, 8), (gid, 40, 30, 9)]
+    # ER (no long rows) and BA (hub rows split into segments) pairs
+    work = ([(gid, 16, 30, s) for s in range(1, 7)] + [(gid, 16, 25, 7), (gid2, 16, 30, 8), (gid, 40, 30, 9)]
+            + [(gid2, 16, 30, 10), (gid2, 16, 30, 11)])
     with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
         alone = [_run_one(srv, *w) for w in work]
         assert srv.stats()["pair_slots"] == 0
@@ -121,7 +123,7 @@ def test_server_pair_slots_same_bits_as_alone(ctx, pool):
         mixed = [srv.poll(t, want_quad=True) for t in ts]
         info = srv.stats()
     _say("  pair slots %d of %d tasks" % (info["pair_slots"], info["tasks"]))
-    assert info["pair_slots"] >= 3
+    assert info["pair_slots"] >= 3          # submissions race the worker: most pair up
     for a, b in zip(alone, mixed):
         assert a["status"] == 0 and b["status"] == 0
         assert np.array_equal(a["quad"], b["quad"])
