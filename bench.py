@@ -465,6 +465,8 @@ def main():
     ap.add_argument("--rel-eps", type=float, default=1e-3, help="probing-eps workload: relative target")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 2 GiB device copy (for counter calibration)")
+    ap.add_argument("--copy-rate", action="store_true",
+                    help="time a plain 2 GiB device copy (read + write GB/s)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -482,6 +484,23 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": x.numel() * 4, "copies": 3}))
+        return
+    if args.copy_rate:
+        # the read + write rate a plain 2 GiB device copy reaches (context for
+        # the step kernels' measured HBM traffic)
+        x = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps({"copy_bytes_each_way": x.numel() * 4, "copy_ms": round(ms, 4),
+                          "copy_read_write_GBps": round(2 * x.numel() * 4 / (ms * 1e-3) / 1e9, 1)}))
         return
 
     if args.workload == "batch":
