@@ -233,6 +233,8 @@ struct BallFit {
         *t_next = cl.t1;
     }
 
+    bool finished() const { return overflow; }
+
     void scan(const ChunkLists &cl, const std::vector<int32_t> &order) {
         int64_t t = cl.t0;
         while (t < cl.t1 && !overflow) {
@@ -260,6 +262,8 @@ struct DirectFit {
         banned.clear();
         ncol = 0;
     }
+
+    bool finished() const { return false; }
 
     void scan(const ChunkLists &cl, const std::vector<int32_t> &order) {
         for (int64_t t = cl.t0; t < cl.t1; ++t) {
@@ -289,7 +293,7 @@ int color_threads(int64_t n) {
 
 // Lists to `depth` (whole balls, or earlier nodes when pos is given) chunk by
 // chunk, each chunk scanned by every fit of `fits` (one thread per fit)
-// while the next chunk is listed.
+// while the next chunk is listed; stops early once every fit has given up.
 template <class Fit>
 void run_pipeline(int64_t n, const int32_t *rp, const int32_t *ci, const std::vector<int32_t> &order,
                   int32_t depth, const int32_t *pos, std::vector<Fit *> &fits) {
@@ -327,6 +331,9 @@ void run_pipeline(int64_t n, const int32_t *rp, const int32_t *ci, const std::ve
         if (lister.joinable()) lister.join();
         std::swap(cur, nxt);
         if (cur.t0 >= n) break;
+        bool all = true;
+        for (Fit *f : fits) all = all && f->finished();
+        if (all) break;
     }
 }
 
