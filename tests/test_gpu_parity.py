@@ -344,3 +344,29 @@ def test_hutchpp_changing_sketch_width(ctx):
         _say("   N_r=%d estimate rel err %.2e (sens %.1e)" % (nr, err, sens))
         assert err < max(TOL[True], 20 * sens)
     ctx.release(gid)
+
+
+@pytest.mark.parametrize("nr,nh", [(8, 0), (1, 7), (128, 8)])
+def test_hutchpp_sketch_width_edges(ctx, nr, nh):
+    """Hutch++ with no Hutchinson part (N_H = 0: the estimate is the sum over
+    Q), a one-column sketch, and the widest sketch (N_r = 128), FP64 vectors,
+    against the oracle (eq. (3.9))."""
+    _say("case Hutch++ N_r=%d N_H=%d" % (nr, nh))
+    n, e = synth.erdos_renyi(1500, 8.0, 29)
+    gid, ref = _setup(ctx, n, e, True)
+    k = 20
+    out = ctx.estimate(gid, vne.PROBE_HUTCHPP, nr + nh, k, vne.MODE_DESING | vne.MODE_F64, seed=31,
+                       n_sketch=nr, want_coeffs=False)
+    Om = oracle.rademacher_block(31, ref.node_ids, np.arange(nr))
+    G = oracle.rademacher_block(31, ref.node_ids, np.arange(nr, nr + nh))
+    est, det = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(True))
+    import scipy.sparse as sp
+    P = np.arange(ref.n)[::-1]
+    Ap = sp.csr_matrix(ref.scipy())[P][:, P]
+    est_p, _ = oracle.hutchpp(Ap, Om[P], G[P], k, oracle.breakdown_tau(True))
+    err, sens = abs(out["estimate"] - est) / abs(est), abs(est_p - est) / abs(est)
+    _say("   estimate rel err %.2e (sens %.1e)" % (err, sens))
+    assert err < max(TOL[True], 20 * sens)
+    if nh == 0:
+        assert abs(out["estimate"] - out["quad"].sum()) <= 1e-13 * abs(out["estimate"])
+    ctx.release(gid)
