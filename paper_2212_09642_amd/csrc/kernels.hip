@@ -2128,26 +2128,43 @@ __global__ void __launch_bounds__(256) k_gram(const T *X, int32_t ldx, const T *
     const int chunk = blockIdx.x;
     const int64_t r0 = (int64_t)chunk * kGramRows;
     const int64_t r1 = min((int64_t)n, r0 + kGramRows);
-    const int a0 = (threadIdx.x / 16) * 8, b0 = (threadIdx.x % 16) * 8;
+    // thread (ta, tb) owns rows ta + 16 u and columns tb + 16 v of the output:
+    // the 16 threads of a quarter-wave read 16 consecutive doubles of a staged
+    // row (no LDS bank conflicts), the 4 quarter-waves read 4 broadcast rows
+    const int ta = threadIdx.x / 16, tb = threadIdx.x % 16;
     double acc[8][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+    // staging: thread t moves column t % 128 of rows t / 128 + 2 i; the next
+    // round's values are loaded into registers while this round computes
+    constexpr int PER = RS * 128 / 256;
+    const int scol = threadIdx.x % 128, srow = threadIdx.x / 128;
+    T xr[PER], yr[PER];
+    auto fetch = [&](int64_t rs) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int64_t r = rs + srow + 2 * i;
+            xr[i] = (r < r1 && scol < na) ? X[r * ldx + scol] : (T)0;
+            yr[i] = (r < r1 && scol < nb) ? Y[r * ldy + scol] : (T)0;
+        }
+    };
+    fetch(r0);
     for (int64_t rs = r0; rs < r1; rs += RS) {
-        for (int q = threadIdx.x; q < RS * 128; q += 256) {
-            const int rr = q / 128, cc = q % 128;
-            const int64_t r = rs + rr;
-            xs[rr][cc] = (r < r1 && cc < na) ? (double)X[r * ldx + cc] : 0.0;
-            ys[rr][cc] = (r < r1 && cc < nb) ? (double)Y[r * ldy + cc] : 0.0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            xs[srow + 2 * i][scol] = (double)xr[i];
+            ys[srow + 2 * i][scol] = (double)yr[i];
         }
         __syncthreads();
+        if (rs + RS < r1) fetch(rs + RS);
         for (int rr = 0; rr < RS; ++rr) {
             double xa[8], yb[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                xa[u] = xs[rr][a0 + u];
-                yb[u] = ys[rr][b0 + u];
+                xa[u] = xs[rr][ta + 16 * u];
+                yb[u] = ys[rr][tb + 16 * u];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
@@ -2160,16 +2177,28 @@ __global__ void __launch_bounds__(256) k_gram(const T *X, int32_t ldx, const T *
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
-        for (int v = 0; v < 8; ++v)
-            if (a0 + u < na && b0 + v < nb) out[(int64_t)(a0 + u) * ldo + b0 + v] = acc[u][v];
+        for (int v = 0; v < 8; ++v) {
+            const int a = ta + 16 * u, b = tb + 16 * v;
+            if (a < na && b < nb) out[(int64_t)a * ldo + b] = acc[u][v];
+        }
 }
 
 __global__ void __launch_bounds__(256) k_gram_reduce(const double *part, int64_t chunks, int64_t total,
                                                      double *out) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= total) return;
+    // chunk partials in order, in batches whose loads are issued before the adds
+    constexpr int UB = 16;
     double s = 0.0;
-    for (int64_t q = 0; q < chunks; ++q) s += part[q * total + t];
+    int64_t q = 0;
+    for (; q + UB <= chunks; q += UB) {
+        double v[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) v[u] = part[(q + u) * total + t];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) s += v[u];
+    }
+    for (; q < chunks; ++q) s += part[q * total + t];
     out[t] = s;
 }
 
@@ -2269,31 +2298,49 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_apply(const T *X, int32_t ldx, const double *M, int32_t ldm, int32_t na,
                                                int32_t nb, T *Z, int32_t ldz, int32_t n, int32_t sub) {
     constexpr int TS = 32;
-    __shared__ double xt[TS][128];   // xt[t][row]
-    __shared__ double ms[TS][128];   // ms[t][col]
+    __shared__ double xt[128][TS + 1];   // xt[row][t]; the pad spreads the rows over the banks
+    __shared__ double ms[TS][128];       // ms[t][col]
     const int64_t r0 = (int64_t)blockIdx.x * 128;
-    const int i0 = (threadIdx.x / 16) * 8, b0 = (threadIdx.x % 16) * 8;
+    // thread (i0, tb) owns rows i0 .. i0 + 7 and columns tb + 16 v: the 16
+    // threads of a quarter-wave read 16 consecutive doubles of a row of ms
+    const int i0 = (threadIdx.x / 16) * 8, tb = threadIdx.x % 16;
     double acc[8][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+    // staging: thread t moves X[r0 + t / TS + 8 i][t0 + t % TS] (consecutive
+    // threads read consecutive inner indices) and M[t0 + t / 128 + 2 i][t % 128];
+    // the next step's values are loaded into registers while this one computes
+    constexpr int PER = TS * 128 / 256;
+    const int xc = threadIdx.x % TS, xr0 = threadIdx.x / TS;
+    const int mc = threadIdx.x % 128, mr0 = threadIdx.x / 128;
+    T xv[PER];
+    double mv[PER];
+    auto fetch = [&](int t0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int64_t r = r0 + xr0 + 8 * i;
+            xv[i] = (r < n && t0 + xc < na) ? X[r * ldx + t0 + xc] : (T)0;
+            const int mt = t0 + mr0 + 2 * i;
+            mv[i] = (mt < na && mc < nb) ? M[(int64_t)mt * ldm + mc] : 0.0;
+        }
+    };
+    fetch(0);
     for (int t0 = 0; t0 < na; t0 += TS) {
-        for (int q = threadIdx.x; q < TS * 128; q += 256) {
-            // X rows: consecutive threads read consecutive inner indices
-            const int rr = q / TS, tt = q % TS;
-            const int64_t r = r0 + rr;
-            xt[tt][rr] = (r < n && t0 + tt < na) ? (double)X[r * ldx + t0 + tt] : 0.0;
-            const int mt = q / 128, mc = q % 128;
-            ms[mt][mc] = (t0 + mt < na && mc < nb) ? M[(int64_t)(t0 + mt) * ldm + mc] : 0.0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            xt[xr0 + 8 * i][xc] = (double)xv[i];
+            ms[mr0 + 2 * i][mc] = mv[i];
         }
         __syncthreads();
+        if (t0 + TS < na) fetch(t0 + TS);
         for (int tt = 0; tt < TS; ++tt) {
             double xa[8], mb[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                xa[u] = xt[tt][i0 + u];
-                mb[u] = ms[tt][b0 + u];
+                xa[u] = xt[i0 + u][tt];
+                mb[u] = ms[tt][tb + 16 * u];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
@@ -2308,7 +2355,7 @@ __global__ void __launch_bounds__(256) k_apply(const T *X, int32_t ldx, const do
         if (r >= n) continue;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
-            const int cc = b0 + v;
+            const int cc = tb + 16 * v;
             if (cc >= nb) continue;
             if (sub) Z[r * ldz + cc] = (T)((double)Z[r * ldz + cc] - acc[u][v]);
             else Z[r * ldz + cc] = (T)acc[u][v];
