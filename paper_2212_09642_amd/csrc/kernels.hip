@@ -100,6 +100,10 @@ constexpr int gather_batch() { return VNE_GATHER_U > 0 ? VNE_GATHER_U : (LPR >= 
 #ifndef VNE_RECON_UJ
 #define VNE_RECON_UJ 2
 #endif
+// rows per thread of k_reconstruct
+#ifndef VNE_RECON_RPT
+#define VNE_RECON_RPT 4
+#endif
 
 // minimum waves per SIMD requested for the step kernels (0: compiler's choice)
 #ifndef VNE_STEP_WAVES
@@ -2040,7 +2044,7 @@ template <typename T, int CPL>
 __global__ void __launch_bounds__(256) k_reconstruct(const T *V, int64_t stride, int32_t ldv,
                                                      const double *S, const double *norm2,
                                                      int32_t k, int32_t n, int32_t m, T *Y, int32_t ldy) {
-    constexpr int RPT = 4, UJ = VNE_RECON_UJ;
+    constexpr int RPT = VNE_RECON_RPT, UJ = VNE_RECON_UJ;
     const int groups = (m + CPL - 1) / CPL;            // column groups per row
     const int rows_per_pass = 256 / groups;
     if ((int)threadIdx.x >= rows_per_pass * groups) return;
@@ -2096,7 +2100,7 @@ hipError_t launch_reconstruct(const void *Vstore, bool fp64, int64_t step_stride
     const int cpl = fp64 ? 2 : 4;
     const int groups = (m + cpl - 1) / cpl;
     if (groups > 256 || ldv % cpl) return hipErrorInvalidValue;
-    const int rows_per_block = (256 / groups) * 4;
+    const int rows_per_block = (256 / groups) * VNE_RECON_RPT;
     dim3 g((unsigned)((n + rows_per_block - 1) / rows_per_block));
     if (fp64)
         hipLaunchKernelGGL((k_reconstruct<double, 2>), g, dim3(256), 0, s, (const double *)Vstore, step_stride,
