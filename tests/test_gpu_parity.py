@@ -370,3 +370,30 @@ def test_hutchpp_sketch_width_edges(ctx, nr, nh):
     if nh == 0:
         assert abs(out["estimate"] - out["quad"].sum()) <= 1e-13 * abs(out["estimate"])
     ctx.release(gid)
+
+
+def test_device_csr_and_device_colours(ctx):
+    """A matrix registered from device tensors (borrowed row_ptr and col_idx)
+    and colour indicators given as a device tensor give the same bits as the
+    host registration and host colours."""
+    import torch
+    _say("case device-resident CSR and colours, WS n=4000")
+    n, e = synth.watts_strogatz(4000, 8, 0.1, 33)
+    g = vne.laplacian_from_edges(n, e, np.float32)
+    gid_h = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    rp = torch.tensor(g["row_ptr"], dtype=torch.int32, device="cuda")
+    ci = torch.tensor(g["col_idx"], dtype=torch.int32, device="cuda")
+    va = torch.tensor(g["values"], dtype=torch.float32, device="cuda")
+    gid_d = ctx.register(rp, ci, va, g["scale"], node_keys=g["node_ids"])
+    mode = vne.MODE_DESING
+    a = ctx.estimate(gid_h, vne.PROBE_RADEMACHER, 24, 30, mode, seed=4)
+    b = ctx.estimate(gid_d, vne.PROBE_RADEMACHER, 24, 30, mode, seed=4)
+    assert np.array_equal(a["quad"], b["quad"]) and a["estimate"] == b["estimate"]
+    col, s = vne.color_greedy(g["row_ptr"], g["col_idx"], g["values"], 2)
+    colt = torch.tensor(col, dtype=torch.int32, device="cuda")
+    c1 = ctx.estimate(gid_h, vne.PROBE_COLORING, s, 30, mode, colors=col)
+    c2 = ctx.estimate(gid_d, vne.PROBE_COLORING, s, 30, mode, colors=colt)
+    assert np.array_equal(c1["quad"], c2["quad"]) and c1["estimate"] == c2["estimate"]
+    ctx.release(gid_d)
+    ctx.release(gid_h)
+    del rp, ci, va, colt
