@@ -397,3 +397,38 @@ def test_device_csr_and_device_colours(ctx):
     ctx.release(gid_d)
     ctx.release(gid_h)
     del rp, ci, va, colt
+
+
+def test_stream_memory_and_budget():
+    """A context on a stream of its own gives the bits of the default stream;
+    vne_ctx_memory follows registration and release; an estimate whose
+    workspace exceeds the HBM budget fails with VNE_ENOMEM and leaves the
+    context usable."""
+    import torch
+    _say("case stream, memory accounting and HBM budget")
+    n, e = synth.erdos_renyi(6000, 8.0, 35)
+    g = vne.laplacian_from_edges(n, e, np.float32)
+    mode = vne.MODE_DESING
+    with vne.Context(0) as c0:
+        gid = c0.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+        want = c0.estimate(gid, vne.PROBE_RADEMACHER, 32, 25, mode, seed=8)
+    st = torch.cuda.Stream()                      # default priority
+    with vne.Context(0, stream=st.cuda_stream) as c1:
+        before = c1.memory()
+        gid = c1.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+        after_reg = c1.memory()
+        got = c1.estimate(gid, vne.PROBE_RADEMACHER, 32, 25, mode, seed=8)
+        c1.set_stream(torch.cuda.current_stream().cuda_stream)
+        got2 = c1.estimate(gid, vne.PROBE_RADEMACHER, 32, 25, mode, seed=8)
+        c1.release(gid)
+        assert after_reg > before and c1.memory() < after_reg
+    assert np.array_equal(want["quad"], got["quad"]) and np.array_equal(want["quad"], got2["quad"])
+    # a budget that holds the matrix but not a 256-column workspace
+    with vne.Context(0, hbm_budget_bytes=4 << 20) as c2:
+        gid = c2.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+        with pytest.raises(vne.VneError) as ex:
+            c2.estimate(gid, vne.PROBE_RADEMACHER, 256, 25, mode, seed=8)
+        assert ex.value.status == -2
+        small = c2.estimate(gid, vne.PROBE_RADEMACHER, 4, 10, mode, seed=8)
+        assert np.isfinite(small["estimate"])
+        c2.release(gid)
