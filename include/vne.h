@@ -152,7 +152,8 @@ vne_status vne_csr_validate(const vne_csr *csr, uint32_t flags, char *msg, int64
  * descending degree (number of off-diagonal entries; ties by increasing row
  * index), each taking the smallest colour (from 0) not used by an earlier
  * node within geodesic distance d in the graph of the matrix.  Host CSR only.
- * colors_out: host [n]; *n_colors = number of colours used.  d >= 1. */
+ * colors_out: host [n]; *n_colors = number of colours used.  1 <= d <= 254
+ * (VNE_EINVAL otherwise). */
 vne_status vne_color_greedy(const vne_csr *csr, int32_t d, int32_t *colors_out,
                             int32_t *n_colors, char *msg, int64_t msg_len);
 

@@ -409,7 +409,8 @@ extern "C" vne_status vne_color_greedy(const vne_csr *csr, int32_t d, int32_t *c
         set_msg(msg, msg_len, "vne_color_greedy needs a host CSR");
         return VNE_EINVAL;
     }
-    if (d < 1) { set_msg(msg, msg_len, "distance d must be >= 1"); return VNE_EINVAL; }
+    // distances are kept in one byte per listed node
+    if (d < 1 || d > 254) { set_msg(msg, msg_len, "distance d must be in [1, 254]"); return VNE_EINVAL; }
     if (!colors_out || !n_colors) { set_msg(msg, msg_len, "NULL output"); return VNE_EINVAL; }
     std::string m;
     vne_status st = validate_host_csr(csr, 0, &m);

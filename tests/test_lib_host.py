@@ -69,6 +69,30 @@ def test_coloring_bit_exact_with_oracle(maker, d):
     assert s1 == s2 and np.array_equal(c1, c2)
 
 
+@pytest.mark.parametrize("maker", [lambda: synth.erdos_renyi(300, 2.0, 5), lambda: synth.grid2d_graph(20, 31),
+                                   lambda: synth.watts_strogatz(600, 6, 0.1, 8), lambda: synth.path_graph(400)])
+@pytest.mark.parametrize("d", [5, 8, 13])
+def test_coloring_larger_distances_bit_exact_with_oracle(maker, d):
+    # odd and even d split the distance between the two balls differently
+    n, e = maker()
+    a = vne.laplacian_from_edges(n, e)
+    c1, s1 = vne.color_greedy(a["row_ptr"], a["col_idx"], a["values"], d)
+    c2, s2 = oracle.greedy_distance_coloring(a["row_ptr"], a["col_idx"], a["n"], d)
+    assert s1 == s2 and np.array_equal(c1, c2)
+
+
+def test_coloring_distance_range():
+    a = vne.laplacian_from_edges(*synth.path_graph(300))
+    c, s = vne.color_greedy(a["row_ptr"], a["col_idx"], a["values"], 254)
+    # nodes of a path within distance 254 of each other all differ: 255 colours
+    assert s == 255
+    for i in range(a["n"]):
+        assert c[i] not in c[i + 1:i + 255]
+    for d in (0, 255):
+        with pytest.raises(vne.VneError):
+            vne.color_greedy(a["row_ptr"], a["col_idx"], a["values"], d)
+
+
 @pytest.mark.slow
 def test_coloring_probing_workload_full_size():
     # WS n=1e6, k=10, p=0.1, distance 2: the probing configuration
