@@ -300,6 +300,10 @@ vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool sto
     p->mt = choose_tile(m, fp64, env_int("VNE_TILE", 0));
     p->m_pad = pad_columns(m, p->mt);
     const size_t es = fp64 ? 8 : 4;
+    // sizes far beyond any device (and beyond size_t arithmetic) fail here
+    if ((double)set->n * p->m_pad * es * (store ? k : 1) > 0x1p56)
+        return fail(c, VNE_ENOMEM, "probe block of " + std::to_string(m) + " columns on " +
+                                       std::to_string(set->n) + " rows exceeds any device memory");
     const size_t blk = (size_t)set->n * p->m_pad * es;
     const Schedule &s = set->sched;
     const size_t cols = (size_t)p->G * p->m_pad;      // (graph, column) pairs
