@@ -205,6 +205,15 @@ def _is_device(a):
     return hasattr(a, "is_cuda") and a.is_cuda
 
 
+def _check_device(t, dtypes, name):
+    """A device tensor handed to the library as a plain pointer must be
+    contiguous and of the element type the call reads."""
+    if not t.is_contiguous():
+        raise ValueError("%s: device tensor must be contiguous" % name)
+    if t.dtype not in dtypes:
+        raise ValueError("%s: device tensor of dtype %s, expected %s" % (name, t.dtype, " or ".join(map(str, dtypes))))
+
+
 def _check(st, msg):
     if st != 0:
         raise VneError(st, msg)
@@ -244,6 +253,9 @@ def _csr_struct(row_ptr, col_idx, values, scale, node_keys=None):
         vd = F64 if values.dtype == np.float64 else F32
     else:
         import torch
+        _check_device(row_ptr, (torch.int32,), "row_ptr")
+        _check_device(col_idx, (torch.int32,), "col_idx")
+        _check_device(values, (torch.float32, torch.float64), "values")
         vd = F64 if values.dtype == torch.float64 else F32
     keys = None
     if node_keys is not None:
@@ -330,12 +342,16 @@ class Context:
         keep = []
         if colors is not None:
             if _is_device(colors):
+                import torch
+                _check_device(colors, (torch.int32,), "colors")
                 loc = DEVICE
             else:
                 colors = np.ascontiguousarray(colors, np.int32)
             keep.append(colors)
         if dense is not None:
             if _is_device(dense):
+                import torch
+                _check_device(dense, (torch.float64 if mode & MODE_F64 else torch.float32,), "dense")
                 loc = DEVICE
             else:
                 dense = np.ascontiguousarray(dense, np.float64 if mode & MODE_F64 else np.float32)
@@ -408,12 +424,16 @@ class Context:
         keep = []
         if colors is not None:
             if _is_device(colors):
+                import torch
+                _check_device(colors, (torch.int32,), "colors")
                 loc = DEVICE
             else:
                 colors = np.ascontiguousarray(colors, np.int32)
             keep.append(colors)
         if dense is not None:
             if _is_device(dense):
+                import torch
+                _check_device(dense, (torch.float64 if mode & MODE_F64 else torch.float32,), "dense")
                 loc = DEVICE
             else:
                 dense = np.ascontiguousarray(dense, np.float64 if mode & MODE_F64 else np.float32)

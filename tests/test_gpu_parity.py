@@ -122,6 +122,12 @@ def test_dense_probes_device_tensor(ctx):
     out = ctx.estimate(gid, vne.PROBE_DENSE, 12, 30, vne.MODE_F64 | vne.MODE_DESING, dense=Bt)
     want = oracle.quadforms(ref.scipy(), B, 30, oracle.breakdown_tau(True))
     _check_quad(out, want, True, sens=_order_sensitivity(ref.scipy(), B, 30, True), n=ref.n)
+    # the binding refuses device tensors the library would misread
+    with pytest.raises(ValueError):
+        ctx.estimate(gid, vne.PROBE_DENSE, 12, 30, vne.MODE_F64 | vne.MODE_DESING,
+                     dense=Bt.t().contiguous().t())        # (n, 12) view with column-major strides
+    with pytest.raises(ValueError):
+        ctx.estimate(gid, vne.PROBE_DENSE, 12, 30, vne.MODE_F64 | vne.MODE_DESING, dense=Bt.float())
 
 
 def test_deterministic(ctx):
