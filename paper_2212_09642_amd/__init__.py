@@ -258,9 +258,11 @@ def _csr_struct(row_ptr, col_idx, values, scale, node_keys=None):
         _check_device(values, (torch.float32, torch.float64), "values")
         vd = F64 if values.dtype == torch.float64 else F32
     keys = None
+    n = (row_ptr.numel() if dev else row_ptr.size) - 1
     if node_keys is not None:
         keys = np.ascontiguousarray(node_keys, np.int64)
-    n = (row_ptr.numel() if dev else row_ptr.size) - 1
+        if keys.size != n:
+            raise ValueError("node_keys: %d entries for %d rows" % (keys.size, n))
     nnz = col_idx.numel() if dev else col_idx.size
     s = _Csr(n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(values), vd, DEVICE if dev else HOST,
              _ptr(keys), float(scale))
@@ -295,6 +297,7 @@ class Context:
         _check(st, L.vne_last_error(None).decode())
         self._h = h
         self._L = L
+        self._rows = {}          # graph id -> rows, for the shape checks of probe arrays
 
     def close(self):
         if getattr(self, "_h", None):
@@ -330,10 +333,23 @@ class Context:
         s, keep = _csr_struct(row_ptr, col_idx, values, scale, node_keys)
         gid = ctypes.c_int32()
         self._chk(self._L.vne_graph_register(self._h, ctypes.byref(s), validate, ctypes.byref(gid)))
+        self._rows[gid.value] = s.n
         return gid.value
 
     def release(self, gid):
         self._chk(self._L.vne_graph_release(self._h, gid))
+        self._rows.pop(gid, None)
+
+    def _check_shapes(self, gid, m, colors, dense):
+        """The library reads n colours and an n x m probe block: refuse other
+        shapes before it reads past them."""
+        n = self._rows.get(gid)
+        if n is None:
+            return
+        if colors is not None and tuple(colors.shape) != (n,):
+            raise ValueError("colors: shape %s, expected (%d,)" % (tuple(colors.shape), n))
+        if dense is not None and tuple(dense.shape) != (n, m):
+            raise ValueError("dense: shape %s, expected (%d, %d)" % (tuple(dense.shape), n, m))
 
     def estimate(self, gid, kind, m, k, mode, seed=0, n_sketch=0, colors=None, dense=None,
                  want_coeffs=True):
@@ -356,6 +372,7 @@ class Context:
             else:
                 dense = np.ascontiguousarray(dense, np.float64 if mode & MODE_F64 else np.float32)
             keep.append(dense)
+        self._check_shapes(gid, m, colors, dense)
         pr = _Probes(kind, m, seed, n_sketch, loc, _ptr(colors), _ptr(dense))
         quad = np.zeros(m)
         kef = np.zeros(m, np.int32)
@@ -387,6 +404,7 @@ class Context:
             if dense is not None:
                 dense = np.ascontiguousarray(dense, vdt)
                 keep.append(dense)
+            self._check_shapes(int(q["gid"]), m, colors, dense)
             ids[i] = int(q["gid"])
             ks[i] = k
             prs[i] = _Probes(int(q["kind"]), m, int(q.get("seed", 0)), 0, HOST, _ptr(colors), _ptr(dense))
@@ -439,6 +457,7 @@ class Context:
                 dense = np.ascontiguousarray(dense, np.float64 if mode & MODE_F64 else np.float32)
             keep.append(dense)
         tol = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, np.float64), (m,)))
+        self._check_shapes(gid, m, colors, dense)
         pr = _Probes(kind, m, seed, 0, loc, _ptr(colors), _ptr(dense))
         rule = _StopRule(_ptr(tol), float(lam_lo), float(lam_hi), int(n_grid))
         quad = np.zeros(m)

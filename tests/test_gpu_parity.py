@@ -400,6 +400,13 @@ def test_device_csr_and_device_colours(ctx):
     c1 = ctx.estimate(gid_h, vne.PROBE_COLORING, s, 30, mode, colors=col)
     c2 = ctx.estimate(gid_d, vne.PROBE_COLORING, s, 30, mode, colors=colt)
     assert np.array_equal(c1["quad"], c2["quad"]) and c1["estimate"] == c2["estimate"]
+    # arrays of the wrong length are refused before the library reads them
+    with pytest.raises(ValueError):
+        ctx.estimate(gid_h, vne.PROBE_COLORING, s, 30, mode, colors=col[:-1])
+    with pytest.raises(ValueError):
+        ctx.estimate(gid_h, vne.PROBE_DENSE, 4, 30, mode, dense=np.ones((g["n"], 5), np.float32))
+    with pytest.raises(ValueError):
+        ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"][:-1])
     ctx.release(gid_d)
     ctx.release(gid_h)
     del rp, ci, va, colt
