@@ -104,7 +104,10 @@ typedef struct {
     int32_t n_sketch;         /* HUTCHPP: N_r = columns of Omega (the first
                                  n_sketch hash columns); G uses the next m-N_r */
     int32_t location;         /* DENSE / COLORING arrays: VNE_HOST/VNE_DEVICE    */
-    const int32_t *colors;    /* COLORING: [n] colour of each row in [0, m)     */
+    const int32_t *colors;    /* COLORING: [n] colour of each row in [0, m);
+                                 host arrays are checked (VNE_EINVAL), device
+                                 arrays are not: a row with a colour outside
+                                 [0, m) belongs to no probe vector             */
     const void *dense;        /* DENSE: n x m row-major, FP32 (default mode) or
                                  FP64 (VNE_MODE_F64)                             */
 } vne_probes;
