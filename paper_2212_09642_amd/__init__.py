@@ -125,6 +125,10 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libvne.so not built: run __graft_entry__.build() (%s)" % LIB_PATH)
+        # torch first: its HIP runtime is then the one libvne.so binds to, so
+        # that the process holds a single runtime (loaded the other way round,
+        # two runtimes are mapped and torch's device initialisation fails)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         i32, i64, u64, vp, cp, dbl = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                       ctypes.c_void_p, ctypes.c_char_p, ctypes.c_double)

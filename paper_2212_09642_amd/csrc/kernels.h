@@ -95,8 +95,10 @@ struct FinalizeArgs {
     int32_t flag_split;
 };
 
-// Returns the column tile width the step kernel uses for this probe width.
-int choose_tile(int m, bool fp64, int requested);
+// Returns the column tile width the step kernel uses for this probe width;
+// three: FP32 widths 3 * 2^j (12 .. 192) may take a tile of three columns per
+// lane (launch_step only; the slot kernels have four per lane).
+int choose_tile(int m, bool fp64, int requested, bool three = false);
 int pad_columns(int m, int mt);
 
 // [normalize pass,] step kernel, then (if the matrix has long rows) the long-row kernel

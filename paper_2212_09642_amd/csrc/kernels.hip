@@ -70,6 +70,31 @@ __device__ __forceinline__ void store_vec_nt(T *p, const T (&in)[N]) {
     __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
 }
 
+// three FP32 columns per lane (tiles of 3 * 2^j columns): 12-byte runs,
+// as three scalar accesses (no 3-wide vector type: it would be 16 bytes)
+template <>
+__device__ __forceinline__ void load_vec<float, 3>(const float *p, float (&out)[3]) {
+    out[0] = p[0];
+    out[1] = p[1];
+    out[2] = p[2];
+}
+template <>
+__device__ __forceinline__ void store_vec<float, 3>(float *p, const float (&in)[3]) {
+    p[0] = in[0];
+    p[1] = in[1];
+    p[2] = in[2];
+}
+template <>
+__device__ __forceinline__ void load_vec_nt<float, 3>(const float *p, float (&out)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[k] = __builtin_nontemporal_load(p + k);
+}
+template <>
+__device__ __forceinline__ void store_vec_nt<float, 3>(float *p, const float (&in)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) __builtin_nontemporal_store(in[k], p + k);
+}
+
 template <bool NT, typename T, int N>
 __device__ __forceinline__ void load_s(const T *p, T (&out)[N]) {
     if (NT) load_vec_nt<T, N>(p, out);
@@ -610,7 +635,13 @@ __global__ void __launch_bounds__(256) k_long_rows_slots(const StepArgs *args, c
     long_rows_group<T, CPL, LPR, false, true>(a, e.y, e.z);
 }
 
-int choose_tile(int m, bool fp64, int requested) {
+int choose_tile(int m, bool fp64, int requested, bool three) {
+    // FP32 widths 3 * 2^j (12 .. 192) as one tile of three columns per lane,
+    // without padding to the next power of two
+    if (three && !fp64 && requested <= 0 && m % 3 == 0) {
+        const int q = m / 3;
+        if (q >= 4 && q <= 64 && (q & (q - 1)) == 0) return m;
+    }
     // column tile = CPL * LPR; by default at most 128 FP32 (64 FP64) columns,
     // the widest tile whose gathered block stays cache friendly on large graphs
     const int cpl = fp64 ? 2 : 4;
@@ -708,6 +739,11 @@ hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s) 
             case 64: return launch_step_t<float, 4, 16>(a, first, s);
             case 128: return launch_step_t<float, 4, 32>(a, first, s);
             case 256: return launch_step_t<float, 4, 64>(a, first, s);
+            case 12: return launch_step_t<float, 3, 4>(a, first, s);
+            case 24: return launch_step_t<float, 3, 8>(a, first, s);
+            case 48: return launch_step_t<float, 3, 16>(a, first, s);
+            case 96: return launch_step_t<float, 3, 32>(a, first, s);
+            case 192: return launch_step_t<float, 3, 64>(a, first, s);
         }
     } else {
         switch (a.mt) {
@@ -1005,8 +1041,9 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Probe block.  Thread layout: columns of one tile fastest, 256 / mt rows per
-// pass.  Pass 1 sums every column (for the centring of Remark 4.6), pass 2
-// writes P_1 = c (element type of the mode) and sums c^2 of the stored values.
+// pass (integer division).  Pass 1 sums every column (for the centring of
+// Remark 4.6), pass 2 writes P_1 = c (element type of the mode) and sums c^2
+// of the stored values.
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -1027,6 +1064,8 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     __shared__ double sh[256];
     const int rows_per = 256 / a.mt;
     const int cc = threadIdx.x % a.mt, rr = threadIdx.x / a.mt;
+    // a tile width that does not divide 256 leaves the last threads idle
+    const bool active = rr < rows_per;
     const int b = blockIdx.x;
     const int g = a.block_graph ? a.block_graph[b] : 0;
     const int64_t r0 = a.block_row_begin[b], r1 = a.block_row_begin[b + 1];
@@ -1036,7 +1075,7 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
         const int c = t0 + cc;
         double acc = 0.0;
         const double mu = PASS == 2 ? a.mean[(int64_t)g * a.m_pad + c] : 0.0;
-        for (int64_t i = r0 + rr; i < r1; i += rows_per) {
+        for (int64_t i = r0 + rr; active && i < r1; i += rows_per) {
             const double v = probe_value<T>(a, g, i, c);
             if (PASS == 1) {
                 acc += v;

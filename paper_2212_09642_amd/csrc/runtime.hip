@@ -297,7 +297,7 @@ vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool sto
     p->m = m;
     p->k = k;
     p->store = store;
-    p->mt = choose_tile(m, fp64, env_int("VNE_TILE", 0));
+    p->mt = choose_tile(m, fp64, env_int("VNE_TILE", 0), env_int("VNE_TILE3", 1) != 0);
     p->m_pad = pad_columns(m, p->mt);
     const size_t es = fp64 ? 8 : 4;
     // sizes far beyond any device (and beyond size_t arithmetic) fail here
@@ -688,6 +688,7 @@ vne_status autotune(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, boo
     std::vector<int> cands;
     for (int t = cpl * 4; t <= cpl * 64; t *= 2)
         if (t <= p->m_pad && p->m_pad % t == 0) cands.push_back(t);
+    if (std::find(cands.begin(), cands.end(), p->mt) == cands.end()) cands.push_back(p->mt);
     int best = p->mt;
     if (cands.size() > 1) {
         hipEvent_t e0 = nullptr, e1 = nullptr;

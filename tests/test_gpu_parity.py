@@ -445,3 +445,59 @@ def test_stream_memory_and_budget():
         small = c2.estimate(gid, vne.PROBE_RADEMACHER, 4, 10, mode, seed=8)
         assert np.isfinite(small["estimate"])
         c2.release(gid)
+
+
+@pytest.mark.parametrize("m", [12, 24, 48, 96, 192])
+def test_three_column_tiles(ctx, m, monkeypatch):
+    """FP32 widths 3 * 2^j run in tiles of three columns per lane (no padding
+    to the next power of two): Rademacher forms on a BA graph with hub rows
+    (long rows in segments) against the oracle."""
+    _say("case three-column tiles m=%d" % m)
+    # a context of its own with the autotuner off, so that the three-column
+    # tile is the one that runs
+    monkeypatch.setenv("VNE_AUTOTUNE", "0")
+    n, e = synth.barabasi_albert(6000, 3, 41)
+    with vne.Context(0) as c:
+        gid, ref = _setup(c, n, e, False)
+        k = 25
+        out = c.estimate(gid, vne.PROBE_RADEMACHER, m, k, vne.MODE_DESING, seed=43)
+    B = oracle.rademacher_block(43, ref.node_ids, np.arange(m))
+    want = oracle.quadforms(ref.scipy(), B, k, oracle.breakdown_tau(False))
+    _check_quad(out, want, False, sens=_order_sensitivity(ref.scipy(), B, k, False), n=ref.n)
+
+
+def test_three_column_tiles_colouring_and_sketch(ctx, monkeypatch):
+    """Colour indicators with 24 colours and a Hutch++ sketch of 24 columns in
+    three-column tiles, against the oracle; the padded power-of-two tile
+    gives the same forms within the bar."""
+    _say("case three-column tiles: 24 colours, Hutch++ sketch of 24")
+    n, e = synth.watts_strogatz(9000, 6, 0.1, 44)
+    gid, ref = _setup(ctx, n, e, False)
+    # a colouring with exactly 24 colours: rows coloured round robin
+    col = (np.arange(ref.n) % 24).astype(np.int32)
+    out = ctx.estimate(gid, vne.PROBE_COLORING, 24, 30, vne.MODE_DESING, colors=col)
+    P = oracle.indicator_block(col, 24)
+    want = oracle.quadforms(ref.scipy(), P, 30, oracle.breakdown_tau(False))
+    _check_quad(out, want, False, sens=_order_sensitivity(ref.scipy(), P, 30, False), n=ref.n)
+    nr, nh, k = 24, 40, 20
+    hp = ctx.estimate(gid, vne.PROBE_HUTCHPP, nr + nh, k, vne.MODE_DESING, seed=45, n_sketch=nr,
+                      want_coeffs=False)
+    Om = oracle.rademacher_block(45, ref.node_ids, np.arange(nr))
+    G = oracle.rademacher_block(45, ref.node_ids, np.arange(nr, nr + nh))
+    est, _ = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(False))
+    import scipy.sparse as sp
+    Pm = np.arange(ref.n)[::-1]
+    Ap = sp.csr_matrix(ref.scipy())[Pm][:, Pm]
+    est_p, _ = oracle.hutchpp(Ap, Om[Pm], G[Pm], k, oracle.breakdown_tau(False))
+    err, sens = abs(hp["estimate"] - est) / abs(est), abs(est_p - est) / abs(est)
+    _say("   Hutch++ estimate rel err %.2e (sens %.1e)" % (err, sens))
+    assert err < max(TOL[False], 20 * sens)
+    ctx.release(gid)
+    # the padded power-of-two tile (VNE_TILE3=0) gives the same forms within the bar
+    monkeypatch.setenv("VNE_TILE3", "0")
+    with vne.Context(0) as c2:
+        g2 = vne.laplacian_from_edges(n, e, np.float32)
+        gid2 = c2.register(g2["row_ptr"], g2["col_idx"], g2["values"], g2["scale"], node_keys=g2["node_ids"])
+        out2 = c2.estimate(gid2, vne.PROBE_COLORING, 24, 30, vne.MODE_DESING, colors=col)
+    rel = np.abs(out2["quad"] - out["quad"]) / np.abs(out["quad"])
+    assert rel.max() < TOL[False], rel.max()
