@@ -100,6 +100,10 @@ struct FinalizeArgs {
 // lane (launch_step only; the slot kernels have four per lane).
 int choose_tile(int m, bool fp64, int requested, bool three = false);
 int pad_columns(int m, int mt);
+// The tile of a plan for an n-row matrix with nnz entries (launch_step
+// widths: 4 columns per lane, or 3 for FP32 widths 3 * 2^j): the one whose
+// padding, CSR passes and gathers move the fewest bytes per step.
+int choose_plan_tile(int m, bool fp64, int64_t n, int64_t nnz);
 
 // [normalize pass,] step kernel, then (if the matrix has long rows) the long-row kernel
 hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s);

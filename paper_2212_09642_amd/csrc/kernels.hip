@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "kernels.h"
 
@@ -654,6 +655,30 @@ int choose_tile(int m, bool fp64, int requested, bool three) {
 }
 
 int pad_columns(int m, int mt) { return ((m + mt - 1) / mt) * mt; }
+
+int choose_plan_tile(int m, bool fp64, int64_t n, int64_t nnz) {
+    // Bytes of one step by a simple model: six streams of the padded block,
+    // and per column tile the CSR (8 B per entry) and one gather per entry
+    // of at least a 128-byte line.  The cheapest tile wins (ties: the wider).
+    const int es = fp64 ? 8 : 4, cpl = fp64 ? 2 : 4;
+    std::vector<int> cands;
+    for (int t = cpl * 4; t <= (fp64 ? 64 : 128); t *= 2) cands.push_back(t);
+    if (!fp64) {
+        for (int t = 12; t <= 96; t *= 2) cands.push_back(t);
+        if (m == 192) cands.push_back(192);
+    }
+    int best = 0;
+    double best_cost = 0.0;
+    for (int t : cands) {
+        const int mp = pad_columns(m, t), tiles = mp / t;
+        const double cost = 6.0 * (double)n * mp * es + (double)tiles * (double)nnz * (8.0 + std::max(t * es, 128));
+        if (best == 0 || cost < best_cost || (cost == best_cost && t > best)) {
+            best = t;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
 
 template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
 static void launch_step_k(const StepArgs &a, hipStream_t s) {

@@ -297,7 +297,9 @@ vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool sto
     p->m = m;
     p->k = k;
     p->store = store;
-    p->mt = choose_tile(m, fp64, env_int("VNE_TILE", 0), env_int("VNE_TILE3", 1) != 0);
+    const int forced = env_int("VNE_TILE", 0);
+    p->mt = forced > 0 || env_int("VNE_TILE3", 1) == 0 ? choose_tile(m, fp64, forced)
+                                                       : choose_plan_tile(m, fp64, set->n, set->nnz);
     p->m_pad = pad_columns(m, p->mt);
     const size_t es = fp64 ? 8 : 4;
     // sizes far beyond any device (and beyond size_t arithmetic) fail here
