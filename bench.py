@@ -291,7 +291,12 @@ def run_serve(args):
     for rate in [float(r) for r in args.rates.split(",")]:
         rng = np.random.Generator(np.random.PCG64(workloads.GRAPH_SEED_SERVE + int(rate)))
         gaps = rng.exponential(1.0 / rate, args.queries)
-        picks = rng.integers(0, len(pool), args.queries)
+        if args.zipf > 0:
+            # skewed popularity: graph i (pool order) drawn with weight 1 / (i + 1)^s
+            w = 1.0 / np.arange(1, len(pool) + 1) ** args.zipf
+            picks = rng.choice(len(pool), size=args.queries, p=w / w.sum())
+        else:
+            picks = rng.integers(0, len(pool), args.queries)
         tickets = []
         t0 = time.perf_counter()
         due = t0
@@ -333,7 +338,7 @@ def run_serve(args):
         "warmup": len(pool), "ms_per_step": round(1e3 / max(best["completed_per_s"], 1e-9), 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve_pool%d_er_ba_ws_n1e3_2e6_eps1e-3_f32" % len(pool), "graphs": len(pool),
-                   "rel_eps": eps, "rates": args.rates, "queries_per_rate": args.queries,
+                   "rel_eps": eps, "rates": args.rates, "queries_per_rate": args.queries, "zipf": args.zipf,
                    "graph_seed": workloads.GRAPH_SEED_SERVE},
         "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"], "rates": rows,
         "roofline": None, "cpu_baseline": None,
@@ -461,6 +466,8 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=96.0, help="serve workload: server arena (GiB)")
     ap.add_argument("--max-slots", type=int, default=64, help="serve workload: tasks running at once")
     ap.add_argument("--max-cols", type=int, default=256, help="serve workload: probe columns per task")
+    ap.add_argument("--zipf", type=float, default=0.0,
+                    help="serve workload: Zipf exponent of graph popularity (0: uniform)")
     ap.add_argument("--graph", default="ws", help="probing-eps workload: ws (small-world) or ring (lattice)")
     ap.add_argument("--rel-eps", type=float, default=1e-3, help="probing-eps workload: relative target")
     ap.add_argument("--copy-calibration", action="store_true",
