@@ -359,6 +359,14 @@ vne_status vne_enable_kernel_timing(vne_ctx *ctx, int32_t enable);
 vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, double *total_ms,
                              double *algorithmic_bytes);
 
+/* Diagnostics: the column tile (columns per work block of the Lanczos step
+ * kernels) and the padded block width m_pad of the Lanczos run of the last
+ * estimate on ctx (for Hutch++, its quadratic-form block; 0, 0 before any
+ * estimate).  The tile comes from a byte model of the step (plan creation)
+ * or the autotuner (batches; VNE_AUTOTUNE=0 keeps the model's tile),
+ * VNE_TILE forces one. */
+vne_status vne_last_plan(const vne_ctx *ctx, int32_t *tile, int32_t *m_pad);
+
 /* ----------------------------------------------------------------------------
  * Serving loop (continuous batching).
  *

@@ -11,11 +11,12 @@
 * Probing vectors v_l = sum of e_i over the nodes of colour l (eq. (3.1)).
 * Implicit desingularization (Remark 4.6): c = b - (1^T b / n) 1.
 
-Pinned by: statistical properties of the Rademacher block (mean, second
-moment, independence of neighbouring counters), one-hot structure of the
-probing block and c being orthogonal to 1 (tests).  The exact bit stream is
-pinned only against the HIP implementation (same published definition),
-which is a bitwise GPU test.
+Pinned by: the published SplitMix64 known-answer sequence
+(tests/golden/splitmix64_kat.txt, outputs of the generator started from a
+fixed state), which fixes the mixer bit for bit; statistical properties of
+the Rademacher block (mean, second moment, independence of neighbouring
+counters), one-hot structure of the probing block and c being orthogonal
+to 1 (tests).
 """
 import numpy as np
 

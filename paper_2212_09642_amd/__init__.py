@@ -37,7 +37,7 @@ EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_c
            "vne_entropy_estimate_batch", "vne_enable_kernel_timing", "vne_kernel_timing",
            "vne_server_start", "vne_server_submit", "vne_server_poll", "vne_server_stats",
            "vne_server_stop", "vne_plan_steps", "vne_plan_probes", "vne_error_bounds",
-           "vne_entropy_estimate_adaptive", "vne_entropy_probing", "vne_probing_select"]
+           "vne_entropy_estimate_adaptive", "vne_entropy_probing", "vne_probing_select", "vne_last_plan"]
 
 
 class VneError(RuntimeError):
@@ -188,6 +188,8 @@ def lib():
         L.vne_enable_kernel_timing.argtypes = [vp, i32]
         L.vne_kernel_timing.restype = i32
         L.vne_kernel_timing.argtypes = [vp, i32, P(i64), P(dbl), P(dbl)]
+        L.vne_last_plan.restype = i32
+        L.vne_last_plan.argtypes = [vp, P(i32), P(i32)]
         _LIB = L
     return _LIB
 
@@ -384,8 +386,7 @@ class Context:
         alpha = np.zeros((m, k)) if want_coeffs else None
         beta = np.zeros((m, k)) if want_coeffs else None
         res = _Result(0.0, _ptr(quad), _ptr(alpha), _ptr(beta), _ptr(kef), _ptr(nrm))
-        self._chk(self._L.vne_entropy_estimate(self._h, gid, ctypes.byref(pr), k, mode,
-                                               ctypes.byref(res)))
+        self._chk(self._L.vne_entropy_estimate(self._h, gid, ctypes.byref(pr), k, mode, ctypes.byref(res)))
         return dict(estimate=res.estimate, quad=quad, alpha=alpha, beta=beta, k_eff=kef, norm2=nrm)
 
     def estimate_batch(self, queries, mode, want_coeffs=False):
@@ -506,6 +507,12 @@ class Context:
         self._chk(self._L.vne_kernel_timing(self._h, 1 if reset else 0, ctypes.byref(n),
                                             ctypes.byref(ms), ctypes.byref(by)))
         return dict(launches=n.value, total_ms=ms.value, bytes=by.value)
+
+    def last_plan(self):
+        """Column tile and padded width of the last estimate's Lanczos run."""
+        t, mp = ctypes.c_int32(), ctypes.c_int32()
+        self._chk(self._L.vne_last_plan(self._h, ctypes.byref(t), ctypes.byref(mp)))
+        return dict(tile=t.value, m_pad=mp.value)
 
 
 def probing_select(T, eps_hat, n, lambda_ub, d_max, use_bound=False):

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -120,6 +121,7 @@ struct vne_ctx {
     };
     std::vector<Pending> pending;        // timed step loops not yet collected
     std::map<std::string, int> tuned;    // autotuner: set signature -> column tile
+    int32_t last_tile = 0, last_m_pad = 0;   // column tile and padded width of the last run
     std::string tune_file;
     // serialises the registry (register, release, estimates) against the
     // worker thread of a server running on this context
@@ -151,6 +153,11 @@ Graph *get_graph(vne_ctx *c, int32_t gid);
 vne_status get_set(vne_ctx *c, const std::vector<int32_t> &ids, GraphSet **out);
 // buffers of an m-column, k-step problem on a set (cached per shape and tag)
 vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool store, int tag, Plan **out);
+// tile and padded width of a plan (no buffers), and the list of its device
+// buffers with their sizes in a fixed order
+vne_status plan_shape(vne_ctx *c, const GraphSet *set, Plan *p, int m, int k, bool fp64, bool store);
+void plan_buffers(const GraphSet *set, Plan *p, const std::function<void(DevBuf *, size_t)> &take);
+void free_graph(vne_ctx *c, Graph *g);
 
 // Probe description for run_lanczos.
 struct ProbeSpec {
@@ -173,6 +180,7 @@ struct RunOpts {
     bool adaptive = false;
     double lam_lo = 0.0, lam_hi = 0.0;
     int n_grid = kBoundGrid;
+    bool direct = false;               // launch every step directly (no captured graph)
 };
 
 // Probe block, Lanczos steps, quadrature; leaves psi, coefficients, k_eff and

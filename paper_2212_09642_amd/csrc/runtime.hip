@@ -283,15 +283,8 @@ vne_status get_set(vne_ctx *c, const std::vector<int32_t> &ids, GraphSet **out) 
     return VNE_OK;
 }
 
-// Workspace for probe blocks of width m (per graph) and k steps on a set.
-vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool store, int tag, Plan **out) {
-    auto key = std::make_tuple(m, k, (int)fp64, (int)store, tag);
-    auto it = set->plans.find(key);
-    if (it != set->plans.end()) {
-        *out = it->second.get();
-        return VNE_OK;
-    }
-    auto p = std::make_unique<Plan>();
+// Shape of a plan (tile, padded width) for m columns per graph and k steps.
+vne_status plan_shape(vne_ctx *c, const GraphSet *set, Plan *p, int m, int k, bool fp64, bool store) {
     p->fp64 = fp64;
     p->G = set->G;
     p->m = m;
@@ -306,40 +299,59 @@ vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool sto
     if ((double)set->n * p->m_pad * es * (store ? k : 1) > 0x1p56)
         return fail(c, VNE_ENOMEM, "probe block of " + std::to_string(m) + " columns on " +
                                        std::to_string(set->n) + " rows exceeds any device memory");
+    return VNE_OK;
+}
+
+// Every device buffer of a shaped plan, in a fixed order: take(buffer, bytes).
+void plan_buffers(const GraphSet *set, Plan *p, const std::function<void(DevBuf *, size_t)> &take) {
+    const size_t es = p->fp64 ? 8 : 4;
     const size_t blk = (size_t)set->n * p->m_pad * es;
     const Schedule &s = set->sched;
     const size_t cols = (size_t)p->G * p->m_pad;      // (graph, column) pairs
-    vne_status st = VNE_OK;
-    auto A = [&](DevBuf *b, size_t bytes) {
-        if (st == VNE_OK) st = dev_alloc(c, b, bytes);
-    };
-    A(&p->P[0], blk);
-    A(&p->P[1], blk);
-    if (store) {
-        A(&p->Vstore, blk * (size_t)k);
+    const size_t k = (size_t)p->k;
+    take(&p->P[0], blk);
+    take(&p->P[1], blk);
+    if (p->store) {
+        take(&p->Vstore, blk * k);
     } else {
-        A(&p->V[0], blk);
-        A(&p->V[1], blk);
+        take(&p->V[0], blk);
+        take(&p->V[1], blk);
     }
-    A(&p->alpha, cols * k * 8);
-    A(&p->beta, cols * k * 8);
-    A(&p->st_alpha, cols * 8);
-    A(&p->st_inv, cols * 8);
-    A(&p->st_coup, cols * 8);
-    A(&p->k_eff, cols * 4);
-    A(&p->norm2, cols * 8);
-    A(&p->mean, cols * 8);
-    A(&p->psi, cols * 8);
-    A(&p->estimate, (size_t)p->G * 8);
-    A(&p->flags, 4);
-    A(&p->partials, (size_t)s.n_blocks() * 3 * p->m_pad * 8);
-    A(&p->level2, (size_t)kLevel2 * 3 * p->m_pad * 8);
-    A(&p->probe_part, (size_t)set->probe_blocks * p->m_pad * 8);
-    A(&p->seg_acc, (size_t)std::max(1, s.n_seg) * p->m_pad * 8);
-    A(&p->long_part, (size_t)std::max(1, s.n_long) * 3 * p->m_pad * 8);
-    A(&p->graph_k, (size_t)p->G * 4);
-    A(&p->graph_m, (size_t)p->G * 4);
-    A(&p->seeds, (size_t)p->G * 8);
+    take(&p->alpha, cols * k * 8);
+    take(&p->beta, cols * k * 8);
+    take(&p->st_alpha, cols * 8);
+    take(&p->st_inv, cols * 8);
+    take(&p->st_coup, cols * 8);
+    take(&p->k_eff, cols * 4);
+    take(&p->norm2, cols * 8);
+    take(&p->mean, cols * 8);
+    take(&p->psi, cols * 8);
+    take(&p->estimate, (size_t)p->G * 8);
+    take(&p->flags, 4);
+    take(&p->partials, (size_t)s.n_blocks() * 3 * p->m_pad * 8);
+    take(&p->level2, (size_t)kLevel2 * 3 * p->m_pad * 8);
+    take(&p->probe_part, (size_t)set->probe_blocks * p->m_pad * 8);
+    take(&p->seg_acc, (size_t)std::max(1, s.n_seg) * p->m_pad * 8);
+    take(&p->long_part, (size_t)std::max(1, s.n_long) * 3 * p->m_pad * 8);
+    take(&p->graph_k, (size_t)p->G * 4);
+    take(&p->graph_m, (size_t)p->G * 4);
+    take(&p->seeds, (size_t)p->G * 8);
+}
+
+// Workspace for probe blocks of width m (per graph) and k steps on a set.
+vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool store, int tag, Plan **out) {
+    auto key = std::make_tuple(m, k, (int)fp64, (int)store, tag);
+    auto it = set->plans.find(key);
+    if (it != set->plans.end()) {
+        *out = it->second.get();
+        return VNE_OK;
+    }
+    auto p = std::make_unique<Plan>();
+    VNE_TRY(plan_shape(c, set, p.get(), m, k, fp64, store));
+    vne_status st = VNE_OK;
+    plan_buffers(set, p.get(), [&](DevBuf *b, size_t bytes) {
+        if (st == VNE_OK) st = dev_alloc(c, b, bytes);
+    });
     if (st != VNE_OK) {
         free_plan(c, p.get());
         return st;
@@ -371,6 +383,10 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
                        const RunOpts &opt) {
     const Schedule &s = set->sched;
     const int mt = opt.tile > 0 ? opt.tile : p->mt;
+    if (opt.steps < 0) {                 // not an autotuner trial
+        c->last_tile = mt;
+        c->last_m_pad = p->m_pad;
+    }
     HIP_TRY(c, hipMemsetAsync(p->flags.p, 0, 4, c->stream));
     // per-graph steps, widths and seeds: uploaded only when they change (a
     // copy from pageable memory waits for the stream, which would expose the
@@ -492,7 +508,7 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
 
     const bool tuning = opt.steps > 0;
     const int nsteps = tuning ? std::min(opt.steps, p->k) : p->k;
-    const bool use_graph = env_int("VNE_GRAPH", 1) != 0 && !tuning;
+    const bool use_graph = env_int("VNE_GRAPH", 1) != 0 && !tuning && !opt.direct;
     const bool timing = c->timing && opt.collect;
     // part 0: the step kernels of step j; part 1: its reduction and finalize
     auto issue = [&](int j, int part) -> vne_status {
@@ -843,10 +859,10 @@ vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int
                                   (const double *)sk->norm2.p, k, (int32_t)n, nr, q->B.p, m, s));
     // 2. G block, raw +-1 in the columns after the sketch
     if (nh > 0) HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)n, nh, m, nr, nr, pr->seed, keys, s));
-    // 3. Q = orth(Y) by CholeskyQR (FP64 Gram and triangular factors), in
-    // place; a second pass in FP64 mode (with FP32 storage the rounding of Q
-    // itself bounds its orthogonality, so one pass suffices)
-    for (int pass = 0; pass < (fp64 ? 2 : 1); ++pass) {
+    // 3. Q = orth(Y) by CholeskyQR2 (FP64 Gram and triangular factors, two
+    // passes, in place): the first pass leaves an orthogonality error of
+    // about u cond(Y)^2, the second brings it to the rounding of Q's storage
+    for (int pass = 0; pass < 2; ++pass) {
         HIP_TRY(c, launch_gram(q->B.p, m, q->B.p, m, fp64, (int32_t)n, nr, nr, (double *)q->gram_part.p,
                                (double *)q->gram.p, s));
         HIP_TRY(c, launch_cholinv((double *)q->gram.p, (double *)q->rinv.p, nr, (int32_t *)sk->flags.p, s));
@@ -1140,7 +1156,15 @@ extern "C" vne_status vne_graph_register(vne_ctx *c, const vne_csr *csr, uint32_
     g->sched = build_schedule(g->h_row_ptr.data(), n, seg_len, cpb, max_blocks);
     g->alive = true;
     c->graphs.push_back(std::move(g));
-    *graph_id = (int32_t)c->graphs.size() - 1;
+    const int32_t gid = (int32_t)c->graphs.size() - 1;
+    // the device arrays of the graph alone (values, keys, work schedule) are
+    // built here, so that later estimates on it allocate only workspaces
+    GraphSet *set = nullptr;
+    if ((st = get_set(c, {gid}, &set)) != VNE_OK) {
+        free_graph(c, c->graphs[gid].get());
+        return st;
+    }
+    *graph_id = gid;
     return VNE_OK;
 }
 
@@ -1204,6 +1228,14 @@ extern "C" vne_status vne_entropy_estimate(vne_ctx *c, int32_t gid, const vne_pr
         return fail(c, VNE_EINVAL, "VNE_MODE_DESING needs a matrix whose rows sum to zero (A 1 = 0)");
     if (pr->kind == VNE_PROBE_HUTCHPP) return estimate_hutchpp(c, set, pr, k, fp64, desing, out);
     return estimate_set(c, set, pr, &k, fp64, desing, out);
+}
+
+extern "C" vne_status vne_last_plan(const vne_ctx *c, int32_t *tile, int32_t *m_pad) {
+    if (!c || !tile || !m_pad) return VNE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lock(const_cast<vne_ctx *>(c)->mu);
+    *tile = c->last_tile;
+    *m_pad = c->last_m_pad;
+    return VNE_OK;
 }
 
 extern "C" vne_status vne_error_bounds(vne_ctx *c, int32_t m, int32_t k, const double *alpha, const double *beta,

@@ -9,7 +9,7 @@ import pytest
 import oracle
 import synth
 import paper_2212_09642_amd as vne
-from gpu_common import TOL, ctx, _say, _rel, _order_sensitivity, _check_quad  # noqa: F401
+from gpu_common import TOL, ctx, _say, _rel, _order_sensitivity, _check_quad, _bar, _assert_within  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -57,8 +57,7 @@ def test_batch_rademacher_vs_oracle_and_solo(ctx, fp64):
         assert abs(out["estimate"] - out["quad"].mean()) <= 1e-13 * abs(out["estimate"])
         solo = ctx.estimate(gid, vne.PROBE_RADEMACHER, m, k, mode, seed=100 + i)
         assert np.array_equal(solo["k_eff"], out["k_eff"])
-        tol = max(TOL[fp64], 20 * float(np.max(sens)))
-        assert np.all(_rel(out["quad"], solo["quad"]) < tol)
+        _assert_within(_rel(out["quad"], solo["quad"]), _bar(fp64, sens), "batch vs solo")
         # the first steps agree closely (before any loss of orthogonality)
         j = min(k, 4)
         live = out["k_eff"] >= j
@@ -135,11 +134,15 @@ def test_batch_tile_choice_within_tolerance(ctx, monkeypatch):
             B = oracle.rademacher_block(7 + i, ref.node_ids, np.arange(64))
             sens = _order_sensitivity(ref.scipy(), B, 12, False)
             assert np.array_equal(a["k_eff"], b["k_eff"])
-            assert np.all(_rel(a["quad"], b["quad"]) < max(TOL[False], 20 * float(np.max(sens))))
+            _assert_within(_rel(a["quad"], b["quad"]), _bar(False, sens), "tile %s vs autotuned" % tile)
 
 
-def test_batch_errors_and_release(ctx):
+def test_batch_errors_and_release(ctx, monkeypatch):
     _say("case batch error paths and release")
+    # one column tile for every set: a graph's work blocks and per-graph sums
+    # do not depend on the other graphs of the batch, so its results are
+    # bitwise the same in any batch that runs the same tile
+    monkeypatch.setenv("VNE_TILE", "16")
     regs = _register_all(ctx, _graphs()[:3], False)
     ids = [r[1] for r in regs]
     q = [dict(gid=g, kind=vne.PROBE_RADEMACHER, m=4, k=5, seed=1) for g in ids]
@@ -165,5 +168,6 @@ def test_batch_errors_and_release(ctx):
         ctx.estimate_batch(q, vne.MODE_DESING)
     after = ctx.estimate_batch(q[1:], vne.MODE_DESING)
     for a, b in zip(before[1:], after):
-        assert np.array_equal(a["k_eff"], b["k_eff"])
-        assert np.all(_rel(a["quad"], b["quad"]) < 1e-4)
+        for key in ("quad", "k_eff", "norm2"):
+            assert np.array_equal(a[key], b[key]), key
+        assert a["estimate"] == b["estimate"]

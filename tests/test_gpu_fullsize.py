@@ -1,12 +1,14 @@
 """Parity at the benchmark sizes, in the benchmark's launch configuration,
 on sampled outputs the oracle computes one by one.
 
-* large: BA n = 2e5 (3 edges per node), FP32, k = 60.  The 256-wide
-  Rademacher block runs through the same step kernels and column tile as the
-  bench's quadratic-form phase; columns 0, 77, 200, 255 are checked against
-  the oracle.  The Hutch++ estimate of the bench is checked against that
-  Hutchinson estimate on the same probes (both unbiased for S; the difference
-  must stay within five standard errors of the Hutchinson mean).
+* large: BA n = 2e5 (3 edges per node), FP32, k = 60.  The bench's own
+  Hutch++ estimate (128 sketch + 128 Hutchinson columns) against the
+  oracle's Hutch++ on the same probes, read from tests/golden/
+  hutchpp_large.json (written by tests/golden/make_hutchpp_large.py, which
+  calls only the oracle): the estimate, the sum of the Q forms and every
+  G~ form.  The 256-wide Rademacher block through the same step kernels:
+  columns 0, 77, 200, 255 against the oracle, and the Hutch++ estimate
+  within five standard errors of that Hutchinson estimate.
 * probing: WS n = 1e6 (k = 10, p = 0.1), distance-2 colouring, k = 80:
   colours 0, 11 and the last one against the oracle; the colouring itself is
   compared bit for bit with the oracle elsewhere (CPU, slow).
@@ -14,8 +16,9 @@ on sampled outputs the oracle computes one by one.
   (smallest, largest, one ER, one BA), four columns each.
 * the probing configuration without rewiring (ring lattice): the whole
   estimate against the exact entropy, within Corollary 3.2's bound.
-Bars: 1e-5 relative per quadratic form, widened to 20x the oracle's own
-rounding-order sensitivity (same problem, rows reversed) where that is larger.
+Bars: 1e-5 relative per quadratic form, per column widened to 5x that
+column's own rounding-order spread (the oracle in four row orders) where
+that is larger.
 """
 import numpy as np
 import pytest
@@ -23,23 +26,19 @@ import pytest
 import oracle
 from synth import workloads
 import paper_2212_09642_amd as vne
-from gpu_common import TOL, ctx, _say, _rel  # noqa: F401
+from gpu_common import TOL, ctx, _say, _rel, _orders, _spread, _bar, _assert_within  # noqa: F401
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
 def _sampled_check(A, keys, B, out_quad, cols, k, desing=True):
-    want = oracle.quadforms(A, B, k, oracle.breakdown_tau(False), desing)["psi"]
-    n = A.shape[0]
-    P = np.arange(n)[::-1]
     import scipy.sparse as sp
-    Ap = sp.csr_matrix(A)[P][:, P]
-    alt = oracle.quadforms(Ap, np.asarray(B)[P], k, oracle.breakdown_tau(False), desing)["psi"]
-    sens = _rel(alt, want)
-    rel = _rel(out_quad[cols], want)
-    bar = max(TOL[False], 20 * float(sens.max()))
-    _say("   sampled columns %s: max rel err %.2e (bar %.1e)" % (list(cols), rel.max(), bar))
-    assert np.all(rel < bar), rel
+    A = sp.csr_matrix(A)
+    B = np.asarray(B)
+    tau = oracle.breakdown_tau(False)
+    want = oracle.quadforms(A, B, k, tau, desing)["psi"]
+    runs = [want] + [oracle.quadforms(A[P][:, P], B[P], k, tau, desing)["psi"] for P in _orders(A.shape[0])]
+    _assert_within(_rel(out_quad[cols], want), _bar(False, _spread(runs, want)), "sampled columns %s" % list(cols))
 
 
 def test_large_configuration_sampled(ctx):
@@ -60,6 +59,42 @@ def test_large_configuration_sampled(ctx):
     se = out["quad"].std(ddof=1) / np.sqrt(m)
     _say("   Hutch++ %.8f, Hutchinson %.8f +- %.1e" % (hpp["estimate"], out["estimate"], se))
     assert abs(hpp["estimate"] - out["estimate"]) < 5 * se
+
+
+def test_large_hutchpp_against_oracle(ctx):
+    """The bench's configuration itself: Hutch++ on BA n = 2e5 with 128 + 128
+    Rademacher columns and 60 steps, FP32 vectors (eq. (3.9) with f(A) Omega
+    by eq. (4.3)), against the oracle's Hutch++ on the same probes."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hutchpp_large.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    w = workloads.large()
+    _say("case full size: Hutch++ BA n=2e5, 128 + 128, k=60 against the oracle")
+    g = vne.laplacian_from_edges(w["n_nodes"], w["edges"], np.float32)
+    assert (g["n"], len(g["col_idx"])) == (gold["n"], gold["nnz"])
+    nr, m = w["n_sketch"], w["n_sketch"] + w["n_hutch"]
+    assert (nr, m, w["k"], w["probe_seed"]) == (gold["n_sketch"], gold["n_sketch"] + gold["n_hutch"], gold["k"],
+                                                gold["probe_seed"])
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    out = ctx.estimate(gid, vne.PROBE_HUTCHPP, m, w["k"], vne.MODE_DESING, seed=w["probe_seed"], n_sketch=nr,
+                       want_coeffs=False)
+    psi = np.array(gold["psi"])
+    sens_psi = np.array(gold["psi_spread"]) / np.abs(psi)
+    est = gold["estimate"]
+    _say("   estimate %.12f, oracle %.12f (spread %.1e), oracle |Q^T Q - I| %.1e"
+         % (out["estimate"], est, gold["estimate_spread"], gold["q_orthogonality"]))
+    _assert_within(abs(out["estimate"] - est) / abs(est), _bar(False, gold["estimate_spread"] / abs(est)),
+                   "estimate")
+    sq = gold["sum_q"]
+    _assert_within(abs(out["quad"][:nr].sum() - sq) / abs(sq), _bar(False, gold["sum_q_spread"] / abs(sq)),
+                   "sum over Q")
+    _assert_within(_rel(out["quad"][nr:], psi[nr:]), _bar(False, sens_psi[nr:]), "G~ forms")
+    rq = _rel(out["quad"][:nr], psi[:nr])
+    _say("   Q forms one by one (FP32 sketch; not asserted): max rel err %.3e" % rq.max())
+    assert np.array_equal(out["k_eff"], np.array(gold["k_eff"]))
+    ctx.release(gid)
 
 
 def test_probing_configuration_sampled(ctx):

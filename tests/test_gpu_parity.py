@@ -14,7 +14,8 @@ import paper_2212_09642_amd as vne
 
 pytestmark = pytest.mark.gpu
 
-from gpu_common import TOL, ctx, _say, _setup, _rel, _order_sensitivity, _check_quad  # noqa: F401
+from gpu_common import (TOL, ctx, _say, _setup, _rel, _order_sensitivity, _check_quad, _bar,  # noqa: F401
+                        _assert_within, _hutchpp_oracle, _check_hutchpp, _model_tile)
 
 
 @pytest.mark.parametrize("fp64", [True, False])
@@ -87,16 +88,27 @@ def test_hub_rows_use_segments(ctx, fp64):
 
 
 @pytest.mark.parametrize("m,k", [(1, 1), (1, 7), (37, 3), (257, 5), (64, 50)])
-def test_ragged_shapes(ctx, m, k):
+def test_ragged_shapes(ctx, m, k, monkeypatch):
+    """Ragged widths with the autotuner off, so that the byte model's tile
+    runs (padded three-column tiles for FP32 m = 1, 37, 257) and the test
+    asserts which one did."""
     _say("case ragged m=%d k=%d" % (m, k))
+    monkeypatch.setenv("VNE_AUTOTUNE", "0")
     n, e = synth.watts_strogatz(1237, 6, 0.2, 9)
-    for fp64 in (True, False):
-        gid, ref = _setup(ctx, n, e, fp64)
-        mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
-        out = ctx.estimate(gid, vne.PROBE_RADEMACHER, m, k, mode, seed=21)
-        B = oracle.rademacher_block(21, ref.node_ids, np.arange(m))
-        want = oracle.quadforms(ref.scipy(), B, k, oracle.breakdown_tau(fp64))
-        _check_quad(out, want, fp64, n=ref.n)
+    with vne.Context(0) as c:
+        for fp64 in (True, False):
+            gid, ref = _setup(c, n, e, fp64)
+            mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+            out = c.estimate(gid, vne.PROBE_RADEMACHER, m, k, mode, seed=21)
+            plan = c.last_plan()
+            tile = _model_tile(m, fp64, ref.n, ref.nnz)
+            _say("   fp64=%s tile %d, m_pad %d" % (fp64, plan["tile"], plan["m_pad"]))
+            assert plan == dict(tile=tile, m_pad=-(-m // tile) * tile)
+            if not fp64 and m in (1, 37, 257):
+                assert tile % 3 == 0 and plan["m_pad"] > m      # a padded three-column tile ran
+            B = oracle.rademacher_block(21, ref.node_ids, np.arange(m))
+            want = oracle.quadforms(ref.scipy(), B, k, oracle.breakdown_tau(fp64))
+            _check_quad(out, want, fp64, n=ref.n)
 
 
 def test_coloring_probes(ctx):
@@ -151,25 +163,8 @@ def test_hutchpp_small(ctx, fp64):
     out = ctx.estimate(gid, vne.PROBE_HUTCHPP, nr + nh, k, mode, seed=13, n_sketch=nr)
     Om = oracle.rademacher_block(13, ref.node_ids, np.arange(nr))
     G = oracle.rademacher_block(13, ref.node_ids, np.arange(nr, nr + nh))
-    est, det = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(fp64))
-    # oracle against itself in reversed node order: rounding-order sensitivity
-    import scipy.sparse as sp
-    P = np.arange(ref.n)[::-1]
-    Ap = sp.csr_matrix(ref.scipy())[P][:, P]
-    est_p, det_p = oracle.hutchpp(Ap, Om[P], G[P], k, oracle.breakdown_tau(fp64))
-    sens_g = _rel(det_p["psi"][nr:], det["psi"][nr:])
-    sens_q = abs(det_p["psi"][:nr].sum() - det["psi"][:nr].sum()) / abs(det["psi"][:nr].sum())
-    sens_e = abs(est_p - est) / abs(est)
-    bar = TOL[fp64]
-    err_e = abs(out["estimate"] - est) / abs(est)
-    err_g = _rel(out["quad"][nr:], det["psi"][nr:])
-    err_q = abs(out["quad"][:nr].sum() - det["psi"][:nr].sum()) / abs(det["psi"][:nr].sum())
-    _say("   estimate rel err %.3e (sens %.1e); G~ max %.3e (sens %.1e); sum over Q %.3e (sens %.1e)"
-         % (err_e, sens_e, err_g.max(), sens_g.max(), err_q, sens_q))
-    # G~ forms depend only on span(Q); Q's own forms only on the columns up to sign
-    assert err_e < max(bar, 20 * sens_e)
-    assert np.all(err_g < max(bar, 20 * float(sens_g.max())))
-    assert err_q < max(bar, 20 * sens_q)
+    est, det, sens = _hutchpp_oracle(ref.scipy(), Om, G, k, fp64)
+    _check_hutchpp(out, est, det, sens, nr, fp64)
 
 
 def test_error_paths(ctx):
@@ -282,17 +277,8 @@ def test_hutchpp_wide_g_block(ctx):
     out = ctx.estimate(gid, vne.PROBE_HUTCHPP, nr + nh, k, vne.MODE_DESING, seed=19, n_sketch=nr)
     Om = oracle.rademacher_block(19, ref.node_ids, np.arange(nr))
     G = oracle.rademacher_block(19, ref.node_ids, np.arange(nr, nr + nh))
-    est, det = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(False))
-    import scipy.sparse as sp
-    P = np.arange(ref.n)[::-1]
-    Ap = sp.csr_matrix(ref.scipy())[P][:, P]
-    est_p, det_p = oracle.hutchpp(Ap, Om[P], G[P], k, oracle.breakdown_tau(False))
-    sens_g = _rel(det_p["psi"][nr:], det["psi"][nr:])
-    err_g = _rel(out["quad"][nr:], det["psi"][nr:])
-    err_e = abs(out["estimate"] - est) / abs(est)
-    _say("   estimate rel err %.3e; G~ max %.3e (sens %.1e)" % (err_e, err_g.max(), sens_g.max()))
-    assert np.all(err_g < max(TOL[False], 20 * float(sens_g.max())))
-    assert err_e < max(TOL[False], 20 * abs(est_p - est) / abs(est))
+    est, det, sens = _hutchpp_oracle(ref.scipy(), Om, G, k, False)
+    _check_hutchpp(out, est, det, sens, nr, False)
 
 
 @pytest.mark.parametrize("fp64", [True, False])
@@ -337,18 +323,13 @@ def test_hutchpp_changing_sketch_width(ctx):
     gid, ref = _setup(ctx, n, e, True)
     m, k = 128, 20
     mode = vne.MODE_DESING | vne.MODE_F64
-    import scipy.sparse as sp
-    P = np.arange(ref.n)[::-1]
-    Ap = sp.csr_matrix(ref.scipy())[P][:, P]
     for nr in (8, 96, 8):
         out = ctx.estimate(gid, vne.PROBE_HUTCHPP, m, k, mode, seed=5, n_sketch=nr, want_coeffs=False)
         Om = oracle.rademacher_block(5, ref.node_ids, np.arange(nr))
         G = oracle.rademacher_block(5, ref.node_ids, np.arange(nr, m))
-        est, _ = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(True))
-        est_p, _ = oracle.hutchpp(Ap, Om[P], G[P], k, oracle.breakdown_tau(True))
-        err, sens = abs(out["estimate"] - est) / abs(est), abs(est_p - est) / abs(est)
-        _say("   N_r=%d estimate rel err %.2e (sens %.1e)" % (nr, err, sens))
-        assert err < max(TOL[True], 20 * sens)
+        est, det, sens = _hutchpp_oracle(ref.scipy(), Om, G, k, True)
+        _say("   N_r=%d" % nr)
+        _check_hutchpp(out, est, det, sens, nr, True)
     ctx.release(gid)
 
 
@@ -365,14 +346,8 @@ def test_hutchpp_sketch_width_edges(ctx, nr, nh):
                        n_sketch=nr, want_coeffs=False)
     Om = oracle.rademacher_block(31, ref.node_ids, np.arange(nr))
     G = oracle.rademacher_block(31, ref.node_ids, np.arange(nr, nr + nh))
-    est, det = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(True))
-    import scipy.sparse as sp
-    P = np.arange(ref.n)[::-1]
-    Ap = sp.csr_matrix(ref.scipy())[P][:, P]
-    est_p, _ = oracle.hutchpp(Ap, Om[P], G[P], k, oracle.breakdown_tau(True))
-    err, sens = abs(out["estimate"] - est) / abs(est), abs(est_p - est) / abs(est)
-    _say("   estimate rel err %.2e (sens %.1e)" % (err, sens))
-    assert err < max(TOL[True], 20 * sens)
+    est, det, sens = _hutchpp_oracle(ref.scipy(), Om, G, k, True)
+    _check_hutchpp(out, est, det, sens, nr, True)
     if nh == 0:
         assert abs(out["estimate"] - out["quad"].sum()) <= 1e-13 * abs(out["estimate"])
     ctx.release(gid)
@@ -466,6 +441,26 @@ def test_three_column_tiles(ctx, m, monkeypatch):
     _check_quad(out, want, False, sens=_order_sensitivity(ref.scipy(), B, k, False), n=ref.n)
 
 
+def test_padded_three_column_tile_colouring(monkeypatch):
+    """37 colour indicators (not a width 3 * 2^j) with the autotuner off: the
+    byte model pads them to a three-column tile of 48; every colour's form
+    against the oracle."""
+    _say("case colouring with 37 colours in a padded three-column tile")
+    monkeypatch.setenv("VNE_AUTOTUNE", "0")
+    n, e = synth.watts_strogatz(6000, 8, 0.1, 46)
+    with vne.Context(0) as c:
+        gid, ref = _setup(c, n, e, False)
+        col = (np.arange(ref.n) % 37).astype(np.int32)
+        out = c.estimate(gid, vne.PROBE_COLORING, 37, 30, vne.MODE_DESING, colors=col)
+        plan = c.last_plan()
+    tile = _model_tile(37, False, ref.n, ref.nnz)
+    _say("   tile %d, m_pad %d" % (plan["tile"], plan["m_pad"]))
+    assert tile % 3 == 0 and plan == dict(tile=tile, m_pad=-(-37 // tile) * tile) and plan["m_pad"] > 37
+    P = oracle.indicator_block(col, 37)
+    want = oracle.quadforms(ref.scipy(), P, 30, oracle.breakdown_tau(False))
+    _check_quad(out, want, False, sens=_order_sensitivity(ref.scipy(), P, 30, False), n=ref.n)
+
+
 def test_three_column_tiles_colouring_and_sketch(ctx, monkeypatch):
     """Colour indicators with 24 colours and a Hutch++ sketch of 24 columns in
     three-column tiles, against the oracle; the padded power-of-two tile
@@ -484,14 +479,8 @@ def test_three_column_tiles_colouring_and_sketch(ctx, monkeypatch):
                       want_coeffs=False)
     Om = oracle.rademacher_block(45, ref.node_ids, np.arange(nr))
     G = oracle.rademacher_block(45, ref.node_ids, np.arange(nr, nr + nh))
-    est, _ = oracle.hutchpp(ref.scipy(), Om, G, k, oracle.breakdown_tau(False))
-    import scipy.sparse as sp
-    Pm = np.arange(ref.n)[::-1]
-    Ap = sp.csr_matrix(ref.scipy())[Pm][:, Pm]
-    est_p, _ = oracle.hutchpp(Ap, Om[Pm], G[Pm], k, oracle.breakdown_tau(False))
-    err, sens = abs(hp["estimate"] - est) / abs(est), abs(est_p - est) / abs(est)
-    _say("   Hutch++ estimate rel err %.2e (sens %.1e)" % (err, sens))
-    assert err < max(TOL[False], 20 * sens)
+    est, det, sens = _hutchpp_oracle(ref.scipy(), Om, G, k, False)
+    _check_hutchpp(hp, est, det, sens, nr, False)
     ctx.release(gid)
     # the padded power-of-two tile (VNE_TILE3=0) gives the same forms within the bar
     monkeypatch.setenv("VNE_TILE3", "0")
