@@ -359,6 +359,30 @@ vne_status vne_enable_kernel_timing(vne_ctx *ctx, int32_t enable);
 vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, double *total_ms,
                              double *algorithmic_bytes);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the estimate of
+ * vne_entropy_estimate for RADEMACHER, COLORING or DENSE probes (HUTCHPP:
+ * VNE_ENOTSUP), with the same arguments and results, that calls no
+ * allocating routine.  Its whole workspace (probe and Lanczos blocks,
+ * coefficients, reduction partials, results) is carved from one static
+ * device array of VNE_NOALLOC_SCRATCH_BYTES per GPU, which the library holds
+ * from its first context on that GPU until the process ends; host colour or
+ * dense arrays are staged in it too.  A request whose workspace does not
+ * fit fails with VNE_ENOMEM (the message gives the bytes it needed); about
+ * 16 n m_pad bytes of FP32 vectors (32 for FP64) plus coefficients and
+ * partials, e.g. n = 1e5 rows and 32 probes.  The graph's device arrays are
+ * built by vne_graph_register.  Steps are launched one by one (no captured
+ * graph, no autotuner: the column tile of the byte model, or VNE_TILE) and
+ * results go straight to the caller's host buffers; the call synchronizes
+ * the context's stream.  Every call on a GPU shares that GPU's array and
+ * leaves its contents behind (what must start at zero is cleared by each
+ * call): calls that overlap on one GPU, from different contexts or
+ * processes' threads, race and must be serialized by the caller.  Results
+ * are bitwise those of vne_entropy_estimate with the same column tile. */
+#define VNE_NOALLOC_SCRATCH_BYTES (64ull << 20)
+vne_status vne_entropy_estimate_noalloc(vne_ctx *ctx, int32_t graph_id, const vne_probes *probes,
+                                        int32_t k_steps, uint32_t mode, vne_result *out);
+
 /* Diagnostics: the column tile (columns per work block of the Lanczos step
  * kernels) and the padded block width m_pad of the Lanczos run of the last
  * estimate on ctx (for Hutch++, its quadratic-form block; 0, 0 before any

@@ -37,7 +37,8 @@ EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_c
            "vne_entropy_estimate_batch", "vne_enable_kernel_timing", "vne_kernel_timing",
            "vne_server_start", "vne_server_submit", "vne_server_poll", "vne_server_stats",
            "vne_server_stop", "vne_plan_steps", "vne_plan_probes", "vne_error_bounds",
-           "vne_entropy_estimate_adaptive", "vne_entropy_probing", "vne_probing_select", "vne_last_plan"]
+           "vne_entropy_estimate_adaptive", "vne_entropy_probing", "vne_probing_select", "vne_last_plan",
+           "vne_entropy_estimate_noalloc"]
 
 
 class VneError(RuntimeError):
@@ -188,6 +189,8 @@ def lib():
         L.vne_enable_kernel_timing.argtypes = [vp, i32]
         L.vne_kernel_timing.restype = i32
         L.vne_kernel_timing.argtypes = [vp, i32, P(i64), P(dbl), P(dbl)]
+        L.vne_entropy_estimate_noalloc.restype = i32
+        L.vne_entropy_estimate_noalloc.argtypes = [vp, i32, P(_Probes), i32, ctypes.c_uint32, P(_Result)]
         L.vne_last_plan.restype = i32
         L.vne_last_plan.argtypes = [vp, P(i32), P(i32)]
         _LIB = L
@@ -358,7 +361,7 @@ class Context:
             raise ValueError("dense: shape %s, expected (%d, %d)" % (tuple(dense.shape), n, m))
 
     def estimate(self, gid, kind, m, k, mode, seed=0, n_sketch=0, colors=None, dense=None,
-                 want_coeffs=True):
+                 want_coeffs=True, _entry="vne_entropy_estimate"):
         """One estimate; returns dict(estimate, quad, alpha, beta, k_eff, norm2)."""
         loc = HOST
         keep = []
@@ -386,8 +389,14 @@ class Context:
         alpha = np.zeros((m, k)) if want_coeffs else None
         beta = np.zeros((m, k)) if want_coeffs else None
         res = _Result(0.0, _ptr(quad), _ptr(alpha), _ptr(beta), _ptr(kef), _ptr(nrm))
-        self._chk(self._L.vne_entropy_estimate(self._h, gid, ctypes.byref(pr), k, mode, ctypes.byref(res)))
+        self._chk(getattr(self._L, _entry)(self._h, gid, ctypes.byref(pr), k, mode, ctypes.byref(res)))
         return dict(estimate=res.estimate, quad=quad, alpha=alpha, beta=beta, k_eff=kef, norm2=nrm)
+
+    def estimate_noalloc(self, gid, kind, m, k, mode, seed=0, colors=None, dense=None, want_coeffs=True):
+        """vne_entropy_estimate_noalloc: the estimate of `estimate` with its
+        workspace in the library's static scratch array (no allocation)."""
+        return self.estimate(gid, kind, m, k, mode, seed=seed, colors=colors, dense=dense,
+                             want_coeffs=want_coeffs, _entry="vne_entropy_estimate_noalloc")
 
     def estimate_batch(self, queries, mode, want_coeffs=False):
         """Several queries in one stacked launch per step.  queries: list of

@@ -158,6 +158,9 @@ vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool sto
 vne_status plan_shape(vne_ctx *c, const GraphSet *set, Plan *p, int m, int k, bool fp64, bool store);
 void plan_buffers(const GraphSet *set, Plan *p, const std::function<void(DevBuf *, size_t)> &take);
 void free_graph(vne_ctx *c, Graph *g);
+// device address of the allocation-free estimate's static scratch array on
+// `device` (the current device), resolved once per device
+vne_status noalloc_attach(int device, std::string *err);
 
 // Probe description for run_lanczos.
 struct ProbeSpec {

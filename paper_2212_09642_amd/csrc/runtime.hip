@@ -1021,6 +1021,13 @@ extern "C" vne_status vne_ctx_create(int device, uint64_t hbm_budget_bytes, void
         g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
         return VNE_EDEVICE;
     }
+    {
+        std::string err;
+        if (noalloc_attach(device, &err) != VNE_OK) {
+            g_create_error = err;
+            return VNE_EDEVICE;
+        }
+    }
     auto *c = new vne_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
