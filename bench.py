@@ -105,6 +105,8 @@ def reorder_csr(g, how):
     elif how == "degree":
         deg = np.diff(g["row_ptr"])
         perm = np.argsort(-deg, kind="stable")
+    elif how == "random":
+        perm = np.random.default_rng(12345).permutation(g["n"])
     else:
         raise SystemExit("unknown reorder %s" % how)
     B = A[perm][:, perm].tocsr()
@@ -535,7 +537,7 @@ def main():
     ap.add_argument("--workload", default="large")
     ap.add_argument("--cpu-sample-cols", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--reorder", default=None, help="experiment: relabel rows (rcm | degree)")
+    ap.add_argument("--reorder", default=None, help="experiment: relabel rows (rcm | degree | random)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="batch workload: seconds of oracle work in the CPU baseline sample")
     ap.add_argument("--rates", default="10,50,200,1000,2000", help="serve workload: arrival rates (1/s)")

@@ -71,29 +71,40 @@ __device__ __forceinline__ void store_vec_nt(T *p, const T (&in)[N]) {
     __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
 }
 
-// three FP32 columns per lane (tiles of 3 * 2^j columns): 12-byte runs,
-// as three scalar accesses (no 3-wide vector type: it would be 16 bytes)
+// three FP32 columns per lane (tiles of 3 * 2^j columns): 12-byte runs, one
+// three-dword access each (a 3-wide vector type with 4-byte alignment; the
+// default alignment of a 3-wide vector is 16 bytes)
+typedef float f3v __attribute__((ext_vector_type(3)));
+typedef f3v __attribute__((aligned(4))) f3u;
 template <>
 __device__ __forceinline__ void load_vec<float, 3>(const float *p, float (&out)[3]) {
-    out[0] = p[0];
-    out[1] = p[1];
-    out[2] = p[2];
+    const f3v v = *reinterpret_cast<const f3u *>(p);
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
 }
 template <>
 __device__ __forceinline__ void store_vec<float, 3>(float *p, const float (&in)[3]) {
-    p[0] = in[0];
-    p[1] = in[1];
-    p[2] = in[2];
+    f3v v;
+    v.x = in[0];
+    v.y = in[1];
+    v.z = in[2];
+    *reinterpret_cast<f3u *>(p) = v;
 }
 template <>
 __device__ __forceinline__ void load_vec_nt<float, 3>(const float *p, float (&out)[3]) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) out[k] = __builtin_nontemporal_load(p + k);
+    const f3v v = __builtin_nontemporal_load(reinterpret_cast<const f3u *>(p));
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
 }
 template <>
 __device__ __forceinline__ void store_vec_nt<float, 3>(float *p, const float (&in)[3]) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) __builtin_nontemporal_store(in[k], p + k);
+    f3v v;
+    v.x = in[0];
+    v.y = in[1];
+    v.z = in[2];
+    __builtin_nontemporal_store(v, reinterpret_cast<f3u *>(p));
 }
 
 template <bool NT, typename T, int N>
@@ -120,6 +131,12 @@ constexpr bool kNT = VNE_STREAM_NT != 0;
 #endif
 template <int LPR>
 constexpr int gather_batch() { return VNE_GATHER_U > 0 ? VNE_GATHER_U : (LPR >= 16 ? 16 : 8); }
+
+// slots of a gather batch skipped together when no row of the wave needs
+// them (0: the default of the step core)
+#ifndef VNE_SLOT_RUN
+#define VNE_SLOT_RUN 0
+#endif
 
 // basis steps of k_reconstruct in flight per thread (2 measured faster than 4:
 // at 4 the register count halves the waves per SIMD)
@@ -238,41 +255,99 @@ struct StepCore {
 
     static constexpr int U = gather_batch<LPR>();
 
-    // column indices and weights of entries [p, p + UB) of a row; slots past
-    // p1 point at the row itself with a zero weight
+    // Column indices and weights of a batch of UB entries [p, p + UB) of a
+    // row, held spread over the lane group: lane gl keeps entries
+    // p + gl + r LPR (r < R).  One coalesced load per array and round r
+    // replaces UB same-address loads per lane: the step kernels are bound by
+    // the vector-memory pipeline (address and data paths), in which every
+    // load instruction costs its 64 lanes whatever their addresses.  Slots
+    // past p1 hold the row itself with a zero weight.
     template <int UB>
-    __device__ __forceinline__ void batch_index(int row, int p, int p1, int (&jj)[UB], T (&vv)[UB]) const {
+    struct Idx {
+        static constexpr int R = (UB + LPR - 1) / LPR;
+        int j[R];
+        T v[R];
+    };
+
+    template <int UB>
+    __device__ __forceinline__ void batch_fetch(int row, int p, int p1, Idx<UB> &x) const {
+        const int gl = (int)(threadIdx.x & 63) % LPR;
 #pragma unroll
-        for (int u = 0; u < UB; ++u) {
-            const bool ok = p + u < p1;
-            jj[u] = ok ? a.col[p + u] : row;
-            vv[u] = ok ? val[p + u] : (T)0;
+        for (int r = 0; r < Idx<UB>::R; ++r) {
+            const int s = gl + r * LPR, e = p + s;
+            const bool ok = s < UB && e < p1;
+            x.j[r] = ok ? a.col[e] : row;
+            x.v[r] = ok ? val[e] : (T)0;
         }
     }
 
-    // the gathered entries of v_j (lazy: P_j and v_{j-1}) of a batch
+    // the value of slot u for every lane of the group: from lane u % LPR of
+    // the group, round u / LPR (a wave-wide group reads it as a scalar)
+    template <typename V>
+    static __device__ __forceinline__ V from_lane(V x, int src) {
+        if constexpr (sizeof(V) == 8) {
+            const int64_t b = __builtin_bit_cast(int64_t, x);
+            const int lo = from_lane<int>((int)(b & 0xffffffff), src), hi = from_lane<int>((int)(b >> 32), src);
+            return __builtin_bit_cast(V, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+        } else {
+            const int b = __builtin_bit_cast(int, x);
+            int r;
+            if constexpr (LPR == 64) r = __builtin_amdgcn_readlane(b, src);
+            else r = __builtin_amdgcn_ds_bpermute(4 * (((int)(threadIdx.x & 63) & ~(LPR - 1)) + src), b);
+            return __builtin_bit_cast(V, r);
+        }
+    }
+
     template <int UB>
-    __device__ __forceinline__ void batch_load(const int (&jj)[UB], T (&pv)[UB][CPL], T (&qv)[UB][CPL]) const {
+    __device__ __forceinline__ void batch_spread(const Idx<UB> &x, int (&jj)[UB], T (&vv)[UB]) const {
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
-            if (TWO) {
-                load_vec<T, CPL>(V_cur + (int64_t)jj[u] * ld + c0, pv[u]);
-            } else {
-                load_vec<T, CPL>(P_in + (int64_t)jj[u] * ld + c0, pv[u]);
-                if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)jj[u] * ld + c0, qv[u]);
+            jj[u] = from_lane<int>(x.j[u / LPR], u % LPR);
+            vv[u] = from_lane<T>(x.v[u / LPR], u % LPR);
+        }
+    }
+
+    // Slots of a batch in runs of kSlotRun: a run that no lane group of the
+    // wave needs (every row of the wave has fewer entries left) is neither
+    // loaded nor added (a wave-uniform branch; its slots would have added
+    // val 0 times the row's own entry, exactly nothing).
+    static constexpr int kSlotRun = VNE_SLOT_RUN > 0 ? VNE_SLOT_RUN : (U >= 16 ? 8 : U);
+
+    // the gathered entries of v_j (lazy: P_j and v_{j-1}) of a batch whose
+    // first cnt slots are entries of the row
+    template <int UB>
+    __device__ __forceinline__ void batch_load(const int (&jj)[UB], int cnt, T (&pv)[UB][CPL],
+                                               T (&qv)[UB][CPL]) const {
+#pragma unroll
+        for (int c = 0; c < UB; c += kSlotRun) {
+            if (c == 0 || __any(cnt > c)) {
+#pragma unroll
+                for (int u = c; u < c + kSlotRun && u < UB; ++u) {
+                    if (TWO) {
+                        load_vec<T, CPL>(V_cur + (int64_t)jj[u] * ld + c0, pv[u]);
+                    } else {
+                        load_vec<T, CPL>(P_in + (int64_t)jj[u] * ld + c0, pv[u]);
+                        if (!FIRST) load_vec<T, CPL>(V_prev + (int64_t)jj[u] * ld + c0, qv[u]);
+                    }
+                }
             }
         }
     }
 
     template <int UB>
-    __device__ __forceinline__ void batch_acc(const T (&vv)[UB], const T (&pv)[UB][CPL], const T (&qv)[UB][CPL],
-                                              double (&acc)[CPL]) const {
+    __device__ __forceinline__ void batch_acc(const T (&vv)[UB], int cnt, const T (&pv)[UB][CPL],
+                                              const T (&qv)[UB][CPL], double (&acc)[CPL]) const {
 #pragma unroll
-        for (int u = 0; u < UB; ++u) {
+        for (int c = 0; c < UB; c += kSlotRun) {
+            if (c == 0 || __any(cnt > c)) {
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                const T v = TWO ? pv[u][k] : materialize(pv[u][k], FIRST ? (T)0 : qv[u][k], al[k], inv[k]);
-                acc[k] = fma((double)vv[u], (double)v, acc[k]);
+                for (int u = c; u < c + kSlotRun && u < UB; ++u) {
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) {
+                        const T v = TWO ? pv[u][k] : materialize(pv[u][k], FIRST ? (T)0 : qv[u][k], al[k], inv[k]);
+                        acc[k] = fma((double)vv[u], (double)v, acc[k]);
+                    }
+                }
             }
         }
     }
@@ -282,18 +357,15 @@ struct StepCore {
     template <int UB = U>
     __device__ __forceinline__ void gather_from(int row, int p0, int p1, double (&acc)[CPL]) const {
         for (int p = p0; p < p1; p += UB) {
+            Idx<UB> x;
             int jj[UB];
             T vv[UB], pv[UB][CPL], qv[UB][CPL];
-            batch_index<UB>(row, p, p1, jj, vv);
-            batch_load<UB>(jj, pv, qv);
-            batch_acc<UB>(vv, pv, qv, acc);
+            const int cnt = min(UB, p1 - p);
+            batch_fetch<UB>(row, p, p1, x);
+            batch_spread<UB>(x, jj, vv);
+            batch_load<UB>(jj, cnt, pv, qv);
+            batch_acc<UB>(vv, cnt, pv, qv, acc);
         }
-    }
-
-    __device__ __forceinline__ void gather(int row, int p0, int p1, double (&acc)[CPL]) const {
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
-        gather_from(row, p0, p1, acc);
     }
 
     // the row's own entries: pv = P_j (lazy) or v_j (two-pass), qv = v_{j-1}
@@ -425,25 +497,25 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int b, int tile0,
     Item cur = locate(gid);
     bool cur_skip;
     settle(cur, cur_skip, gid);
-    int jj[U];
-    T vv[U];
-    core.template batch_index<U>(cur.row, cur.p0, cur.p1, jj, vv);
+    typename Core::template Idx<U> ix;
+    core.template batch_fetch<U>(cur.row, cur.p0, cur.p1, ix);
     Item nxt = locate(gid + NG);
     for (int t = gid; t < total; t += NG) {
-        T pv[U][CPL], qv[U][CPL];
-        core.template batch_load<U>(jj, pv, qv);
+        int jj[U];
+        T vv[U], pv[U][CPL], qv[U][CPL];
+        const int cnt = min(U, cur.p1 - cur.p0);
+        core.template batch_spread<U>(ix, jj, vv);
+        core.template batch_load<U>(jj, cnt, pv, qv);
         T sp[CPL], sq[CPL];
         if (!cur.seg) core.load_self(cur.row, sp, sq);
         bool nxt_skip;
         settle(nxt, nxt_skip, t + NG);
-        int njj[U];
-        T nvv[U];
-        core.template batch_index<U>(nxt.row, nxt.p0, nxt.p1, njj, nvv);
+        core.template batch_fetch<U>(nxt.row, nxt.p0, nxt.p1, ix);
         const Item nn = locate(t + 2 * NG);
         double acc[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
-        core.template batch_acc<U>(vv, pv, qv, acc);
+        core.template batch_acc<U>(vv, cnt, pv, qv, acc);
         if (cur.p1 - cur.p0 > U) core.template gather_from<(U > 1 ? U / 2 : 1)>(cur.row, cur.p0 + U, cur.p1, acc);
         if (!cur_skip) {
             if (!cur.seg) {
@@ -465,11 +537,6 @@ __device__ __forceinline__ void step_block(const StepArgs &a, int b, int tile0,
         }
         cur = nxt;
         cur_skip = nxt_skip;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            jj[u] = njj[u];
-            vv[u] = nvv[u];
-        }
         nxt = nn;
     }
 
