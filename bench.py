@@ -455,8 +455,10 @@ def run_probing_eps(args):
     ctx = vne.Context(0, stream=stream)
     gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
 
+    stop = {"bound": vne.STOP_BOUND, "estimate": vne.STOP_ESTIMATE}[args.stop]
+
     def one():
-        return ctx.probing(gid, w["rel_eps"], d_max=16, k_max=128, mode=vne.MODE_DESING)
+        return ctx.probing(gid, w["rel_eps"], d_max=16, k_max=128, mode=vne.MODE_DESING, stop=stop)
 
     for _ in range(args.warmup):
         one()
@@ -482,7 +484,7 @@ def run_probing_eps(args):
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w["name"], "n": n, "nnz": nnz, "rel_eps": w["rel_eps"], "d_max": 16, "k_max": 128,
-                   "graph_seed": w["graph_seed"]},
+                   "graph_seed": w["graph_seed"], "krylov_stop": args.stop},
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
         "estimate": o["estimate"], "d": o["d"], "n_colors": o["n_colors"], "passes": o["passes"],
@@ -550,6 +552,8 @@ def main():
                     help="serve workload: Zipf exponent of graph popularity (0: uniform)")
     ap.add_argument("--graph", default="ws", help="probing-eps workload: ws (small-world) or ring (lattice)")
     ap.add_argument("--rel-eps", type=float, default=1e-3, help="probing-eps workload: relative target")
+    ap.add_argument("--stop", default="bound", choices=("bound", "estimate"),
+                    help="probing-eps workload: Krylov stopping rule (eq. (4.9) bound or eq. (4.10) estimate)")
     ap.add_argument("--no-extras", action="store_true",
                     help="large workload: skip the serve and batch objects of the default line")
     ap.add_argument("--serve-rates", default="20,200",

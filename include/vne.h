@@ -235,22 +235,32 @@ vne_status vne_entropy_estimate_batch(vne_ctx *ctx, int32_t n_queries, const int
                                       uint32_t mode, vne_result *out);
 
 /* Per-vector stopping rule of vne_entropy_estimate_adaptive. */
+enum { VNE_STOP_BOUND = 0, VNE_STOP_ESTIMATE = 1 };
+
 typedef struct {
     const double *tol;          /* host [m]: tolerance of each quadratic form (> 0)        */
     double lam_lo, lam_hi;      /* interval of the Theorem 4.8 bound, 0 < lam_lo < lam_hi  */
     int32_t n_grid;             /* log-spaced points of the interval, 2..65536 (0: 256)    */
+    int32_t stop;               /* VNE_STOP_BOUND: stop when the upper bound hi of the
+                                   bracket (eq. (4.9)) is within tol; VNE_STOP_ESTIMATE:
+                                   when the geometric mean sqrt(lo hi) of the bracket
+                                   (eq. (4.10)) is (no guarantee: Remark 4.11)             */
 } vne_stop_rule;
 
 /* Quadratic forms with an a-posteriori stopping rule (Theorem 4.8, used as
  * in step 3 of Algorithm 2): Lanczos on every probe vector as in
- * vne_entropy_estimate, with the upper bound of the bracket (the one
- * vne_error_bounds returns, on [rule->lam_lo, rule->lam_hi] with
- * rule->n_grid points) evaluated for every running vector after steps 3, 5,
- * 7, ... (at most k_max).  Vector c stops at the first such step s with
- * hi <= rule->tol[c]; its psi is the Gauss quadrature after min(k_eff, s)
- * steps.  A vector that never meets its tolerance ends at k_max.  The block
- * stops when every vector has stopped (the call synchronises its stream
- * after each check to read the running count).  steps_out (host [m], may be
+ * vne_entropy_estimate, with the bracket (the one vne_error_bounds returns,
+ * on [rule->lam_lo, rule->lam_hi] with rule->n_grid points) evaluated for
+ * every running vector after steps 3, 5, 7, ... (at most k_max).  Vector c
+ * stops at the first such step s with hi <= rule->tol[c] (rule->stop =
+ * VNE_STOP_BOUND) or sqrt(lo hi) <= rule->tol[c] (VNE_STOP_ESTIMATE); its
+ * psi is the Gauss quadrature after min(k_eff, s) steps.  A stopped vector
+ * is not computed further: a column tile of the step kernels whose vectors
+ * have all stopped (or broken down) is skipped, and so are groups of
+ * stopped vectors in the normalize pass.  A vector that never meets its
+ * tolerance ends at k_max.  The block stops when every vector has stopped
+ * (the call synchronises its stream after each check to read the running
+ * count).  steps_out (host [m], may be
  * NULL) receives each vector's stop step, or 0 for a vector that never met
  * its tolerance (its psi is the quadrature after k_max steps).  out->alpha /
  * out->beta entries past a vector's stop step are unspecified.  Probe kinds RADEMACHER, COLORING and DENSE on one graph;
@@ -272,6 +282,7 @@ typedef struct {
     uint32_t mode;              /* VNE_MODE_* bits of the Lanczos runs                     */
     double lam_lo_fraction;     /* lower end of the bound interval / lambda_ub (0: 1e-12)  */
     int32_t n_grid;             /* bound grid points (0: 256)                              */
+    int32_t stop;               /* VNE_STOP_BOUND or VNE_STOP_ESTIMATE (vne_stop_rule)     */
 } vne_probing_cfg;
 
 typedef struct {
@@ -307,8 +318,8 @@ typedef struct {
  *     n lambda_ub / (2 (d^2 - 1)) <= eps_hat.
  *  2. a greedy distance-d colouring (Algorithm 1, as vne_color_greedy);
  *  3. psi of each colour indicator v_l with the stopping rule of
- *     vne_entropy_estimate_adaptive, tolerance eps_hat |V_l| / n (eq. (5.3)),
- *     on [lam_lo_fraction lambda_ub, lambda_ub];
+ *     vne_entropy_estimate_adaptive (cfg->stop), tolerance eps_hat |V_l| / n
+ *     (eq. (5.3)), on [lam_lo_fraction lambda_ub, lambda_ub];
  *  4. estimate = sum of psi.
  * A selected d of 1, 2 or 3 reuses that preprocessing pass.  The colourings
  * run on the host; the passes on the context's stream. */

@@ -20,10 +20,12 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   for either kappa, or e_1 = 0 < e_2).  Both T_d differences zero: d = 1.
 * adaptive_quadforms: psi_l ~ v_l^T f(A) v_l by Lanczos and Gauss quadrature
   (eq. (4.2)) stopped, column by column, at the first check step m (m = 3, 5,
-  7, ...) where the upper bound of Theorem 4.8 is within that column's
-  tolerance; a column that never meets it ends at k_max.  The bound is the
-  polynomial-case g_m of eq. (4.8) maximised over a log-spaced grid of
-  [lam_lo, lam_hi] and the Ritz values inside it.
+  7, ...) where the stopping quantity is within that column's tolerance; a
+  column that never meets it ends at k_max.  The quantity is the upper bound
+  of Theorem 4.8, eq. (4.9) (rule="bound"), or the geometric mean of the
+  lower and upper bounds, eq. (4.10) (rule="estimate": a heuristic with no
+  guarantee, Remark 4.11).  The bounds are the polynomial-case g_m of
+  eq. (4.8) over [lam_lo, lam_hi].
 * probing_entropy: Algorithm 2.  Readings where the paper leaves a choice:
   - the rough entropy of Remark 5.1 is S0 = -log tr(A^2) (a lower bound of S
     for a density matrix) while T_1..T_3 are computed, then
@@ -100,9 +102,12 @@ def select_d(T, eps_hat, n, b, d_max):
     return d_max, fits, False, True
 
 
-def adaptive_quadforms(A, B, k_max, tau, tol, lam_lo, lam_hi, grid=256, desing=True):
-    """psi[c] at the first check step whose Theorem 4.8 upper bound is within
-    tol[c]; returns (psi, steps, converged, lanczos result)."""
+def adaptive_quadforms(A, B, k_max, tau, tol, lam_lo, lam_hi, grid=256, desing=True, rule="bound"):
+    """psi[c] at the first check step whose stopping quantity (Theorem 4.8's
+    upper bound, or the eq. (4.10) estimate) is within tol[c]; returns (psi,
+    steps, converged, lanczos result)."""
+    if rule not in ("bound", "estimate"):
+        raise ValueError("rule must be 'bound' or 'estimate'")
     C = desingularize(B) if desing else np.asarray(B, np.float64)
     res = lanczos(A, C, k_max, tau)
     m = C.shape[1]
@@ -112,11 +117,12 @@ def adaptive_quadforms(A, B, k_max, tau, tol, lam_lo, lam_hi, grid=256, desing=T
         for s in range(3, k_max + 1, 2):
             mm = min(int(res["k_eff"][c]), s)
             if mm <= 0 or res["beta"][c, mm - 1] == 0.0:
-                hi = 0.0                       # invariant Krylov space: exact
+                q = 0.0                        # invariant Krylov space: exact
             else:
-                _, hi, _ = posterior_bracket(res["alpha"][c], res["beta"][c], mm, res["norm2"][c],
-                                             lam_lo, lam_hi, grid=grid)
-            if hi <= tol[c]:
+                lo, hi, _ = posterior_bracket(res["alpha"][c], res["beta"][c], mm, res["norm2"][c],
+                                              lam_lo, lam_hi, grid=grid)
+                q = hi if rule == "bound" else np.sqrt(lo * hi)
+            if q <= tol[c]:
                 steps[c] = s
                 converged[c] = True
                 break
@@ -125,21 +131,24 @@ def adaptive_quadforms(A, B, k_max, tau, tol, lam_lo, lam_hi, grid=256, desing=T
     return psi, steps, converged, res
 
 
-def probing_run(A, row_ptr, col_idx, d, eps_hat, k_max, tau, lam_lo, lam_hi, grid=256, desing=True):
+def probing_run(A, row_ptr, col_idx, d, eps_hat, k_max, tau, lam_lo, lam_hi, grid=256, desing=True,
+                rule="bound"):
     """One distance-d probing pass with the tolerances of eq. (5.3)."""
     n = A.shape[0]
     colors, s = greedy_distance_coloring(row_ptr, col_idx, n, d)
     sizes = np.bincount(colors, minlength=s).astype(np.float64)
     tol = eps_hat * sizes / n
     psi, steps, conv, _ = adaptive_quadforms(A, indicator_block(colors, s), k_max, tau, tol, lam_lo, lam_hi,
-                                             grid, desing)
+                                             grid, desing, rule)
     return dict(d=d, colors=colors, n_colors=s, psi=psi, steps=steps, converged=conv, tol=tol,
                 T=float(np.sum(psi)))
 
 
 def probing_entropy(g, eps, d_max=12, k_max=128, tau=None, lam_lo_fraction=1e-12, grid=256,
-                    select="heuristic", desing=True):
-    """Algorithm 2 on a GraphCSR density matrix g (A = g.scipy())."""
+                    select="heuristic", desing=True, stop="bound"):
+    """Algorithm 2 on a GraphCSR density matrix g (A = g.scipy()); stop is the
+    Krylov stopping rule of step 3 ("bound", eq. (4.9); "estimate",
+    eq. (4.10))."""
     from .lanczos import breakdown_tau
     if tau is None:
         tau = breakdown_tau(False)
@@ -153,7 +162,8 @@ def probing_entropy(g, eps, d_max=12, k_max=128, tau=None, lam_lo_fraction=1e-12
     out = dict(s0=s0, lam_hi=lam_hi)
     if select == "heuristic":
         for d in (1, 2, 3):
-            runs[d] = probing_run(A, g.row_ptr, g.col_idx, d, eps_hat0, k_max, tau, lam_lo, lam_hi, grid, desing)
+            runs[d] = probing_run(A, g.row_ptr, g.col_idx, d, eps_hat0, k_max, tau, lam_lo, lam_hi, grid, desing,
+                                  stop)
         T = tuple(runs[d]["T"] for d in (1, 2, 3))
         s_hat = max(s0, *T)
         eps_hat = 0.5 * eps * s_hat
@@ -167,7 +177,7 @@ def probing_entropy(g, eps, d_max=12, k_max=128, tau=None, lam_lo_fraction=1e-12
         raise ValueError("select must be 'heuristic' or 'bound'")
     final = runs.get(d)
     if final is None:
-        final = probing_run(A, g.row_ptr, g.col_idx, d, eps_hat, k_max, tau, lam_lo, lam_hi, grid, desing)
+        final = probing_run(A, g.row_ptr, g.col_idx, d, eps_hat, k_max, tau, lam_lo, lam_hi, grid, desing, stop)
     out.update(estimate=final["T"], d=d, s_hat=s_hat, eps_hat=eps_hat, fallback=fallback, capped=capped,
                final=final, runs=runs)
     return out

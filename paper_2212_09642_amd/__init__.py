@@ -16,7 +16,7 @@ __all__ = ["VneError", "lib", "version", "laplacian_from_edges", "csr_validate",
            "color_greedy", "Context", "F32", "F64", "MODE_F64", "MODE_DESING",
            "PROBE_RADEMACHER", "PROBE_HUTCHPP", "PROBE_COLORING", "PROBE_DENSE",
            "VALIDATE_SYMMETRIC", "VALIDATE_ZERO_ROWSUM", "LIB_PATH", "EXPORTS", "SELECT_HEURISTIC",
-           "SELECT_BOUND", "probing_select"]
+           "SELECT_BOUND", "STOP_BOUND", "STOP_ESTIMATE", "probing_select"]
 
 LIB_PATH = os.environ.get("VNE_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                            "libvne.so")
@@ -26,6 +26,7 @@ HOST, DEVICE = 0, 1
 MODE_F64, MODE_DESING = 1, 2
 PROBE_RADEMACHER, PROBE_HUTCHPP, PROBE_COLORING, PROBE_DENSE = 0, 1, 2, 3
 SELECT_HEURISTIC, SELECT_BOUND = 0, 1
+STOP_BOUND, STOP_ESTIMATE = 0, 1
 VALIDATE_SYMMETRIC, VALIDATE_ZERO_ROWSUM = 1, 2
 STATUS = {0: "VNE_OK", -1: "VNE_EINVAL", -2: "VNE_ENOMEM", -3: "VNE_EDEVICE",
           -4: "VNE_ENOTSUP", -5: "VNE_EBUSY", -6: "VNE_ENUMERIC"}
@@ -69,13 +70,13 @@ class _Result(ctypes.Structure):
 
 class _StopRule(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_void_p), ("lam_lo", ctypes.c_double), ("lam_hi", ctypes.c_double),
-                ("n_grid", ctypes.c_int32)]
+                ("n_grid", ctypes.c_int32), ("stop", ctypes.c_int32)]
 
 
 class _ProbingCfg(ctypes.Structure):
     _fields_ = [("rel_eps", ctypes.c_double), ("select", ctypes.c_int32), ("d_max", ctypes.c_int32),
                 ("k_max", ctypes.c_int32), ("mode", ctypes.c_uint32), ("lam_lo_fraction", ctypes.c_double),
-                ("n_grid", ctypes.c_int32)]
+                ("n_grid", ctypes.c_int32), ("stop", ctypes.c_int32)]
 
 
 class _ProbingResult(ctypes.Structure):
@@ -448,10 +449,11 @@ class Context:
         return lo, hi
 
     def estimate_adaptive(self, gid, kind, m, k_max, mode, tol, lam_lo, lam_hi, n_grid=0, seed=0, colors=None,
-                          dense=None, want_coeffs=False):
+                          dense=None, want_coeffs=False, stop=STOP_BOUND):
         """Quadratic forms stopped per vector on the Theorem 4.8 upper bound
-        (tolerance tol[c]); returns dict(estimate, quad, steps, alpha, beta,
-        k_eff, norm2)."""
+        (stop=STOP_BOUND) or the eq. (4.10) geometric-mean estimate
+        (STOP_ESTIMATE), tolerance tol[c]; returns dict(estimate, quad, steps,
+        alpha, beta, k_eff, norm2)."""
         loc = HOST
         keep = []
         if colors is not None:
@@ -473,7 +475,7 @@ class Context:
         tol = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, np.float64), (m,)))
         self._check_shapes(gid, m, colors, dense)
         pr = _Probes(kind, m, seed, 0, loc, _ptr(colors), _ptr(dense))
-        rule = _StopRule(_ptr(tol), float(lam_lo), float(lam_hi), int(n_grid))
+        rule = _StopRule(_ptr(tol), float(lam_lo), float(lam_hi), int(n_grid), int(stop))
         quad = np.zeros(m)
         steps = np.zeros(m, np.int32)
         kef = np.zeros(m, np.int32)
@@ -486,12 +488,14 @@ class Context:
         return dict(estimate=res.estimate, quad=quad, steps=steps, alpha=alpha, beta=beta, k_eff=kef, norm2=nrm)
 
     def probing(self, gid, rel_eps, select=SELECT_HEURISTIC, d_max=0, k_max=0, mode=MODE_DESING,
-                lam_lo_fraction=0.0, n_grid=0, n=None, quad_cap=0):
+                lam_lo_fraction=0.0, n_grid=0, n=None, quad_cap=0, stop=STOP_BOUND):
         """Algorithm 2 (probing with a relative accuracy target).  With n (the
         matrix size) the final colouring is returned; quad_cap > 0 returns the
-        first quad_cap psi and stop steps of the final pass."""
+        first quad_cap psi and stop steps of the final pass.  stop: the
+        Krylov stopping rule of step 3 (STOP_BOUND, eq. (4.9); STOP_ESTIMATE,
+        eq. (4.10))."""
         cfg = _ProbingCfg(float(rel_eps), int(select), int(d_max), int(k_max), int(mode), float(lam_lo_fraction),
-                          int(n_grid))
+                          int(n_grid), int(stop))
         colors = np.zeros(n, np.int32) if n else None
         quad = np.zeros(quad_cap) if quad_cap > 0 else None
         steps = np.zeros(quad_cap, np.int32) if quad_cap > 0 else None

@@ -183,6 +183,7 @@ struct RunOpts {
     bool adaptive = false;
     double lam_lo = 0.0, lam_hi = 0.0;
     int n_grid = kBoundGrid;
+    bool estimate = false;             // stop on the eq. (4.10) estimate instead of the upper bound
     bool direct = false;               // launch every step directly (no captured graph)
 };
 

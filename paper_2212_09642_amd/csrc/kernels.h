@@ -59,6 +59,11 @@ struct StepArgs {
     const int2 *stop_state;
     int32_t stop_uid;
     int32_t stop_count;
+    // per-column stopping (one graph): col_stop[c] > 0 is the step at which
+    // column c met its tolerance; such a column is done (nullptr: none).  A
+    // work block whose tile holds only done or frozen columns returns at
+    // once, and the normalize pass skips groups of done columns.
+    const int32_t *col_stop;
 };
 
 constexpr int kLevel2 = 32;       // first-level reduction rows of the step partials
@@ -93,6 +98,7 @@ struct FinalizeArgs {
     int32_t stop_count;
     int32_t *flags_hi;                 // slots: flags of columns >= flag_split (nullptr: flags)
     int32_t flag_split;
+    const int32_t *col_stop;           // as in StepArgs: done columns keep their coefficients
 };
 
 // Returns the column tile width the step kernel uses for this probe width;
@@ -222,10 +228,11 @@ hipError_t launch_error_bound_cols(const BoundArgs *args, int32_t m, hipStream_t
 // hi[c] is within tol[c] records `step` in col_stop[c]; *remaining receives
 // the number of columns still running.  One block, any m.
 struct ColStopArgs {
-    const double *hi, *tol;
+    const double *lo, *hi, *tol;
     int32_t *col_stop;
     int32_t m, step;
     int32_t *remaining;
+    int32_t estimate;           // 0: stop on hi <= tol (eq. (4.9)); 1: on sqrt(lo hi) <= tol (eq. (4.10))
 };
 hipError_t launch_column_stop(const ColStopArgs *args, hipStream_t s);
 constexpr int kBoundGrid = 256;            // grid points of the serving loop's checks

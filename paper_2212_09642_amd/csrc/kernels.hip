@@ -411,6 +411,12 @@ __global__ void __launch_bounds__(256) k_normalize(StepArgs a) {
         const int64_t i = t / cg;
         const int c0 = (int)(t % cg) * CPL;
         const int64_t s0 = (a.row_graph ? (int64_t)a.row_graph[i] * a.m_pad : 0) + c0;
+        if (a.col_stop) {
+            bool done = true;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) done = done && a.col_stop[s0 + k] > 0;
+            if (done) continue;
+        }
         T pv[CPL], qv[CPL], v[CPL];
         load_s<kNT, T, CPL>(P + i * a.m_pad + c0, pv);
         if (!FIRST) load_s<kNT, T, CPL>(Vp + i * a.m_pad + c0, qv);
@@ -419,6 +425,18 @@ __global__ void __launch_bounds__(256) k_normalize(StepArgs a) {
             v[k] = materialize(pv[k], FIRST ? (T)0 : qv[k], (T)a.st_alpha[s0 + k], (T)a.st_inv[s0 + k]);
         store_vec<T, CPL>(Vo + i * a.m_pad + c0, v);
     }
+}
+
+// Whether any column of tiles tile0 .. tile0 + ntile - 1 (mt columns each)
+// still runs: not stopped by its a-posteriori rule and not frozen.  The same
+// answer for every thread of the block (a barrier inside).
+__device__ __forceinline__ bool tile_live(const StepArgs &a, int tile0, int ntile, int mt) {
+    bool live = false;
+    for (int t = threadIdx.x; t < ntile * mt; t += blockDim.x) {
+        const int c = tile0 * mt + t;
+        live = live || (c < a.m_pad && a.col_stop[c] == 0 && a.st_inv[c] != 0.0);
+    }
+    return __syncthreads_or(live) != 0;
 }
 
 // One work block b of the schedule, column tiles tile0 .. tile0 + JT - 1:
@@ -562,6 +580,7 @@ __global__ void __launch_bounds__(kStepThreads) VNE_STEP_OCCUPANCY k_lanczos_ste
     // the gathered block of one tile stays resident in the last-level cache;
     // within a tile each XCD takes one contiguous range of row blocks
     // (n_blocks is a multiple of 8)
+    if (a.col_stop && !tile_live(a, blockIdx.y, 1, CPL * LPR)) return;
     step_block<T, CPL, LPR, FIRST, TWO>(a, xcd_remap(blockIdx.x, a.n_blocks), blockIdx.y, red);
 }
 
@@ -691,6 +710,7 @@ __device__ __forceinline__ void long_rows_group(const StepArgs &a, int group, in
 
 template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
 __global__ void __launch_bounds__(256) k_long_rows(StepArgs a) {
+    if (a.col_stop && !tile_live(a, blockIdx.y, 1, CPL * LPR)) return;
     long_rows_group<T, CPL, LPR, FIRST, TWO>(a, blockIdx.x, blockIdx.y);
 }
 
@@ -914,6 +934,7 @@ __global__ void __launch_bounds__(256) k_reduce_partials(FinalizeArgs a) {
 __device__ __forceinline__ void update_coefficients(const FinalizeArgs &a, int g, int c, double svw, double sww,
                                                     double svv) {
     const int64_t gc = (int64_t)g * a.m_pad + c;
+    if (a.col_stop && a.col_stop[gc] > 0) return;      // met its tolerance: done
     const int j = a.step - 1;
     const int kg = a.graph_k ? a.graph_k[g] : a.k;
     const int mg = a.graph_m ? a.graph_m[g] : a.m;
@@ -1886,7 +1907,8 @@ __global__ void __launch_bounds__(256) k_column_stop(const ColStopArgs *args) {
     int run = 0;
     for (int c = threadIdx.x; c < a.m; c += 256) {
         int cs = a.col_stop[c];
-        if (cs == 0 && a.hi[c] <= a.tol[c]) {
+        const double e = a.estimate ? sqrt(a.lo[c] * a.hi[c]) : a.hi[c];
+        if (cs == 0 && e <= a.tol[c]) {
             cs = a.step;
             a.col_stop[c] = cs;
         }

@@ -39,7 +39,7 @@ struct PassOut {
 // One run with per-vector stopping on a set of one graph; tol is host [m].
 // out (may be NULL) receives quad / alpha / beta / k_eff / norm2 when asked.
 vne_status adaptive_run(vne_ctx *c, GraphSet *set, const vne_probes *pr, int k_max, bool fp64, bool desing,
-                        const double *tol, double lam_lo, double lam_hi, int n_grid, vne_result *out,
+                        const double *tol, double lam_lo, double lam_hi, int n_grid, bool estimate, vne_result *out,
                         PassOut *po) {
     const int m = pr->m;
     Plan *p = nullptr;
@@ -58,6 +58,7 @@ vne_status adaptive_run(vne_ctx *c, GraphSet *set, const vne_probes *pr, int k_m
     o.lam_lo = lam_lo;
     o.lam_hi = lam_hi;
     o.n_grid = n_grid;
+    o.estimate = estimate;
     VNE_TRY(run_lanczos(c, set, p, ps, desing, o));
     HIP_TRY(c, launch_combine_graphs((const double *)p->psi.p, p->m_pad, (const int32_t *)p->graph_m.p, 1,
                                      combine_kind, (double *)p->estimate.p, c->stream));
@@ -113,6 +114,8 @@ extern "C" vne_status vne_entropy_estimate_adaptive(vne_ctx *c, int32_t gid, con
     if (n_grid < 2 || n_grid > 65536) return fail(c, VNE_EINVAL, "n_grid must be in [2, 65536]");
     if (!(rule->lam_lo > 0.0) || !(rule->lam_hi > rule->lam_lo) || !std::isfinite(rule->lam_hi))
         return fail(c, VNE_EINVAL, "need 0 < lam_lo < lam_hi");
+    if (rule->stop != VNE_STOP_BOUND && rule->stop != VNE_STOP_ESTIMATE)
+        return fail(c, VNE_EINVAL, "stop must be VNE_STOP_BOUND or VNE_STOP_ESTIMATE");
     for (int j = 0; j < pr->m; ++j)
         if (!(rule->tol[j] >= 0.0) || !std::isfinite(rule->tol[j]))
             return fail(c, VNE_EINVAL, "tolerance " + std::to_string(j) + " is negative or not finite");
@@ -125,7 +128,8 @@ extern "C" vne_status vne_entropy_estimate_adaptive(vne_ctx *c, int32_t gid, con
     if (desing && !set->zero_rowsum)
         return fail(c, VNE_EINVAL, "VNE_MODE_DESING needs a matrix whose rows sum to zero (A 1 = 0)");
     PassOut po;
-    VNE_TRY(adaptive_run(c, set, pr, k_max, fp64, desing, rule->tol, rule->lam_lo, rule->lam_hi, n_grid, out, &po));
+    VNE_TRY(adaptive_run(c, set, pr, k_max, fp64, desing, rule->tol, rule->lam_lo, rule->lam_hi, n_grid,
+                         rule->stop == VNE_STOP_ESTIMATE, out, &po));
     if (steps_out) std::memcpy(steps_out, po.steps.data(), (size_t)pr->m * 4);
     return VNE_OK;
 }
@@ -149,6 +153,8 @@ extern "C" vne_status vne_entropy_probing(vne_ctx *c, int32_t gid, const vne_pro
     if (k_max < 3 || k_max > kMaxSteps) return fail(c, VNE_EINVAL, "k_max must be in [3, 128]");
     if (!(frac > 0.0 && frac < 1.0)) return fail(c, VNE_EINVAL, "lam_lo_fraction must be in (0, 1)");
     if (n_grid < 2 || n_grid > 65536) return fail(c, VNE_EINVAL, "n_grid must be in [2, 65536]");
+    if (cfg->stop != VNE_STOP_BOUND && cfg->stop != VNE_STOP_ESTIMATE)
+        return fail(c, VNE_EINVAL, "stop must be VNE_STOP_BOUND or VNE_STOP_ESTIMATE");
     VNE_TRY(check_mode(c, cfg->mode));
     if (!(std::fabs(g->trace - 1.0) < 1e-9 && g->fro2 > 0.0 && g->fro2 < 1.0))
         return fail(c, VNE_EINVAL, "the probing method with a target needs a unit-trace matrix (a density matrix)");
@@ -195,8 +201,8 @@ extern "C" vne_status vne_entropy_probing(vne_ctx *c, int32_t gid, const vne_pro
         pr.location = VNE_HOST;
         pr.colors = ps->colors.data();
         t0 = Clock::now();
-        VNE_TRY(adaptive_run(c, set, &pr, k_max, fp64, desing, tol.data(), lam_lo, lam_hi, n_grid, nullptr,
-                             &ps->out));
+        VNE_TRY(adaptive_run(c, set, &pr, k_max, fp64, desing, tol.data(), lam_lo, lam_hi, n_grid,
+                             cfg->stop == VNE_STOP_ESTIMATE, nullptr, &ps->out));
         res->lanczos_ms += ms_since(t0);
         res->passes++;
         for (int32_t st : ps->out.steps) res->vector_steps += st > 0 ? st : k_max;

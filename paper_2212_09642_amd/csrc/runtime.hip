@@ -605,6 +605,8 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
             b.flags = (int32_t *)p->flags.p;
             b.col_stop = (const int32_t *)p->col_stop.p;
             ColStopArgs &q = hs[j];
+            q.lo = (const double *)p->bound_lo.p;
+            q.estimate = opt.estimate ? 1 : 0;
             q.hi = (const double *)p->bound_hi.p;
             q.tol = (const double *)p->col_tol.p;
             q.col_stop = (int32_t *)p->col_stop.p;
@@ -614,6 +616,13 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         }
         HIP_TRY(c, hipMemcpyAsync(p->adapt_args.p, p->h_adapt.data(), nb, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipMemsetAsync(p->col_stop.p, 0, (size_t)p->m_pad * 4, c->stream));
+        // done columns: their tiles and normalize groups are skipped, their
+        // coefficients kept (the quadrature takes the stop step's);
+        // VNE_FREEZE=0 keeps computing them (for measurements)
+        if (env_int("VNE_FREEZE", 1) != 0) {
+            a.col_stop = (const int32_t *)p->col_stop.p;
+            f.col_stop = (const int32_t *)p->col_stop.p;
+        }
         struct Chunk {
             int j0, j1;
             bool check;
@@ -641,7 +650,10 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
         int ran = 0;
         for (const Chunk &ch : chunks) {
             if (use_graph && !timing) {
-                hipGraphExec_t &ex = p->chunk_exec[std::make_tuple(key.first, key.second, ch.j0)];
+                // (the captured launches hold the arguments: one graph per
+                // schedule, tile, freezing and first step of the chunk)
+                hipGraphExec_t &ex =
+                    p->chunk_exec[std::make_tuple(key.first | (a.col_stop ? 2 : 0), key.second, ch.j0)];
                 if (!ex) VNE_TRY(capture_fn(&ex, [&]() { return body(ch); }));
                 HIP_TRY(c, hipGraphLaunch(ex, c->stream));
             } else {

@@ -40,36 +40,45 @@ def _gq_at(res, steps):
     return oracle.gauss_quadrature(res["alpha"], res["beta"], k_use, res["norm2"])
 
 
-def _hi(alpha, beta, k_eff, norm2, s, lam_lo, lam_hi):
+def _hi(alpha, beta, k_eff, norm2, s, lam_lo, lam_hi, rule="bound"):
+    """The stopping quantity after s steps: the upper bound of Theorem 4.8
+    (eq. (4.9)) or the geometric mean of the bracket (eq. (4.10))."""
     mm = min(int(k_eff), s)
     if mm <= 0 or beta[mm - 1] == 0.0:
         return 0.0
-    return oracle.bounds.posterior_bracket(alpha, beta, mm, norm2, lam_lo, lam_hi, grid=GRID)[1]
+    lo, hi, _ = oracle.bounds.posterior_bracket(alpha, beta, mm, norm2, lam_lo, lam_hi, grid=GRID)
+    return hi if rule == "bound" else np.sqrt(lo * hi)
 
 
-def _check_adaptive(ctx, gid, ref, B, tol, k_max, fp64, kind, colors=None, seed=0, dense=None):
+RULES = {vne.STOP_BOUND: "bound", vne.STOP_ESTIMATE: "estimate"}
+
+
+def _check_adaptive(ctx, gid, ref, B, tol, k_max, fp64, kind, colors=None, seed=0, dense=None,
+                    stop_rule=vne.STOP_BOUND):
     A = ref.scipy()
     lam_hi = float(np.abs(A).sum(axis=1).max())
     lam_lo = 1e-12 * lam_hi
     mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
     m = B.shape[1]
+    rule = RULES[stop_rule]
     out = ctx.estimate_adaptive(gid, kind, m, k_max, mode, tol, lam_lo, lam_hi, n_grid=GRID, seed=seed,
-                                colors=colors, dense=dense, want_coeffs=True)
+                                colors=colors, dense=dense, want_coeffs=True, stop=stop_rule)
     stop = out["steps"]                          # 0: never met its tolerance
     steps = np.where(stop > 0, stop, k_max)
-    # 1. the decisions, on the GPU's own coefficients
+    # 1. the decisions, on the GPU's own coefficients (up to each column's stop
+    # step: a stopped column is not computed further)
     for c in range(m):
         s_c = int(steps[c])
         for s in range(3, s_c if stop[c] > 0 else k_max + 1, 2):
             assert _hi(out["alpha"][c], out["beta"][c], out["k_eff"][c], out["norm2"][c], s, lam_lo,
-                       lam_hi) > tol[c] * (1 - 1e-9), (c, s, s_c)
+                       lam_hi, rule) > tol[c] * (1 - 1e-9), (c, s, s_c)
         if stop[c] > 0:
             assert s_c >= 3 and s_c % 2 == 1
-            h = _hi(out["alpha"][c], out["beta"][c], out["k_eff"][c], out["norm2"][c], s_c, lam_lo, lam_hi)
+            h = _hi(out["alpha"][c], out["beta"][c], out["k_eff"][c], out["norm2"][c], s_c, lam_lo, lam_hi, rule)
             assert h <= tol[c] * (1 + 1e-9), (c, s_c, h, tol[c])
     # 2. the oracle's decisions on its FP64 coefficients
     psi_o, steps_o, conv_o, res = oprobing.adaptive_quadforms(A, B, k_max, oracle.breakdown_tau(fp64), tol,
-                                                              lam_lo, lam_hi, grid=GRID)
+                                                              lam_lo, lam_hi, grid=GRID, rule=rule)
     Asp = sp.csr_matrix(A)
     others = [oracle.lanczos(Asp[P][:, P], oracle.desingularize(np.asarray(B)[P]), k_max,
                              oracle.breakdown_tau(fp64)) for P in _orders(A.shape[0])]
@@ -78,7 +87,7 @@ def _check_adaptive(ctx, gid, ref, B, tol, k_max, fp64, kind, colors=None, seed=
         # the decision may differ only where the tolerance lies within the
         # bound's own rounding-order spread (oracle, four row orders)
         s0 = int(min(steps[c], steps_o[c]))
-        hs = [_hi(r["alpha"][c], r["beta"][c], r["k_eff"][c], r["norm2"][c], s0, lam_lo, lam_hi)
+        hs = [_hi(r["alpha"][c], r["beta"][c], r["k_eff"][c], r["norm2"][c], s0, lam_lo, lam_hi, rule)
               for r in [res] + others]
         h = hs[0]
         slack = 0.02 if fp64 else 0.25
@@ -112,6 +121,52 @@ def test_adaptive_colour_indicators(ctx, name, mk, fp64):
                           colors=col.astype(np.int32))
     ctx.release(gid)
     assert out["steps"].min() >= 3              # every colour met its tolerance
+
+
+@pytest.mark.parametrize("name,mk", CASES[:2])
+@pytest.mark.parametrize("fp64", [False, True])
+def test_adaptive_estimate_rule(ctx, name, mk, fp64):
+    """The eq. (4.10) stopping rule: the decisions on the device's own
+    coefficients, the oracle's decisions and psi at the device's steps as
+    for the bound; no column stops later than under the bound rule."""
+    _say("case adaptive stopping on the eq. (4.10) estimate, %s fp64=%s" % (name, fp64))
+    gid, ref = _setup(ctx, *mk(), fp64=fp64)
+    col, s = oracle.greedy_distance_coloring(ref.row_ptr, ref.col_idx, ref.n, 2)
+    S0 = -np.log((ref.scipy().data ** 2).sum())
+    tol = 0.5 * 1e-4 * S0 * np.bincount(col, minlength=s) / ref.n
+    B = oracle.indicator_block(col, s)
+    est = _check_adaptive(ctx, gid, ref, B, tol, 60, fp64, vne.PROBE_COLORING, colors=col.astype(np.int32),
+                          stop_rule=vne.STOP_ESTIMATE)
+    bnd = _check_adaptive(ctx, gid, ref, B, tol, 60, fp64, vne.PROBE_COLORING, colors=col.astype(np.int32))
+    assert np.all(est["steps"] <= bnd["steps"]) and est["steps"].min() >= 3
+    _say("   vector steps: estimate %d, bound %d" % (est["steps"].sum(), bnd["steps"].sum()))
+    ctx.release(gid)
+
+
+def test_stopped_columns_are_not_computed_further(ctx, monkeypatch):
+    """Columns that met their tolerance are skipped (their tiles and normalize
+    groups): psi, stop steps and every coefficient up to each column's stop
+    step are bitwise those of a run that keeps computing them (VNE_FREEZE=0)."""
+    _say("case stopped columns frozen vs computed")
+    gid, ref = _setup(ctx, *synth.watts_strogatz(6000, 8, 0.1, 65), fp64=False)
+    col, s = oracle.greedy_distance_coloring(ref.row_ptr, ref.col_idx, ref.n, 3)
+    S0 = -np.log((ref.scipy().data ** 2).sum())
+    tol = 0.5 * 1e-5 * S0 * np.bincount(col, minlength=s) / ref.n
+    tol[::5] *= 1e3                                     # some colours stop long before the others
+    A = ref.scipy()
+    lam_hi = float(np.abs(A).sum(axis=1).max())
+    args = (gid, vne.PROBE_COLORING, s, 80, vne.MODE_DESING, tol, 1e-12 * lam_hi, lam_hi)
+    frozen = ctx.estimate_adaptive(*args, n_grid=GRID, colors=col.astype(np.int32), want_coeffs=True)
+    monkeypatch.setenv("VNE_FREEZE", "0")
+    full = ctx.estimate_adaptive(*args, n_grid=GRID, colors=col.astype(np.int32), want_coeffs=True)
+    assert np.array_equal(frozen["steps"], full["steps"]) and np.array_equal(frozen["quad"], full["quad"])
+    assert frozen["estimate"] == full["estimate"]
+    steps = np.where(frozen["steps"] > 0, frozen["steps"], 80)
+    for c in range(s):
+        assert np.array_equal(frozen["alpha"][c, :steps[c]], full["alpha"][c, :steps[c]])
+        assert np.array_equal(frozen["beta"][c, :steps[c]], full["beta"][c, :steps[c]])
+    _say("   %d colours, stop steps %d..%d" % (s, steps.min(), steps.max()))
+    ctx.release(gid)
 
 
 def test_adaptive_rademacher_and_unreachable_tolerances(ctx):
@@ -210,6 +265,36 @@ def test_algorithm_2_matches_oracle(ctx, name, mk, eps):
         _assert_within(abs(got["estimate"] - want["estimate"]) / abs(want["estimate"]),
                        TOL[False] if same else 1e-4, "estimate")
     assert got["unconverged"] == 0
+    assert err <= eps
+    ctx.release(gid)
+
+
+@pytest.mark.parametrize("name,mk,eps", ALG_CASES[:3])
+def test_algorithm_2_with_the_estimate_rule(ctx, name, mk, eps):
+    """Algorithm 2 with the eq. (4.10) stopping rule against the oracle's
+    with the same rule: the same d and colouring, the final pass's stop
+    steps, psi and the estimate at 1e-5 when the decisions agree; fewer
+    vector steps than with the bound, and the exact entropy within eps S."""
+    _say("case Algorithm 2 with the estimate rule, %s, eps=%g" % (name, eps))
+    gid, ref = _setup(ctx, *mk(), fp64=False)
+    got = ctx.probing(gid, eps, d_max=16, k_max=100, n=ref.n, quad_cap=4096, stop=vne.STOP_ESTIMATE)
+    bnd = ctx.probing(gid, eps, d_max=16, k_max=100)
+    want = oprobing.probing_entropy(ref, eps, d_max=16, k_max=100, stop="estimate")
+    S = _exact_S(ref)
+    err = abs(got["estimate"] - S) / S
+    _say("   d=%d (oracle %d), vector steps %d (bound %d), rel err %.2e"
+         % (got["d"], want["d"], got["vector_steps"], bnd["vector_steps"], err))
+    if got["d"] == want["d"]:
+        fin = want["final"]
+        s = fin["n_colors"]
+        assert np.array_equal(got["colors"], fin["colors"])
+        gsteps = np.where(got["steps"][:s] > 0, got["steps"][:s], 100)
+        same = np.array_equal(got["steps"][:s] > 0, fin["converged"]) and np.array_equal(gsteps, fin["steps"])
+        if same:
+            _assert_within(_rel(got["quad"][:s], fin["psi"]), TOL[False], "final pass psi per colour")
+        _assert_within(abs(got["estimate"] - want["estimate"]) / abs(want["estimate"]),
+                       TOL[False] if same else 1e-4, "estimate")
+    assert got["vector_steps"] <= bnd["vector_steps"]
     assert err <= eps
     ctx.release(gid)
 

@@ -133,3 +133,38 @@ def test_algorithm_2_with_the_bound(kind, g):
     if not out["capped"]:
         assert abs(out["estimate"] - S) <= 1e-2 * S
     assert out["fallback"]
+
+
+@pytest.mark.parametrize("kind,g", _graphs())
+def test_estimate_rule_stops_no_later_and_keeps_the_krylov_budget(kind, g):
+    """eq. (4.10): sqrt(lo hi) <= hi, so every column stops no later than on
+    the upper bound (4.9).  The estimate carries no guarantee (Remark 4.11:
+    with an approximate interval it can underestimate the error); on these
+    graphs, with the interval [1e-12 lambda_ub, lambda_ub], the forms it
+    stops stay within 2x their tolerance and their sum within the Krylov
+    budget eps_hat of eq. (5.4) (measured: 0.47..1.8x per form, sum 0.2..0.7
+    of the budget)."""
+    A = g.scipy()
+    rho = A.toarray()
+    lam_hi = float(np.abs(rho).sum(1).max())
+    col, s = oracle.greedy_distance_coloring(g.row_ptr, g.col_idx, g.n, 2)
+    B = oracle.indicator_block(col, s)
+    S = oracle.exact_entropy(rho)
+    tol = 0.5 * 1e-3 * S * np.bincount(col, minlength=s) / g.n
+    args = (A, B, 80, oracle.breakdown_tau(False), tol, 1e-12 * lam_hi, lam_hi)
+    psi_e, steps_e, conv_e, _ = probing.adaptive_quadforms(*args, grid=256, rule="estimate")
+    psi_b, steps_b, conv_b, _ = probing.adaptive_quadforms(*args, grid=256, rule="bound")
+    assert conv_e.all() and np.all(steps_e <= steps_b)
+    exact = oracle.exact_quadform(rho, B)
+    assert np.all(np.abs(psi_e - exact) <= 2 * tol)
+    assert abs(psi_e.sum() - exact.sum()) <= 0.5 * 1e-3 * S
+
+
+@pytest.mark.parametrize("kind,g", _graphs()[:3])
+def test_algorithm_2_with_the_estimate_rule_meets_the_target(kind, g):
+    """Algorithm 2 with the eq. (4.10) stopping rule (the paper's choice for
+    its large runs) within eps S of the exact entropy on these graphs."""
+    S = oracle.exact_entropy(g.scipy().toarray())
+    for eps in (1e-2, 1e-3):
+        out = probing.probing_entropy(g, eps, d_max=12, k_max=100, stop="estimate")
+        assert abs(out["estimate"] - S) <= eps * S, (kind, eps, out["d"])
