@@ -50,7 +50,8 @@ typedef enum {
     VNE_EDEVICE = -3,   /* a HIP runtime call failed                           */
     VNE_ENOTSUP = -4,   /* valid request outside what this build supports      */
     VNE_EBUSY = -5,     /* resource in use (e.g. releasing a graph in a plan)  */
-    VNE_ENUMERIC = -6   /* NaN or Inf appeared in the Lanczos coefficients     */
+    VNE_ENUMERIC = -6   /* NaN or Inf in a start vector or the coefficients,
+                           or a failed factorisation of the Hutch++ sketch  */
 } vne_status;
 
 enum { VNE_F32 = 0, VNE_F64 = 1 };          /* element type of values / dense blocks */

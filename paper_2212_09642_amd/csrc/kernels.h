@@ -167,6 +167,7 @@ struct ProbeArgs {
     const int32_t *graph_k;            // [G]
     const int32_t *graph_m;            // [G]
     int32_t n_graphs;
+    int32_t *flags;                    // bit 0 set for a start vector whose norm is not finite
 };
 hipError_t launch_probe(const ProbeArgs &a, bool fp64, hipStream_t s);
 

@@ -1230,7 +1230,9 @@ __global__ void __launch_bounds__(256) k_probe_reduce(ProbeArgs a) {
         a.norm2[gc] = sum;
         a.st_alpha[gc] = 0.0;
         a.st_coup[gc] = 0.0;
-        if (sum > 0.0 && c < mg) {
+        // a NaN or Inf in a caller's probe block: reported, the column frozen
+        if (!isfinite(sum) && c < mg && a.flags) atomicOr(a.flags, 1);
+        if (sum > 0.0 && isfinite(sum) && c < mg) {
             a.st_inv[gc] = 1.0 / sqrt(sum);
             a.k_eff[gc] = kg;
         } else {

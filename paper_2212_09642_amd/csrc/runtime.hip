@@ -434,6 +434,7 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
     pa.graph_k = (const int32_t *)p->graph_k.p;
     pa.graph_m = (const int32_t *)p->graph_m.p;
     pa.n_graphs = p->G;
+    pa.flags = (int32_t *)p->flags.p;
     HIP_TRY(c, launch_probe(pa, p->fp64, c->stream));
 
     const size_t es = p->fp64 ? 8 : 4;
@@ -762,7 +763,7 @@ vne_status autotune(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, boo
 
 vne_status check_flags(vne_ctx *c, int32_t fl) {
     if (fl & 2) return fail(c, VNE_ENUMERIC, "Cholesky of the sketch Gram matrix failed (rank-deficient sketch)");
-    if (fl & 1) return fail(c, VNE_ENUMERIC, "non-finite Lanczos coefficient");
+    if (fl & 1) return fail(c, VNE_ENUMERIC, "non-finite start vector or Lanczos coefficient");
     if (fl & 4) return fail(c, VNE_ENUMERIC, "tridiagonal QR did not converge");
     if (fl & 8) return fail(c, VNE_ENUMERIC, "tridiagonal QR rotation record overflowed");
     return VNE_OK;

@@ -201,6 +201,38 @@ def test_error_paths(ctx):
 
 
 @pytest.mark.parametrize("fp64", [True, False])
+def test_numerical_failures_are_reported(ctx, fp64):
+    """A NaN in a dense probe block makes the Lanczos coefficients non-finite
+    and the call fails with VNE_ENUMERIC; a Hutch++ sketch whose Gram matrix
+    is singular (single edge: rho has eigenvalues 0 and 1 and f(1) = 0, so
+    f(A) Omega is exactly zero) fails with VNE_ENUMERIC in its Cholesky
+    factorisation; the context stays usable after both."""
+    _say("case VNE_ENUMERIC: NaN probe, singular sketch Gram, fp64=%s" % fp64)
+    n, e = synth.erdos_renyi(500, 6.0, 51)
+    gid, ref = _setup(ctx, n, e, fp64)
+    mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+    B = np.random.default_rng(2).standard_normal((ref.n, 6))
+    bad = B.copy()
+    bad[17, 3] = np.nan
+    with pytest.raises(vne.VneError) as ei:
+        ctx.estimate(gid, vne.PROBE_DENSE, 6, 12, mode, dense=bad)
+    assert ei.value.status == -6 and "non-finite" in str(ei.value)
+    if not fp64:
+        B = B.astype(np.float32).astype(np.float64)
+    good = ctx.estimate(gid, vne.PROBE_DENSE, 6, 12, mode, dense=B)
+    want = oracle.quadforms(ref.scipy(), B, 12, oracle.breakdown_tau(fp64))
+    _check_quad(good, want, fp64, n=ref.n)
+    g1, _ = _setup(ctx, 2, np.array([[0, 1]]), fp64)
+    with pytest.raises(vne.VneError) as ei:
+        ctx.estimate(g1, vne.PROBE_HUTCHPP, 8, 5, mode, seed=3, n_sketch=4)
+    assert ei.value.status == -6 and "Cholesky" in str(ei.value)
+    again = ctx.estimate(gid, vne.PROBE_DENSE, 6, 12, mode, dense=B)
+    assert np.array_equal(again["quad"], good["quad"])
+    ctx.release(g1)
+    ctx.release(gid)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
 def test_schedules_bitwise_identical(ctx, fp64, monkeypatch):
     # lazy one-pass and normalize + single-stream schedules evaluate every
     # entry of v_j with the same expression and sum in the same order
