@@ -50,3 +50,72 @@ def test_rational_converges_to_exact():
         psi, _ = rational.rational_quadform(rho, c, rational.default_poles(m, 2, lam[1], lam[-1]))
         errs.append(abs(psi - exact) / abs(exact))
     assert errs[-1] < 1e-8 and errs[-1] < errs[0]
+
+
+def test_switch_step_on_geometric_errors():
+    # psi_j = r^j: err_j = r^(j-1) (1 - r), err_j / err_(j-ell) = r^ell, so the
+    # rule fires at the first checked step j = ell + 2 exactly when r >= c
+    # (r = c = 0.75: every power and difference is exact in binary)
+    for r, want in ((0.8, 5), (0.75, 5), (0.7, 0), (0.3, 0)):
+        psi = [r ** j for j in range(1, 30)]
+        assert rational.switch_step(psi, 3, 0.75) == want, r
+    assert rational.switch_step([1.0, 0.5, 0.25], 3, 0.75) == 0          # too short to check
+    # errors 2^-j up to j = 6, then flat: err_7 / err_4 = 1/4 < 0.421875 and
+    # err_8 / err_5 = 1/2 >= 0.421875, so the rule fires at j = 8
+    err = [2.0 ** -j for j in range(2, 7)] + [2.0 ** -6] * 6
+    psi = [1.0]
+    for e in err:
+        psi.append(psi[-1] - e)
+    assert rational.switch_step(psi, 3, 0.75) == 8
+    assert rational.switch_step(psi, 1, 0.9) == 7                        # err_7 / err_6 = 1 >= 0.9
+
+
+def test_stepwise_run_matches_the_one_shot_form():
+    rho, lam, c = _setup()
+    steps = 9
+    poles = rational.default_poles(steps, 3, lam[1], lam[-1])
+    run = rational.rational_run(rho, c, steps, poles=poles)
+    for j in range(1, steps + 1):
+        q, _ = rational.rational_quadform(rho, c, poles[: j - 1])
+        assert abs(run["psi"][j - 1] - q) < 1e-12 * abs(q), j
+    assert run["basis"] == steps and run["poles"] == poles
+
+
+def test_switch_rule_run_on_an_ill_conditioned_path():
+    n, e = synth.path_graph(300)
+    A = oracle.laplacian_from_edges(n, e).scipy().toarray()
+    lam = np.linalg.eigvalsh(A)
+    b = oracle.rademacher_block(5, np.arange(n), np.arange(1))[:, 0]
+    c = oracle.desingularize(b[:, None])[:, 0]
+    exact = float(oracle.exact_quadform(A, c)[0])
+    steps = 24
+    fin = list(-np.geomspace(lam[-1], lam[1], 12))
+    run = rational.rational_run(A, c, steps, finite_poles=fin, ell=3, c=0.75)
+    s = run["switch"]
+    # Lanczos on a path graph stalls early: the rule fires, and it fires at the
+    # step that the rule gives on the run's own forms up to that step
+    assert 5 <= s < steps
+    assert rational.switch_step(run["psi"][:s], 3, 0.75) == s
+    # poles: infinity before the switch, then (from the switch step on) the
+    # finite list in order, then infinity again past its end
+    k = min(len(fin), steps - s)
+    assert run["poles"] == [np.inf] * (s - 1) + fin[:k] + [np.inf] * (steps - s - k)
+    # the same basis rebuilt in one shot from those poles gives the same form
+    q, _ = rational.rational_quadform(A, c, run["poles"])
+    assert abs(q - run["psi"][-1]) < 1e-11 * abs(q)
+    # and the finite poles beat poles at infinity at the same dimension
+    poly, _ = rational.rational_quadform(A, c, [np.inf] * (steps - 1))
+    assert abs(run["psi"][-1] - exact) < 0.1 * abs(poly - exact)
+
+
+def test_invariant_subspace_stops_the_basis():
+    g = oracle.laplacian_from_edges(*synth.path_graph(6))
+    rho = oracle.dense_matrix(g)
+    c = oracle.desingularize(np.arange(6, dtype=np.float64)[:, None] ** 2)[:, 0]
+    exact = float(oracle.exact_quadform(rho, c)[0])
+    run = rational.rational_run(rho, c, 10, poles=[np.inf] * 9)
+    # the centred vector lives in the 5-dimensional range of the Laplacian
+    assert run["basis"] == 5
+    assert all(abs(p - exact) < 1e-12 * abs(exact) for p in run["psi"][4:])
+    zero = rational.rational_run(rho, np.zeros(6), 4, poles=[np.inf] * 3)
+    assert zero["psi"] == [0.0] * 4 and zero["basis"] == 0
