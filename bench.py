@@ -35,7 +35,7 @@ and `estimate_p50_ms` / `estimate_p99_ms` of the line are back-to-back
 large Hutch++ estimates, not served queries.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload large|tiny|probing|batch|serve]
+                       [--workload large|tiny|probing|batch|serve|probing-eps|rational]
 """
 import argparse
 import hashlib
@@ -426,6 +426,100 @@ def run_serve(args):
     print(json.dumps(res), flush=True)
 
 
+def _dense_quadform(g, c):
+    """c^T f(rho) c by a dense eigendecomposition (eq. (2.1) applied to one
+    form; small graphs only)."""
+    import numpy as np
+    import scipy.sparse as sp
+    L = sp.csr_matrix((np.asarray(g["values"], np.float64), g["col_idx"], g["row_ptr"]),
+                      shape=(g["n"], g["n"])).toarray() * g["scale"]
+    lam, U = np.linalg.eigh(L)
+    pr = (U.T @ c) ** 2
+    pos = lam > 0
+    return float(-np.sum(pr[pos] * lam[pos] * np.log(lam[pos]))), lam
+
+
+def run_rational(args):
+    """Rational Krylov cross-check against the Lanczos path at equal error:
+    one desingularised random-sign form on an ill-conditioned path graph
+    (n = 1000) and a 40 x 40 grid, relative error 1e-6 against a dense
+    eigendecomposition.  Lanczos: the smallest k that meets it (one
+    application of A per step).  Rational: poles at infinity, then 12
+    negative poles log-spaced over [-lambda_max, -lambda_2] once the switch
+    rule (ell = 3, c = 0.75) fires; and separately a fixed sequence of 3
+    poles at infinity followed by log-spaced poles over the rest of the
+    basis.  Applications of A = basis vectors + conjugate-gradient
+    iterations of the shifted solves (relative residual 1e-12).  Times are
+    wall-clock per call (median of repeats, results copied to the host)."""
+    import numpy as np
+    import synth
+    import paper_2212_09642_amd as vne
+    tol = 1e-6
+    mode = vne.MODE_F64 | vne.MODE_DESING
+    ctx = vne.Context(0)
+    cases = []
+    for name in ("path1000", "grid40x40"):
+        n0, e = synth.path_graph(1000) if name == "path1000" else synth.grid2d_graph(40, 40)
+        g = vne.laplacian_from_edges(n0, e, np.float64)
+        gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+        n = g["n"]
+        b = np.random.default_rng(3).choice([-1.0, 1.0], size=(n, 1))
+        c = b[:, 0] - b[:, 0].mean()
+        exact, lam = _dense_quadform(g, c)
+        lam = lam[lam > 1e-12 * lam[-1]]
+        pr = dict(dense=b)
+
+        def timed(fn, reps):
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return float(np.median(ts))
+
+        lanczos = None
+        for k in range(1, 129):
+            q = ctx.estimate(gid, vne.PROBE_DENSE, 1, k, mode, want_coeffs=False, **pr)["quad"][0]
+            if abs(q - exact) <= tol * abs(exact):
+                lanczos = k
+                break
+        row = dict(case=name, n=n, kappa=float(lam[-1] / lam[0]), rel_tol=tol)
+        if lanczos is not None:
+            ms = timed(lambda: ctx.estimate(gid, vne.PROBE_DENSE, 1, lanczos, mode, want_coeffs=False, **pr), 20)
+            row["lanczos"] = dict(steps=lanczos, apps=lanczos, ms=ms)
+        else:
+            row["lanczos"] = None
+        fin = list(-np.geomspace(lam[-1], lam[0], 12))
+        sw = dict(finite_poles=fin, ell=3, c=0.75, cg_tol=1e-12)
+        r = ctx.rational(gid, vne.PROBE_DENSE, 1, mode, 48, **sw, **pr)
+        err = np.abs(r["psi_steps"][0] - exact) / abs(exact)
+        ok = np.nonzero(err <= tol)[0]
+        row["switch_rule"] = None
+        if ok.size:
+            j = int(ok[0]) + 1
+            rr = ctx.rational(gid, vne.PROBE_DENSE, 1, mode, j, **sw, **pr)
+            ms = timed(lambda: ctx.rational(gid, vne.PROBE_DENSE, 1, mode, j, **sw, **pr), 5)
+            row["switch_rule"] = dict(steps=j, apps=int(rr["apps_steps"][0, -1]),
+                                      cg_iterations=int(rr["cg_iterations"]),
+                                      switch_step=int(rr["switch_step"][0]), ms=ms)
+        row["fixed_poles"] = None
+        for mm in range(4, 49):
+            poles = [np.inf] * 3 + list(-np.geomspace(lam[-1], lam[0], mm - 4))
+            rr = ctx.rational(gid, vne.PROBE_DENSE, 1, mode, mm, poles=poles, cg_tol=1e-12, **pr)
+            if abs(rr["quad"][0] - exact) <= tol * abs(exact):
+                ms = timed(lambda: ctx.rational(gid, vne.PROBE_DENSE, 1, mode, mm, poles=poles, cg_tol=1e-12,
+                                                **pr), 5)
+                row["fixed_poles"] = dict(steps=mm, apps=int(rr["apps_steps"][0, -1]),
+                                          cg_iterations=int(rr["cg_iterations"]), ms=ms)
+                break
+        cases.append(row)
+        print(json.dumps(row), flush=True)
+    ctx.close()
+    print(json.dumps({"metric": "rational_vs_lanczos_at_equal_error", "unit": "applications of A", "n_gpus": 1,
+                      "dtype": "f64", "data": "synthetic", "higher_is_better": False,
+                      "config": {"workload": "rational_path1000_grid40x40_tol1e-6"}, "cases": cases}), flush=True)
+
+
 def ring_lattice_entropy(n, k):
     """Exact S(rho) of the ring lattice Laplacian (circulant: eigenvalues
     k - 2 sum_{r=1..k/2} cos(2 pi j r / n))."""
@@ -607,6 +701,9 @@ def main():
         return
     if args.workload == "probing-eps":
         run_probing_eps(args)
+        return
+    if args.workload == "rational":
+        run_rational(args)
         return
 
     w, g, spec = build_workload(args.workload, args.reorder)

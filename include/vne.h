@@ -371,6 +371,56 @@ vne_status vne_enable_kernel_timing(vne_ctx *ctx, int32_t enable);
 vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, double *total_ms,
                              double *algorithmic_bytes);
 
+/* Rational Krylov cross-check of the polynomial path (Section 4: the
+ * rational Krylov space q_{m-1}(A)^{-1} K_m(A, b) of eq. (4.1) and the
+ * form psi_m = ||b||^2 e_1^T f(A_m) e_1 of eq. (4.2) with A_m = V_m^T A V_m;
+ * rational Arnoldi with full orthogonalization, Remark 4.2).  FP64 only
+ * (VNE_MODE_F64, else VNE_ENOTSUP); RADEMACHER, COLORING or DENSE probes,
+ * 1 <= m <= 128; start vectors as in vne_entropy_estimate (VNE_MODE_DESING
+ * centres them).  Step j applies A to v_j, adds column j of A_m, evaluates
+ * psi_j, and (j < steps) takes w = A v_j for a pole at infinity or solves
+ * (I - A / xi) w = A v_j for a finite pole xi < 0 (symmetric positive
+ * definite; conjugate gradients on the sparse product until the residual
+ * is within cg_tol of the right-hand side, at most cg_max iterations), then
+ * orthogonalizes w twice against v_1..v_j (v_{j+1} = w / ||w||; a column
+ * whose w vanishes in the orthogonalization, an invariant subspace, stops
+ * growing).  Poles: `poles` [steps - 1] gives the pole of every step
+ * (+INFINITY or < 0) for all columns; with poles == NULL each column starts
+ * with poles at infinity and switches to `finite_poles` (in order; past the
+ * list, infinity again) after the first step j at which the error estimate
+ * err_j = |psi_j - psi_{j-1}| has not dropped by c^ell over the last ell
+ * steps, err_j >= c^ell err_{j-ell} (the switch rule of the Krylov method
+ * implementation of Section 5; the paper's choice is ell = 3, c = 0.75).
+ * Results: psi after the last step, psi after every step, the applications
+ * of A behind each (one per basis vector plus every conjugate-gradient
+ * iteration), the switch step per column and the basis size.  The call
+ * allocates its workspace (steps + 6 blocks of n x m_pad FP64) and frees it
+ * before returning. */
+typedef struct {
+    int32_t steps;              /* basis vectors per column (Krylov dimension), 1..64     */
+    const double *poles;        /* host [steps - 1] or NULL (switch rule)                 */
+    const double *finite_poles; /* switch rule: host [n_finite] negative poles, in order   */
+    int32_t n_finite;
+    int32_t ell;                /* switch rule: window (>= 1)                             */
+    double c;                   /* switch rule: factor, 0 < c < 1                          */
+    double cg_tol;              /* relative residual of a shifted solve (0: 1e-10)        */
+    int32_t cg_max;             /* iteration cap of one solve (0: 20000)                  */
+} vne_rational_cfg;
+
+typedef struct {
+    double *quad;               /* host [m] or NULL: psi after the last step              */
+    double *psi_steps;          /* host [m*steps] or NULL: psi_j at c*steps + j - 1        */
+    int64_t *apps_steps;        /* host [m*steps] or NULL: applications of A behind psi_j  */
+    int32_t *switch_step;       /* host [m] or NULL: step of the switch (0: none)         */
+    int32_t *basis;             /* host [m] or NULL: basis vectors built                  */
+    double *norm2;              /* host [m] or NULL: ||c||^2 of the start vector          */
+    int64_t cg_iterations;      /* out: conjugate-gradient iterations, all columns        */
+    double ms;                  /* out: wall time of the call                             */
+} vne_rational_out;
+
+vne_status vne_rational_quadforms(vne_ctx *ctx, int32_t graph_id, const vne_probes *probes, uint32_t mode,
+                                  const vne_rational_cfg *cfg, vne_rational_out *out);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): the estimate of
  * vne_entropy_estimate for RADEMACHER, COLORING or DENSE probes (HUTCHPP:

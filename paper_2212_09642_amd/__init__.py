@@ -39,7 +39,7 @@ EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_c
            "vne_server_start", "vne_server_submit", "vne_server_poll", "vne_server_stats",
            "vne_server_stop", "vne_plan_steps", "vne_plan_probes", "vne_error_bounds",
            "vne_entropy_estimate_adaptive", "vne_entropy_probing", "vne_probing_select", "vne_last_plan",
-           "vne_entropy_estimate_noalloc"]
+           "vne_entropy_estimate_noalloc", "vne_rational_quadforms"]
 
 
 class VneError(RuntimeError):
@@ -71,6 +71,18 @@ class _Result(ctypes.Structure):
 class _StopRule(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_void_p), ("lam_lo", ctypes.c_double), ("lam_hi", ctypes.c_double),
                 ("n_grid", ctypes.c_int32), ("stop", ctypes.c_int32)]
+
+
+class _RationalCfg(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("poles", ctypes.c_void_p), ("finite_poles", ctypes.c_void_p),
+                ("n_finite", ctypes.c_int32), ("ell", ctypes.c_int32), ("c", ctypes.c_double),
+                ("cg_tol", ctypes.c_double), ("cg_max", ctypes.c_int32)]
+
+
+class _RationalOut(ctypes.Structure):
+    _fields_ = [("quad", ctypes.c_void_p), ("psi_steps", ctypes.c_void_p), ("apps_steps", ctypes.c_void_p),
+                ("switch_step", ctypes.c_void_p), ("basis", ctypes.c_void_p), ("norm2", ctypes.c_void_p),
+                ("cg_iterations", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
 class _ProbingCfg(ctypes.Structure):
@@ -192,6 +204,8 @@ def lib():
         L.vne_kernel_timing.argtypes = [vp, i32, P(i64), P(dbl), P(dbl)]
         L.vne_entropy_estimate_noalloc.restype = i32
         L.vne_entropy_estimate_noalloc.argtypes = [vp, i32, P(_Probes), i32, ctypes.c_uint32, P(_Result)]
+        L.vne_rational_quadforms.restype = i32
+        L.vne_rational_quadforms.argtypes = [vp, i32, P(_Probes), ctypes.c_uint32, P(_RationalCfg), P(_RationalOut)]
         L.vne_last_plan.restype = i32
         L.vne_last_plan.argtypes = [vp, P(i32), P(i32)]
         _LIB = L
@@ -520,6 +534,34 @@ class Context:
         self._chk(self._L.vne_kernel_timing(self._h, 1 if reset else 0, ctypes.byref(n),
                                             ctypes.byref(ms), ctypes.byref(by)))
         return dict(launches=n.value, total_ms=ms.value, bytes=by.value)
+
+    def rational(self, gid, kind, m, mode, steps, poles=None, finite_poles=None, ell=3, c=0.75, cg_tol=0.0,
+                 cg_max=0, seed=0, colors=None, dense=None):
+        """Rational Krylov quadratic forms (vne_rational_quadforms).  poles: the
+        pole of each of the steps - 1 steps (np.inf or < 0) for every column,
+        or None for the switch rule with finite_poles.  Returns dict(quad,
+        psi_steps [m, steps], apps_steps [m, steps], switch_step, basis, norm2,
+        cg_iterations, ms)."""
+        if colors is not None:
+            colors = np.ascontiguousarray(colors, np.int32)
+        if dense is not None:
+            dense = np.ascontiguousarray(dense, np.float64)
+        self._check_shapes(gid, m, colors, dense)
+        pl = None if poles is None else np.ascontiguousarray(poles, np.float64)
+        if pl is not None and pl.size != steps - 1:
+            raise ValueError("poles must have steps - 1 entries")
+        fp = None if finite_poles is None else np.ascontiguousarray(finite_poles, np.float64)
+        cfg = _RationalCfg(int(steps), _ptr(pl), _ptr(fp), 0 if fp is None else int(fp.size), int(ell), float(c),
+                           float(cg_tol), int(cg_max))
+        pr = _Probes(kind, m, seed, 0, HOST, _ptr(colors), _ptr(dense))
+        quad, nrm = np.zeros(m), np.zeros(m)
+        ps, ap = np.zeros((m, steps)), np.zeros((m, steps), np.int64)
+        sw, bs = np.zeros(m, np.int32), np.zeros(m, np.int32)
+        o = _RationalOut(_ptr(quad), _ptr(ps), _ptr(ap), _ptr(sw), _ptr(bs), _ptr(nrm), 0, 0.0)
+        self._chk(self._L.vne_rational_quadforms(self._h, gid, ctypes.byref(pr), mode, ctypes.byref(cfg),
+                                                 ctypes.byref(o)))
+        return dict(quad=quad, psi_steps=ps, apps_steps=ap, switch_step=sw, basis=bs, norm2=nrm,
+                    cg_iterations=o.cg_iterations, ms=o.ms)
 
     def last_plan(self):
         """Column tile and padded width of the last estimate's Lanczos run."""

@@ -18,7 +18,8 @@ PAIRS = {
     "vne_stop_rule": vne._StopRule, "vne_probing_cfg": vne._ProbingCfg,
     "vne_probing_result": vne._ProbingResult, "vne_distance_choice": vne._DistanceChoice,
     "vne_server_cfg": vne._ServerCfg, "vne_query": vne._Query, "vne_query_result": vne._QueryResult,
-    "vne_server_info": vne._ServerInfo,
+    "vne_server_info": vne._ServerInfo, "vne_rational_cfg": vne._RationalCfg,
+    "vne_rational_out": vne._RationalOut,
 }
 
 
