@@ -764,6 +764,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     "traffic_counts": "bytes leaving L2 per step launch (FETCH_SIZE and WRITE_SIZE scaled by "
+                                       "a plain 2 GiB copy); the Infinity Cache serves part of them",
                      "kernel": "k_lanczos_step", "launches": kt["launches"],
                      "avg_launch_ms": round(kt["total_ms"] / max(kt["launches"], 1), 5),
                      "algorithmic_bytes_per_launch": round(kt["bytes"] / max(kt["launches"], 1))},

@@ -5,6 +5,7 @@
     python -m paper_2212_09642_amd.profiling traffic FETCH_DB WRITE_DB COPY_FETCH_DB \
         COPY_WRITE_DB OUT.json --workload NAME --copy-bytes B --cmd "..."
     python -m paper_2212_09642_amd.profiling serve BENCH_LINE.json OUT.md --cmd "..."
+    python -m paper_2212_09642_amd.profiling counters OUT.md --kernel NAME DB [DB ...] --cmd "..."
 
 The Lanczos step unit is the normalize pass (two-pass schedule), the SpMM +
 recurrence kernel and the long-row kernel of one step; its average duration
@@ -132,6 +133,57 @@ def cmd_serve(args):
     print("\n".join(out))
 
 
+def _ratio(tab, num, den, scale=1.0):
+    if num in tab and den in tab and tab[den] > 0:
+        return scale * tab[num] / tab[den]
+    return None
+
+
+def cmd_counters(args):
+    """Per-dispatch averages of the counters of several --pmc runs for the
+    dispatches whose kernel name contains --kernel, and the ratios read from
+    them."""
+    tab = {}
+    for db in args.dbs:
+        acc, calls = _counter(db, (args.kernel,))
+        per = collections.defaultdict(float)
+        cnt = collections.Counter()
+        for (k, ctr), v in acc.items():
+            per[ctr] += v
+            cnt[ctr] += calls[(k, ctr)]
+        for ctr in per:
+            tab[ctr] = per[ctr] / max(cnt[ctr], 1)
+    out = ["# Hardware counters of `%s`" % args.kernel, "", "Commands (one rocprofv3 --pmc pass each):", "", "```"]
+    out += args.cmd
+    out += ["```", "", "| counter | per dispatch |", "|---|---:|"]
+    for ctr in sorted(tab):
+        out.append("| `%s` | %.4g |" % (ctr, tab[ctr]))
+    derived = [
+        ("L2 hit rate, TCC_HIT / (TCC_HIT + TCC_MISS)",
+         _ratio({"h": tab.get("TCC_HIT_sum", 0.0), "t": tab.get("TCC_HIT_sum", 0.0) + tab.get("TCC_MISS_sum", 0.0)},
+                "h", "t")),
+        ("mean L1-to-L2 read latency, cycles", _ratio(tab, "TCP_TCC_READ_REQ_LATENCY_sum", "TCP_TCC_READ_REQ_sum")),
+        ("wave-cycles waiting on a counter (s_waitcnt), SQ_WAIT_ANY / SQ_WAVE_CYCLES",
+         _ratio(tab, "SQ_WAIT_ANY", "SQ_WAVE_CYCLES")),
+        ("wave-cycles issuing, SQ_ACTIVE_INST_ANY / SQ_WAVE_CYCLES", _ratio(tab, "SQ_ACTIVE_INST_ANY", "SQ_WAVE_CYCLES")),
+        ("TA busy per CU over GPU-active cycles (TA_TA_BUSY_sum / 256 CUs, GRBM_GUI_ACTIVE / 8 XCDs)",
+         _ratio({"a": tab.get("TA_TA_BUSY_sum", 0.0) / 256.0, "b": tab.get("GRBM_GUI_ACTIVE", 0.0) / 8.0}, "a", "b")),
+        ("TD cycles stalled on the L1 (TD_TC_STALL_sum / 256 CUs, over GRBM_GUI_ACTIVE / 8 XCDs)",
+         _ratio({"a": tab.get("TD_TC_STALL_sum", 0.0) / 256.0, "b": tab.get("GRBM_GUI_ACTIVE", 0.0) / 8.0}, "a", "b")),
+        ("L1-to-L2 read requests per vector-memory read instruction",
+         _ratio(tab, "TCP_TCC_READ_REQ_sum", "SQ_INSTS_VMEM_RD")),
+        ("L2-to-memory read requests that went to DRAM, TCC_EA0_RDREQ_DRAM / TCC_EA0_RDREQ",
+         _ratio(tab, "TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_RDREQ_sum")),
+    ]
+    out += ["", "| derived | value |", "|---|---:|"]
+    for name, v in derived:
+        if v is not None:
+            out.append("| %s | %.3g |" % (name, v))
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -152,8 +204,13 @@ def main():
     v.add_argument("line")
     v.add_argument("out")
     v.add_argument("--cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("dbs", nargs="+")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--cmd", action="append", required=True)
     args = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic, "serve": cmd_serve}[args.what](args)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "serve": cmd_serve, "counters": cmd_counters}[args.what](args)
 
 
 if __name__ == "__main__":
