@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvne.so")
 
-HOST_SOURCES = ["host_graph.cpp", "coloring.cpp", "serve_host.cpp", "probing_host.cpp"]
+HOST_SOURCES = ["host_graph.cpp", "coloring.cpp", "serve_host.cpp", "serve_core.cpp", "probing_host.cpp"]
 HIP_SOURCES = ["kernels.hip", "runtime.hip", "server.hip", "probing.hip", "noalloc.hip", "rational.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
