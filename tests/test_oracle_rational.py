@@ -1,5 +1,6 @@
 """Pins of the rational Krylov cross-check (eq. (4.1), (4.2), Lemma 4.3)."""
 import numpy as np
+import pytest
 
 import oracle
 import synth
@@ -53,21 +54,21 @@ def test_rational_converges_to_exact():
 
 
 def test_switch_step_on_geometric_errors():
-    # psi_j = r^j: err_j = r^(j-1) (1 - r), err_j / err_(j-ell) = r^ell, so the
-    # rule fires at the first checked step j = ell + 2 exactly when r >= c
-    # (r = c = 0.75: every power and difference is exact in binary)
-    for r, want in ((0.8, 5), (0.75, 5), (0.7, 0), (0.3, 0)):
-        psi = [r ** j for j in range(1, 30)]
-        assert rational.switch_step(psi, 3, 0.75) == want, r
-    assert rational.switch_step([1.0, 0.5, 0.25], 3, 0.75) == 0          # too short to check
-    # errors 2^-j up to j = 6, then flat: err_7 / err_4 = 1/4 < 0.421875 and
-    # err_8 / err_5 = 1/2 >= 0.421875, so the rule fires at j = 8
-    err = [2.0 ** -j for j in range(2, 7)] + [2.0 ** -6] * 6
-    psi = [1.0]
-    for e in err:
-        psi.append(psi[-1] - e)
-    assert rational.switch_step(psi, 3, 0.75) == 8
-    assert rational.switch_step(psi, 1, 0.9) == 7                        # err_7 / err_6 = 1 >= 0.9
+    # err_j = r^j: err_j / err_(j-ell-1) = r^(ell+1), so the rule fires at
+    # the first checked step j = ell + 2 exactly when r^(ell+1) >= c^ell
+    for r, want in ((0.81, 5), (0.8, 0), (0.9, 5), (0.3, 0)):
+        err = [r ** j for j in range(1, 30)]
+        assert rational.switch_step(err, 3, 0.75) == want, r
+    # equality (powers of two, exact in binary): r^(ell+1) = c^ell fires
+    assert rational.switch_step([0.5 ** j for j in range(1, 10)], 1, 0.25) == 3
+    assert rational.switch_step([0.125 ** j for j in range(1, 10)], 3, 0.0625) == 5
+    assert rational.switch_step([1.0, 0.5, 0.25, 0.125], 3, 0.75) == 0          # too short to check
+    # by hand, ell = 3, c^3 = 0.421875: e5/e1 = 0.1, e6/e2 = 0.18, e7/e3 = 0.34,
+    # e8/e4 = 0.48, so the rule fires at j = 8
+    err = [1.0, 0.5, 0.25, 0.125, 0.1, 0.09, 0.085, 0.06, 0.05]
+    assert rational.switch_step(err, 3, 0.75) == 8
+    # ell = 1, c = 0.5: e3/e1 = 0.25, e4/e2 = 0.25, e5/e3 = 0.4, e6/e4 = 0.72
+    assert rational.switch_step(err, 1, 0.5) == 6
 
 
 def test_stepwise_run_matches_the_one_shot_form():
@@ -81,21 +82,32 @@ def test_stepwise_run_matches_the_one_shot_form():
     assert run["basis"] == steps and run["poles"] == poles
 
 
-def test_switch_rule_run_on_an_ill_conditioned_path():
+@pytest.mark.parametrize("estimate", [False, True])
+def test_switch_rule_run_on_an_ill_conditioned_path(estimate):
     n, e = synth.path_graph(300)
     A = oracle.laplacian_from_edges(n, e).scipy().toarray()
     lam = np.linalg.eigvalsh(A)
+    lo, hi = 0.999 * lam[1], 1.001 * lam[-1]
     b = oracle.rademacher_block(5, np.arange(n), np.arange(1))[:, 0]
     c = oracle.desingularize(b[:, None])[:, 0]
     exact = float(oracle.exact_quadform(A, c)[0])
     steps = 24
     fin = list(-np.geomspace(lam[-1], lam[1], 12))
-    run = rational.rational_run(A, c, steps, finite_poles=fin, ell=3, c=0.75)
+    run = rational.rational_run(A, c, steps, finite_poles=fin, ell=3, c=0.75, lam_lo=lo, lam_hi=hi,
+                                estimate=estimate)
     s = run["switch"]
-    # Lanczos on a path graph stalls early: the rule fires, and it fires at the
-    # step that the rule gives on the run's own forms up to that step
-    assert 5 <= s < steps
-    assert rational.switch_step(run["psi"][:s], 3, 0.75) == s
+    # Lanczos on a path graph stalls early: the rule fires, at the step that
+    # the rule gives on the run's own bounds
+    assert 5 <= s < steps and len(run["err"]) == s
+    assert rational.switch_step(run["err"], 3, 0.75) == s
+    # the bounds are Theorem 4.8's (eq. (4.9), or (4.10)) on the Lanczos
+    # coefficients of the same start vector: the polynomial phase spans the
+    # same Krylov spaces
+    res = oracle.lanczos_full_reorth(A, c[:, None], s + 1, oracle.breakdown_tau(True))
+    for j in range(1, s + 1):
+        blo, bhi, best = oracle.bounds.posterior_bracket(res["alpha"][0], res["beta"][0], j, res["norm2"][0], lo, hi)
+        want = best if estimate else bhi
+        assert abs(run["err"][j - 1] - want) <= 1e-6 * want, j
     # poles: infinity before the switch, then (from the switch step on) the
     # finite list in order, then infinity again past its end
     k = min(len(fin), steps - s)
