@@ -446,7 +446,8 @@ def run_rational(args):
     eigendecomposition.  Lanczos: the smallest k that meets it (one
     application of A per step).  Rational: poles at infinity, then 12
     negative poles log-spaced over [-lambda_max, -lambda_2] once the switch
-    rule (ell = 3, c = 0.75) fires; and separately a fixed sequence of 3
+    rule (ell = 3, c = 0.75, on Theorem 4.8's upper bound over [lambda_2,
+    lambda_max]) fires; and separately a fixed sequence of 3
     poles at infinity followed by log-spaced poles over the rest of the
     basis.  Applications of A = basis vectors + conjugate-gradient
     iterations of the shifted solves (relative residual 1e-12).  Times are
@@ -490,7 +491,7 @@ def run_rational(args):
         else:
             row["lanczos"] = None
         fin = list(-np.geomspace(lam[-1], lam[0], 12))
-        sw = dict(finite_poles=fin, ell=3, c=0.75, cg_tol=1e-12)
+        sw = dict(finite_poles=fin, ell=3, c=0.75, cg_tol=1e-12, lam_lo=0.999 * lam[0], lam_hi=1.001 * lam[-1])
         r = ctx.rational(gid, vne.PROBE_DENSE, 1, mode, 48, **sw, **pr)
         err = np.abs(r["psi_steps"][0] - exact) / abs(exact)
         ok = np.nonzero(err <= tol)[0]

@@ -387,10 +387,15 @@ vne_status vne_kernel_timing(vne_ctx *ctx, int32_t reset, int64_t *launches, dou
  * growing).  Poles: `poles` [steps - 1] gives the pole of every step
  * (+INFINITY or < 0) for all columns; with poles == NULL each column starts
  * with poles at infinity and switches to `finite_poles` (in order; past the
- * list, infinity again) after the first step j at which the error estimate
- * err_j = |psi_j - psi_{j-1}| has not dropped by c^ell over the last ell
- * steps, err_j >= c^ell err_{j-ell} (the switch rule of the Krylov method
+ * list, infinity again) after the first step j >= ell + 2 at which its error
+ * bound err_j has not dropped by c^ell since step j - ell - 1,
+ * err_j >= c^ell err_{j-ell-1} (the switch rule of the Krylov method
  * implementation of Section 5; the paper's choice is ell = 3, c = 0.75).
+ * err_j is the a-posteriori upper bound of Theorem 4.8, eq. (4.9), or with
+ * estimate != 0 the geometric mean of eq. (4.10), for the polynomial Krylov
+ * space of step j over [lam_lo, lam_hi] (0 < lam_lo < lam_hi: an interval
+ * that holds the spectrum of A on the Krylov space, e.g. [lambda_2,
+ * lambda_max] for centred vectors of a connected graph's Laplacian).
  * Results: psi after the last step, psi after every step, the applications
  * of A behind each (one per basis vector plus every conjugate-gradient
  * iteration), the switch step per column and the basis size.  The call
@@ -405,6 +410,8 @@ typedef struct {
     double c;                   /* switch rule: factor, 0 < c < 1                          */
     double cg_tol;              /* relative residual of a shifted solve (0: 1e-10)        */
     int32_t cg_max;             /* iteration cap of one solve (0: 20000)                  */
+    double lam_lo, lam_hi;      /* switch rule: interval of the error bound               */
+    int32_t estimate;           /* switch rule: 0 upper bound (4.9), 1 estimate (4.10)    */
 } vne_rational_cfg;
 
 typedef struct {
@@ -414,6 +421,8 @@ typedef struct {
     int32_t *switch_step;       /* host [m] or NULL: step of the switch (0: none)         */
     int32_t *basis;             /* host [m] or NULL: basis vectors built                  */
     double *norm2;              /* host [m] or NULL: ||c||^2 of the start vector          */
+    double *err_steps;          /* host [m*steps] or NULL: switch rule's err_j up to the
+                                   switch (0 after it, and with explicit poles)           */
     int64_t cg_iterations;      /* out: conjugate-gradient iterations, all columns        */
     double ms;                  /* out: wall time of the call                             */
 } vne_rational_out;

@@ -76,13 +76,14 @@ class _StopRule(ctypes.Structure):
 class _RationalCfg(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("poles", ctypes.c_void_p), ("finite_poles", ctypes.c_void_p),
                 ("n_finite", ctypes.c_int32), ("ell", ctypes.c_int32), ("c", ctypes.c_double),
-                ("cg_tol", ctypes.c_double), ("cg_max", ctypes.c_int32)]
+                ("cg_tol", ctypes.c_double), ("cg_max", ctypes.c_int32), ("lam_lo", ctypes.c_double),
+                ("lam_hi", ctypes.c_double), ("estimate", ctypes.c_int32)]
 
 
 class _RationalOut(ctypes.Structure):
     _fields_ = [("quad", ctypes.c_void_p), ("psi_steps", ctypes.c_void_p), ("apps_steps", ctypes.c_void_p),
                 ("switch_step", ctypes.c_void_p), ("basis", ctypes.c_void_p), ("norm2", ctypes.c_void_p),
-                ("cg_iterations", ctypes.c_int64), ("ms", ctypes.c_double)]
+                ("err_steps", ctypes.c_void_p), ("cg_iterations", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
 class _ProbingCfg(ctypes.Structure):
@@ -536,12 +537,13 @@ class Context:
         return dict(launches=n.value, total_ms=ms.value, bytes=by.value)
 
     def rational(self, gid, kind, m, mode, steps, poles=None, finite_poles=None, ell=3, c=0.75, cg_tol=0.0,
-                 cg_max=0, seed=0, colors=None, dense=None):
+                 cg_max=0, seed=0, colors=None, dense=None, lam_lo=0.0, lam_hi=0.0, estimate=False):
         """Rational Krylov quadratic forms (vne_rational_quadforms).  poles: the
         pole of each of the steps - 1 steps (np.inf or < 0) for every column,
-        or None for the switch rule with finite_poles.  Returns dict(quad,
-        psi_steps [m, steps], apps_steps [m, steps], switch_step, basis, norm2,
-        cg_iterations, ms)."""
+        or None for the switch rule with finite_poles (its error bound over
+        [lam_lo, lam_hi]; estimate: eq. (4.10) instead of the upper bound).
+        Returns dict(quad, psi_steps [m, steps], apps_steps [m, steps],
+        err_steps [m, steps], switch_step, basis, norm2, cg_iterations, ms)."""
         if colors is not None:
             colors = np.ascontiguousarray(colors, np.int32)
         if dense is not None:
@@ -552,15 +554,15 @@ class Context:
             raise ValueError("poles must have steps - 1 entries")
         fp = None if finite_poles is None else np.ascontiguousarray(finite_poles, np.float64)
         cfg = _RationalCfg(int(steps), _ptr(pl), _ptr(fp), 0 if fp is None else int(fp.size), int(ell), float(c),
-                           float(cg_tol), int(cg_max))
+                           float(cg_tol), int(cg_max), float(lam_lo), float(lam_hi), 1 if estimate else 0)
         pr = _Probes(kind, m, seed, 0, HOST, _ptr(colors), _ptr(dense))
         quad, nrm = np.zeros(m), np.zeros(m)
-        ps, ap = np.zeros((m, steps)), np.zeros((m, steps), np.int64)
+        ps, ap, es = np.zeros((m, steps)), np.zeros((m, steps), np.int64), np.zeros((m, steps))
         sw, bs = np.zeros(m, np.int32), np.zeros(m, np.int32)
-        o = _RationalOut(_ptr(quad), _ptr(ps), _ptr(ap), _ptr(sw), _ptr(bs), _ptr(nrm), 0, 0.0)
+        o = _RationalOut(_ptr(quad), _ptr(ps), _ptr(ap), _ptr(sw), _ptr(bs), _ptr(nrm), _ptr(es), 0, 0.0)
         self._chk(self._L.vne_rational_quadforms(self._h, gid, ctypes.byref(pr), mode, ctypes.byref(cfg),
                                                  ctypes.byref(o)))
-        return dict(quad=quad, psi_steps=ps, apps_steps=ap, switch_step=sw, basis=bs, norm2=nrm,
+        return dict(quad=quad, psi_steps=ps, apps_steps=ap, err_steps=es, switch_step=sw, basis=bs, norm2=nrm,
                     cg_iterations=o.cg_iterations, ms=o.ms)
 
     def last_plan(self):

@@ -2,7 +2,7 @@
 // rational Krylov space of eq. (4.1), the Rayleigh-Ritz form of eq. (4.2);
 // rational Arnoldi with full orthogonalization, Remark 4.2; the switch from
 // poles at infinity to finite poles of the Krylov method implementation of
-// Section 5).  FP64 blocks of n x mp (probe index fastest, mp a power of two
+// Section 5, on the a-posteriori bound of Theorem 4.8).  FP64 blocks of n x mp (probe index fastest, mp a power of two
 // up to 128), one independent basis per column:
 //   v_1 = c / ||c||;  for j = 1, 2, ...:  u_j = A v_j,
 //   H(1:j, j) = V_j^T u_j,  psi_j = ||c||^2 e_1^T f(H_j) e_1,
@@ -365,24 +365,38 @@ __global__ void __launch_bounds__(256) k_r_grow(const double *ww, const double *
         if (ke[c] == j && ww[c] > 1e-24 * ww0[c] && ww[c] > 0.0) ke[c] = j + 1;
 }
 
-// The switch rule (Section 5, Krylov method implementation): after step j,
-// a column still on poles at infinity switches to finite poles once the
-// error estimate err_j = |psi_j - psi_{j-1}| has not dropped by c^ell over
-// the last ell steps (err_j / err_{j-ell} >= c^ell); it then takes the
-// finite poles in order.  xi[c] is the pole of step j + 1 (0: infinity).
-__global__ void __launch_bounds__(256) k_r_switch(int32_t mp, int32_t m, const double *hist, int32_t kb, int32_t j,
-                                                  int32_t ell, double c_ell, const double *finite, int32_t n_finite,
+// beta_j of the polynomial phase: the norm of A v_j orthogonalized against
+// v_1..v_j (ww), for a column whose basis has j vectors and whose direction
+// passes the invariant-subspace test of k_r_normalize; else 0.  Row c of beta
+// at c * kb, entry j - 1.
+__global__ void __launch_bounds__(256) k_r_beta_next(const double *ww, const double *ww0, const int32_t *ke,
+                                                     int32_t j, int32_t mp, int32_t kb, double *beta) {
+    for (int c = threadIdx.x; c < mp; c += 256) {
+        const bool keep = ke[c] == j && ww[c] > 1e-24 * ww0[c] && ww[c] > 0.0;
+        beta[(int64_t)c * kb + j - 1] = keep ? sqrt(ww[c]) : 0.0;
+    }
+}
+
+// The switch rule (Section 5, Krylov method implementation): after
+// polynomial step j, a column still on poles at infinity records its error
+// bound err_j (Theorem 4.8's upper bound hi, or the estimate sqrt(lo hi) of
+// eq. (4.10)) and switches to finite poles when err_j >= c^ell err_{j-ell-1}
+// (j >= ell + 2); it then takes the finite poles in order.  xi[c] is the
+// pole of step j (0: infinity).
+__global__ void __launch_bounds__(256) k_r_switch(int32_t mp, int32_t m, const double *lo, const double *hi,
+                                                  int32_t estimate, double *errs, int32_t kb, int32_t j, int32_t ell,
+                                                  double c_ell, const double *finite, int32_t n_finite,
                                                   int32_t *switched, double *xi) {
     for (int c = threadIdx.x; c < mp; c += 256) {
         if (c >= m) {
             xi[c] = 0.0;
             continue;
         }
-        const double *h = hist + (int64_t)c * kb;
+        double *e = errs + (int64_t)c * kb;
         int s = switched[c];
-        if (s == 0 && j - ell >= 2) {
-            const double ej = fabs(h[j - 1] - h[j - 2]), e0 = fabs(h[j - ell - 1] - h[j - ell - 2]);
-            if (ej >= c_ell * e0) s = j;
+        if (s == 0) {
+            e[j - 1] = estimate ? sqrt(lo[c] * hi[c]) : hi[c];
+            if (j - ell - 1 >= 1 && e[j - 1] >= c_ell * e[j - ell - 2]) s = j;
         }
         switched[c] = s;
         const int t = s > 0 ? j - s : -1;
@@ -413,6 +427,8 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
     const bool switching = cfg->poles == nullptr;
     if (switching && (cfg->ell < 1 || !(cfg->c > 0.0 && cfg->c < 1.0)))
         return fail(c, VNE_EINVAL, "the switch rule needs ell >= 1 and 0 < c < 1");
+    if (switching && !(cfg->lam_lo > 0.0 && cfg->lam_hi > cfg->lam_lo && std::isfinite(cfg->lam_hi)))
+        return fail(c, VNE_EINVAL, "the switch rule's bound needs 0 < lam_lo < lam_hi");
     const int n_fin = switching ? cfg->n_finite : kb - 1;
     const double *fin = switching ? cfg->finite_poles : cfg->poles;
     if (n_fin < 0 || (n_fin > 0 && !fin)) return fail(c, VNE_EINVAL, "pole list missing");
@@ -436,9 +452,9 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
 
     // device memory of the call: basis, work blocks, small per-column arrays
     DevBuf dV, dU, dW, dX, dR, dP, dQ, dPart, dH, dSmall, dAl, dBe, dKe, dPsi, dHist, dNorm, dMean, dFlags, dInt, dApps,
-        dXi, dFin, dProbePart, dStA, dStI, dStC;
+        dXi, dFin, dProbePart, dStA, dStI, dStC, dErr, dLo, dHi, dBa;
     auto all = {&dV, &dU, &dW, &dX, &dR, &dP, &dQ, &dPart, &dH, &dSmall, &dAl, &dBe, &dKe, &dPsi, &dHist, &dNorm,
-                &dMean, &dFlags, &dInt, &dApps, &dXi, &dFin, &dProbePart, &dStA, &dStI, &dStC};
+                &dMean, &dFlags, &dInt, &dApps, &dXi, &dFin, &dProbePart, &dStA, &dStI, &dStC, &dErr, &dLo, &dHi, &dBa};
     auto fin_all = [&](vne_status st) {
         for (DevBuf *b : all) dev_free(c, b);
         return st;
@@ -473,6 +489,10 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
     A(&dStA, (size_t)mp * 8);
     A(&dStI, (size_t)mp * 8);
     A(&dStC, (size_t)mp * 8);
+    A(&dErr, (size_t)mp * kb * 8);          // error bounds of the polynomial steps (switch rule)
+    A(&dLo, (size_t)mp * 8);
+    A(&dHi, (size_t)mp * 8);
+    A(&dBa, sizeof(BoundArgs) * kb);
     if (st != VNE_OK) return fin_all(st);
     double *V = (double *)dV.p, *U = (double *)dU.p, *W = (double *)dW.p, *X = (double *)dX.p, *R = (double *)dR.p,
            *P = (double *)dP.p, *Q = (double *)dQ.p, *part = (double *)dPart.p, *H = (double *)dH.p;
@@ -493,6 +513,32 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
     R_TRY(hipMemsetAsync(dApps.p, 0, dApps.bytes, s));
     R_TRY(hipMemsetAsync(dHist.p, 0, dHist.bytes, s));
     R_TRY(hipMemsetAsync(dFlags.p, 0, 4, s));
+    R_TRY(hipMemsetAsync(dErr.p, 0, dErr.bytes, s));
+    if (switching) {
+        // the bound of each polynomial step j (steps = j) over the caller's
+        // interval; switched columns are skipped
+        std::vector<BoundArgs> hb(kb);
+        for (int jj = 1; jj <= kb; ++jj) {
+            BoundArgs &b = hb[jj - 1];
+            b.alpha = (const double *)dAl.p;
+            b.beta = (const double *)dBe.p;
+            b.k_eff = (const int32_t *)dKe.p;
+            b.norm2 = (const double *)dNorm.p;
+            b.k = kb;
+            b.m = m;
+            b.steps = jj;
+            b.lam_lo = cfg->lam_lo;
+            b.lam_hi = cfg->lam_hi;
+            b.n_grid = kBoundGrid;
+            b.lo = (double *)dLo.p;
+            b.hi = (double *)dHi.p;
+            b.flags = (int32_t *)dFlags.p;
+            b.col_stop = switched;
+            b.stop_state = nullptr;
+        }
+        R_TRY(hipMemcpyAsync(dBa.p, hb.data(), sizeof(BoundArgs) * kb, hipMemcpyHostToDevice, s));
+        R_TRY(hipStreamSynchronize(s));     // hb leaves scope
+    }
     if (n_fin > 0) R_TRY(hipMemcpyAsync(dFin.p, fin, (size_t)n_fin * 8, hipMemcpyHostToDevice, s));
     // start vectors c = b - mean (desingularized) into V_1 via the probe
     // kernels of the polynomial path (which also give ||c||^2)
@@ -559,7 +605,8 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
     hipLaunchKernelGGL(k_r_init_ke, dim3(1), dim3(256), 0, s, (const double *)dNorm.p, m, mp, ke);
     RMat am{set->d_row_ptr, set->d_col, (const double *)set->val64.p, set->scale, (int32_t)n, mp};
     std::vector<double> h_xi(mp, 0.0);
-    std::vector<int32_t> h_live(mp, 0);
+    std::vector<int32_t> h_live(mp, 0), h_sw(mp, 0);
+    bool all_switched = false;
     int64_t total_cg = 0;
     int steps_done = 0;
     for (int j = 1; j <= kb; ++j) {
@@ -581,13 +628,44 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
         // cumulative applications of A per column: one for u_j
         hipLaunchKernelGGL(k_r_count, dim3(1), dim3(256), 0, s, (const int32_t *)ke, j, mp, apps, apps_hist);
         if (j == kb) break;
+        // w_j orthogonalized twice against v_1..v_j (classical Gram-Schmidt),
+        // with ||w||^2 before (ww0) and after (ww)
+        auto orthogonalize = [&]() {
+            hipLaunchKernelGGL(k_r_dot, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, (const double *)W,
+                               (const double *)W, part);
+            hipLaunchKernelGGL(k_r_reduce, dim3((mp + 255) / 256), dim3(256), 0, s, part, kRBlocks, mp, 1, ww0);
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_r_basis_dots, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, V, j,
+                                   (const double *)W, part);
+                hipLaunchKernelGGL(k_r_reduce, dim3((j * mp + 255) / 256), dim3(256), 0, s, part, kRBlocks, mp, j, h);
+                hipLaunchKernelGGL(k_r_basis_axpy, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, V, j,
+                                   (const double *)h, W);
+            }
+            hipLaunchKernelGGL(k_r_dot, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, (const double *)W,
+                               (const double *)W, part);
+            hipLaunchKernelGGL(k_r_reduce, dim3((mp + 255) / 256), dim3(256), 0, s, part, kRBlocks, mp, 1, ww);
+        };
+        bool w_ready = false;    // W holds the orthogonalized polynomial direction
         // the pole of step j
         if (switching) {
-            hipLaunchKernelGGL(k_r_switch, dim3(1), dim3(256), 0, s, mp, m, (const double *)dHist.p, kb, j,
-                               cfg->ell, std::pow(cfg->c, cfg->ell), (const double *)dFin.p, n_fin, switched,
-                               (double *)dXi.p);
+            if (!all_switched) {
+                // the polynomial direction of every column first: beta_j of
+                // the bound (Theorem 4.8) that the switch rule reads
+                R_TRY(hipMemcpyAsync(W, U, blk, hipMemcpyDeviceToDevice, s));
+                orthogonalize();
+                w_ready = true;
+                hipLaunchKernelGGL(k_r_beta_next, dim3(1), dim3(256), 0, s, (const double *)ww, (const double *)ww0,
+                                   (const int32_t *)ke, j, mp, kb, (double *)dBe.p);
+                R_TRY(launch_error_bound_cols((const BoundArgs *)dBa.p + (j - 1), m, s));
+            }
+            hipLaunchKernelGGL(k_r_switch, dim3(1), dim3(256), 0, s, mp, m, (const double *)dLo.p,
+                               (const double *)dHi.p, cfg->estimate ? 1 : 0, (double *)dErr.p, kb, j, cfg->ell,
+                               std::pow(cfg->c, cfg->ell), (const double *)dFin.p, n_fin, switched, (double *)dXi.p);
             R_TRY(hipMemcpyAsync(h_xi.data(), dXi.p, (size_t)mp * 8, hipMemcpyDeviceToHost, s));
+            R_TRY(hipMemcpyAsync(h_sw.data(), switched, (size_t)mp * 4, hipMemcpyDeviceToHost, s));
             R_TRY(hipStreamSynchronize(s));
+            all_switched = true;
+            for (int cc = 0; cc < m; ++cc) all_switched = all_switched && h_sw[cc] > 0;
         } else {
             const double xi = fin[j - 1];
             for (int cc = 0; cc < mp; ++cc) h_xi[cc] = cc < m && std::isfinite(xi) ? xi : 0.0;
@@ -600,8 +678,9 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
             any = any || h_live[cc];
         }
         if (!any) {
-            R_TRY(hipMemcpyAsync(W, U, blk, hipMemcpyDeviceToDevice, s));
+            if (!w_ready) R_TRY(hipMemcpyAsync(W, U, blk, hipMemcpyDeviceToDevice, s));
         } else {
+            w_ready = false;
             R_TRY(hipMemcpyAsync(live, h_live.data(), (size_t)mp * 4, hipMemcpyHostToDevice, s));
             R_TRY(hipMemsetAsync(iters, 0, (size_t)mp * 4, s));
             hipLaunchKernelGGL(k_r_cg_init, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, (const double *)U,
@@ -634,20 +713,7 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
             R_TRY(hipStreamSynchronize(s));
             for (int cc = 0; cc < m; ++cc) total_cg += hi[cc];
         }
-        // orthogonalize twice against v_1..v_j, normalize
-        hipLaunchKernelGGL(k_r_dot, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, (const double *)W,
-                           (const double *)W, part);
-        hipLaunchKernelGGL(k_r_reduce, dim3((mp + 255) / 256), dim3(256), 0, s, part, kRBlocks, mp, 1, ww0);
-        for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(k_r_basis_dots, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, V, j,
-                               (const double *)W, part);
-            hipLaunchKernelGGL(k_r_reduce, dim3((j * mp + 255) / 256), dim3(256), 0, s, part, kRBlocks, mp, j, h);
-            hipLaunchKernelGGL(k_r_basis_axpy, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, V, j,
-                               (const double *)h, W);
-        }
-        hipLaunchKernelGGL(k_r_dot, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, (const double *)W,
-                           (const double *)W, part);
-        hipLaunchKernelGGL(k_r_reduce, dim3((mp + 255) / 256), dim3(256), 0, s, part, kRBlocks, mp, 1, ww);
+        if (!w_ready) orthogonalize();
         hipLaunchKernelGGL(k_r_normalize, dim3(kRBlocks), dim3(kRThreads), 0, s, (int32_t)n, mp, (const double *)W,
                            (const double *)ww, (const double *)ww0, V + (size_t)j * n * mp);
         // basis size: a column grows while its new vector is not zero
@@ -656,9 +722,11 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
     // results
     std::vector<double> hist((size_t)mp * kb);
     std::vector<int64_t> ah((size_t)kb * mp);
+    std::vector<double> eh((size_t)mp * kb);
     std::vector<int32_t> sw(mp), kk(mp);
     int32_t fl = 0;
     R_TRY(hipMemcpyAsync(hist.data(), dHist.p, hist.size() * 8, hipMemcpyDeviceToHost, s));
+    R_TRY(hipMemcpyAsync(eh.data(), dErr.p, eh.size() * 8, hipMemcpyDeviceToHost, s));
     R_TRY(hipMemcpyAsync(ah.data(), apps_hist, ah.size() * 8, hipMemcpyDeviceToHost, s));
     R_TRY(hipMemcpyAsync(sw.data(), switched, (size_t)mp * 4, hipMemcpyDeviceToHost, s));
     R_TRY(hipMemcpyAsync(kk.data(), ke, (size_t)mp * 4, hipMemcpyDeviceToHost, s));
@@ -671,6 +739,7 @@ extern "C" vne_status vne_rational_quadforms(vne_ctx *c, int32_t gid, const vne_
         for (int j = 0; j < kb; ++j) {
             if (out->psi_steps) out->psi_steps[(size_t)cc * kb + j] = j < steps_done ? hist[(size_t)cc * kb + j] : 0.0;
             if (out->apps_steps) out->apps_steps[(size_t)cc * kb + j] = j < steps_done ? ah[(size_t)j * mp + cc] : 0;
+            if (out->err_steps) out->err_steps[(size_t)cc * kb + j] = eh[(size_t)cc * kb + j];
         }
         if (out->switch_step) out->switch_step[cc] = sw[cc];
         if (out->basis) out->basis[cc] = kk[cc];

@@ -92,37 +92,48 @@ def test_all_poles_at_infinity_is_the_polynomial_path(ctx):
     assert np.all(_rel(out["quad"], poly["quad"]) <= 1e-11)
 
 
-def test_switch_rule_on_a_path(ctx):
+@pytest.mark.parametrize("estimate", [False, True])
+def test_switch_rule_on_a_path(ctx, estimate):
     n, e = synth.path_graph(300)
-    _say("case rational switch rule path n=300 m=4 steps=24 ell=3 c=0.75")
+    _say("case rational switch rule path n=300 m=4 steps=24 ell=3 c=0.75 estimate=%s" % estimate)
     gid, ref = _setup(ctx, n, e)
     A = ref.scipy().toarray()
     lam = np.linalg.eigvalsh(A)
+    lo, hi = 0.999 * lam[1], 1.001 * lam[-1]
     steps, m = 24, 4
     fin = list(-np.geomspace(lam[-1], lam[1], 12))
     out = ctx.rational(gid, vne.PROBE_RADEMACHER, m, MODE, steps, finite_poles=fin, ell=3, c=0.75,
-                       cg_tol=CG_TOL, seed=5)
+                       cg_tol=CG_TOL, seed=5, lam_lo=lo, lam_hi=hi, estimate=estimate)
     C = _start(ref, 5, m)
-    runs = [rational_run(A, C[:, c], steps, finite_poles=fin, ell=3, c=0.75) for c in range(m)]
+    runs = [rational_run(A, C[:, c], steps, finite_poles=fin, ell=3, c=0.75, lam_lo=lo, lam_hi=hi,
+                         estimate=estimate) for c in range(m)]
     flipped = set()
+    worst = 0.0
     for c, r in enumerate(runs):
         s_gpu, s_ora = int(out["switch_step"][c]), r["switch"]
+        # the bounds of the polynomial steps: Theorem 4.8 on both sides (the
+        # device's integral route against the oracle's residue form)
+        j_max = min(s_gpu, s_ora) if s_gpu and s_ora else len(r["err"])
+        err = _rel(out["err_steps"][c, :j_max], np.array(r["err"][:j_max]))
+        worst = max(worst, float(err.max()))
+        assert np.all(err <= 1e-6), (c, err.max())
         _say("  column %d: switch at step %d (oracle %d)" % (c, s_gpu, s_ora))
         if s_gpu != s_ora:
-            # a decision taken on FP64 values on both sides may flip only at
-            # the threshold itself: the oracle's ratio there is within 1e-8
-            j = min(s for s in (s_gpu, s_ora) if s > 0)
-            psi = r["psi"]
-            ratio = abs(psi[j - 1] - psi[j - 2]) / (0.75 ** 3 * abs(psi[j - 5] - psi[j - 6]))
-            assert abs(ratio - 1.0) < 1e-8, (c, s_gpu, s_ora, ratio)
+            # a decision on bounds that agree to 1e-6 may flip only where the
+            # oracle's ratio is within 1e-5 of the threshold
+            j = min(v for v in (s_gpu, s_ora) if v > 0)
+            ratio = r["err"][j - 1] / (0.75 ** 3 * r["err"][j - 5])
+            assert abs(ratio - 1.0) < 1e-5, (c, s_gpu, s_ora, ratio)
             flipped.add(c)
+    _say("  worst bound rel err %.2e" % worst)
     assert len(flipped) < m and np.all(out["switch_step"] > 0)
     _check_steps(out, runs, steps, skip=flipped)
-    # the GPU's own forms give its switch step under the rule
+    # the GPU's own bounds give its switch step under the rule
     for c in range(m):
         if c not in flipped:
             s = int(out["switch_step"][c])
-            assert switch_step(list(out["psi_steps"][c, :s]), 3, 0.75) == s
+            assert switch_step(list(out["err_steps"][c, :s]), 3, 0.75) == s
+            assert np.all(out["err_steps"][c, s:] == 0.0)
 
 
 @pytest.mark.parametrize("m", [1, 37, 128])
@@ -170,14 +181,16 @@ def test_rational_errors(ctx):
            dict(poles=[1.0, np.inf], steps=3, status=-1),               # positive pole
            dict(poles=[np.nan, -1.0], steps=3, status=-1),
            dict(c=1.0, status=-1), dict(ell=0, status=-1),             # switch rule arguments
+           dict(lam_lo=0.0, status=-1), dict(lam_lo=2.0, lam_hi=1.0, status=-1),
            dict(kind=vne.PROBE_HUTCHPP, status=-4)]
     for b in bad:
-        kw = dict(kind=vne.PROBE_RADEMACHER, m=4, mode=MODE, steps=5, poles=None, c=0.75, ell=3)
+        kw = dict(kind=vne.PROBE_RADEMACHER, m=4, mode=MODE, steps=5, poles=None, c=0.75, ell=3, lam_lo=1e-3,
+                  lam_hi=4.0)
         kw.update(b)
         st = kw.pop("status")
         with pytest.raises(vne.VneError) as ei:
             ctx.rational(gid, kw["kind"], kw["m"], kw["mode"], kw["steps"], poles=kw["poles"],
-                         finite_poles=[-1.0], ell=kw["ell"], c=kw["c"])
+                         finite_poles=[-1.0], ell=kw["ell"], c=kw["c"], lam_lo=kw["lam_lo"], lam_hi=kw["lam_hi"])
         assert ei.value.status == st, b
     # the context still works
     out = ctx.rational(gid, vne.PROBE_RADEMACHER, 4, MODE, 5, poles=[np.inf] * 4)
