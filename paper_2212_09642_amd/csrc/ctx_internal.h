@@ -50,6 +50,9 @@ struct Plan {
     int32_t *h_remaining = nullptr;
     std::vector<char> h_adapt;
     std::map<std::tuple<int, int, int>, hipGraphExec_t> chunk_exec;
+    // the k-step loop of each concurrent tile chain, per (schedule, tile,
+    // chains, chain)
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> chain_exec;
     int steps_run = 0;               // steps the block ran in the last run
     // values last uploaded to graph_k / graph_m / seeds (skipped when equal)
     std::vector<int32_t> up_graph_k, up_graph_m;
@@ -118,11 +121,16 @@ struct vne_ctx {
         void *plan;
         double bytes;
         int steps;                       // step launches with recorded events
+        bool loop = false;               // one event pair around the whole loop (tile chains)
     };
     std::vector<Pending> pending;        // timed step loops not yet collected
     std::map<std::string, int> tuned;    // autotuner: set signature -> column tile
     int32_t last_tile = 0, last_m_pad = 0;   // column tile and padded width of the last run
     std::string tune_file;
+    // concurrent tile chains: their streams (default priority) and the
+    // fork / join events, created on first use
+    std::vector<hipStream_t> chain_streams;
+    std::vector<hipEvent_t> chain_events;
     // serialises the registry (register, release, estimates) against the
     // worker thread of a server running on this context
     std::recursive_mutex mu;
@@ -175,6 +183,8 @@ struct ProbeSpec {
 struct RunOpts {
     bool collect = true;               // record kernel timing for this run
     int steps = -1;                    // autotuner: only this many steps, no graph, no quadrature
+    bool graph_trial = false;          // autotuner: the whole loop as the run would launch it (captured
+                                       // graphs kept for later runs), no quadrature
     int tile = 0;                      // column tile (0: the plan's)
     // per-column a-posteriori stopping (one graph): the Theorem 4.8 upper
     // bound on [lam_lo, lam_hi] (n_grid points) is checked after steps 3, 5,

@@ -64,6 +64,11 @@ struct StepArgs {
     // work block whose tile holds only done or frozen columns returns at
     // once, and the normalize pass skips groups of done columns.
     const int32_t *col_stop;
+    // a launch over part of the block: its tiles start at tile_base (grid y
+    // counts from there) and the normalize pass covers columns [col_base,
+    // col_base + col_count) (col_count 0: every column)
+    int32_t tile_base;
+    int32_t col_base, col_count;
 };
 
 constexpr int kLevel2 = 32;       // first-level reduction rows of the step partials
@@ -99,6 +104,9 @@ struct FinalizeArgs {
     int32_t *flags_hi;                 // slots: flags of columns >= flag_split (nullptr: flags)
     int32_t flag_split;
     const int32_t *col_stop;           // as in StepArgs: done columns keep their coefficients
+    // one graph: the reduction and update of columns [col_base, col_base +
+    // col_count) only (col_count 0: every column)
+    int32_t col_base, col_count;
 };
 
 // Returns the column tile width the step kernel uses for this probe width;

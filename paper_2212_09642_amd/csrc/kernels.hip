@@ -405,11 +405,12 @@ __global__ void __launch_bounds__(256) k_normalize(StepArgs a) {
     const T *P = static_cast<const T *>(a.P_in);
     const T *Vp = static_cast<const T *>(a.V_prev);
     T *Vo = static_cast<T *>(a.V_out);
-    const int64_t groups = (int64_t)a.n * (a.m_pad / CPL);
-    const int cg = a.m_pad / CPL;
+    const int width = a.col_count > 0 ? a.col_count : a.m_pad;
+    const int64_t groups = (int64_t)a.n * (width / CPL);
+    const int cg = width / CPL;
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < groups; t += (int64_t)gridDim.x * 256) {
         const int64_t i = t / cg;
-        const int c0 = (int)(t % cg) * CPL;
+        const int c0 = a.col_base + (int)(t % cg) * CPL;
         const int64_t s0 = (a.row_graph ? (int64_t)a.row_graph[i] * a.m_pad : 0) + c0;
         if (a.col_stop) {
             bool done = true;
@@ -580,8 +581,9 @@ __global__ void __launch_bounds__(kStepThreads) VNE_STEP_OCCUPANCY k_lanczos_ste
     // the gathered block of one tile stays resident in the last-level cache;
     // within a tile each XCD takes one contiguous range of row blocks
     // (n_blocks is a multiple of 8)
-    if (a.col_stop && !tile_live(a, blockIdx.y, 1, CPL * LPR)) return;
-    step_block<T, CPL, LPR, FIRST, TWO>(a, xcd_remap(blockIdx.x, a.n_blocks), blockIdx.y, red);
+    const int tile = a.tile_base + (int)blockIdx.y;
+    if (a.col_stop && !tile_live(a, tile, 1, CPL * LPR)) return;
+    step_block<T, CPL, LPR, FIRST, TWO>(a, xcd_remap(blockIdx.x, a.n_blocks), tile, red);
 }
 
 // Several independent problems ("slots") in one launch: entry e = {slot,
@@ -710,8 +712,9 @@ __device__ __forceinline__ void long_rows_group(const StepArgs &a, int group, in
 
 template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
 __global__ void __launch_bounds__(256) k_long_rows(StepArgs a) {
-    if (a.col_stop && !tile_live(a, blockIdx.y, 1, CPL * LPR)) return;
-    long_rows_group<T, CPL, LPR, FIRST, TWO>(a, blockIdx.x, blockIdx.y);
+    const int tile = a.tile_base + (int)blockIdx.y;
+    if (a.col_stop && !tile_live(a, tile, 1, CPL * LPR)) return;
+    long_rows_group<T, CPL, LPR, FIRST, TWO>(a, blockIdx.x, tile);
 }
 
 // entry {slot, group of long rows, tile}
@@ -770,7 +773,7 @@ int choose_plan_tile(int m, bool fp64, int64_t n, int64_t nnz) {
 template <typename T, int CPL, int LPR, bool FIRST, bool TWO>
 static void launch_step_k(const StepArgs &a, hipStream_t s) {
     if (TWO) {
-        const int64_t groups = (int64_t)a.n * (a.m_pad / CPL);
+        const int64_t groups = (int64_t)a.n * ((a.col_count > 0 ? a.col_count : a.m_pad) / CPL);
         const unsigned nb = (unsigned)std::min<int64_t>((groups + 255) / 256, 8192);
         hipLaunchKernelGGL((k_normalize<T, CPL, FIRST>), dim3(nb), dim3(256), 0, s, a);
     }
@@ -881,10 +884,11 @@ hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s) 
 __global__ void __launch_bounds__(256) k_reduce_partials(FinalizeArgs a) {
     __shared__ double sh[3][4][64];
     const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    const int c = blockIdx.x * 64 + lane;
+    const int c = a.col_base + (int)blockIdx.x * 64 + lane;
+    const int c_end = a.col_count > 0 ? a.col_base + a.col_count : a.m_pad;
     const int r = blockIdx.y, R = gridDim.y;
     double s3[3] = {0.0, 0.0, 0.0};
-    if (c < a.m_pad) {
+    if (c < c_end) {
         constexpr int UB = 4;
         const int stride = 4 * R;
         int bb = r + grp * R;
@@ -921,7 +925,7 @@ __global__ void __launch_bounds__(256) k_reduce_partials(FinalizeArgs a) {
     sh[1][grp][lane] = s3[1];
     sh[2][grp][lane] = s3[2];
     __syncthreads();
-    if (grp != 0 || c >= a.m_pad) return;
+    if (grp != 0 || c >= c_end) return;
     double* out = a.level2 + (int64_t)r * 3 * a.m_pad + c;
 #pragma unroll
     for (int q = 0; q < 3; ++q) out[(int64_t)q * a.m_pad] = sh[q][0][lane] + sh[q][1][lane] + sh[q][2][lane] + sh[q][3][lane];
@@ -975,8 +979,8 @@ __device__ __forceinline__ void update_coefficients(const FinalizeArgs &a, int g
 // overlap instead of forming a chain of dependent round trips; the sums keep
 // the same order.
 __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs a) {
-    const int c = blockIdx.x * 64 + threadIdx.x;
-    if (c >= a.m_pad) return;
+    const int c = a.col_base + (int)blockIdx.x * 64 + (int)threadIdx.x;
+    if (c >= (a.col_count > 0 ? a.col_base + a.col_count : a.m_pad)) return;
     double svw = 0.0, sww = 0.0, svv = 0.0;
     if (a.n_level2 == kLevel2) {
         double v[kLevel2][3];
@@ -1147,8 +1151,9 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(k_finalize_graphs, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_reduce_partials, dim3((a.m_pad + 63) / 64, a.n_level2), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_finalize, dim3((a.m_pad + 63) / 64), dim3(64), 0, s, a);
+    const int width = a.col_count > 0 ? a.col_count : a.m_pad;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((width + 63) / 64, a.n_level2), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3((width + 63) / 64), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -86,6 +86,9 @@ void free_plan(vne_ctx *c, Plan *p) {
     for (auto &kv : p->chunk_exec)
         if (kv.second) (void)hipGraphExecDestroy(kv.second);
     p->chunk_exec.clear();
+    for (auto &kv : p->chain_exec)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    p->chain_exec.clear();
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     p->ev.clear();
     if (p->h_remaining) (void)hipHostFree(p->h_remaining);
@@ -366,6 +369,15 @@ vne_status get_plan(vne_ctx *c, GraphSet *set, int m, int k, bool fp64, bool sto
 vne_status collect_timing(vne_ctx *c) {
     for (auto &pd : c->pending) {
         Plan *p = (Plan *)pd.plan;
+        if (pd.loop) {
+            // concurrent tile chains: the loop's span, every step counted once
+            float ms = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+            c->t_ms += ms;
+            c->t_bytes += pd.bytes * pd.steps;
+            c->t_launches += pd.steps;
+            continue;
+        }
         for (int j = 0; j < pd.steps; ++j) {
             float ms = 0.f;
             HIP_TRY(c, hipEventElapsedTime(&ms, p->ev[2 * j], p->ev[2 * j + 1]));
@@ -509,35 +521,36 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
 
     const bool tuning = opt.steps > 0;
     const int nsteps = tuning ? std::min(opt.steps, p->k) : p->k;
-    const bool use_graph = env_int("VNE_GRAPH", 1) != 0 && !tuning && !opt.direct;
+    const bool use_graph = env_int("VNE_GRAPH", 1) != 0 && (!tuning || opt.graph_trial) && !opt.direct;
     const bool timing = c->timing && opt.collect;
     // part 0: the step kernels of step j; part 1: its reduction and finalize
-    auto issue = [&](int j, int part) -> vne_status {
+    auto issue_on = [&](StepArgs &sa, FinalizeArgs &fa, int j, int part, hipStream_t st) -> vne_status {
         char *Pb[2] = {(char *)p->P[0].p, (char *)p->P[1].p};
-        a.P_in = Pb[(j - 1) & 1];
-        a.P_out = Pb[j & 1];
+        sa.P_in = Pb[(j - 1) & 1];
+        sa.P_out = Pb[j & 1];
         if (p->store) {
             char *base = (char *)p->Vstore.p;
-            a.V_out = base + (size_t)(j - 1) * blk_elems * es;
-            a.V_prev = j >= 2 ? base + (size_t)(j - 2) * blk_elems * es : nullptr;
+            sa.V_out = base + (size_t)(j - 1) * blk_elems * es;
+            sa.V_prev = j >= 2 ? base + (size_t)(j - 2) * blk_elems * es : nullptr;
         } else {
-            a.V_out = p->V[(j - 1) & 1].p;
-            a.V_prev = p->V[j & 1].p;
+            sa.V_out = p->V[(j - 1) & 1].p;
+            sa.V_prev = p->V[j & 1].p;
         }
-        a.V_cur = a.V_out;
+        sa.V_cur = sa.V_out;
         if (part == 0) {
-            HIP_TRY(c, launch_step(a, p->fp64, j == 1, c->stream));
+            HIP_TRY(c, launch_step(sa, p->fp64, j == 1, st));
         } else {
-            f.step = j;
-            HIP_TRY(c, launch_finalize(f, c->stream));
+            fa.step = j;
+            HIP_TRY(c, launch_finalize(fa, st));
         }
         return VNE_OK;
     };
-    auto capture_fn = [&](hipGraphExec_t *ex, const std::function<vne_status()> &body) -> vne_status {
+    auto issue = [&](int j, int part) -> vne_status { return issue_on(a, f, j, part, c->stream); };
+    auto capture_on = [&](hipStream_t cs, hipGraphExec_t *ex, const std::function<vne_status()> &body) -> vne_status {
         hipGraph_t graph = nullptr;
-        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
         vne_status st = body();
-        hipError_t e_end = hipStreamEndCapture(c->stream, &graph);
+        hipError_t e_end = hipStreamEndCapture(cs, &graph);
         if (st != VNE_OK) {
             if (graph) (void)hipGraphDestroy(graph);
             return st;
@@ -550,6 +563,9 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
             return hip_fail(c, e_inst, "hipGraphInstantiate");
         }
         return VNE_OK;
+    };
+    auto capture_fn = [&](hipGraphExec_t *ex, const std::function<vne_status()> &body) -> vne_status {
+        return capture_on(c->stream, ex, body);
     };
     auto capture = [&](hipGraphExec_t *ex, int j0, int j1, int part_only) -> vne_status {
         return capture_fn(ex, [&]() -> vne_status {
@@ -675,7 +691,76 @@ vne_status run_lanczos(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, 
                                      (const int32_t *)p->col_stop.p));
         return VNE_OK;
     }
-    if (use_graph && !timing) {
+    // Concurrent tile chains (one graph, two-pass schedule, two or more
+    // tiles): the tiles of the block are split into up to VNE_CHAINS groups
+    // (default 2), each with its whole k-step loop on a stream of its own
+    // after a fork from the caller's stream and joined back at the end.
+    // Columns never meet across tiles, so each chain's kernels touch only
+    // their own columns of the shared buffers and the results are the same
+    // bits; the chains overlap one tile's streaming pass with another's
+    // gathers.  Kernel timing then records the loop's span once.
+    // (2 chains: BA n = 2e5 Hutch++ 128 + 128 at tile 64, 35.9 ms per
+    // estimate against 38.1 ms with one chain and 37.7 ms with 4)
+    const int max_chains = std::min(env_int("VNE_CHAINS", 2), 8);
+    const int chains = (a.two_pass && set->G == 1 && a.n_tiles >= 2 && !opt.direct && max_chains >= 2)
+                           ? std::min(a.n_tiles, max_chains)
+                           : 1;
+    if (chains > 1) {
+        while ((int)c->chain_streams.size() < chains) {
+            hipStream_t cs = nullptr;
+            HIP_TRY(c, hipStreamCreate(&cs));
+            c->chain_streams.push_back(cs);
+        }
+        while ((int)c->chain_events.size() < chains + 1) {
+            hipEvent_t e = nullptr;
+            HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            c->chain_events.push_back(e);
+        }
+        std::vector<StepArgs> ca(chains, a);
+        std::vector<FinalizeArgs> cf(chains, f);
+        for (int i = 0, t0 = 0; i < chains; ++i) {
+            const int cnt = a.n_tiles / chains + (i < a.n_tiles % chains ? 1 : 0);
+            ca[i].tile_base = t0;
+            ca[i].n_tiles = cnt;
+            ca[i].col_base = t0 * mt;
+            ca[i].col_count = cnt * mt;
+            cf[i].col_base = t0 * mt;
+            cf[i].col_count = cnt * mt;
+            t0 += cnt;
+        }
+        const bool chain_graphs = use_graph;
+        if (timing) HIP_TRY(c, hipEventRecord(p->ev[0], c->stream));
+        HIP_TRY(c, hipEventRecord(c->chain_events[0], c->stream));
+        for (int i = 0; i < chains; ++i) {
+            hipStream_t cs = c->chain_streams[i];
+            HIP_TRY(c, hipStreamWaitEvent(cs, c->chain_events[0], 0));
+            if (chain_graphs) {
+                hipGraphExec_t &ex = p->chain_exec[std::make_tuple(key.first, key.second, chains, i)];
+                if (!ex) {
+                    VNE_TRY(capture_on(cs, &ex, [&]() -> vne_status {
+                        for (int j = 1; j <= p->k; ++j)
+                            for (int part = 0; part < 2; ++part) VNE_TRY(issue_on(ca[i], cf[i], j, part, cs));
+                        return VNE_OK;
+                    }));
+                }
+                HIP_TRY(c, hipGraphLaunch(ex, cs));
+            } else {
+                for (int j = 1; j <= nsteps; ++j)
+                    for (int part = 0; part < 2; ++part) VNE_TRY(issue_on(ca[i], cf[i], j, part, cs));
+            }
+            HIP_TRY(c, hipEventRecord(c->chain_events[1 + i], cs));
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->chain_events[1 + i], 0));
+        }
+        if (timing) HIP_TRY(c, hipEventRecord(p->ev[1], c->stream));
+        if (tuning) return VNE_OK;
+        if (timing) c->pending.push_back({p, bytes, p->k, true});
+        if (p->store) return VNE_OK;
+        HIP_TRY(c, launch_quadrature((const double *)p->alpha.p, (const double *)p->beta.p,
+                                     (const int32_t *)p->k_eff.p, (const double *)p->norm2.p, p->k, p->k,
+                                     p->G * p->m_pad, (double *)p->psi.p, (int32_t *)p->flags.p, c->stream, p->fp64));
+        return VNE_OK;
+    }
+    if (use_graph && (!timing || tuning)) {
         hipGraphExec_t &ex = p->exec[key];
         if (!ex) VNE_TRY(capture(&ex, 1, p->k, -1));
         HIP_TRY(c, hipGraphLaunch(ex, c->stream));
@@ -728,9 +813,14 @@ vne_status autotune(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, boo
         float best_ms = 1e30f;
         vne_status st = VNE_OK;
         for (int t : cands) {
+            // each candidate runs the whole loop the way the estimate will
+            // (captured graphs, concurrent tile chains), the first time to
+            // capture and warm up, the second timed; the graphs stay for
+            // later runs (VNE_TUNE_GRAPH=0: a few direct-launched steps)
             RunOpts o;
             o.collect = false;
-            o.steps = std::min(3, p->k);
+            o.graph_trial = env_int("VNE_TUNE_GRAPH", 1) != 0;
+            o.steps = o.graph_trial ? p->k : std::min(3, p->k);
             o.tile = t;
             if ((st = run_lanczos(c, set, p, ps, desing, o)) != VNE_OK) break;   // warm-up
             hipError_t e = hipEventRecord(e0, c->stream);
@@ -864,6 +954,11 @@ vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int
     ProbeSpec ps;
     ps.gen = GEN_RADEMACHER;
     ps.seeds = {pr->seed};
+    // column tiles of both Lanczos runs, timed on Rademacher blocks of their
+    // widths (the speed of a step does not depend on the values; the runs
+    // below probe their own blocks again)
+    VNE_TRY(autotune(c, set, sk, ps, desing));
+    VNE_TRY(autotune(c, set, q, ps, desing));
     VNE_TRY(run_lanczos(c, set, sk, ps, desing));
     HIP_TRY(c, launch_fT_e1((const double *)sk->alpha.p, (const double *)sk->beta.p, (const int32_t *)sk->k_eff.p,
                             k, nr, (double *)q->S.p, q->rot.p, (int32_t *)sk->flags.p, s, fp64));
@@ -1074,6 +1169,8 @@ extern "C" void vne_ctx_destroy(vne_ctx *c) {
     c->sets.clear();
     for (auto &g : c->graphs)
         if (g) free_graph(c, g.get());
+    for (hipStream_t cs : c->chain_streams) (void)hipStreamDestroy(cs);
+    for (hipEvent_t e : c->chain_events) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }

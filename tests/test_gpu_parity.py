@@ -248,6 +248,42 @@ def test_schedules_bitwise_identical(ctx, fp64, monkeypatch):
         assert np.array_equal(outs[0][key], outs[1][key]), key
 
 
+@pytest.mark.parametrize("fp64", [True, False])
+def test_tile_chains_bitwise_identical(ctx, fp64, monkeypatch):
+    # the tiles of a block split into concurrent chains on streams of their
+    # own touch only their own columns: every result is the same to the bit
+    # as one chain, with captured graphs, with direct launches under kernel
+    # timing, and for the stored basis of the Hutch++ sketch
+    _say("case tile chains fp64=%s" % fp64)
+    n, e = synth.barabasi_albert(20000, 3, 12)
+    gid, ref = _setup(ctx, n, e, fp64)
+    mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+    monkeypatch.setenv("VNE_AUTOTUNE", "0")
+    monkeypatch.setenv("VNE_TILE", "16" if fp64 else "32")
+    outs = []
+    for chains, timing in (("1", False), ("2", False), ("4", False), ("3", True)):
+        monkeypatch.setenv("VNE_CHAINS", chains)
+        ctx.enable_kernel_timing(timing)
+        r = ctx.estimate(gid, vne.PROBE_RADEMACHER, 100, 25, mode, seed=31)
+        h = ctx.estimate(gid, vne.PROBE_HUTCHPP, 96, 20, mode, seed=32, n_sketch=64)
+        assert ctx.last_plan()["tile"] == (16 if fp64 else 32)
+        outs.append((r, h))
+        ctx.enable_kernel_timing(False)
+    for r, h in outs[1:]:
+        for key in ("quad", "alpha", "beta", "k_eff", "norm2"):
+            assert np.array_equal(r[key], outs[0][0][key]), key
+            assert np.array_equal(h[key], outs[0][1][key]), key
+        assert h["estimate"] == outs[0][1]["estimate"]
+    # the chains against the oracle at 12 steps (at 25, some columns of this
+    # graph have lost orthogonality and their forms move by ~1e-7 under any
+    # change of rounding, as the tile width alone shows)
+    monkeypatch.setenv("VNE_CHAINS", "4")
+    out = ctx.estimate(gid, vne.PROBE_RADEMACHER, 100, 12, mode, seed=31)
+    B = oracle.rademacher_block(31, ref.node_ids, np.arange(100))
+    want = oracle.quadforms(ref.scipy(), B, 12, oracle.breakdown_tau(fp64))
+    _check_quad(out, want, fp64, sens=_order_sensitivity(ref.scipy(), B, 12, fp64), n=ref.n)
+
+
 def test_graph_and_timing_paths_agree(ctx, monkeypatch):
     # captured graph, per-part graphs with kernel timing, and direct launches
     # run the same kernels in the same order
