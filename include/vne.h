@@ -210,7 +210,13 @@ vne_status vne_graph_release(vne_ctx *ctx, int32_t graph_id);
  * be NULL except `out` itself).  For HUTCHPP, quad/alpha/beta/k_eff/norm2
  * describe the final block [Q | G~] of m quadratic forms (the sketch's own
  * coefficients are not returned).  Workspaces are cached per (graph, probe
- * width, k, mode, kind) and reused by later calls. */
+ * width, k, mode, kind) and reused by later calls.  The column tile of a
+ * workspace is picked on its first use by timing each admissible tile's
+ * whole step loop (see vne_last_plan).  When the block spans two or more
+ * tiles, its tiles run as up to two concurrent chains, each chain's step
+ * loop on a stream the context owns (VNE_CHAINS, default 2, 1 disables); the
+ * context's stream waits for them, and the results are bitwise those of one
+ * chain. */
 vne_status vne_entropy_estimate(vne_ctx *ctx, int32_t graph_id, const vne_probes *probes,
                                 int32_t k_steps, uint32_t mode, vne_result *out);
 
@@ -228,8 +234,8 @@ vne_status vne_entropy_estimate(vne_ctx *ctx, int32_t graph_id, const vne_probes
  * more than once.  The stacked copy of the matrices is cached for the exact
  * id sequence (at most VNE_MAX_SETS such sets, default 4, least recently
  * used freed first); the column tile of the launch is picked on first use by
- * timing three steps of each admissible tile (VNE_AUTOTUNE=0 disables;
- * VNE_AUTOTUNE_CACHE=<file> keeps the choices).  Errors: VNE_EINVAL for bad
+ * timing each admissible tile's whole captured step loop (VNE_AUTOTUNE=0
+ * disables; VNE_AUTOTUNE_CACHE=<file> keeps the choices).  Errors: VNE_EINVAL for bad
  * ids, sizes or mode bits; VNE_ENOMEM when the HBM budget is exceeded. */
 vne_status vne_entropy_estimate_batch(vne_ctx *ctx, int32_t n_queries, const int32_t *graph_ids,
                                       const vne_probes *probes, const int32_t *k_steps,
@@ -457,9 +463,10 @@ vne_status vne_entropy_estimate_noalloc(vne_ctx *ctx, int32_t graph_id, const vn
 /* Diagnostics: the column tile (columns per work block of the Lanczos step
  * kernels) and the padded block width m_pad of the Lanczos run of the last
  * estimate on ctx (for Hutch++, its quadratic-form block; 0, 0 before any
- * estimate).  The tile comes from a byte model of the step (plan creation)
- * or the autotuner (batches; VNE_AUTOTUNE=0 keeps the model's tile),
- * VNE_TILE forces one. */
+ * estimate).  The tile comes from the autotuner on a plan's first use (it
+ * times the whole step loop of every tile that divides the padded width,
+ * concurrent chains included, and keeps the fastest); VNE_AUTOTUNE=0 keeps
+ * the byte model's tile of plan creation, VNE_TILE forces one. */
 vne_status vne_last_plan(const vne_ctx *ctx, int32_t *tile, int32_t *m_pad);
 
 /* ----------------------------------------------------------------------------

@@ -8,8 +8,15 @@
     python -m paper_2212_09642_amd.profiling counters OUT.md --kernel NAME DB [DB ...] --cmd "..."
 
 The Lanczos step unit is the normalize pass (two-pass schedule), the SpMM +
-recurrence kernel and the long-row kernel of one step; its average duration
-is what bench.py times with HIP events around each step.
+recurrence kernel, the long-row kernel and the partial-sum reductions of one
+step.  bench.py brackets its timed region with two marker kernels (torch's
+spin kernel); the summaries count only the dispatches between them, which
+leaves out warm-up, tile tuning and what a run does afterwards.  A loop may
+run its column tiles as concurrent chains on streams of their own, each
+chain dispatching every step for its tiles: a Lanczos step is then counted
+once, from the step kernels of the stream that carries the markers (loops
+run as one chain) plus those of the busiest other stream (the first chain
+takes part in every chained loop).
 """
 import argparse
 import collections
@@ -19,6 +26,8 @@ import sqlite3
 import sys
 
 STEP_KERNELS = ("k_normalize", "k_lanczos_step", "k_long_rows")
+UNIT_KERNELS = STEP_KERNELS + ("k_reduce_partials", "k_finalize")
+MARKER = "spin_kernel"
 
 
 def _short(name):
@@ -32,79 +41,132 @@ def kernel_stats(db):
     return [(n, int(c), float(t), float(a)) for n, c, t, a in rows]
 
 
-def step_unit(rows):
-    steps = sum(c for n, c, t, a in rows if "k_lanczos_step" in n)
-    total = sum(t for n, c, t, a in rows if any(k in n for k in STEP_KERNELS))
-    return steps, total
+def _dispatches(con):
+    """(dispatch id, kernel name, stream id, start ns, end ns) of every
+    dispatch, by start time."""
+    return con.execute(
+        "select K.dispatch_id, S.display_name, K.stream_id, K.start, K.end from rocpd_kernel_dispatch K "
+        "join rocpd_info_kernel_symbol S on S.id = K.kernel_id and S.guid = K.guid "
+        "order by K.start, K.dispatch_id").fetchall()
+
+
+def _region(disp):
+    """The dispatches between the two marker kernels (after the first when
+    there is one only) and the markers' stream; all dispatches and None
+    without a marker.  Everything in the region was issued after the first
+    marker ended and before the second started (the host synchronizes in
+    between), so start times order them."""
+    marks = [i for i, d in enumerate(disp) if MARKER in d[1]]
+    if not marks:
+        return disp, None
+    hi = marks[1] if len(marks) > 1 else len(disp)
+    return disp[marks[0] + 1:hi], disp[marks[0]][2]
+
+
+def _logical_steps(disp, main):
+    """Lanczos steps among the dispatches (see the module's docstring)."""
+    per = collections.Counter(d[2] for d in disp if "k_lanczos_step" in d[1])
+    if main is None:
+        return sum(per.values())
+    return per.get(main, 0) + max([v for st, v in per.items() if st != main], default=0)
+
+
+def _busy_ns(disp, names):
+    """Length of the union of the intervals of the dispatches whose kernel
+    name contains one of names."""
+    total, lo, hi = 0, None, None
+    for a, b in sorted((d[3], d[4]) for d in disp if any(k in d[1] for k in names)):
+        if hi is None or a > hi:
+            if hi is not None:
+                total += hi - lo
+            lo, hi = a, b
+        else:
+            hi = max(hi, b)
+    return total + (hi - lo if hi is not None else 0)
 
 
 def cmd_stats(args):
     rows = kernel_stats(args.db)
     tot = sum(r[2] for r in rows)
     out = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", args.cmd, "```", "",
+           "Whole run (warm-up and tile tuning included):", "",
            "| kernel | calls | total ms | avg us | share |", "|---|---:|---:|---:|---:|"]
     for n, c, t, a in rows:
         out.append("| `%s` | %d | %.3f | %.2f | %.1f%% |" % (_short(n), c, t / 1e3, a, 100 * t / tot))
-    steps, st = step_unit(rows)
-    out += ["", "All kernels: %.3f ms." % (tot / 1e3),
-            "Lanczos step unit (normalize + SpMM/recurrence + long rows): %d steps, %.3f ms total, "
-            "%.2f us average per step." % (steps, st / 1e3, st / max(steps, 1))]
+    out += ["", "All kernels: %.3f ms." % (tot / 1e3)]
+    region, main = _region(_dispatches(sqlite3.connect(args.db)))
+    if main is not None:
+        steps = _logical_steps(region, main)
+        busy = _busy_ns(region, UNIT_KERNELS) / 1e3
+        per = collections.defaultdict(list)
+        for d in region:
+            per[_short(d[1])].append((d[4] - d[3]) / 1e3)
+        out += ["", "Timed region (between the marker kernels):", "",
+                "| kernel | calls | total ms | avg us |", "|---|---:|---:|---:|"]
+        for k in sorted(per, key=lambda k: -sum(per[k])):
+            out.append("| `%s` | %d | %.3f | %.2f |" % (k, len(per[k]), sum(per[k]) / 1e3,
+                                                        sum(per[k]) / len(per[k])))
+        n_streams = len({d[2] for d in region if "k_lanczos_step" in d[1]})
+        out += ["", "Lanczos step unit (normalize, SpMM/recurrence, long rows, partial reductions, finalize) "
+                    "in the timed region: %d steps on %d stream(s); the union of its kernels' intervals is "
+                    "%.3f ms, %.2f us per step." % (steps, n_streams, busy / 1e3, busy / max(steps, 1))]
+    if args.bench_line:
+        # the JSON line the profiled bench.py run printed: its own HIP-event
+        # timing of the same steps, for comparison with the trace
+        with open(args.bench_line) as fh:
+            line = [x for x in fh.read().splitlines() if x.startswith("{")][-1]
+        r = json.loads(line)["roofline"]
+        out += ["", "The profiled bench.py run timed %d step launches at %.2f us each with HIP events "
+                    "(roofline fraction %.4f under the profiler)." % (r["launches"], 1e3 * r["avg_launch_ms"],
+                                                                     r["frac"])]
     with open(args.out, "w") as fh:
         fh.write("\n".join(out) + "\n")
     print("\n".join(out))
 
 
-def _counter(db, name_filter=None, skip_steps=0, max_steps=0):
-    """Counter sums per (kernel, counter) over the dispatches matching
-    name_filter, in dispatch order.  skip_steps / max_steps (with step
-    kernels in the filter) keep the dispatches from the (skip_steps + 1)-th
-    Lanczos step kernel on, for max_steps steps (0: all): a step's normalize
-    pass comes before its step kernel, its long rows after."""
+def _counter(db, name_filter=None):
+    """Counter sums and dispatch counts per (kernel, counter) over the
+    timed region's dispatches whose kernel name contains one of name_filter
+    (the whole run without markers), and the region's Lanczos steps."""
     con = sqlite3.connect(db)
+    region, main = _region(_dispatches(con))
+    keep = {d[0] for d in region}
     acc = collections.defaultdict(float)
     calls = collections.Counter()
     rows = con.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection "
                        "order by dispatch_id").fetchall()
-    step_no = 0          # index of the step the current dispatch belongs to
-    seen_step = False
-    for _, kname, ctr, val in rows:
-        if name_filter and not any(k in kname for k in name_filter):
-            continue
-        if "k_normalize" in kname and seen_step:
-            step_no += 1
-            seen_step = False
-        if "k_lanczos_step" in kname:
-            seen_step = True
-        if step_no < skip_steps or (max_steps and step_no >= skip_steps + max_steps):
+    for did, kname, ctr, val in rows:
+        if did not in keep or (name_filter and not any(k in kname for k in name_filter)):
             continue
         acc[(kname, ctr)] += float(val)
         calls[(kname, ctr)] += 1
-    return acc, calls
+    return acc, calls, _logical_steps(region, main)
 
 
 def cmd_traffic(args):
-    fetch, fcalls = _counter(args.fetch_db, STEP_KERNELS, args.skip_steps, args.max_steps)
-    write, wcalls = _counter(args.write_db, STEP_KERNELS, args.skip_steps, args.max_steps)
-    cf, _ = _counter(args.copy_fetch_db, ("copyBuffer",))
-    cw, _ = _counter(args.copy_write_db, ("copyBuffer",))
+    fetch, _, steps = _counter(args.fetch_db, UNIT_KERNELS)
+    write, _, steps_w = _counter(args.write_db, UNIT_KERNELS)
+    if steps != steps_w:
+        sys.exit("the FETCH_SIZE and WRITE_SIZE runs hold %d and %d Lanczos steps" % (steps, steps_w))
+    cf, _, _ = _counter(args.copy_fetch_db, ("copyBuffer",))
+    cw, _, _ = _counter(args.copy_write_db, ("copyBuffer",))
     # calibration: what the counters read (KiB per dispatch) for a plain copy
     # of known size, one dispatch per copy
     copy_fetch_kib = sum(cf.values()) / max(args.copies, 1)
     copy_write_kib = sum(cw.values()) / max(args.copies, 1)
     f_scale = args.copy_bytes / (copy_fetch_kib * 1024.0)
     w_scale = args.copy_bytes / (copy_write_kib * 1024.0)
-    steps = sum(c for (k, _), c in fcalls.items() if "k_lanczos_step" in k)
     fetch_kib = sum(fetch.values())
     write_kib = sum(write.values())
     per_step = (fetch_kib * f_scale + write_kib * w_scale) * 1024.0 / max(steps, 1)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
-    d = {"workload": args.workload, "kernel": "Lanczos step unit (" + ", ".join(STEP_KERNELS) + ")",
+    d = {"workload": args.workload, "kernel": "Lanczos step unit (" + ", ".join(UNIT_KERNELS) + ")",
          "steps": steps, "fetch_kib_total": fetch_kib, "write_kib_total": write_kib,
          "copy_calibration": {"bytes_each_way": args.copy_bytes, "fetch_kib": copy_fetch_kib,
                               "write_kib": copy_write_kib, "fetch_scale": f_scale, "write_scale": w_scale},
          "hbm_bytes_per_launch": per_step, "kernel_source_hash": bench.kernel_source_hash(),
-         "skip_steps": args.skip_steps, "max_steps": args.max_steps, "command": args.cmd}
+         "command": args.cmd}
     with open(args.out, "w") as fh:
         json.dump(d, fh, indent=1)
     print(json.dumps(d, indent=1))
@@ -143,9 +205,16 @@ def cmd_counters(args):
     """Per-dispatch averages of the counters of several --pmc runs for the
     dispatches whose kernel name contains --kernel, and the ratios read from
     them."""
+    if args.kernel == "auto":
+        # the step kernel with the most dispatches in the first run's timed region
+        region, _ = _region(_dispatches(sqlite3.connect(args.dbs[0])))
+        top = collections.Counter(d[1] for d in region if "k_lanczos_step" in d[1]).most_common(1)
+        if not top:
+            sys.exit("no step kernel in the timed region of " + args.dbs[0])
+        args.kernel = _short(top[0][0])
     tab = {}
     for db in args.dbs:
-        acc, calls = _counter(db, (args.kernel,))
+        acc, calls, _ = _counter(db, (args.kernel,))
         per = collections.defaultdict(float)
         cnt = collections.Counter()
         for (k, ctr), v in acc.items():
@@ -191,14 +260,13 @@ def main():
     s.add_argument("db")
     s.add_argument("out")
     s.add_argument("--cmd", required=True)
+    s.add_argument("--bench-line", help="output of the profiled bench.py run (its JSON line)")
     t = sub.add_parser("traffic")
     for k in ("fetch_db", "write_db", "copy_fetch_db", "copy_write_db", "out"):
         t.add_argument(k)
     t.add_argument("--workload", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--copies", type=int, default=3)
-    t.add_argument("--skip-steps", type=int, default=0, help="leave out the first Lanczos steps (autotuning)")
-    t.add_argument("--max-steps", type=int, default=0, help="count this many steps after those (0: all)")
     t.add_argument("--cmd", required=True)
     v = sub.add_parser("serve")
     v.add_argument("line")
