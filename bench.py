@@ -35,7 +35,8 @@ and `estimate_p50_ms` / `estimate_p99_ms` of the line are back-to-back
 large Hutch++ estimates, not served queries.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload large|tiny|probing|batch|serve|probing-eps|rational]
+                       [--workload large|tiny|probing|batch|serve|probing-eps|rational|
+                                   hutchpp-adaptive]
 """
 import argparse
 import hashlib
@@ -533,6 +534,53 @@ def run_rational(args):
                       "config": {"workload": "rational_path1000_grid40x40_tol1e-6"}, "cases": cases}), flush=True)
 
 
+def run_hutchpp_adaptive(args):
+    """Adaptive Hutch++ (vne_hutchpp_adaptive) on the large workload's graph
+    (BA n = 2e5, FP32 vectors, k = 60 steps per Krylov run) at relative
+    targets 1e-2 (the paper's setting for large matrices) and 1e-3 with
+    delta = 1e-2, beside the fixed 128 + 128 Hutch++ of the large workload.
+    Wall-clock per estimate: median of --steps calls after --warmup (plans
+    and tiles are made in the warm-up)."""
+    import numpy as np
+    import paper_2212_09642_amd as vne
+    from synth import workloads
+    w = workloads.large()
+    g = vne.laplacian_from_edges(w["n_nodes"], w["edges"], np.float32)
+    ctx = vne.Context(0)
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    k, seed, mode = w["k"], w["probe_seed"], vne.MODE_DESING
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 1)):
+            out = fn()
+        ts = []
+        for _ in range(max(args.steps, 1)):
+            t0 = time.perf_counter()
+            out = fn()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return out, float(np.median(ts))
+
+    m = w["n_sketch"] + w["n_hutch"]
+    fixed, fixed_ms = timed(lambda: ctx.estimate(gid, vne.PROBE_HUTCHPP, m, k, mode, seed=seed,
+                                                 n_sketch=w["n_sketch"], want_coeffs=False))
+    rows = []
+    for eps in (1e-2, 1e-3):
+        out, ms = timed(lambda: ctx.hutchpp_adaptive(gid, k, rel_eps=eps, delta=1e-2, mode=mode, seed=seed))
+        rows.append(dict(rel_eps=eps, delta=1e-2, ms=round(ms, 3), n_sketch=out["n_sketch"], n_hutch=out["n_hutch"],
+                         rounds=[(r["nr"], r["nh"]) for r in out["rounds"]], krylov_runs=out["krylov_runs"],
+                         estimate=out["estimate"], std_error=out["std_error"], eps_hat=out["eps_hat"],
+                         capped=out["capped"],
+                         vs_fixed_sigmas=abs(out["estimate"] - fixed["estimate"]) / max(out["std_error"], 1e-300)))
+        print(json.dumps(rows[-1]), flush=True)
+    ctx.close()
+    print(json.dumps({"metric": "adaptive_hutchpp_ms_per_estimate", "unit": "ms", "n_gpus": 1, "dtype": "f32",
+                      "data": "synthetic", "higher_is_better": False,
+                      "config": {"workload": w["name"].replace("hutchpp256", "hutchpp_adaptive"), "k": k},
+                      "fixed_hutchpp_128_128": {"ms": round(fixed_ms, 3), "estimate": fixed["estimate"],
+                                                "krylov_runs": 128 + 256},
+                      "adaptive": rows}), flush=True)
+
+
 def ring_lattice_entropy(n, k):
     """Exact S(rho) of the ring lattice Laplacian (circulant: eigenvalues
     k - 2 sum_{r=1..k/2} cos(2 pi j r / n))."""
@@ -717,6 +765,9 @@ def main():
         return
     if args.workload == "rational":
         run_rational(args)
+        return
+    if args.workload == "hutchpp-adaptive":
+        run_hutchpp_adaptive(args)
         return
 
     w, g, spec = build_workload(args.workload, args.reorder)

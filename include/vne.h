@@ -345,6 +345,66 @@ typedef struct {
 vne_status vne_probing_select(const double *T, double eps_hat, double n, double lambda_ub, int32_t d_max,
                               int32_t use_bound, vne_distance_choice *out);
 
+/* Adaptive Hutch++: Hutch++ (eq. (3.9)) with the sketch width N_r and the
+ * Hutchinson count N_H chosen for a target of the form of eq. (3.10),
+ * P[|estimate - tr f(A)| >= eps_hat] <= delta (Section 3.2; the adaptive
+ * Hutch++ implementation of Section 5).  The paper takes this algorithm
+ * from elsewhere without stating it; the rule below is this library's
+ * reading of what the paper fixes (eps_hat = eps/2 tr f(A) for a relative
+ * target, at least three products with f(A), N_r and N_H chosen for the
+ * least effort N_r + (N_r + N_H)):
+ *  - rounds of sketch width N_r = r_first, 2 r_first, 4 r_first, ... (at
+ *    most r_max): Omega = the first N_r Rademacher hash columns of `seed`
+ *    (the same columns in every round), Q an orthonormal basis of
+ *    f(A) Omega (eq. (4.3)), n_pilot deflated forms on the Rademacher
+ *    hash columns 128, 129, ... of `seed`;
+ *  - round estimate t = sum of the Q forms + mean of the deflated forms;
+ *    eps_hat = abs_eps, or rel_eps / 2 |t|;
+ *  - N_H = max(n_pilot, ceil(min((z s / eps_hat)^2, 1e15))), s the sample
+ *    standard deviation of the deflated forms, z the two-sided normal
+ *    quantile of delta; effort 2 N_r + N_H;
+ *  - a next round runs only while its effort could still be below the least
+ *    so far (2 N_r' + n_pilot < least effort); the round of least effort is
+ *    kept (the earlier on ties);
+ *  - final: Hutch++ with the kept N_r and min(N_H, n_h_max) deflated forms
+ *    (their first n_pilot columns are the pilot's).
+ * Every Krylov run takes k_steps Lanczos steps (the caller picks k_steps
+ * for the Krylov share of the error, e.g. with vne_plan_steps).  The round
+ * statistics (mean, standard deviation, counts) are computed on the host
+ * from the device forms.  quad (host [quad_cap], may be NULL) receives the
+ * final forms, the N_r Q forms first.  Errors: VNE_EINVAL for bad
+ * arguments, VNE_ENOMEM when a round's workspace exceeds the budget,
+ * VNE_ENUMERIC as for vne_entropy_estimate. */
+typedef struct {
+    double rel_eps;             /* relative target, 0 < rel_eps < 1 (used when abs_eps == 0) */
+    double abs_eps;             /* absolute tolerance eps_hat (> 0: overrides rel_eps)       */
+    double delta;               /* failure probability, 0 < delta < 1                        */
+    int32_t k_steps;            /* Lanczos steps of every Krylov run, 1..128                 */
+    int32_t n_pilot;            /* deflated forms per round, 2..1024 (0: 16)                 */
+    int32_t r_first;            /* first sketch width, 1..128 (0: 3)                         */
+    int32_t r_max;              /* widest sketch, r_first..128 (0: max(96, r_first))         */
+    int32_t n_h_max;            /* most deflated forms of the final run, n_pilot..2^20
+                                   (0: 4096)                                                 */
+    uint32_t mode;              /* VNE_MODE_* bits                                           */
+    uint64_t seed;
+} vne_hutchpp_cfg;
+
+#define VNE_HUTCHPP_MAX_ROUNDS 8
+typedef struct {
+    double estimate;            /* final Hutch++ estimate                                    */
+    double std_error;           /* s / sqrt(N_H) of the final deflated forms                 */
+    double eps_hat;             /* tolerance of the kept round                               */
+    int32_t n_sketch, n_hutch;  /* kept N_r; N_H of the final run                            */
+    int32_t capped;             /* 1: n_h_max cut the kept round's N_H                       */
+    int32_t rounds;             /* rounds run                                                */
+    int32_t round_nr[VNE_HUTCHPP_MAX_ROUNDS], round_nh[VNE_HUTCHPP_MAX_ROUNDS];
+    double round_estimate[VNE_HUTCHPP_MAX_ROUNDS], round_sd[VNE_HUTCHPP_MAX_ROUNDS];
+    int64_t krylov_runs;        /* Lanczos runs made in all (rounds and final)               */
+    double ms;                  /* wall time of the call                                     */
+} vne_hutchpp_result;
+vne_status vne_hutchpp_adaptive(vne_ctx *ctx, int32_t graph_id, const vne_hutchpp_cfg *cfg,
+                                vne_hutchpp_result *res, double *quad, int32_t quad_cap);
+
 /* A-posteriori error bracket of Theorem 4.8 for the polynomial Krylov
  * method, per column of a result (host arrays laid out as in vne_result:
  * alpha, beta [m*k], k_eff, norm2 [m]) after min(k_eff[c], steps) steps:

@@ -30,9 +30,11 @@ reading of those facts, not that algorithm: parity unpinned against it.
   (the earlier on ties).  (Stopping at the first round whose effort rose
   instead would end on the noise of a 16-form standard deviation.)
 * Final estimate: Hutch++ with the kept N_r and min(N_H, n_h_max) deflated
-  forms, whose first n_pilot columns are the pilot's; `capped` says that
+  forms, whose first n_pilot columns are the pilot's (when that is the last
+  round with the pilot's count, the round itself); `capped` says that
   n_h_max cut the count (the target of eq. (3.10) is then not met by the
-  rule).
+  rule).  `krylov_runs` counts the Krylov runs made: 2 N_r + n_pilot per
+  round and 2 N_r + N_H for a final run that is not the last round.
 
 Pinned by (tests/test_oracle_adaptive_hutchpp.py): the normal quantile
 against its textbook values, the count and round rules on hand-worked
@@ -81,13 +83,15 @@ def adaptive_hutchpp(A, node_ids, seed, k, eps=1e-2, eps_abs=0.0, delta=1e-2, n_
     """Adaptive Hutch++ estimate of tr f(A) by the reading above.
 
     Returns dict(estimate, n_sketch, n_hutch, std_error, eps_hat, capped,
-    rounds=[dict(nr, estimate, sd, eps_hat, nh, effort)], psi)."""
+    krylov_runs, rounds=[dict(nr, estimate, sd, eps_hat, nh, effort)], psi)."""
     tau = breakdown_tau(fp64_tau)
     z = normal_quantile_two_sided(delta)
     rounds = []
+    runs = 0
     nr = r_first
     while True:
         est, psi = _run(A, node_ids, seed, nr, g_col0, n_pilot, k, tau, desing)
+        runs += 2 * nr + n_pilot
         sd = float(np.std(psi[nr:], ddof=1))
         eh = eps_abs if eps_abs > 0 else 0.5 * eps * abs(est)
         nh = hutch_count(sd, eh, z, n_pilot)
@@ -96,9 +100,12 @@ def adaptive_hutchpp(A, node_ids, seed, k, eps=1e-2, eps_abs=0.0, delta=1e-2, n_
         if nr >= r_max or 2 * nxt + n_pilot >= min(r["effort"] for r in rounds):
             break
         nr = nxt
-    best = rounds[kept_round([r["effort"] for r in rounds])]
+    ib = kept_round([r["effort"] for r in rounds])
+    best = rounds[ib]
     nr, nh = best["nr"], min(best["nh"], n_h_max)
-    est, psi = _run(A, node_ids, seed, nr, g_col0, nh, k, tau, desing)
+    if ib + 1 != len(rounds) or nh != n_pilot:
+        est, psi = _run(A, node_ids, seed, nr, g_col0, nh, k, tau, desing)
+        runs += 2 * nr + nh
     q = psi[nr:]
     return dict(estimate=est, n_sketch=nr, n_hutch=nh, std_error=float(np.std(q, ddof=1) / math.sqrt(nh)),
-                eps_hat=best["eps_hat"], capped=best["nh"] > n_h_max, rounds=rounds, psi=psi)
+                eps_hat=best["eps_hat"], capped=best["nh"] > n_h_max, krylov_runs=runs, rounds=rounds, psi=psi)

@@ -39,7 +39,7 @@ EXPORTS = ["vne_version", "vne_laplacian_from_edges", "vne_csr_validate", "vne_c
            "vne_server_start", "vne_server_submit", "vne_server_poll", "vne_server_stats",
            "vne_server_stop", "vne_plan_steps", "vne_plan_probes", "vne_error_bounds",
            "vne_entropy_estimate_adaptive", "vne_entropy_probing", "vne_probing_select", "vne_last_plan",
-           "vne_entropy_estimate_noalloc", "vne_rational_quadforms"]
+           "vne_entropy_estimate_noalloc", "vne_rational_quadforms", "vne_hutchpp_adaptive"]
 
 
 class VneError(RuntimeError):
@@ -84,6 +84,26 @@ class _RationalOut(ctypes.Structure):
     _fields_ = [("quad", ctypes.c_void_p), ("psi_steps", ctypes.c_void_p), ("apps_steps", ctypes.c_void_p),
                 ("switch_step", ctypes.c_void_p), ("basis", ctypes.c_void_p), ("norm2", ctypes.c_void_p),
                 ("err_steps", ctypes.c_void_p), ("cg_iterations", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
+HUTCHPP_MAX_ROUNDS = 8
+
+
+class _HutchppCfg(ctypes.Structure):
+    _fields_ = [("rel_eps", ctypes.c_double), ("abs_eps", ctypes.c_double), ("delta", ctypes.c_double),
+                ("k_steps", ctypes.c_int32), ("n_pilot", ctypes.c_int32), ("r_first", ctypes.c_int32),
+                ("r_max", ctypes.c_int32), ("n_h_max", ctypes.c_int32), ("mode", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _HutchppResult(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("std_error", ctypes.c_double), ("eps_hat", ctypes.c_double),
+                ("n_sketch", ctypes.c_int32), ("n_hutch", ctypes.c_int32), ("capped", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("round_nr", ctypes.c_int32 * HUTCHPP_MAX_ROUNDS),
+                ("round_nh", ctypes.c_int32 * HUTCHPP_MAX_ROUNDS),
+                ("round_estimate", ctypes.c_double * HUTCHPP_MAX_ROUNDS),
+                ("round_sd", ctypes.c_double * HUTCHPP_MAX_ROUNDS), ("krylov_runs", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
 
 
 class _ProbingCfg(ctypes.Structure):
@@ -207,6 +227,8 @@ def lib():
         L.vne_entropy_estimate_noalloc.argtypes = [vp, i32, P(_Probes), i32, ctypes.c_uint32, P(_Result)]
         L.vne_rational_quadforms.restype = i32
         L.vne_rational_quadforms.argtypes = [vp, i32, P(_Probes), ctypes.c_uint32, P(_RationalCfg), P(_RationalOut)]
+        L.vne_hutchpp_adaptive.restype = i32
+        L.vne_hutchpp_adaptive.argtypes = [vp, i32, P(_HutchppCfg), P(_HutchppResult), P(dbl), i32]
         L.vne_last_plan.restype = i32
         L.vne_last_plan.argtypes = [vp, P(i32), P(i32)]
         _LIB = L
@@ -564,6 +586,27 @@ class Context:
                                                  ctypes.byref(o)))
         return dict(quad=quad, psi_steps=ps, apps_steps=ap, err_steps=es, switch_step=sw, basis=bs, norm2=nrm,
                     cg_iterations=o.cg_iterations, ms=o.ms)
+
+    def hutchpp_adaptive(self, gid, k, rel_eps=1e-2, abs_eps=0.0, delta=1e-2, mode=MODE_DESING, seed=0,
+                         n_pilot=0, r_first=0, r_max=0, n_h_max=0, quad_cap=0):
+        """Adaptive Hutch++ (vne_hutchpp_adaptive): sketch width and Hutchinson
+        count picked by the library's rule for P[|err| >= eps_hat] <= delta.
+        Returns dict(estimate, std_error, eps_hat, n_sketch, n_hutch, capped,
+        rounds=[dict(nr, nh, estimate, sd)], krylov_runs, ms[, quad])."""
+        cfg = _HutchppCfg(float(rel_eps), float(abs_eps), float(delta), int(k), int(n_pilot), int(r_first),
+                          int(r_max), int(n_h_max), int(mode), int(seed))
+        r = _HutchppResult()
+        quad = np.zeros(quad_cap) if quad_cap > 0 else None
+        self._chk(self._L.vne_hutchpp_adaptive(self._h, gid, ctypes.byref(cfg), ctypes.byref(r),
+                                               None if quad is None else quad.ctypes.data_as(
+                                                   ctypes.POINTER(ctypes.c_double)), int(quad_cap)))
+        out = dict(estimate=r.estimate, std_error=r.std_error, eps_hat=r.eps_hat, n_sketch=r.n_sketch,
+                   n_hutch=r.n_hutch, capped=bool(r.capped), krylov_runs=r.krylov_runs, ms=r.ms,
+                   rounds=[dict(nr=r.round_nr[i], nh=r.round_nh[i], estimate=r.round_estimate[i],
+                                sd=r.round_sd[i]) for i in range(min(r.rounds, HUTCHPP_MAX_ROUNDS))])
+        if quad is not None:
+            out["quad"] = quad[:min(quad_cap, r.n_sketch + r.n_hutch)]
+        return out
 
     def last_plan(self):
         """Column tile and padded width of the last estimate's Lanczos run."""

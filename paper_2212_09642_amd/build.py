@@ -10,7 +10,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvne.so")
 
 HOST_SOURCES = ["host_graph.cpp", "coloring.cpp", "serve_host.cpp", "serve_core.cpp", "probing_host.cpp"]
-HIP_SOURCES = ["kernels.hip", "runtime.hip", "server.hip", "probing.hip", "noalloc.hip", "rational.hip"]
+HIP_SOURCES = ["kernels.hip", "runtime.hip", "server.hip", "probing.hip", "noalloc.hip", "rational.hip",
+               "hutchpp_adaptive.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

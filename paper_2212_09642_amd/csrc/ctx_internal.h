@@ -208,6 +208,13 @@ vne_status check_flags(vne_ctx *c, int32_t fl);
 vne_status make_probe_spec(vne_ctx *c, GraphSet *set, Plan *p, const vne_probes *pr, int m_max, bool fp64,
                            ProbeSpec *ps, int *combine_kind);
 vne_status collect_timing(vne_ctx *c);
+// Hutch++ (eq. (3.9)) on one graph: sketch Omega = Rademacher hash columns
+// [0, nr) of `seed`, nh Hutchinson vectors on hash columns [g_col0,
+// g_col0 + nh).  Leaves the forms of [Q | G~] in (*q_out)->psi and their
+// combination in (*q_out)->estimate on the context's stream (nothing is
+// copied to the host); *sk_out (may be NULL) receives the sketch's plan.
+vne_status hutchpp_run(vne_ctx *c, GraphSet *set, int nr, int nh, int g_col0, int k, uint64_t seed, bool fp64,
+                       bool desing, Plan **sk_out, Plan **q_out);
 vne_status check_mode(vne_ctx *c, uint32_t mode);
 
 }  // namespace rt

@@ -1,0 +1,173 @@
+// Adaptive Hutch++ (Section 3.2, the tail bound eq. (3.10); the adaptive
+// Hutch++ implementation of Section 5).  Host driver: every round is a
+// Hutch++ run of the device path (sketch Lanczos with a kept basis, f(A)
+// Omega by eq. (4.3), CholeskyQR2, projection, quadratic forms of
+// [Q | G~]); the rule that picks the sketch width and the Hutchinson count
+// reads the round's forms on the host.  The rule is stated with its
+// declaration in vne.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx_internal.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace vne;
+using namespace vne::rt;
+
+namespace {
+
+// hash column of the first deflated (Hutchinson) vector: past every sketch
+// width, so the deflated vectors do not depend on N_r
+constexpr int kGCol0 = 128;
+
+// z with P(|N(0, 1)| >= z) = delta: the root of erfc(z / sqrt 2) = delta on
+// [0, 40], by bisection (erfc decreases; 200 halvings end at the double
+// spacing)
+double normal_quantile_two_sided(double delta) {
+    double lo = 0.0, hi = 40.0;
+    for (int i = 0; i < 200 && hi > lo; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (std::erfc(mid / std::sqrt(2.0)) > delta)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// deflated forms a round asks for
+int64_t hutch_count(double s, double eps_hat, double z, int n_pilot) {
+    if (!(s > 0.0)) return n_pilot;
+    double x = eps_hat > 0.0 ? (z * s / eps_hat) * (z * s / eps_hat) : 1e15;
+    x = std::min(x, 1e15);
+    return std::max<int64_t>((int64_t)std::ceil(x), n_pilot);
+}
+
+// sample standard deviation (n - 1 in the denominator), two passes
+double sample_sd(const double *x, int n) {
+    double mean = 0.0;
+    for (int i = 0; i < n; ++i) mean += x[i];
+    mean /= n;
+    double ss = 0.0;
+    for (int i = 0; i < n; ++i) ss += (x[i] - mean) * (x[i] - mean);
+    return std::sqrt(ss / (n - 1));
+}
+
+struct RoundOut {
+    double estimate = 0.0;
+    std::vector<double> psi;
+};
+
+vne_status round_run(vne_ctx *c, GraphSet *set, int nr, int nh, int k, uint64_t seed, bool fp64, bool desing,
+                     RoundOut *ro) {
+    Plan *sk = nullptr, *q = nullptr;
+    VNE_TRY(hutchpp_run(c, set, nr, nh, kGCol0, k, seed, fp64, desing, &sk, &q));
+    hipStream_t s = c->stream;
+    const int m = nr + nh;
+    ro->psi.assign(m, 0.0);
+    int32_t fl[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(&ro->estimate, q->estimate.p, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(ro->psi.data(), q->psi.p, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(&fl[0], q->flags.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(&fl[1], sk->flags.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return check_flags(c, fl[0] | fl[1]);
+}
+
+}  // namespace
+
+extern "C" vne_status vne_hutchpp_adaptive(vne_ctx *c, int32_t gid, const vne_hutchpp_cfg *cfg,
+                                           vne_hutchpp_result *res, double *quad, int32_t quad_cap) {
+    if (!c) return VNE_EINVAL;
+    std::lock_guard<std::recursive_mutex> lock(c->mu);
+    c->err.clear();
+    if (!cfg || !res) return fail(c, VNE_EINVAL, "NULL argument");
+    if (!get_graph(c, gid)) return fail(c, VNE_EINVAL, "unknown graph id");
+    const int k = cfg->k_steps;
+    const int n_pilot = cfg->n_pilot == 0 ? 16 : cfg->n_pilot;
+    const int r_first = cfg->r_first == 0 ? 3 : cfg->r_first;
+    const int r_max = cfg->r_max == 0 ? std::max(96, r_first) : cfg->r_max;
+    const int n_h_max = cfg->n_h_max == 0 ? 4096 : cfg->n_h_max;
+    if (k < 1 || k > kMaxSteps) return fail(c, VNE_EINVAL, "k_steps must be in [1, 128]");
+    if (!(cfg->delta > 0.0 && cfg->delta < 1.0)) return fail(c, VNE_EINVAL, "delta must be in (0, 1)");
+    if (!(cfg->abs_eps >= 0.0) || !std::isfinite(cfg->abs_eps))
+        return fail(c, VNE_EINVAL, "abs_eps must be finite and >= 0");
+    if (cfg->abs_eps == 0.0 && !(cfg->rel_eps > 0.0 && cfg->rel_eps < 1.0))
+        return fail(c, VNE_EINVAL, "rel_eps must be in (0, 1) when abs_eps is 0");
+    if (n_pilot < 2 || n_pilot > 1024) return fail(c, VNE_EINVAL, "n_pilot must be in [2, 1024]");
+    if (r_first < 1 || r_first > 128) return fail(c, VNE_EINVAL, "r_first must be in [1, 128]");
+    if (r_max < r_first || r_max > 128) return fail(c, VNE_EINVAL, "r_max must be in [r_first, 128]");
+    if (n_h_max < n_pilot || n_h_max > (1 << 20)) return fail(c, VNE_EINVAL, "n_h_max must be in [n_pilot, 2^20]");
+    if (quad_cap < 0 || (quad_cap > 0 && !quad)) return fail(c, VNE_EINVAL, "quad_cap > 0 needs a quad buffer");
+    VNE_TRY(check_mode(c, cfg->mode));
+    HIP_TRY(c, hipSetDevice(c->device));
+    GraphSet *set = nullptr;
+    VNE_TRY(get_set(c, {gid}, &set));
+    const bool fp64 = (cfg->mode & VNE_MODE_F64) != 0;
+    const bool desing = (cfg->mode & VNE_MODE_DESING) != 0;
+    if (desing && !set->zero_rowsum)
+        return fail(c, VNE_EINVAL, "VNE_MODE_DESING needs a matrix whose rows sum to zero (A 1 = 0)");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::memset(res, 0, sizeof(*res));
+    const double z = normal_quantile_two_sided(cfg->delta);
+
+    struct Round {
+        int nr;
+        int64_t nh, effort;
+        double estimate, sd, eps_hat;
+    };
+    std::vector<Round> rounds;
+    int64_t runs = 0;
+    int nr = r_first;
+    RoundOut ro;
+    for (;;) {
+        VNE_TRY(round_run(c, set, nr, n_pilot, k, cfg->seed, fp64, desing, &ro));
+        runs += 2 * nr + n_pilot;
+        const double sd = sample_sd(ro.psi.data() + nr, n_pilot);
+        const double eh = cfg->abs_eps > 0.0 ? cfg->abs_eps : 0.5 * cfg->rel_eps * std::fabs(ro.estimate);
+        const int64_t nh = hutch_count(sd, eh, z, n_pilot);
+        rounds.push_back({nr, nh, 2 * nr + nh, ro.estimate, sd, eh});
+        int64_t least = rounds[0].effort;
+        for (const Round &r : rounds) least = std::min(least, r.effort);
+        const int next = std::min(2 * nr, r_max);
+        if (nr >= r_max || 2 * (int64_t)next + n_pilot >= least) break;
+        nr = next;
+    }
+    size_t best = 0;
+    for (size_t i = 1; i < rounds.size(); ++i)
+        if (rounds[i].effort < rounds[best].effort) best = i;
+    const Round &kb = rounds[best];
+    const int nh_final = (int)std::min<int64_t>(kb.nh, n_h_max);
+    // the last round with the pilot's count is the final run itself (same
+    // columns, same plans: the device would repeat it bit for bit)
+    if (best + 1 != rounds.size() || nh_final != n_pilot) {
+        VNE_TRY(round_run(c, set, kb.nr, nh_final, k, cfg->seed, fp64, desing, &ro));
+        runs += 2 * kb.nr + nh_final;
+    }
+
+    res->estimate = ro.estimate;
+    res->std_error = sample_sd(ro.psi.data() + kb.nr, nh_final) / std::sqrt((double)nh_final);
+    res->eps_hat = kb.eps_hat;
+    res->n_sketch = kb.nr;
+    res->n_hutch = nh_final;
+    res->capped = kb.nh > n_h_max ? 1 : 0;
+    res->rounds = (int32_t)rounds.size();
+    for (size_t i = 0; i < rounds.size() && i < VNE_HUTCHPP_MAX_ROUNDS; ++i) {
+        res->round_nr[i] = rounds[i].nr;
+        res->round_nh[i] = (int32_t)std::min<int64_t>(rounds[i].nh, INT32_MAX);
+        res->round_estimate[i] = rounds[i].estimate;
+        res->round_sd[i] = rounds[i].sd;
+    }
+    res->krylov_runs = runs;
+    if (quad && quad_cap > 0)
+        std::memcpy(quad, ro.psi.data(), (size_t)std::min<int64_t>(quad_cap, (int64_t)ro.psi.size()) * 8);
+    res->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return VNE_OK;
+}

@@ -917,9 +917,9 @@ vne_status copy_out(vne_ctx *c, Plan *p, const int32_t *m, const int32_t *k, vne
     return check_flags(c, fl[0] | fl[1]);
 }
 
-vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int k, bool fp64, bool desing,
-                            vne_result *out) {
-    const int nr = pr->n_sketch, m = pr->m, nh = m - nr;
+vne_status hutchpp_run(vne_ctx *c, GraphSet *set, int nr, int nh, int g_col0, int k, uint64_t seed, bool fp64,
+                       bool desing, Plan **sk_out, Plan **q_out) {
+    const int m = nr + nh;
     if (nr < 1 || nh < 0 || nr > 128) return fail(c, VNE_ENOTSUP, "Hutch++ needs 1 <= n_sketch <= min(m, 128)");
     const size_t es = fp64 ? 8 : 4;
     Plan *sk = nullptr, *q = nullptr;
@@ -953,7 +953,7 @@ vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int
     // 1. sketch: k Lanczos steps on Omega (kept basis), then Y = f(A) Omega by eq. (4.3)
     ProbeSpec ps;
     ps.gen = GEN_RADEMACHER;
-    ps.seeds = {pr->seed};
+    ps.seeds = {seed};
     // column tiles of both Lanczos runs, timed on Rademacher blocks of their
     // widths (the speed of a step does not depend on the values; the runs
     // below probe their own blocks again)
@@ -965,8 +965,9 @@ vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int
     const int64_t step_stride = n * sk->m_pad;
     HIP_TRY(c, launch_reconstruct(sk->Vstore.p, fp64, step_stride, sk->m_pad, (const double *)q->S.p,
                                   (const double *)sk->norm2.p, k, (int32_t)n, nr, q->B.p, m, s));
-    // 2. G block, raw +-1 in the columns after the sketch
-    if (nh > 0) HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)n, nh, m, nr, nr, pr->seed, keys, s));
+    // 2. G block, raw +-1 in the columns after the sketch (hash columns
+    // g_col0, g_col0 + 1, ...)
+    if (nh > 0) HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)n, nh, m, nr, g_col0, seed, keys, s));
     // 3. Q = orth(Y) by CholeskyQR2 (FP64 Gram and triangular factors, two
     // passes, in place): the first pass leaves an orthogonality error of
     // about u cond(Y)^2, the second brings it to the rounding of Q's storage
@@ -990,6 +991,18 @@ vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int
     pq.ld_dense = m;
     VNE_TRY(run_lanczos(c, set, q, pq, desing));
     HIP_TRY(c, launch_combine((const double *)q->psi.p, m, 2, nr, (double *)q->estimate.p, s));
+    if (sk_out) *sk_out = sk;
+    *q_out = q;
+    return VNE_OK;
+}
+
+vne_status estimate_hutchpp(vne_ctx *c, GraphSet *set, const vne_probes *pr, int k, bool fp64, bool desing,
+                            vne_result *out) {
+    const int nr = pr->n_sketch, m = pr->m;
+    if (nr < 1 || m < nr || nr > 128) return fail(c, VNE_ENOTSUP, "Hutch++ needs 1 <= n_sketch <= min(m, 128)");
+    Plan *sk = nullptr, *q = nullptr;
+    // the Hutchinson columns follow the sketch's in the hash (columns nr .. m - 1)
+    VNE_TRY(hutchpp_run(c, set, nr, m - nr, nr, k, pr->seed, fp64, desing, &sk, &q));
     const int32_t mm = m, kk = k;
     return copy_out(c, q, &mm, &kk, out, sk);
 }

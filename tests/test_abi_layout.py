@@ -19,7 +19,8 @@ PAIRS = {
     "vne_probing_result": vne._ProbingResult, "vne_distance_choice": vne._DistanceChoice,
     "vne_server_cfg": vne._ServerCfg, "vne_query": vne._Query, "vne_query_result": vne._QueryResult,
     "vne_server_info": vne._ServerInfo, "vne_rational_cfg": vne._RationalCfg,
-    "vne_rational_out": vne._RationalOut,
+    "vne_rational_out": vne._RationalOut, "vne_hutchpp_cfg": vne._HutchppCfg,
+    "vne_hutchpp_result": vne._HutchppResult,
 }
 
 

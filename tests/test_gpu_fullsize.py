@@ -9,6 +9,9 @@ on sampled outputs the oracle computes one by one.
   G~ form.  The 256-wide Rademacher block through the same step kernels:
   columns 0, 77, 200, 255 against the oracle, and the Hutch++ estimate
   within five standard errors of that Hutchinson estimate.
+* the same graph under adaptive Hutch++ (relative target 1e-2, delta 1e-2)
+  against the oracle's run of the same rule, read from tests/golden/
+  hutchpp_adaptive_large.json (written by make_hutchpp_adaptive_large.py).
 * probing: WS n = 1e6 (k = 10, p = 0.1), distance-2 colouring, k = 80:
   colours 0, 11 and the last one against the oracle; the colouring itself is
   compared bit for bit with the oracle elsewhere (CPU, slow).
@@ -94,6 +97,52 @@ def test_large_hutchpp_against_oracle(ctx):
     rq = _rel(out["quad"][:nr], psi[:nr])
     _say("   Q forms one by one (FP32 sketch; not asserted): max rel err %.3e" % rq.max())
     assert np.array_equal(out["k_eff"], np.array(gold["k_eff"]))
+    ctx.release(gid)
+
+
+def test_large_adaptive_hutchpp_against_oracle(ctx):
+    """Adaptive Hutch++ on the bench's graph (BA n = 2e5, relative target
+    1e-2, delta = 1e-2, k = 60, FP32 vectors) against the oracle's run of the
+    same rule, read from tests/golden/hutchpp_adaptive_large.json (written by
+    tests/golden/make_hutchpp_adaptive_large.py, which calls only the
+    oracle): each round's width and count exactly, its estimate, and the
+    sample standard deviation of its pilot forms within ||dq|| / sqrt(n - 1)
+    (dq: the per-form bars); the final estimate, the sum over Q and every
+    deflated form within the usual bars."""
+    import json
+    import math
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hutchpp_adaptive_large.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    w = workloads.large()
+    _say("case full size: adaptive Hutch++ BA n=2e5, rel_eps %g, k=60 against the oracle" % gold["rel_eps"])
+    g = vne.laplacian_from_edges(w["n_nodes"], w["edges"], np.float32)
+    assert (g["n"], len(g["col_idx"]), w["k"], w["probe_seed"]) == (gold["n"], gold["nnz"], gold["k"],
+                                                                     gold["probe_seed"])
+    gid = ctx.register(g["row_ptr"], g["col_idx"], g["values"], g["scale"], node_keys=g["node_ids"])
+    out = ctx.hutchpp_adaptive(gid, w["k"], rel_eps=gold["rel_eps"], delta=gold["delta"], mode=vne.MODE_DESING,
+                               seed=w["probe_seed"], quad_cap=4096)
+    assert [(r["nr"], r["nh"]) for r in out["rounds"]] == [(r["nr"], r["nh"]) for r in gold["rounds"]]
+    for gr, o in zip(out["rounds"], gold["rounds"]):
+        est = o["estimate"]
+        _assert_within(abs(gr["estimate"] - est) / abs(est), _bar(False, o["estimate_spread"] / abs(est)),
+                       "round %d estimate" % o["nr"])
+        q = np.array(o["pilot"])
+        dq = np.sqrt(np.sum((_bar(False, np.array(o["pilot_spread"]) / np.abs(q)) * np.abs(q)) ** 2))
+        b_sd = dq / math.sqrt(q.size - 1)
+        _say("   round N_r=%d: sd %.6e, oracle %.6e (bar %.1e)" % (o["nr"], gr["sd"], o["sd"], b_sd))
+        assert abs(gr["sd"] - o["sd"]) <= b_sd
+    assert (out["n_sketch"], out["n_hutch"], out["krylov_runs"]) == (gold["n_sketch"], gold["n_hutch"],
+                                                                     gold["krylov_runs"])
+    est, nr = gold["estimate"], gold["n_sketch"]
+    _say("   estimate %.12f, oracle %.12f (spread %.1e)" % (out["estimate"], est, gold["estimate_spread"]))
+    _assert_within(abs(out["estimate"] - est) / abs(est), _bar(False, gold["estimate_spread"] / abs(est)),
+                   "estimate")
+    psi, spread = np.array(gold["psi"]), np.array(gold["psi_spread"])
+    sq, sq_spread = gold["sum_q"], gold["sum_q_spread"]
+    _assert_within(abs(out["quad"][:nr].sum() - sq) / abs(sq), _bar(False, sq_spread / abs(sq)), "sum over Q")
+    _assert_within(_rel(out["quad"][nr:], psi[nr:]), _bar(False, spread[nr:] / np.abs(psi[nr:])), "G~ forms")
     ctx.release(gid)
 
 

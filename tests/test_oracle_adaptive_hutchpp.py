@@ -80,6 +80,13 @@ def test_rank_10_function_keeps_a_sketch_of_12():
     assert out["rounds"][0]["nh"] > 10 ** 5 and out["rounds"][1]["nh"] > 10 ** 5
     assert out["n_sketch"] == 12 and out["n_hutch"] == 16 and not out["capped"]
     assert abs(out["estimate"] - exact) <= 1e-9 * exact
+    # the last round is the final run: 2 * (3 + 6 + 12) + 3 * 16 Krylov runs
+    assert out["krylov_runs"] == 2 * 21 + 48
+    # and it is the same as running it again
+    Om = oracle.rademacher_block(5, ids, np.arange(12))
+    G = oracle.rademacher_block(5, ids, np.arange(128, 144))
+    est, det = oracle.hutchpp(A, Om, G, 4, oracle.breakdown_tau(True), False)
+    assert out["estimate"] == est
 
 
 def test_capped_count_is_flagged():
