@@ -292,6 +292,7 @@ struct StepCore {
         } else {
             const int b = __builtin_bit_cast(int, x);
             int r;
+            if constexpr (LPR == 1) return x;       // the lane is the group
             if constexpr (LPR == 64) r = __builtin_amdgcn_readlane(b, src);
             else r = __builtin_amdgcn_ds_bpermute(4 * (((int)(threadIdx.x & 63) & ~(LPR - 1)) + src), b);
             return __builtin_bit_cast(V, r);
@@ -734,9 +735,11 @@ int choose_tile(int m, bool fp64, int requested, bool three) {
         if (q >= 4 && q <= 64 && (q & (q - 1)) == 0) return m;
     }
     // column tile = CPL * LPR; by default at most 128 FP32 (64 FP64) columns,
-    // the widest tile whose gathered block stays cache friendly on large graphs
+    // the widest tile whose gathered block stays cache friendly on large graphs;
+    // a requested tile may also be one of the narrow ones (one or two lanes
+    // per row)
     const int cpl = fp64 ? 2 : 4;
-    const int maxt = cpl * 64, mint = cpl * 4;
+    const int maxt = cpl * 64, mint = requested > 0 ? cpl : cpl * 4;
     const int cap = requested > 0 ? maxt : (fp64 ? 64 : 128);
     const int want = requested > 0 ? requested : m;
     int t = mint;
@@ -750,9 +753,12 @@ int choose_plan_tile(int m, bool fp64, int64_t n, int64_t nnz) {
     // Bytes of one step by a simple model: six streams of the padded block,
     // and per column tile the CSR (8 B per entry) and one gather per entry
     // of at least a 128-byte line.  The cheapest tile wins (ties: the wider).
+    // The narrow tiles (one or two lanes per row: 4 and 8 FP32 columns, 2 and
+    // 4 FP64) win only for blocks of a few columns, where padding to the
+    // next wide tile would multiply the streams.
     const int es = fp64 ? 8 : 4, cpl = fp64 ? 2 : 4;
     std::vector<int> cands;
-    for (int t = cpl * 4; t <= (fp64 ? 64 : 128); t *= 2) cands.push_back(t);
+    for (int t = cpl; t <= (fp64 ? 64 : 128); t *= 2) cands.push_back(t);
     if (!fp64) {
         for (int t = 12; t <= 96; t *= 2) cands.push_back(t);
         if (m == 192) cands.push_back(192);
@@ -849,6 +855,8 @@ hipError_t launch_step_pairs(const StepArgs *args, const int4 *pair_map, int32_t
 hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s) {
     if (!fp64) {
         switch (a.mt) {
+            case 4: return launch_step_t<float, 4, 1>(a, first, s);
+            case 8: return launch_step_t<float, 4, 2>(a, first, s);
             case 16: return launch_step_t<float, 4, 4>(a, first, s);
             case 32: return launch_step_t<float, 4, 8>(a, first, s);
             case 64: return launch_step_t<float, 4, 16>(a, first, s);
@@ -862,6 +870,8 @@ hipError_t launch_step(const StepArgs &a, bool fp64, bool first, hipStream_t s) 
         }
     } else {
         switch (a.mt) {
+            case 2: return launch_step_t<double, 2, 1>(a, first, s);
+            case 4: return launch_step_t<double, 2, 2>(a, first, s);
             case 8: return launch_step_t<double, 2, 4>(a, first, s);
             case 16: return launch_step_t<double, 2, 8>(a, first, s);
             case 32: return launch_step_t<double, 2, 16>(a, first, s);

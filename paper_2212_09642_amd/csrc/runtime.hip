@@ -802,7 +802,8 @@ vne_status autotune(vne_ctx *c, GraphSet *set, Plan *p, const ProbeSpec &ps, boo
     }
     const int cpl = p->fp64 ? 2 : 4;
     std::vector<int> cands;
-    for (int t = cpl * 4; t <= cpl * 64; t *= 2)
+    // the narrow tiles (one or two lanes per row) only for narrow blocks
+    for (int t = p->m_pad <= cpl * 4 ? cpl : cpl * 4; t <= cpl * 64; t *= 2)
         if (t <= p->m_pad && p->m_pad % t == 0) cands.push_back(t);
     if (std::find(cands.begin(), cands.end(), p->mt) == cands.end()) cands.push_back(p->mt);
     int best = p->mt;

@@ -144,11 +144,12 @@ def _model_tile(m, fp64, n, nnz):
     """The column tile a plan takes without the autotuner: the cheapest, under
     a byte model of one step (six streams of the padded block, and per tile
     the CSR and one gather of at least a 128-byte line per entry), among the
-    power-of-two tiles and, for FP32, the three-column tiles 12..96 (192 for
-    m = 192); ties go to the wider tile."""
+    power-of-two tiles (from one lane per row: 4 FP32 / 2 FP64 columns) and,
+    for FP32, the three-column tiles 12..96 (192 for m = 192); ties go to the
+    wider tile."""
     es, cpl = (8, 2) if fp64 else (4, 4)
     cands = []
-    t = cpl * 4
+    t = cpl
     while t <= (64 if fp64 else 128):
         cands.append(t)
         t *= 2

@@ -90,8 +90,8 @@ def test_hub_rows_use_segments(ctx, fp64):
 @pytest.mark.parametrize("m,k", [(1, 1), (1, 7), (37, 3), (257, 5), (64, 50)])
 def test_ragged_shapes(ctx, m, k, monkeypatch):
     """Ragged widths with the autotuner off, so that the byte model's tile
-    runs (padded three-column tiles for FP32 m = 1, 37, 257) and the test
-    asserts which one did."""
+    runs (padded three-column tiles for FP32 m = 37, 257; the one-lane tile
+    for m = 1) and the test asserts which one did."""
     _say("case ragged m=%d k=%d" % (m, k))
     monkeypatch.setenv("VNE_AUTOTUNE", "0")
     n, e = synth.watts_strogatz(1237, 6, 0.2, 9)
@@ -104,8 +104,10 @@ def test_ragged_shapes(ctx, m, k, monkeypatch):
             tile = _model_tile(m, fp64, ref.n, ref.nnz)
             _say("   fp64=%s tile %d, m_pad %d" % (fp64, plan["tile"], plan["m_pad"]))
             assert plan == dict(tile=tile, m_pad=-(-m // tile) * tile)
-            if not fp64 and m in (1, 37, 257):
+            if not fp64 and m in (37, 257):
                 assert tile % 3 == 0 and plan["m_pad"] > m      # a padded three-column tile ran
+            if m == 1:
+                assert tile == (2 if fp64 else 4)               # one lane per row
             B = oracle.rademacher_block(21, ref.node_ids, np.arange(m))
             want = oracle.quadforms(ref.scipy(), B, k, oracle.breakdown_tau(fp64))
             _check_quad(out, want, fp64, n=ref.n)
@@ -151,6 +153,40 @@ def test_deterministic(ctx):
     for key in ("quad", "alpha", "beta", "k_eff", "norm2"):
         assert np.array_equal(a[key], b[key]), key
     assert a["estimate"] == b["estimate"]
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_narrow_tiles(ctx, fp64, monkeypatch):
+    """Tiles of one and two lanes per row (4 and 8 FP32 columns, 2 and 4
+    FP64): the byte model's choice for blocks of a few columns, forced tiles
+    (two tiles of a block run as concurrent chains), the long rows of a hub
+    graph in segments, and a Hutch++ whose three-column sketch takes a
+    narrow tile; each against the oracle at the usual bar."""
+    cpl = 2 if fp64 else 4
+    monkeypatch.setenv("VNE_AUTOTUNE", "0")
+    n, e = synth.barabasi_albert(6000, 3, 31)
+    mode = vne.MODE_DESING | (vne.MODE_F64 if fp64 else 0)
+    with vne.Context(0) as c:
+        gid, ref = _setup(c, n, e, fp64)
+        A = ref.scipy()
+        for m, forced in ((1, 0), (3, 0), (cpl, 0), (2 * cpl, cpl), (2 * cpl, 2 * cpl), (5, cpl)):
+            monkeypatch.setenv("VNE_TILE", str(forced))
+            _say("case narrow tile fp64=%s m=%d forced=%d" % (fp64, m, forced))
+            out = c.estimate(gid, vne.PROBE_RADEMACHER, m, 20, mode, seed=40 + m)
+            plan = c.last_plan()
+            tile = forced if forced else _model_tile(m, fp64, ref.n, ref.nnz)
+            _say("   tile %d, m_pad %d" % (plan["tile"], plan["m_pad"]))
+            assert tile <= 2 * cpl and plan == dict(tile=tile, m_pad=-(-m // tile) * tile)
+            B = oracle.rademacher_block(40 + m, ref.node_ids, np.arange(m))
+            want = oracle.quadforms(A, B, 20, oracle.breakdown_tau(fp64))
+            _check_quad(out, want, fp64, sens=_order_sensitivity(A, B, 20, fp64), n=ref.n)
+        monkeypatch.setenv("VNE_TILE", "0")
+        _say("case narrow tile fp64=%s: Hutch++ 3 + 13" % fp64)
+        out = c.estimate(gid, vne.PROBE_HUTCHPP, 16, 20, mode, seed=5, n_sketch=3)
+        Om = oracle.rademacher_block(5, ref.node_ids, np.arange(3))
+        G = oracle.rademacher_block(5, ref.node_ids, np.arange(3, 16))
+        est, det, sens = _hutchpp_oracle(A, Om, G, 20, fp64)
+        _check_hutchpp(out, est, det, sens, 3, fp64)
 
 
 @pytest.mark.parametrize("fp64", [True, False])
