@@ -78,21 +78,17 @@ def _run(A, node_ids, seed, nr, g_col0, nh, k, tau, desing):
     return est, np.asarray(det["psi"])
 
 
-def adaptive_hutchpp(A, node_ids, seed, k, eps=1e-2, eps_abs=0.0, delta=1e-2, n_pilot=16, r_first=3,
-                     r_max=96, n_h_max=4096, g_col0=128, fp64_tau=True, desing=True):
-    """Adaptive Hutch++ estimate of tr f(A) by the reading above.
-
-    Returns dict(estimate, n_sketch, n_hutch, std_error, eps_hat, capped,
-    krylov_runs, rounds=[dict(nr, estimate, sd, eps_hat, nh, effort)], psi)."""
-    tau = breakdown_tau(fp64_tau)
+def run_rule(round_stats, eps=1e-2, eps_abs=0.0, delta=1e-2, n_pilot=16, r_first=3, r_max=96, n_h_max=4096):
+    """The rule's decisions from the rounds' statistics: round_stats(nr)
+    returns (estimate, sd) of the round of sketch width nr.  Returns
+    dict(rounds=[dict(nr, estimate, sd, eps_hat, nh, effort)], kept,
+    n_hutch, capped, reuse, krylov_runs); reuse: the final run is the last
+    round itself."""
     z = normal_quantile_two_sided(delta)
     rounds = []
-    runs = 0
     nr = r_first
     while True:
-        est, psi = _run(A, node_ids, seed, nr, g_col0, n_pilot, k, tau, desing)
-        runs += 2 * nr + n_pilot
-        sd = float(np.std(psi[nr:], ddof=1))
+        est, sd = round_stats(nr)
         eh = eps_abs if eps_abs > 0 else 0.5 * eps * abs(est)
         nh = hutch_count(sd, eh, z, n_pilot)
         rounds.append(dict(nr=nr, estimate=est, sd=sd, eps_hat=eh, nh=nh, effort=2 * nr + nh))
@@ -101,11 +97,35 @@ def adaptive_hutchpp(A, node_ids, seed, k, eps=1e-2, eps_abs=0.0, delta=1e-2, n_
             break
         nr = nxt
     ib = kept_round([r["effort"] for r in rounds])
-    best = rounds[ib]
-    nr, nh = best["nr"], min(best["nh"], n_h_max)
-    if ib + 1 != len(rounds) or nh != n_pilot:
+    nh = min(rounds[ib]["nh"], n_h_max)
+    reuse = ib + 1 == len(rounds) and nh == n_pilot
+    runs = sum(2 * r["nr"] + n_pilot for r in rounds) + (0 if reuse else 2 * rounds[ib]["nr"] + nh)
+    return dict(rounds=rounds, kept=ib, n_hutch=nh, capped=rounds[ib]["nh"] > n_h_max, reuse=reuse,
+                krylov_runs=runs)
+
+
+def adaptive_hutchpp(A, node_ids, seed, k, eps=1e-2, eps_abs=0.0, delta=1e-2, n_pilot=16, r_first=3,
+                     r_max=96, n_h_max=4096, g_col0=128, fp64_tau=True, desing=True):
+    """Adaptive Hutch++ estimate of tr f(A) by the reading above.
+
+    Returns dict(estimate, n_sketch, n_hutch, std_error, eps_hat, capped,
+    krylov_runs, rounds=[dict(nr, estimate, sd, eps_hat, nh, effort)], psi)."""
+    tau = breakdown_tau(fp64_tau)
+    runs = {}
+
+    def round_stats(nr):
+        est, psi = _run(A, node_ids, seed, nr, g_col0, n_pilot, k, tau, desing)
+        runs[nr] = (est, psi)
+        return est, float(np.std(psi[nr:], ddof=1))
+
+    rule = run_rule(round_stats, eps, eps_abs, delta, n_pilot, r_first, r_max, n_h_max)
+    best = rule["rounds"][rule["kept"]]
+    nr, nh = best["nr"], rule["n_hutch"]
+    if rule["reuse"]:
+        est, psi = runs[nr]
+    else:
         est, psi = _run(A, node_ids, seed, nr, g_col0, nh, k, tau, desing)
-        runs += 2 * nr + nh
     q = psi[nr:]
     return dict(estimate=est, n_sketch=nr, n_hutch=nh, std_error=float(np.std(q, ddof=1) / math.sqrt(nh)),
-                eps_hat=best["eps_hat"], capped=best["nh"] > n_h_max, krylov_runs=runs, rounds=rounds, psi=psi)
+                eps_hat=best["eps_hat"], capped=rule["capped"], krylov_runs=rule["krylov_runs"],
+                rounds=rule["rounds"], psi=psi)

@@ -3,8 +3,8 @@
 // Hutch++ run of the device path (sketch Lanczos with a kept basis, f(A)
 // Omega by eq. (4.3), CholeskyQR2, projection, quadratic forms of
 // [Q | G~]); the rule that picks the sketch width and the Hutchinson count
-// reads the round's forms on the host.  The rule is stated with its
-// declaration in vne.h.
+// (hutchpp_rule.h, host only) reads the round's forms on the host.  The
+// rule is stated with its declaration in vne.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "ctx_internal.h"
+#include "hutchpp_rule.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -25,40 +26,6 @@ namespace {
 // hash column of the first deflated (Hutchinson) vector: past every sketch
 // width, so the deflated vectors do not depend on N_r
 constexpr int kGCol0 = 128;
-
-// z with P(|N(0, 1)| >= z) = delta: the root of erfc(z / sqrt 2) = delta on
-// [0, 40], by bisection (erfc decreases; 200 halvings end at the double
-// spacing)
-double normal_quantile_two_sided(double delta) {
-    double lo = 0.0, hi = 40.0;
-    for (int i = 0; i < 200 && hi > lo; ++i) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
-        if (std::erfc(mid / std::sqrt(2.0)) > delta)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return 0.5 * (lo + hi);
-}
-
-// deflated forms a round asks for
-int64_t hutch_count(double s, double eps_hat, double z, int n_pilot) {
-    if (!(s > 0.0)) return n_pilot;
-    double x = eps_hat > 0.0 ? (z * s / eps_hat) * (z * s / eps_hat) : 1e15;
-    x = std::min(x, 1e15);
-    return std::max<int64_t>((int64_t)std::ceil(x), n_pilot);
-}
-
-// sample standard deviation (n - 1 in the denominator), two passes
-double sample_sd(const double *x, int n) {
-    double mean = 0.0;
-    for (int i = 0; i < n; ++i) mean += x[i];
-    mean /= n;
-    double ss = 0.0;
-    for (int i = 0; i < n; ++i) ss += (x[i] - mean) * (x[i] - mean);
-    return std::sqrt(ss / (n - 1));
-}
 
 struct RoundOut {
     double estimate = 0.0;
@@ -116,56 +83,33 @@ extern "C" vne_status vne_hutchpp_adaptive(vne_ctx *c, int32_t gid, const vne_hu
         return fail(c, VNE_EINVAL, "VNE_MODE_DESING needs a matrix whose rows sum to zero (A 1 = 0)");
     const auto t0 = std::chrono::steady_clock::now();
     std::memset(res, 0, sizeof(*res));
-    const double z = normal_quantile_two_sided(cfg->delta);
-
-    struct Round {
-        int nr;
-        int64_t nh, effort;
-        double estimate, sd, eps_hat;
-    };
-    std::vector<Round> rounds;
-    int64_t runs = 0;
-    int nr = r_first;
+    HutchppRule rule(cfg->rel_eps, cfg->abs_eps, cfg->delta, n_pilot, r_first, r_max, n_h_max);
     RoundOut ro;
-    for (;;) {
+    while (const int nr = rule.next()) {
         VNE_TRY(round_run(c, set, nr, n_pilot, k, cfg->seed, fp64, desing, &ro));
-        runs += 2 * nr + n_pilot;
-        const double sd = sample_sd(ro.psi.data() + nr, n_pilot);
-        const double eh = cfg->abs_eps > 0.0 ? cfg->abs_eps : 0.5 * cfg->rel_eps * std::fabs(ro.estimate);
-        const int64_t nh = hutch_count(sd, eh, z, n_pilot);
-        rounds.push_back({nr, nh, 2 * nr + nh, ro.estimate, sd, eh});
-        int64_t least = rounds[0].effort;
-        for (const Round &r : rounds) least = std::min(least, r.effort);
-        const int next = std::min(2 * nr, r_max);
-        if (nr >= r_max || 2 * (int64_t)next + n_pilot >= least) break;
-        nr = next;
+        rule.record(ro.estimate, hpp_sample_sd(ro.psi.data() + nr, n_pilot));
     }
-    size_t best = 0;
-    for (size_t i = 1; i < rounds.size(); ++i)
-        if (rounds[i].effort < rounds[best].effort) best = i;
-    const Round &kb = rounds[best];
-    const int nh_final = (int)std::min<int64_t>(kb.nh, n_h_max);
+    const HutchppRound &kb = rule.rounds()[rule.kept()];
+    const int nh_final = rule.final_nh();
     // the last round with the pilot's count is the final run itself (same
     // columns, same plans: the device would repeat it bit for bit)
-    if (best + 1 != rounds.size() || nh_final != n_pilot) {
-        VNE_TRY(round_run(c, set, kb.nr, nh_final, k, cfg->seed, fp64, desing, &ro));
-        runs += 2 * kb.nr + nh_final;
-    }
+    if (!rule.reuse_last()) VNE_TRY(round_run(c, set, kb.nr, nh_final, k, cfg->seed, fp64, desing, &ro));
 
     res->estimate = ro.estimate;
-    res->std_error = sample_sd(ro.psi.data() + kb.nr, nh_final) / std::sqrt((double)nh_final);
+    res->std_error = hpp_sample_sd(ro.psi.data() + kb.nr, nh_final) / std::sqrt((double)nh_final);
     res->eps_hat = kb.eps_hat;
     res->n_sketch = kb.nr;
     res->n_hutch = nh_final;
-    res->capped = kb.nh > n_h_max ? 1 : 0;
-    res->rounds = (int32_t)rounds.size();
-    for (size_t i = 0; i < rounds.size() && i < VNE_HUTCHPP_MAX_ROUNDS; ++i) {
-        res->round_nr[i] = rounds[i].nr;
-        res->round_nh[i] = (int32_t)std::min<int64_t>(rounds[i].nh, INT32_MAX);
-        res->round_estimate[i] = rounds[i].estimate;
-        res->round_sd[i] = rounds[i].sd;
+    res->capped = rule.capped() ? 1 : 0;
+    res->rounds = (int32_t)rule.rounds().size();
+    for (size_t i = 0; i < rule.rounds().size() && i < VNE_HUTCHPP_MAX_ROUNDS; ++i) {
+        const HutchppRound &r = rule.rounds()[i];
+        res->round_nr[i] = r.nr;
+        res->round_nh[i] = (int32_t)std::min<int64_t>(r.nh, INT32_MAX);
+        res->round_estimate[i] = r.estimate;
+        res->round_sd[i] = r.sd;
     }
-    res->krylov_runs = runs;
+    res->krylov_runs = rule.krylov_runs();
     if (quad && quad_cap > 0)
         std::memcpy(quad, ro.psi.data(), (size_t)std::min<int64_t>(quad_cap, (int64_t)ro.psi.size()) * 8);
     res->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
