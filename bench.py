@@ -81,6 +81,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def oracle_check(golden, estimate, **match):
+    """The estimate against the oracle's FP64 value of the same problem (same
+    graph, probes and sizes), read from a committed golden file written by a
+    script under tests/golden/ that calls only the oracle; None when the file
+    is missing or describes another problem."""
+    path = os.path.join(ROOT, "tests", "golden", golden)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if any(d.get(k) != v for k, v in match.items()):
+        return None
+    ref = d["estimate"]
+    return {"oracle_estimate": ref, "rel_err": abs(estimate - ref) / abs(ref), "bar": 1e-5,
+            "oracle_rounding_spread": d.get("estimate_spread"), "golden": "tests/golden/" + golden}
+
+
 def load_traffic(workload):
     """HBM bytes per step launch from the committed rocprofv3 counter summary
     (null when missing or taken on a different kernel source)."""
@@ -566,7 +583,10 @@ def run_hutchpp_adaptive(args):
     rows = []
     for eps in (1e-2, 1e-3):
         out, ms = timed(lambda: ctx.hutchpp_adaptive(gid, k, rel_eps=eps, delta=1e-2, mode=mode, seed=seed))
+        chk = oracle_check("hutchpp_adaptive_large.json", out["estimate"], rel_eps=eps, delta=1e-2, k=k,
+                           probe_seed=seed, n=g["n"], nnz=len(g["col_idx"]))
         rows.append(dict(rel_eps=eps, delta=1e-2, ms=round(ms, 3), n_sketch=out["n_sketch"], n_hutch=out["n_hutch"],
+                         oracle_check=chk,
                          rounds=[(r["nr"], r["nh"]) for r in out["rounds"]], krylov_runs=out["krylov_runs"],
                          estimate=out["estimate"], std_error=out["std_error"], eps_hat=out["eps_hat"],
                          capped=out["capped"],
@@ -837,6 +857,9 @@ def main():
                      "algorithmic_bytes_per_launch": round(kt["bytes"] / max(kt["launches"], 1))},
         "cpu_baseline": None,
     }
+    if args.workload == "large":
+        res["oracle_check"] = oracle_check("hutchpp_large.json", out["estimate"], workload=w["name"], n=n, nnz=nnz,
+                                           n_sketch=spec["n_sketch"], k=spec["k"], probe_seed=spec["seed"])
     if not args.no_cpu_baseline and args.workload in ("large", "tiny"):
         res["cpu_baseline"] = cpu_baseline(g, spec, min(args.cpu_sample_cols, spec["m"]), spec["k"])
     ctx.close()
