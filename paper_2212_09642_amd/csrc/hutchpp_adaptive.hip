@@ -1,5 +1,5 @@
 // Adaptive Hutch++ (Section 3.2, the tail bound eq. (3.10); the adaptive
-// Hutch++ implementation of Section 5).  Host driver: every round is a
+// Hutch++ implementation of Section 5).  Host code: every round is a
 // Hutch++ run of the device path (sketch Lanczos with a kept basis, f(A)
 // Omega by eq. (4.3), CholeskyQR2, projection, quadratic forms of
 // [Q | G~]); the rule that picks the sketch width and the Hutchinson count

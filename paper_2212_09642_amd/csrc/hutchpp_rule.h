@@ -2,8 +2,9 @@
 // (3.10) and the adaptive Hutch++ implementation of Section 5, in the
 // reading stated with the declaration in vne.h): which sketch width to run
 // next, when to stop, which round to keep and how many deflated forms its
-// final run takes.  Host only, no device code: the driver feeds it each
-// round's estimate and the sample standard deviation of its pilot forms.
+// final run takes.  Host only, no device code: vne_hutchpp_adaptive feeds
+// it each round's estimate and the sample standard deviation of its pilot
+// forms.
 #pragma once
 
 #include <algorithm>
