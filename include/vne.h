@@ -367,7 +367,9 @@ vne_status vne_probing_select(const double *T, double eps_hat, double n, double 
  *    so far (2 N_r' + n_pilot < least effort); the round of least effort is
  *    kept (the earlier on ties);
  *  - final: Hutch++ with the kept N_r and min(N_H, n_h_max) deflated forms
- *    (their first n_pilot columns are the pilot's).
+ *    (their first n_pilot columns are the pilot's): the kept round itself
+ *    when it asked for the pilot's count, else a run on the kept round's Q
+ *    (kept on the device, not sketched again) with new deflated columns.
  * Every Krylov run takes k_steps Lanczos steps (the caller picks k_steps
  * for the Krylov share of the error, e.g. with vne_plan_steps).  The round
  * statistics (mean, standard deviation, counts) are computed on the host
@@ -399,7 +401,8 @@ typedef struct {
     int32_t rounds;             /* rounds run                                                */
     int32_t round_nr[VNE_HUTCHPP_MAX_ROUNDS], round_nh[VNE_HUTCHPP_MAX_ROUNDS];
     double round_estimate[VNE_HUTCHPP_MAX_ROUNDS], round_sd[VNE_HUTCHPP_MAX_ROUNDS];
-    int64_t krylov_runs;        /* Lanczos runs made in all (rounds and final)               */
+    int64_t krylov_runs;        /* Lanczos runs: 2 N_r + n_pilot per round, N_r + N_H for a
+                                   final run on a kept Q                                     */
     double ms;                  /* wall time of the call                                     */
 } vne_hutchpp_result;
 vne_status vne_hutchpp_adaptive(vne_ctx *ctx, int32_t graph_id, const vne_hutchpp_cfg *cfg,

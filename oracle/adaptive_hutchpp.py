@@ -30,11 +30,13 @@ reading of those facts, not that algorithm: parity unpinned against it.
   (the earlier on ties).  (Stopping at the first round whose effort rose
   instead would end on the noise of a 16-form standard deviation.)
 * Final estimate: Hutch++ with the kept N_r and min(N_H, n_h_max) deflated
-  forms, whose first n_pilot columns are the pilot's (when that is the last
-  round with the pilot's count, the round itself); `capped` says that
-  n_h_max cut the count (the target of eq. (3.10) is then not met by the
-  rule).  `krylov_runs` counts the Krylov runs made: 2 N_r + n_pilot per
-  round and 2 N_r + N_H for a final run that is not the last round.
+  forms, whose first n_pilot columns are the pilot's (when the count is the
+  pilot's, the kept round itself); `capped` says that n_h_max cut the count
+  (the target of eq. (3.10) is then not met by the rule).  `krylov_runs`
+  counts the Krylov runs: 2 N_r + n_pilot per round (N_r products, N_r +
+  n_pilot forms) and N_r + N_H forms for a final run, whose Q is the kept
+  round's (an implementation keeps it; this module forms it again, the same
+  Q).
 
 Pinned by (tests/test_oracle_adaptive_hutchpp.py): the normal quantile
 against its textbook values, the count and round rules on hand-worked
@@ -82,7 +84,7 @@ def run_rule(round_stats, eps=1e-2, eps_abs=0.0, delta=1e-2, n_pilot=16, r_first
     """The rule's decisions from the rounds' statistics: round_stats(nr)
     returns (estimate, sd) of the round of sketch width nr.  Returns
     dict(rounds=[dict(nr, estimate, sd, eps_hat, nh, effort)], kept,
-    n_hutch, capped, reuse, krylov_runs); reuse: the final run is the last
+    n_hutch, capped, reuse, krylov_runs); reuse: the final run is the kept
     round itself."""
     z = normal_quantile_two_sided(delta)
     rounds = []
@@ -98,8 +100,8 @@ def run_rule(round_stats, eps=1e-2, eps_abs=0.0, delta=1e-2, n_pilot=16, r_first
         nr = nxt
     ib = kept_round([r["effort"] for r in rounds])
     nh = min(rounds[ib]["nh"], n_h_max)
-    reuse = ib + 1 == len(rounds) and nh == n_pilot
-    runs = sum(2 * r["nr"] + n_pilot for r in rounds) + (0 if reuse else 2 * rounds[ib]["nr"] + nh)
+    reuse = nh == n_pilot
+    runs = sum(2 * r["nr"] + n_pilot for r in rounds) + (0 if reuse else rounds[ib]["nr"] + nh)
     return dict(rounds=rounds, kept=ib, n_hutch=nh, capped=rounds[ib]["nh"] > n_h_max, reuse=reuse,
                 krylov_runs=runs)
 

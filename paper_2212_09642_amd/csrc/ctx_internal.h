@@ -212,9 +212,12 @@ vne_status collect_timing(vne_ctx *c);
 // [0, nr) of `seed`, nh Hutchinson vectors on hash columns [g_col0,
 // g_col0 + nh).  Leaves the forms of [Q | G~] in (*q_out)->psi and their
 // combination in (*q_out)->estimate on the context's stream (nothing is
-// copied to the host); *sk_out (may be NULL) receives the sketch's plan.
+// copied to the host); *sk_out (may be NULL) receives the sketch's plan
+// (NULL with q_src).  q_src (device, may be NULL): the orthonormal Q of an
+// earlier run of the same sketch (n x nr, leading dimension q_ld), used
+// instead of sketching again.
 vne_status hutchpp_run(vne_ctx *c, GraphSet *set, int nr, int nh, int g_col0, int k, uint64_t seed, bool fp64,
-                       bool desing, Plan **sk_out, Plan **q_out);
+                       bool desing, Plan **sk_out, Plan **q_out, const void *q_src = nullptr, int q_ld = 0);
 vne_status check_mode(vne_ctx *c, uint32_t mode);
 
 }  // namespace rt

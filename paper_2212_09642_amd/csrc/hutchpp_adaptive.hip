@@ -30,20 +30,28 @@ constexpr int kGCol0 = 128;
 struct RoundOut {
     double estimate = 0.0;
     std::vector<double> psi;
+    const Plan *q = nullptr;         // the run's plan: its B holds [Q | G~]
 };
 
+// one Hutch++ run (a round, or the final run on the Q of `from`) and its
+// results on the host
 vne_status round_run(vne_ctx *c, GraphSet *set, int nr, int nh, int k, uint64_t seed, bool fp64, bool desing,
-                     RoundOut *ro) {
+                     const RoundOut *from, RoundOut *ro) {
     Plan *sk = nullptr, *q = nullptr;
-    VNE_TRY(hutchpp_run(c, set, nr, nh, kGCol0, k, seed, fp64, desing, &sk, &q));
+    if (from)
+        VNE_TRY(hutchpp_run(c, set, nr, nh, kGCol0, k, seed, fp64, desing, nullptr, &q, from->q->B.p,
+                            from->q->m));
+    else
+        VNE_TRY(hutchpp_run(c, set, nr, nh, kGCol0, k, seed, fp64, desing, &sk, &q));
     hipStream_t s = c->stream;
     const int m = nr + nh;
     ro->psi.assign(m, 0.0);
+    ro->q = q;
     int32_t fl[2] = {0, 0};
     HIP_TRY(c, hipMemcpyAsync(&ro->estimate, q->estimate.p, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(ro->psi.data(), q->psi.p, (size_t)m * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(&fl[0], q->flags.p, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipMemcpyAsync(&fl[1], sk->flags.p, 4, hipMemcpyDeviceToHost, s));
+    if (sk) HIP_TRY(c, hipMemcpyAsync(&fl[1], sk->flags.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     return check_flags(c, fl[0] | fl[1]);
 }
@@ -84,16 +92,22 @@ extern "C" vne_status vne_hutchpp_adaptive(vne_ctx *c, int32_t gid, const vne_hu
     const auto t0 = std::chrono::steady_clock::now();
     std::memset(res, 0, sizeof(*res));
     HutchppRule rule(cfg->rel_eps, cfg->abs_eps, cfg->delta, n_pilot, r_first, r_max, n_h_max);
-    RoundOut ro;
+    std::vector<RoundOut> outs;
     while (const int nr = rule.next()) {
-        VNE_TRY(round_run(c, set, nr, n_pilot, k, cfg->seed, fp64, desing, &ro));
-        rule.record(ro.estimate, hpp_sample_sd(ro.psi.data() + nr, n_pilot));
+        outs.emplace_back();
+        VNE_TRY(round_run(c, set, nr, n_pilot, k, cfg->seed, fp64, desing, nullptr, &outs.back()));
+        rule.record(outs.back().estimate, hpp_sample_sd(outs.back().psi.data() + nr, n_pilot));
     }
     const HutchppRound &kb = rule.rounds()[rule.kept()];
     const int nh_final = rule.final_nh();
-    // the last round with the pilot's count is the final run itself (same
-    // columns, same plans: the device would repeat it bit for bit)
-    if (!rule.reuse_last()) VNE_TRY(round_run(c, set, kb.nr, nh_final, k, cfg->seed, fp64, desing, &ro));
+    // a kept round with the pilot's count is the final run itself (same
+    // columns: the device would repeat it bit for bit); otherwise the final
+    // run takes the kept round's Q (the rounds have distinct widths, so no
+    // later round's plan holds it) and new deflated columns
+    RoundOut fin;
+    const RoundOut &ro = rule.reuse() ? outs[rule.kept()] : fin;
+    if (!rule.reuse())
+        VNE_TRY(round_run(c, set, kb.nr, nh_final, k, cfg->seed, fp64, desing, &outs[rule.kept()], &fin));
 
     res->estimate = ro.estimate;
     res->std_error = hpp_sample_sd(ro.psi.data() + kb.nr, nh_final) / std::sqrt((double)nh_final);

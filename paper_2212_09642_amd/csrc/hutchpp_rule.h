@@ -98,13 +98,15 @@ public:
     }
     int final_nh() const { return (int)std::min<int64_t>(rounds_[kept()].nh, n_h_max_); }
     bool capped() const { return rounds_[kept()].nh > n_h_max_; }
-    // the last round with the pilot's count is the final run itself
-    bool reuse_last() const { return kept() + 1 == rounds_.size() && final_nh() == n_pilot_; }
-    // Krylov runs: 2 N_r + n_pilot per round, 2 N_r + N_H for a final run
+    // a kept round that asks for the pilot's count is the final run itself;
+    // otherwise the final run takes the kept round's Q and new deflated forms
+    bool reuse() const { return final_nh() == n_pilot_; }
+    // Krylov runs: 2 N_r + n_pilot per round (N_r products, N_r + n_pilot
+    // forms), and N_r + N_H forms for a final run (its Q is the kept round's)
     int64_t krylov_runs() const {
         int64_t r = 0;
         for (const HutchppRound &q : rounds_) r += 2 * (int64_t)q.nr + n_pilot_;
-        if (!reuse_last()) r += 2 * (int64_t)rounds_[kept()].nr + final_nh();
+        if (!reuse()) r += (int64_t)rounds_[kept()].nr + final_nh();
         return r;
     }
 

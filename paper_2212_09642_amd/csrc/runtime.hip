@@ -919,12 +919,12 @@ vne_status copy_out(vne_ctx *c, Plan *p, const int32_t *m, const int32_t *k, vne
 }
 
 vne_status hutchpp_run(vne_ctx *c, GraphSet *set, int nr, int nh, int g_col0, int k, uint64_t seed, bool fp64,
-                       bool desing, Plan **sk_out, Plan **q_out) {
+                       bool desing, Plan **sk_out, Plan **q_out, const void *q_src, int q_ld) {
     const int m = nr + nh;
     if (nr < 1 || nh < 0 || nr > 128) return fail(c, VNE_ENOTSUP, "Hutch++ needs 1 <= n_sketch <= min(m, 128)");
     const size_t es = fp64 ? 8 : 4;
     Plan *sk = nullptr, *q = nullptr;
-    VNE_TRY(get_plan(c, set, nr, k, fp64, true, 1, &sk));
+    if (!q_src) VNE_TRY(get_plan(c, set, nr, k, fp64, true, 1, &sk));
     VNE_TRY(get_plan(c, set, m, k, fp64, false, 2, &q));
     const int64_t n = set->n;
     // the Hutch++ workspace of the quadratic-form plan depends on N_r, which
@@ -945,38 +945,50 @@ vne_status hutchpp_run(vne_ctx *c, GraphSet *set, int nr, int nh, int g_col0, in
         VNE_TRY(ensure(&q->rinv, (size_t)nr * nr * 8));
         VNE_TRY(ensure(&q->rot, (size_t)nr * rot_capacity(k) * kRotBytes));
     }
-    sk->h_graph_k = {k};
-    sk->h_graph_m = {nr};
     q->h_graph_k = {k};
     q->h_graph_m = {m};
     hipStream_t s = c->stream;
     const int64_t *keys = (const int64_t *)set->keys.p;
-    // 1. sketch: k Lanczos steps on Omega (kept basis), then Y = f(A) Omega by eq. (4.3)
     ProbeSpec ps;
     ps.gen = GEN_RADEMACHER;
     ps.seeds = {seed};
-    // column tiles of both Lanczos runs, timed on Rademacher blocks of their
+    // column tiles of the Lanczos runs, timed on Rademacher blocks of their
     // widths (the speed of a step does not depend on the values; the runs
     // below probe their own blocks again)
-    VNE_TRY(autotune(c, set, sk, ps, desing));
     VNE_TRY(autotune(c, set, q, ps, desing));
-    VNE_TRY(run_lanczos(c, set, sk, ps, desing));
-    HIP_TRY(c, launch_fT_e1((const double *)sk->alpha.p, (const double *)sk->beta.p, (const int32_t *)sk->k_eff.p,
-                            k, nr, (double *)q->S.p, q->rot.p, (int32_t *)sk->flags.p, s, fp64));
-    const int64_t step_stride = n * sk->m_pad;
-    HIP_TRY(c, launch_reconstruct(sk->Vstore.p, fp64, step_stride, sk->m_pad, (const double *)q->S.p,
-                                  (const double *)sk->norm2.p, k, (int32_t)n, nr, q->B.p, m, s));
-    // 2. G block, raw +-1 in the columns after the sketch (hash columns
-    // g_col0, g_col0 + 1, ...)
-    if (nh > 0) HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)n, nh, m, nr, g_col0, seed, keys, s));
-    // 3. Q = orth(Y) by CholeskyQR2 (FP64 Gram and triangular factors, two
-    // passes, in place): the first pass leaves an orthogonality error of
-    // about u cond(Y)^2, the second brings it to the rounding of Q's storage
-    for (int pass = 0; pass < 2; ++pass) {
-        HIP_TRY(c, launch_gram(q->B.p, m, q->B.p, m, fp64, (int32_t)n, nr, nr, (double *)q->gram_part.p,
-                               (double *)q->gram.p, s));
-        HIP_TRY(c, launch_cholinv((double *)q->gram.p, (double *)q->rinv.p, nr, (int32_t *)sk->flags.p, s));
-        HIP_TRY(c, launch_apply(q->B.p, m, (const double *)q->rinv.p, nr, nr, q->B.p, m, fp64, (int32_t)n, 0, s));
+    if (q_src) {
+        // Q of an earlier run of the same sketch (n x nr, leading dimension
+        // q_ld, another plan's buffer): copied into the first nr columns
+        if (q_src != q->B.p || q_ld != m)
+            HIP_TRY(c, hipMemcpy2DAsync(q->B.p, (size_t)m * es, q_src, (size_t)q_ld * es, (size_t)nr * es,
+                                        (size_t)n, hipMemcpyDeviceToDevice, s));
+        if (nh > 0) HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)n, nh, m, nr, g_col0, seed, keys, s));
+    } else {
+        sk->h_graph_k = {k};
+        sk->h_graph_m = {nr};
+        VNE_TRY(autotune(c, set, sk, ps, desing));
+        // 1. sketch: k Lanczos steps on Omega (kept basis), then Y = f(A) Omega by eq. (4.3)
+        VNE_TRY(run_lanczos(c, set, sk, ps, desing));
+        HIP_TRY(c, launch_fT_e1((const double *)sk->alpha.p, (const double *)sk->beta.p,
+                                (const int32_t *)sk->k_eff.p, k, nr, (double *)q->S.p, q->rot.p,
+                                (int32_t *)sk->flags.p, s, fp64));
+        const int64_t step_stride = n * sk->m_pad;
+        HIP_TRY(c, launch_reconstruct(sk->Vstore.p, fp64, step_stride, sk->m_pad, (const double *)q->S.p,
+                                      (const double *)sk->norm2.p, k, (int32_t)n, nr, q->B.p, m, s));
+        // 2. G block, raw +-1 in the columns after the sketch (hash columns
+        // g_col0, g_col0 + 1, ...)
+        if (nh > 0) HIP_TRY(c, launch_rademacher_fill(q->B.p, fp64, (int32_t)n, nh, m, nr, g_col0, seed, keys, s));
+        // 3. Q = orth(Y) by CholeskyQR2 (FP64 Gram and triangular factors,
+        // two passes, in place): the first pass leaves an orthogonality
+        // error of about u cond(Y)^2, the second brings it to the rounding
+        // of Q's storage
+        for (int pass = 0; pass < 2; ++pass) {
+            HIP_TRY(c, launch_gram(q->B.p, m, q->B.p, m, fp64, (int32_t)n, nr, nr, (double *)q->gram_part.p,
+                                   (double *)q->gram.p, s));
+            HIP_TRY(c, launch_cholinv((double *)q->gram.p, (double *)q->rinv.p, nr, (int32_t *)sk->flags.p, s));
+            HIP_TRY(c, launch_apply(q->B.p, m, (const double *)q->rinv.p, nr, nr, q->B.p, m, fp64, (int32_t)n, 0,
+                                    s));
+        }
     }
     // 4. G~ = G - Q (Q^T G)
     if (nh > 0) {

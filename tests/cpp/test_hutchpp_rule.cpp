@@ -54,13 +54,18 @@ static void self_checks() {
     CHECK(r.next() == 12);
     r.record(3.68, 1e-5);
     CHECK(r.done() && r.next() == 0 && r.rounds().size() == 3);
-    CHECK(r.kept() == 2 && r.final_nh() == 16 && !r.capped() && r.reuse_last());
+    CHECK(r.kept() == 2 && r.final_nh() == 16 && !r.capped() && r.reuse());
     CHECK(r.krylov_runs() == 2 * (3 + 6 + 12) + 3 * 16);
     // one round at r_max, capped
     HutchppRule c(1e-4, 0.0, 1e-2, 16, 3, 3, 32);
     c.record(10.0, 1.0);
-    CHECK(c.done() && c.capped() && c.final_nh() == 32 && !c.reuse_last());
-    CHECK(c.krylov_runs() == (6 + 16) + (6 + 32));
+    CHECK(c.done() && c.capped() && c.final_nh() == 32 && !c.reuse());
+    CHECK(c.krylov_runs() == (6 + 16) + (3 + 32));
+    // a round that asks for the pilot's count ends the rounds (the next
+    // width costs at least 2 * 6 + 16 = 28 > 22) and is the final run itself
+    HutchppRule e(1e-2, 0.0, 1e-2, 16, 3, 96, 4096);
+    e.record(10.0, 1e-6);
+    CHECK(e.done() && e.rounds().size() == 1 && e.reuse() && e.krylov_runs() == 22);
 }
 
 static int run_cases() {
@@ -92,7 +97,7 @@ static int run_cases() {
         for (const HutchppRound &r : rule.rounds())
             std::printf("  %d %lld %.17g", r.nr, (long long)r.nh, r.eps_hat);
         std::printf(" kept %zu nh %d capped %d reuse %d runs %lld\n", rule.kept(), rule.final_nh(),
-                    rule.capped() ? 1 : 0, rule.reuse_last() ? 1 : 0, (long long)rule.krylov_runs());
+                    rule.capped() ? 1 : 0, rule.reuse() ? 1 : 0, (long long)rule.krylov_runs());
     }
     return 0;
 }
