@@ -191,7 +191,24 @@ def cpu_baseline(g, spec, sample_cols, k):
     return dict(value=bytes_equiv / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
                 sample="oracle Lanczos + Gauss quadrature on %d Rademacher columns x %d steps "
                        "of the same graph (%.1f s); GB/s counts the bytes the FP32 path would move "
-                       "for the same steps" % (sample_cols, k, dt))
+                       "for the same steps" % (sample_cols, k, dt),
+                host=host_cpu())
+
+
+def host_cpu():
+    """The host CPU the oracle ran on: model name, logical CPUs of the
+    machine and CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def measure_batch(warmup, steps, cpu_seconds=None):
