@@ -361,7 +361,7 @@ def exact_entropy_dense(g):
     return float(-np.sum(lam * np.log(lam)))
 
 
-def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max_cols=256, zipf=0.0,
+def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max_cols=256, zipf=0.0, pilot=0,
                   exact_n_max=4000):
     """Poisson streams of 1e-3 relative-accuracy queries on a pool of ER / BA
     / WS graphs (n log-uniform in [1e3, 2e6]).  Per rate: completed queries/s,
@@ -388,7 +388,7 @@ def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max
           file=sys.stderr, flush=True)
     eps = 1e-3
     srv = vne.Server(ctx, vne.MODE_DESING, arena_bytes=int(arena_gb * (1 << 30)), max_slots=max_slots,
-                     max_cols=max_cols, max_probes=4096)
+                     max_cols=max_cols, max_probes=4096, pilot_probes=pilot)
     # untimed: one query per graph (device arrays of every graph, first launches)
     for gid, *_ in pool:
         srv.poll(srv.submit(gid, rel_eps=eps, seed=1))
@@ -456,7 +456,8 @@ def run_serve(args):
     """Poisson stream of 1e-3 relative-accuracy queries on a pool of ER / BA /
     WS graphs (n log-uniform in [1e3, 2e6]) at several arrival rates."""
     rates = [float(r) for r in args.rates.split(",")]
-    sv = measure_serve(rates, args.queries, args.pool, args.arena_gb, args.max_slots, args.max_cols, args.zipf)
+    sv = measure_serve(rates, args.queries, args.pool, args.arena_gb, args.max_slots, args.max_cols, args.zipf,
+                       args.pilot)
     rows = sv["rows"]
     best = max(rows, key=lambda r: r["completed_per_s"])
     res = {
@@ -740,6 +741,8 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=96.0, help="serve workload: server arena (GiB)")
     ap.add_argument("--max-slots", type=int, default=64, help="serve workload: tasks running at once")
     ap.add_argument("--max-cols", type=int, default=256, help="serve workload: probe columns per task")
+    ap.add_argument("--pilot", type=int, default=0,
+                    help="serve workload: pilot probes of a query (0: the server's default, 16)")
     ap.add_argument("--zipf", type=float, default=0.0,
                     help="serve workload: Zipf exponent of graph popularity (0: uniform)")
     ap.add_argument("--graph", default="ws", help="probing-eps workload: ws (small-world) or ring (lattice)")
