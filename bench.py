@@ -362,7 +362,7 @@ def exact_entropy_dense(g):
 
 
 def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max_cols=256, zipf=0.0, pilot=0,
-                  exact_n_max=4000):
+                  exact_n_max=4000, max_group=0):
     """Poisson streams of 1e-3 relative-accuracy queries on a pool of ER / BA
     / WS graphs (n log-uniform in [1e3, 2e6]).  Per rate: completed queries/s,
     p50/p99 latency, the fraction that meet the sampling target, and on the
@@ -388,7 +388,7 @@ def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max
           file=sys.stderr, flush=True)
     eps = 1e-3
     srv = vne.Server(ctx, vne.MODE_DESING, arena_bytes=int(arena_gb * (1 << 30)), max_slots=max_slots,
-                     max_cols=max_cols, max_probes=4096, pilot_probes=pilot)
+                     max_cols=max_cols, max_probes=4096, pilot_probes=pilot, max_group=max_group)
     # untimed: one query per graph (device arrays of every graph, first launches)
     for gid, *_ in pool:
         srv.poll(srv.submit(gid, rel_eps=eps, seed=1))
@@ -427,7 +427,7 @@ def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max
         # this rate's share of the server's running counters
         dt_ticks = max(1, info["ticks"] - prev["ticks"])
         occ = (info["slot_occupancy"] * info["ticks"] - prev["slot_occupancy"] * prev["ticks"]) / dt_ticks
-        tasks, pairs = info["tasks"] - prev["tasks"], info["pair_slots"] - prev["pair_slots"]
+        tasks, grouped = info["tasks"] - prev["tasks"], info["group_tasks"] - prev["group_tasks"]
         prev = info
         row = {"offered_per_s": rate, "queries": queries, "completed": ok,
                "completed_per_s": round(ok / wall, 3), "p50_ms": round(float(np.percentile(lat, 50)), 3),
@@ -437,7 +437,7 @@ def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max
                "sampling_target_met": met, "fraction_sampling_target_met": round(met / queries, 4),
                "queries_with_exact_entropy": len(with_exact), "within_1e-3_of_exact": within,
                "worst_rel_err_vs_exact": worst,
-               "slot_occupancy": round(occ, 2), "tasks": tasks, "tasks_in_pair_slots": 2 * pairs}
+               "slot_occupancy": round(occ, 2), "tasks": tasks, "tasks_in_group_slots": grouped}
         print("rate %s" % json.dumps(row), file=sys.stderr, flush=True)
         rows.append(row)
     srv.stop()
@@ -457,7 +457,7 @@ def run_serve(args):
     WS graphs (n log-uniform in [1e3, 2e6]) at several arrival rates."""
     rates = [float(r) for r in args.rates.split(",")]
     sv = measure_serve(rates, args.queries, args.pool, args.arena_gb, args.max_slots, args.max_cols, args.zipf,
-                       args.pilot)
+                       args.pilot, max_group=args.group)
     rows = sv["rows"]
     best = max(rows, key=lambda r: r["completed_per_s"])
     res = {
@@ -467,7 +467,8 @@ def run_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve_pool%d_er_ba_ws_n1e3_2e6_eps1e-3_f32" % sv["pool"], "graphs": sv["pool"],
                    "rel_eps": sv["rel_eps"], "rates": args.rates, "queries_per_rate": args.queries,
-                   "zipf": args.zipf, "graph_seed": __import__("synth").workloads.GRAPH_SEED_SERVE},
+                   "zipf": args.zipf, "pilot": args.pilot or 16, "max_group": args.group or 2,
+                   "graph_seed": __import__("synth").workloads.GRAPH_SEED_SERVE},
         "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"], "rates": rows,
         "roofline": None, "cpu_baseline": None,
     }
@@ -743,6 +744,8 @@ def main():
     ap.add_argument("--max-cols", type=int, default=256, help="serve workload: probe columns per task")
     ap.add_argument("--pilot", type=int, default=0,
                     help="serve workload: pilot probes of a query (0: the server's default, 16)")
+    ap.add_argument("--group", type=int, default=0,
+                    help="serve workload: largest group slot of 16-column tasks, 1, 2 or 4 (0: the server's default)")
     ap.add_argument("--zipf", type=float, default=0.0,
                     help="serve workload: Zipf exponent of graph popularity (0: uniform)")
     ap.add_argument("--graph", default="ws", help="probing-eps workload: ws (small-world) or ring (lattice)")

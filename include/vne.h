@@ -548,14 +548,17 @@ vne_status vne_last_plan(const vne_ctx *ctx, int32_t *tile, int32_t *m_pad);
  * frees its slot at once, and the query's estimate is combined on the device
  * when its last task ends.  A task's arithmetic depends only on its own graph,
  * probes and step count, so a query's result is bitwise the same alone and
- * among any other queries (for the same server mode).  Two 16-column tasks
- * (FP32 mode) of the same graph with the same step cap and stopping rule may
- * share a pair slot, admitted together: the two 16-column tiles of a work
- * block run in one workgroup and read each neighbour's 32 columns as one
- * 128-byte run, where one task alone would use half of every cache line it
- * fetches.  Each task keeps its own probes, stop record and results, with the
- * arithmetic it has alone; a pair slot's step kernels stop running once both
- * tasks have met their stopping rule.
+ * among any other queries (for the same server mode).  Two or four
+ * 16-column tasks (FP32 mode) of the same graph with the same step cap and
+ * stopping rule may share a group slot, admitted together: the 16-column
+ * tiles of a work block run in one workgroup and read each neighbour's 32 or
+ * 64 columns as one run of 128 or 256 bytes, where one task alone would use
+ * half of every cache line it fetches.  The configuration's
+ * max_group (1, 2 or 4; default 2) sets the largest group; a group is
+ * the largest power of two of the waiting partners that the free mailbox
+ * entries and the arena allow.  Each task keeps its own probes, stop record
+ * and results, with the arithmetic it has alone; a group slot's step kernels
+ * stop running once every task has met its stopping rule.
  *
  * rel_eps == 0: the query gives m (<= max_probes) and k_steps (<= 128).
  * rel_eps > 0: half of the relative error budget goes to the quadrature and
@@ -596,6 +599,8 @@ typedef struct {
     int32_t max_steps;          /* cap on the planned step count (0: 100; at most 128) */
     double z;                   /* standard errors of the sampling bound (0: 2.576, delta = 1e-2) */
     uint32_t mode;              /* VNE_MODE_* bits of every query of the server */
+    int32_t max_group;          /* largest group slot of 16-column FP32 tasks: 1 (none), 2 or 4
+                                   (0: 2); other values fail with VNE_EINVAL */
 } vne_server_cfg;
 
 typedef struct {
@@ -622,7 +627,9 @@ typedef struct {
     double slot_occupancy;      /* mean running tasks per tick */
     uint64_t arena_bytes, arena_in_use, arena_peak;
     int32_t active, pending;    /* running and waiting tasks */
-    int64_t pair_slots;         /* slots admitted with two tasks */
+    int64_t pair_slots;         /* group slots admitted with two tasks */
+    int64_t group_tasks;        /* tasks admitted into group slots (two or four 16-column
+                                   tasks of one graph) */
 } vne_server_info;
 
 /* Start a server on ctx.  cfg is copied.  Fails with VNE_ENOMEM when the

@@ -130,7 +130,7 @@ class _DistanceChoice(ctypes.Structure):
 class _ServerCfg(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("arena_bytes", ctypes.c_uint64), ("max_cols", ctypes.c_int32),
                 ("pilot_probes", ctypes.c_int32), ("max_probes", ctypes.c_int32), ("max_steps", ctypes.c_int32),
-                ("z", ctypes.c_double), ("mode", ctypes.c_uint32)]
+                ("z", ctypes.c_double), ("mode", ctypes.c_uint32), ("max_group", ctypes.c_int32)]
 
 
 class _Query(ctypes.Structure):
@@ -148,7 +148,7 @@ class _ServerInfo(ctypes.Structure):
     _fields_ = [("ticks", ctypes.c_int64), ("tasks", ctypes.c_int64), ("queries_done", ctypes.c_int64),
                 ("slot_occupancy", ctypes.c_double), ("arena_bytes", ctypes.c_uint64),
                 ("arena_in_use", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64), ("active", ctypes.c_int32),
-                ("pending", ctypes.c_int32), ("pair_slots", ctypes.c_int64)]
+                ("pending", ctypes.c_int32), ("pair_slots", ctypes.c_int64), ("group_tasks", ctypes.c_int64)]
 
 
 _LIB = None
@@ -640,10 +640,10 @@ class Server:
     """Serving loop on a context (continuous batching, HBM-budget admission)."""
 
     def __init__(self, ctx, mode, arena_bytes=0, max_slots=0, max_cols=0, pilot_probes=0, max_probes=0,
-                 max_steps=0, z=0.0):
+                 max_steps=0, z=0.0, max_group=0):
         self._ctx = ctx
         self._L = ctx._L
-        cfg = _ServerCfg(max_slots, arena_bytes, max_cols, pilot_probes, max_probes, max_steps, z, mode)
+        cfg = _ServerCfg(max_slots, arena_bytes, max_cols, pilot_probes, max_probes, max_steps, z, mode, max_group)
         h = ctypes.c_void_p()
         ctx._chk(self._L.vne_server_start(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

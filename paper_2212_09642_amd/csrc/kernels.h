@@ -101,8 +101,8 @@ struct FinalizeArgs {
     const int2 *stop_state;            // slots: as in StepArgs
     int32_t stop_uid;
     int32_t stop_count;
-    int32_t *flags_hi;                 // slots: flags of columns >= flag_split (nullptr: flags)
-    int32_t flag_split;
+    int32_t *flags_mem[4];             // group slots: flags of member c / mem_cols (nullptr: flags)
+    int32_t mem_cols;                  // columns per member of a group slot (0: one query)
     const int32_t *col_stop;           // as in StepArgs: done columns keep their coefficients
     // one graph: the reduction and update of columns [col_base, col_base +
     // col_count) only (col_count 0: every column)
@@ -136,12 +136,13 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
 hipError_t launch_step_slots(const StepArgs *args, const int4 *step_map, int32_t n_step, const int4 *long_map,
                              int32_t n_long, int32_t mt, bool fp64, hipStream_t s);
 int long_rows_per_group(int mt, bool fp64);
-// Slots of exactly two 16-column FP32 tiles (m_pad = 32, mt = 16), both
-// tiles of a work block in one workgroup: pair_map entries {slot, work block,
-// 0, 0}; long_map entries {slot, group, tile, 0} as for mt = 16.  Every
-// column gets the same arithmetic, in the same order, as in a 16-column slot.
-hipError_t launch_step_pairs(const StepArgs *args, const int4 *pair_map, int32_t n_pair, const int4 *long_map,
-                             int32_t n_long, hipStream_t s);
+// Group slots of `members` (2 or 4) 16-column FP32 tiles (m_pad = 16 *
+// members, mt = 16), every tile of a work block in one workgroup: group_map
+// entries {slot, work block, 0, 0}; long_map entries {slot, group, tile, 0}
+// as for mt = 16.  Every column gets the same arithmetic, in the same order,
+// as in a 16-column slot.
+hipError_t launch_step_groups(const StepArgs *args, const int4 *group_map, int32_t n_group, const int4 *long_map,
+                              int32_t n_long, int32_t members, hipStream_t s);
 constexpr int kFinalizeCols = 16;
 constexpr int kSlotLevel2 = 16;   // first-level parts of a slot's reduction (FinalizeArgs.n_level2)
 hipError_t launch_finalize_slots(const FinalizeArgs *fargs, const int2 *map, int32_t n_entries, hipStream_t s);

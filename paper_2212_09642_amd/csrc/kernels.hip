@@ -616,18 +616,19 @@ __global__ void __launch_bounds__(kStepThreads) VNE_STEP_OCCUPANCY k_lanczos_ste
     step_block<T, CPL, LPR, false, true>(a, e.y, e.z, red);
 }
 
-// Two column tiles of one slot per block (2 * kStepThreads threads): entry
-// {slot, work block, first tile}.  For slots of two narrow tiles, whose
-// single-tile blocks would each gather half of every cache line they fetch.
-template <typename T, int CPL, int LPR>
-__global__ void __launch_bounds__(2 * kStepThreads) k_lanczos_step_pairs(const StepArgs *args, const int4 *map,
-                                                                          int32_t n_entries) {
+// JT column tiles of one slot per block (JT * kStepThreads threads): entry
+// {slot, work block, first tile}.  For group slots of narrow tiles, whose
+// single-tile blocks would each gather a part of every cache line they
+// fetch; each tile keeps the arithmetic and order it has alone.
+template <typename T, int CPL, int LPR, int JT>
+__global__ void __launch_bounds__(JT * kStepThreads) k_lanczos_step_groups(const StepArgs *args, const int4 *map,
+                                                                            int32_t n_entries) {
     constexpr int NG = (kStepThreads / 64) * (64 / LPR);
-    __shared__ double red[2 * 3][NG * CPL * LPR];
+    __shared__ double red[JT * 3][NG * CPL * LPR];
     const int4 e = map[xcd_remap(blockIdx.x, n_entries)];
     const StepArgs a = args[e.x];
     if (slot_stopped(a.stop_state, a.stop_uid, a.stop_count)) return;
-    step_block<T, CPL, LPR, false, true, 2>(a, e.y, e.z, red);
+    step_block<T, CPL, LPR, false, true, JT>(a, e.y, e.z, red);
 }
 
 // Normalize pass of the slots: entry {slot, work block, tile} writes v_j on
@@ -840,13 +841,23 @@ hipError_t launch_step_slots(const StepArgs *args, const int4 *step_map, int32_t
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_pairs(const StepArgs *args, const int4 *pair_map, int32_t n_pair, const int4 *long_map,
-                             int32_t n_long, hipStream_t s) {
-    if (n_pair > 0) {
-        // the normalize pass is elementwise: both tiles as one 32-column tile
-        hipLaunchKernelGGL((k_normalize_slots<float, 4, 8>), dim3(n_pair), dim3(256), 0, s, args, pair_map, n_pair);
-        hipLaunchKernelGGL((k_lanczos_step_pairs<float, 4, 4>), dim3(n_pair), dim3(2 * kStepThreads), 0, s, args,
-                           pair_map, n_pair);
+hipError_t launch_step_groups(const StepArgs *args, const int4 *group_map, int32_t n_group, const int4 *long_map,
+                              int32_t n_long, int32_t members, hipStream_t s) {
+    if (members != 2 && members != 4) return hipErrorInvalidValue;
+    if (n_group > 0) {
+        // the normalize pass is elementwise: the members' tiles as one tile
+        // of 16 * members columns
+        if (members == 2) {
+            hipLaunchKernelGGL((k_normalize_slots<float, 4, 8>), dim3(n_group), dim3(256), 0, s, args, group_map,
+                               n_group);
+            hipLaunchKernelGGL((k_lanczos_step_groups<float, 4, 4, 2>), dim3(n_group), dim3(2 * kStepThreads), 0, s,
+                               args, group_map, n_group);
+        } else {
+            hipLaunchKernelGGL((k_normalize_slots<float, 4, 16>), dim3(n_group), dim3(256), 0, s, args, group_map,
+                               n_group);
+            hipLaunchKernelGGL((k_lanczos_step_groups<float, 4, 4, 4>), dim3(n_group), dim3(4 * kStepThreads), 0, s,
+                               args, group_map, n_group);
+        }
     }
     if (n_long > 0) hipLaunchKernelGGL((k_long_rows_slots<float, 4, 4>), dim3(n_long), dim3(256), 0, s, args, long_map);
     return hipGetLastError();
@@ -968,7 +979,12 @@ __device__ __forceinline__ void update_coefficients(const FinalizeArgs &a, int g
     const double beta = sqrt(b2);
     a.alpha[gc * a.k + j] = alpha;
     const bool finite = isfinite(alpha) && isfinite(beta);
-    if (!finite) atomicOr(a.flags_hi && c >= a.flag_split ? a.flags_hi : a.flags, 1);
+    if (!finite) {
+        // a group slot's column reports to its member's query
+        int32_t *fl = a.flags;
+        if (a.mem_cols > 0 && a.flags_mem[c / a.mem_cols]) fl = a.flags_mem[c / a.mem_cols];
+        atomicOr(fl, 1);
+    }
     if (!finite || beta <= a.tau * (fabs(alpha) + coup_prev)) {
         a.k_eff[gc] = a.step;
         a.beta[gc * a.k + j] = 0.0;

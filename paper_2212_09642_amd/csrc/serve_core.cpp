@@ -214,17 +214,18 @@ bool ServeCore::open_query(ServeQuery &q, vne_status *st) {
     return true;
 }
 
-// A task that can share a pair slot: 16 FP32 columns in one 16-column tile.
-bool ServeCore::pairable(const ServeTask &t) const {
-    return !cfg_.fp64 && t.n_mem == 1 && t.m == 16 && t.m_pad == 16 && t.mt == 16;
+// A task that can join a group slot: 16 FP32 columns in one 16-column tile.
+bool ServeCore::groupable(const ServeTask &t) const {
+    return !cfg_.fp64 && cfg_.max_group > 1 && t.n_mem == 1 && t.m == 16 && t.m_pad == 16 && t.mt == 16;
 }
 
 // Starts waiting tasks while mailbox entries and arena space allow.  First
 // come, first served: a task that does not fit blocks the ones behind it
 // (with skip_blocked, later tasks that fit start meanwhile).  A 16-column
-// FP32 task takes the first waiting 16-column task of the same graph with
-// the same step cap and stopping mode as its partner in a pair slot, when
-// the arena has room for it.
+// FP32 task takes the first waiting 16-column tasks of the same graph with
+// the same step cap and stopping mode as its partners in a group slot of
+// two or four tasks (at most max_group), as far as mailbox entries and the
+// arena allow.
 vne_status ServeCore::admit() {
     size_t head = 0;   // index in pending_ of the task considered
     while (head < pending_.size() && !free_slots_.empty()) {
@@ -243,29 +244,37 @@ vne_status ServeCore::admit() {
             ++head;
             return true;
         };
-        // partner search
-        size_t partner = 0;
-        ServeQuery *pq = nullptr;
-        uint64_t pair_bytes = 0;
-        if (pairable(t) && free_slots_.size() >= 2) {
+        // partner search: pending indices of the partners, in queue order
+        std::vector<size_t> partners;
+        if (groupable(t) && free_slots_.size() >= 2) {
             const size_t lim = std::min(pending_.size(), head + (size_t)kPairWindow);
-            for (size_t i = head + 1; i < lim; ++i) {
+            for (size_t i = head + 1; i < lim && (int)partners.size() + 1 < cfg_.max_group; ++i) {
                 const ServeTask &c = pending_[i];
-                if (!pairable(c) || c.k != t.k || c.mem[0].adaptive != t.mem[0].adaptive) continue;
+                if (!groupable(c) || c.k != t.k || c.mem[0].adaptive != t.mem[0].adaptive) continue;
                 ServeQuery *cq = query_of(c.mem[0].ticket);
                 if (!cq || cq->q.graph_id != q->q.graph_id) continue;
-                partner = i;
-                pq = cq;
-                break;
-            }
-            if (partner > 0) {
-                pair_bytes = exec_->task_bytes(*q, 32, t.k);
-                uint64_t room = arena_.round(pair_bytes);
-                if (!q->started) room += cfg_.query_bytes;
-                if (pq != q && !pq->started) room += cfg_.query_bytes;
-                if (arena_.largest_free() < room) partner = 0;
+                partners.push_back(i);
             }
         }
+        // the group: the largest power of two of the members found that
+        // fits the free mailbox entries and the arena (with the blocks of the
+        // queries that have not started yet)
+        auto fits = [&](int g) {
+            if (g > (int)free_slots_.size()) return false;
+            uint64_t room = arena_.round(exec_->task_bytes(*q, 16 * g, t.k));
+            std::vector<ServeQuery *> seen;
+            for (int i = 0; i < g; ++i) {
+                ServeQuery *mq = i == 0 ? q : query_of(pending_[partners[i - 1]].mem[0].ticket);
+                if (mq->started || std::find(seen.begin(), seen.end(), mq) != seen.end()) continue;
+                seen.push_back(mq);
+                room += cfg_.query_bytes;
+            }
+            return arena_.largest_free() >= room;
+        };
+        int g = 1;
+        while (2 * g <= 1 + (int)partners.size() && 2 * g <= cfg_.max_group) g *= 2;
+        while (g > 1 && !fits(g)) g /= 2;
+        partners.resize(g - 1);
         if (!q->started) {
             if (arena_.largest_free() < cfg_.query_bytes + arena_.round(t.bytes)) {
                 if (blocked()) continue;
@@ -278,26 +287,39 @@ vne_status ServeCore::admit() {
             }
             SC_TRY(st);
         }
-        if (partner > 0 && !pq->started) {
+        for (size_t pi = 0; pi < partners.size(); ++pi) {
+            ServeQuery *cq = query_of(pending_[partners[pi]].mem[0].ticket);
+            if (cq->started) continue;
             vne_status st;
-            if (!open_query(*pq, &st)) partner = 0;
+            if (!open_query(*cq, &st)) {
+                partners.resize(pi);
+                SC_TRY(st);
+                break;
+            }
             SC_TRY(st);
         }
-        if (partner > 0) {
-            t.mem[1] = pending_[partner].mem[0];
-            t.mem[1].c_off = 16;
-            t.n_mem = 2;
-            t.m = 32;
-            t.m_pad = 32;
-            t.bytes = pair_bytes;
+        // a group cut short by a query that could not open: the largest
+        // power of two that remains
+        g = 1;
+        while (2 * g <= 1 + (int)partners.size()) g *= 2;
+        partners.resize(g - 1);
+        if (g > 1) {
+            for (int i = 1; i < g; ++i) {
+                t.mem[i] = pending_[partners[i - 1]].mem[0];
+                t.mem[i].c_off = 16 * i;
+            }
+            t.n_mem = g;
+            t.m = t.m_pad = 16 * g;
+            t.bytes = exec_->task_bytes(*q, 16 * g, t.k);
         }
         if (!arena_.alloc(t.bytes, &t.off)) {
-            if (partner == 0) {
+            if (g == 1) {
                 if (blocked()) continue;
                 break;
             }
-            // no room for the pair after all: the task alone
-            partner = 0;
+            // no room for the group after all: the task alone
+            g = 1;
+            partners.clear();
             t.n_mem = 1;
             t.m = t.m_pad = 16;
             t.bytes = exec_->task_bytes(*q, 16, t.k);
@@ -307,18 +329,21 @@ vne_status ServeCore::admit() {
             }
         }
         arena_peak_ = std::max(arena_peak_, arena_.in_use());
-        if (partner > 0) pending_.erase(pending_.begin() + partner);
+        for (size_t pi = partners.size(); pi-- > 0;) pending_.erase(pending_.begin() + partners[pi]);
         pending_.erase(pending_.begin() + head);
+        ServeQuery *qm[kMaxMembers] = {};
         for (int i = 0; i < t.n_mem; ++i) {
             t.mem[i].uid = next_uid_ + i;
             t.mem[i].slot = free_slots_.back();
             free_slots_.pop_back();
+            qm[i] = i == 0 ? q : query_of(t.mem[i].ticket);
         }
         next_uid_ += t.n_mem;
-        SC_TRY(exec_->start_task(t, *q, t.pair() ? pq : nullptr));
+        SC_TRY(exec_->start_task(t, qm));
         active_.push_back(t);
         tasks_admitted_ += t.n_mem;
-        pair_slots_ += t.pair() ? 1 : 0;
+        pair_slots_ += t.n_mem == 2 ? 1 : 0;
+        group_tasks_ += t.n_mem > 1 ? t.n_mem : 0;
     }
     return VNE_OK;
 }
@@ -350,14 +375,14 @@ vne_status ServeCore::end_member(ServeTask &t, int i, ServeQuery &q, int steps) 
 // adaptive members whose recorded stop step has reached the host, end.
 vne_status ServeCore::tick() {
     const int A = (int)active_.size();
-    std::vector<ServeQuery *> qs(2 * A, nullptr);
+    std::vector<ServeQuery *> qs((size_t)kMaxMembers * A, nullptr);
     int running = 0;
     for (int i = 0; i < A; ++i)
         for (int mi = 0; mi < active_[i].n_mem; ++mi) {
             // a member that ended may belong to a query that has finished
             // (and whose result the caller may have taken already)
             if (active_[i].mem[mi].ended) continue;
-            qs[2 * i + mi] = query_of(active_[i].mem[mi].ticket);
+            qs[(size_t)kMaxMembers * i + mi] = query_of(active_[i].mem[mi].ticket);
             running++;
         }
     SC_TRY(exec_->tick(active_, qs));
@@ -381,7 +406,7 @@ vne_status ServeCore::tick() {
                 open = true;
                 continue;
             }
-            SC_TRY(end_member(t, mi, *qs[2 * i + mi], use));
+            SC_TRY(end_member(t, mi, *qs[(size_t)kMaxMembers * i + mi], use));
         }
         if (open) keep.push_back(t);
         else arena_.release(t.off);
@@ -403,6 +428,7 @@ void ServeCore::publish() {
     snap_.ticks = ticks_;
     snap_.tasks = tasks_admitted_;
     snap_.pair_slots = pair_slots_;
+    snap_.group_tasks = group_tasks_;
     snap_.slot_occupancy = ticks_ ? occupancy_sum_ / (double)ticks_ : 0.0;
     snap_.arena_bytes = arena_.size();
     snap_.arena_in_use = arena_.in_use();

@@ -41,16 +41,19 @@ struct ServeMember {
     bool ended = false;
 };
 
-// A slot: one task of a query, or two 16-column FP32 tasks of two queries on
-// the same graph with the same step cap (a pair slot, m_pad = 32, mt = 16).
-// Its state lives in the arena at [off, off + bytes).
+constexpr int kMaxMembers = 4;       // tasks of a group slot at most
+
+// A slot: one task of a query, or a group of two or four 16-column FP32
+// tasks of queries on the same graph with the same step cap and stopping
+// mode (a group slot, m_pad = 16 * n_mem, mt = 16).  Its state lives in the
+// arena at [off, off + bytes).
 struct ServeTask {
     int m = 0, m_pad = 0, mt = 0, k = 0;
     int j = 0;                       // steps done
     uint64_t off = 0, bytes = 0;
     int n_mem = 1;
-    ServeMember mem[2];
-    bool pair() const { return n_mem == 2; }
+    ServeMember mem[kMaxMembers];
+    bool group() const { return n_mem > 1; }
 };
 
 struct ServeQuery {
@@ -87,11 +90,12 @@ public:
     // q.off: result buffers and the cleared flags
     virtual vne_status open_query(ServeQuery &q) = 0;
     // slot state at t.off (members' uids and mailbox entries assigned):
-    // probe blocks of the members, cleared stop records
-    virtual vne_status start_task(ServeTask &t, ServeQuery &q0, ServeQuery *q1) = 0;
-    // one Lanczos step of every active slot (qs[2 i + mi]: the query of
-    // member mi of slot i, null for a member that has ended: its query may
-    // be gone), with the a-posteriori checks of adaptive members
+    // probe blocks of the members (qm[i]: the query of member i), cleared
+    // stop records
+    virtual vne_status start_task(ServeTask &t, ServeQuery *const *qm) = 0;
+    // one Lanczos step of every active slot (qs[kMaxMembers i + mi]: the
+    // query of member mi of slot i, null for a member that has ended: its
+    // query may be gone), with the a-posteriori checks of adaptive members
     virtual vne_status tick(const std::vector<ServeTask> &active, const std::vector<ServeQuery *> &qs) = 0;
     // the stop record of a mailbox entry as the host sees it now
     virtual void stop_record(int slot, int32_t *uid, int32_t *step) = 0;
@@ -124,6 +128,9 @@ struct ServeConfig {
     // admission: a task that does not fit may let later tasks that do fit
     // start before it (false: first come, first served)
     bool skip_blocked = false;
+    // largest group slot of 16-column FP32 tasks of one graph: 1 (none), 2
+    // or 4
+    int max_group = 2;
 };
 
 class ServeCore {
@@ -154,7 +161,7 @@ private:
     vne_status end_member(ServeTask &t, int i, ServeQuery &q, int steps);
     vne_status poll_events(bool block_one);
     bool open_query(ServeQuery &q, vne_status *st);
-    bool pairable(const ServeTask &t) const;
+    bool groupable(const ServeTask &t) const;
     vne_status admit();
     vne_status tick();
     bool has_waits();
@@ -182,7 +189,7 @@ private:
     std::vector<ServeTask> active_;
     std::vector<int> free_slots_;
     int32_t next_uid_ = 1;
-    int64_t ticks_ = 0, tasks_admitted_ = 0, pair_slots_ = 0;
+    int64_t ticks_ = 0, tasks_admitted_ = 0, pair_slots_ = 0, group_tasks_ = 0;
     double occupancy_sum_ = 0.0;
 };
 

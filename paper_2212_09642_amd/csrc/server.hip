@@ -2,15 +2,16 @@
 // budget, run with continuous batching.
 //
 // A query is split into slot tasks of at most max_cols probe columns.  An
-// admitted task gets a slot (two 16-column FP32 tasks of one graph that wait
-// together may share a pair slot): its matrix stays the registered graph's,
+// admitted task gets a slot (two or four 16-column FP32 tasks of one graph
+// that wait together may share a group slot): its matrix stays the
+// registered graph's,
 // its vectors and Lanczos state live in the server's arena.  One tick
 // advances every active slot by one Lanczos step in a few launches
 // (normalize, SpMM + recurrence, long rows, finalize) whatever graphs the
 // slots belong to; a task that reaches its step count gets its quadrature
 // and leaves, and waiting tasks are admitted between ticks as mailbox
 // entries and arena space free up.  A task's arithmetic depends only on its
-// own graph, probes and step count (in a pair slot too), so a query gives
+// own graph, probes and step count (in a group slot too), so a query gives
 // the same bits alone and in any mix.
 //
 // With rel_eps > 0 a query first runs a pilot of pilot_probes columns; the
@@ -147,7 +148,7 @@ public:
     char *d_desc = nullptr;
     size_t d_desc_cap = 0;
     int2 *mailbox = nullptr;         // pinned [max_slots]: stop records
-    // flags word of the columns of a pair slot's member that has ended (its
+    // flags word of the columns of a group slot's member that has ended (its
     // query's block may belong to another query by now)
     DevBuf sink;
     std::mutex err_mu;
@@ -221,7 +222,7 @@ public:
         pa.gen = GEN_RADEMACHER;
         pa.n = (int32_t)set->n;
         pa.m = u.m;
-        pa.m_pad = t.pair() ? t.mt : t.m_pad;
+        pa.m_pad = t.group() ? t.mt : t.m_pad;
         pa.mt = t.mt;
         pa.ld_out = t.m_pad;
         pa.col_offset = u.col0;
@@ -246,13 +247,12 @@ public:
         return hip_err(launch_probe(pa, fp64, stream), "launch_probe");
     }
 
-    vne_status start_task(ServeTask &t, ServeQuery &q0, ServeQuery *q1) override {
-        const DevTask d = dev(t, q0);
+    vne_status start_task(ServeTask &t, ServeQuery *const *qm) override {
+        const DevTask d = dev(t, *qm[0]);
         VNE_TRY(hip_err(hipMemsetAsync(d.d_state, 0, sizeof(int2) * t.n_mem, stream), "hipMemsetAsync"));
-        VNE_TRY(member_probes(t, d, 0, q0));
-        if (t.pair()) VNE_TRY(member_probes(t, d, 1, *q1));
+        for (int i = 0; i < t.n_mem; ++i) VNE_TRY(member_probes(t, d, i, *qm[i]));
         // zero v_0
-        return hip_err(hipMemsetAsync(d.V[1], 0, (size_t)gq(q0)->set->n * t.m_pad * (fp64 ? 8 : 4), stream),
+        return hip_err(hipMemsetAsync(d.V[1], 0, (size_t)gq(*qm[0])->set->n * t.m_pad * (fp64 ? 8 : 4), stream),
                        "hipMemsetAsync");
     }
 
@@ -293,8 +293,8 @@ public:
         return a;
     }
 
-    FinalizeArgs fin_args(const ServeTask &t, const DevTask &d, const GraphSet *set, int32_t *flags,
-                          int32_t *flags_hi) const {
+    // flags_m[i]: the flags word of member i's query
+    FinalizeArgs fin_args(const ServeTask &t, const DevTask &d, const GraphSet *set, int32_t *const *flags_m) const {
         FinalizeArgs f{};
         f.partials = d.partials;
         f.long_part = d.long_part;
@@ -314,13 +314,15 @@ public:
         f.alpha = d.alpha;
         f.beta = d.beta;
         f.k_eff = d.k_eff;
-        f.flags = flags;
+        f.flags = flags_m[0];
         f.n_graphs = 1;
         f.stop_state = all_adaptive(t) ? d.d_state : nullptr;
         f.stop_uid = t.mem[0].uid;
         f.stop_count = t.n_mem;
-        f.flags_hi = t.pair() ? flags_hi : nullptr;
-        f.flag_split = t.pair() ? t.mem[1].c_off : t.m_pad;
+        if (t.group()) {
+            for (int i = 0; i < t.n_mem; ++i) f.flags_mem[i] = flags_m[i];
+            f.mem_cols = t.mt;
+        }
         return f;
     }
 
@@ -328,26 +330,30 @@ public:
     vne_status tick(const std::vector<ServeTask> &active, const std::vector<ServeQuery *> &qs) override {
         const int A = (int)active.size();
         // descriptors: StepArgs[A], FinalizeArgs[A], then per tile width the
-        // step and long-row maps (and those of the pair slots), then the
-        // finalize map
+        // step and long-row maps (and per group size those of the group
+        // slots), then the finalize map
         std::vector<DevTask> dt(A);
         std::vector<StepArgs> sa(A);
         std::vector<FinalizeArgs> fa(A);
-        std::map<int, std::vector<int4>> smap, lmap;
-        std::vector<int4> pmap, plmap;
+        std::map<int, std::vector<int4>> smap, lmap, gmap, glmap;
         std::vector<int2> fmap;
         auto flags_of = [&](const ServeQuery *q) { return q ? d_flags(*q) : (int32_t *)sink.p; };
         for (int i = 0; i < A; ++i) {
             const ServeTask &t = active[i];
-            // a running member's query (both members of a pair share the graph)
-            const ServeQuery *q0 = qs[2 * i] ? qs[2 * i] : qs[2 * i + 1];
+            ServeQuery *const *qi = qs.data() + (size_t)kMaxMembers * i;
+            // a running member's query (the members of a group share the graph)
+            const ServeQuery *q0 = nullptr;
+            for (int mi = 0; mi < t.n_mem && !q0; ++mi) q0 = qi[mi];
             const GraphSet *set = gq(*q0)->set;
             dt[i] = dev(t, *q0);
             sa[i] = step_args(t, dt[i], set);
-            fa[i] = fin_args(t, dt[i], set, flags_of(qs[2 * i]), t.pair() ? flags_of(qs[2 * i + 1]) : nullptr);
+            int32_t *flags_m[kMaxMembers] = {};
+            for (int mi = 0; mi < t.n_mem; ++mi) flags_m[mi] = flags_of(qi[mi]);
+            fa[i] = fin_args(t, dt[i], set, flags_m);
             const int nt = t.m_pad / t.mt, nb = set->sched.n_blocks();
-            if (t.pair()) {
-                for (int b = 0; b < nb; ++b) pmap.push_back(make_int4(i, b, 0, 0));
+            if (t.group()) {
+                auto &gm = gmap[t.n_mem];
+                for (int b = 0; b < nb; ++b) gm.push_back(make_int4(i, b, 0, 0));
             } else {
                 auto &sm = smap[t.mt];
                 for (int tile = 0; tile < nt; ++tile)
@@ -355,7 +361,7 @@ public:
             }
             if (set->sched.n_long > 0) {
                 const int per = long_rows_per_group(t.mt, fp64);
-                auto &lm = t.pair() ? plmap : lmap[t.mt];
+                auto &lm = t.group() ? glmap[t.n_mem] : lmap[t.mt];
                 for (int tile = 0; tile < nt; ++tile)
                     for (int gi = 0; gi < (set->sched.n_long + per - 1) / per; ++gi)
                         lm.push_back(make_int4(i, gi, tile, 0));
@@ -376,7 +382,7 @@ public:
             for (int mi = 0; mi < t.n_mem; ++mi) {
                 const ServeMember &u = t.mem[mi];
                 if (!u.adaptive || u.ended) continue;
-                const ServeQuery *q = qs[2 * i + mi];
+                const ServeQuery *q = qs[(size_t)kMaxMembers * i + mi];
                 const Graph *g = gq(*q)->g;
                 const int64_t co = u.c_off;
                 BoundArgs b{};
@@ -413,7 +419,8 @@ public:
         bytes += rnd(sizeof(BoundArgs) * ba.size()) + rnd(sizeof(int2) * bmap.size()) + rnd(sizeof(StopArgs) * sta.size());
         for (auto &kv : smap) bytes += rnd(sizeof(int4) * kv.second.size());
         for (auto &kv : lmap) bytes += rnd(sizeof(int4) * kv.second.size());
-        bytes += rnd(sizeof(int4) * pmap.size()) + rnd(sizeof(int4) * plmap.size());
+        for (auto &kv : gmap) bytes += rnd(sizeof(int4) * kv.second.size());
+        for (auto &kv : glmap) bytes += rnd(sizeof(int4) * kv.second.size());
         // staging ring: wait until the copy that last used this slot has run
         const int r = ring_pos;
         ring_pos = (r + 1) % kRing;
@@ -448,8 +455,9 @@ public:
         std::map<int, const int4 *> d_sm, d_lm;
         for (auto &kv : smap) d_sm[kv.first] = (const int4 *)put(kv.second.data(), sizeof(int4) * kv.second.size());
         for (auto &kv : lmap) d_lm[kv.first] = (const int4 *)put(kv.second.data(), sizeof(int4) * kv.second.size());
-        const int4 *d_pm = (const int4 *)put(pmap.data(), sizeof(int4) * pmap.size());
-        const int4 *d_plm = (const int4 *)put(plmap.data(), sizeof(int4) * plmap.size());
+        std::map<int, const int4 *> d_gm, d_glm;
+        for (auto &kv : gmap) d_gm[kv.first] = (const int4 *)put(kv.second.data(), sizeof(int4) * kv.second.size());
+        for (auto &kv : glmap) d_glm[kv.first] = (const int4 *)put(kv.second.data(), sizeof(int4) * kv.second.size());
         const BoundArgs *d_ba = (const BoundArgs *)put(ba.data(), sizeof(BoundArgs) * ba.size());
         const int2 *d_bm = (const int2 *)put(bmap.data(), sizeof(int2) * bmap.size());
         const StopArgs *d_st = (const StopArgs *)put(sta.data(), sizeof(StopArgs) * sta.size());
@@ -464,10 +472,14 @@ public:
                                               n_long, mt, fp64, stream),
                             "launch_step_slots"));
         }
-        if (!pmap.empty())
-            VNE_TRY(hip_err(launch_step_pairs(d_sa, d_pm, (int32_t)pmap.size(), plmap.empty() ? nullptr : d_plm,
-                                              (int32_t)plmap.size(), stream),
-                            "launch_step_pairs"));
+        for (auto &kv : gmap) {
+            const int members = kv.first;
+            const auto lit = glmap.find(members);
+            const int n_long = lit == glmap.end() ? 0 : (int)lit->second.size();
+            VNE_TRY(hip_err(launch_step_groups(d_sa, d_gm[members], (int32_t)kv.second.size(),
+                                               n_long ? d_glm[members] : nullptr, n_long, members, stream),
+                            "launch_step_groups"));
+        }
         VNE_TRY(hip_err(launch_finalize_slots(d_fa, d_fm, (int32_t)fmap.size(), stream), "launch_finalize_slots"));
         if (!sta.empty()) {
             VNE_TRY(hip_err(launch_error_bound(d_ba, d_bm, (int32_t)bmap.size(), stream), "launch_error_bound"));
@@ -585,6 +597,9 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
     if (k.max_probes <= 0) k.max_probes = 4096;
     if (k.max_steps <= 0) k.max_steps = 100;
     if (!(k.z > 0.0)) k.z = 2.576;
+    if (k.max_group == 0) k.max_group = 2;
+    if (k.max_group != 1 && k.max_group != 2 && k.max_group != 4)
+        return fail(c, VNE_EINVAL, "max_group must be 0, 1, 2 or 4");
     if (k.mode & ~(uint32_t)(VNE_MODE_F64 | VNE_MODE_DESING)) return fail(c, VNE_EINVAL, "unknown mode bits");
     if (k.max_steps > kMaxSteps || k.max_cols > 4096 || k.pilot_probes > k.max_probes)
         return fail(c, VNE_EINVAL, "bad server limits");
@@ -635,6 +650,7 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
     sc.arena_bytes = bytes;
     sc.query_bytes = rnd((size_t)x.psi_cap * 8) + 512;
     sc.skip_blocked = env_int("VNE_SERVE_SKIP_BLOCKED", 0) != 0;
+    sc.max_group = k.max_group;
     s->core = std::make_unique<ServeCore>(sc, &s->exec);
     vne_server *raw = s.release();
     raw->worker = std::thread([raw] { raw->core->run(); });

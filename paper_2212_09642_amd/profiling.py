@@ -178,13 +178,14 @@ def cmd_serve(args):
         d = json.loads(fh.read().strip().splitlines()[-1])
     c = d["config"]
     out = ["# Serving loop: Poisson arrivals at several rates", "", "Command:", "", "```", args.cmd, "```", "",
-           "Workload `%s`: %d graphs, relative accuracy %g per query, %d queries per rate."
-           % (c["workload"], c["graphs"], c["rel_eps"], c["queries_per_rate"]), "",
+           "Workload `%s`: %d graphs, relative accuracy %g per query, %d queries per rate, group slots of "
+           "up to %d tasks." % (c["workload"], c["graphs"], c["rel_eps"], c["queries_per_rate"], c.get("max_group", 2)),
+           "",
            "| offered /s | completed /s | p50 ms | p99 ms | algorithmic GB/s | mean probes | mean steps | "
-           "sampling target met | running tasks per tick | tasks in pair slots |",
+           "sampling target met | running tasks per tick | tasks in group slots |",
            "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for r in d["rates"]:
-        pairs = "%d/%d" % (r["tasks_in_pair_slots"], r["tasks"]) if "tasks" in r else "-"
+        pairs = "%d/%d" % (r["tasks_in_group_slots"], r["tasks"]) if "tasks" in r else "-"
         out.append("| %g | %.1f | %.1f | %.1f | %.0f | %.0f | %.1f | %d/%d | %.2f | %s |" % (
             r["offered_per_s"], r["completed_per_s"], r["p50_ms"], r["p99_ms"], r["algorithmic_GBps"],
             r["mean_probes"], r["mean_steps"], r["sampling_target_met"], r["queries"], r["slot_occupancy"],

@@ -6,10 +6,13 @@
 //    is held by one running member at a time.
 //  - Each quadratic form reaches its own query's column: form c of a query
 //    is a function of (seed, c) only, so a column routed to the wrong query
-//    or the wrong place in a pair slot shows.
+//    or the wrong place in a group slot shows.
 //  - A member ends at its step cap, or (a-posteriori stopping) at the stop
 //    step its device record holds, and never steps past its cap.
 //  - First come, first served: with one slot, tasks start in ticket order.
+//  - Group slots: 16-column tasks of one graph queued together start in
+//    groups of up to max_group, the largest power of two the free mailbox
+//    entries allow.
 //  - Arena peak within the arena; everything released at the end.
 //  - Oversize queries fail with VNE_ENOMEM, a non-finite stage with
 //    VNE_ENUMERIC, a device failure ends every open query with VNE_EDEVICE.
@@ -86,6 +89,9 @@ public:
     std::mt19937 rng{3};
     int fail_tick = -1;              // tick at which the device fails (-1: never)
     int ticks = 0;
+    // while hold is set, a tick waits (and sets held): submissions then
+    // queue up behind the running tasks
+    std::atomic<bool> hold{false}, held{false};
     // checks
     std::map<uint64_t, uint64_t> live;        // arena offset -> end
     std::map<uint64_t, int> task_members;     // task offset -> members not ended
@@ -129,11 +135,16 @@ public:
         take(q.off, query_bytes);
         return VNE_OK;
     }
-    vne_status start_task(ServeTask &t, ServeQuery &q0, ServeQuery *q1) override {
-        CHECK(fq(q0)->opened, "task of a query that is not open");
-        CHECK(!t.pair() || (q1 && fq(*q1)->opened), "pair member of a query that is not open");
-        CHECK(t.pair() == (q1 != nullptr), "pair slot without its second query");
-        if (t.pair()) CHECK(q1->q.graph_id == q0.q.graph_id && t.m == 32 && t.mem[1].c_off == 16, "bad pair slot");
+    vne_status start_task(ServeTask &t, ServeQuery *const *qm) override {
+        CHECK(t.n_mem == 1 || t.n_mem == 2 || t.n_mem == 4, "group slot of %d tasks", t.n_mem);
+        for (int i = 0; i < t.n_mem; ++i) {
+            CHECK(qm[i] && fq(*qm[i])->opened, "member %d of a query that is not open", i);
+            CHECK(qm[i]->ticket == t.mem[i].ticket, "member %d's query mismatch", i);
+            if (t.group())
+                CHECK(qm[i]->q.graph_id == qm[0]->q.graph_id && t.mem[i].c_off == 16 * i && t.mem[i].m == 16 &&
+                          t.m == 16 * t.n_mem && t.m_pad == t.m && t.mt == 16,
+                      "bad group slot");
+        }
         take(t.off, t.bytes);
         task_members[t.off] = t.n_mem;
         for (int i = 0; i < t.n_mem; ++i) {
@@ -147,6 +158,10 @@ public:
     }
     vne_status tick(const std::vector<ServeTask> &active, const std::vector<ServeQuery *> &qs) override {
         if (ticks++ == fail_tick) return VNE_EDEVICE;
+        if (hold.load()) {
+            held.store(true);
+            while (hold.load()) std::this_thread::yield();
+        }
         for (size_t i = 0; i < active.size(); ++i) {
             const ServeTask &t = active[i];
             CHECK(t.j < t.k, "a slot stepped past its cap");
@@ -155,8 +170,8 @@ public:
                 const ServeMember &u = t.mem[mi];
                 // a running member's query, and none for a member that ended
                 // (its query may be gone)
-                CHECK(u.ended ? qs[2 * i + mi] == nullptr : (qs[2 * i + mi] && qs[2 * i + mi]->ticket == u.ticket),
-                      "member's query mismatch");
+                const ServeQuery *mq = qs[(size_t)kMaxMembers * i + mi];
+                CHECK(u.ended ? mq == nullptr : (mq && mq->ticket == u.ticket), "member's query mismatch");
                 if (u.ended || !u.adaptive) continue;
                 const int j = t.j + 1, s = stop_of(u.ticket, u.col0);
                 if (j >= 3 && j % 2 == 1 && j < t.k && j >= s && mailbox[u.slot].x != u.uid) mailbox[u.slot] = {u.uid, s};
@@ -244,7 +259,7 @@ struct Setup {
     std::unique_ptr<ServeCore> core;
     std::thread worker;
     std::atomic<int64_t> clock_ms{0};
-    Setup(int max_slots, uint64_t arena, int psi_cap, bool skip, int fail_tick = -1) {
+    Setup(int max_slots, uint64_t arena, int psi_cap, bool skip, int fail_tick = -1, int max_group = 2) {
         ex.arena_bytes = arena;
         ex.query_bytes = (uint64_t)psi_cap * 8 + 512;
         ex.psi_cap = psi_cap;
@@ -265,6 +280,7 @@ struct Setup {
         c.arena_bytes = arena;
         c.query_bytes = ex.query_bytes;
         c.skip_blocked = skip;
+        c.max_group = max_group;
         core.reset(new ServeCore(c, &ex, [this] { return (double)clock_ms.fetch_add(1); }));
         worker = std::thread([this] { core->run(); });
     }
@@ -336,9 +352,9 @@ static void check_result(const Want &w, const vne_query_result &r, const std::ve
 }
 
 // Several client threads submit and poll a mix of queries.
-static void mixed_clients(bool skip) {
+static void mixed_clients(bool skip, int group) {
     const int psi_cap = 512;
-    Setup s(12, 24ull << 20, psi_cap, skip);
+    Setup s(12, 24ull << 20, psi_cap, skip, -1, group);
     const int T = 4, Q = 30;
     std::vector<std::thread> clients;
     std::mutex want_mu;
@@ -402,9 +418,11 @@ static void mixed_clients(bool skip) {
     CHECK(s.ex.live.empty() && s.ex.busy_slots.empty() && s.ex.task_members.empty(), "state left behind");
     for (int v : s.ex.in_use) CHECK(v == 0, "graph still in use");
     if (!skip) CHECK(info.pair_slots > 0, "no pair slot was formed");
-    std::printf("mixed clients (skip_blocked=%d): %lld queries, %lld tasks, %lld pair slots, arena peak %llu of %llu\n",
-                (int)skip, (long long)info.queries_done, (long long)info.tasks, (long long)info.pair_slots,
-                (unsigned long long)info.arena_peak, (unsigned long long)info.arena_bytes);
+    if (group == 2) CHECK(info.group_tasks == 2 * info.pair_slots, "a group beyond two with max_group 2");
+    std::printf("mixed clients (skip_blocked=%d, groups of up to %d): %lld queries, %lld tasks, %lld pair slots, "
+                "%lld tasks in group slots, arena peak %llu of %llu\n",
+                (int)skip, group, (long long)info.queries_done, (long long)info.tasks, (long long)info.pair_slots,
+                (long long)info.group_tasks, (unsigned long long)info.arena_peak, (unsigned long long)info.arena_bytes);
 }
 
 // One slot: tasks start in ticket order, each query's tasks in column order.
@@ -436,6 +454,50 @@ static void fcfs_order() {
         for (size_t i = 1; i < kv.second.size(); ++i)
             CHECK(kv.second[i].first > kv.second[i - 1].first, "columns of a query out of order with one slot");
     std::printf("first come, first served: %zu tasks in ticket order\n", s.ex.start_order.size());
+}
+
+// Eight 16-column queries of one graph queue up while a one-column query
+// holds the worker in a tick; then they start in group slots as large as
+// max_group and the free mailbox entries allow.
+static void group_slots(int slots, int group, int64_t want_group_tasks, int64_t want_pairs) {
+    const int psi_cap = 64;
+    Setup s(slots, 32ull << 20, psi_cap, false, -1, group);
+    s.ex.hold.store(true);
+    Want blocker{};
+    blocker.graph = 0;
+    blocker.m = 1;
+    blocker.k = 24;
+    blocker.seed = 99;
+    blocker.status = VNE_OK;
+    CHECK(s.submit(blocker.graph, 0.0, blocker.m, blocker.k, blocker.seed, &blocker.ticket) == VNE_OK, "submit");
+    while (!s.ex.held.load()) std::this_thread::yield();
+    std::vector<Want> ws(8);
+    for (int i = 0; i < 8; ++i) {
+        ws[i] = Want{};
+        ws[i].graph = 1;
+        ws[i].m = 16;
+        ws[i].k = 8;
+        ws[i].seed = 1000 + i;
+        ws[i].status = VNE_OK;
+        CHECK(s.submit(ws[i].graph, 0.0, ws[i].m, ws[i].k, ws[i].seed, &ws[i].ticket) == VNE_OK, "submit");
+    }
+    s.ex.hold.store(false);
+    ws.push_back(blocker);
+    for (Want &w : ws) {
+        vne_query_result res{};
+        std::vector<double> quad(psi_cap);
+        CHECK(s.core->poll(w.ticket, -1, &res, quad.data(), psi_cap) == VNE_OK, "poll failed");
+        check_result(w, res, quad, psi_cap);
+    }
+    vne_server_info info{};
+    s.core->stats(&info);
+    s.finish();
+    CHECK(info.group_tasks == want_group_tasks && info.pair_slots == want_pairs,
+          "%d mailbox entries, groups of up to %d: %lld tasks in group slots, %lld pair slots (expected %lld, %lld)",
+          slots, group, (long long)info.group_tasks, (long long)info.pair_slots, (long long)want_group_tasks,
+          (long long)want_pairs);
+    std::printf("group slots (%d mailbox entries, up to %d): %lld tasks in group slots, %lld pair slots\n", slots,
+                group, (long long)info.group_tasks, (long long)info.pair_slots);
 }
 
 // A stage whose flags report a failure ends its query; the others complete.
@@ -517,8 +579,14 @@ static void device_failure() {
 }
 
 int main() {
-    mixed_clients(false);
-    mixed_clients(true);
+    mixed_clients(false, 2);
+    mixed_clients(true, 2);
+    mixed_clients(false, 4);
+    mixed_clients(true, 4);
+    group_slots(9, 4, 8, 0);   // two groups of four
+    group_slots(8, 4, 6, 1);   // seven free entries: four, two, one, then one
+    group_slots(9, 2, 8, 4);   // four pairs
+    group_slots(9, 1, 0, 0);   // no groups
     fcfs_order();
     numeric_stage();
     stop_in_flight();

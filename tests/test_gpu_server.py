@@ -105,24 +105,33 @@ def test_server_adaptive_same_bits_alone_and_in_a_mix(ctx, pool):
     assert alone["estimate"] == mixed["estimate"]
 
 
-def test_server_pair_slots_same_bits_as_alone(ctx, pool):
-    """16-column tasks of one graph with the same step cap share pair slots;
-    each gives the bits it gives alone, and matches the oracle."""
-    _say("case server: pair slots of 16-column tasks")
+@pytest.mark.parametrize("group", [2, 4, 1])
+def test_server_group_slots_same_bits_as_alone(ctx, pool, group):
+    """16-column tasks of one graph with the same step cap share group slots
+    of up to `group` tasks; each gives the bits it gives alone, and matches
+    the oracle."""
+    _say("case server: group slots of up to %d 16-column tasks" % group)
     gid, ref = pool[5]                       # ER n = 20000
     gid2, _ = pool[1]
     # ER (no long rows) and BA (hub rows split into segments) pairs
     work = ([(gid, 16, 30, s) for s in range(1, 7)] + [(gid, 16, 25, 7), (gid2, 16, 30, 8), (gid, 40, 30, 9)]
             + [(gid2, 16, 30, 10), (gid2, 16, 30, 11)])
-    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30, max_group=1) as srv:
         alone = [_run_one(srv, *w) for w in work]
-        assert srv.stats()["pair_slots"] == 0
-    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+        assert srv.stats()["group_tasks"] == 0
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30, max_group=group) as srv:
         ts = [srv.submit(g, m=m, k=k, seed=sd) for g, m, k, sd in work]
         mixed = [srv.poll(t, want_quad=True) for t in ts]
         info = srv.stats()
-    _say("  pair slots %d of %d tasks" % (info["pair_slots"], info["tasks"]))
-    assert info["pair_slots"] >= 3          # submissions race the worker: most pair up
+    fours = info["group_tasks"] - 2 * info["pair_slots"]
+    _say("  %d of %d tasks in group slots (%d pair slots)" % (info["group_tasks"], info["tasks"], info["pair_slots"]))
+    # submissions race the worker: most tasks join a group
+    if group == 1:
+        assert info["group_tasks"] == 0
+    elif group == 2:
+        assert info["pair_slots"] >= 3 and fours == 0
+    else:
+        assert fours >= 4
     for a, b in zip(alone, mixed):
         assert a["status"] == 0 and b["status"] == 0
         assert np.array_equal(a["quad"], b["quad"])
@@ -130,25 +139,26 @@ def test_server_pair_slots_same_bits_as_alone(ctx, pool):
     B = oracle.rademacher_block(3, ref.node_ids, np.arange(16))
     want = oracle.quadforms(ref.scipy(), B, 30, oracle.breakdown_tau(False))
     sens = _order_sensitivity(ref.scipy(), B, 30, False)
-    _assert_within(_rel(mixed[2]["quad"], want["psi"]), _bar(False, sens), "pair member vs oracle")
+    _assert_within(_rel(mixed[2]["quad"], want["psi"]), _bar(False, sens), "group member vs oracle")
 
 
-def test_server_adaptive_pairs_same_bits_as_alone(ctx, pool):
-    """rel_eps queries on one graph: their 16-column pilots share pair slots,
+@pytest.mark.parametrize("group", [2, 4])
+def test_server_adaptive_groups_same_bits_as_alone(ctx, pool, group):
+    """rel_eps queries on one graph: their 16-column pilots share group slots,
     each member stops on its own record, and every query gives the bits it
     gives alone."""
-    _say("case server: adaptive queries in pair slots")
+    _say("case server: adaptive queries in group slots of up to %d" % group)
     gid, _ = pool[5]
-    seeds = [21, 22, 23, 24, 25]
-    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+    seeds = [21, 22, 23, 24, 25, 26]
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30, max_group=1) as srv:
         alone = [srv.poll(srv.submit(gid, rel_eps=1e-3, seed=sd), want_quad=True) for sd in seeds]
-    with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30, max_group=group) as srv:
         ts = [srv.submit(gid, rel_eps=1e-3, seed=sd) for sd in seeds]
         mixed = [srv.poll(t, want_quad=True) for t in ts]
         info = srv.stats()
-    _say("  pair slots %d of %d tasks; steps %s" % (info["pair_slots"], info["tasks"],
-                                                     [r["steps"] for r in alone]))
-    assert info["pair_slots"] >= 2
+    _say("  %d of %d tasks in group slots (%d pair slots); steps %s"
+         % (info["group_tasks"], info["tasks"], info["pair_slots"], [r["steps"] for r in alone]))
+    assert info["group_tasks"] >= 4
     for a, b in zip(alone, mixed):
         assert a["status"] == 0 and b["status"] == 0
         assert a["probes"] == b["probes"]
@@ -179,7 +189,7 @@ def test_server_fp64_matches_oracle_and_mix(ctx):
                  for i in range(4)]
         ts = [srv.submit(graphs[i % 2][0], rel_eps=1e-3, seed=70 + i) for i in range(4)]
         mixed = [srv.poll(t, want_quad=True) for t in ts]
-        assert srv.stats()["pair_slots"] == 0        # pairs are FP32 only
+        assert srv.stats()["group_tasks"] == 0       # group slots are FP32 only
     for a, b in zip(alone, mixed):
         assert a["status"] == 0 and b["status"] == 0
         assert np.array_equal(a["quad"], b["quad"]) and a["estimate"] == b["estimate"]
@@ -250,6 +260,10 @@ def test_server_errors_and_busy_release(ctx, pool):
             ctx.release(gid)
         assert ei.value.status == -5
         assert srv.poll(t)["status"] == 0
+    for bad in (3, 8, -1):
+        with pytest.raises(vne.VneError) as ei:
+            vne.Server(ctx, MODE, arena_bytes=1 << 26, max_group=bad)
+        assert ei.value.status == -1
     # a graph without zero row sums cannot run desingularized
     rp = np.arange(11, dtype=np.int32)
     g2 = ctx.register(rp, np.arange(10, dtype=np.int32), np.ones(10, np.float32), 0.1)
