@@ -18,7 +18,7 @@ namespace {
     } while (0)
 
 constexpr int kPlanRounds = 4;     // probe-count plans of a rel_eps query (pilot included)
-constexpr int kPairWindow = 256;   // pending tasks searched for a partner
+constexpr int kGroupWindow = 256;  // pending tasks searched for partners
 
 double steady_ms() {
     using C = std::chrono::steady_clock;
@@ -247,7 +247,7 @@ vne_status ServeCore::admit() {
         // partner search: pending indices of the partners, in queue order
         std::vector<size_t> partners;
         if (groupable(t) && free_slots_.size() >= 2) {
-            const size_t lim = std::min(pending_.size(), head + (size_t)kPairWindow);
+            const size_t lim = std::min(pending_.size(), head + (size_t)kGroupWindow);
             for (size_t i = head + 1; i < lim && (int)partners.size() + 1 < cfg_.max_group; ++i) {
                 const ServeTask &c = pending_[i];
                 if (!groupable(c) || c.k != t.k || c.mem[0].adaptive != t.mem[0].adaptive) continue;
