@@ -362,7 +362,7 @@ def exact_entropy_dense(g):
 
 
 def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max_cols=256, zipf=0.0, pilot=0,
-                  exact_n_max=4000, max_group=0):
+                  exact_n_max=4000, max_group=0, stop="bound"):
     """Poisson streams of 1e-3 relative-accuracy queries on a pool of ER / BA
     / WS graphs (n log-uniform in [1e3, 2e6]).  Per rate: completed queries/s,
     p50/p99 latency, the fraction that meet the sampling target, and on the
@@ -387,8 +387,23 @@ def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max
           % (len(pool), min(p[1] for p in pool), max(p[1] for p in pool), len(exact), time.perf_counter() - t0),
           file=sys.stderr, flush=True)
     eps = 1e-3
+    rules = [stop] if isinstance(stop, str) else list(stop)
+    rows_by_rule = {}
+    for rule in rules:
+        rows_by_rule[rule] = serve_rates(ctx, vne, np, workloads, pool, exact, rates, queries, eps, arena_gb,
+                                         max_slots, max_cols, zipf, pilot, max_group, rule)
+    ctx.close()
+    return dict(pool=len(pool), exact_graphs=len(exact), rows=rows_by_rule[rules[0]], rows_by_rule=rows_by_rule,
+                rel_eps=eps)
+
+
+def serve_rates(ctx, vne, np, workloads, pool, exact, rates, queries, eps, arena_gb, max_slots, max_cols, zipf,
+                pilot, max_group, stop):
+    """One server on the pool with the given stopping rule: Poisson streams at
+    each rate; one result row per rate."""
     srv = vne.Server(ctx, vne.MODE_DESING, arena_bytes=int(arena_gb * (1 << 30)), max_slots=max_slots,
-                     max_cols=max_cols, max_probes=4096, pilot_probes=pilot, max_group=max_group)
+                     max_cols=max_cols, max_probes=4096, pilot_probes=pilot, max_group=max_group,
+                     stop={"bound": vne.STOP_BOUND, "estimate": vne.STOP_ESTIMATE}[stop])
     # untimed: one query per graph (device arrays of every graph, first launches)
     for gid, *_ in pool:
         srv.poll(srv.submit(gid, rel_eps=eps, seed=1))
@@ -438,18 +453,25 @@ def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max
                "queries_with_exact_entropy": len(with_exact), "within_1e-3_of_exact": within,
                "worst_rel_err_vs_exact": worst,
                "slot_occupancy": round(occ, 2), "tasks": tasks, "tasks_in_group_slots": grouped}
-        print("rate %s" % json.dumps(row), file=sys.stderr, flush=True)
+        print("rate (stop %s) %s" % (stop, json.dumps(row)), file=sys.stderr, flush=True)
         rows.append(row)
     srv.stop()
-    ctx.close()
-    return dict(pool=len(pool), exact_graphs=len(exact), rows=rows, rel_eps=eps)
+    return rows
 
 
 def serve_summary(sv, rates, queries):
-    return {"workload": "serve_pool%d_er_ba_ws_n1e3_2e6_eps1e-3_f32" % sv["pool"], "rel_eps": sv["rel_eps"],
-            "pool_graphs": sv["pool"], "pool_seed": __import__("synth").workloads.GRAPH_SEED_SERVE,
-            "arrivals": "Poisson, seed %d + rate" % __import__("synth").workloads.GRAPH_SEED_SERVE,
-            "queries_per_rate": queries, "exact_entropy_graphs": sv["exact_graphs"], "rates": sv["rows"]}
+    """The serve object of the default line: the rates under the first
+    stopping rule measured (the upper bound, eq. (4.9)), and under each other
+    rule (the eq. (4.10) estimate) on the same pool and arrivals."""
+    rules = list(sv["rows_by_rule"])
+    out = {"workload": "serve_pool%d_er_ba_ws_n1e3_2e6_eps1e-3_f32" % sv["pool"], "rel_eps": sv["rel_eps"],
+           "pool_graphs": sv["pool"], "pool_seed": __import__("synth").workloads.GRAPH_SEED_SERVE,
+           "arrivals": "Poisson, seed %d + rate" % __import__("synth").workloads.GRAPH_SEED_SERVE,
+           "queries_per_rate": queries, "exact_entropy_graphs": sv["exact_graphs"], "stop": rules[0],
+           "rates": sv["rows_by_rule"][rules[0]]}
+    for rule in rules[1:]:
+        out["stop_" + rule] = {"stop": rule, "rates": sv["rows_by_rule"][rule]}
+    return out
 
 
 def run_serve(args):
@@ -457,7 +479,7 @@ def run_serve(args):
     WS graphs (n log-uniform in [1e3, 2e6]) at several arrival rates."""
     rates = [float(r) for r in args.rates.split(",")]
     sv = measure_serve(rates, args.queries, args.pool, args.arena_gb, args.max_slots, args.max_cols, args.zipf,
-                       args.pilot, max_group=args.group)
+                       args.pilot, max_group=args.group, stop=args.stop)
     rows = sv["rows"]
     best = max(rows, key=lambda r: r["completed_per_s"])
     res = {
@@ -468,6 +490,7 @@ def run_serve(args):
         "config": {"workload": "serve_pool%d_er_ba_ws_n1e3_2e6_eps1e-3_f32" % sv["pool"], "graphs": sv["pool"],
                    "rel_eps": sv["rel_eps"], "rates": args.rates, "queries_per_rate": args.queries,
                    "zipf": args.zipf, "pilot": args.pilot or 16, "max_group": args.group or 2,
+                   "stop": args.stop,
                    "graph_seed": __import__("synth").workloads.GRAPH_SEED_SERVE},
         "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"], "rates": rows,
         "roofline": None, "cpu_baseline": None,
@@ -751,7 +774,8 @@ def main():
     ap.add_argument("--graph", default="ws", help="probing-eps workload: ws (small-world) or ring (lattice)")
     ap.add_argument("--rel-eps", type=float, default=1e-3, help="probing-eps workload: relative target")
     ap.add_argument("--stop", default="bound", choices=("bound", "estimate"),
-                    help="probing-eps workload: Krylov stopping rule (eq. (4.9) bound or eq. (4.10) estimate)")
+                    help="probing-eps and serve workloads: Krylov stopping rule, the upper bound of the "
+                         "bracket (eq. (4.9)) or its geometric mean (eq. (4.10))")
     ap.add_argument("--no-extras", action="store_true",
                     help="large workload: skip the serve and batch objects of the default line")
     ap.add_argument("--serve-rates", default="20,200",
@@ -891,7 +915,7 @@ def main():
         # 1e-3 queries (a light and a near-saturation rate) and the 512-graph
         # batch against per-graph launches
         rates = [float(r) for r in args.serve_rates.split(",")]
-        sv = measure_serve(rates, args.serve_queries)
+        sv = measure_serve(rates, args.serve_queries, stop=("bound", "estimate"))
         res["serve"] = serve_summary(sv, rates, args.serve_queries)
         res["batch"] = batch_summary(measure_batch(1, 3))
     print(json.dumps(res), flush=True)

@@ -601,6 +601,11 @@ typedef struct {
     uint32_t mode;              /* VNE_MODE_* bits of every query of the server */
     int32_t max_group;          /* largest group slot of 16-column FP32 tasks: 1 (none), 2 or 4
                                    (0: 2); other values fail with VNE_EINVAL */
+    int32_t stop;               /* check of a rel_eps query's tasks: VNE_STOP_BOUND (0) stops a
+                                   task when the upper bound of every column's bracket
+                                   (eq. (4.9)) is within tol; VNE_STOP_ESTIMATE when the
+                                   geometric mean sqrt(lo hi) of every bracket (eq. (4.10)) is
+                                   (no guarantee: Remark 4.11); other values: VNE_EINVAL */
 } vne_server_cfg;
 
 typedef struct {

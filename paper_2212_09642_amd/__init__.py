@@ -130,7 +130,8 @@ class _DistanceChoice(ctypes.Structure):
 class _ServerCfg(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("arena_bytes", ctypes.c_uint64), ("max_cols", ctypes.c_int32),
                 ("pilot_probes", ctypes.c_int32), ("max_probes", ctypes.c_int32), ("max_steps", ctypes.c_int32),
-                ("z", ctypes.c_double), ("mode", ctypes.c_uint32), ("max_group", ctypes.c_int32)]
+                ("z", ctypes.c_double), ("mode", ctypes.c_uint32), ("max_group", ctypes.c_int32),
+                ("stop", ctypes.c_int32)]
 
 
 class _Query(ctypes.Structure):
@@ -640,10 +641,11 @@ class Server:
     """Serving loop on a context (continuous batching, HBM-budget admission)."""
 
     def __init__(self, ctx, mode, arena_bytes=0, max_slots=0, max_cols=0, pilot_probes=0, max_probes=0,
-                 max_steps=0, z=0.0, max_group=0):
+                 max_steps=0, z=0.0, max_group=0, stop=0):
         self._ctx = ctx
         self._L = ctx._L
-        cfg = _ServerCfg(max_slots, arena_bytes, max_cols, pilot_probes, max_probes, max_steps, z, mode, max_group)
+        cfg = _ServerCfg(max_slots, arena_bytes, max_cols, pilot_probes, max_probes, max_steps, z, mode, max_group,
+                         stop)
         h = ctypes.c_void_p()
         ctx._chk(self._L.vne_server_start(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -223,7 +223,8 @@ struct BoundArgs {
 hipError_t launch_error_bound(const BoundArgs *args, const int2 *map, int32_t n_entries, hipStream_t s);
 
 struct StopArgs {
-    const double *hi;
+    const double *lo, *hi;
+    int32_t estimate;           // 0: every hi <= tol (eq. (4.9)); 1: every sqrt(lo hi) <= tol (eq. (4.10))
     int32_t m;
     double tol;
     int32_t step;

@@ -1896,13 +1896,17 @@ hipError_t launch_error_bound(const BoundArgs *args, const int2 *map, int32_t n_
     return hipGetLastError();
 }
 
-// One block per problem: if every column's upper bound is within tol, the
-// first such step is recorded in state = {uid, stop step} (a state left by an
-// earlier owner of the memory, with another uid, is reset first).
+// One block per problem: if every column's upper bound (or, with estimate,
+// the geometric mean of its bracket) is within tol, the first such step is
+// recorded in state = {uid, stop step} (a state left by an earlier owner of
+// the memory, with another uid, is reset first).
 __global__ void __launch_bounds__(64) k_stop_check(const StopArgs *args) {
     const StopArgs a = args[blockIdx.x];
     bool ok = true;
-    for (int c = threadIdx.x; c < a.m; c += 64) ok = ok && a.hi[c] <= a.tol;
+    for (int c = threadIdx.x; c < a.m; c += 64) {
+        const double e = a.estimate ? sqrt(a.lo[c] * a.hi[c]) : a.hi[c];
+        ok = ok && e <= a.tol;
+    }
     const bool all = __all(ok);
     if (threadIdx.x != 0) return;
     int2 st = *a.state;

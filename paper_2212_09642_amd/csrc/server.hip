@@ -135,6 +135,7 @@ public:
     vne_ctx *ctx = nullptr;
     bool fp64 = false, desing = false;
     int psi_cap = 0;
+    int stop_rule = VNE_STOP_BOUND;  // what a task's check compares with its tolerance
     hipStream_t stream = nullptr;
     DevBuf arena_mem;
     std::vector<double *> pinned_pool;
@@ -405,7 +406,9 @@ public:
                 for (int grp = 0; grp < (u.m + 3) / 4; ++grp) bmap.push_back(make_int2((int)ba.size(), grp));
                 ba.push_back(b);
                 StopArgs sc{};
+                sc.lo = d.b_lo + co;
                 sc.hi = d.b_hi + co;
+                sc.estimate = stop_rule == VNE_STOP_ESTIMATE ? 1 : 0;
                 sc.m = u.m;
                 sc.tol = u.tol;
                 sc.step = j;
@@ -598,6 +601,8 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
     if (k.max_steps <= 0) k.max_steps = 100;
     if (!(k.z > 0.0)) k.z = 2.576;
     if (k.max_group == 0) k.max_group = 2;
+    if (k.stop != VNE_STOP_BOUND && k.stop != VNE_STOP_ESTIMATE)
+        return fail(c, VNE_EINVAL, "stop must be VNE_STOP_BOUND or VNE_STOP_ESTIMATE");
     if (k.max_group != 1 && k.max_group != 2 && k.max_group != 4)
         return fail(c, VNE_EINVAL, "max_group must be 0, 1, 2 or 4");
     if (k.mode & ~(uint32_t)(VNE_MODE_F64 | VNE_MODE_DESING)) return fail(c, VNE_EINVAL, "unknown mode bits");
@@ -610,6 +615,7 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
     x.fp64 = (k.mode & VNE_MODE_F64) != 0;
     x.desing = (k.mode & VNE_MODE_DESING) != 0;
     x.psi_cap = k.max_probes;
+    x.stop_rule = k.stop;
     uint64_t bytes = k.arena_bytes;
     if (bytes == 0) {
         size_t fr = 0, tot = 0;

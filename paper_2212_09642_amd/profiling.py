@@ -179,16 +179,21 @@ def cmd_serve(args):
     c = d["config"]
     out = ["# Serving loop: Poisson arrivals at several rates", "", "Command:", "", "```", args.cmd, "```", "",
            "Workload `%s`: %d graphs, relative accuracy %g per query, %d queries per rate, group slots of "
-           "up to %d tasks." % (c["workload"], c["graphs"], c["rel_eps"], c["queries_per_rate"], c.get("max_group", 2)),
+           "up to %d tasks, tasks stopped on the %s." % (
+               c["workload"], c["graphs"], c["rel_eps"], c["queries_per_rate"], c.get("max_group", 2),
+               {"bound": "upper bound of each bracket (eq. (4.9))",
+                "estimate": "geometric mean of each bracket (eq. (4.10))"}[c.get("stop", "bound")]),
            "",
            "| offered /s | completed /s | p50 ms | p99 ms | algorithmic GB/s | mean probes | mean steps | "
-           "sampling target met | running tasks per tick | tasks in group slots |",
-           "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+           "sampling target met | within 1e-3 of the exact entropy | running tasks per tick | tasks in group slots |",
+           "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for r in d["rates"]:
         pairs = "%d/%d" % (r["tasks_in_group_slots"], r["tasks"]) if "tasks" in r else "-"
-        out.append("| %g | %.1f | %.1f | %.1f | %.0f | %.0f | %.1f | %d/%d | %.2f | %s |" % (
+        exact = ("%d/%d" % (r["within_1e-3_of_exact"], r["queries_with_exact_entropy"])
+                 if "queries_with_exact_entropy" in r else "-")
+        out.append("| %g | %.1f | %.1f | %.1f | %.0f | %.0f | %.1f | %d/%d | %s | %.2f | %s |" % (
             r["offered_per_s"], r["completed_per_s"], r["p50_ms"], r["p99_ms"], r["algorithmic_GBps"],
-            r["mean_probes"], r["mean_steps"], r["sampling_target_met"], r["queries"], r["slot_occupancy"],
+            r["mean_probes"], r["mean_steps"], r["sampling_target_met"], r["queries"], exact, r["slot_occupancy"],
             pairs))
     out += ["", "Saturated throughput: %.1f queries/s." % d["value"]]
     with open(args.out, "w") as fh:

@@ -46,3 +46,16 @@ def test_traffic_is_dropped_for_other_sources(tmp_path, monkeypatch):
         {"hbm_bytes_per_launch": 123.0, "kernel_source_hash": "this-source"}))
     assert bench.load_traffic("w") == 123.0
     assert bench.load_traffic("missing") is None
+
+
+def test_serve_summary_keeps_each_stopping_rule_apart():
+    # the first rule's rates are the object's own; each other rule sits in a
+    # sub-object of its own, with the same pool and arrivals
+    rows_b, rows_e = [{"offered_per_s": 20.0, "completed_per_s": 19.0}], [{"offered_per_s": 20.0,
+                                                                           "completed_per_s": 20.0}]
+    sv = dict(pool=24, exact_graphs=2, rel_eps=1e-3, rows=rows_b, rows_by_rule={"bound": rows_b, "estimate": rows_e})
+    out = bench.serve_summary(sv, [20.0], 200)
+    assert out["stop"] == "bound" and out["rates"] is rows_b
+    assert out["stop_estimate"] == {"stop": "estimate", "rates": rows_e}
+    one = bench.serve_summary(dict(sv, rows_by_rule={"bound": rows_b}), [20.0], 200)
+    assert "stop_estimate" not in one and one["rates"] is rows_b

@@ -242,6 +242,40 @@ def test_server_error_rule_accuracy(ctx):
     assert sum(e <= 1e-3 for e in errs) >= 3 and max(errs) <= 2e-3
 
 
+def test_server_estimate_stop_rule(ctx, pool):
+    """A server whose tasks stop on the eq. (4.10) estimate (the geometric
+    mean of each bracket) instead of its upper bound: no more steps than the
+    bound rule, estimates on graphs with exact entropy still within the
+    target, and a query gives the same bits alone and among others."""
+    _say("case server: stop on the eq. (4.10) estimate")
+    cases = [synth.erdos_renyi(1500, 8.0, 51), synth.barabasi_albert(1200, 3, 52),
+             synth.watts_strogatz(2000, 8, 0.1, 53), synth.grid2d_graph(30, 40)]
+    regs = [_reg(ctx, *c) for c in cases]
+    got = {}
+    for rule in (vne.STOP_BOUND, vne.STOP_ESTIMATE):
+        with vne.Server(ctx, MODE, arena_bytes=1 << 30, stop=rule) as srv:
+            got[rule] = [srv.poll(srv.submit(gid, rel_eps=1e-3, seed=900 + i), want_quad=True)
+                         for i, (gid, _) in enumerate(regs)]
+    errs = []
+    for (gid, ref), rb, re_ in zip(regs, got[vne.STOP_BOUND], got[vne.STOP_ESTIMATE]):
+        S = oracle.exact_entropy(oracle.dense_matrix(ref))
+        err = abs(re_["estimate"] - S) / S
+        _say("  n=%d steps %d (bound rule %d), probes %d (%d), rel err %.2e (bound rule %.2e)"
+             % (ref.n, re_["steps"], rb["steps"], re_["probes"], rb["probes"], err, abs(rb["estimate"] - S) / S))
+        assert re_["status"] == 0 and 3 <= re_["steps"] <= rb["steps"]
+        errs.append(err)
+    assert sum(e <= 1e-3 for e in errs) >= 3 and max(errs) <= 2e-3
+    # same bits alone and in a mix under the estimate rule
+    gid, _ = pool[1]
+    with vne.Server(ctx, MODE, arena_bytes=1 << 30, stop=vne.STOP_ESTIMATE) as srv:
+        alone = srv.poll(srv.submit(gid, rel_eps=1e-3, seed=5), want_quad=True)
+        ts = [srv.submit(pool[i % len(pool)][0], rel_eps=1e-3, seed=100 + i) for i in range(6)]
+        mine = srv.submit(gid, rel_eps=1e-3, seed=5)
+        mixed = srv.poll(mine, want_quad=True)
+        assert all(srv.poll(t)["status"] == 0 for t in ts)
+    assert np.array_equal(alone["quad"], mixed["quad"]) and alone["estimate"] == mixed["estimate"]
+
+
 def test_server_errors_and_busy_release(ctx, pool):
     _say("case server: error paths")
     gid, ref = pool[5]
@@ -263,6 +297,10 @@ def test_server_errors_and_busy_release(ctx, pool):
     for bad in (3, 8, -1):
         with pytest.raises(vne.VneError) as ei:
             vne.Server(ctx, MODE, arena_bytes=1 << 26, max_group=bad)
+        assert ei.value.status == -1
+    for bad in (2, -1):
+        with pytest.raises(vne.VneError) as ei:
+            vne.Server(ctx, MODE, arena_bytes=1 << 26, stop=bad)
         assert ei.value.status == -1
     # a graph without zero row sums cannot run desingularized
     rp = np.arange(11, dtype=np.int32)
