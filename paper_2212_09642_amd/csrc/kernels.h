@@ -194,7 +194,7 @@ hipError_t launch_rademacher_fill(void *out, bool fp64, int32_t n, int32_t m, in
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
                              const double *norm2, int32_t k, int32_t steps, int32_t m, double *psi,
                              int32_t *flags, hipStream_t s, bool fp64, const int2 *stop = nullptr,
-                             int32_t uid = 0, const int32_t *col_stop = nullptr);
+                             int32_t uid = 0, const int32_t *col_stop = nullptr, int32_t *steps_out = nullptr);
 // f(T) e1 for every column (rows >= k_eff are 0), step-major: S[r*m + c]; rot_scratch
 // holds rot_capacity(k) recorded rotations (24 bytes each) per column
 __host__ __device__ int64_t rot_capacity(int32_t k);

@@ -1635,7 +1635,7 @@ __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const d
                                                     const int32_t *k_eff, const double *norm2, int32_t k,
                                                     int32_t steps, int32_t m, double *psi, int32_t *flags,
                                                     const int2 *stop, int32_t uid, const int32_t *col_stop,
-                                                    int32_t shift_max) {
+                                                    int32_t shift_max, int32_t *steps_out) {
     const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (c >= m) return;
@@ -1643,6 +1643,10 @@ __global__ void __launch_bounds__(256) k_quadrature(const double *alpha, const d
         const int2 st = *stop;
         if (st.x == uid && st.y > 0) steps = min(steps, st.y);
     }
+    // the steps the problem's quadrature takes (the same for every column
+    // before per-column stops), kept as the largest over the problems that
+    // share the word
+    if (steps_out && c == 0 && lane == 0) atomicMax(steps_out, steps);
     if (col_stop) {
         const int cs = __builtin_amdgcn_readfirstlane(col_stop[c]);
         if (cs > 0) steps = min(steps, cs);
@@ -1966,12 +1970,12 @@ hipError_t launch_column_stop(const ColStopArgs *args, hipStream_t s) {
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int32_t *k_eff,
                              const double *norm2, int32_t k, int32_t steps, int32_t m, double *psi,
                              int32_t *flags, hipStream_t s, bool fp64, const int2 *stop, int32_t uid,
-                             const int32_t *col_stop) {
+                             const int32_t *col_stop, int32_t *steps_out) {
     if (k > kMaxSteps || steps < 1 || steps > k) return hipErrorInvalidValue;
     // FP64 vectors: shifts up to 5e-14 (below 1e-13 relative); FP32: up to 5e-8
     const int32_t shift_max = fp64 ? 1 : 4;
     hipLaunchKernelGGL(k_quadrature, dim3((m + 3) / 4), dim3(256), 0, s, alpha, beta, k_eff, norm2, k, steps, m,
-                       psi, flags, stop, uid, col_stop, shift_max);
+                       psi, flags, stop, uid, col_stop, shift_max, steps_out);
     return hipGetLastError();
 }
 

@@ -116,7 +116,11 @@ void ServeCore::finish_query(ServeQuery &q, vne_status st, const std::string &ms
     q.res.status = st;
     std::snprintf(q.res.message, sizeof(q.res.message), "%s", msg.c_str());
     q.res.probes = q.N;
-    q.res.steps = q.steps_used > 0 ? q.steps_used : q.k;
+    // the device's count when the final copy came back (a stop recorded on
+    // the device can reach the host only after the task's cap), else the
+    // host's
+    const int32_t dev_steps = f && st == VNE_OK ? exec_->steps_taken(q) : 0;
+    q.res.steps = dev_steps > 0 ? dev_steps : (q.steps_used > 0 ? q.steps_used : q.k);
     q.res.quad_bound = q.bound;
     q.res.queue_ms = q.started ? q.t_admit - q.t_submit : 0.0;
     q.res.latency_ms = q.t_done - q.t_submit;

@@ -111,6 +111,9 @@ public:
     virtual const double *forms(ServeQuery &q) = 0;
     virtual double estimate(ServeQuery &q) = 0;
     virtual int32_t flags(ServeQuery &q, bool final) = 0;
+    // after the final copy: the most steps a quadrature of the query took on
+    // the device (0: not known)
+    virtual int32_t steps_taken(ServeQuery &q) = 0;
     // the query ended: its executor state back
     virtual void close_query(ServeQuery &q) = 0;
     // the query no longer uses its graph

@@ -168,6 +168,8 @@ public:
     int32_t *d_flags(const ServeQuery &q) const {
         return (int32_t *)(arena_base() + q.off + rnd((size_t)psi_cap * 8) + 256);
     }
+    // the most steps a quadrature of the query took (the word after the flags)
+    int32_t *d_steps(const ServeQuery &q) const { return d_flags(q) + 1; }
     DevTask dev(const ServeTask &t, const ServeQuery &q) const {
         return carve(t, arena_base() + t.off, gq(q)->set, fp64);
     }
@@ -210,7 +212,7 @@ public:
         x->h_buf = get_pinned();
         x->ev = get_event();
         if (!x->h_buf || !x->ev) return hip_err(hipErrorOutOfMemory, "pinned buffer or event");
-        return hip_err(hipMemsetAsync(d_flags(q), 0, 4, stream), "hipMemsetAsync");
+        return hip_err(hipMemsetAsync(d_flags(q), 0, 8, stream), "hipMemsetAsync");   // flags and steps
     }
 
     // Probe block of member i (the query's hash columns col0.., eq. (3.8))
@@ -507,11 +509,13 @@ public:
         const ServeMember &u = t.mem[i];
         const DevTask d = dev(t, q);
         // an adaptive task's own stop record (if the device made one) decides
-        // the step count, whenever the host noticed it
+        // the step count, whenever the host noticed it (a task can reach its
+        // cap before the record reaches the host: the device's count of the
+        // steps taken is the one reported)
         const int64_t co = u.c_off;
         return hip_err(launch_quadrature(d.alpha + co * t.k, d.beta + co * t.k, d.k_eff + co, d.norm2 + co, t.k,
                                          steps, u.m, d_psi(q) + u.col0, d_flags(q), stream, fp64,
-                                         u.adaptive ? d.d_state + i : nullptr, u.uid),
+                                         u.adaptive ? d.d_state + i : nullptr, u.uid, nullptr, d_steps(q)),
                        "launch_quadrature");
     }
 
@@ -532,7 +536,8 @@ public:
         VNE_TRY(hip_err(hipMemcpyAsync(x->h_buf, d_psi(q), (size_t)q.N * 8, hipMemcpyDeviceToHost, stream),
                         "hipMemcpyAsync"));
         VNE_TRY(hip_err(hipMemcpyAsync(x->h_buf + q.N, d_est(q), 8, hipMemcpyDeviceToHost, stream), "hipMemcpyAsync"));
-        VNE_TRY(hip_err(hipMemcpyAsync(x->h_buf + q.N + 1, d_flags(q), 4, hipMemcpyDeviceToHost, stream),
+        // flags and the step count, adjacent words
+        VNE_TRY(hip_err(hipMemcpyAsync(x->h_buf + q.N + 1, d_flags(q), 8, hipMemcpyDeviceToHost, stream),
                         "hipMemcpyAsync"));
         return hip_err(hipEventRecord(x->ev, stream), "hipEventRecord");
     }
@@ -550,6 +555,11 @@ public:
         int32_t fl = 0;
         std::memcpy(&fl, gq(q)->h_buf + (final ? q.N + 1 : psi_cap + 1), 4);
         return fl;
+    }
+    int32_t steps_taken(ServeQuery &q) override {
+        int32_t st = 0;
+        std::memcpy(&st, reinterpret_cast<const char *>(gq(q)->h_buf + q.N + 1) + 4, 4);
+        return st;
     }
 
     void close_query(ServeQuery &q) override {

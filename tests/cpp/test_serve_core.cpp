@@ -8,7 +8,10 @@
 //    is a function of (seed, c) only, so a column routed to the wrong query
 //    or the wrong place in a group slot shows.
 //  - A member ends at its step cap, or (a-posteriori stopping) at the stop
-//    step its device record holds, and never steps past its cap.
+//    step its device record holds, and never steps past its cap; the
+//    records reach the host 0 to 3 ticks late, so a member can reach its cap
+//    first, and the device's own record still decides its steps and the
+//    query's reported step count.
 //  - First come, first served: with one slot, tasks start in ticket order.
 //  - Group slots: 16-column tasks of one graph queued together start in
 //    groups of up to max_group, the largest power of two the free mailbox
@@ -77,6 +80,7 @@ struct FakeQ {
     int countdown = -1;              // polls until the copy lands (-1: none)
     bool opened = false;
     bool numeric = false;            // the stage's flags report a failure
+    int dev_steps = 0;               // the most steps a quadrature took (device side)
 };
 
 class FakeExec : public ServeExec {
@@ -96,7 +100,16 @@ public:
     std::map<uint64_t, uint64_t> live;        // arena offset -> end
     std::map<uint64_t, int> task_members;     // task offset -> members not ended
     std::set<int> busy_slots;
-    std::vector<I2> mailbox;                // {uid, step}
+    std::vector<I2> mailbox;                // {uid, step} as the host sees it
+    // stop records: on the device at once (by uid), in the host's mailbox
+    // 0 to 3 ticks later, as over the real copy path
+    std::map<int32_t, int> dev_stop;
+    struct Post {
+        int visible_at, slot;
+        I2 rec;
+    };
+    std::vector<Post> posts;
+    int cap_first = 0;                        // members that reached the cap before their record
     std::vector<uint64_t> start_order;        // ticket of each started task
     std::map<uint64_t, std::vector<std::pair<int, int>>> ended;   // ticket -> (col0, steps)
     std::mutex log_mu;                        // start_order / ended are read by the main thread at the end
@@ -174,26 +187,46 @@ public:
                 CHECK(u.ended ? mq == nullptr : (mq && mq->ticket == u.ticket), "member's query mismatch");
                 if (u.ended || !u.adaptive) continue;
                 const int j = t.j + 1, s = stop_of(u.ticket, u.col0);
-                if (j >= 3 && j % 2 == 1 && j < t.k && j >= s && mailbox[u.slot].x != u.uid) mailbox[u.slot] = {u.uid, s};
+                if (j >= 3 && j % 2 == 1 && j < t.k && j >= s && dev_stop.count(u.uid) == 0) {
+                    dev_stop[u.uid] = s;
+                    posts.push_back({ticks + (int)(rng() % 4), u.slot, {u.uid, s}});
+                }
             }
         }
         return VNE_OK;
     }
     void stop_record(int slot, int32_t *uid, int32_t *step) override {
+        for (size_t i = 0; i < posts.size();) {
+            if (posts[i].visible_at <= ticks) {
+                mailbox[posts[i].slot] = posts[i].rec;
+                posts[i] = posts.back();
+                posts.pop_back();
+            } else {
+                ++i;
+            }
+        }
         *uid = mailbox[slot].x;
         *step = mailbox[slot].y;
     }
     vne_status quadrature(const ServeTask &t, int i, ServeQuery &q, int steps) override {
         const ServeMember &u = t.mem[i];
         const int want = u.adaptive ? std::min(stop_of(u.ticket, u.col0), t.k) : t.k;
-        CHECK(steps == want, "member of ticket %llu ended at %d steps, expected %d", (unsigned long long)u.ticket,
-              steps, want);
+        // the host passes its step count (the cap when the record had not
+        // reached it yet); the device takes its own record first
+        int used = steps;
+        if (u.adaptive && dev_stop.count(u.uid)) used = std::min(used, dev_stop[u.uid]);
+        CHECK(used == want, "member of ticket %llu ended at %d steps (host %d), expected %d",
+              (unsigned long long)u.ticket, used, steps, want);
+        CHECK(steps == want || (steps == t.k && u.adaptive), "host ended member of ticket %llu at %d, not %d or the cap",
+              (unsigned long long)u.ticket, steps, want);
+        fq(q)->dev_steps = std::max(fq(q)->dev_steps, used);
+        if (steps == t.k && used < t.k) cap_first++;
         CHECK(u.col0 + u.m <= psi_cap, "columns beyond the query's forms");
         for (int c = 0; c < u.m; ++c) fq(q)->dev[u.col0 + c] = form_of(q.q.seed, u.col0 + c);
         CHECK(busy_slots.erase(u.slot) == 1, "mailbox entry freed twice");
         {
             std::lock_guard<std::mutex> lk(log_mu);
-            ended[q.ticket].push_back({u.col0, steps});
+            ended[q.ticket].push_back({u.col0, used});
         }
         if (--task_members[t.off] == 0) {
             task_members.erase(t.off);
@@ -216,6 +249,7 @@ public:
         x->staged.assign(x->dev.begin(), x->dev.begin() + q.N);
         x->staged.push_back(mean / q.N);
         x->staged.push_back(0.0);
+        x->staged.push_back((double)x->dev_steps);
         x->countdown = (int)(rng() % 3);
         return VNE_OK;
     }
@@ -234,6 +268,14 @@ public:
     }
     const double *forms(ServeQuery &q) override { return q.x && fq(q)->opened ? fq(q)->host.data() : nullptr; }
     double estimate(ServeQuery &q) override { return fq(q)->host[q.N]; }
+    int32_t steps_taken(ServeQuery &q) override { return (int32_t)fq(q)->host[q.N + 2]; }
+    // the most steps a member of the query ended at (device side), once done
+    int max_steps_of(uint64_t ticket) {
+        std::lock_guard<std::mutex> lk(log_mu);
+        int m = 0;
+        for (const auto &e : ended[ticket]) m = std::max(m, e.second);
+        return m;
+    }
     int32_t flags(ServeQuery &q, bool final) override {
         return fq(q)->host[final ? q.N + 1 : psi_cap + 1] != 0.0 ? 1 : 0;
     }
@@ -330,10 +372,16 @@ struct Want {
     vne_status status;
 };
 
-static void check_result(const Want &w, const vne_query_result &r, const std::vector<double> &quad, int psi_cap) {
+static void check_result(const Want &w, const vne_query_result &r, const std::vector<double> &quad, int psi_cap,
+                         FakeExec *ex = nullptr) {
     CHECK(r.status == w.status, "ticket %llu: status %d, expected %d (%s)", (unsigned long long)w.ticket, r.status,
           w.status, r.message);
     if (r.status != VNE_OK) return;
+    // the reported steps are the device's: a task that reached its cap
+    // before its stop record reached the host still reports its stop
+    if (ex)
+        CHECK(r.steps == ex->max_steps_of(w.ticket), "ticket %llu: %d steps reported, the tasks took %d",
+              (unsigned long long)w.ticket, r.steps, ex->max_steps_of(w.ticket));
     if (w.rel_eps == 0.0) {
         CHECK(r.probes == w.m, "ticket %llu: %d probes, expected %d", (unsigned long long)w.ticket, r.probes, w.m);
         CHECK(r.steps == w.k, "ticket %llu: %d steps, expected %d", (unsigned long long)w.ticket, r.steps, w.k);
@@ -401,7 +449,7 @@ static void mixed_clients(bool skip, int group) {
                         std::this_thread::yield();
                 }
                 CHECK(st == VNE_OK, "poll failed");
-                check_result(mine[i], res, quad, psi_cap);
+                check_result(mine[i], res, quad, psi_cap, &s.ex);
                 vne_query_result again{};
                 CHECK(s.core->poll(mine[i].ticket, 0, &again, nullptr, 0) == VNE_EINVAL, "ticket kept after poll");
             }
@@ -409,9 +457,11 @@ static void mixed_clients(bool skip, int group) {
             all.insert(all.end(), mine.begin(), mine.end());
         });
     for (auto &c : clients) c.join();
+    // after the worker has stopped: its last snapshot (a client's poll can
+    // return before the worker publishes the iteration that completed it)
+    s.finish();
     vne_server_info info{};
     s.core->stats(&info);
-    s.finish();
     CHECK(info.queries_done == T * Q, "queries done %lld", (long long)info.queries_done);
     CHECK(info.arena_peak <= info.arena_bytes, "arena peak beyond the arena");
     CHECK(info.arena_in_use == 0 && info.active == 0 && info.pending == 0, "server not empty at the end");
@@ -420,9 +470,10 @@ static void mixed_clients(bool skip, int group) {
     if (!skip) CHECK(info.pair_slots > 0, "no pair slot was formed");
     if (group == 2) CHECK(info.group_tasks == 2 * info.pair_slots, "a group beyond two with max_group 2");
     std::printf("mixed clients (skip_blocked=%d, groups of up to %d): %lld queries, %lld tasks, %lld pair slots, "
-                "%lld tasks in group slots, arena peak %llu of %llu\n",
+                "%lld tasks in group slots, %d reached the cap before their stop record, arena peak %llu of %llu\n",
                 (int)skip, group, (long long)info.queries_done, (long long)info.tasks, (long long)info.pair_slots,
-                (long long)info.group_tasks, (unsigned long long)info.arena_peak, (unsigned long long)info.arena_bytes);
+                (long long)info.group_tasks, s.ex.cap_first, (unsigned long long)info.arena_peak,
+                (unsigned long long)info.arena_bytes);
 }
 
 // One slot: tasks start in ticket order, each query's tasks in column order.
@@ -487,11 +538,11 @@ static void group_slots(int slots, int group, int64_t want_group_tasks, int64_t 
         vne_query_result res{};
         std::vector<double> quad(psi_cap);
         CHECK(s.core->poll(w.ticket, -1, &res, quad.data(), psi_cap) == VNE_OK, "poll failed");
-        check_result(w, res, quad, psi_cap);
+        check_result(w, res, quad, psi_cap, &s.ex);
     }
+    s.finish();
     vne_server_info info{};
     s.core->stats(&info);
-    s.finish();
     CHECK(info.group_tasks == want_group_tasks && info.pair_slots == want_pairs,
           "%d mailbox entries, groups of up to %d: %lld tasks in group slots, %lld pair slots (expected %lld, %lld)",
           slots, group, (long long)info.group_tasks, (long long)info.pair_slots, (long long)want_group_tasks,
