@@ -48,7 +48,7 @@ typedef enum {
     VNE_EINVAL = -1,    /* malformed argument or matrix                        */
     VNE_ENOMEM = -2,    /* device allocation failed or the HBM budget is spent */
     VNE_EDEVICE = -3,   /* a HIP runtime call failed                           */
-    VNE_ENOTSUP = -4,   /* valid request outside what this build supports      */
+    VNE_ENOTSUP = -4,   /* valid request outside what the library supports     */
     VNE_EBUSY = -5,     /* resource in use (e.g. releasing a graph in a plan)  */
     VNE_ENUMERIC = -6   /* NaN or Inf in a start vector or the coefficients,
                            or a failed factorisation of the Hutch++ sketch  */
