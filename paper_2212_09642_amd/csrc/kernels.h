@@ -230,6 +230,7 @@ struct StopArgs {
     int32_t step;
     int32_t uid;
     int2 *state;                // {uid, first step with every hi <= tol, or 0}
+    int2 *mail;                 // a copy of *state in an array copied to the host at once (or NULL)
 };
 hipError_t launch_stop_check(const StopArgs *args, int32_t n, hipStream_t s);
 // the bracket for the m columns of one problem (args in device memory)

@@ -1917,6 +1917,7 @@ __global__ void __launch_bounds__(64) k_stop_check(const StopArgs *args) {
     if (st.x != a.uid) st = make_int2(a.uid, 0);
     if (all && st.y == 0) st.y = a.step;
     *a.state = st;
+    if (a.mail) *a.mail = st;
 }
 
 hipError_t launch_stop_check(const StopArgs *args, int32_t n, hipStream_t s) {

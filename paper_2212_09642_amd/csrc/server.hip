@@ -149,6 +149,10 @@ public:
     char *d_desc = nullptr;
     size_t d_desc_cap = 0;
     int2 *mailbox = nullptr;         // pinned [max_slots]: stop records
+    // [max_slots] on the device: each check's record at its mailbox entry,
+    // the whole array copied to the pinned mailbox once per checking tick
+    DevBuf mail;
+    int max_slots = 0;
     // flags word of the columns of a group slot's member that has ended (its
     // query's block may belong to another query by now)
     DevBuf sink;
@@ -376,7 +380,6 @@ public:
         std::vector<BoundArgs> ba;
         std::vector<StopArgs> sta;
         std::vector<int2> bmap;
-        std::vector<int2> checked;       // {slot, member}
         for (int i = 0; i < A; ++i) {
             const ServeTask &t = active[i];
             const DevTask &d = dt[i];
@@ -416,8 +419,8 @@ public:
                 sc.step = j;
                 sc.uid = u.uid;
                 sc.state = d.d_state + mi;
+                sc.mail = (int2 *)mail.p + u.slot;
                 sta.push_back(sc);
-                checked.push_back(make_int2(i, mi));
             }
         }
         size_t bytes = rnd(sizeof(StepArgs) * A) + rnd(sizeof(FinalizeArgs) * A) + rnd(sizeof(int2) * fmap.size());
@@ -489,12 +492,10 @@ public:
         if (!sta.empty()) {
             VNE_TRY(hip_err(launch_error_bound(d_ba, d_bm, (int32_t)bmap.size(), stream), "launch_error_bound"));
             VNE_TRY(hip_err(launch_stop_check(d_st, (int32_t)sta.size(), stream), "launch_stop_check"));
-            for (const int2 &c : checked) {
-                const ServeTask &t = active[c.x];
-                VNE_TRY(hip_err(hipMemcpyAsync(mailbox + t.mem[c.y].slot, dt[c.x].d_state + c.y, sizeof(int2),
-                                               hipMemcpyDeviceToHost, stream),
-                                "hipMemcpyAsync"));
-            }
+            // an entry of a slot's earlier owner carries another uid: the
+            // host passes over it
+            VNE_TRY(hip_err(hipMemcpyAsync(mailbox, mail.p, sizeof(int2) * max_slots, hipMemcpyDeviceToHost, stream),
+                            "hipMemcpyAsync"));
         }
         return VNE_OK;
     }
@@ -642,6 +643,7 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
             if (x.ring_ev[r]) (void)hipEventDestroy(x.ring_ev[r]);
         if (x.mailbox) (void)hipHostFree(x.mailbox);
         if (x.stream) (void)hipStreamDestroy(x.stream);
+        dev_free(c, &x.mail);
         dev_free(c, &x.sink);
         dev_free(c, &x.arena_mem);
         return st;
@@ -655,6 +657,10 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
     e = hipHostMalloc((void **)&x.mailbox, sizeof(int2) * k.max_slots, hipHostMallocDefault);
     if (e != hipSuccess) return undo(hip_fail(c, e, "hipHostMalloc"));
     std::memset(x.mailbox, 0, sizeof(int2) * k.max_slots);
+    x.max_slots = k.max_slots;
+    if (vne_status st1 = dev_alloc(c, &x.mail, sizeof(int2) * k.max_slots); st1 != VNE_OK) return undo(st1);
+    e = hipMemsetAsync(x.mail.p, 0, sizeof(int2) * k.max_slots, x.stream);
+    if (e != hipSuccess) return undo(hip_fail(c, e, "hipMemsetAsync"));
     ServeConfig sc;
     sc.max_slots = k.max_slots;
     sc.max_cols = k.max_cols;
@@ -746,6 +752,7 @@ extern "C" vne_status vne_server_stop(vne_server *s) {
     }
     if (x.d_desc) (void)hipFree(x.d_desc);
     if (x.mailbox) (void)hipHostFree(x.mailbox);
+    dev_free(c, &x.mail);
     dev_free(c, &x.sink);
     dev_free(c, &x.arena_mem);
     (void)hipStreamDestroy(x.stream);
