@@ -276,8 +276,9 @@ def test_server_estimate_stop_rule(ctx, pool):
     assert np.array_equal(alone["quad"], mixed["quad"]) and alone["estimate"] == mixed["estimate"]
 
 
+@pytest.mark.parametrize("fp64", [False, True])
 @pytest.mark.parametrize("rule", ["bound", "estimate"])
-def test_server_stop_step_matches_oracle(ctx, rule):
+def test_server_stop_step_matches_oracle(ctx, rule, fp64):
     """The a-posteriori check of a served task against the oracle: with
     max_probes = pilot_probes = 16 a rel_eps query is its 16-column pilot
     alone, so its step count is the task's stop step.  The oracle runs
@@ -286,14 +287,15 @@ def test_server_stop_step_matches_oracle(ctx, rule):
     [1e-12 lambda_ub, lambda_ub] (256 points; Theorem 4.8) has its upper
     bound, or its eq. (4.10) estimate, within tol = (rel_eps / 2) S_lower;
     the steps must be equal and the 16 forms must match the oracle's at that
-    step (Remarks 5.1, 5.2; Theorem 4.8)."""
+    step, at the bar of the server's mode (Remarks 5.1, 5.2; Theorem 4.8)."""
     from oracle import probing as oprobing
-    _say("case server: stop step of the %s rule against the oracle" % rule)
+    _say("case server: stop step of the %s rule against the oracle (%s)" % (rule, "FP64" if fp64 else "FP32"))
     eps = 1e-3
     cases = [synth.erdos_renyi(1500, 8.0, 51), synth.grid2d_graph(30, 40), synth.barabasi_albert(1200, 3, 52)]
-    regs = [_reg(ctx, *c) for c in cases]
+    regs = [_reg(ctx, *c, fp64=fp64) for c in cases]
     stop = {"bound": vne.STOP_BOUND, "estimate": vne.STOP_ESTIMATE}[rule]
-    with vne.Server(ctx, MODE, arena_bytes=1 << 30, max_probes=16, pilot_probes=16, stop=stop) as srv:
+    mode = MODE | (vne.MODE_F64 if fp64 else 0)
+    with vne.Server(ctx, mode, arena_bytes=1 << 30, max_probes=16, pilot_probes=16, stop=stop) as srv:
         res = [srv.poll(srv.submit(gid, rel_eps=eps, seed=700 + i), want_quad=True) for i, (gid, _) in enumerate(regs)]
     for i, ((gid, ref), r) in enumerate(zip(regs, res)):
         assert r["status"] == 0 and r["probes"] == 16, r["message"]
@@ -304,7 +306,7 @@ def test_server_stop_step_matches_oracle(ctx, rule):
         K = vne.plan_steps(float(ref.n), lam_ub, s_lower, eps, 0.5, 100)
         tol = 0.5 * eps * s_lower
         B = oracle.rademacher_block(700 + i, ref.node_ids, np.arange(16))
-        _, _, _, lz = oprobing.adaptive_quadforms(A, B, K, oracle.breakdown_tau(False), np.full(16, tol),
+        _, _, _, lz = oprobing.adaptive_quadforms(A, B, K, oracle.breakdown_tau(fp64), np.full(16, tol),
                                                   1e-12 * lam_ub, lam_ub, grid=256, desing=True, rule=rule)
         want_step, margin = K, None
         for j in range(3, K, 2):
@@ -323,8 +325,8 @@ def test_server_stop_step_matches_oracle(ctx, rule):
         _say("  n=%d cap %d: stop step %d (oracle %d, largest q/tol there %s), forms max rel %.2e"
              % (ref.n, K, r["steps"], want_step, "%.3f" % margin if margin is not None else "-", rel.max()))
         assert r["steps"] == want_step
-        sens = _order_sensitivity(A, B, want_step, False)
-        _assert_within(rel, _bar(False, sens), "n=%d %s rule" % (ref.n, rule))
+        sens = _order_sensitivity(A, B, want_step, fp64)
+        _assert_within(rel, _bar(fp64, sens), "n=%d %s rule" % (ref.n, rule))
 
 
 def test_server_errors_and_busy_release(ctx, pool):
