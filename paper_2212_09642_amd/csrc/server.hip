@@ -137,6 +137,17 @@ public:
     int psi_cap = 0;
     int stop_rule = VNE_STOP_BOUND;  // what a task's check compares with its tolerance
     hipStream_t stream = nullptr;
+    // the width classes of a tick (each its normalize, step and long-row
+    // launches) touch disjoint tasks: they run on the stream and up to kSide
+    // side streams, forked after the tick's descriptor copy and joined before
+    // its finalize
+    // (two side streams measured best: 486 and 520 queries/s at 1000 and
+    // 2000 req/s against 447 and 479 on one stream, 485 and 510 with one
+    // side stream, 475 and 493 with three)
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
+    int n_side = 2;
     DevBuf arena_mem;
     std::vector<double *> pinned_pool;
     std::vector<hipEvent_t> event_pool;
@@ -472,21 +483,38 @@ public:
         VNE_TRY(hip_err(hipMemcpyAsync(d_desc, h, off, hipMemcpyHostToDevice, stream), "hipMemcpyAsync"));
         VNE_TRY(hip_err(hipEventRecord(ring_ev[r], stream), "hipEventRecord"));
         ring_used[r] = true;
-        for (auto &kv : smap) {
-            const int mt = kv.first;
-            const auto lit = lmap.find(mt);
-            const int n_long = lit == lmap.end() ? 0 : (int)lit->second.size();
-            VNE_TRY(hip_err(launch_step_slots(d_sa, d_sm[mt], (int32_t)kv.second.size(), n_long ? d_lm[mt] : nullptr,
-                                              n_long, mt, fp64, stream),
-                            "launch_step_slots"));
-        }
+        // class 0 (the group slots when there are any, which carry most of
+        // the work at saturation) on the tick's own stream, class i >= 1 on
+        // side stream (i - 1) mod n_side
+        const int n_cls = (int)gmap.size() + (int)smap.size();
+        const int n_str = std::min(n_cls, n_side + 1);
+        if (n_str > 1) VNE_TRY(hip_err(hipEventRecord(fork_ev, stream), "hipEventRecord"));
+        for (int j = 1; j < n_str; ++j)
+            VNE_TRY(hip_err(hipStreamWaitEvent(side[j - 1], fork_ev, 0), "hipStreamWaitEvent"));
+        int cls = 0;
+        auto class_stream = [&]() {
+            const int i = cls++;
+            return i == 0 || n_str == 1 ? stream : side[(i - 1) % (n_str - 1)];
+        };
         for (auto &kv : gmap) {
             const int members = kv.first;
             const auto lit = glmap.find(members);
             const int n_long = lit == glmap.end() ? 0 : (int)lit->second.size();
             VNE_TRY(hip_err(launch_step_groups(d_sa, d_gm[members], (int32_t)kv.second.size(),
-                                               n_long ? d_glm[members] : nullptr, n_long, members, stream),
+                                               n_long ? d_glm[members] : nullptr, n_long, members, class_stream()),
                             "launch_step_groups"));
+        }
+        for (auto &kv : smap) {
+            const int mt = kv.first;
+            const auto lit = lmap.find(mt);
+            const int n_long = lit == lmap.end() ? 0 : (int)lit->second.size();
+            VNE_TRY(hip_err(launch_step_slots(d_sa, d_sm[mt], (int32_t)kv.second.size(), n_long ? d_lm[mt] : nullptr,
+                                              n_long, mt, fp64, class_stream()),
+                            "launch_step_slots"));
+        }
+        for (int j = 1; j < n_str; ++j) {
+            VNE_TRY(hip_err(hipEventRecord(join_ev[j - 1], side[j - 1]), "hipEventRecord"));
+            VNE_TRY(hip_err(hipStreamWaitEvent(stream, join_ev[j - 1], 0), "hipStreamWaitEvent"));
         }
         VNE_TRY(hip_err(launch_finalize_slots(d_fa, d_fm, (int32_t)fmap.size(), stream), "launch_finalize_slots"));
         if (!sta.empty()) {
@@ -642,6 +670,11 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
         for (int r = 0; r < GpuExec::kRing; ++r)
             if (x.ring_ev[r]) (void)hipEventDestroy(x.ring_ev[r]);
         if (x.mailbox) (void)hipHostFree(x.mailbox);
+        for (int j = 0; j < GpuExec::kSide; ++j) {
+            if (x.side[j]) (void)hipStreamDestroy(x.side[j]);
+            if (x.join_ev[j]) (void)hipEventDestroy(x.join_ev[j]);
+        }
+        if (x.fork_ev) (void)hipEventDestroy(x.fork_ev);
         if (x.stream) (void)hipStreamDestroy(x.stream);
         dev_free(c, &x.mail);
         dev_free(c, &x.sink);
@@ -650,6 +683,14 @@ extern "C" vne_status vne_server_start(vne_ctx *c, const vne_server_cfg *cfg, vn
     };
     hipError_t e = hipStreamCreate(&x.stream);
     if (e != hipSuccess) return undo(hip_fail(c, e, "hipStreamCreate"));
+    x.n_side = std::max(0, std::min(GpuExec::kSide, env_int("VNE_SERVE_STREAMS", 3) - 1));
+    for (int j = 0; j < GpuExec::kSide; ++j) {
+        e = hipStreamCreate(&x.side[j]);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x.join_ev[j], hipEventDisableTiming);
+        if (e != hipSuccess) return undo(hip_fail(c, e, "hipStreamCreate"));
+    }
+    e = hipEventCreateWithFlags(&x.fork_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return undo(hip_fail(c, e, "hipEventCreate"));
     for (int r = 0; r < GpuExec::kRing; ++r) {
         e = hipEventCreateWithFlags(&x.ring_ev[r], hipEventDisableTiming);
         if (e != hipSuccess) return undo(hip_fail(c, e, "hipEventCreate"));
@@ -738,6 +779,7 @@ extern "C" vne_status vne_server_stop(vne_server *s) {
     GpuExec &x = s->exec;
     vne_ctx *c = x.ctx;
     (void)hipSetDevice(c->device);
+    for (int j = 0; j < GpuExec::kSide; ++j) (void)hipStreamSynchronize(x.side[j]);
     (void)hipStreamSynchronize(x.stream);
     for (ServeQuery *q : s->core->unfinished()) {
         x.release_graph(*q);
@@ -755,6 +797,11 @@ extern "C" vne_status vne_server_stop(vne_server *s) {
     dev_free(c, &x.mail);
     dev_free(c, &x.sink);
     dev_free(c, &x.arena_mem);
+    for (int j = 0; j < GpuExec::kSide; ++j) {
+        (void)hipStreamDestroy(x.side[j]);
+        (void)hipEventDestroy(x.join_ev[j]);
+    }
+    (void)hipEventDestroy(x.fork_ev);
     (void)hipStreamDestroy(x.stream);
     delete s;
     return VNE_OK;
