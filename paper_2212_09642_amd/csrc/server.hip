@@ -485,7 +485,8 @@ public:
         ring_used[r] = true;
         // class 0 (the group slots when there are any, which carry most of
         // the work at saturation) on the tick's own stream, class i >= 1 on
-        // side stream (i - 1) mod n_side
+        // side stream (i - 1) mod (the side streams this tick uses: at most
+        // n_side, and no more than the classes after the first)
         const int n_cls = (int)gmap.size() + (int)smap.size();
         const int n_str = std::min(n_cls, n_side + 1);
         if (n_str > 1) VNE_TRY(hip_err(hipEventRecord(fork_ev, stream), "hipEventRecord"));
