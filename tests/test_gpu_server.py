@@ -329,6 +329,27 @@ def test_server_stop_step_matches_oracle(ctx, rule, fp64):
         _assert_within(rel, _bar(fp64, sens), "n=%d %s rule" % (ref.n, rule))
 
 
+def test_server_side_streams_same_bits(ctx, pool, monkeypatch):
+    """The width classes of a tick on one stream or spread over side
+    streams: every query of a mix of widths (16-column pilots in pairs,
+    lone tasks of 16 to 128 columns) gives the same bits."""
+    _say("case server: one stream against side streams")
+    work = [(pool[i % len(pool)][0], m, k, 300 + i) for i, (m, k) in
+            enumerate([(16, 20), (16, 20), (40, 25), (130, 15), (16, 30), (64, 12), (200, 18), (16, 20)])]
+    adaptive = [(pool[i % len(pool)][0], 500 + i) for i in range(6)]
+    got = {}
+    for streams in ("1", "3"):
+        monkeypatch.setenv("VNE_SERVE_STREAMS", streams)
+        with vne.Server(ctx, MODE, arena_bytes=1 << 30) as srv:
+            ts = [srv.submit(g, m=m, k=k, seed=sd) for g, m, k, sd in work]
+            ts += [srv.submit(g, rel_eps=1e-3, seed=sd) for g, sd in adaptive]
+            got[streams] = [srv.poll(t, want_quad=True) for t in ts]
+    for a, b in zip(got["1"], got["3"]):
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["probes"] == b["probes"] and a["steps"] == b["steps"]
+        assert np.array_equal(a["quad"], b["quad"]) and a["estimate"] == b["estimate"]
+
+
 def test_server_errors_and_busy_release(ctx, pool):
     _say("case server: error paths")
     gid, ref = pool[5]
