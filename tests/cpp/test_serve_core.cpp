@@ -15,7 +15,7 @@
 //  - First come, first served: with one slot, tasks start in ticket order.
 //  - Group slots: 16-column tasks of one graph queued together start in
 //    groups of up to max_group, the largest power of two the free mailbox
-//    entries allow.
+//    entries and the arena allow.
 //  - Arena peak within the arena; everything released at the end.
 //  - Oversize queries fail with VNE_ENOMEM, a non-finite stage with
 //    VNE_ENUMERIC, a device failure ends every open query with VNE_EDEVICE.
@@ -510,9 +510,10 @@ static void fcfs_order() {
 // Eight 16-column queries of one graph queue up while a one-column query
 // holds the worker in a tick; then they start in group slots as large as
 // max_group and the free mailbox entries allow.
-static void group_slots(int slots, int group, int64_t want_group_tasks, int64_t want_pairs) {
+static void group_slots(int slots, int group, int64_t want_group_tasks, int64_t want_pairs,
+                        uint64_t arena = 32ull << 20) {
     const int psi_cap = 64;
-    Setup s(slots, 32ull << 20, psi_cap, false, -1, group);
+    Setup s(slots, arena, psi_cap, false, -1, group);
     s.ex.hold.store(true);
     Want blocker{};
     blocker.graph = 0;
@@ -547,8 +548,8 @@ static void group_slots(int slots, int group, int64_t want_group_tasks, int64_t 
           "%d mailbox entries, groups of up to %d: %lld tasks in group slots, %lld pair slots (expected %lld, %lld)",
           slots, group, (long long)info.group_tasks, (long long)info.pair_slots, (long long)want_group_tasks,
           (long long)want_pairs);
-    std::printf("group slots (%d mailbox entries, up to %d): %lld tasks in group slots, %lld pair slots\n", slots,
-                group, (long long)info.group_tasks, (long long)info.pair_slots);
+    std::printf("group slots (%d mailbox entries, up to %d, arena %llu): %lld tasks in group slots, %lld pair slots\n",
+                slots, group, (unsigned long long)arena, (long long)info.group_tasks, (long long)info.pair_slots);
 }
 
 // A stage whose flags report a failure ends its query; the others complete.
@@ -638,6 +639,10 @@ int main() {
     group_slots(8, 4, 6, 1);   // seven free entries: four, two, one, then one
     group_slots(9, 2, 8, 4);   // four pairs
     group_slots(9, 1, 0, 0);   // no groups
+    // an arena of 80000 bytes: with the one-column task running (15360),
+    // a group of four (four query blocks of 1024 and a 64-column task of
+    // 92416) does not fit, a pair (2 x 1024 + 48384) does: four pairs
+    group_slots(9, 4, 8, 4, 80000);
     fcfs_order();
     numeric_stage();
     stop_in_flight();
