@@ -361,7 +361,7 @@ def exact_entropy_dense(g):
     return float(-np.sum(lam * np.log(lam)))
 
 
-def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=64, max_cols=256, zipf=0.0, pilot=0,
+def measure_serve(rates, queries, pool_size=24, arena_gb=96.0, max_slots=256, max_cols=256, zipf=0.0, pilot=0,
                   exact_n_max=4000, max_group=0, stop="bound"):
     """Poisson streams of 1e-3 relative-accuracy queries on a pool of ER / BA
     / WS graphs (n log-uniform in [1e3, 2e6]).  Per rate: completed queries/s,
@@ -489,7 +489,7 @@ def run_serve(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serve_pool%d_er_ba_ws_n1e3_2e6_eps1e-3_f32" % sv["pool"], "graphs": sv["pool"],
                    "rel_eps": sv["rel_eps"], "rates": args.rates, "queries_per_rate": args.queries,
-                   "zipf": args.zipf, "pilot": args.pilot or 16, "max_group": args.group or 2,
+                   "zipf": args.zipf, "pilot": args.pilot or 16, "max_group": args.group or 2, "max_slots": args.max_slots,
                    "stop": args.stop,
                    "graph_seed": __import__("synth").workloads.GRAPH_SEED_SERVE},
         "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"], "rates": rows,
@@ -763,7 +763,7 @@ def main():
     ap.add_argument("--queries", type=int, default=200, help="serve workload: queries per rate")
     ap.add_argument("--pool", type=int, default=24, help="serve workload: graphs in the pool")
     ap.add_argument("--arena-gb", type=float, default=96.0, help="serve workload: server arena (GiB)")
-    ap.add_argument("--max-slots", type=int, default=64, help="serve workload: tasks running at once")
+    ap.add_argument("--max-slots", type=int, default=256, help="serve workload: tasks running at once")
     ap.add_argument("--max-cols", type=int, default=256, help="serve workload: probe columns per task")
     ap.add_argument("--pilot", type=int, default=0,
                     help="serve workload: pilot probes of a query (0: the server's default, 16)")

@@ -591,7 +591,7 @@ vne_status vne_last_plan(const vne_ctx *ctx, int32_t *tile, int32_t *m_pad);
 typedef struct vne_server vne_server;
 
 typedef struct {
-    int32_t max_slots;          /* tasks running at once (0: 64) */
+    int32_t max_slots;          /* tasks running at once (0: 256) */
     uint64_t arena_bytes;       /* device memory for running tasks (0: a quarter of free memory) */
     int32_t max_cols;           /* probe columns per task (0: 256; at most 4096) */
     int32_t pilot_probes;       /* pilot width (0: 16) */
