@@ -778,7 +778,7 @@ def main():
                          "bracket (eq. (4.9)) or its geometric mean (eq. (4.10))")
     ap.add_argument("--no-extras", action="store_true",
                     help="large workload: skip the serve and batch objects of the default line")
-    ap.add_argument("--serve-rates", default="20,200",
+    ap.add_argument("--serve-rates", default="20,300",
                     help="large workload: arrival rates of the serve object (a light one, one near saturation)")
     ap.add_argument("--serve-queries", type=int, default=200, help="large workload: queries per serve rate")
     ap.add_argument("--copy-calibration", action="store_true",
